@@ -1,0 +1,143 @@
+"""Benchmark: CTMRG sweeps per second on one MI355X.
+
+Workload (one "step" = one CTMRG sweep = left, right, up and down moves over
+the whole unit cell): iTPS on a 2x2 unit cell, physical dimension 2, bond
+dimension D = 6, environment dimension chi = 144, real site tensors with
+seeded N(0, 1) entries divided by their max-abs entry; projectors from the
+randomized SVD with oversampling p = 48 and q = 1 power iteration.
+
+Prints one JSON line.  `roofline` is for the dominant phase (the sketch
+GEMMs: products of an n x n enlarged corner with n x k panels), timed live
+with HIP events on the library's stream over the timed sweeps.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload (one left move on a random full-dimension environment) and scales
+it to sweeps per second.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as wl  # noqa: E402
+
+PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "f16split": 2.5e15}
+METRIC = "CTMRG sweeps/s + MFMA util at D=6 chi=144; solves/s and p99 latency"
+
+
+def flops_per_sweep(D, chi, d, p, q, Lx=2, Ly=2):
+    """Algorithmic flops of one sweep (single-layer contractions, randomized SVD)."""
+    Db = D * D
+    n = chi * Db
+    k = min(chi + p, n)
+    ncut = 4 * Lx * Ly
+    corner = chi ** 3 * Db + chi ** 3 * Db * Db + 2 * chi ** 2 * Db * Db * D * D * d
+    sketch = (10 + 8 * q) * n * n * k
+    renorm = 2 * chi ** 3 * Db * Db + 2 * chi ** 2 * Db * Db * D * D * d
+    return 2.0 * (4 * ncut * corner + ncut * sketch + ncut * renorm)
+
+
+def cpu_baseline(D, chi, p, q, seed):
+    """Oracle time for one left move on a random full-dimension environment."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.ctmrg import Environment
+    cores = min(os.cpu_count() or 1, 16)
+    A = wl.random_itps(2, 2, D, 2, seed=seed)
+    env = Environment(A, 2, 2, chi=chi, layers=2, mode="rsvd", oversample=p, power_iters=q, seed=7)
+    rng = np.random.default_rng(3)
+    for i in range(4):
+        env.C[i] = [rng.standard_normal((chi, chi)) for _ in range(4)]
+        env.T[i] = [rng.standard_normal((chi, chi, D * D)) for _ in range(4)]
+    with threadpool_limits(limits=cores):
+        t0 = time.perf_counter()
+        env.left_move(0)
+        dt = time.perf_counter() - t0
+    return dict(value=1.0 / (4.0 * dt), unit="sweeps/s", cores=cores, kind="oracle",
+                sample=f"one left move (1/4 sweep) of the 2x2 D={D} chi={chi} workload on a random "
+                       f"full-dimension environment, NumPy/OpenBLAS FP64, {dt:.1f} s; scaled x4")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="f64", choices=sorted(PEAK))
+    ap.add_argument("--D", type=int, default=6)
+    ap.add_argument("--chi", type=int, default=144)
+    ap.add_argument("--p", type=int, default=48)
+    ap.add_argument("--q", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2112_13184_amd as lib
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    lib.load()
+    D, chi, d, p, q = args.D, args.chi, 2, args.p, args.q
+    A = wl.random_itps(2, 2, D, d, seed=2)
+    ctx = lib.Ctm(A, 2, 2, D, chi, d=d, prec=args.prec, rsvd_oversample=p, rsvd_power_iters=q, seed=12)
+    moves = ("left", "right", "up", "down")
+    for _ in range(args.warmup):
+        for m in moves:
+            ctx.ctm_move(m)
+    torch.cuda.synchronize()
+    ctx.ctm_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for m in moves:
+            ctx.ctm_move(m)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phases = ctx.ctm_timing_read()
+    ctx.ctm_timing_enable(False)
+    sweeps_per_s = args.steps / dt
+    sk = phases["sketch_gemm"]
+    achieved = sk["flops"] / (sk["ms"] * 1e-3) if sk["ms"] > 0 else 0.0
+    H = wl.heisenberg_bond()
+    energy = sum(ctx.ctm_expect_2site(i, dr, H) for i in range(4) for dr in (0, 1)) / 4
+    alg = flops_per_sweep(D, chi, d, p, q)
+    out = {
+        "metric": METRIC,
+        "value": sweeps_per_s,
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"itps_2x2_d2_D{D}_chi{chi}", "Lx": 2, "Ly": 2, "d": d, "D": D,
+                   "chi": chi, "rsvd_p": p, "rsvd_q": q, "precision": args.prec, "tensor_seed": 2},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[args.prec] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec], "traffic": None,
+                     "kernel": "sketch GEMMs (n x k panel times n x n corner)",
+                     "launches": sk["launches"], "avg_launch_ms": sk["ms"] / max(sk["launches"], 1),
+                     "flops_per_launch": sk["flops"] / max(sk["launches"], 1)},
+        "whole_sweep": {"alg_tflop": alg / 1e12, "achieved_tflops": alg * sweeps_per_s / 1e12,
+                        "frac_of_peak": alg * sweeps_per_s / PEAK[args.prec]},
+        "phases_ms_per_sweep": {k: v["ms"] / args.steps for k, v in phases.items()},
+        "energy_per_site": energy,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(D, chi, p, q, seed=2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

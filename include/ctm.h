@@ -1,0 +1,237 @@
+/*
+ * ctm.h -- C ABI of the MI355X CTMRG library (libctm.so).
+ *
+ * The library runs the corner transfer matrix renormalization group (CTMRG)
+ * contraction of an infinite tensor product state (iTPS) on one AMD Instinct
+ * MI355X (gfx950), as described in Sec. 2.2 and Fig. 2 of Motoyama et al.,
+ * "TeNeS: Tensor Network Solver for Quantum Lattice Systems" (arXiv:2112.13184):
+ * the ket and bra site tensors form a double-layer network of bond dimension
+ * D^2; each site gets four corner matrices C (chi x chi) and four edge tensors
+ * T (chi x chi x D^2), fixed by directional moves (absorb a column, build the
+ * enlarged corners, compute QR-free projectors from a partial / randomized SVD
+ * of the 2x2 cluster, renormalise).  The converged environment gives one-site
+ * and nearest-neighbour expectation values (Sec. 4.5).
+ *
+ * Conventions (all arrays row-major, C order, FP64 unless stated):
+ *   site tensor     A[l][u][r][d][p] (D^4 d values); classical network
+ *                   (layers = 1): a[l][u][r][d] (D^4 values, d must be 1)
+ *   site index      i = x + Lx * y, +y points up (r = (0,1) is the upper
+ *                   neighbour, Sec. 4.5)
+ *   pair index      ket * D + bra for a double-layer bond (Db = D^2);
+ *                   Db = D for a classical network
+ *   environment     per site, clockwise C1 T1 C2 T2 C3 T3 C4 T4 (C1 upper
+ *                   left, T1 above).  Corner C_k[next][prev], edge
+ *                   T_k[prev][next][pair]; next / prev name the clockwise
+ *                   neighbour.  Stored zero padded to chi on every chi leg.
+ *   directions      CTM_LEFT moves absorb columns into C1 T4 C4, CTM_RIGHT
+ *                   into C3 T2 C2, CTM_UP into C2 T1 C1, CTM_DOWN into C4 T3 C3.
+ *   operators       one-site op[out][in] (d x d); two-site
+ *                   op[(out_i, out_j)][(in_i, in_j)] (d^2 x d^2), the element
+ *                   order of the paper's operator input (Sec. 3.2).
+ *
+ * Errors: every call returns a ctm_status.  Invalid arguments give
+ * CTM_EINVAL and leave the state unchanged; device failures CTM_EDEVICE;
+ * NaN / Inf or a cut without any singular value above zero CTM_ENUMERIC.
+ * ctm_last_error() describes the last failure on a context.  A context is
+ * single threaded; a queue may be called from any thread.
+ *
+ * Ownership: host inputs are copied; device inputs are read during the call
+ * only; outputs go to caller buffers.  The context owns all device memory it
+ * allocates and frees it in ctm_free().
+ */
+#ifndef CTM_H
+#define CTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CTM_OK = 0,
+  CTM_EINVAL = -1,     /* bad argument or shape                                  */
+  CTM_ENOMEM = -2,     /* device allocation failed                               */
+  CTM_EDEVICE = -3,    /* HIP / rocSOLVER failure                                */
+  CTM_ENUMERIC = -4,   /* NaN / Inf, or a cut with no singular value above zero  */
+  CTM_ETOOBIG = -5,    /* request larger than the queue's memory budget          */
+  CTM_EAGAIN = -6,     /* result not ready yet                                   */
+  CTM_ECANCELED = -7   /* request cancelled                                      */
+} ctm_status;
+
+/* Arithmetic of the contraction GEMMs (enlarged corners, sketch products,
+ * renormalisation).  QR, SVD, projector scaling, normalisation, convergence
+ * and expectation values always run in FP64.  Reduced precisions round the
+ * operands of each GEMM to nearest even and accumulate in FP32.
+ * CTM_F16_SPLIT writes each operand as hi + lo (two FP16 numbers with a
+ * power-of-two scale) and sums the three products hi*hi, hi*lo, lo*hi. */
+typedef enum { CTM_F64 = 0, CTM_F32 = 1, CTM_BF16 = 2, CTM_F16_SPLIT = 3 } ctm_precision;
+
+typedef enum { CTM_LEFT = 0, CTM_RIGHT = 1, CTM_UP = 2, CTM_DOWN = 3 } ctm_dir;
+
+typedef struct {
+  int Lx, Ly;              /* unit cell                                            */
+  int d;                   /* physical dimension (1 for layers = 1)                */
+  int D;                   /* virtual bond dimension of the site tensors           */
+  int chi;                 /* environment bond dimension                           */
+  int layers;              /* 2 = ket/bra iTPS (bra = ket, real), 1 = classical    */
+  ctm_precision prec;      /* precision of the contraction GEMMs                   */
+  double svd_rel_cutoff;   /* singular values <= cutoff * sigma_0 are dropped;
+                              0 selects the default 1e-12                          */
+  int rsvd_oversample;     /* p of the randomized SVD (k = chi + p); < 0 selects
+                              the exact FP64 SVD of the explicitly formed cluster
+                              matrix (small problems only)                         */
+  int rsvd_power_iters;    /* q, number of power iterations                        */
+  uint64_t seed;           /* key of the counter-based sketch generator            */
+  void* stream;            /* hipStream_t to run on, or NULL for a private stream  */
+} ctm_config;
+
+typedef struct ctm_ctx ctm_ctx;
+
+/* Sec. 2.2: set up a context for the given site tensors.  tensors holds
+ * Lx*Ly site tensors back to back (site order i = x + Lx*y), in host memory
+ * (tensors_on_device = 0) or device memory (1).  boundary (Db values, host)
+ * is the vector on every outer leg of the initial environment, or NULL for
+ * the ket/bra identity (layers = 2) / all ones (layers = 1).  The initial
+ * environment has C = [[1]] and T[0][0][:] = boundary (all chi legs of
+ * dimension 1).  On success *out owns the new context. */
+ctm_status ctm_init(const ctm_config* cfg, const double* tensors, int tensors_on_device,
+                    const double* boundary, ctm_ctx** out);
+
+/* Sec. 2.2: one directional move over every column (row) of the unit cell. */
+ctm_status ctm_move(ctm_ctx* ctx, ctm_dir dir);
+
+/* Up to max_sweeps sweeps (left, right, up, down).  After every sweep the
+ * singular values of every corner, normalised to sum 1, are compared with
+ * those of the previous sweep; the run stops when the largest L1 change
+ * (delta) is below tol.  Any out pointer may be NULL.  Not converging is not
+ * an error (*converged = 0). */
+ctm_status ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done,
+                     double* delta, int* converged);
+
+/* Projectors of one cut of a move, computed from the current environment and
+ * not applied.  (x, y) are the column and cut row in the frame of the move
+ * (the frame in which the move is a left move: the lattice rotated by 0, 2, 1,
+ * 3 quarter turns counter-clockwise for left, right, up, down).  With
+ * n = chi * Db, Pt (n x chi, host) renormalises the side above the cut and
+ * P (chi x n, host) the side below; both are zero padded.  *k_eff is the
+ * number of non-zero projector columns.  May be NULL. */
+ctm_status ctm_projectors(ctm_ctx* ctx, ctm_dir dir, int x, int y, double* P, double* Pt,
+                          int* k_eff);
+
+/* Enlarged corner of role `corner` (0..3 = C1..C4) around `site`, as the
+ * n x n matrix E[(c_next, o_next)][(c_prev, o_prev)] (host buffer): the
+ * corner, its two edge tensors and the site seen from that corner, with ket
+ * and bra contracted one after the other.  For testing. */
+ctm_status ctm_enlarged_corner(ctm_ctx* ctx, int corner, int site, double* E);
+
+/* Sec. 4.5: <op> at `site` from the 3x3 patch of the environment. */
+ctm_status ctm_expect_1site(ctm_ctx* ctx, int site, const double* op, double* val);
+
+/* Sec. 4.5: <op> on the bond from `site` to its neighbour at +x (dir = 0) or
+ * +y (dir = 1), from the 3x4 / 4x3 patch.  op is d^2 x d^2 (see above). */
+ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, double* val);
+
+/* Reduced density matrices behind the two calls above (host, ket index first:
+ * rho[p][p'] and rho[(p_s, p_t)][(p_s', p_t')]), normalised to trace 1. */
+ctm_status ctm_rho_1site(ctm_ctx* ctx, int site, double* rho);
+ctm_status ctm_rho_2site(ctm_ctx* ctx, int site, int dir, double* rho);
+
+/* Classical network (layers = 1): Z(b) / Z(a) on the 3x3 patch of `site`,
+ * with b (D^4, host) in place of the site tensor (e.g. a magnetisation). */
+ctm_status ctm_impurity(ctm_ctx* ctx, int site, const double* b, double* val);
+
+/* 1x1 cell: ln kappa, the log of the partition function (norm) per site, as
+ * ln Z(3x3) + ln Z(corners) - ln Z(2x3) - ln Z(3x2). */
+ctm_status ctm_log_kappa(ctm_ctx* ctx, double* ln_kappa);
+
+/* Environment of one site as host FP64: C1..C4 (chi*chi each) then T1..T4
+ * (chi*chi*Db each), zero padded; bytes must be >= ctm_env_bytes().  dims
+ * (16 ints, may be NULL) gets the actual leg dimensions: C_k (next, prev) for
+ * k = 1..4, then T_k (prev, next). */
+size_t ctm_env_bytes(const ctm_ctx* ctx);
+ctm_status ctm_get_env(ctm_ctx* ctx, int site, double* buf, size_t bytes, int* dims);
+/* Replace the environment of one site (same layout; entries beyond dims must
+ * be zero).  dims may be NULL: then every chi leg is taken as chi. */
+ctm_status ctm_set_env(ctm_ctx* ctx, int site, const double* buf, size_t bytes, const int* dims);
+
+/* Number of moves done since ctm_init (keys the sketch of each cut). */
+ctm_status ctm_move_count(const ctm_ctx* ctx, int64_t* moves);
+
+/* Per-phase GPU timing with HIP events recorded on the context's stream
+ * around every launch of a phase, while enabled.  Phases:
+ *   0 edge GEMMs      (n x n x chi: enlarged-corner step 2, edge renormalisation)
+ *   1 sketch GEMMs    (products with an n x n enlarged corner or absorbed edge)
+ *   2 absorption      (single-layer ket and bra contractions of the site)
+ *   3 factorisations  (QR, SVD and projector scaling, FP64)
+ *   4 other           (small GEMMs, normalisation, permutations, spectra)
+ * flops counts the algorithmic floating-point operations of the launches
+ * (2 M N K per GEMM; 0 for phases 3 and 4).  ctm_timing_read() synchronises
+ * the stream. */
+#define CTM_NPHASE 5
+typedef struct {
+  int64_t launches[CTM_NPHASE];
+  double ms[CTM_NPHASE];
+  double flops[CTM_NPHASE];
+} ctm_timing;
+ctm_status ctm_timing_enable(ctm_ctx* ctx, int on);   /* on != 0 also clears the counters */
+ctm_status ctm_timing_read(ctm_ctx* ctx, ctm_timing* out);
+
+/* Device memory a context with this configuration allocates (resident state
+ * plus workspaces), in bytes; 0 for an invalid configuration. */
+size_t ctm_footprint_bytes(const ctm_config* cfg);
+
+/* Text of the last error on ctx (valid until the next call on ctx); a static
+ * message for ctx == NULL. */
+const char* ctm_last_error(const ctm_ctx* ctx);
+
+void ctm_free(ctm_ctx* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of independent CTMRG solves on one GPU.      */
+/* ------------------------------------------------------------------------ */
+typedef struct ctm_queue ctm_queue;
+
+typedef struct {
+  ctm_config cfg;            /* stream is ignored: the queue owns its streams      */
+  const double* tensors;     /* host, Lx*Ly site tensors (copied at submit)        */
+  const double* bond_op;     /* d^2 x d^2 bond operator on every +x and +y bond     */
+  const double* onsite_op;   /* d x d, or NULL                                      */
+  double tol;                /* stop when delta < tol                               */
+  int max_sweeps;
+  uint64_t tag;              /* returned unchanged                                  */
+} ctm_request;
+
+typedef struct {
+  ctm_status status;
+  int converged, sweeps;
+  double delta;
+  double energy_per_site;    /* (1/N) sum_s <h_{s,s+x}> + <h_{s,s+y}> + <h_s>       */
+  double mz[4];              /* <sigma_z> style one-site values of op diag(1,-1)
+                                on the first min(4, N) sites (d = 2 only)          */
+  uint64_t tag;
+  int64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady clock                   */
+} ctm_result;
+
+/* A queue admits requests while the summed footprints of the active ones stay
+ * within hbm_budget_bytes and at most max_active run at once.  Active solves
+ * advance one directional move per scheduling round; moves of solves with the
+ * same (D, chi, d, layers) run their enlarged-corner and sketch GEMMs as one
+ * grouped launch. */
+ctm_status ctm_queue_create(size_t hbm_budget_bytes, int max_active, ctm_queue** out);
+/* Copies the request and returns at once; *ticket identifies it.  A request
+ * whose footprint exceeds the budget is rejected with CTM_ETOOBIG. */
+ctm_status ctm_queue_submit(ctm_queue* q, const ctm_request* req, uint64_t* ticket);
+/* CTM_EAGAIN while pending; otherwise the final status, result filled in. */
+ctm_status ctm_queue_poll(ctm_queue* q, uint64_t ticket, ctm_result* res);
+/* Waits up to timeout_ms (< 0: forever); CTM_EAGAIN on timeout. */
+ctm_status ctm_queue_wait(ctm_queue* q, uint64_t ticket, int timeout_ms, ctm_result* res);
+ctm_status ctm_queue_cancel(ctm_queue* q, uint64_t ticket);
+/* Cancels pending requests, waits for active ones, frees everything. */
+void ctm_queue_destroy(ctm_queue* q);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTM_H */

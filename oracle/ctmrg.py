@@ -37,7 +37,9 @@ Conventions (the paper leaves these open; each one is a reading)
 * If the cut bond has n_alpha <= chi, P = Pt = identity (nothing is
   discarded, the environment stays exact).  Otherwise exactly chi singular
   triplets are kept; those with sigma_i <= cutoff * sigma_0 get zero
-  projector rows / columns, so bond dimensions depend only on shapes.
+  projector rows / columns, so bond dimensions depend only on shapes.  Nor
+  is any singular value past the smallest bond of the four-corner product
+  kept (it can only be rounding noise).
 * Sign of each singular pair: the entry of largest modulus of U[:, i] (first
   one on ties) is made positive.
 * Every new C and T is divided by its largest absolute entry.
@@ -257,9 +259,12 @@ def projectors(G_ur, G_ul, G_ll, G_lr, chi, cutoff, mode="rsvd", oversample=32,
         raise ValueError(mode)
     if not S.size or not S[0] > 0 or not np.all(np.isfinite(S)):
         raise FloatingPointError("the cut has no singular value above zero")
+    # M = G_ur G_ul G_ll G_lr cannot have rank above its smallest bond: any
+    # singular value past that bound is rounding noise and is not kept.
+    r_struct = min(G_ur.shape + G_ul.shape + G_ll.shape + G_lr.shape)
     m = min(chi, S.size)
     U, V, S = U[:, :m].copy(), V[:, :m].copy(), S[:m].copy()
-    keep = S > cutoff * S[0]
+    keep = (S > cutoff * S[0]) & (np.arange(m) < r_struct)
     U, V = _fix_signs(U, V)
     isq = np.where(keep, 1.0 / np.sqrt(np.where(keep, S, 1.0)), 0.0)
     P = np.zeros((chi, n_alpha))

@@ -1,0 +1,276 @@
+"""ctypes binding of libctm.so (include/ctm.h).  Argument marshalling only.
+
+Every computation happens inside the HIP library; this module converts numpy
+arrays (or device pointers) to the C ABI and raises ``CtmError`` on a
+non-zero status.  It never falls back to anything else: if the library is
+missing, ``load()`` raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libctm.so")
+
+CTM_OK, CTM_EINVAL, CTM_ENOMEM, CTM_EDEVICE, CTM_ENUMERIC, CTM_ETOOBIG, CTM_EAGAIN, CTM_ECANCELED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {0: "CTM_OK", -1: "CTM_EINVAL", -2: "CTM_ENOMEM", -3: "CTM_EDEVICE", -4: "CTM_ENUMERIC",
+                -5: "CTM_ETOOBIG", -6: "CTM_EAGAIN", -7: "CTM_ECANCELED"}
+CTM_F64, CTM_F32, CTM_BF16, CTM_F16_SPLIT = 0, 1, 2, 3
+PRECISIONS = {"f64": CTM_F64, "f32": CTM_F32, "bf16": CTM_BF16, "f16split": CTM_F16_SPLIT}
+CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN = 0, 1, 2, 3
+DIRS = {"left": CTM_LEFT, "right": CTM_RIGHT, "up": CTM_UP, "down": CTM_DOWN}
+
+# Every symbol include/ctm.h declares.
+EXPORTS = (
+    "ctm_init", "ctm_move", "ctm_sweep", "ctm_projectors", "ctm_enlarged_corner",
+    "ctm_expect_1site", "ctm_expect_2site", "ctm_rho_1site", "ctm_rho_2site", "ctm_impurity",
+    "ctm_log_kappa", "ctm_env_bytes", "ctm_get_env", "ctm_set_env", "ctm_move_count",
+    "ctm_footprint_bytes", "ctm_last_error", "ctm_free", "ctm_timing_enable", "ctm_timing_read",
+    "ctm_queue_create", "ctm_queue_submit", "ctm_queue_poll", "ctm_queue_wait",
+    "ctm_queue_cancel", "ctm_queue_destroy",
+)
+
+
+class CtmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ctm_config(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("d", ctypes.c_int), ("D", ctypes.c_int),
+                ("chi", ctypes.c_int), ("layers", ctypes.c_int), ("prec", ctypes.c_int),
+                ("svd_rel_cutoff", ctypes.c_double), ("rsvd_oversample", ctypes.c_int),
+                ("rsvd_power_iters", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("stream", ctypes.c_void_p)]
+
+
+class ctm_request(ctypes.Structure):
+    _fields_ = [("cfg", ctm_config), ("tensors", ctypes.POINTER(ctypes.c_double)),
+                ("bond_op", ctypes.POINTER(ctypes.c_double)),
+                ("onsite_op", ctypes.POINTER(ctypes.c_double)),
+                ("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int), ("tag", ctypes.c_uint64)]
+
+
+PHASES = ("edge_gemm", "sketch_gemm", "absorb", "factorise", "other")
+
+
+class ctm_timing(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 5), ("ms", ctypes.c_double * 5), ("flops", ctypes.c_double * 5)]
+
+
+class ctm_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("converged", ctypes.c_int), ("sweeps", ctypes.c_int),
+                ("delta", ctypes.c_double), ("energy_per_site", ctypes.c_double),
+                ("mz", ctypes.c_double * 4), ("tag", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+
+
+def load(path=LIB_PATH):
+    """Load libctm.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not built; run paper_2112_13184_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    V, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    sig = {
+        "ctm_init": (I, [ctypes.POINTER(ctm_config), _DP, I, _DP, ctypes.POINTER(V)]),
+        "ctm_move": (I, [V, I]),
+        "ctm_sweep": (I, [V, I, D, _IP, _DP, _IP]),
+        "ctm_projectors": (I, [V, I, I, I, _DP, _DP, _IP]),
+        "ctm_enlarged_corner": (I, [V, I, I, _DP]),
+        "ctm_expect_1site": (I, [V, I, _DP, _DP]),
+        "ctm_expect_2site": (I, [V, I, I, _DP, _DP]),
+        "ctm_rho_1site": (I, [V, I, _DP]),
+        "ctm_rho_2site": (I, [V, I, I, _DP]),
+        "ctm_impurity": (I, [V, I, _DP, _DP]),
+        "ctm_log_kappa": (I, [V, _DP]),
+        "ctm_env_bytes": (S, [V]),
+        "ctm_get_env": (I, [V, I, _DP, S, _IP]),
+        "ctm_set_env": (I, [V, I, _DP, S, _IP]),
+        "ctm_move_count": (I, [V, ctypes.POINTER(ctypes.c_int64)]),
+        "ctm_footprint_bytes": (S, [ctypes.POINTER(ctm_config)]),
+        "ctm_last_error": (ctypes.c_char_p, [V]),
+        "ctm_free": (None, [V]),
+        "ctm_timing_enable": (I, [V, I]),
+        "ctm_timing_read": (I, [V, ctypes.POINTER(ctm_timing)]),
+        "ctm_queue_create": (I, [S, I, ctypes.POINTER(V)]),
+        "ctm_queue_submit": (I, [V, ctypes.POINTER(ctm_request), ctypes.POINTER(ctypes.c_uint64)]),
+        "ctm_queue_poll": (I, [V, ctypes.c_uint64, ctypes.POINTER(ctm_result)]),
+        "ctm_queue_wait": (I, [V, ctypes.c_uint64, I, ctypes.POINTER(ctm_result)]),
+        "ctm_queue_cancel": (I, [V, ctypes.c_uint64]),
+        "ctm_queue_destroy": (None, [V]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_config(Lx, Ly, D, chi, d=2, layers=2, prec="f64", svd_rel_cutoff=0.0, rsvd_oversample=32,
+                rsvd_power_iters=1, seed=0, stream=None):
+    cfg = ctm_config()
+    cfg.Lx, cfg.Ly, cfg.d, cfg.D, cfg.chi, cfg.layers = Lx, Ly, d, D, chi, layers
+    cfg.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+    cfg.svd_rel_cutoff = svd_rel_cutoff
+    cfg.rsvd_oversample, cfg.rsvd_power_iters = rsvd_oversample, rsvd_power_iters
+    cfg.seed = seed
+    cfg.stream = stream
+    return cfg
+
+
+def ctm_footprint_bytes(cfg):
+    return int(load().ctm_footprint_bytes(ctypes.byref(cfg)))
+
+
+class Ctm:
+    """One CTMRG context (ctm_ctx) on the GPU."""
+
+    def __init__(self, tensors, Lx, Ly, D, chi, d=2, layers=2, boundary=None, device_ptr=None, **kw):
+        lib = load()
+        self.cfg = make_config(Lx, Ly, D, chi, d=d if layers == 2 else 1, layers=layers, **kw)
+        self.Lx, self.Ly, self.D, self.chi, self.layers = Lx, Ly, D, chi, layers
+        self.d = d if layers == 2 else 1
+        self.Db = D * D if layers == 2 else D
+        self.n = chi * self.Db
+        h = ctypes.c_void_p()
+        if device_ptr is not None:
+            tp, on_dev = ctypes.cast(ctypes.c_void_p(int(device_ptr)), _DP), 1
+            self._keep = None
+        else:
+            arr = _f64(np.concatenate([np.asarray(t, dtype=np.float64).reshape(-1) for t in tensors]))
+            tp, on_dev = _dp(arr), 0
+            self._keep = arr
+        b = None
+        if boundary is not None:
+            self._bnd = _f64(boundary).reshape(-1)
+            b = _dp(self._bnd)
+        st = lib.ctm_init(ctypes.byref(self.cfg), tp, on_dev, b, ctypes.byref(h))
+        if st != CTM_OK:
+            raise CtmError(st, lib.ctm_last_error(None).decode())
+        self._h = h
+        self._lib = lib
+
+    def _check(self, st):
+        if st != CTM_OK:
+            raise CtmError(st, self._lib.ctm_last_error(self._h).decode())
+
+    def ctm_move(self, direction):
+        d = DIRS[direction] if isinstance(direction, str) else int(direction)
+        self._check(self._lib.ctm_move(self._h, d))
+
+    def ctm_sweep(self, max_sweeps, tol):
+        done, conv, delta = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._check(self._lib.ctm_sweep(self._h, max_sweeps, tol, ctypes.byref(done),
+                                        ctypes.byref(delta), ctypes.byref(conv)))
+        return done.value, delta.value, bool(conv.value)
+
+    def ctm_projectors(self, direction, x, y):
+        d = DIRS[direction] if isinstance(direction, str) else int(direction)
+        P = np.zeros((self.chi, self.n))
+        Pt = np.zeros((self.n, self.chi))
+        k = ctypes.c_int()
+        self._check(self._lib.ctm_projectors(self._h, d, x, y, _dp(P), _dp(Pt), ctypes.byref(k)))
+        return P, Pt, k.value
+
+    def ctm_enlarged_corner(self, corner, site):
+        E = np.zeros((self.n, self.n))
+        self._check(self._lib.ctm_enlarged_corner(self._h, corner, site, _dp(E)))
+        return E
+
+    def ctm_expect_1site(self, site, op):
+        v = ctypes.c_double()
+        o = _f64(op)
+        self._check(self._lib.ctm_expect_1site(self._h, site, _dp(o), ctypes.byref(v)))
+        return v.value
+
+    def ctm_expect_2site(self, site, direction, op):
+        v = ctypes.c_double()
+        o = _f64(op)
+        self._check(self._lib.ctm_expect_2site(self._h, site, direction, _dp(o), ctypes.byref(v)))
+        return v.value
+
+    def ctm_rho_1site(self, site):
+        r = np.zeros((self.d, self.d))
+        self._check(self._lib.ctm_rho_1site(self._h, site, _dp(r)))
+        return r
+
+    def ctm_rho_2site(self, site, direction):
+        r = np.zeros((self.d * self.d, self.d * self.d))
+        self._check(self._lib.ctm_rho_2site(self._h, site, direction, _dp(r)))
+        return r
+
+    def ctm_impurity(self, site, b):
+        v = ctypes.c_double()
+        bb = _f64(b)
+        self._check(self._lib.ctm_impurity(self._h, site, _dp(bb), ctypes.byref(v)))
+        return v.value
+
+    def ctm_log_kappa(self):
+        v = ctypes.c_double()
+        self._check(self._lib.ctm_log_kappa(self._h, ctypes.byref(v)))
+        return v.value
+
+    def ctm_get_env(self, site):
+        nb = int(self._lib.ctm_env_bytes(self._h))
+        buf = np.zeros(nb // 8)
+        dims = np.zeros(16, dtype=np.int32)
+        self._check(self._lib.ctm_get_env(self._h, site, _dp(buf), nb,
+                                          dims.ctypes.data_as(_IP)))
+        cc, tt = self.chi * self.chi, self.chi * self.chi * self.Db
+        C = [buf[k * cc:(k + 1) * cc].reshape(self.chi, self.chi) for k in range(4)]
+        T = [buf[4 * cc + k * tt:4 * cc + (k + 1) * tt].reshape(self.chi, self.chi, self.Db)
+             for k in range(4)]
+        return C, T, dims.reshape(2, 4, 2)
+
+    def ctm_set_env(self, site, C, T, dims=None):
+        buf = _f64(np.concatenate([np.asarray(x).reshape(-1) for x in list(C) + list(T)]))
+        dp = None
+        if dims is not None:
+            self._dims = np.ascontiguousarray(np.asarray(dims).reshape(16), dtype=np.int32)
+            dp = self._dims.ctypes.data_as(_IP)
+        self._check(self._lib.ctm_set_env(self._h, site, _dp(buf), buf.nbytes, dp))
+
+    def ctm_move_count(self):
+        m = ctypes.c_int64()
+        self._check(self._lib.ctm_move_count(self._h, ctypes.byref(m)))
+        return m.value
+
+    def ctm_timing_enable(self, on=True):
+        self._check(self._lib.ctm_timing_enable(self._h, 1 if on else 0))
+
+    def ctm_timing_read(self):
+        t = ctm_timing()
+        self._check(self._lib.ctm_timing_read(self._h, ctypes.byref(t)))
+        return {name: dict(launches=int(t.launches[i]), ms=float(t.ms[i]), flops=float(t.flops[i]))
+                for i, name in enumerate(PHASES)}
+
+    def ctm_free(self):
+        if getattr(self, "_h", None):
+            self._lib.ctm_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.ctm_free()
+        except Exception:
+            pass

@@ -1,0 +1,152 @@
+// CTMRG context: resident environment, workspaces and the sweep driver.
+#pragma once
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "../../include/ctm.h"
+#include "common.hpp"
+#include "gemm.hpp"
+#include "linalg.hpp"
+
+namespace ctm {
+
+// Bump allocator for the transient tensors of the expectation-value
+// contractions: a list of device chunks, reused after reset().
+struct Arena {
+  std::vector<DevBuf*> chunks;
+  size_t cur = 0, used = 0;   // current chunk, elements used in it
+  double* alloc(size_t elems);
+  void reset() { cur = 0; used = 0; }
+  ~Arena() { for (auto* b : chunks) delete b; }
+};
+
+// Device tensor view (row-major).
+struct DT {
+  double* p = nullptr;
+  std::vector<long> dims;
+  long size() const {
+    long s = 1;
+    for (long d : dims) s *= d;
+    return s;
+  }
+};
+
+// Per-phase launch timing with HIP events on the context stream.
+struct PhaseTimer {
+  enum { EDGE = 0, SKETCH = 1, ABSORB = 2, LINALG = 3, OTHER = 4, N = 5 };
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  struct Rec { int phase; hipEvent_t a, b; double flops; };
+  std::vector<Rec> recs;
+  int64_t launches[N] = {};
+  double ms[N] = {}, flops[N] = {};
+  hipEvent_t get() {
+    if (next == pool.size()) {
+      hipEvent_t e;
+      CTM_HIP(hipEventCreate(&e));
+      pool.push_back(e);
+    }
+    return pool[next++];
+  }
+  void clear() {
+    recs.clear();
+    next = 0;
+    for (int i = 0; i < N; ++i) { launches[i] = 0; ms[i] = 0; flops[i] = 0; }
+  }
+  void resolve() {
+    for (auto& r : recs) {
+      float t = 0.f;
+      CTM_HIP(hipEventSynchronize(r.b));
+      CTM_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      launches[r.phase] += 1;
+      ms[r.phase] += t;
+      flops[r.phase] += r.flops;
+    }
+    recs.clear();
+    next = 0;
+  }
+  ~PhaseTimer() { for (auto e : pool) (void)hipEventDestroy(e); }
+};
+
+struct Context {
+  ctm_config cfg{};
+  PhaseTimer timer;
+  int Lx = 0, Ly = 0, N = 0;
+  int D = 0, d = 0, DK = 0, DB = 0, Db = 0, chi = 0, n = 0, layers = 2;
+  int kk = 0;               // sketch width
+  double cutoff = 1e-12;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  Linalg* la = nullptr;
+  std::string err;
+  long long moves = 0;
+
+  // site tensors, four rotations each: [rot][site][...]
+  DevBuf Aket, Abra;
+  long szk = 0, szb = 0;    // elements per site tensor (ket / bra)
+  // environment: [site][k][...]
+  DevBuf envC, envTa, envTb;
+  // leg dims (host): cdim[site][k][0..1] = (next, prev); tdim[site][k][0..1] = (prev, next)
+  std::vector<std::array<std::array<int, 2>, 4>> cdim, tdim;
+
+  // absorption offset tables
+  DevBuf ketA_r, ketA_c, ketC_r, ketC_c, braB_r, braB_c, braCn_r, braCn_c, braCt_r, braCt_c;
+
+  // workspaces
+  DevBuf G[4], X1, X2, Ybuf;
+  DevBuf pan[8];             // n x kk panels
+  DevBuf small[6];           // kk x kk
+  DevBuf Svals, wvec, keff, badflag, redscratch, delta;
+  DevBuf Pt, PT, P3;         // [Ly][n][chi]
+  DevBuf newC1, newT4, newC4;
+  DevBuf spec, specprev, cornerscratch;
+  DevBuf gws;                // GEMM split-K workspace
+  size_t gws_elems = 0;
+  Arena arena;
+  std::vector<int> nact_cut; // per cut of the current column: bond dim after the move
+  bool last_cut_svd = false; // the last cut_projectors() call went through the SVD
+
+  // helpers
+  double* C(int s, int k) const { return envC.as<double>() + ((long)s * 4 + k) * chi * chi; }
+  double* Ta(int s, int k) const { return envTa.as<double>() + ((long)s * 4 + k) * chi * chi * Db; }
+  double* Tb(int s, int k) const { return envTb.as<double>() + ((long)s * 4 + k) * chi * chi * Db; }
+  const double* Ak(int rot, int s) const { return Aket.as<double>() + ((long)rot * N + s) * szk; }
+  const double* Ab(int rot, int s) const { return Abra.as<double>() + ((long)rot * N + s) * szb; }
+  GemmWorkspace ws() const { return GemmWorkspace{gws.as<double>(), gws_elems}; }
+};
+
+// Run f (which enqueues work on c.st) inside a timed region of `phase`.
+template <typename F>
+inline void timed(Context& c, int phase, double flops, F&& f) {
+  if (!c.timer.on) {
+    f();
+    return;
+  }
+  hipEvent_t a = c.timer.get(), b = c.timer.get();
+  CTM_HIP(hipEventRecord(a, c.st));
+  f();
+  CTM_HIP(hipEventRecord(b, c.st));
+  c.timer.recs.push_back({phase, a, b, flops});
+}
+
+void context_init(Context& c, const ctm_config& cfg, const double* tensors, int on_device,
+                  const double* boundary);
+size_t context_footprint(const ctm_config& cfg);
+void do_move(Context& c, int rot);
+void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta, int* converged);
+void cut_projectors(Context& c, int rot, int x, int y, int slot);
+void enlarged_corner(Context& c, int s, int j, double* out);
+// Reduced density matrices, normalised to trace 1, in the device buffer
+// rho_dev (d*d or d^4 doubles); copied to rho_host when it is not null.
+void rho_1site(Context& c, int site, double* rho_dev, double* rho_host);
+void rho_2site(Context& c, int site, int dir, double* rho_dev, double* rho_host);
+// sum_{i,o} rho[i][o] op[o][i] for a dim x dim operator (host), on the device.
+double expect_op(Context& c, const double* rho_dev, const double* op_host, int dim);
+double impurity(Context& c, int site, const double* b_host);
+double log_kappa(Context& c);
+void check_bad(Context& c, const char* where);
+
+}  // namespace ctm

@@ -1,0 +1,251 @@
+// MFMA GEMM for gfx950 with strided / table-addressed operands (see gemm.hpp).
+//
+// Tiling: 256 threads = 4 wave64s per workgroup, output tile BM x BN, K step
+// BK = 16 (FP64).  A and B tiles are staged through LDS as As[m][k] and
+// Bs[n][k] (k contiguous, one padding element per row so that both the
+// transposing stores and the MFMA fragment reads are free of bank conflicts),
+// double buffered with the next tile's global loads in flight during the
+// MFMAs.  Each wave owns a WM x WN sub-tile of 16x16 MFMA blocks.
+//
+// FP64 uses v_mfma_f64_16x16x4f64: lane l supplies A[l%16][k] and B[k][l%16]
+// for k-slot l/16, and holds D[(l/16) + 4r][l%16] in register r.  Within a K
+// step of 16 the four MFMAs take k = 4*(l/16) + s (s = 0..3), so each lane
+// reads its four A (B) values as one contiguous 32-byte LDS run.
+#include "gemm.hpp"
+
+#include <algorithm>
+
+namespace ctm {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct KArgs {
+  const double* A;
+  const double* B;
+  double* C;
+  long sa0, sa1, sb0, sb1, sc0, sc1;
+  const int *ta0, *ta1, *tb0, *tb1, *tc0, *tc1;
+  long bsa, bsb, bsc;
+  int M, N, K;
+  double alpha, beta;
+  int splits, kchunk;   // split-K: each split covers kchunk of K (multiple of BK)
+  double* ws;           // partials [split][batch][M][N] when splits > 1
+  int batch;
+};
+
+__device__ __forceinline__ long off0(const int* t, long s, int i) { return t ? (long)t[i] : (long)i * s; }
+
+template <int BM, int BN, int WAVES_M, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
+  constexpr int BK = 16;
+  constexpr int LDK = BK + 1;
+  constexpr int WAVES_N = 4 / WAVES_M;
+  constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  static_assert(TM >= 1 && TN >= 1 && EA >= 1 && EB >= 1, "tile");
+  __shared__ double As[2][BM * LDK];
+  __shared__ double Bs[2][BN * LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int tm_ = blockIdx.x / tiles_n, tn_ = blockIdx.x % tiles_n;
+  const int split = blockIdx.y, b = blockIdx.z;
+  const int m0 = tm_ * BM, n0 = tn_ * BN;
+  const int kb = split * g.kchunk;
+  const int ke = min(g.K, kb + g.kchunk);
+  const double* A = g.A + (long)b * g.bsa;
+  const double* B = g.B + (long)b * g.bsb;
+
+  // ---- per-thread load coordinates ------------------------------------
+  // A tile element (r, kk): A_KC -> threads walk k fastest, else m fastest.
+  int a_r[EA], a_k[EA];
+  long a_roff[EA];
+  bool a_rok[EA];
+#pragma unroll
+  for (int j = 0; j < EA; ++j) {
+    int e = tid + 256 * j;
+    if (A_KC) { a_k[j] = e % BK; a_r[j] = e / BK; }
+    else      { a_r[j] = e % BM; a_k[j] = e / BM; }
+    int m = m0 + a_r[j];
+    a_rok[j] = m < g.M;
+    a_roff[j] = a_rok[j] ? off0(g.ta0, g.sa0, m) : 0;
+  }
+  int b_c[EB], b_k[EB];
+  long b_coff[EB];
+  bool b_cok[EB];
+#pragma unroll
+  for (int j = 0; j < EB; ++j) {
+    int e = tid + 256 * j;
+    if (B_KC) { b_k[j] = e % BK; b_c[j] = e / BK; }
+    else      { b_c[j] = e % BN; b_k[j] = e / BN; }
+    int n = n0 + b_c[j];
+    b_cok[j] = n < g.N;
+    b_coff[j] = b_cok[j] ? off0(g.tb1, g.sb1, n) : 0;
+  }
+
+  double ra[EA], rb[EB];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < EA; ++j) {
+      int k = k0 + a_k[j];
+      ra[j] = (a_rok[j] && k < ke) ? A[a_roff[j] + off0(g.ta1, g.sa1, k)] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < EB; ++j) {
+      int k = k0 + b_k[j];
+      rb[j] = (b_cok[j] && k < ke) ? B[b_coff[j] + off0(g.tb0, g.sb0, k)] : 0.0;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < EA; ++j) As[buf][a_r[j] * LDK + a_k[j]] = ra[j];
+#pragma unroll
+    for (int j = 0; j < EB; ++j) Bs[buf][b_c[j] * LDK + b_k[j]] = rb[j];
+  };
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+  const int r16 = lane & 15, kg = lane >> 4;
+
+  int nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
+  if (nk > 0) {
+    load_tile(kb);
+    store_tile(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
+    double af[TM][4], bf[TN][4];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) af[i][s] = As[cur][(wm0 + i * 16 + r16) * LDK + 4 * kg + s];
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) bf[j][s] = Bs[cur][(wn0 + j * 16 + r16) * LDK + 4 * kg + s];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+    if (it + 1 < nk) store_tile(cur ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue ----------------------------------------------------------
+  double* C = g.C + (long)b * g.bsc;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int m = m0 + wm0 + i * 16 + kg + 4 * r;
+        int n = n0 + wn0 + j * 16 + r16;
+        if (m < g.M && n < g.N) {
+          double v = g.alpha * acc[i][j][r];
+          if (g.splits > 1) {
+            g.ws[(((long)split * g.batch + b) * g.M + m) * g.N + n] = v;
+          } else {
+            long o = off0(g.tc0, g.sc0, m) + off0(g.tc1, g.sc1, n);
+            C[o] = (g.beta == 0.0) ? v : v + g.beta * C[o];
+          }
+        }
+      }
+}
+
+// Sum the split-K partials in split order (deterministic) into C.
+__global__ void splitk_reduce(KArgs g) {
+  long total = (long)g.batch * g.M * g.N;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    int n = (int)(e % g.N);
+    long t = e / g.N;
+    int m = (int)(t % g.M);
+    int b = (int)(t / g.M);
+    double s = 0.0;
+    for (int k = 0; k < g.splits; ++k) s += g.ws[(((long)k * g.batch + b) * g.M + m) * g.N + n];
+    double* C = g.C + (long)b * g.bsc;
+    long o = off0(g.tc0, g.sc0, m) + off0(g.tc1, g.sc1, n);
+    C[o] = (g.beta == 0.0) ? s : s + g.beta * C[o];
+  }
+}
+
+template <int BM, int BN, int WAVES_M>
+void launch_f64(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
+  if (a_kc && b_kc)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, true, true>), grid, dim3(256), 0, st, g);
+  else if (a_kc && !b_kc)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, true, false>), grid, dim3(256), 0, st, g);
+  else if (!a_kc && b_kc)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, false, true>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, false, false>), grid, dim3(256), 0, st, g);
+}
+
+// Choose the split of K so that a small output grid still fills the GPU.
+int choose_splits(long tiles, int K) {
+  const long target = 1024;   // ~4 workgroups per CU on 256 CUs
+  if (tiles >= target / 2) return 1;
+  int s = (int)std::min<long>((target + tiles - 1) / tiles, (long)K / 256);
+  return std::max(1, std::min(s, 16));
+}
+
+}  // namespace
+
+size_t gemm_workspace_elems(int M, int N, int K, int batch) {
+  long tiles = (long)ceil_div(M, 64) * ceil_div(N, 64) * batch;
+  int s = choose_splits(tiles, K);
+  return s > 1 ? (size_t)s * batch * M * N : 0;
+}
+
+void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, const Operand& A,
+          const Operand& B, double beta, const OutOperand& C, int batch, const GemmWorkspace& ws) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  CTM_CHECK(type == GemmType::F64, -1, "gemm: only FP64 is built in this path");
+  KArgs g{};
+  g.A = static_cast<const double*>(A.p);
+  g.B = static_cast<const double*>(B.p);
+  g.C = static_cast<double*>(C.p);
+  g.sa0 = A.s0; g.sa1 = A.s1; g.ta0 = A.t0; g.ta1 = A.t1; g.bsa = A.bs;
+  g.sb0 = B.s0; g.sb1 = B.s1; g.tb0 = B.t0; g.tb1 = B.t1; g.bsb = B.bs;
+  g.sc0 = C.s0; g.sc1 = C.s1; g.tc0 = C.t0; g.tc1 = C.t1; g.bsc = C.bs;
+  g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.beta = beta; g.batch = batch;
+  if (K <= 0) {   // C = beta * C
+    g.splits = 1; g.kchunk = 1;
+  }
+  // k contiguous in memory -> walk k fastest when loading
+  const bool a_kc = (A.t1 == nullptr && A.s1 == 1);
+  const bool b_kc = (B.t0 == nullptr && B.s0 == 1);
+  // tile shape: narrow N (sketch panels, bond-sized outputs) -> tall tiles
+  int BM = 64, BN = 64;
+  if (N <= 48) { BM = 128; BN = 32; }
+  long tiles = (long)ceil_div(M, BM) * ceil_div(N, BN) * batch;
+  int splits = (K > 0) ? choose_splits(tiles, K) : 1;
+  if (splits > 1 && (ws.p == nullptr || ws.elems < (size_t)splits * batch * M * N)) splits = 1;
+  int kchunk = (K > 0) ? ((ceil_div(K, splits) + 15) / 16) * 16 : 16;
+  splits = (K > 0) ? ceil_div(K, kchunk) : 1;
+  g.splits = splits; g.kchunk = kchunk; g.ws = ws.p;
+  dim3 grid((unsigned)(ceil_div(M, BM) * ceil_div(N, BN)), (unsigned)splits, (unsigned)batch);
+  if (BN == 32) launch_f64<128, 32, 4>(st, g, a_kc, b_kc, grid);
+  else          launch_f64<64, 64, 2>(st, g, a_kc, b_kc, grid);
+  CTM_HIP(hipGetLastError());
+  if (splits > 1) {
+    long total = (long)batch * M * N;
+    int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, st, g);
+    CTM_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace ctm

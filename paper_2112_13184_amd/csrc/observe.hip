@@ -1,0 +1,252 @@
+// Expectation values from the converged environment (Sec. 4.5 of arXiv:2112.13184).
+//
+// Each quantity is a ratio of contractions of one finite patch (3x3 for one
+// site, 3x4 / 4x3 for a bond), so the normalisation of C and T drops out.  The
+// patch is contracted column by column: left boundary LB[t1][l][t3] = C1 T4 C4,
+// one column per site (T1 above, ket then bra site tensor, T3 below), right
+// boundary RB[t1][r][t3] = C2 T2 C3.  Contractions are permute + MFMA GEMM
+// (tensordot) on transient buffers; all of it runs once per solve.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "context.hpp"
+#include "kernels.hpp"
+
+namespace ctm {
+namespace {
+
+inline int mod(int a, int b) { return ((a % b) + b) % b; }
+
+int view_site(const Context& c, int rot, int xv, int yv) {
+  int x = xv, y = yv;
+  for (int i = 0; i < rot; ++i) { int t = x; x = y; y = -t; }
+  return mod(x, c.Lx) + c.Lx * mod(y, c.Ly);
+}
+
+DT make(double* p, std::vector<long> dims) { DT t; t.p = p; t.dims = std::move(dims); return t; }
+
+DT transpose(Context& c, const DT& A, const std::vector<int>& perm) {
+  bool ident = true;
+  for (size_t i = 0; i < perm.size(); ++i) ident &= (perm[i] == (int)i);
+  if (ident) return A;
+  DT out;
+  out.dims.resize(perm.size());
+  for (size_t i = 0; i < perm.size(); ++i) out.dims[i] = A.dims[perm[i]];
+  out.p = c.arena.alloc(A.size());
+  permute(c.st, A.p, out.p, (int)A.dims.size(), A.dims.data(), perm.data());
+  return out;
+}
+
+// numpy.tensordot(A, B, axes=(axA, axB)): free axes of A, then free axes of B.
+DT tdot(Context& c, const DT& A, const std::vector<int>& axA, const DT& B, const std::vector<int>& axB) {
+  std::vector<int> fa, fb;
+  for (int i = 0; i < (int)A.dims.size(); ++i)
+    if (std::find(axA.begin(), axA.end(), i) == axA.end()) fa.push_back(i);
+  for (int i = 0; i < (int)B.dims.size(); ++i)
+    if (std::find(axB.begin(), axB.end(), i) == axB.end()) fb.push_back(i);
+  std::vector<int> pa = fa, pb = axB;
+  pa.insert(pa.end(), axA.begin(), axA.end());
+  pb.insert(pb.end(), fb.begin(), fb.end());
+  DT Ap = transpose(c, A, pa), Bp = transpose(c, B, pb);
+  long M = 1, K = 1, N = 1;
+  std::vector<long> od;
+  for (int i : fa) { M *= A.dims[i]; od.push_back(A.dims[i]); }
+  for (size_t i = 0; i < axA.size(); ++i) {
+    CTM_CHECK(A.dims[axA[i]] == B.dims[axB[i]], -1, "tdot: contracted dims differ");
+    K *= A.dims[axA[i]];
+  }
+  for (int i : fb) { N *= B.dims[i]; od.push_back(B.dims[i]); }
+  DT out;
+  out.dims = od;
+  out.p = c.arena.alloc((size_t)std::max<long>(M * N, 1));
+  gemm(c.st, GemmType::F64, (int)M, (int)N, (int)K, 1.0, rowmajor(Ap.p, K), rowmajor(Bp.p, N), 0.0,
+       out_rowmajor(out.p, N), 1, c.ws());
+  return out;
+}
+
+struct View {
+  DT C[4], T[4], Ak, Ab;
+};
+
+View view_of(Context& c, int s, int rot) {
+  View v;
+  const long chi = c.chi, Db = c.Db;
+  for (int m = 0; m < 4; ++m) {
+    v.C[m] = make(c.C(s, (m + rot) % 4), {chi, chi});
+    v.T[m] = make(c.Ta(s, (m + rot) % 4), {chi, chi, Db});
+  }
+  v.Ak = make(const_cast<double*>(c.Ak(rot, s)), {c.DK, c.DK, c.DK, c.DK, c.d});
+  v.Ab = make(const_cast<double*>(c.Ab(rot, s)), {c.DB, c.DB, c.DB, c.DB, c.d});
+  return v;
+}
+
+DT left_boundary(Context& c, const View& v) {
+  DT X = tdot(c, v.C[0], {1}, v.T[3], {1});     // C1[t1][a] T4[b][a][l] -> [t1][b][l]
+  return tdot(c, X, {1}, v.C[3], {0});           // C4[b][t3] -> [t1][l][t3]
+}
+
+DT right_boundary(Context& c, const View& v) {
+  DT X = tdot(c, v.C[1], {0}, v.T[1], {0});     // C2[a][t1] T2[a][b][r] -> [t1][b][r]
+  return tdot(c, X, {1}, v.C[2], {1});           // C3[t3][b] -> [t1][r][t3]
+}
+
+// LB[t1][Lp][t3][e...] through the column of one site; open: append (p, p').
+DT column(Context& c, const DT& LB, const DT& T1, const DT& T3, const DT& Ak, const DT& Ab, bool open) {
+  const int ne = (int)LB.dims.size() - 3;
+  const long DK = c.DK, DB = c.DB;
+  DT X = tdot(c, LB, {0}, T1, {0});              // [Lp, t3, e.., t1', U]
+  std::vector<long> xd = {DK, DB};
+  for (int i = 1; i < (int)X.dims.size() - 1; ++i) xd.push_back(X.dims[i]);
+  xd.push_back(DK);
+  xd.push_back(DB);
+  X.dims = xd;                                   // [Lk, Lb, t3, e.., t1', Uk, Ub]
+  DT Y = tdot(c, X, {0, 4 + ne}, Ak, {0, 1});    // [Lb, t3, e.., t1', Ub, Rk, Dk, p]
+  DT Z;
+  std::vector<int> perm;
+  if (!open) {
+    Z = tdot(c, Y, {0, 3 + ne, 6 + ne}, Ab, {0, 1, 4});   // [t3, e.., t1', Rk, Dk, Rb, Db]
+    perm = {1 + ne, 2 + ne, 4 + ne, 0, 3 + ne, 5 + ne};
+    for (int i = 1; i <= ne; ++i) perm.push_back(i);
+  } else {
+    Z = tdot(c, Y, {0, 3 + ne}, Ab, {0, 1});              // [t3, e.., t1', Rk, Dk, p, Rb, Db, p']
+    perm = {1 + ne, 2 + ne, 5 + ne, 0, 3 + ne, 6 + ne};
+    for (int i = 1; i <= ne; ++i) perm.push_back(i);
+    perm.push_back(4 + ne);
+    perm.push_back(7 + ne);
+  }
+  Z = transpose(c, Z, perm);                     // [t1', Rk, Rb, t3, Dk, Db, e.., (p, p')]
+  std::vector<long> zd = {Z.dims[0], DK * DB, Z.dims[3], DK * DB};
+  for (size_t i = 6; i < Z.dims.size(); ++i) zd.push_back(Z.dims[i]);
+  Z.dims = zd;                                   // [t1', R, t3, Dd, e.., (p, p')]
+  DT W = tdot(c, Z, {2, 3}, T3, {1, 2});         // [t1', R, e.., (p, p'), t3']
+  std::vector<int> p2 = {0, 1, (int)W.dims.size() - 1};
+  for (int i = 2; i < (int)W.dims.size() - 1; ++i) p2.push_back(i);
+  return transpose(c, W, p2);                    // [t1', R, t3', e.., (p, p')]
+}
+
+DT close_lr(Context& c, const DT& X, const DT& RB) { return tdot(c, X, {0, 1, 2}, RB, {0, 1, 2}); }
+
+__global__ void k_trace_normalize(const double* in, double* out, int dim) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < dim; ++i) tr += in[i * dim + i];
+    for (int i = 0; i < dim * dim; ++i) out[i] = in[i] / tr;
+  }
+}
+
+__global__ void k_expect(const double* rho, const double* op, int dim, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < dim; ++i)
+      for (int o = 0; o < dim; ++o) s += rho[i * dim + o] * op[o * dim + i];
+    *out = s;
+  }
+}
+
+// ln |z33 zc / (z23 z32)| and z_b / z_a
+__global__ void k_logkappa(const double* z33, const double* zc, const double* z23, const double* z32, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = log(fabs(*z33)) + log(fabs(*zc)) - log(fabs(*z23)) - log(fabs(*z32));
+}
+__global__ void k_ratio(const double* a, const double* b, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = *a / *b;
+}
+
+double fetch_scalar(Context& c, const double* dev) {
+  double h = 0.0;
+  CTM_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, c.st));
+  CTM_HIP(hipStreamSynchronize(c.st));
+  return h;
+}
+
+}  // namespace
+
+void rho_1site(Context& c, int site, double* rho_dev, double* rho_host) {
+  c.arena.reset();
+  View v = view_of(c, site, 0);
+  DT LB = left_boundary(c, v), RB = right_boundary(c, v);
+  DT X = column(c, LB, v.T[0], v.T[2], v.Ak, v.Ab, true);
+  DT R = close_lr(c, X, RB);                     // [p, p']
+  hipLaunchKernelGGL(k_trace_normalize, dim3(1), dim3(64), 0, c.st, R.p, rho_dev, c.d);
+  CTM_HIP(hipGetLastError());
+  if (rho_host) {
+    CTM_HIP(hipMemcpyAsync(rho_host, rho_dev, sizeof(double) * c.d * c.d, hipMemcpyDeviceToHost, c.st));
+    CTM_HIP(hipStreamSynchronize(c.st));
+  }
+}
+
+void rho_2site(Context& c, int site, int dir, double* rho_dev, double* rho_host) {
+  c.arena.reset();
+  const int rot = (dir == 0) ? 0 : 3;   // +y becomes +x three quarter turns on
+  int x = site % c.Lx, y = site / c.Lx;
+  for (int i = 0; i < rot; ++i) { int t = x; x = -y; y = t; }
+  const int s = view_site(c, rot, x, y), t = view_site(c, rot, x + 1, y);
+  CTM_CHECK(s == site, -3, "rho_2site: view bookkeeping");
+  View vs = view_of(c, s, rot), vt = view_of(c, t, rot);
+  DT LB = left_boundary(c, vs), RB = right_boundary(c, vt);
+  DT X = column(c, LB, vs.T[0], vs.T[2], vs.Ak, vs.Ab, true);
+  X = column(c, X, vt.T[0], vt.T[2], vt.Ak, vt.Ab, true);
+  DT R = close_lr(c, X, RB);                     // [ps, ps', pt, pt']
+  R = transpose(c, R, {0, 2, 1, 3});             // [(ps, pt), (ps', pt')]
+  const int dim = c.d * c.d;
+  hipLaunchKernelGGL(k_trace_normalize, dim3(1), dim3(64), 0, c.st, R.p, rho_dev, dim);
+  CTM_HIP(hipGetLastError());
+  if (rho_host) {
+    CTM_HIP(hipMemcpyAsync(rho_host, rho_dev, sizeof(double) * dim * dim, hipMemcpyDeviceToHost, c.st));
+    CTM_HIP(hipStreamSynchronize(c.st));
+  }
+}
+
+double expect_op(Context& c, const double* rho_dev, const double* op_host, int dim) {
+  double* op = c.arena.alloc((size_t)dim * dim + 1);
+  CTM_HIP(hipMemcpyAsync(op, op_host, sizeof(double) * dim * dim, hipMemcpyHostToDevice, c.st));
+  hipLaunchKernelGGL(k_expect, dim3(1), dim3(64), 0, c.st, rho_dev, op, dim, op + dim * dim);
+  CTM_HIP(hipGetLastError());
+  return fetch_scalar(c, op + dim * dim);
+}
+
+double impurity(Context& c, int site, const double* b_host) {
+  c.arena.reset();
+  View v = view_of(c, site, 0);
+  const long szb = (long)c.DK * c.DK * c.DK * c.DK;
+  double* bd = c.arena.alloc(szb);
+  CTM_HIP(hipMemcpyAsync(bd, b_host, sizeof(double) * szb, hipMemcpyHostToDevice, c.st));
+  DT B = make(bd, {c.DK, c.DK, c.DK, c.DK, 1});
+  DT LB = left_boundary(c, v), RB = right_boundary(c, v);
+  DT za = close_lr(c, column(c, LB, v.T[0], v.T[2], v.Ak, v.Ab, false), RB);
+  DT zb = close_lr(c, column(c, LB, v.T[0], v.T[2], B, v.Ab, false), RB);
+  double* r = c.arena.alloc(1);
+  hipLaunchKernelGGL(k_ratio, dim3(1), dim3(64), 0, c.st, zb.p, za.p, r);
+  CTM_HIP(hipGetLastError());
+  return fetch_scalar(c, r);
+}
+
+double log_kappa(Context& c) {
+  c.arena.reset();
+  View v = view_of(c, 0, 0);
+  DT LB = left_boundary(c, v), RB = right_boundary(c, v);
+  DT z33 = close_lr(c, column(c, LB, v.T[0], v.T[2], v.Ak, v.Ab, false), RB);
+  // corners only: trace(C2 C1 C4 C3)
+  DT X = tdot(c, v.C[1], {1}, v.C[0], {0});
+  X = tdot(c, X, {1}, v.C[3], {0});
+  DT zc = tdot(c, X, {0, 1}, v.C[2], {1, 0});
+  // two rows, three columns
+  DT LB0 = tdot(c, v.C[0], {1}, v.C[3], {0});    // [t1][t3]
+  DT RB0 = tdot(c, v.C[1], {0}, v.C[2], {1});    // [t1'][t3']
+  DT Y = tdot(c, LB0, {0}, v.T[0], {0});         // [t3][t1'][u]
+  Y = tdot(c, Y, {0, 2}, v.T[2], {1, 2});        // [t1'][t3']
+  DT z23 = tdot(c, Y, {0, 1}, RB0, {0, 1});
+  // three rows, two columns
+  DT L = tdot(c, v.C[0], {1}, v.T[3], {1});      // [t][b][l]
+  L = tdot(c, L, {1}, v.C[3], {0});              // [t][l][s]
+  DT R = tdot(c, v.C[1], {0}, v.T[1], {0});      // [t][e][l]
+  R = tdot(c, R, {1}, v.C[2], {1});              // [t][l][s]
+  DT z32 = tdot(c, L, {0, 1, 2}, R, {0, 1, 2});
+  double* out = c.arena.alloc(1);
+  hipLaunchKernelGGL(k_logkappa, dim3(1), dim3(64), 0, c.st, z33.p, zc.p, z23.p, z32.p, out);
+  CTM_HIP(hipGetLastError());
+  return fetch_scalar(c, out);
+}
+
+}  // namespace ctm

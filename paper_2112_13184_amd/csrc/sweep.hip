@@ -1,0 +1,547 @@
+// Directional moves and sweeps of the CTMRG (Sec. 2.2 of arXiv:2112.13184).
+//
+// Layout in HBM (FP64, zero padded to chi on every chi leg):
+//   envC [site][k][chi][chi]          C_k[next][prev]
+//   envTa[site][k][chi][chi][Db]      T_k[prev][next][pair]   (edge as "next" of a corner)
+//   envTb[site][k][chi][Db][chi]      T_k[prev][pair][next]   (edge as "prev" of a corner)
+//   Aket / Abra [rot][site][...]      site tensor seen from corner rot (rotated rot
+//                                     quarter turns counter-clockwise)
+// Both edge layouts are kept so that every edge contraction is a plain GEMM.
+//
+// A move in direction `rot` is a left move on the lattice rotated rot quarter
+// turns: view corner m is physical corner (m + rot) % 4, the same for edges.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "context.hpp"
+#include "kernels.hpp"
+
+namespace ctm {
+
+namespace {
+
+inline int mod(int a, int b) { return ((a % b) + b) % b; }
+
+// Physical site of view position (xv, yv) in the frame rotated rot quarter turns.
+int view_site(const Context& c, int rot, int xv, int yv) {
+  int x = xv, y = yv;
+  for (int i = 0; i < rot; ++i) { int t = x; x = y; y = -t; }
+  return mod(x, c.Lx) + c.Lx * mod(y, c.Ly);
+}
+
+void view_dims(const Context& c, int rot, int& Lxv, int& Lyv) {
+  Lxv = (rot % 2 == 0) ? c.Lx : c.Ly;
+  Lyv = (rot % 2 == 0) ? c.Ly : c.Lx;
+}
+
+uint64_t stream_id(long long move, int x, int y) {
+  return ((uint64_t)(move & 0xFFFFFFFFll) << 32) | ((uint64_t)(x & 0xFFFF) << 16) | (uint64_t)(y & 0xFFFF);
+}
+
+// Rotate a site tensor t[l][u][r][d][p] (dims Dd) one quarter turn
+// counter-clockwise: out[a][b][c][e][p] = in[e][a][b][c][p].
+void rotate_host(const std::vector<double>& in, std::vector<double>& out, int Dd, int d) {
+  out.resize(in.size());
+  for (int a = 0; a < Dd; ++a)
+    for (int b = 0; b < Dd; ++b)
+      for (int cc = 0; cc < Dd; ++cc)
+        for (int e = 0; e < Dd; ++e)
+          for (int p = 0; p < d; ++p)
+            out[(((a * Dd + b) * Dd + cc) * Dd + e) * d + p] = in[(((e * Dd + a) * Dd + b) * Dd + cc) * d + p];
+}
+
+void upload_tables(DevBuf& buf, const std::vector<int>& v) {
+  buf.alloc(v.size() * sizeof(int));
+  CTM_HIP(hipMemcpy(buf.p, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
+}
+
+// Offset tables of the two absorption GEMMs (see absorb()).
+void build_tables(Context& c) {
+  const int chi = c.chi, DK = c.DK, DB = c.DB, Db = c.Db, d = c.d;
+  const long n = c.n;
+  std::vector<int> v;
+  // ket: rows m = (cp, l', cn, u'), k = (l, u), cols = (r, dd, p)
+  v.resize((size_t)chi * DB * chi * DB);
+  for (int cp = 0; cp < chi; ++cp)
+    for (int lb = 0; lb < DB; ++lb)
+      for (int cn = 0; cn < chi; ++cn)
+        for (int ub = 0; ub < DB; ++ub)
+          v[(((size_t)cp * DB + lb) * chi + cn) * DB + ub] = (int)((cp * (long)Db + lb) * n + cn * (long)Db + ub);
+  upload_tables(c.ketA_r, v);
+  v.resize((size_t)DK * DK);
+  for (int l = 0; l < DK; ++l)
+    for (int u = 0; u < DK; ++u) v[l * DK + u] = (int)(l * (long)DB * n + u * DB);
+  upload_tables(c.ketA_c, v);
+  const long ldy = (long)DB * DB * d;
+  v.resize((size_t)chi * DB * chi * DB);
+  for (int cp = 0; cp < chi; ++cp)
+    for (int lb = 0; lb < DB; ++lb)
+      for (int cn = 0; cn < chi; ++cn)
+        for (int ub = 0; ub < DB; ++ub)
+          v[(((size_t)cp * DB + lb) * chi + cn) * DB + ub] =
+              (int)((cp * (long)chi + cn) * DK * DK * ldy + (lb * DB + ub) * d);
+  upload_tables(c.ketC_r, v);
+  v.resize((size_t)DK * DK * d);
+  for (int r = 0; r < DK; ++r)
+    for (int dd = 0; dd < DK; ++dd)
+      for (int p = 0; p < d; ++p) v[(r * DK + dd) * d + p] = (int)((r * DK + dd) * ldy + p);
+  upload_tables(c.ketC_c, v);
+  // bra: rows m = (cp, cn, r, dd) (plain in Y), k = (l', u', p), cols = (r', d')
+  v.resize((size_t)DB * DB * d);
+  for (int lb = 0; lb < DB; ++lb)
+    for (int ub = 0; ub < DB; ++ub)
+      for (int p = 0; p < d; ++p) v[(lb * DB + ub) * d + p] = (int)((lb * DB + ub) * (long)DB * DB * d + p);
+  upload_tables(c.braB_r, v);
+  v.resize((size_t)DB * DB);
+  for (int rb = 0; rb < DB; ++rb)
+    for (int db = 0; db < DB; ++db) v[rb * DB + db] = (rb * DB + db) * d;
+  upload_tables(c.braB_c, v);
+  std::vector<int> vn((size_t)chi * chi * DK * DK), vt(vn.size());
+  for (int cp = 0; cp < chi; ++cp)
+    for (int cn = 0; cn < chi; ++cn)
+      for (int r = 0; r < DK; ++r)
+        for (int dd = 0; dd < DK; ++dd) {
+          size_t m = (((size_t)cp * chi + cn) * DK + r) * DK + dd;
+          vn[m] = (int)((cn * (long)Db + r * DB) * n + cp * (long)Db + dd * DB);
+          vt[m] = (int)((cp * (long)Db + dd * DB) * n + cn * (long)Db + r * DB);
+        }
+  upload_tables(c.braCn_r, vn);
+  upload_tables(c.braCt_r, vt);
+  vn.assign((size_t)DB * DB, 0);
+  vt.assign((size_t)DB * DB, 0);
+  for (int rb = 0; rb < DB; ++rb)
+    for (int db = 0; db < DB; ++db) {
+      vn[rb * DB + db] = (int)(rb * n + db);
+      vt[rb * DB + db] = (int)(db * n + rb);
+    }
+  upload_tables(c.braCn_c, vn);
+  upload_tables(c.braCt_c, vt);
+}
+
+struct Sizes {
+  long n, nn, kk, chi, Db, y;
+  size_t total_bytes;
+};
+
+Sizes sizes_of(const ctm_config& cfg) {
+  Sizes s{};
+  int DK = cfg.D, DB = (cfg.layers == 2) ? cfg.D : 1;
+  s.Db = (long)DK * DB;
+  s.chi = cfg.chi;
+  s.n = s.chi * s.Db;
+  s.nn = s.n * s.n;
+  int p = cfg.rsvd_oversample;
+  s.kk = (p < 0) ? s.n : std::min<long>(s.chi + p, s.n);
+  int d = (cfg.layers == 2) ? cfg.d : 1;
+  s.y = s.nn * d;
+  long N = (long)cfg.Lx * cfg.Ly;
+  size_t b = 0;
+  b += 8 * (size_t)(4 * N * (s.chi * s.chi + 2 * s.chi * s.chi * s.Db));      // environment
+  b += 8 * (size_t)(4 * s.nn + s.nn + s.y + s.chi * s.n);                      // G, X2, Y, X1
+  b += 8 * (size_t)(8 * s.n * s.kk + 6 * s.kk * s.kk);                         // panels
+  b += 8 * (size_t)(3 * cfg.Ly * s.n * s.chi + cfg.Lx * s.n * s.chi);          // projectors
+  b += 8 * (size_t)(3 * std::max(cfg.Lx, cfg.Ly) * s.chi * s.chi * s.Db);      // staging
+  b += 4 * (size_t)(4 * s.chi * s.chi * DB * DB + 2 * s.chi * s.chi * DK * DK); // tables
+  b += 8 * (size_t)(8 * s.n * std::max(s.kk, s.chi));                         // split-K
+  s.total_bytes = b;
+  return s;
+}
+
+}  // namespace
+
+double* Arena::alloc(size_t elems) {
+  elems = ((elems + 31) / 32) * 32;
+  while (cur < chunks.size() && used + elems > chunks[cur]->bytes / sizeof(double)) {
+    ++cur;
+    used = 0;
+  }
+  if (cur == chunks.size()) {
+    DevBuf* b = new DevBuf();
+    try {
+      b->alloc(std::max(elems, (size_t)32 << 20) * sizeof(double));
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    chunks.push_back(b);
+    used = 0;
+  }
+  double* p = chunks[cur]->as<double>() + used;
+  used += elems;
+  return p;
+}
+
+size_t context_footprint(const ctm_config& cfg) { return sizes_of(cfg).total_bytes; }
+
+void check_bad(Context& c, const char* where) {
+  int bad = 0;
+  CTM_HIP(hipMemcpyAsync(&bad, c.badflag.p, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  CTM_HIP(hipStreamSynchronize(c.st));
+  if (bad) {
+    CTM_HIP(hipMemsetAsync(c.badflag.p, 0, sizeof(int), c.st));
+    throw Error(-4, std::string(where) + ": NaN/Inf or zero environment / cut");
+  }
+}
+
+void context_init(Context& c, const ctm_config& cfg, const double* tensors, int on_device,
+                  const double* boundary) {
+  c.cfg = cfg;
+  c.Lx = cfg.Lx; c.Ly = cfg.Ly; c.N = cfg.Lx * cfg.Ly;
+  c.layers = cfg.layers;
+  c.D = cfg.D;
+  c.d = (cfg.layers == 2) ? cfg.d : 1;
+  c.DK = cfg.D;
+  c.DB = (cfg.layers == 2) ? cfg.D : 1;
+  c.Db = c.DK * c.DB;
+  c.chi = cfg.chi;
+  c.n = c.chi * c.Db;
+  c.cutoff = (cfg.svd_rel_cutoff > 0) ? cfg.svd_rel_cutoff : 1e-12;
+  const Sizes sz = sizes_of(cfg);
+  c.kk = (int)sz.kk;
+
+  if (cfg.stream) {
+    c.st = (hipStream_t)cfg.stream;
+  } else {
+    CTM_HIP(hipStreamCreate(&c.st));
+    c.own_stream = true;
+  }
+  c.la = linalg_create(c.st);
+
+  // ---- site tensors and their rotations (host side, tiny) ---------------
+  c.szk = (long)c.DK * c.DK * c.DK * c.DK * c.d;
+  c.szb = (long)c.DB * c.DB * c.DB * c.DB * c.d;
+  std::vector<double> host((size_t)c.N * c.szk);
+  if (on_device) {
+    CTM_HIP(hipMemcpy(host.data(), tensors, host.size() * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    std::memcpy(host.data(), tensors, host.size() * sizeof(double));
+  }
+  for (double v : host) CTM_CHECK(std::isfinite(v), -4, "site tensor has NaN/Inf entries");
+  std::vector<double> ket((size_t)4 * c.N * c.szk), bra((size_t)4 * c.N * c.szb);
+  for (int s = 0; s < c.N; ++s) {
+    std::vector<double> t(host.begin() + (long)s * c.szk, host.begin() + (long)(s + 1) * c.szk), r;
+    for (int rot = 0; rot < 4; ++rot) {
+      std::copy(t.begin(), t.end(), ket.begin() + ((long)rot * c.N + s) * c.szk);
+      if (c.layers == 2)
+        std::copy(t.begin(), t.end(), bra.begin() + ((long)rot * c.N + s) * c.szb);
+      else
+        bra[(long)rot * c.N + s] = 1.0;
+      rotate_host(t, r, c.DK, c.d);
+      t.swap(r);
+    }
+  }
+  c.Aket.alloc(ket.size() * sizeof(double));
+  c.Abra.alloc(bra.size() * sizeof(double));
+  CTM_HIP(hipMemcpy(c.Aket.p, ket.data(), ket.size() * sizeof(double), hipMemcpyHostToDevice));
+  CTM_HIP(hipMemcpy(c.Abra.p, bra.data(), bra.size() * sizeof(double), hipMemcpyHostToDevice));
+
+  // ---- environment ------------------------------------------------------
+  const long cc = (long)c.chi * c.chi, tt = cc * c.Db;
+  c.envC.alloc(sizeof(double) * 4 * c.N * cc);
+  c.envTa.alloc(sizeof(double) * 4 * c.N * tt);
+  c.envTb.alloc(sizeof(double) * 4 * c.N * tt);
+  std::vector<double> hb(c.Db);
+  if (boundary) {
+    std::memcpy(hb.data(), boundary, sizeof(double) * c.Db);
+  } else if (c.layers == 2) {
+    for (int a = 0; a < c.D; ++a) hb[a * c.D + a] = 1.0;
+  } else {
+    std::fill(hb.begin(), hb.end(), 1.0);
+  }
+  std::vector<double> hc(4 * c.N * cc, 0.0), ht(4 * c.N * tt, 0.0);
+  for (int s = 0; s < 4 * c.N; ++s) {
+    hc[s * cc] = 1.0;
+    for (int b = 0; b < c.Db; ++b) ht[s * tt + b] = hb[b];   // T[0][0][b] in the [prev][next][pair] layout
+  }
+  CTM_HIP(hipMemcpy(c.envC.p, hc.data(), hc.size() * sizeof(double), hipMemcpyHostToDevice));
+  CTM_HIP(hipMemcpy(c.envTa.p, ht.data(), ht.size() * sizeof(double), hipMemcpyHostToDevice));
+  for (int s = 0; s < c.N; ++s)
+    for (int k = 0; k < 4; ++k) swap_last2(c.st, c.Ta(s, k), c.Tb(s, k), c.chi, c.chi, c.Db);
+  c.cdim.assign(c.N, {{{1, 1}, {1, 1}, {1, 1}, {1, 1}}});
+  c.tdim.assign(c.N, {{{1, 1}, {1, 1}, {1, 1}, {1, 1}}});
+
+  // ---- workspaces --------------------------------------------------------
+  build_tables(c);
+  for (auto& g : c.G) g.alloc(sizeof(double) * sz.nn);
+  c.X1.alloc(sizeof(double) * c.chi * c.n);
+  c.X2.alloc(sizeof(double) * sz.nn);
+  c.Ybuf.alloc(sizeof(double) * sz.y);
+  for (auto& p : c.pan) p.alloc(sizeof(double) * c.n * c.kk);
+  for (auto& p : c.small) p.alloc(sizeof(double) * (size_t)c.kk * c.kk);
+  c.Svals.alloc(sizeof(double) * std::max(c.kk, c.n));
+  c.wvec.alloc(sizeof(double) * c.chi);
+  c.keff.alloc(sizeof(int) * 64);
+  c.badflag.alloc(sizeof(int));
+  CTM_HIP(hipMemset(c.badflag.p, 0, sizeof(int)));
+  c.redscratch.alloc(sizeof(double) * 2048);
+  c.delta.alloc(sizeof(double));
+  int Lmax = std::max(c.Lx, c.Ly);
+  c.Pt.alloc(sizeof(double) * Lmax * c.n * c.chi);
+  c.PT.alloc(sizeof(double) * Lmax * c.n * c.chi);
+  c.P3.alloc(sizeof(double) * Lmax * c.n * c.chi);
+  c.newC1.alloc(sizeof(double) * Lmax * cc);
+  c.newC4.alloc(sizeof(double) * Lmax * cc);
+  c.newT4.alloc(sizeof(double) * Lmax * tt);
+  c.spec.alloc(sizeof(double) * 4 * c.N * c.chi);
+  c.specprev.alloc(sizeof(double) * 4 * c.N * c.chi);
+  c.cornerscratch.alloc(sizeof(double) * 4 * c.N * cc);
+  c.gws_elems = (size_t)8 * c.n * std::max(c.kk, c.chi);
+  c.gws.alloc(sizeof(double) * c.gws_elems);
+  c.nact_cut.assign(Lmax, c.chi);
+  CTM_HIP(hipStreamSynchronize(c.st));
+}
+
+// ----------------------------------------------------------------------------
+// Single-layer absorption of the site: out = X absorbed with ket then bra.
+//   ket: Y[(cp,cn,r,dd)][(l',u',p)] = sum_{l,u} X[(cp,l,l')][(cn,u,u')] Ak[l][u][r][dd][p]
+//   bra: out[(cn,r,r')][(cp,dd,d')] = sum_{l',u',p} Y[..][(l',u',p)] Ab[l'][u'][r'][d'][p]
+//        (transposed = true: out[(cp,dd,d')][(cn,r,r')])
+// ----------------------------------------------------------------------------
+// FP64 GEMM on the context stream, timed under `phase` when timing is on.
+static void mm(Context& c, int phase, int M, int N, int K, const Operand& A, const Operand& B,
+               const OutOperand& C, int batch = 1) {
+  timed(c, phase, 2.0 * M * N * (double)K * batch, [&] {
+    gemm(c.st, GemmType::F64, M, N, K, 1.0, A, B, 0.0, C, batch, c.ws());
+  });
+}
+
+static void absorb(Context& c, const double* X, const double* Ak, const double* Ab, double* out,
+                   bool transposed) {
+  const int chi = c.chi, DK = c.DK, DB = c.DB, d = c.d;
+  Operand A{};
+  A.p = X; A.t0 = c.ketA_r.as<int>(); A.t1 = c.ketA_c.as<int>();
+  Operand B = rowmajor(Ak, (long)DK * DK * d);
+  OutOperand Cy{};
+  Cy.p = c.Ybuf.p; Cy.t0 = c.ketC_r.as<int>(); Cy.t1 = c.ketC_c.as<int>();
+  mm(c, PhaseTimer::ABSORB, chi * DB * chi * DB, DK * DK * d, DK * DK, A, B, Cy);
+  Operand A2 = rowmajor(c.Ybuf.p, (long)DB * DB * d);
+  Operand B2{};
+  B2.p = Ab; B2.t0 = c.braB_r.as<int>(); B2.t1 = c.braB_c.as<int>();
+  OutOperand Co{};
+  Co.p = out;
+  Co.t0 = transposed ? c.braCt_r.as<int>() : c.braCn_r.as<int>();
+  Co.t1 = transposed ? c.braCt_c.as<int>() : c.braCn_c.as<int>();
+  mm(c, PhaseTimer::ABSORB, chi * chi * DK * DK, DB * DB, DB * DB * d, A2, B2, Co);
+}
+
+// Enlarged corner j of site s: G[(cn, o_n)][(cp, o_p)] (n x n, row-major).
+void enlarged_corner(Context& c, int s, int j, double* out) {
+  const int chi = c.chi;
+  const long n = c.n;
+  // X1[tp][(cn, i_n)] = sum_t C[t][tp] Tn[t][(cn, i_n)]
+  mm(c, PhaseTimer::OTHER, chi, (int)n, chi, colmajor(c.C(s, j), chi), rowmajor(c.Ta(s, j), n),
+     out_rowmajor(c.X1.p, n));
+  // X2[(cp, i_p)][(cn, i_n)] = sum_tp Tp[(cp, i_p)][tp] X1[tp][..]
+  mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, rowmajor(c.Tb(s, (j + 3) % 4), chi), rowmajor(c.X1.p, n),
+     out_rowmajor(c.X2.p, n));
+  absorb(c, c.X2.as<double>(), c.Ak(j, s), c.Ab(j, s), out, false);
+}
+
+namespace {
+
+// Y = M X with M = G_ur G_ul G_ll G_lr; panels column-major n x m.
+void apply_M(Context& c, double* const G[4], const double* X, double* Y, int m, double* t1, double* t2) {
+  const int n = c.n;
+  // G order: 0 = UL, 1 = UR, 2 = LR, 3 = LL
+  mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[2], n), colmajor(X, n), out_colmajor(t1, n));
+  mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[3], n), colmajor(t1, n), out_colmajor(t2, n));
+  mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[0], n), colmajor(t2, n), out_colmajor(t1, n));
+  mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[1], n), colmajor(t1, n), out_colmajor(Y, n));
+}
+
+// Z = M^T X; W (if not null) receives G_ul^T G_ur^T X.
+void apply_Mt(Context& c, double* const G[4], const double* X, double* Z, int m, double* t1, double* W) {
+  const int n = c.n;
+  mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[1], n), colmajor(X, n), out_colmajor(t1, n));
+  mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[0], n), colmajor(t1, n), out_colmajor(W, n));
+  mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[3], n), colmajor(W, n), out_colmajor(t1, n));
+  mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[2], n), colmajor(t1, n), out_colmajor(Z, n));
+}
+
+}  // namespace
+
+// Projectors of the cut (x, y) of a move in frame rot, into slot `slot` of
+// Pt / PT (n x chi, row-major each).  Records the new bond dimension.
+void cut_projectors(Context& c, int rot, int x, int y, int slot) {
+  const int chi = c.chi, n = c.n;
+  double* Pt = c.Pt.as<double>() + (long)slot * n * chi;
+  double* PT = c.PT.as<double>() + (long)slot * n * chi;
+  const int sUL = view_site(c, rot, x, y), sUR = view_site(c, rot, x + 1, y);
+  const int sLR = view_site(c, rot, x + 1, y - 1), sLL = view_site(c, rot, x, y - 1);
+  const int nact = c.tdim[sUL][(3 + rot) % 4][0] * c.Db;
+  if (nact <= chi) {   // nothing to discard: identity projectors
+    identity_panel(c.st, Pt, n, chi, nact);
+    identity_panel(c.st, PT, n, chi, nact);
+    c.nact_cut[slot] = nact;
+    c.last_cut_svd = false;
+    return;
+  }
+  c.nact_cut[slot] = chi;
+  c.last_cut_svd = true;
+  // structural rank bound: smallest bond of M = G_ur G_ul G_ll G_lr (actual dims)
+  int kcap = chi;
+  {
+    const int sites[4] = {sUL, sUR, sLR, sLL};
+    for (int q = 0; q < 4; ++q) {
+      const int j = (q + rot) % 4, s = sites[q];
+      kcap = std::min(kcap, c.tdim[s][j][1] * c.Db);             // next leg: T_j far end
+      kcap = std::min(kcap, c.tdim[s][(j + 3) % 4][0] * c.Db);   // prev leg: T_{j-1} far end
+    }
+  }
+  double* G[4] = {c.G[0].as<double>(), c.G[1].as<double>(), c.G[2].as<double>(), c.G[3].as<double>()};
+  enlarged_corner(c, sUL, (0 + rot) % 4, G[0]);
+  enlarged_corner(c, sUR, (1 + rot) % 4, G[1]);
+  enlarged_corner(c, sLR, (2 + rot) % 4, G[2]);
+  enlarged_corner(c, sLL, (3 + rot) % 4, G[3]);
+  double* P[8];
+  for (int i = 0; i < 8; ++i) P[i] = c.pan[i].as<double>();
+  double* S = c.Svals.as<double>();
+  double* w = c.wvec.as<double>();
+
+  if (c.cfg.rsvd_oversample < 0) {
+    // exact mode: form H_u, H_d^T and M explicitly, full SVD
+    double* Hu = c.X2.as<double>();
+    double* HdT = c.Ybuf.as<double>();
+    double* M = G[0];   // the corners are not needed once H_u and H_d^T exist
+    mm(c, PhaseTimer::SKETCH, n, n, n, rowmajor(G[1], n), rowmajor(G[0], n), out_rowmajor(Hu, n));
+    mm(c, PhaseTimer::SKETCH, n, n, n, rowmajor(G[3], n), rowmajor(G[2], n), out_rowmajor(HdT, n));
+    mm(c, PhaseTimer::SKETCH, n, n, n, rowmajor(Hu, n), rowmajor(HdT, n), out_colmajor(M, n));
+    // M column-major: M = U S V^T directly
+    double* U = P[0];
+    double* VT = P[1];
+    timed(c, PhaseTimer::LINALG, 0.0, [&] { la_svd(c.la, M, n, S, U, VT); });
+    // V (col-major) = VT^T
+    transpose_square(c.st, VT, P[2], n);
+    double* V = P[2];
+    projector_weights(c.st, S, U, n, n, chi, kcap, c.cutoff, w, c.keff.as<int>(), c.badflag.as<int>());
+    scale_columns(c.st, V, n, chi, w);
+    scale_columns(c.st, U, n, chi, w);
+    // Pt = H_d^T V' ; PT = H_u^T U'
+    mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(HdT, n), colmajor(V, n), out_rowmajor(Pt, chi));
+    mm(c, PhaseTimer::SKETCH, n, chi, n, colmajor(Hu, n), colmajor(U, n), out_rowmajor(PT, chi));
+    return;
+  }
+
+  const int kk = c.kk;
+  double *Y = P[0], *Z = P[1], *W = P[2], *t1 = P[3], *t2 = P[4], *V = P[5], *U = P[6];
+  const uint64_t sid = stream_id(c.moves, x, mod(y, (rot % 2 == 0) ? c.Ly : c.Lx));
+  omega_fill(c.st, Z, n, c.Db, kk, c.cfg.seed, sid);
+  apply_M(c, G, Z, Y, kk, t1, t2);
+  timed(c, PhaseTimer::LINALG, 0.0, [&] { la_orth(c.la, Y, n, kk); });
+  for (int q = 0; q < c.cfg.rsvd_power_iters; ++q) {
+    apply_Mt(c, G, Y, Z, kk, t1, W);
+    timed(c, PhaseTimer::LINALG, 0.0, [&] { la_orth(c.la, Z, n, kk); });
+    apply_M(c, G, Z, Y, kk, t1, t2);
+    timed(c, PhaseTimer::LINALG, 0.0, [&] { la_orth(c.la, Y, n, kk); });
+  }
+  apply_Mt(c, G, Y, Z, kk, t1, W);                 // Z = M^T Q = B^T, W = G_ul^T G_ur^T Q
+  double* R = c.small[0].as<double>();
+  double* Us = c.small[1].as<double>();
+  double* VTs = c.small[2].as<double>();
+  timed(c, PhaseTimer::LINALG, 0.0, [&] { la_qr(c.la, Z, n, kk, R); });                         // Z <- Q2, B^T = Q2 R
+  timed(c, PhaseTimer::LINALG, 0.0, [&] { la_svd(c.la, R, kk, S, Us, VTs); });                  // R = Us S VTs
+  // B = R^T Q2^T = VTs^T S Us^T Q2^T  ->  Ub = VTs^T, V = Q2 Us
+  mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Z, n), colmajor(Us, kk), out_colmajor(V, n));
+  // U = Q Ub, Ub(i, j) = VTs(j, i)
+  mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Y, n), rowmajor(VTs, kk), out_colmajor(U, n));
+  timed(c, PhaseTimer::LINALG, 0.0, [&] { projector_weights(c.st, S, U, n, kk, chi, kcap, c.cutoff, w, c.keff.as<int>(), c.badflag.as<int>()); });
+  scale_columns(c.st, V, n, chi, w);
+  // Pt = G_ll (G_lr V')
+  mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(G[2], n), colmajor(V, n), out_colmajor(t1, n));
+  mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(G[3], n), colmajor(t1, n), out_rowmajor(Pt, chi));
+  // PT = W Ub' with Ub'(:, i) = Ub(:, i) w_i: scale the rows of VTs first
+  // (row i of VTs is column i of Ub)
+  transpose_square(c.st, VTs, Us, kk);             // Us <- Ub (col-major)
+  scale_columns(c.st, Us, kk, chi, w);
+  mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n), colmajor(Us, kk), out_rowmajor(PT, chi));
+}
+
+// One directional move (Sec. 2.2) in the frame rotated rot quarter turns.
+void do_move(Context& c, int rot) {
+  int Lxv, Lyv;
+  view_dims(c, rot, Lxv, Lyv);
+  const int chi = c.chi, n = c.n, Db = c.Db;
+  const long cc = (long)chi * chi, tt = cc * Db;
+  const int kc1 = (0 + rot) % 4, kt1 = (0 + rot) % 4, kt3 = (2 + rot) % 4, kt4 = (3 + rot) % 4, kc4 = (3 + rot) % 4;
+  for (int x = 0; x < Lxv; ++x) {
+    for (int y = 0; y < Lyv; ++y) cut_projectors(c, rot, x, y, y);
+    std::vector<std::array<int, 2>> newdC1(Lyv), newdT4(Lyv), newdC4(Lyv);
+    for (int y = 0; y < Lyv; ++y) {
+      const int s = view_site(c, rot, x, y);
+      const int up = (y + 1) % Lyv;
+      double* Pt_up = c.Pt.as<double>() + (long)up * n * chi;
+      double* Pt_dn = c.Pt.as<double>() + (long)y * n * chi;
+      double* PT_dn = c.PT.as<double>() + (long)y * n * chi;
+      double* P3_up = c.P3.as<double>() + (long)up * n * chi;
+      swap_last2(c.st, c.PT.as<double>() + (long)up * n * chi, P3_up, chi, Db, chi);
+      double* C1n = c.newC1.as<double>() + y * cc;
+      double* C4n = c.newC4.as<double>() + y * cc;
+      double* T4n = c.newT4.as<double>() + y * tt;
+      // C1' = (C1 T1) Pt_up: X1p[c2][(t4, u)] then times Pt
+      mm(c, PhaseTimer::OTHER, chi, Db, chi, colmajor(c.C(s, kc1), chi), rowmajor(c.Ta(s, kt1), n, Db),
+         out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
+      mm(c, PhaseTimer::OTHER, chi, chi, n, rowmajor(c.X1.p, n), rowmajor(Pt_up, chi), out_rowmajor(C1n, chi));
+      // C4'^T[c3][k] = sum_{(t4,d)} Yc[c3][(t4, d)] PT_dn[(t4, d)][k], Yc[c3] = C4 T3[c3]
+      mm(c, PhaseTimer::OTHER, chi, Db, chi, rowmajor(c.C(s, kc4), chi), rowmajor(c.Ta(s, kt3), Db, (long)chi * Db),
+         out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
+      mm(c, PhaseTimer::OTHER, chi, chi, n, rowmajor(c.X1.p, n), rowmajor(PT_dn, chi), out_colmajor(C4n, chi));
+      // T4' = Pt_dn^T absorb(T4 P3_up)
+      mm(c, PhaseTimer::EDGE, n, n, chi, rowmajor(c.Tb(s, kt4), chi), rowmajor(P3_up, n), out_rowmajor(c.X2.p, n));
+      absorb(c, c.X2.as<double>(), c.Ak(rot, s), c.Ab(rot, s), c.G[0].as<double>(), true);
+      mm(c, PhaseTimer::SKETCH, chi, n, n, colmajor(Pt_dn, chi), rowmajor(c.G[0].p, n), out_rowmajor(T4n, n));
+      normalize_maxabs(c.st, C1n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
+      normalize_maxabs(c.st, C4n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
+      normalize_maxabs(c.st, T4n, tt, c.redscratch.as<double>(), c.badflag.as<int>());
+      newdC1[y] = {c.tdim[s][kt1][1], c.nact_cut[up]};
+      newdT4[y] = {c.nact_cut[y], c.nact_cut[up]};
+      newdC4[y] = {c.nact_cut[y], c.tdim[s][kt3][0]};
+    }
+    for (int y = 0; y < Lyv; ++y) {
+      const int t = view_site(c, rot, x + 1, y);
+      CTM_HIP(hipMemcpyAsync(c.C(t, kc1), c.newC1.as<double>() + y * cc, cc * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+      CTM_HIP(hipMemcpyAsync(c.C(t, kc4), c.newC4.as<double>() + y * cc, cc * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+      CTM_HIP(hipMemcpyAsync(c.Ta(t, kt4), c.newT4.as<double>() + y * tt, tt * sizeof(double), hipMemcpyDeviceToDevice, c.st));
+      swap_last2(c.st, c.Ta(t, kt4), c.Tb(t, kt4), chi, chi, Db);
+      c.cdim[t][kc1] = newdC1[y];
+      c.tdim[t][kt4] = newdT4[y];
+      c.cdim[t][kc4] = newdC4[y];
+    }
+  }
+  c.moves += 1;
+  check_bad(c, "ctm_move");
+}
+
+static const int kSweepRot[4] = {0, 2, 1, 3};   // left, right, up, down
+
+static void corner_spectra(Context& c, double* out) {
+  const long cc = (long)c.chi * c.chi;
+  timed(c, PhaseTimer::OTHER, 0.0, [&] {
+    CTM_HIP(hipMemcpyAsync(c.cornerscratch.p, c.envC.p, sizeof(double) * 4 * c.N * cc, hipMemcpyDeviceToDevice, c.st));
+    la_singular_values_batched(c.la, c.cornerscratch.as<double>(), c.chi, 4 * c.N, out);
+  });
+}
+
+void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta, int* converged) {
+  corner_spectra(c, c.specprev.as<double>());
+  // normalise the reference spectra (delta of this call is discarded)
+  spectra_delta(c.st, c.specprev.as<double>(), c.spec.as<double>(), 4 * c.N, c.chi, c.delta.as<double>());
+  CTM_HIP(hipMemcpyAsync(c.specprev.p, c.spec.p, sizeof(double) * 4 * c.N * c.chi, hipMemcpyDeviceToDevice, c.st));
+  double dl = INFINITY;
+  int it = 0, conv = 0;
+  for (it = 1; it <= max_sweeps; ++it) {
+    for (int m = 0; m < 4; ++m) do_move(c, kSweepRot[m]);
+    corner_spectra(c, c.spec.as<double>());
+    spectra_delta(c.st, c.spec.as<double>(), c.specprev.as<double>(), 4 * c.N, c.chi, c.delta.as<double>());
+    CTM_HIP(hipMemcpyAsync(&dl, c.delta.p, sizeof(double), hipMemcpyDeviceToHost, c.st));
+    CTM_HIP(hipStreamSynchronize(c.st));
+    if (dl < tol) { conv = 1; break; }
+  }
+  if (it > max_sweeps) it = max_sweeps;
+  if (done) *done = it;
+  if (delta) *delta = dl;
+  if (converged) *converged = conv;
+}
+
+}  // namespace ctm

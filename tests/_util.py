@@ -1,0 +1,32 @@
+"""Helpers shared by the GPU parity tests: same seeded inputs to both sides."""
+import numpy as np
+
+
+def random_env(Lx, Ly, chi, Db, seed):
+    """Random corners / edges (all legs chi) for every site: list of (C[4], T[4])."""
+    rng = np.random.default_rng(seed)
+    env = []
+    for _ in range(Lx * Ly):
+        C = [rng.standard_normal((chi, chi)) for _ in range(4)]
+        T = [rng.standard_normal((chi, chi, Db)) for _ in range(4)]
+        env.append((C, T))
+    return env
+
+
+def inject(oracle_env, gpu_ctx, env):
+    for i, (C, T) in enumerate(env):
+        oracle_env.C[i] = [c.copy() for c in C]
+        oracle_env.T[i] = [t.copy() for t in T]
+        if gpu_ctx is not None:
+            gpu_ctx.ctm_set_env(i, C, T)
+
+
+def rel_err(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def pad_to(x, shape):
+    out = np.zeros(shape)
+    out[tuple(slice(0, s) for s in x.shape)] = x
+    return out

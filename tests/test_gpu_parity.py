@@ -1,0 +1,238 @@
+"""GPU (HIP, through the C ABI) against the FP64 CPU oracle on the same seeded inputs.
+
+Tolerances (FP64 everywhere on both sides; only summation order differs):
+* single contractions (enlarged corner): 1e-12 relative to the largest entry;
+* projectors and one move: 1e-8 relative (the projector divides by
+  sqrt(sigma_i) down to the cutoff, which amplifies rounding by up to
+  sqrt(sigma_0 / sigma_chi));
+* energies and magnetisations after full runs: 1e-10 absolute, or 20x the
+  oracle's own change under a 1e-15 input perturbation where the truncation is
+  near-degenerate (then several results are correct);
+* corner spectra: the same rule on the normalised spectra.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import closed_forms as cf
+from oracle import observables as ob
+from oracle.ctmrg import Environment, enlarged_corner, projectors
+from oracle.philox import stream_id
+from tests._util import inject, pad_to, random_env, rel_err
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2112_13184_amd as p
+    p.load()
+    return p
+
+
+# --------------------------------------------------------------------------
+# single building blocks on an injected environment
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("layers,D,chi", [(2, 3, 13), (2, 2, 20), (1, 3, 21)])
+def test_enlarged_corner_parity(lib, layers, D, chi):
+    d = 2 if layers == 2 else 1
+    Db = D * D if layers == 2 else D
+    if layers == 2:
+        A = wl.random_itps(2, 2, D, d, seed=5)
+    else:
+        A = wl.random_classical(2, 2, D, seed=5, positive=False)
+    ctx = lib.Ctm(A, 2, 2, D, chi, d=d, layers=layers, rsvd_oversample=8)
+    ora = Environment(A, 2, 2, chi=chi, layers=layers)
+    env = random_env(2, 2, chi, Db, seed=7)
+    inject(ora, ctx, env)
+    for site in range(4):
+        for j in range(4):
+            G = ctx.ctm_enlarged_corner(j, site)
+            ref = ora.corner(site, j)
+            assert rel_err(G, ref) < 1e-12, (site, j)
+
+
+@pytest.mark.parametrize("mode", ["rsvd", "dense"])
+def test_projectors_parity(lib, mode):
+    D, chi, p, q, seed = 2, 10, 6, 2, 21
+    A = wl.random_itps(2, 2, D, 2, seed=6)
+    kw = dict(rsvd_oversample=(p if mode == "rsvd" else -1), rsvd_power_iters=q, seed=seed)
+    ctx = lib.Ctm(A, 2, 2, D, chi, **kw)
+    ora = Environment(A, 2, 2, chi=chi, layers=2, mode=mode, oversample=p, power_iters=q, seed=seed)
+    inject(ora, ctx, random_env(2, 2, chi, D * D, seed=8))
+    Db = D * D
+    for direction, r in (("left", 0), ("up", 1), ("right", 2), ("down", 3)):
+        for x in range(2):
+            for y in range(2):
+                P, Pt, k = ctx.ctm_projectors(direction, x, y)
+                from oracle.ctmrg import view_site
+                vs = lambda a, b: view_site(2, 2, r, a, b)
+                G_ul = ora.corner(vs(x, y), (0 + r) % 4)
+                G_ur = ora.corner(vs(x + 1, y), (1 + r) % 4)
+                G_lr = ora.corner(vs(x + 1, y - 1), (2 + r) % 4)
+                G_ll = ora.corner(vs(x, y - 1), (3 + r) % 4)
+                Pr, Ptr = projectors(G_ur, G_ul, G_ll, G_lr, chi, 1e-12, mode, p, q, seed,
+                                     stream_id(0, x, y), G_lr.shape[1] // Db, Db)
+                scale = np.max(np.abs(Ptr @ Pr))
+                assert np.max(np.abs(Pt @ P - Ptr @ Pr)) / scale < 1e-8
+                assert rel_err(P, Pr) < 1e-8 and rel_err(Pt, Ptr) < 1e-8
+                assert k == chi
+
+
+@pytest.mark.parametrize("direction,r", [("left", 0), ("up", 1), ("right", 2), ("down", 3)])
+def test_one_move_parity(lib, direction, r):
+    D, chi = 2, 9
+    A = wl.random_itps(2, 2, D, 2, seed=9)
+    ctx = lib.Ctm(A, 2, 2, D, chi, rsvd_oversample=6, rsvd_power_iters=2, seed=3)
+    ora = Environment(A, 2, 2, chi=chi, layers=2, mode="rsvd", oversample=6, power_iters=2, seed=3)
+    inject(ora, ctx, random_env(2, 2, chi, D * D, seed=10))
+    ctx.ctm_move(direction)
+    ora.left_move(r)
+    for i in range(4):
+        C, T, _ = ctx.ctm_get_env(i)
+        for k in range(4):
+            assert rel_err(C[k], ora.C[i][k]) < 1e-8, (i, k)
+            assert rel_err(T[k], ora.T[i][k]) < 1e-8, (i, k)
+
+
+# --------------------------------------------------------------------------
+# whole runs from the trivial environment
+# --------------------------------------------------------------------------
+def _gpu_energy(ctx, H, N):
+    e = 0.0
+    for i in range(N):
+        e += ctx.ctm_expect_2site(i, 0, H) + ctx.ctm_expect_2site(i, 1, H)
+    return e / N
+
+
+def _oracle_run(A, Lx, Ly, chi, sweeps):
+    env = Environment(A, Lx, Ly, chi=chi, layers=2, mode="rsvd", oversample=8, power_iters=1, seed=5)
+    for _ in range(sweeps):
+        env.sweep()
+    return env
+
+
+def _spectra(Cs, chi):
+    out = []
+    for C in Cs:
+        s = np.linalg.svd(pad_to(C, (chi, chi)), compute_uv=False)
+        out.append(s / s.sum())
+    return np.array(out)
+
+
+# (Lx, Ly, D, chi, tensor seed).  A truncation whose kept and discarded
+# singular values nearly coincide makes the result depend on rounding (the
+# oracle itself moves when its inputs are perturbed by 1e-15); the bound is
+# therefore max(1e-10, 20 x that self-sensitivity), measured here.
+@pytest.mark.parametrize("Lx,Ly,D,chi,seed", [(2, 2, 2, 16, 14), (1, 1, 2, 8, 14), (2, 1, 3, 17, 3),
+                                              (2, 2, 3, 18, 14)])
+def test_sweeps_energy_and_spectra(lib, Lx, Ly, D, chi, seed):
+    sweeps = 6
+    A = wl.random_itps(Lx, Ly, D, 2, seed=seed)
+    ctx = lib.Ctm(A, Lx, Ly, D, chi, rsvd_oversample=8, rsvd_power_iters=1, seed=5)
+    for _ in range(sweeps):
+        for dname in ("left", "right", "up", "down"):
+            ctx.ctm_move(dname)
+    ora = _oracle_run(A, Lx, Ly, chi, sweeps)
+    rng = np.random.default_rng(0)
+    ora_p = _oracle_run([a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in A], Lx, Ly, chi, sweeps)
+    H = wl.heisenberg_bond()
+    N = Lx * Ly
+    e_ora = ob.energy_per_site(ora, H)
+    sens_e = abs(e_ora - ob.energy_per_site(ora_p, H))
+    assert abs(_gpu_energy(ctx, H, N) - e_ora) < max(1e-10, 20 * sens_e)
+    for i in range(N):
+        C, T, dims = ctx.ctm_get_env(i)
+        s_gpu, s_ora, s_p = _spectra(C, chi), _spectra(ora.C[i], chi), _spectra(ora_p.C[i], chi)
+        sens_s = np.max(np.abs(s_ora - s_p))
+        assert np.max(np.abs(s_gpu - s_ora)) < max(1e-10, 20 * sens_s)
+        rho = ctx.ctm_rho_1site(i)
+        ref = ob.rho_one_site(ora, i)
+        ref_p = ob.rho_one_site(ora_p, i)
+        sens_r = np.max(np.abs(ref / np.trace(ref) - ref_p / np.trace(ref_p)))
+        assert np.max(np.abs(rho - ref / np.trace(ref))) < max(1e-10, 20 * sens_r)
+
+
+def test_classical_ising_closed_forms(lib):
+    beta = 0.5
+    a, b, w = wl.ising_classical(beta)
+    ctx = lib.Ctm([a], 1, 1, 2, 16, layers=1, boundary=w, rsvd_oversample=16, rsvd_power_iters=2, seed=5)
+    n, delta, conv = ctx.ctm_sweep(400, 1e-12)
+    assert conv, delta
+    f = -ctx.ctm_log_kappa() / beta
+    m = ctx.ctm_impurity(0, b)
+    assert abs(f - (-cf.onsager_lnz(beta) / beta)) < 1e-8
+    assert abs(m - cf.yang_magnetization(beta)) < 1e-5
+    ora = Environment([a], 1, 1, chi=16, layers=1, boundary=w, mode="rsvd", oversample=16,
+                      power_iters=2, seed=5)
+    ora.run(400, 1e-12)
+    assert abs(m - ob.impurity_ratio(ora, 0, b)) < 1e-10
+    assert abs(ctx.ctm_log_kappa() - ob.log_kappa(ora)) < 1e-10
+
+
+def test_ising_peps_closed_forms(lib):
+    beta = 0.5
+    A, wp = wl.ising_peps(beta)
+    ctx = lib.Ctm([A], 1, 1, 2, 16, boundary=wp, rsvd_oversample=16, rsvd_power_iters=2, seed=2)
+    ctx.ctm_sweep(400, 1e-11)
+    zz = np.kron(wl.SZ, wl.SZ)
+    assert abs(ctx.ctm_expect_2site(0, 0, zz) - cf.nn_correlator(beta)) < 1e-9
+    assert abs(ctx.ctm_expect_2site(0, 1, zz) - cf.nn_correlator(beta)) < 1e-9
+    assert abs(ctx.ctm_expect_1site(0, wl.SZ) - cf.yang_magnetization(beta)) < 1e-9
+    assert abs(ctx.ctm_log_kappa() - cf.onsager_lnz(beta)) < 1e-10
+
+
+@pytest.mark.parametrize("D", [1, 4])
+def test_product_state_exact(lib, D):
+    rng = np.random.default_rng(8)
+    phis = [rng.standard_normal(2) for _ in range(4)]
+    A = wl.product_itps(phis, D=D)
+    ctx = lib.Ctm(A, 2, 2, D, 8, rsvd_oversample=8, seed=1)
+    ctx.ctm_sweep(3, 1e-14)
+    for i in range(4):
+        for op in (wl.SX, wl.SZ):
+            exact = phis[i] @ op @ phis[i] / (phis[i] @ phis[i])
+            assert abs(ctx.ctm_expect_1site(i, op) - exact) < 1e-13
+
+
+def test_tfim_mean_field_energy(lib):
+    h = 2.9
+    phi, e_mf = wl.tfim_mean_field(h)
+    A = wl.product_itps([phi], D=2)
+    ctx = lib.Ctm(A, 1, 1, 2, 8, rsvd_oversample=8, seed=1)
+    ctx.ctm_sweep(3, 1e-14)
+    assert abs(_gpu_energy(ctx, wl.tfim_bond(h), 1) - e_mf) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# full sizes against stored oracle values (tests/golden/make_golden.py)
+# --------------------------------------------------------------------------
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"{name}.json not generated")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("name", ["itps_d4_chi64", "itps_d6_chi144"])
+def test_full_size_against_stored_oracle(lib, name):
+    g = _golden(name)
+    w = g["params"]
+    A = wl.random_itps(2, 2, w["D"], 2, seed=w["seed"])
+    ctx = lib.Ctm(A, 2, 2, w["D"], w["chi"], rsvd_oversample=w["p"], rsvd_power_iters=w["q"],
+                  seed=w["sketch_seed"], svd_rel_cutoff=g["cutoff"])
+    H = wl.heisenberg_bond()
+    last = max(int(s) for s in g["energies"])
+    for s in range(1, last + 1):
+        for dname in ("left", "right", "up", "down"):
+            ctx.ctm_move(dname)
+        if str(s) in g["energies"]:
+            e = _gpu_energy(ctx, H, 4)
+            ref = g["energies"][str(s)]
+            sens = abs(ref - g["energies_perturbed"][str(s)])
+            assert abs(e - ref) < max(1e-10, 20 * sens), (s, e, ref, sens)
