@@ -118,7 +118,7 @@ ctm_status ctm_projectors(ctm_ctx* ctx, ctm_dir dir, int x, int y, double* P, do
   int Lxv = (rot % 2 == 0) ? c.Lx : c.Ly, Lyv = (rot % 2 == 0) ? c.Ly : c.Lx;
   if (x < 0 || x >= Lxv || y < 0 || y >= Lyv) { c.err = "cut outside the unit cell"; return CTM_EINVAL; }
   return guarded(ctx, [&] {
-    ctm::cut_projectors(c, rot, x, y, 0);
+    ctm::cut_projectors_fast(c, rot, x, y);
     const long nc = (long)c.n * c.chi;
     if (Pt) CTM_HIP(hipMemcpyAsync(Pt, c.Pt.p, sizeof(double) * nc, hipMemcpyDeviceToHost, c.st));
     if (P) {

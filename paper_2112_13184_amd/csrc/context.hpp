@@ -9,6 +9,7 @@
 #include "common.hpp"
 #include "gemm.hpp"
 #include "linalg.hpp"
+#include "smallla.hpp"
 
 namespace ctm {
 
@@ -81,6 +82,7 @@ struct Context {
   hipStream_t st = nullptr;
   bool own_stream = false;
   Linalg* la = nullptr;
+  SmallLA sla;
   std::string err;
   long long moves = 0;
 
@@ -138,6 +140,7 @@ size_t context_footprint(const ctm_config& cfg);
 void do_move(Context& c, int rot);
 void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta, int* converged);
 void cut_projectors(Context& c, int rot, int x, int y, int slot);
+void cut_projectors_fast(Context& c, int rot, int x, int y);
 void enlarged_corner(Context& c, int s, int j, double* out);
 // Reduced density matrices, normalised to trace 1, in the device buffer
 // rho_dev (d*d or d^4 doubles); copied to rho_host when it is not null.

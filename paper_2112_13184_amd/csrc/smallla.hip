@@ -1,0 +1,432 @@
+// FP64 factorisations of the projector computation, written for one MI355X.
+//
+// * Cholesky QR of a tall n x k panel Y: G = Y^T Y (MFMA GEMM), G (+ shift) =
+//   L L^T in one 1024-thread workgroup with the packed lower triangle in
+//   registers (outer-product form, one barrier per column), R^-1 = L^-T one wave per
+//   column, then Y <- Y R^-1 (MFMA GEMM).  The first pass uses the shift of
+//   Fukaya, Kannan, Nakatsukasa, Yamamoto and Yanagisawa (SIAM J. Sci. Comput.
+//   42 (2020) A477), s = 11 (n k + k (k + 1)) u ||Y||_F^2, which keeps the Gram
+//   matrix positive definite for condition numbers up to about 1e12; two more
+//   unshifted passes restore orthogonality to working precision.
+// * SVD of a k x k matrix by block one-sided Jacobi (Hestenes): the columns are
+//   split into an even number of blocks; each kernel launch orthogonalises the
+//   column pairs inside every block pair of one round of a round-robin
+//   tournament, with the two blocks and their rotation accumulators staged in
+//   LDS.  A sweep is one full tournament; sweeps stop on the device once no
+//   pair is rotated by more than the tolerance.
+#include "smallla.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace ctm {
+namespace {
+
+constexpr int kCholThreads = 1024;
+constexpr int kCholME = (kSmallLAMaxK * (kSmallLAMaxK + 1) / 2 + kCholThreads - 1) / kCholThreads;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ double block_reduce(double v, bool is_max, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  v = is_max ? wave_max(v) : wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int i = 1; i < (int)(blockDim.x >> 6); ++i) r = is_max ? fmax(r, sh[i]) : r + sh[i];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
+
+// G_b (k x k, col-major) [+ s I] = L L^T, rank revealing: a pivot below
+// drop_rel times the largest one so far marks its column as dependent
+// (mask 0): the column is taken as zero, L gets a unit diagonal there (so
+// that L stays invertible) and R = L^T gets a zero row (so that accumulated
+// factors keep the zero).  shifted: add s = shift_scale * trace(G).
+// check_id: flag the problem if the non-zero part of G is not within 0.5 of
+// the identity.  NaN / Inf pivots flag the problem too.
+// The lower triangle lives in registers (entry e of the packed triangle
+// belongs to thread e % 1024); step j broadcasts column j through a
+// double-buffered LDS column, so one barrier per column suffices.
+__global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, int shifted, int check_id,
+                                                        double shift_scale, double drop_rel, double* Lout,
+                                                        double* Rout, double* mask, int* flag) {
+  __shared__ double col[2][kSmallLAMaxK];
+  __shared__ double piv[kSmallLAMaxK];
+  __shared__ double red[16];
+  __shared__ int bad;
+  __shared__ unsigned char dropped[kSmallLAMaxK];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const long kk2 = (long)k * k;
+  const double* g = G + b * kk2;
+  if (tid == 0) bad = 0;
+  double tr = 0.0;
+  for (int i = tid; i < k; i += blockDim.x) tr += g[i + (long)i * k];
+  tr = block_reduce(tr, false, red);
+  const double s = shifted ? shift_scale * tr : 0.0;
+  const int T = k * (k + 1) / 2;
+  // entry q of this thread: row i = code >> 8, column l = code & 255; unused
+  // slots carry l = 255, which no step reaches
+  int code[kCholME];
+  double val[kCholME];
+  double dev = 0.0;
+#pragma unroll
+  for (int q = 0; q < kCholME; ++q) {
+    const int e = tid + q * kCholThreads;
+    code[q] = 255;
+    val[q] = 0.0;
+    if (e < T) {
+      int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (tri(i + 1, 0) <= e) ++i;
+      while (tri(i, 0) > e) --i;
+      const int l = e - tri(i, 0);
+      code[q] = (i << 8) | l;
+      const double v = g[i + (long)l * k];
+      if (check_id) {
+        const double gi = g[i + (long)i * k], gl = g[l + (long)l * k];
+        if (gi > 1e-3 && gl > 1e-3) dev = fmax(dev, fabs(v - (i == l ? 1.0 : 0.0)));
+      }
+      val[q] = v + (i == l ? s : 0.0);
+    }
+  }
+  if (check_id) {
+    dev = block_reduce(dev, true, red);
+    if (tid == 0 && !(dev <= 0.5)) bad = 1;
+  }
+  double dmax = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double* cj = col[j & 1];
+#pragma unroll
+    for (int q = 0; q < kCholME; ++q)
+      if ((code[q] & 255) == j) cj[code[q] >> 8] = val[q];
+    __syncthreads();
+    const double d = cj[j];
+    const bool drop = !(d > drop_rel * dmax) || !(d > 0.0) || !isfinite(d);
+    if (tid == 0) {
+      dropped[j] = drop ? 1 : 0;
+      piv[j] = d;
+      if (!isfinite(d)) bad = 1;
+    }
+    if (!drop) {
+      dmax = fmax(dmax, d);
+      const double inv = 1.0 / d;
+#pragma unroll
+      for (int q = 0; q < kCholME; ++q) {
+        const int l = code[q] & 255;
+        if (l > j && l < 255) val[q] -= cj[code[q] >> 8] * cj[l] * inv;
+      }
+    }
+  }
+  __syncthreads();
+  double* Lb = Lout + b * kk2;
+  double* Rb = Rout + b * kk2;
+  for (long e = tid; e < kk2; e += blockDim.x) {   // strictly upper part of L / lower part of R
+    const int i = (int)(e % k), l = (int)(e / k);
+    if (i < l) {
+      Lb[e] = 0.0;
+      Rb[l + (long)i * k] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kCholME; ++q) {
+    const int i = code[q] >> 8, l = code[q] & 255;
+    if (l == 255) continue;
+    double v = 0.0, r = 0.0;
+    if (dropped[l]) {
+      v = (i == l) ? 1.0 : 0.0;          // unit column in L, zero row in R
+    } else {
+      // a dependent row i keeps its coefficients on the earlier directions
+      const double sd = sqrt(piv[l]);
+      v = (i == l) ? sd : val[q] / sd;
+      r = v;
+    }
+    Lb[i + (long)l * k] = v;             // L[i][l]
+    Rb[l + (long)i * k] = r;             // R[l][i] = L[i][l]
+  }
+  for (int j = tid; j < k; j += blockDim.x) mask[(long)b * k + j] = dropped[j] ? 0.0 : 1.0;
+  if (tid == 0 && bad) flag[b] = 1;
+}
+
+// Rinv = R^-1 for R = L^T upper triangular; one wave per column c.
+__global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* Rinv) {
+  const int b = blockIdx.y;
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= k) return;
+  const long kk2 = (long)k * k;
+  const double* Lb = L + b * kk2;
+  double x[3] = {0.0, 0.0, 0.0};     // x[q] = column entry lane + 64 q
+  for (int i = c; i >= 0; --i) {
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int kx = lane + 64 * q;
+      if (kx > i && kx <= c) part += Lb[kx + (long)i * k] * x[q];   // R[i][kx] = L[kx][i]
+    }
+    const double sum = wave_sum(part);
+    if ((i & 63) == lane) {
+      const double v = (((i == c) ? 1.0 : 0.0) - sum) / Lb[i + (long)i * k];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if ((i >> 6) == q) x[q] = v;
+    }
+  }
+  double* out = Rinv + b * kk2 + (long)c * k;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = lane + 64 * q;
+    if (i < k) out[i] = (i <= c) ? x[q] : 0.0;
+  }
+}
+
+// dst_b = src_b with column j scaled by mask_b[j] (column-major n x k panels).
+__global__ void k_copy_panels(const double* src, long sstride, double* dst, long dstride, int n, int k,
+                              const double* mask) {
+  const int b = blockIdx.y;
+  const long elems = (long)n * k;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < elems; e += (long)gridDim.x * blockDim.x)
+    dst[b * dstride + e] = src[b * sstride + e] * mask[(long)b * k + e / n];
+}
+
+// ---------------------------------------------------------------------------
+// block one-sided Jacobi
+// ---------------------------------------------------------------------------
+__global__ void k_jacobi_init(double* J, int k, double* off, int* conv) {
+  const int b = blockIdx.y;
+  const long kk2 = (long)k * k;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < kk2; e += (long)gridDim.x * blockDim.x)
+    J[b * kk2 + e] = ((e % k) == (e / k)) ? 1.0 : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    off[b] = 0.0;
+    conv[b] = 0;
+  }
+}
+
+// After a sweep: converged if no pair needed a rotation above tol.
+__global__ void k_jacobi_sweep_end(double* off, int* conv, int batch, double tol) {
+  const int b = threadIdx.x;
+  if (b < batch) {
+    if (off[b] <= tol) conv[b] = 1;
+    off[b] = 0.0;
+  }
+}
+
+__device__ __forceinline__ int circle(int pos, int round, int m) {
+  // position pos in round `round` of a round-robin tournament of m (even) players
+  if (pos == 0) return 0;
+  return ((pos - 1 + round) % (m - 1)) + 1;
+}
+
+// One tournament round over blocks: workgroup w of problem b orthogonalises
+// the 2*bs columns of its block pair (columns >= k are zero padding).
+__global__ __launch_bounds__(256) void k_jacobi_round(double* A, double* J, int k, int nb, int bs, int round,
+                                                       double* off, const int* conv, double tol) {
+  extern __shared__ double sm[];
+  const int b = blockIdx.y;
+  if (conv[b]) return;
+  const long kk2 = (long)k * k;
+  double* Ab = A + b * kk2;
+  double* Jb = J + b * kk2;
+  const int pa = circle(blockIdx.x, round, nb), pb = circle(nb - 1 - blockIdx.x, round, nb);
+  const int m = 2 * bs;
+  double* As = sm;                 // [m][k]
+  double* Js = sm + (long)m * k;   // [m][k]
+  for (long e = threadIdx.x; e < (long)m * k; e += blockDim.x) {
+    const int lc = (int)(e / k), r = (int)(e % k);
+    const int gc = (lc < bs) ? pa * bs + lc : pb * bs + (lc - bs);
+    As[e] = (gc < k) ? Ab[(long)gc * k + r] : 0.0;
+    Js[e] = (gc < k) ? Jb[(long)gc * k + r] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double offl = 0.0;
+  for (int rr = 0; rr < m - 1; ++rr) {
+    for (int q = wv; q < bs; q += nw) {
+      const int ci = circle(q, rr, m), cj = circle(m - 1 - q, rr, m);
+      double* ai = As + (long)ci * k;
+      double* aj = As + (long)cj * k;
+      double al = 0.0, be = 0.0, ga = 0.0;
+      for (int r = lane; r < k; r += 64) {
+        const double x = ai[r], y = aj[r];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
+      }
+      al = wave_sum(al);
+      be = wave_sum(be);
+      ga = wave_sum(ga);
+      const double nrm = sqrt(al * be);
+      if (nrm > 0.0 && fabs(ga) > tol * nrm) {
+        offl = fmax(offl, fabs(ga) / nrm);
+        const double zeta = (be - al) / (2.0 * ga);
+        const double t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        double* ji = Js + (long)ci * k;
+        double* jj = Js + (long)cj * k;
+        for (int r = lane; r < k; r += 64) {
+          const double x = ai[r], y = aj[r];
+          ai[r] = cs * x - sn * y;
+          aj[r] = sn * x + cs * y;
+          const double u = ji[r], v = jj[r];
+          ji[r] = cs * u - sn * v;
+          jj[r] = sn * u + cs * v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (long e = threadIdx.x; e < (long)m * k; e += blockDim.x) {
+    const int lc = (int)(e / k), r = (int)(e % k);
+    const int gc = (lc < bs) ? pa * bs + lc : pb * bs + (lc - bs);
+    if (gc < k) {
+      Ab[(long)gc * k + r] = As[e];
+      Jb[(long)gc * k + r] = Js[e];
+    }
+  }
+  // largest relative rotation of this workgroup -> off[b] (positive doubles order like their bits)
+  __shared__ double red[4];
+  offl = wave_max(offl);
+  if (lane == 0) red[wv] = offl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = red[0];
+    for (int i = 1; i < nw; ++i) mx = fmax(mx, red[i]);
+    atomicMax(reinterpret_cast<unsigned long long*>(off + b), (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+// Column norms -> singular values, sorted descending; X = A S^-1, Y = J.
+__global__ __launch_bounds__(256) void k_svd_finalize(const double* A, const double* J, int k, double* X,
+                                                       double* S, double* Y) {
+  __shared__ double sig[kSmallLAMaxK];
+  __shared__ int pos[kSmallLAMaxK];
+  const int b = blockIdx.x;
+  const long kk2 = (long)k * k;
+  const double* Ab = A + b * kk2;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int c = wv; c < k; c += nw) {
+    double s = 0.0;
+    for (int r = lane; r < k; r += 64) s += Ab[(long)c * k + r] * Ab[(long)c * k + r];
+    s = wave_sum(s);
+    if (lane == 0) sig[c] = sqrt(s);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    int rnk = 0;
+    for (int o = 0; o < k; ++o) rnk += (sig[o] > sig[c]) || (sig[o] == sig[c] && o < c);
+    pos[c] = rnk;
+  }
+  __syncthreads();
+  for (long e = threadIdx.x; e < kk2; e += blockDim.x) {
+    const int r = (int)(e % k), c = (int)(e / k);
+    const int p = pos[c];
+    const double sc = sig[c];
+    X[b * kk2 + (long)p * k + r] = (sc > 0.0) ? Ab[e] / sc : 0.0;
+    Y[b * kk2 + (long)p * k + r] = J[b * kk2 + e];
+  }
+  for (int c = threadIdx.x; c < k; c += blockDim.x) S[(long)b * k + pos[c]] = sig[c];
+}
+
+
+}  // namespace
+
+void smallla_alloc(SmallLA& s, int kmax, int batch_max, long nmax) {
+  s.kmax = kmax;
+  s.batch_max = batch_max;
+  const size_t m = (size_t)kmax * kmax * batch_max;
+  s.G.alloc(m * 8); s.L.alloc(m * 8); s.R.alloc(m * 8); s.Rinv.alloc(m * 8);
+  s.Racc.alloc(m * 8); s.Rtmp.alloc(m * 8); s.J.alloc(m * 8);
+  CTM_CHECK(batch_max <= 64, -1, "smallla: at most 64 problems per batch");
+  s.flag.alloc(sizeof(int) * 256);
+  s.off.alloc(sizeof(double) * 64);
+  s.mask.alloc(sizeof(double) * (size_t)kmax * batch_max);
+  s.tmp_elems = (size_t)nmax * kmax * batch_max;
+  s.tmp.alloc(s.tmp_elems * 8);
+  CTM_HIP(hipMemset(s.flag.p, 0, sizeof(int) * 256));
+}
+
+static int jacobi_block(int k) { return std::max(1, (k + 31) / 32); }
+
+bool smallla_fits(const SmallLA& s, int k) {
+  // the Jacobi round stages two blocks of A and of the rotations in LDS
+  const size_t jac = sizeof(double) * 2 * (size_t)(2 * jacobi_block(k)) * k;
+  return k <= kSmallLAMaxK && k <= s.kmax && jac <= 48 * 1024;
+}
+
+void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, int batch, int passes,
+            double* Racc, const GemmWorkspace& ws) {
+  CTM_CHECK(k <= kSmallLAMaxK && k <= s.kmax && batch <= s.batch_max && n >= k, -1, "cholqr: size");
+  CTM_CHECK((size_t)n * k * batch <= s.tmp_elems, -1, "cholqr: workspace");
+  const long kk2 = (long)k * k;
+  const double shift_scale = 11.0 * ((double)n * k + (double)k * (k + 1)) * 0x1p-53;
+  double* G = s.G.as<double>();
+  double* L = s.L.as<double>();
+  double* R = s.R.as<double>();
+  double* Ri = s.Rinv.as<double>();
+  double* tmp = s.tmp.as<double>();
+  for (int pass = 0; pass < passes; ++pass) {
+    // G = Y^T Y
+    gemm(st, GemmType::F64, k, k, n, 1.0, rowmajor(Y, n, ystride), colmajor(Y, n, ystride), 0.0,
+         out_colmajor(G, k, kk2), batch, ws);
+    // the shifted pass never drops; later passes drop directions whose pivot is
+    // below 1e-14 of the largest (they lie below any projector cutoff)
+    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass == 0 ? 1 : 0,
+                       (pass == passes - 1 && passes > 1) ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14,
+                       L, R, s.mask.as<double>(), s.flag.as<int>());
+    CTM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_trinv, dim3((k + 3) / 4, batch), dim3(256), 0, st, L, k, Ri);
+    CTM_HIP(hipGetLastError());
+    gemm(st, GemmType::F64, n, k, k, 1.0, colmajor(Y, n, ystride), colmajor(Ri, k, kk2), 0.0,
+         out_colmajor(tmp, n, (long)n * k), batch, ws);
+    hipLaunchKernelGGL(k_copy_panels, dim3(256, batch), dim3(256), 0, st, tmp, (long)n * k, Y, ystride, n, k,
+                       s.mask.as<double>());
+    CTM_HIP(hipGetLastError());
+    if (Racc) {
+      if (pass == 0) {
+        CTM_HIP(hipMemcpyAsync(Racc, R, sizeof(double) * kk2 * batch, hipMemcpyDeviceToDevice, st));
+      } else {
+        gemm(st, GemmType::F64, k, k, k, 1.0, colmajor(R, k, kk2), colmajor(Racc, k, kk2), 0.0,
+             out_colmajor(s.Rtmp.p, k, kk2), batch, ws);
+        CTM_HIP(hipMemcpyAsync(Racc, s.Rtmp.p, sizeof(double) * kk2 * batch, hipMemcpyDeviceToDevice, st));
+      }
+    }
+  }
+}
+
+void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, double* Y) {
+  CTM_CHECK(k <= kSmallLAMaxK && batch <= s.batch_max, -1, "jacobi_svd: size");
+  int bs = jacobi_block(k);
+  int nb = (k + bs - 1) / bs;
+  if (nb & 1) ++nb;
+  if (nb < 2) nb = 2;
+  double* J = s.J.as<double>();
+  int* conv = s.flag.as<int>() + 64;
+  double* off = s.off.as<double>();
+  hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, off, conv);
+  const size_t lds = sizeof(double) * 2 * (size_t)(2 * bs) * k;
+  const double tol = 1e-15;
+  const int max_sweeps = 14;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    for (int r = 0; r < nb - 1; ++r)
+      hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(256), lds, st, A, J, k, nb, bs, r, off, conv, tol);
+    hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, batch, tol);
+  }
+  CTM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, Y);
+  CTM_HIP(hipGetLastError());
+}
+
+}  // namespace ctm

@@ -1,0 +1,42 @@
+// FP64 QR of tall panels (shifted Cholesky QR) and SVD of small square
+// matrices (block one-sided Jacobi), batched over independent problems.
+#pragma once
+
+#include "common.hpp"
+#include "gemm.hpp"
+
+namespace ctm {
+
+struct SmallLA {
+  int kmax = 0, batch_max = 0;
+  // flag: 256 ints; [0, 64) Cholesky failure per problem, [64, 128) Jacobi
+  // convergence per problem, [128, 192) projector-weight failure per problem
+  DevBuf G, L, R, Rinv, Racc, Rtmp, J, flag, off, tmp, mask;
+  size_t tmp_elems = 0;
+};
+
+// True if order-k problems fit the workspaces and the LDS of the kernels below.
+bool smallla_fits(const SmallLA& s, int k);
+
+// Largest k (panel width / matrix order) the kernels below handle.
+constexpr int kSmallLAMaxK = 192;
+
+void smallla_alloc(SmallLA& s, int kmax, int batch_max, long nmax);
+
+// Orthonormalise `batch` column-major n x k panels Y_b = Y + b * ystride in
+// place by `passes` Cholesky QR passes, the first one with the shift of
+// Fukaya et al. (2020) so that ill-conditioned panels stay positive
+// definite.  If Racc != nullptr, Racc_b (k x k, col-major) receives the upper
+// triangular factor with Y_in = Q R.  A pass whose Gram matrix is not
+// numerically positive definite (or whose last pass is far from the
+// identity) sets flag[b] = 1 (device ints, batch of them; cleared by the
+// caller).
+void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, int batch, int passes,
+            double* Racc, const GemmWorkspace& ws);
+
+// SVD of `batch` k x k column-major matrices A_b = X_b diag(S_b) Y_b^T by
+// block one-sided Jacobi (A is overwritten).  S_b descending; X, Y k x k
+// col-major, batch strides k*k; S stride k.
+void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, double* Y);
+
+}  // namespace ctm

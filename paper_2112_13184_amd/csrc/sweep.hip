@@ -12,17 +12,23 @@
 // turns: view corner m is physical corner (m + rot) % 4, the same for edges.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
 #include "context.hpp"
 #include "kernels.hpp"
+#include "smallla.hpp"
 
 namespace ctm {
 
 namespace {
 
 inline int mod(int a, int b) { return ((a % b) + b) % b; }
+
+// CTM_DEBUG=1 in the environment prints the projector path taken per column.
+const bool g_debug = getenv("CTM_DEBUG") != nullptr;
 
 // Physical site of view position (xv, yv) in the frame rotated rot quarter turns.
 int view_site(const Context& c, int rot, int xv, int yv) {
@@ -264,14 +270,16 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
 
   // ---- workspaces --------------------------------------------------------
   build_tables(c);
-  for (auto& g : c.G) g.alloc(sizeof(double) * sz.nn);
+  const int Lmax0 = std::max(c.Lx, c.Ly);
+  for (auto& g : c.G) g.alloc(sizeof(double) * sz.nn * Lmax0);      // one slot per cut of a column
   c.X1.alloc(sizeof(double) * c.chi * c.n);
   c.X2.alloc(sizeof(double) * sz.nn);
   c.Ybuf.alloc(sizeof(double) * sz.y);
-  for (auto& p : c.pan) p.alloc(sizeof(double) * c.n * c.kk);
-  for (auto& p : c.small) p.alloc(sizeof(double) * (size_t)c.kk * c.kk);
-  c.Svals.alloc(sizeof(double) * std::max(c.kk, c.n));
-  c.wvec.alloc(sizeof(double) * c.chi);
+  for (auto& p : c.pan) p.alloc(sizeof(double) * c.n * c.kk * Lmax0);
+  for (auto& p : c.small) p.alloc(sizeof(double) * (size_t)c.kk * c.kk * Lmax0);
+  c.Svals.alloc(sizeof(double) * std::max(c.kk, c.n) * Lmax0);
+  c.wvec.alloc(sizeof(double) * c.chi * Lmax0);
+  if (c.kk <= kSmallLAMaxK && c.cfg.rsvd_oversample >= 0) smallla_alloc(c.sla, c.kk, Lmax0, c.n);
   c.keff.alloc(sizeof(int) * 64);
   c.badflag.alloc(sizeof(int));
   CTM_HIP(hipMemset(c.badflag.p, 0, sizeof(int)));
@@ -458,6 +466,162 @@ void cut_projectors(Context& c, int rot, int x, int y, int slot) {
   mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n), colmajor(Us, kk), out_rowmajor(PT, chi));
 }
 
+// Randomized-SVD projectors of cuts y0 .. y0+nb-1 of column x, batched: the
+// cut y0+b works in slot s0+b of every workspace and writes Pt / PT slot
+// s0+b.  Orthonormalisation by shifted Cholesky QR, the final small SVD by
+// block one-sided Jacobi.  Returns false (outputs undefined) for the cuts
+// whose Cholesky factorisation was not numerically positive definite; those
+// are recomputed with Householder QR by the caller.
+static void rsvd_batched(Context& c, int rot, int x, int y0, int s0, int nb, std::vector<int>& failed) {
+  const int chi = c.chi, n = c.n, kk = c.kk;
+  const long nn = (long)n * n, pk = (long)n * kk, k2 = (long)kk * kk, nc = (long)n * chi;
+  auto Gp = [&](int role, int slot) { return c.G[role].as<double>() + slot * nn; };
+  auto pan = [&](int i, int slot) { return c.pan[i].as<double>() + slot * pk; };
+  std::vector<int> kcap(nb);
+  for (int b = 0; b < nb; ++b) {
+    const int y = y0 + b, slot = s0 + b;
+    const int sites[4] = {view_site(c, rot, x, y), view_site(c, rot, x + 1, y), view_site(c, rot, x + 1, y - 1),
+                          view_site(c, rot, x, y - 1)};
+    kcap[b] = chi;
+    for (int q = 0; q < 4; ++q) {
+      const int j = (q + rot) % 4, s = sites[q];
+      kcap[b] = std::min(kcap[b], c.tdim[s][j][1] * c.Db);
+      kcap[b] = std::min(kcap[b], c.tdim[s][(j + 3) % 4][0] * c.Db);
+      enlarged_corner(c, s, j, Gp(q, slot));   // roles: 0 UL, 1 UR, 2 LR, 3 LL
+    }
+    const uint64_t sid = stream_id(c.moves, x, y);
+    timed(c, PhaseTimer::OTHER, 0.0, [&] { omega_fill(c.st, pan(1, slot), n, c.Db, kk, c.cfg.seed, sid); });
+  }
+  // batched products with the four corners of every cut
+  auto prod = [&](int role, bool trans, const double* X, double* Yo, int m) {
+    Operand A = trans ? colmajor(Gp(role, s0), n, nn) : rowmajor(Gp(role, s0), n, nn);
+    mm(c, PhaseTimer::SKETCH, n, m, n, A, colmajor(X, n, pk), out_colmajor(Yo, n, pk), nb);
+  };
+  double *Y = pan(0, s0), *Z = pan(1, s0), *W = pan(2, s0), *t1 = pan(3, s0), *t2 = pan(4, s0);
+  double *V = pan(5, s0), *U = pan(6, s0);
+  auto applyM = [&](const double* X, double* Yo) {   // Yo = G_ur G_ul G_ll G_lr X
+    prod(2, false, X, t1, kk); prod(3, false, t1, t2, kk); prod(0, false, t2, t1, kk); prod(1, false, t1, Yo, kk);
+  };
+  auto applyMt = [&](const double* X, double* Zo) {  // Zo = M^T X, W = G_ul^T G_ur^T X
+    prod(1, true, X, t1, kk); prod(0, true, t1, W, kk); prod(3, true, W, t1, kk); prod(2, true, t1, Zo, kk);
+  };
+  auto orth = [&](double* P, int passes, double* Racc) {
+    timed(c, PhaseTimer::LINALG, 0.0, [&] { cholqr(c.st, c.sla, P, pk, n, kk, nb, passes, Racc, c.ws()); });
+  };
+  // Intermediate bases need unit-norm directions but not full orthogonality:
+  // the shifted pass alone damps every direction below the shift (so power
+  // iterations would lose the small kept singular values), the second pass
+  // restores the norms.  The final basis takes a third pass.
+  applyM(Z, Y);
+  const int q = c.cfg.rsvd_power_iters;
+  orth(Y, q == 0 ? 3 : 2, nullptr);
+  for (int it = 0; it < q; ++it) {
+    applyMt(Y, Z);
+    orth(Z, 2, nullptr);
+    applyM(Z, Y);
+    orth(Y, it == q - 1 ? 3 : 2, nullptr);
+  }
+  applyMt(Y, Z);                                     // Z = M^T Q = B^T
+  double* R = c.small[0].as<double>() + s0 * k2;
+  double* X = c.small[1].as<double>() + s0 * k2;
+  double* Ysv = c.small[2].as<double>() + s0 * k2;
+  double* S = c.Svals.as<double>() + (long)s0 * std::max(kk, n);
+  orth(Z, 3, R);                                     // Z <- Q2, B^T = Q2 R
+  // R = X diag(S) Ysv^T  ->  B = Ysv S (Q2 X)^T : Ub = Ysv, V = Q2 X
+  timed(c, PhaseTimer::LINALG, 0.0, [&] {
+    // S slots are max(kk, n) apart; jacobi_svd writes kk values per problem, so
+    // run it per problem when the strides differ
+    if (nb == 1 || std::max(kk, n) == kk) {
+      jacobi_svd(c.st, c.sla, R, kk, nb, X, S, Ysv);
+    } else {
+      for (int b = 0; b < nb; ++b)
+        jacobi_svd(c.st, c.sla, R + b * k2, kk, 1, X + b * k2, S + (long)b * std::max(kk, n), Ysv + b * k2);
+    }
+  });
+  mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Z, n, pk), colmajor(X, kk, k2), out_colmajor(V, n, pk), nb);
+  mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Y, n, pk), colmajor(Ysv, kk, k2), out_colmajor(U, n, pk), nb);
+  for (int b = 0; b < nb; ++b) {
+    double* w = c.wvec.as<double>() + (long)(s0 + b) * chi;
+    timed(c, PhaseTimer::LINALG, 0.0, [&] {
+      projector_weights(c.st, S + (long)b * std::max(kk, n), U + b * pk, n, kk, chi, kcap[b], c.cutoff, w,
+                        c.keff.as<int>() + s0 + b, c.sla.flag.as<int>() + 128 + b);
+      scale_columns(c.st, V + b * pk, n, chi, w);
+      scale_columns(c.st, Ysv + b * k2, kk, chi, w);
+    });
+  }
+  // Pt = G_ll (G_lr V'), PT = W Ub'
+  double* Pt = c.Pt.as<double>() + s0 * nc;
+  double* PT = c.PT.as<double>() + s0 * nc;
+  mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(Gp(2, s0), n, nn), colmajor(V, n, pk), out_colmajor(t1, n, pk), nb);
+  mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(Gp(3, s0), n, nn), colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nb);
+  mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n, pk), colmajor(Ysv, kk, k2), out_rowmajor(PT, chi, nc), nb);
+  // cuts whose Cholesky QR broke down
+  int flags[192] = {0};
+  CTM_HIP(hipMemcpyAsync(flags, c.sla.flag.p, sizeof(int) * 192, hipMemcpyDeviceToHost, c.st));
+  CTM_HIP(hipStreamSynchronize(c.st));
+  failed.clear();
+  bool any = false, numeric = false;
+  for (int b = 0; b < nb; ++b) {
+    if (flags[b]) failed.push_back(b);
+    else if (flags[128 + b]) numeric = true;   // no singular value above zero
+    any |= flags[b] || flags[128 + b];
+  }
+  if (any) {
+    const int zero[192] = {0};
+    CTM_HIP(hipMemcpyAsync(c.sla.flag.p, zero, sizeof(int) * 64, hipMemcpyHostToDevice, c.st));
+    CTM_HIP(hipMemcpyAsync(c.sla.flag.as<int>() + 128, zero, sizeof(int) * 64, hipMemcpyHostToDevice, c.st));
+    CTM_HIP(hipStreamSynchronize(c.st));
+  }
+  if (g_debug) {
+    fprintf(stderr, "[ctm] move %lld rot %d col %d cuts %d..%d: cholqr failed %zu, no-sigma %d\n", c.moves, rot, x,
+            y0, y0 + nb - 1, failed.size(), (int)numeric);
+  }
+  if (numeric) throw Error(-4, "projectors: a cut has no singular value above zero");
+}
+
+// Projectors of every cut of column x (identity, batched randomized SVD, or
+// the Householder / exact-SVD path).
+static void column_projectors(Context& c, int rot, int x, int Lyv) {
+  std::vector<int> svd;
+  for (int y = 0; y < Lyv; ++y) {
+    const int nact = c.tdim[view_site(c, rot, x, y)][(3 + rot) % 4][0] * c.Db;
+    if (nact <= c.chi) cut_projectors(c, rot, x, y, y);   // identity
+    else svd.push_back(y);
+  }
+  if (svd.empty()) return;
+  const bool fast = c.cfg.rsvd_oversample >= 0 && c.sla.kmax > 0 && smallla_fits(c.sla, c.kk);
+  if (!fast) {
+    for (int y : svd) cut_projectors(c, rot, x, y, y);
+    return;
+  }
+  std::vector<int> failed;
+  auto run = [&](int y0, int nb) {
+    rsvd_batched(c, rot, x, y0, y0, nb, failed);
+    for (int b : failed) cut_projectors(c, rot, x, y0 + b, y0 + b);   // Householder fallback
+    for (int b = 0; b < nb; ++b) c.nact_cut[y0 + b] = c.chi;
+  };
+  if ((int)svd.size() == Lyv) {
+    run(0, Lyv);
+  } else {
+    for (int y : svd) run(y, 1);
+  }
+  c.last_cut_svd = true;
+}
+
+// Single cut through the same path as a move (used by ctm_projectors); slot 0.
+void cut_projectors_fast(Context& c, int rot, int x, int y) {
+  const int nact = c.tdim[view_site(c, rot, x, y)][(3 + rot) % 4][0] * c.Db;
+  if (nact <= c.chi || c.cfg.rsvd_oversample < 0 || c.sla.kmax == 0 || !smallla_fits(c.sla, c.kk)) {
+    cut_projectors(c, rot, x, y, 0);
+    return;
+  }
+  std::vector<int> failed;
+  rsvd_batched(c, rot, x, y, 0, 1, failed);
+  if (!failed.empty()) cut_projectors(c, rot, x, y, 0);
+  c.nact_cut[0] = c.chi;
+  c.last_cut_svd = true;
+}
+
 // One directional move (Sec. 2.2) in the frame rotated rot quarter turns.
 void do_move(Context& c, int rot) {
   int Lxv, Lyv;
@@ -466,7 +630,7 @@ void do_move(Context& c, int rot) {
   const long cc = (long)chi * chi, tt = cc * Db;
   const int kc1 = (0 + rot) % 4, kt1 = (0 + rot) % 4, kt3 = (2 + rot) % 4, kt4 = (3 + rot) % 4, kc4 = (3 + rot) % 4;
   for (int x = 0; x < Lxv; ++x) {
-    for (int y = 0; y < Lyv; ++y) cut_projectors(c, rot, x, y, y);
+    column_projectors(c, rot, x, Lyv);
     std::vector<std::array<int, 2>> newdC1(Lyv), newdT4(Lyv), newdC4(Lyv);
     for (int y = 0; y < Lyv; ++y) {
       const int s = view_site(c, rot, x, y);

@@ -30,3 +30,14 @@ def pad_to(x, shape):
     out = np.zeros(shape)
     out[tuple(slice(0, s) for s in x.shape)] = x
     return out
+
+
+def load_state(gpu_ctx, oracle_env):
+    """Copy the oracle's environment (any bond dimensions up to chi) into the
+    GPU context, zero padded, with its dimensions."""
+    chi, Db = gpu_ctx.chi, gpu_ctx.Db
+    for i in range(len(oracle_env.C)):
+        C, T = oracle_env.C[i], oracle_env.T[i]
+        dims = [list(C[k].shape) for k in range(4)] + [list(T[k].shape[:2]) for k in range(4)]
+        gpu_ctx.ctm_set_env(i, [pad_to(c, (chi, chi)) for c in C], [pad_to(t, (chi, chi, Db)) for t in T],
+                            np.array(dims, dtype=np.int32))

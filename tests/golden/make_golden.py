@@ -33,13 +33,13 @@ WORKLOADS = {
 
 
 def run(name):
-    """Oracle energies, and the same run with inputs perturbed by 1e-15 (relative):
+    """Oracle energies, and the same run with inputs perturbed by 1e-13 (relative):
     their difference is the run's own sensitivity to rounding, the scale below
     which two correct FP64 implementations cannot be told apart."""
     w = WORKLOADS[name]
     A = wl.random_itps(2, 2, w["D"], 2, seed=w["seed"])
     rng = np.random.default_rng(0)
-    Ap = [a * (1 + 1e-15 * rng.standard_normal(a.shape)) for a in A]
+    Ap = [a * (1 + 1e-13 * rng.standard_normal(a.shape)) for a in A]
     H = wl.heisenberg_bond()
     out = dict(workload=name, params=w, cutoff=1e-12, energies={}, energies_perturbed={}, bonds={})
     t0 = time.time()
