@@ -133,6 +133,7 @@ def main():
                         "frac_of_peak": alg * sweeps_per_s / PEAK[args.prec]},
         "phases_ms_per_sweep": {k: v["ms"] / args.steps for k, v in phases.items()},
         "energy_per_site": energy,
+        "cuts": dict(zip(("identity", "rsvd_batched", "fallback"), ctx.ctm_cut_stats())),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, p, q, seed=2)

@@ -159,6 +159,14 @@ ctm_status ctm_set_env(ctm_ctx* ctx, int site, const double* buf, size_t bytes, 
 /* Number of moves done since ctm_init (keys the sketch of each cut). */
 ctm_status ctm_move_count(const ctm_ctx* ctx, int64_t* moves);
 
+/* Projector cuts computed since ctm_init (moves and ctm_projectors), by path:
+ * counts[0] identity (the cut bond is no larger than chi), counts[1] the
+ * batched randomized SVD (Cholesky QR + Jacobi), counts[2] the fallback
+ * (Householder QR and LAPACK-style SVD, or the dense SVD when
+ * rsvd_oversample < 0) taken when the Cholesky QR of a panel breaks down.
+ * All paths compute the same projectors (Sec. 2.2). */
+ctm_status ctm_cut_stats(const ctm_ctx* ctx, int64_t counts[3]);
+
 /* Per-phase GPU timing with HIP events recorded on the context's stream
  * around every launch of a phase, while enabled.  Phases:
  *   0 edge GEMMs      (n x n x chi: enlarged-corner step 2, edge renormalisation)

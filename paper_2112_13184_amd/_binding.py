@@ -25,7 +25,7 @@ DIRS = {"left": CTM_LEFT, "right": CTM_RIGHT, "up": CTM_UP, "down": CTM_DOWN}
 EXPORTS = (
     "ctm_init", "ctm_move", "ctm_sweep", "ctm_projectors", "ctm_enlarged_corner",
     "ctm_expect_1site", "ctm_expect_2site", "ctm_rho_1site", "ctm_rho_2site", "ctm_impurity",
-    "ctm_log_kappa", "ctm_env_bytes", "ctm_get_env", "ctm_set_env", "ctm_move_count",
+    "ctm_log_kappa", "ctm_env_bytes", "ctm_get_env", "ctm_set_env", "ctm_move_count", "ctm_cut_stats",
     "ctm_footprint_bytes", "ctm_last_error", "ctm_free", "ctm_timing_enable", "ctm_timing_read",
     "ctm_queue_create", "ctm_queue_submit", "ctm_queue_poll", "ctm_queue_wait",
     "ctm_queue_cancel", "ctm_queue_destroy",
@@ -98,6 +98,7 @@ def load(path=LIB_PATH):
         "ctm_get_env": (I, [V, I, _DP, S, _IP]),
         "ctm_set_env": (I, [V, I, _DP, S, _IP]),
         "ctm_move_count": (I, [V, ctypes.POINTER(ctypes.c_int64)]),
+        "ctm_cut_stats": (I, [V, ctypes.POINTER(ctypes.c_int64)]),
         "ctm_footprint_bytes": (S, [ctypes.POINTER(ctm_config)]),
         "ctm_last_error": (ctypes.c_char_p, [V]),
         "ctm_free": (None, [V]),
@@ -254,6 +255,12 @@ class Ctm:
         m = ctypes.c_int64()
         self._check(self._lib.ctm_move_count(self._h, ctypes.byref(m)))
         return m.value
+
+    def ctm_cut_stats(self):
+        """(identity, batched randomized SVD, fallback) cut counts since init."""
+        c = (ctypes.c_int64 * 3)()
+        self._check(self._lib.ctm_cut_stats(self._h, c))
+        return tuple(int(v) for v in c)
 
     def ctm_timing_enable(self, on=True):
         self._check(self._lib.ctm_timing_enable(self._h, 1 if on else 0))

@@ -249,6 +249,12 @@ ctm_status ctm_move_count(const ctm_ctx* ctx, int64_t* moves) {
   return CTM_OK;
 }
 
+ctm_status ctm_cut_stats(const ctm_ctx* ctx, int64_t counts[3]) {
+  if (!ctx || !counts) return CTM_EINVAL;
+  for (int i = 0; i < 3; ++i) counts[i] = ctx->c.cuts[i];
+  return CTM_OK;
+}
+
 ctm_status ctm_timing_enable(ctm_ctx* ctx, int on) {
   if (!ctx) return CTM_EINVAL;
   return guarded(ctx, [&] {

@@ -109,6 +109,7 @@ struct Context {
   size_t gws_elems = 0;
   Arena arena;
   std::vector<int> nact_cut; // per cut of the current column: bond dim after the move
+  int64_t cuts[3] = {0, 0, 0}; // cuts by path: identity, batched randomized SVD, fallback
   bool last_cut_svd = false; // the last cut_projectors() call went through the SVD
 
   // helpers

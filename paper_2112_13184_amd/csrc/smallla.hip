@@ -61,9 +61,9 @@ __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 // The lower triangle lives in registers (entry e of the packed triangle
 // belongs to thread e % 1024); step j broadcasts column j through a
 // double-buffered LDS column, so one barrier per column suffices.
-__global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, int shifted, int check_id,
-                                                        double shift_scale, double drop_rel, double* Lout,
-                                                        double* Rout, double* mask, int* flag) {
+__global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, int pass, int shifted,
+                                                        int check_id, double shift_scale, double drop_rel,
+                                                        double* Lout, double* Rout, double* mask, int* flag) {
   __shared__ double col[2][kSmallLAMaxK];
   __shared__ double piv[kSmallLAMaxK];
   __shared__ double red[16];
@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   }
   if (check_id) {
     dev = block_reduce(dev, true, red);
-    if (tid == 0 && !(dev <= 0.5)) bad = 1;
+    if (tid == 0 && !(dev <= 0.5)) bad = 2;
   }
   double dmax = 0.0;
   for (int j = 0; j < k; ++j) {
@@ -157,7 +157,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     Rb[l + (long)i * k] = r;             // R[l][i] = L[i][l]
   }
   for (int j = tid; j < k; j += blockDim.x) mask[(long)b * k + j] = dropped[j] ? 0.0 : 1.0;
-  if (tid == 0 && bad) flag[b] = 1;
+  // reason code: 10 * pass + 1 (non-finite pivot) or + 2 (not orthonormal)
+  if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
 }
 
 // Rinv = R^-1 for R = L^T upper triangular; one wave per column c.
@@ -382,9 +383,11 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
     gemm(st, GemmType::F64, k, k, n, 1.0, rowmajor(Y, n, ystride), colmajor(Y, n, ystride), 0.0,
          out_colmajor(G, k, kk2), batch, ws);
     // the shifted pass never drops; later passes drop directions whose pivot is
-    // below 1e-14 of the largest (they lie below any projector cutoff)
-    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass == 0 ? 1 : 0,
-                       (pass == passes - 1 && passes > 1) ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14,
+    // below 1e-14 of the largest (they lie below any projector cutoff).  Only
+    // the output of two passes is near orthonormal, so the identity check runs
+    // from the third pass on.
+    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass, pass == 0 ? 1 : 0,
+                       pass >= 2 ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14,
                        L, R, s.mask.as<double>(), s.flag.as<int>());
     CTM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_trinv, dim3((k + 3) / 4, batch), dim3(256), 0, st, L, k, Ri);

@@ -27,10 +27,10 @@ void smallla_alloc(SmallLA& s, int kmax, int batch_max, long nmax);
 // place by `passes` Cholesky QR passes, the first one with the shift of
 // Fukaya et al. (2020) so that ill-conditioned panels stay positive
 // definite.  If Racc != nullptr, Racc_b (k x k, col-major) receives the upper
-// triangular factor with Y_in = Q R.  A pass whose Gram matrix is not
-// numerically positive definite (or whose last pass is far from the
-// identity) sets flag[b] = 1 (device ints, batch of them; cleared by the
-// caller).
+// triangular factor with Y_in = Q R.  A pass whose Gram matrix has a
+// non-finite pivot, or (from the third pass on) is far from the identity,
+// sets flag[b] to 10 * pass + 1 or 10 * pass + 2 (device ints, one per
+// problem; cleared by the caller).
 void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, int batch, int passes,
             double* Racc, const GemmWorkspace& ws);
 

@@ -573,8 +573,10 @@ static void rsvd_batched(Context& c, int rot, int x, int y0, int s0, int nb, std
     CTM_HIP(hipStreamSynchronize(c.st));
   }
   if (g_debug) {
-    fprintf(stderr, "[ctm] move %lld rot %d col %d cuts %d..%d: cholqr failed %zu, no-sigma %d\n", c.moves, rot, x,
-            y0, y0 + nb - 1, failed.size(), (int)numeric);
+    fprintf(stderr, "[ctm] move %lld rot %d col %d cuts %d..%d: cholqr failed %zu, no-sigma %d, codes", c.moves, rot,
+            x, y0, y0 + nb - 1, failed.size(), (int)numeric);
+    for (int b = 0; b < nb; ++b) fprintf(stderr, " %d", flags[b]);
+    fprintf(stderr, "\n");
   }
   if (numeric) throw Error(-4, "projectors: a cut has no singular value above zero");
 }
@@ -585,13 +587,18 @@ static void column_projectors(Context& c, int rot, int x, int Lyv) {
   std::vector<int> svd;
   for (int y = 0; y < Lyv; ++y) {
     const int nact = c.tdim[view_site(c, rot, x, y)][(3 + rot) % 4][0] * c.Db;
-    if (nact <= c.chi) cut_projectors(c, rot, x, y, y);   // identity
-    else svd.push_back(y);
+    if (nact <= c.chi) {
+      cut_projectors(c, rot, x, y, y);   // identity
+      ++c.cuts[0];
+    } else {
+      svd.push_back(y);
+    }
   }
   if (svd.empty()) return;
   const bool fast = c.cfg.rsvd_oversample >= 0 && c.sla.kmax > 0 && smallla_fits(c.sla, c.kk);
   if (!fast) {
     for (int y : svd) cut_projectors(c, rot, x, y, y);
+    c.cuts[2] += (int64_t)svd.size();
     return;
   }
   std::vector<int> failed;
@@ -599,6 +606,8 @@ static void column_projectors(Context& c, int rot, int x, int Lyv) {
     rsvd_batched(c, rot, x, y0, y0, nb, failed);
     for (int b : failed) cut_projectors(c, rot, x, y0 + b, y0 + b);   // Householder fallback
     for (int b = 0; b < nb; ++b) c.nact_cut[y0 + b] = c.chi;
+    c.cuts[1] += nb - (int64_t)failed.size();
+    c.cuts[2] += (int64_t)failed.size();
   };
   if ((int)svd.size() == Lyv) {
     run(0, Lyv);
@@ -613,11 +622,13 @@ void cut_projectors_fast(Context& c, int rot, int x, int y) {
   const int nact = c.tdim[view_site(c, rot, x, y)][(3 + rot) % 4][0] * c.Db;
   if (nact <= c.chi || c.cfg.rsvd_oversample < 0 || c.sla.kmax == 0 || !smallla_fits(c.sla, c.kk)) {
     cut_projectors(c, rot, x, y, 0);
+    ++c.cuts[nact <= c.chi ? 0 : 2];
     return;
   }
   std::vector<int> failed;
   rsvd_batched(c, rot, x, y, 0, 1, failed);
   if (!failed.empty()) cut_projectors(c, rot, x, y, 0);
+  ++c.cuts[failed.empty() ? 1 : 2];
   c.nact_cut[0] = c.chi;
   c.last_cut_svd = true;
 }

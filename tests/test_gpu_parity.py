@@ -82,6 +82,8 @@ def test_projectors_parity(lib, mode):
                 assert np.max(np.abs(Pt @ P - Ptr @ Pr)) / scale < 1e-8
                 assert rel_err(P, Pr) < 1e-8 and rel_err(Pt, Ptr) < 1e-8
                 assert k == chi
+    # every cut went through the path under test (no fallback)
+    assert ctx.ctm_cut_stats()[1 if mode == "rsvd" else 2] == 16
 
 
 def test_graded_cut_after_growth(lib):
@@ -115,6 +117,7 @@ def test_graded_cut_after_growth(lib):
             ref = H_u @ Ptr @ Pr @ H_dT
             got = H_u @ Pt @ P @ H_dT
             assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref)), (x, y)
+    assert ctx.ctm_cut_stats()[1] > 0 and ctx.ctm_cut_stats()[2] == 0
     H = wl.heisenberg_bond()
     ctx.ctm_move("left")
     ora.left_move(0)
@@ -130,6 +133,7 @@ def test_one_move_parity(lib, direction, r):
     inject(ora, ctx, random_env(2, 2, chi, D * D, seed=10))
     ctx.ctm_move(direction)
     ora.left_move(r)
+    assert ctx.ctm_cut_stats() == (0, 4, 0)
     for i in range(4):
         C, T, _ = ctx.ctm_get_env(i)
         for k in range(4):
@@ -175,6 +179,7 @@ def test_sweeps_energy_and_spectra(lib, Lx, Ly, D, chi, seed):
     for _ in range(sweeps):
         for dname in ("left", "right", "up", "down"):
             ctx.ctm_move(dname)
+    assert ctx.ctm_cut_stats()[2] == 0
     ora = _oracle_run(A, Lx, Ly, chi, sweeps)
     # the oracle's own spread under input perturbations of the size of
     # summation-order differences (1e-13 relative), three samples
