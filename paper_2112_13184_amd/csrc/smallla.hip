@@ -15,6 +15,7 @@
 //   LDS.  A sweep is one full tournament; sweeps stop on the device once no
 //   pair is rotated by more than the tolerance.
 #include "smallla.hpp"
+#include "wave.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -25,17 +26,6 @@ namespace {
 constexpr int kCholThreads = 1024;
 constexpr int kCholME = (kSmallLAMaxK * (kSmallLAMaxK + 1) / 2 + kCholThreads - 1) / kCholThreads;
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
 
 __device__ double block_reduce(double v, bool is_max, double* sh) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -232,8 +222,9 @@ __device__ __forceinline__ int circle(int pos, int round, int m) {
 }
 
 // One tournament round over blocks: workgroup w of problem b orthogonalises
-// the 2*bs columns of its block pair (columns >= k are zero padding).
-__global__ __launch_bounds__(256) void k_jacobi_round(double* A, double* J, int k, int nb, int bs, int round,
+// the 2*bs columns of its block pair (columns >= k are zero padding), one
+// wave per column pair of each inner round (launched with 64 * bs threads).
+__global__ __launch_bounds__(1024) void k_jacobi_round(double* A, double* J, int k, int nb, int bs, int round,
                                                        double* off, const int* conv, double tol) {
   extern __shared__ double sm[];
   const int b = blockIdx.y;
@@ -298,7 +289,7 @@ __global__ __launch_bounds__(256) void k_jacobi_round(double* A, double* J, int 
     }
   }
   // largest relative rotation of this workgroup -> off[b] (positive doubles order like their bits)
-  __shared__ double red[4];
+  __shared__ double red[16];
   offl = wave_max(offl);
   if (lane == 0) red[wv] = offl;
   __syncthreads();
@@ -424,7 +415,8 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   const int max_sweeps = 14;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < nb - 1; ++r)
-      hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(256), lds, st, A, J, k, nb, bs, r, off, conv, tol);
+      hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(64 * bs), lds, st, A, J, k, nb, bs, r, off, conv,
+                         tol);
     hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, batch, tol);
   }
   CTM_HIP(hipGetLastError());

@@ -1,16 +1,12 @@
 """Helpers shared by the GPU parity tests: same seeded inputs to both sides."""
 import numpy as np
 
+import workloads as wl
+
 
 def random_env(Lx, Ly, chi, Db, seed):
     """Random corners / edges (all legs chi) for every site: list of (C[4], T[4])."""
-    rng = np.random.default_rng(seed)
-    env = []
-    for _ in range(Lx * Ly):
-        C = [rng.standard_normal((chi, chi)) for _ in range(4)]
-        T = [rng.standard_normal((chi, chi, Db)) for _ in range(4)]
-        env.append((C, T))
-    return env
+    return wl.random_environment(Lx, Ly, chi, Db, seed)
 
 
 def inject(oracle_env, gpu_ctx, env):

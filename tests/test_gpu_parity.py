@@ -267,6 +267,10 @@ def _golden(name):
 
 @pytest.mark.parametrize("name", ["itps_d4_chi64", "itps_d6_chi144"])
 def test_full_size_against_stored_oracle(lib, name):
+    """Runs from the trivial boundary: the early sweeps amplify rounding by
+    orders of magnitude (the truncation gaps are small while the environment
+    grows), so each recorded energy is compared within 20x the oracle's own
+    spread over three 1e-13 input perturbations."""
     g = _golden(name)
     w = g["params"]
     A = wl.random_itps(2, 2, w["D"], 2, seed=w["seed"])
@@ -280,5 +284,34 @@ def test_full_size_against_stored_oracle(lib, name):
         if str(s) in g["energies"]:
             e = _gpu_energy(ctx, H, 4)
             ref = g["energies"][str(s)]
-            sens = abs(ref - g["energies_perturbed"][str(s)])
+            sens = max(abs(ref - p[str(s)]) for p in g["energies_perturbed"])
             assert abs(e - ref) < max(1e-10, 20 * sens), (s, e, ref, sens)
+    assert ctx.ctm_cut_stats()[2] == 0
+
+
+@pytest.mark.parametrize("direction", ["left", "up", "right", "down"])
+def test_full_size_one_move(lib, direction):
+    """One move of the D=6, chi=144 workload (the benchmark's configuration)
+    from a random full-dimension environment, against sampled entries of the
+    oracle's renormalised tensors (max-abs normalised): 1e-8, as for the
+    small one-move test."""
+    g = _golden("move_d6_chi144")
+    w = g["params"]
+    D, chi = w["D"], w["chi"]
+    A = wl.random_itps(2, 2, D, 2, seed=w["seed"])
+    ctx = lib.Ctm(A, 2, 2, D, chi, rsvd_oversample=w["p"], rsvd_power_iters=w["q"], seed=w["sketch_seed"],
+                  svd_rel_cutoff=g["cutoff"])
+    for i, (C, T) in enumerate(wl.random_environment(2, 2, chi, D * D, seed=w["env_seed"])):
+        ctx.ctm_set_env(i, C, T)
+    ctx.ctm_move(direction)
+    assert ctx.ctm_cut_stats() == (0, 4, 0)
+    for key, rec in g["moves"][direction].items():
+        kind, rest = key[0], key[1:]
+        k = int(rest.split("_")[0]) - 1
+        i = int(rest.split("site")[1])
+        C, T, _ = ctx.ctm_get_env(i)
+        x = C[k] if kind == "C" else T[k]
+        assert list(x.shape) == rec["shape"]
+        got = x.reshape(-1)[np.asarray(rec["pos"])]
+        assert np.max(np.abs(got - np.asarray(rec["val"]))) < 1e-8, key
+        assert abs(np.linalg.norm(x) - rec["fro"]) < 1e-8 * rec["fro"], key

@@ -14,6 +14,8 @@ Workloads (sizes as in the benchmark configurations):
   with W' W'^T = exp((beta/2) s s').
 * ``random_itps(Lx, Ly, D, d, seed)``: N(0, 1) entries (PCG64, sites drawn in
   order, C order), each tensor divided by its max-abs entry.
+* ``random_environment(Lx, Ly, chi, Db, seed)``: N(0, 1) corners and edges
+  with every leg of full size (generic spectra at every cut).
 * ``heisenberg_bond()``: S=1/2 Heisenberg bond operator of the paper's worked
   example (Sec. 3.2), op[(out_i, out_j), (in_i, in_j)].
 * ``tfim_bond(h)`` / ``tfim_product_state(h)``: transverse-field Ising in
@@ -69,6 +71,20 @@ def random_itps(Lx, Ly, D, d, seed):
         A = rng.standard_normal((D, D, D, D, d))
         out.append(A / np.max(np.abs(A)))
     return out
+
+
+def random_environment(Lx, Ly, chi, Db, seed):
+    """Random corners and edges, every chi leg of full size: one ([C1..C4],
+    [T1..T4]) pair per site, N(0, 1) entries (PCG64, sites in order, C
+    matrices then T tensors, C order), C_k of shape (chi, chi) and T_k of
+    shape (chi, chi, Db)."""
+    rng = np.random.default_rng(seed)
+    env = []
+    for _ in range(Lx * Ly):
+        C = [rng.standard_normal((chi, chi)) for _ in range(4)]
+        T = [rng.standard_normal((chi, chi, Db)) for _ in range(4)]
+        env.append((C, T))
+    return env
 
 
 def random_classical(Lx, Ly, D, seed, positive=True):
