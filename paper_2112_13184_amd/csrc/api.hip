@@ -44,7 +44,10 @@ bool valid_config(const ctm_config* cfg, std::string& why) {
   if (cfg->layers == 2 && (cfg->d < 1 || cfg->d > 8)) { why = "d must be in 1..8"; return false; }
   if (cfg->layers == 1 && cfg->d != 1) { why = "a classical network (layers = 1) has d = 1"; return false; }
   if (cfg->chi < 1 || cfg->chi > 1024) { why = "chi must be in 1..1024"; return false; }
-  if (cfg->prec != CTM_F64) { why = "this build computes in FP64 only"; return false; }
+  if (cfg->prec != CTM_F64 && cfg->prec != CTM_F32 && cfg->prec != CTM_BF16 && cfg->prec != CTM_F16_SPLIT) {
+    why = "prec must be CTM_F64, CTM_F32, CTM_BF16 or CTM_F16_SPLIT";
+    return false;
+  }
   if (cfg->rsvd_power_iters < 0 || cfg->rsvd_power_iters > 8) { why = "rsvd_power_iters must be 0..8"; return false; }
   if (!(cfg->svd_rel_cutoff >= 0.0) || cfg->svd_rel_cutoff >= 1.0) { why = "svd_rel_cutoff must be in [0, 1)"; return false; }
   long Db = (long)cfg->D * (cfg->layers == 2 ? cfg->D : 1);

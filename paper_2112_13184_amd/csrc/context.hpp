@@ -107,6 +107,8 @@ struct Context {
   DevBuf spec, specprev, cornerscratch;
   DevBuf gws;                // GEMM split-K workspace
   size_t gws_elems = 0;
+  DevBuf amax;               // split-FP16 operand scaling (2 words)
+  GemmType ctype = GemmType::F64;   // arithmetic of the contraction GEMMs
   Arena arena;
   std::vector<int> nact_cut; // per cut of the current column: bond dim after the move
   int64_t cuts[3] = {0, 0, 0}; // cuts by path: identity, batched randomized SVD, fallback
@@ -118,7 +120,7 @@ struct Context {
   double* Tb(int s, int k) const { return envTb.as<double>() + ((long)s * 4 + k) * chi * chi * Db; }
   const double* Ak(int rot, int s) const { return Aket.as<double>() + ((long)rot * N + s) * szk; }
   const double* Ab(int rot, int s) const { return Abra.as<double>() + ((long)rot * N + s) * szb; }
-  GemmWorkspace ws() const { return GemmWorkspace{gws.as<double>(), gws_elems}; }
+  GemmWorkspace ws() const { return GemmWorkspace{gws.as<double>(), gws_elems, amax.as<unsigned>()}; }
 };
 
 // Run f (which enqueues work on c.st) inside a timed region of `phase`.

@@ -32,6 +32,7 @@ struct KArgs {
   int splits, kchunk;   // split-K: each split covers kchunk of K (multiple of BK)
   double* ws;           // partials [split][batch][M][N] when splits > 1
   int batch;
+  const unsigned* amax; // F16 split: largest |A|, |B| as FP32 bits
 };
 
 __device__ __forceinline__ long off0(const int* t, long s, int i) { return t ? (long)t[i] : (long)i * s; }
@@ -193,6 +194,277 @@ void launch_f64(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid)
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, false, false>), grid, dim3(256), 0, st, g);
 }
 
+// ---------------------------------------------------------------------------
+// Reduced-precision kernels: FP64 operands are rounded while being staged into
+// LDS (k contiguous per row, padded so that every lane's 8-element fragment
+// is one 16-byte LDS read and the 16 rows of a fragment hit distinct banks);
+// MFMA with FP32 accumulation; the epilogue widens to FP64.
+//
+// Lane layouts (checked on gfx950 against exact integer products):
+//   v_mfma_f32_16x16x4f32:          lane l supplies A[l%16][k(l/16)], B[k(l/16)][l%16];
+//   v_mfma_f32_16x16x32_{bf16,f16}: lane l supplies A[l%16][8(l/16)+i], B[8(l/16)+i][l%16], i < 8;
+//   both return D[4(l/16)+r][l%16] in register r.
+// In the FP32 kernel the eight MFMAs of a 32-wide K step take k = 8(l/16)+s
+// at step s, so each lane also reads eight contiguous values.
+// ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+enum { LP_F32 = 1, LP_BF16 = 2, LP_F16 = 3 };
+
+template <int KIND> struct LpStore;
+template <> struct LpStore<LP_F32> { typedef float T; };
+template <> struct LpStore<LP_BF16> { typedef __bf16 T; };
+template <> struct LpStore<LP_F16> { typedef _Float16 T; };
+
+// 2^s with |x| * 2^s <= 2^14 for every entry x of an operand whose largest
+// magnitude is m (FP32 bits); 1 for m = 0 or non-finite m.
+__device__ __forceinline__ double f16_scale(unsigned mbits) {
+  const float m = __uint_as_float(mbits);
+  if (!(m > 0.0f) || !(m < 3.0e38f)) return 1.0;
+  return ldexp(1.0, 14 - (ilogbf(m) + 1));
+}
+
+template <int KIND, int BM, int BN, int WAVES_M, bool A_KC, bool B_KC>
+__global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
+  typedef typename LpStore<KIND>::T T;
+  constexpr int BK = 32;
+  constexpr int LDK = BK + (KIND == LP_F32 ? 4 : 8);
+  constexpr int NP = (KIND == LP_F16) ? 2 : 1;   // hi (and lo) parts
+  constexpr int WAVES_N = 4 / WAVES_M;
+  constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
+  static_assert(TM >= 1 && TN >= 1 && EA >= 1 && EB >= 1, "tile");
+  __shared__ __attribute__((aligned(16))) T As[2][NP][BM * LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_n = (g.N + BN - 1) / BN;
+  const int tm_ = blockIdx.x / tiles_n, tn_ = blockIdx.x % tiles_n;
+  const int split = blockIdx.y, b = blockIdx.z;
+  const int m0 = tm_ * BM, n0 = tn_ * BN;
+  const int kb = split * g.kchunk;
+  const int ke = min(g.K, kb + g.kchunk);
+  const double* A = g.A + (long)b * g.bsa;
+  const double* B = g.B + (long)b * g.bsb;
+  double sa = 1.0, sb = 1.0;
+  if (KIND == LP_F16) {
+    sa = f16_scale(g.amax[0]);
+    sb = f16_scale(g.amax[1]);
+  }
+
+  int a_r[EA], a_k[EA];
+  long a_roff[EA];
+  bool a_rok[EA];
+#pragma unroll
+  for (int j = 0; j < EA; ++j) {
+    int e = tid + 256 * j;
+    if (A_KC) { a_k[j] = e % BK; a_r[j] = e / BK; }
+    else      { a_r[j] = e % BM; a_k[j] = e / BM; }
+    int m = m0 + a_r[j];
+    a_rok[j] = m < g.M;
+    a_roff[j] = a_rok[j] ? off0(g.ta0, g.sa0, m) : 0;
+  }
+  int b_c[EB], b_k[EB];
+  long b_coff[EB];
+  bool b_cok[EB];
+#pragma unroll
+  for (int j = 0; j < EB; ++j) {
+    int e = tid + 256 * j;
+    if (B_KC) { b_k[j] = e % BK; b_c[j] = e / BK; }
+    else      { b_c[j] = e % BN; b_k[j] = e / BN; }
+    int n = n0 + b_c[j];
+    b_cok[j] = n < g.N;
+    b_coff[j] = b_cok[j] ? off0(g.tb1, g.sb1, n) : 0;
+  }
+
+  double ra[EA], rb[EB];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < EA; ++j) {
+      int k = k0 + a_k[j];
+      ra[j] = (a_rok[j] && k < ke) ? A[a_roff[j] + off0(g.ta1, g.sa1, k)] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < EB; ++j) {
+      int k = k0 + b_k[j];
+      rb[j] = (b_cok[j] && k < ke) ? B[b_coff[j] + off0(g.tb0, g.sb0, k)] : 0.0;
+    }
+  };
+  auto put = [&](T* hi, T* lo, int idx, double x, double sc) {
+    if constexpr (KIND == LP_F16) {
+      const double xs = x * sc;                        // exact (power of two)
+      const _Float16 h = (_Float16)(float)xs;
+      hi[idx] = h;
+      lo[idx] = (_Float16)(float)((xs - (double)h) * 2048.0);
+    } else {
+      hi[idx] = (T)(float)x;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < EA; ++j) put(As[buf][0], As[buf][NP - 1], a_r[j] * LDK + a_k[j], ra[j], sa);
+#pragma unroll
+    for (int j = 0; j < EB; ++j) put(Bs[buf][0], Bs[buf][NP - 1], b_c[j] * LDK + b_k[j], rb[j], sb);
+  };
+
+  f4 acc[TM][TN], acc2[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc2[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+  const int r16 = lane & 15, kg = lane >> 4;
+
+  int nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
+  if (nk > 0) {
+    load_tile(kb);
+    store_tile(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
+    if constexpr (KIND == LP_F32) {
+      f4 af[TM][2], bfr[TN][2];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const f4* p = reinterpret_cast<const f4*>(&As[cur][0][(wm0 + i * 16 + r16) * LDK + 8 * kg]);
+        af[i][0] = p[0];
+        af[i][1] = p[1];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const f4* p = reinterpret_cast<const f4*>(&Bs[cur][0][(wn0 + j * 16 + r16) * LDK + 8 * kg]);
+        bfr[j][0] = p[0];
+        bfr[j][1] = p[1];
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s >> 2][s & 3], bfr[j][s >> 2][s & 3],
+                                                             acc[i][j], 0, 0, 0);
+    } else if constexpr (KIND == LP_BF16) {
+      bf8 af[TM], bfr[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        af[i] = *reinterpret_cast<const bf8*>(&As[cur][0][(wm0 + i * 16 + r16) * LDK + 8 * kg]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bfr[j] = *reinterpret_cast<const bf8*>(&Bs[cur][0][(wn0 + j * 16 + r16) * LDK + 8 * kg]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    } else {
+      h8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int o = (wm0 + i * 16 + r16) * LDK + 8 * kg;
+        ah[i] = *reinterpret_cast<const h8*>(&As[cur][0][o]);
+        al[i] = *reinterpret_cast<const h8*>(&As[cur][NP - 1][o]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int o = (wn0 + j * 16 + r16) * LDK + 8 * kg;
+        bh[j] = *reinterpret_cast<const h8*>(&Bs[cur][0][o]);
+        bl[j] = *reinterpret_cast<const h8*>(&Bs[cur][NP - 1][o]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc2[i][j], 0, 0, 0);
+          acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc2[i][j], 0, 0, 0);
+        }
+    }
+    if (it + 1 < nk) store_tile(cur ^ 1);
+    __syncthreads();
+  }
+
+  double* C = g.C + (long)b * g.bsc;
+  const double unscale = g.alpha / (sa * sb);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int m = m0 + wm0 + i * 16 + kg * 4 + r;
+        int n = n0 + wn0 + j * 16 + r16;
+        if (m < g.M && n < g.N) {
+          double v = (double)acc[i][j][r];
+          if constexpr (KIND == LP_F16) v += (double)acc2[i][j][r] * (1.0 / 2048.0);
+          v *= unscale;
+          if (g.splits > 1) {
+            g.ws[(((long)split * g.batch + b) * g.M + m) * g.N + n] = v;
+          } else {
+            long o = off0(g.tc0, g.sc0, m) + off0(g.tc1, g.sc1, n);
+            C[o] = (g.beta == 0.0) ? v : v + g.beta * C[o];
+          }
+        }
+      }
+}
+
+__global__ void k_amax_clear(unsigned* out) {
+  if (threadIdx.x < 2) out[threadIdx.x] = 0u;
+}
+
+// out[which] = max(out[which], largest |x| over an R x Cn operand (FP32 bits;
+// non-negative floats order like their bit patterns).
+__global__ void k_operand_amax(const double* P, long s0, long s1, const int* t0, const int* t1, long bs, int R,
+                               int Cn, int batch, unsigned* out, int which) {
+  __shared__ float red[4];
+  const long per = (long)R * Cn, total = per * batch;
+  float m = 0.0f;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long bb = e / per, rem = e % per;
+    const int i = (int)(rem / Cn), j = (int)(rem % Cn);
+    m = fmaxf(m, fabsf((float)P[bb * bs + off0(t0, s0, i) + off0(t1, s1, j)]));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmaxf(r, red[w]);
+    atomicMax(out + which, __float_as_uint(r));
+  }
+}
+
+template <int KIND, int BM, int BN, int WAVES_M>
+void launch_lp(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
+  if (a_kc && b_kc)
+    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, true, true>), grid, dim3(256), 0, st, g);
+  else if (a_kc && !b_kc)
+    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, true, false>), grid, dim3(256), 0, st, g);
+  else if (!a_kc && b_kc)
+    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, false, true>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, false, false>), grid, dim3(256), 0, st, g);
+}
+
+template <int BM, int BN, int WAVES_M>
+void launch_typed(hipStream_t st, GemmType type, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
+  switch (type) {
+    case GemmType::F64: launch_f64<BM, BN, WAVES_M>(st, g, a_kc, b_kc, grid); break;
+    case GemmType::F32: launch_lp<LP_F32, BM, BN, WAVES_M>(st, g, a_kc, b_kc, grid); break;
+    case GemmType::BF16: launch_lp<LP_BF16, BM, BN, WAVES_M>(st, g, a_kc, b_kc, grid); break;
+    case GemmType::F16: launch_lp<LP_F16, BM, BN, WAVES_M>(st, g, a_kc, b_kc, grid); break;
+  }
+}
+
 // Choose the split of K so that a small output grid still fills the GPU.
 int choose_splits(long tiles, int K) {
   const long target = 1024;   // ~4 workgroups per CU on 256 CUs
@@ -212,7 +484,7 @@ size_t gemm_workspace_elems(int M, int N, int K, int batch) {
 void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, const Operand& A,
           const Operand& B, double beta, const OutOperand& C, int batch, const GemmWorkspace& ws) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
-  CTM_CHECK(type == GemmType::F64, -1, "gemm: only FP64 is built in this path");
+  CTM_CHECK(type != GemmType::F16 || ws.amax != nullptr, -1, "gemm: split FP16 needs a scaling workspace");
   KArgs g{};
   g.A = static_cast<const double*>(A.p);
   g.B = static_cast<const double*>(B.p);
@@ -234,11 +506,20 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   int splits = (K > 0) ? choose_splits(tiles, K) : 1;
   if (splits > 1 && (ws.p == nullptr || ws.elems < (size_t)splits * batch * M * N)) splits = 1;
   int kchunk = (K > 0) ? ((ceil_div(K, splits) + 15) / 16) * 16 : 16;
+  if (type != GemmType::F64) kchunk = ((kchunk + 31) / 32) * 32;   // whole 32-wide K steps
   splits = (K > 0) ? ceil_div(K, kchunk) : 1;
-  g.splits = splits; g.kchunk = kchunk; g.ws = ws.p;
+  g.splits = splits; g.kchunk = kchunk; g.ws = ws.p; g.amax = ws.amax;
+  if (type == GemmType::F16 && K > 0) {
+    hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, ws.amax);
+    hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.A, g.sa0, g.sa1, g.ta0, g.ta1, g.bsa, M, K,
+                       batch, ws.amax, 0);
+    hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.B, g.sb0, g.sb1, g.tb0, g.tb1, g.bsb, K, N,
+                       batch, ws.amax, 1);
+    CTM_HIP(hipGetLastError());
+  }
   dim3 grid((unsigned)(ceil_div(M, BM) * ceil_div(N, BN)), (unsigned)splits, (unsigned)batch);
-  if (BN == 32) launch_f64<128, 32, 4>(st, g, a_kc, b_kc, grid);
-  else          launch_f64<64, 64, 2>(st, g, a_kc, b_kc, grid);
+  if (BN == 32) launch_typed<128, 32, 4>(st, type, g, a_kc, b_kc, grid);
+  else          launch_typed<64, 64, 2>(st, type, g, a_kc, b_kc, grid);
   CTM_HIP(hipGetLastError());
   if (splits > 1) {
     long total = (long)batch * M * N;

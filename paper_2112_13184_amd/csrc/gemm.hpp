@@ -34,20 +34,26 @@ inline Operand colmajor(const void* p, long ld, long bs = 0) { Operand o; o.p = 
 inline OutOperand out_rowmajor(void* p, long ld, long bs = 0) { OutOperand o; o.p = p; o.s0 = ld; o.s1 = 1; o.bs = bs; return o; }
 inline OutOperand out_colmajor(void* p, long ld, long bs = 0) { OutOperand o; o.p = p; o.s0 = 1; o.s1 = ld; o.bs = bs; return o; }
 
-// Element type of A and B.  Accumulation is FP64 for F64 and FP32 otherwise;
-// C is always FP64.  For the reduced types the operands are converted (round
-// to nearest even) while being staged into LDS.
+// Arithmetic of the multiply.  Accumulation is FP64 for F64 and FP32
+// otherwise; A, B and C are FP64 in memory.  For the reduced types the
+// operands are rounded (to nearest even) while being staged into LDS:
+//   F32  one v_mfma_f32_16x16x4f32 pass;
+//   BF16 one v_mfma_f32_16x16x32_bf16 pass;
+//   F16  split FP16: x * 2^s = hi + 2^-11 lo with hi, lo FP16 and one power
+//        of two s per operand (from its largest entry, so that it fits FP16's
+//        range), three v_mfma_f32_16x16x32_f16 passes (hi hi, hi lo, lo hi)
+//        with the correction accumulated apart (Markidis et al. 2018, Ootomo
+//        and Yokota 2022).
 enum class GemmType { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 
 struct GemmWorkspace {
-  double* p = nullptr;   // split-K partial sums
+  double* p = nullptr;       // split-K partial sums
   size_t elems = 0;
+  unsigned* amax = nullptr;  // 2 words: largest |A| and |B| (F16 scaling)
 };
 
-// C = alpha * A(MxK) * B(KxN) + beta * C for `batch` independent problems.
-// A and B are FP64 in memory.  `type` selects the arithmetic of the
-// multiply: F64 (MFMA f64), F32 / BF16 (one MFMA pass), F16 (FP16 split into
-// hi + lo parts, three MFMA passes).
+// C = alpha * A(MxK) * B(KxN) + beta * C for `batch` independent problems,
+// in the arithmetic `type` selects (F16 needs ws.amax).
 void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, const Operand& A,
           const Operand& B, double beta, const OutOperand& C, int batch, const GemmWorkspace& ws);
 

@@ -297,6 +297,13 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.cornerscratch.alloc(sizeof(double) * 4 * c.N * cc);
   c.gws_elems = (size_t)8 * c.n * std::max(c.kk, c.chi);
   c.gws.alloc(sizeof(double) * c.gws_elems);
+  c.amax.alloc(sizeof(unsigned) * 2);
+  switch (cfg.prec) {
+    case CTM_F32: c.ctype = GemmType::F32; break;
+    case CTM_BF16: c.ctype = GemmType::BF16; break;
+    case CTM_F16_SPLIT: c.ctype = GemmType::F16; break;
+    default: c.ctype = GemmType::F64; break;
+  }
   c.nact_cut.assign(Lmax, c.chi);
   CTM_HIP(hipStreamSynchronize(c.st));
 }
@@ -307,11 +314,14 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
 //   bra: out[(cn,r,r')][(cp,dd,d')] = sum_{l',u',p} Y[..][(l',u',p)] Ab[l'][u'][r'][d'][p]
 //        (transposed = true: out[(cp,dd,d')][(cn,r,r')])
 // ----------------------------------------------------------------------------
-// FP64 GEMM on the context stream, timed under `phase` when timing is on.
+// GEMM on the context stream, timed under `phase` when timing is on.  The
+// contractions (every phase but LINALG) run in the configured precision; the
+// GEMMs inside the QR / SVD of the projectors stay FP64.
 static void mm(Context& c, int phase, int M, int N, int K, const Operand& A, const Operand& B,
                const OutOperand& C, int batch = 1) {
+  const GemmType t = (phase == PhaseTimer::LINALG) ? GemmType::F64 : c.ctype;
   timed(c, phase, 2.0 * M * N * (double)K * batch, [&] {
-    gemm(c.st, GemmType::F64, M, N, K, 1.0, A, B, 0.0, C, batch, c.ws());
+    gemm(c.st, t, M, N, K, 1.0, A, B, 0.0, C, batch, c.ws());
   });
 }
 

@@ -1,0 +1,93 @@
+"""Reduced-precision contraction GEMMs (FP32, BF16, split FP16 on MFMA with FP32
+accumulation; QR, SVD, normalisation and expectation values in FP64) against
+the FP64 CPU oracle and the FP64 GPU path.
+
+Tolerances: enlarged corners relative to their largest entry, 1e-5 for FP32
+and split FP16 (a K-term FP32 sum of rounded products), 2e-2 for BF16 (8-bit
+significands); energies per site 1e-5 for FP32 and split FP16 (the stated
+target for reduced precision), 1e-3 for BF16, which is not expected to meet
+1e-5 and whose error is reported by the benchmark."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import observables as ob
+from oracle.ctmrg import Environment
+from tests._util import inject, random_env, rel_err
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+CORNER_TOL = {"f32": 1e-5, "f16split": 1e-5, "bf16": 2e-2}
+ENERGY_TOL = {"f32": 1e-5, "f16split": 1e-5, "bf16": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2112_13184_amd as p
+    p.load()
+    return p
+
+
+def _energy(ctx, N):
+    H = wl.heisenberg_bond()
+    return sum(ctx.ctm_expect_2site(i, 0, H) + ctx.ctm_expect_2site(i, 1, H) for i in range(N)) / N
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f16split"])
+def test_enlarged_corners_reduced_precision(lib, prec):
+    D, chi = 3, 20
+    A = wl.random_itps(2, 2, D, 2, seed=13)
+    ctx = lib.Ctm(A, 2, 2, D, chi, prec=prec, rsvd_oversample=8, rsvd_power_iters=1, seed=1)
+    ora = Environment(A, 2, 2, chi=chi, layers=2)
+    env = random_env(2, 2, chi, D * D, seed=31)
+    # scale one site's tensors far from 1 to exercise the FP16 power-of-two scaling
+    env[1] = ([c * 3e3 for c in env[1][0]], [t * 1e-3 for t in env[1][1]])
+    inject(ora, ctx, env)
+    for site in range(4):
+        for j in range(4):
+            G = ctx.ctm_enlarged_corner(j, site)
+            assert rel_err(G, ora.corner(site, j)) < CORNER_TOL[prec], (site, j)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16split", "bf16"])
+def test_energy_d4_chi64_against_stored_oracle(lib, prec):
+    """30 sweeps of the D=4, chi=64 workload: energy per site after 10, 20 and
+    30 sweeps (converged region) against the stored FP64 oracle run."""
+    path = os.path.join(GOLDEN, "itps_d4_chi64.json")
+    g = json.load(open(path))
+    w = g["params"]
+    A = wl.random_itps(2, 2, w["D"], 2, seed=w["seed"])
+    ctx = lib.Ctm(A, 2, 2, w["D"], w["chi"], prec=prec, rsvd_oversample=w["p"], rsvd_power_iters=w["q"],
+                  seed=w["sketch_seed"], svd_rel_cutoff=g["cutoff"])
+    for s in range(1, 31):
+        for dname in ("left", "right", "up", "down"):
+            ctx.ctm_move(dname)
+        if s in (10, 20, 30):
+            e = _energy(ctx, 4)
+            err = abs(e - g["energies"][str(s)])
+            print(f"{prec} sweep {s}: |E - E_oracle| = {err:.3e}")
+            assert err < ENERGY_TOL[prec], (s, err)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16split", "bf16"])
+def test_energy_full_size_against_gpu_f64(lib, prec):
+    """The D=6, chi=144 benchmark workload, 20 sweeps: reduced-precision energy
+    per site against the FP64 GPU path (itself matched to the oracle move by
+    move at this size)."""
+    D, chi = 6, 144
+    A = wl.random_itps(2, 2, D, 2, seed=2)
+    out = {}
+    for p in ("f64", prec):
+        ctx = lib.Ctm(A, 2, 2, D, chi, prec=p, rsvd_oversample=48, rsvd_power_iters=1, seed=12)
+        for _ in range(20):
+            for dname in ("left", "right", "up", "down"):
+                ctx.ctm_move(dname)
+        out[p] = _energy(ctx, 4)
+        del ctx
+    err = abs(out[prec] - out["f64"])
+    print(f"{prec}: E = {out[prec]:.12f}, E_f64 = {out['f64']:.12f}, error {err:.3e}")
+    assert err < ENERGY_TOL[prec]
