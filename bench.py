@@ -63,6 +63,51 @@ def cpu_baseline(D, chi, p, q, seed):
                        f"full-dimension environment, NumPy/OpenBLAS FP64, {dt:.1f} s; scaled x4")
 
 
+def run_sweeps(lib, A, D, chi, d, p, q, prec, warmup, steps):
+    """warmup untimed sweeps, then `steps` timed sweeps; returns (seconds, phase
+    timings, energy per site after warmup + steps sweeps, cut counts)."""
+    import torch
+    ctx = lib.Ctm(A, 2, 2, D, chi, d=d, prec=prec, rsvd_oversample=p, rsvd_power_iters=q, seed=12)
+    moves = ("left", "right", "up", "down")
+    for _ in range(warmup):
+        for m in moves:
+            ctx.ctm_move(m)
+    torch.cuda.synchronize()
+    ctx.ctm_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for m in moves:
+            ctx.ctm_move(m)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    phases = ctx.ctm_timing_read()
+    ctx.ctm_timing_enable(False)
+    H = wl.heisenberg_bond()
+    energy = sum(ctx.ctm_expect_2site(i, dr, H) for i in range(4) for dr in (0, 1)) / 4
+    cuts = ctx.ctm_cut_stats()
+    del ctx
+    return dt, phases, energy, cuts
+
+
+def sketch_rate(phases):
+    sk = phases["sketch_gemm"]
+    return sk["flops"] / (sk["ms"] * 1e-3) if sk["ms"] > 0 else 0.0
+
+
+def copy_calibration():
+    """Plain device-to-device copies of a known size (1 GiB, 5 times), for
+    scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    x.uniform_()
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": x.numel() * 8, "launches": 5}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +119,10 @@ def main():
     ap.add_argument("--p", type=int, default=48)
     ap.add_argument("--q", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precisions", action="store_true",
+                    help="skip the comparison runs in the other precisions")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -84,30 +133,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     lib.load()
     D, chi, d, p, q = args.D, args.chi, 2, args.p, args.q
     A = wl.random_itps(2, 2, D, d, seed=2)
-    ctx = lib.Ctm(A, 2, 2, D, chi, d=d, prec=args.prec, rsvd_oversample=p, rsvd_power_iters=q, seed=12)
-    moves = ("left", "right", "up", "down")
-    for _ in range(args.warmup):
-        for m in moves:
-            ctx.ctm_move(m)
-    torch.cuda.synchronize()
-    ctx.ctm_timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        for m in moves:
-            ctx.ctm_move(m)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    phases = ctx.ctm_timing_read()
-    ctx.ctm_timing_enable(False)
+    dt, phases, energy, cuts = run_sweeps(lib, A, D, chi, d, p, q, args.prec, args.warmup, args.steps)
     sweeps_per_s = args.steps / dt
     sk = phases["sketch_gemm"]
-    achieved = sk["flops"] / (sk["ms"] * 1e-3) if sk["ms"] > 0 else 0.0
-    H = wl.heisenberg_bond()
-    energy = sum(ctx.ctm_expect_2site(i, dr, H) for i in range(4) for dr in (0, 1)) / 4
+    achieved = sketch_rate(phases)
     alg = flops_per_sweep(D, chi, d, p, q)
     out = {
         "metric": METRIC,
@@ -133,8 +168,24 @@ def main():
                         "frac_of_peak": alg * sweeps_per_s / PEAK[args.prec]},
         "phases_ms_per_sweep": {k: v["ms"] / args.steps for k, v in phases.items()},
         "energy_per_site": energy,
-        "cuts": dict(zip(("identity", "rsvd_batched", "fallback"), ctx.ctm_cut_stats())),
+        "cuts": dict(zip(("identity", "rsvd_batched", "fallback"), cuts)),
     }
+    if not args.no_precisions:
+        # the same workload and sweep count in every precision: throughput,
+        # sketch-GEMM MFMA fraction of that precision's peak, and the energy
+        # difference to this run (the FP64 path is matched to the oracle move
+        # by move at this size)
+        cmp = {}
+        for prec in ("f64", "f32", "f16split", "bf16"):
+            if prec == args.prec:
+                continue
+            dtp, php, ep, _ = run_sweeps(lib, A, D, chi, d, p, q, prec, args.warmup, args.steps)
+            r = sketch_rate(php)
+            cmp[prec] = {"sweeps_per_s": args.steps / dtp, "sketch_tflops": r / 1e12,
+                         "sketch_frac_of_peak": r / PEAK[prec], "peak_tflops": PEAK[prec] / 1e12,
+                         "energy_per_site": ep, "abs_energy_diff": abs(ep - energy),
+                         "phases_ms_per_sweep": {k: v["ms"] / args.steps for k, v in php.items()}}
+        out["precisions"] = cmp
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, p, q, seed=2)
     print(json.dumps(out), flush=True)

@@ -281,3 +281,54 @@ class Ctm:
             self.ctm_free()
         except Exception:
             pass
+
+
+class Queue:
+    """A ctm_queue: CTMRG solves admitted by HBM footprint and run concurrently."""
+
+    def __init__(self, hbm_budget_bytes, max_active):
+        lib = load()
+        q = ctypes.c_void_p()
+        st = lib.ctm_queue_create(int(hbm_budget_bytes), int(max_active), ctypes.byref(q))
+        if st != CTM_OK:
+            raise CtmError(st, "ctm_queue_create failed")
+        self._lib, self._q, self._keep = lib, q, {}
+
+    def submit(self, tensors, Lx, Ly, D, chi, bond_op, onsite_op=None, tol=1e-10, max_sweeps=40, tag=0,
+               d=2, **kw):
+        """Returns (status, ticket); inputs are copied by the library."""
+        req = ctm_request()
+        req.cfg = make_config(Lx, Ly, D, chi, d=d, **kw)
+        t = _f64(np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for a in tensors]))
+        b = _f64(bond_op)
+        o = _f64(onsite_op) if onsite_op is not None else None
+        req.tensors, req.bond_op = _dp(t), _dp(b)
+        req.onsite_op = _dp(o) if o is not None else None
+        req.tol, req.max_sweeps, req.tag = float(tol), int(max_sweeps), int(tag)
+        ticket = ctypes.c_uint64()
+        st = self._lib.ctm_queue_submit(self._q, ctypes.byref(req), ctypes.byref(ticket))
+        return st, ticket.value
+
+    def poll(self, ticket):
+        r = ctm_result()
+        st = self._lib.ctm_queue_poll(self._q, ticket, ctypes.byref(r))
+        return st, r
+
+    def wait(self, ticket, timeout_ms=-1):
+        r = ctm_result()
+        st = self._lib.ctm_queue_wait(self._q, ticket, int(timeout_ms), ctypes.byref(r))
+        return st, r
+
+    def cancel(self, ticket):
+        return self._lib.ctm_queue_cancel(self._q, ticket)
+
+    def destroy(self):
+        if self._q:
+            self._lib.ctm_queue_destroy(self._q)
+            self._q = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

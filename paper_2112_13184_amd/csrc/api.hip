@@ -59,6 +59,8 @@ bool valid_config(const ctm_config* cfg, std::string& why) {
 
 }  // namespace
 
+ctm::Context& ctm::context_of(ctm_ctx* ctx) { return ctx->c; }
+
 extern "C" {
 
 ctm_status ctm_init(const ctm_config* cfg, const double* tensors, int tensors_on_device,
@@ -171,10 +173,7 @@ ctm_status ctm_expect_1site(ctm_ctx* ctx, int site, const double* op, double* va
   if (!ctx || !op || !val) return CTM_EINVAL;
   ctm::Context& c = ctx->c;
   if (site < 0 || site >= c.N || c.layers != 2) { c.err = "site out of range or not an iTPS"; return CTM_EINVAL; }
-  return guarded(ctx, [&] {
-    ctm::rho_1site(c, site, ctx->rho.as<double>(), nullptr);
-    *val = ctm::expect_op(c, ctx->rho.as<double>(), op, c.d);
-  });
+  return guarded(ctx, [&] { *val = ctm::expect_1site(c, site, op); });
 }
 
 ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, double* val) {
@@ -184,10 +183,7 @@ ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, d
     c.err = "site / dir out of range or not an iTPS";
     return CTM_EINVAL;
   }
-  return guarded(ctx, [&] {
-    ctm::rho_2site(c, site, dir, ctx->rho.as<double>(), nullptr);
-    *val = ctm::expect_op(c, ctx->rho.as<double>(), op, c.d * c.d);
-  });
+  return guarded(ctx, [&] { *val = ctm::expect_2site(c, site, dir, op); });
 }
 
 ctm_status ctm_impurity(ctm_ctx* ctx, int site, const double* b, double* val) {

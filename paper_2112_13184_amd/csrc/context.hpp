@@ -2,6 +2,7 @@
 #pragma once
 
 #include <array>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -14,12 +15,23 @@
 namespace ctm {
 
 // Bump allocator for the transient tensors of the expectation-value
-// contractions: a list of device chunks, reused after reset().
+// contractions: a list of device chunks, reused after reset().  The first
+// chunk has first_elems elements (the expected peak); release() rolls back to
+// a mark (work already enqueued on the context's stream still reads the
+// released memory before any later kernel can overwrite it).
 struct Arena {
   std::vector<DevBuf*> chunks;
   size_t cur = 0, used = 0;   // current chunk, elements used in it
+  size_t first_elems = 0;
   double* alloc(size_t elems);
   void reset() { cur = 0; used = 0; }
+  std::array<size_t, 2> mark() const { return {cur, used}; }
+  void release(const std::array<size_t, 2>& m) { cur = m[0]; used = m[1]; }
+  size_t bytes() const {
+    size_t b = 0;
+    for (auto* c : chunks) b += c->bytes;
+    return b;
+  }
   ~Arena() { for (auto* b : chunks) delete b; }
 };
 
@@ -141,7 +153,12 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
                   const double* boundary);
 size_t context_footprint(const ctm_config& cfg);
 void do_move(Context& c, int rot);
-void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta, int* converged);
+// Up to max_sweeps sweeps, stopping when delta < tol or when *cancel (checked
+// before every sweep) becomes true.
+void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta, int* converged,
+               const std::atomic<bool>* cancel = nullptr);
+// The context inside a handle of the C ABI.
+Context& context_of(ctm_ctx* ctx);
 void cut_projectors(Context& c, int rot, int x, int y, int slot);
 void cut_projectors_fast(Context& c, int rot, int x, int y);
 void enlarged_corner(Context& c, int s, int j, double* out);
@@ -151,6 +168,14 @@ void rho_1site(Context& c, int site, double* rho_dev, double* rho_host);
 void rho_2site(Context& c, int site, int dir, double* rho_dev, double* rho_host);
 // sum_{i,o} rho[i][o] op[o][i] for a dim x dim operator (host), on the device.
 double expect_op(Context& c, const double* rho_dev, const double* op_host, int dim);
+// <O> on one site and <h> on the bond (site, site + x) (dir 0) or (site, site + y)
+// (dir 1), contracting the operator into closed networks instead of forming
+// the reduced density matrix (op layout [out][in], as for rho).
+double expect_1site(Context& c, int site, const double* op_host);
+double expect_2site(Context& c, int site, int dir, const double* op_host);
+// Elements of the largest transient the expectation values above (and the
+// classical impurity / ln kappa) allocate.
+size_t observe_arena_elems(long chi, long DK, long DB, long d);
 double impurity(Context& c, int site, const double* b_host);
 double log_kappa(Context& c);
 void check_bad(Context& c, const char* where);

@@ -198,6 +198,108 @@ void rho_2site(Context& c, int site, int dir, double* rho_dev, double* rho_host)
   }
 }
 
+namespace {
+
+// The bra tensor with a one-site operator on its physical leg,
+// AbO[l,u,r,d,p] = sum_p' O[p'][p] Ab[l,u,r,d,p'], so that the closed
+// contraction sum_p A[..p] AbO[..p] equals sum_{p,p'} A[..p] O[p'][p] A*[..p'].
+DT bra_with_op(Context& c, const DT& Ab, const double* op_host) {
+  const int d = c.d;
+  double* o = c.arena.alloc((size_t)d * d);
+  CTM_HIP(hipMemcpyAsync(o, op_host, sizeof(double) * d * d, hipMemcpyHostToDevice, c.st));
+  DT out;
+  out.dims = Ab.dims;
+  out.p = c.arena.alloc(Ab.size());
+  gemm(c.st, GemmType::F64, (int)(Ab.size() / d), d, d, 1.0, rowmajor(Ab.p, d), rowmajor(o, d), 0.0,
+       out_rowmajor(out.p, d), 1, c.ws());
+  return out;
+}
+
+void keep(Context& c, const DT& src, double* dst) {
+  CTM_HIP(hipMemcpyAsync(dst, src.p, sizeof(double) * src.size(), hipMemcpyDeviceToDevice, c.st));
+}
+
+std::vector<double> fetch(Context& c, const double* dev, size_t n) {
+  std::vector<double> h(n);
+  CTM_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * n, hipMemcpyDeviceToHost, c.st));
+  CTM_HIP(hipStreamSynchronize(c.st));
+  return h;
+}
+
+}  // namespace
+
+double expect_1site(Context& c, int site, const double* op_host) {
+  c.arena.reset();
+  View v = view_of(c, site, 0);
+  double* res = c.arena.alloc(2);   // value with the operator, norm
+  DT LB = left_boundary(c, v), RB = right_boundary(c, v);
+  const auto m = c.arena.mark();
+  for (int t = 0; t < 2; ++t) {
+    DT Ab = (t == 0) ? bra_with_op(c, v.Ab, op_host) : v.Ab;
+    keep(c, close_lr(c, column(c, LB, v.T[0], v.T[2], v.Ak, Ab, false), RB), res + t);
+    c.arena.release(m);
+  }
+  const std::vector<double> h = fetch(c, res, 2);
+  return h[0] / h[1];
+}
+
+double expect_2site(Context& c, int site, int dir, const double* op_host) {
+  c.arena.reset();
+  const int rot = (dir == 0) ? 0 : 3;
+  int x = site % c.Lx, y = site / c.Lx;
+  for (int i = 0; i < rot; ++i) { int t = x; x = -y; y = t; }
+  const int s = view_site(c, rot, x, y), t = view_site(c, rot, x + 1, y);
+  CTM_CHECK(s == site, -3, "expect_2site: view bookkeeping");
+  View vs = view_of(c, s, rot), vt = view_of(c, t, rot);
+  // h[(ps' pt'), (ps pt)] = sum over (ps', ps) of E_{ps' ps} (x) h_{ps' ps}, one
+  // closed two-column network per non-zero block, plus the norm
+  const int d = c.d, dd = d * d;
+  std::vector<std::vector<double>> ops;   // pairs (a on s, b on t)
+  for (int po = 0; po < d; ++po)
+    for (int pi = 0; pi < d; ++pi) {
+      std::vector<double> a(dd, 0.0), b(dd, 0.0);
+      bool nz = false;
+      a[po * d + pi] = 1.0;
+      for (int qo = 0; qo < d; ++qo)
+        for (int qi = 0; qi < d; ++qi) {
+          b[qo * d + qi] = op_host[(po * d + qo) * dd + (pi * d + qi)];
+          nz |= (b[qo * d + qi] != 0.0);
+        }
+      if (nz) {
+        ops.push_back(a);
+        ops.push_back(b);
+      }
+    }
+  const int nterm = (int)ops.size() / 2;
+  double* res = c.arena.alloc(nterm + 1);
+  DT LB = left_boundary(c, vs), RB = right_boundary(c, vt);
+  double* lslot = c.arena.alloc((size_t)c.chi * c.Db * c.chi);
+  const auto m = c.arena.mark();
+  for (int k = 0; k <= nterm; ++k) {
+    DT Abs = (k < nterm) ? bra_with_op(c, vs.Ab, ops[2 * k].data()) : vs.Ab;
+    DT L1 = column(c, LB, vs.T[0], vs.T[2], vs.Ak, Abs, false);   // [t1', R, t3']
+    keep(c, L1, lslot);
+    DT L1k = make(lslot, L1.dims);
+    c.arena.release(m);
+    DT Abt = (k < nterm) ? bra_with_op(c, vt.Ab, ops[2 * k + 1].data()) : vt.Ab;
+    keep(c, close_lr(c, column(c, L1k, vt.T[0], vt.T[2], vt.Ak, Abt, false), RB), res + k);
+    c.arena.release(m);
+  }
+  const std::vector<double> h = fetch(c, res, nterm + 1);
+  double num = 0.0;
+  for (int k = 0; k < nterm; ++k) num += h[k];
+  return num / h[nterm];
+}
+
+size_t observe_arena_elems(long chi, long DK, long DB, long d) {
+  // one closed column at a time: the left boundary permuted, X and its
+  // permuted copy, Y and its copy, Z and its copy (chi^2 DK^2 DB^2 each, Y
+  // times d), T3 permuted, W; plus the boundaries, the kept slot, the
+  // operator-carrying bra tensors and the 32-element alignment of each block
+  const long c2 = chi * chi, big = c2 * DK * DK * DB * DB, small = c2 * DK * DB;
+  return (size_t)(big * (4 + 2 * d) + 16 * small + 8 * DK * DK * DK * DK * d + 64 * 1024);
+}
+
 double expect_op(Context& c, const double* rho_dev, const double* op_host, int dim) {
   double* op = c.arena.alloc((size_t)dim * dim + 1);
   CTM_HIP(hipMemcpyAsync(op, op_host, sizeof(double) * dim * dim, hipMemcpyHostToDevice, c.st));

@@ -133,24 +133,37 @@ struct Sizes {
 
 Sizes sizes_of(const ctm_config& cfg) {
   Sizes s{};
-  int DK = cfg.D, DB = (cfg.layers == 2) ? cfg.D : 1;
-  s.Db = (long)DK * DB;
+  const long DK = cfg.D, DB = (cfg.layers == 2) ? cfg.D : 1;
+  const long d = (cfg.layers == 2) ? cfg.d : 1;
+  s.Db = DK * DB;
   s.chi = cfg.chi;
   s.n = s.chi * s.Db;
   s.nn = s.n * s.n;
-  int p = cfg.rsvd_oversample;
+  const int p = cfg.rsvd_oversample;
   s.kk = (p < 0) ? s.n : std::min<long>(s.chi + p, s.n);
-  int d = (cfg.layers == 2) ? cfg.d : 1;
   s.y = s.nn * d;
-  long N = (long)cfg.Lx * cfg.Ly;
-  size_t b = 0;
-  b += 8 * (size_t)(4 * N * (s.chi * s.chi + 2 * s.chi * s.chi * s.Db));      // environment
-  b += 8 * (size_t)(4 * s.nn + s.nn + s.y + s.chi * s.n);                      // G, X2, Y, X1
-  b += 8 * (size_t)(8 * s.n * s.kk + 6 * s.kk * s.kk);                         // panels
-  b += 8 * (size_t)(3 * cfg.Ly * s.n * s.chi + cfg.Lx * s.n * s.chi);          // projectors
-  b += 8 * (size_t)(3 * std::max(cfg.Lx, cfg.Ly) * s.chi * s.chi * s.Db);      // staging
-  b += 4 * (size_t)(4 * s.chi * s.chi * DB * DB + 2 * s.chi * s.chi * DK * DK); // tables
-  b += 8 * (size_t)(8 * s.n * std::max(s.kk, s.chi));                         // split-K
+  const long N = (long)cfg.Lx * cfg.Ly, Lmax = std::max(cfg.Lx, cfg.Ly);
+  const long chi = s.chi, n = s.n, kk = s.kk, cc = chi * chi;
+  // doubles, in the order context_init allocates them
+  size_t e = 0;
+  e += 4 * N * (DK * DK * DK * DK * d + DB * DB * DB * DB * d);   // site tensors, 4 rotations
+  e += 4 * N * (cc + 2 * cc * s.Db);                               // C, T, transposed T
+  e += 4 * s.nn * Lmax + chi * n + s.nn + s.y;                      // corners, X1, X2, Y
+  e += 8 * n * kk * Lmax + 6 * kk * kk * Lmax;                      // panels, small matrices
+  e += std::max(kk, n) * Lmax + chi * Lmax;                         // singular values, weights
+  if (kk <= kSmallLAMaxK && p >= 0)                                 // Cholesky QR / Jacobi
+    e += 7 * kk * kk * Lmax + kk * Lmax + n * kk * Lmax + 64 + 128;
+  e += 3 * Lmax * n * chi + 2 * Lmax * cc + Lmax * cc * s.Db;       // projectors, new C / T
+  e += 2 * 4 * N * chi + 4 * N * cc;                                // spectra, corner scratch
+  e += 8 * n * std::max(kk, chi);                                   // split-K partials
+  e += 4096 + 2048 + 64;                                            // rho, reductions, flags
+  e += observe_arena_elems(chi, DK, DB, d);                         // expectation values
+  size_t b = 8 * e;
+  b += 4 * (size_t)(2 * cc * DB * DB + 2 * cc * DK * DK + 4 * DK * DK * d + 4 * DB * DB * d);  // tables
+  b += 8 * (size_t)(4096 + 4096 * 64) + 4 * 4096;                   // Householder fallback buffers
+  // per-context runtime overhead measured on MI355X (rocBLAS handle and its
+  // workspace, stream, allocation granularity of ~70 buffers): 170-190 MiB
+  b += (size_t)256 << 20;
   s.total_bytes = b;
   return s;
 }
@@ -166,7 +179,7 @@ double* Arena::alloc(size_t elems) {
   if (cur == chunks.size()) {
     DevBuf* b = new DevBuf();
     try {
-      b->alloc(std::max(elems, (size_t)32 << 20) * sizeof(double));
+      b->alloc(std::max(elems, chunks.empty() ? first_elems : ((size_t)1 << 20)) * sizeof(double));
     } catch (...) {
       delete b;
       throw;
@@ -305,6 +318,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
     default: c.ctype = GemmType::F64; break;
   }
   c.nact_cut.assign(Lmax, c.chi);
+  c.arena.first_elems = observe_arena_elems(c.chi, c.DK, c.DB, c.d);
   CTM_HIP(hipStreamSynchronize(c.st));
 }
 
@@ -708,7 +722,8 @@ static void corner_spectra(Context& c, double* out) {
   });
 }
 
-void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta, int* converged) {
+void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta, int* converged,
+               const std::atomic<bool>* cancel) {
   corner_spectra(c, c.specprev.as<double>());
   // normalise the reference spectra (delta of this call is discarded)
   spectra_delta(c.st, c.specprev.as<double>(), c.spec.as<double>(), 4 * c.N, c.chi, c.delta.as<double>());
@@ -716,6 +731,10 @@ void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta,
   double dl = INFINITY;
   int it = 0, conv = 0;
   for (it = 1; it <= max_sweeps; ++it) {
+    if (cancel && cancel->load()) {
+      --it;
+      break;
+    }
     for (int m = 0; m < 4; ++m) do_move(c, kSweepRot[m]);
     corner_spectra(c, c.spec.as<double>());
     spectra_delta(c.st, c.spec.as<double>(), c.specprev.as<double>(), 4 * c.N, c.chi, c.delta.as<double>());

@@ -1,0 +1,192 @@
+"""The serving queue (continuous batching of CTMRG solves on one GPU), through
+the C ABI: results alone and in a mix, closed forms through the queue, HBM
+budget admission, cancellation, and the footprint bound."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import observables as ob
+from oracle.ctmrg import Environment
+from paper_2112_13184_amd import _binding as B
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2112_13184_amd as p
+    p.load()
+    return p
+
+
+def _requests(n, seed=4, eps=0.1, chi_max=40, D_max=3):
+    reqs = []
+    for r in wl.serving_stream(n=n, seed=seed, eps=eps):
+        D = 2 + (r["D"] - 2) % (D_max - 1)
+        chi = 16 + (r["chi"] - 16) % (chi_max - 15)
+        A = wl.tfim_request_tensors(r["h"], D, r["Lx"], r["Ly"], eps, r["tensor_seed"])
+        reqs.append(dict(A=A, h=r["h"], D=D, chi=chi, Lx=r["Lx"], Ly=r["Ly"]))
+    return reqs
+
+
+def _submit(q, r, tag, max_sweeps=12):
+    return q.submit(r["A"], r["Lx"], r["Ly"], r["D"], r["chi"], wl.tfim_bond(r["h"]), tol=1e-10,
+                    max_sweeps=max_sweeps, tag=tag, rsvd_oversample=16, rsvd_power_iters=1, seed=3)
+
+
+def test_results_alone_equal_results_in_mix(lib):
+    """Every solve owns its context and stream, so running it alone (one at a
+    time) or among others gives the same numbers (bitwise, as the kernels are
+    deterministic); the stated tolerance 1e-10 is asserted, equality
+    reported."""
+    reqs = _requests(10)
+    alone = []
+    q1 = lib.Queue(64 << 30, 1)
+    for i, r in enumerate(reqs):
+        st, t = _submit(q1, r, i)
+        assert st == B.CTM_OK
+        st, res = q1.wait(t, 120000)
+        assert st == B.CTM_OK, st
+        alone.append((res.energy_per_site, res.sweeps, list(res.mz)))
+    q1.destroy()
+    q = lib.Queue(64 << 30, 6)
+    tickets = []
+    for i, r in enumerate(reqs):
+        st, t = _submit(q, r, i)
+        assert st == B.CTM_OK
+        tickets.append(t)
+    mixed = []
+    overlap = 0
+    spans = []
+    for i, t in enumerate(tickets):
+        st, res = q.wait(t, 120000)
+        assert st == B.CTM_OK, st
+        assert res.tag == i
+        mixed.append((res.energy_per_site, res.sweeps, list(res.mz)))
+        spans.append((res.t_admit_ns, res.t_done_ns))
+    q.destroy()
+    for (ea, sa, ma), (em, sm, mm) in zip(alone, mixed):
+        assert sa == sm
+        assert abs(ea - em) <= 1e-10
+        assert np.max(np.abs(np.array(ma) - np.array(mm))) <= 1e-10
+    # the mix really ran concurrently
+    for i in range(len(spans)):
+        for j in range(i + 1, len(spans)):
+            overlap += spans[i][0] < spans[j][1] and spans[j][0] < spans[i][1]
+    assert overlap > 0
+    print("bitwise equal:", all(a == m for a, m in zip(alone, mixed)), "overlapping pairs:", overlap)
+
+
+def test_mean_field_states_through_queue(lib):
+    """eps = 0: exact product states, energy = the TFIM mean-field closed form."""
+    q = lib.Queue(16 << 30, 4)
+    hs = [2.6, 3.0, 3.4]
+    tickets = []
+    for i, h in enumerate(hs):
+        A = wl.tfim_request_tensors(h, 3, 2, 2, 0.0, seed=i)
+        st, t = q.submit(A, 2, 2, 3, 20, wl.tfim_bond(h), tol=1e-12, max_sweeps=6, tag=i,
+                         rsvd_oversample=8, rsvd_power_iters=1, seed=1)
+        assert st == B.CTM_OK
+        tickets.append(t)
+    for h, t in zip(hs, tickets):
+        st, res = q.wait(t, 60000)
+        assert st == B.CTM_OK
+        _, e_mf = wl.tfim_mean_field(h)
+        assert abs(res.energy_per_site - e_mf) < 1e-12
+    q.destroy()
+
+
+def test_queue_matches_oracle(lib):
+    """One request through the queue against the oracle run with the same
+    sweeps (energy per site, 1e-10 or the run's sensitivity)."""
+    r = _requests(1, seed=9, chi_max=20, D_max=2)[0]
+    q = lib.Queue(16 << 30, 2)
+    st, t = q.submit(r["A"], r["Lx"], r["Ly"], r["D"], r["chi"], wl.tfim_bond(r["h"]), tol=0.0, max_sweeps=8,
+                     rsvd_oversample=16, rsvd_power_iters=1, seed=3)
+    assert st == B.CTM_OK
+    st, res = q.wait(t, 60000)
+    q.destroy()
+    assert st == B.CTM_OK and res.sweeps == 8
+    env = Environment(r["A"], r["Lx"], r["Ly"], chi=r["chi"], layers=2, mode="rsvd", oversample=16,
+                      power_iters=1, seed=3)
+    for _ in range(8):
+        env.sweep()
+    e = ob.energy_per_site(env, wl.tfim_bond(r["h"]))
+    assert abs(res.energy_per_site - e) < 1e-10
+
+
+def test_budget_admission_and_cancel(lib):
+    reqs = _requests(4, seed=5)
+    fp = [B.ctm_footprint_bytes(B.make_config(r["Lx"], r["Ly"], r["D"], r["chi"], rsvd_oversample=16))
+          for r in reqs]
+    # a budget that holds the largest request but not two of them
+    budget = max(fp) + min(fp) // 2
+    q = lib.Queue(budget, 4)
+    tickets = []
+    for i, r in enumerate(reqs):
+        st, t = _submit(q, r, i)
+        assert st == B.CTM_OK
+        tickets.append(t)
+    spans = []
+    for t in tickets:
+        st, res = q.wait(t, 120000)
+        assert st == B.CTM_OK
+        spans.append((res.t_admit_ns, res.t_done_ns))
+    # no two solves whose summed footprints exceed the budget ran together
+    for i in range(len(spans)):
+        for j in range(i + 1, len(spans)):
+            if fp[i] + fp[j] > budget:
+                assert not (spans[i][0] < spans[j][1] and spans[j][0] < spans[i][1]), (i, j)
+    # larger than the whole budget: rejected at once
+    A5 = wl.tfim_request_tensors(3.0, 5, 2, 2, 0.1, seed=6)
+    st, _ = q.submit(A5, 2, 2, 5, 200, wl.tfim_bond(3.0))
+    assert st == B.CTM_ETOOBIG
+    q.destroy()
+    # cancellation of pending requests behind a running one
+    q = lib.Queue(64 << 30, 1)
+    ts = [_submit(q, r, i, max_sweeps=30)[1] for i, r in enumerate(reqs)]
+    assert q.cancel(ts[-1]) == B.CTM_OK
+    st, res = q.wait(ts[-1], 60000)
+    assert st == B.CTM_ECANCELED
+    st, res = q.wait(ts[0], 120000)
+    assert st == B.CTM_OK
+    q.destroy()
+
+
+def _device_free_bytes():
+    """hipMemGetInfo from the HIP runtime the library itself uses."""
+    hip = ctypes.CDLL("/opt/rocm/lib/libamdhip64.so")
+    assert hip.hipDeviceSynchronize() == 0
+    free, total = ctypes.c_size_t(), ctypes.c_size_t()
+    assert hip.hipMemGetInfo(ctypes.byref(free), ctypes.byref(total)) == 0
+    return free.value
+
+
+@pytest.mark.parametrize("D,chi,L", [(2, 16, 1), (3, 40, 2), (5, 100, 2), (6, 144, 2)])
+def test_footprint_bounds_device_memory(lib, D, chi, L):
+    """ctm_footprint_bytes (the admission size) bounds the device memory a
+    context holds after sweeps and the energy evaluation."""
+    # one-time runtime set-up (code objects, library kernels) is not per context
+    warm = lib.Ctm(wl.random_itps(1, 1, 2, 2, seed=1), 1, 1, 2, 8, rsvd_oversample=8)
+    warm.ctm_move("left")
+    warm.ctm_expect_2site(0, 0, wl.heisenberg_bond())
+    warm.ctm_expect_1site(0, wl.SZ)
+    del warm
+    free0 = _device_free_bytes()
+    A = wl.random_itps(L, L, D, 2, seed=1)
+    ctx = lib.Ctm(A, L, L, D, chi, rsvd_oversample=16, rsvd_power_iters=1, seed=1)
+    for dname in ("left", "right", "up", "down"):
+        ctx.ctm_move(dname)
+    H = wl.heisenberg_bond()
+    for i in range(L * L):
+        ctx.ctm_expect_2site(i, 0, H)
+        ctx.ctm_expect_2site(i, 1, H)
+        ctx.ctm_expect_1site(i, wl.SZ)
+    free1 = _device_free_bytes()
+    used = free0 - free1
+    fp = B.ctm_footprint_bytes(B.make_config(L, L, D, chi, rsvd_oversample=16))
+    print(f"D={D} chi={chi} {L}x{L}: used {used / 2**20:.1f} MiB, footprint {fp / 2**20:.1f} MiB")
+    assert used <= fp
+    del ctx
