@@ -108,6 +108,63 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_per_launch": x.numel() * 8, "launches": 5}))
 
 
+def serving_requests(n, seed=4, rate_hz=None):
+    out = []
+    for r in wl.serving_stream(n=n, seed=seed, rate_hz=rate_hz, eps=0.1):
+        A = wl.tfim_request_tensors(r["h"], r["D"], r["Lx"], r["Ly"], 0.1, r["tensor_seed"])
+        out.append(dict(r, A=A, op=wl.tfim_bond(r["h"])))
+    return out
+
+
+def serving_bench(lib, n, max_active, budget_gb, p=16, q=1, tol=1e-10, max_sweeps=40):
+    """The mixed TFIM stream through the serving queue: a closed loop (all
+    requests at t = 0) gives the capacity; an open loop replays Poisson
+    arrivals at 0.8 x that capacity for p50 / p99 latency (arrival to done)."""
+    budget = int(budget_gb * (1 << 30))
+
+    def run(reqs, timed_arrivals):
+        qu = lib.Queue(budget, max_active)
+        tickets = []
+        t0 = time.perf_counter()
+        for r in reqs:
+            if timed_arrivals:
+                dt = r["arrival"] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            st, t = qu.submit(r["A"], r["Lx"], r["Ly"], r["D"], r["chi"], r["op"], tol=tol,
+                              max_sweeps=max_sweeps, tag=r["index"], rsvd_oversample=p, rsvd_power_iters=q,
+                              seed=3)
+            if st != 0:
+                raise RuntimeError(f"submit failed with status {st}")
+            tickets.append(t)
+        res = []
+        for i, t in enumerate(tickets):
+            st, r = qu.wait(t, -1)
+            if st != 0:
+                raise RuntimeError(f"request failed with status {st}")
+            res.append(r)
+            if (i + 1) % 8 == 0 or i + 1 == len(tickets):
+                print(f"serving ({'open' if timed_arrivals else 'closed'} loop): {i + 1}/{len(tickets)} done, "
+                      f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        qu.destroy()
+        first = min(r.t_submit_ns for r in res)
+        last = max(r.t_done_ns for r in res)
+        lat = np.array([(r.t_done_ns - r.t_submit_ns) * 1e-6 for r in res])
+        return dict(solves_per_s=len(res) / ((last - first) * 1e-9), p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), mean_sweeps=float(np.mean([r.sweeps for r in res])),
+                    converged=int(sum(r.converged for r in res)),
+                    energies=[float(r.energy_per_site) for r in res])
+
+    closed = run(serving_requests(n), False)
+    rate = 0.8 * closed["solves_per_s"]
+    opened = run(serving_requests(n, rate_hz=rate), True)
+    # the same request gives the same energy in both runs (own context each)
+    same = float(np.max(np.abs(np.array(closed.pop("energies")) - np.array(opened.pop("energies")))))
+    return {"requests": n, "max_active": max_active, "budget_gb": budget_gb, "rsvd_p": p, "rsvd_q": q,
+            "tol": tol, "max_sweeps": max_sweeps, "closed_loop": closed,
+            "open_loop": dict(opened, arrival_rate_hz=rate), "max_energy_diff_closed_vs_open": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +180,11 @@ def main():
                     help="skip the comparison runs in the other precisions")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies (counter calibration)")
+    ap.add_argument("--serving", type=int, default=0, metavar="N",
+                    help="also run the first N requests of the mixed TFIM serving stream (512 = all)")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
+    ap.add_argument("--max-active", type=int, default=8)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -137,6 +199,10 @@ def main():
         copy_calibration()
         return
     lib.load()
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(lib, args.serving or 512, args.max_active, args.budget_gb)}),
+              flush=True)
+        return
     D, chi, d, p, q = args.D, args.chi, 2, args.p, args.q
     A = wl.random_itps(2, 2, D, d, seed=2)
     dt, phases, energy, cuts = run_sweeps(lib, A, D, chi, d, p, q, args.prec, args.warmup, args.steps)
@@ -186,6 +252,8 @@ def main():
                          "energy_per_site": ep, "abs_energy_diff": abs(ep - energy),
                          "phases_ms_per_sweep": {k: v["ms"] / args.steps for k, v in php.items()}}
         out["precisions"] = cmp
+    if args.serving:
+        out["serving"] = serving_bench(lib, args.serving, args.max_active, args.budget_gb)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, p, q, seed=2)
     print(json.dumps(out), flush=True)

@@ -148,8 +148,11 @@ def tfim_request_tensors(h, D, Lx, Ly, eps, seed):
 
 def serving_stream(n=512, seed=4, rate_hz=None, eps=0.1):
     """The mixed TFIM request stream: h ~ U[2.5, 3.5], D ~ U{2..5}, chi ~ U{16..100},
-    cell ~ U{1x1, 2x2}, Poisson arrivals at rate_hz (None: all at t = 0)."""
+    cell ~ U{1x1, 2x2}, Poisson arrivals at rate_hz (None: all at t = 0).  The
+    arrival times come from a generator of their own, so the requests are the
+    same at every rate."""
     rng = np.random.default_rng(seed)
+    arrivals = np.random.default_rng(seed + 7919)
     reqs = []
     t = 0.0
     for i in range(n):
@@ -158,7 +161,7 @@ def serving_stream(n=512, seed=4, rate_hz=None, eps=0.1):
         chi = int(rng.integers(16, 101))
         L = 1 if rng.random() < 0.5 else 2
         if rate_hz:
-            t += float(rng.exponential(1.0 / rate_hz))
+            t += float(arrivals.exponential(1.0 / rate_hz))
         reqs.append(dict(index=i, h=h, D=D, chi=chi, Lx=L, Ly=L, arrival=t,
                          tensor_seed=seed * 100003 + i))
     return reqs
