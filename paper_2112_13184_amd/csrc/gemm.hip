@@ -37,6 +37,20 @@ struct KArgs {
 
 __device__ __forceinline__ long off0(const int* t, long s, int i) { return t ? (long)t[i] : (long)i * s; }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id; remap so
+// that each XCD runs one contiguous range of (tile, split, batch) indices.
+// Neighbouring output tiles share rows of A, which then stay in that XCD's L2.
+__device__ __forceinline__ void xcd_remap(int& tile, int& split, int& b) {
+  const unsigned nx = gridDim.x, ny = gridDim.y;
+  const unsigned total = nx * ny * gridDim.z;
+  const unsigned lin = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+  const unsigned q = total / 8, r = total % 8, x = lin % 8, i = lin / 8;
+  const unsigned id = (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+  tile = (int)(id % nx);
+  split = (int)((id / nx) % ny);
+  b = (int)(id / (nx * ny));
+}
+
 template <int BM, int BN, int WAVES_M, bool A_KC, bool B_KC>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
   constexpr int BK = 16;
@@ -51,8 +65,9 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles_n = (g.N + BN - 1) / BN;
-  const int tm_ = blockIdx.x / tiles_n, tn_ = blockIdx.x % tiles_n;
-  const int split = blockIdx.y, b = blockIdx.z;
+  int tile, split, b;
+  xcd_remap(tile, split, b);
+  const int tm_ = tile / tiles_n, tn_ = tile % tiles_n;
   const int m0 = tm_ * BM, n0 = tn_ * BN;
   const int kb = split * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
@@ -242,8 +257,9 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tiles_n = (g.N + BN - 1) / BN;
-  const int tm_ = blockIdx.x / tiles_n, tn_ = blockIdx.x % tiles_n;
-  const int split = blockIdx.y, b = blockIdx.z;
+  int tile, split, b;
+  xcd_remap(tile, split, b);
+  const int tm_ = tile / tiles_n, tn_ = tile % tiles_n;
   const int m0 = tm_ * BM, n0 = tn_ * BN;
   const int kb = split * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
@@ -465,6 +481,31 @@ void launch_typed(hipStream_t st, GemmType type, const KArgs& g, bool a_kc, bool
   }
 }
 
+// Few outputs, long K (the closing contractions of expectation values): each
+// workgroup sums a K-chunk of every output (<= 16 of them) and writes partials
+// [chunk][batch][M][N]; splitk_reduce adds them in chunk order.
+__global__ __launch_bounds__(256) void k_gemm_dot(KArgs g) {
+  __shared__ double red[4][16];
+  const int chunk = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double* A = g.A + (long)b * g.bsa;
+  const double* B = g.B + (long)b * g.bsb;
+  const int k0 = chunk * g.kchunk, k1 = min(g.K, k0 + g.kchunk);
+  const int mn = g.M * g.N;
+  for (int o = 0; o < mn; ++o) {
+    const int m = o / g.N, n = o % g.N;
+    const long ao = off0(g.ta0, g.sa0, m), bo = off0(g.tb1, g.sb1, n);
+    double acc = 0.0;
+    for (int k = k0 + tid; k < k1; k += 256) acc += A[ao + off0(g.ta1, g.sa1, k)] * B[bo + off0(g.tb0, g.sb0, k)];
+    for (int sft = 32; sft > 0; sft >>= 1) acc += __shfl_xor(acc, sft);
+    if (lane == 0) red[w][o] = acc;
+  }
+  __syncthreads();
+  if (tid < mn) {
+    const double v = g.alpha * (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]);
+    g.ws[(((long)chunk * g.batch + b) * g.M + tid / g.N) * g.N + tid % g.N] = v;
+  }
+}
+
 // Choose the split of K so that a small output grid still fills the GPU.
 int choose_splits(long tiles, int K) {
   const long target = 1024;   // ~4 workgroups per CU on 256 CUs
@@ -486,6 +527,7 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   if (M <= 0 || N <= 0 || batch <= 0) return;
   CTM_CHECK(type != GemmType::F16 || ws.amax != nullptr, -1, "gemm: split FP16 needs a scaling workspace");
   KArgs g{};
+  const bool dot = (long)M * N <= 16 && K >= 8192;
   g.A = static_cast<const double*>(A.p);
   g.B = static_cast<const double*>(B.p);
   g.C = static_cast<double*>(C.p);
@@ -506,6 +548,19 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   int splits = (K > 0) ? choose_splits(tiles, K) : 1;
   if (splits > 1 && (ws.p == nullptr || ws.elems < (size_t)splits * batch * M * N)) splits = 1;
   int kchunk = (K > 0) ? ((ceil_div(K, splits) + 15) / 16) * 16 : 16;
+  if (dot) {   // FP64 dot products regardless of type: negligible work, K-chunks of 4096
+    const int chunks = std::min(ceil_div(K, 4096), (int)std::min<size_t>(1024, ws.elems / ((size_t)batch * M * N)));
+    CTM_CHECK(chunks >= 1, -1, "gemm: workspace too small for the dot-product path");
+    g.kchunk = ceil_div(K, chunks);
+    g.splits = ceil_div(K, g.kchunk);
+    g.ws = ws.p;
+    hipLaunchKernelGGL(k_gemm_dot, dim3(g.splits, batch), dim3(256), 0, st, g);
+    CTM_HIP(hipGetLastError());
+    long total = (long)batch * M * N;
+    hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, g);
+    CTM_HIP(hipGetLastError());
+    return;
+  }
   if (type != GemmType::F64) kchunk = ((kchunk + 31) / 32) * 32;   // whole 32-wide K steps
   splits = (K > 0) ? ceil_div(K, kchunk) : 1;
   g.splits = splits; g.kchunk = kchunk; g.ws = ws.p; g.amax = ws.amax;

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <vector>
 
+#include "absorb.hpp"
 #include "context.hpp"
 #include "kernels.hpp"
 #include "smallla.hpp"
@@ -342,6 +343,11 @@ static void mm(Context& c, int phase, int M, int N, int K, const Operand& A, con
 static void absorb(Context& c, const double* X, const double* Ak, const double* Ab, double* out,
                    bool transposed) {
   const int chi = c.chi, DK = c.DK, DB = c.DB, d = c.d;
+  if (c.ctype == GemmType::F64 && absorb_fused_fits(DK, DB, d)) {
+    const double flops = 2.0 * chi * chi * (double)DB * DB * DK * DK * d * (DK * DK + DB * DB);
+    timed(c, PhaseTimer::ABSORB, flops, [&] { absorb_fused(c.st, X, Ak, Ab, out, chi, DK, DB, d, transposed); });
+    return;
+  }
   Operand A{};
   A.p = X; A.t0 = c.ketA_r.as<int>(); A.t1 = c.ketA_c.as<int>();
   Operand B = rowmajor(Ak, (long)DK * DK * d);
