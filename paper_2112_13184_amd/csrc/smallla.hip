@@ -302,7 +302,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_round(double* A, double* J, int
 
 // Column norms -> singular values, sorted descending; X = A S^-1, Y = J.
 __global__ __launch_bounds__(256) void k_svd_finalize(const double* A, const double* J, int k, double* X,
-                                                       double* S, double* Y) {
+                                                       double* S, long sstride, double* Y) {
   __shared__ double sig[kSmallLAMaxK];
   __shared__ int pos[kSmallLAMaxK];
   const int b = blockIdx.x;
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_svd_finalize(const double* A, const dou
     X[b * kk2 + (long)p * k + r] = (sc > 0.0) ? Ab[e] / sc : 0.0;
     Y[b * kk2 + (long)p * k + r] = J[b * kk2 + e];
   }
-  for (int c = threadIdx.x; c < k; c += blockDim.x) S[(long)b * k + pos[c]] = sig[c];
+  for (int c = threadIdx.x; c < k; c += blockDim.x) S[(long)b * sstride + pos[c]] = sig[c];
 }
 
 
@@ -400,7 +400,8 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
   }
 }
 
-void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, double* Y) {
+void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, long sstride,
+                double* Y) {
   CTM_CHECK(k <= kSmallLAMaxK && batch <= s.batch_max, -1, "jacobi_svd: size");
   int bs = jacobi_block(k);
   int nb = (k + bs - 1) / bs;
@@ -420,7 +421,7 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
     hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, batch, tol);
   }
   CTM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, Y);
+  hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, sstride, Y);
   CTM_HIP(hipGetLastError());
 }
 

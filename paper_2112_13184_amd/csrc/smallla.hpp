@@ -36,7 +36,8 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
 
 // SVD of `batch` k x k column-major matrices A_b = X_b diag(S_b) Y_b^T by
 // block one-sided Jacobi (A is overwritten).  S_b descending; X, Y k x k
-// col-major, batch strides k*k; S stride k.
-void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, double* Y);
+// col-major, batch strides k*k; S_b = S + b * sstride (sstride >= k).
+void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, long sstride,
+                double* Y);
 
 }  // namespace ctm
