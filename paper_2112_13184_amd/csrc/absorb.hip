@@ -26,8 +26,12 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMaxBlock = 2592;   // D^4 d for D = 6, d = 2 (and every smaller case)
 constexpr int kWaves = 4;
+// LDS leading dimensions are = 16 (mod 32) doubles, so that the two halves of
+// a wave (k-slots 0,1 and 2,3 of a fragment read) fall on disjoint banks.
+constexpr int kAkElems = 36 * 80;   // [(l,u)][(r,dd,p)], D = 6, d = 2
+constexpr int kAbElems = 72 * 48;   // [(l',u',p)][(r',d')]
+constexpr int kYElems = 72 * 48;    // per wave: [(l',u',p)][(r,dd)]
 
 struct AbsorbArgs {
   const double* X;
@@ -40,28 +44,29 @@ struct AbsorbArgs {
   int transposed;
 };
 
-__device__ __forceinline__ int pad16(int x) { return (x + 15) & ~15; }
+__host__ __device__ __forceinline__ int padld(int x) { return x + ((16 - x % 32) + 32) % 32; }
 
 // tile counts for the largest supported block (D = 6, d = 2): stage one
 // 48 x 80 outputs over K = 36, stage two 48 x 48 over K = 72
 constexpr int MT1 = 3, NT1 = 5, KS1 = 9, MT2 = 3, NT2 = 3, KS2 = 18;
 
 __global__ __launch_bounds__(64 * kWaves) void k_absorb_fused(AbsorbArgs a) {
-  __shared__ double sAk[kMaxBlock];          // [(l,u)][(r,dd,p)]
-  __shared__ double sAb[kMaxBlock];          // [(l',u',p)][(r',d')]
-  __shared__ double sY[kWaves][kMaxBlock];   // per wave: [(r,dd)][(l',u',p)]
+  __shared__ double sAk[kAkElems];
+  __shared__ double sAb[kAbElems];
+  __shared__ double sY[kWaves][kYElems];
   const int DK = a.DK, DB = a.DB, d = a.d;
   const int Db = DK * DB;
   const int P = DB * DB;          // stage-one rows (l', u')
   const int Q = DK * DK;          // stage-one K (l, u), stage-two rows (r, dd)
   const int R1 = Q * d;           // stage-one columns (r, dd, p)
   const int K2 = P * d;           // stage-two K (l', u', p)
+  const int ldk = padld(R1), ldb = padld(P), ldy = padld(Q);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  for (int e = tid; e < Q * R1; e += blockDim.x) sAk[e] = a.Ak[e];
+  for (int e = tid; e < Q * R1; e += blockDim.x) sAk[(e / R1) * ldk + e % R1] = a.Ak[e];
   for (int e = tid; e < K2 * P; e += blockDim.x) {
     const int k = e / P, c = e % P;                    // k = (l', u', p), c = (r', d')
     const int lu = k / d, p = k % d;
-    sAb[e] = a.Ab[((long)lu * P + c) * d + p];          // Ab[l'][u'][r'][d'][p]
+    sAb[k * ldb + c] = a.Ab[((long)lu * P + c) * d + p];   // Ab[l'][u'][r'][d'][p]
   }
   __syncthreads();
   double* Ys = sY[w];
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_absorb_fused(AbsorbArgs a) {
 #pragma unroll
         for (int nt = 0; nt < NT1; ++nt) {
           const int col = nt * 16 + r16;
-          bv[nt] = (kok && col < R1) ? sAk[k * R1 + col] : 0.0;
+          bv[nt] = (kok && col < R1) ? sAk[k * ldk + col] : 0.0;
         }
 #pragma unroll
         for (int mt = 0; mt < MT1; ++mt)
@@ -107,7 +112,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_absorb_fused(AbsorbArgs a) {
           for (int nt = 0; nt < NT1; ++nt)
             acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
       }
-      // D[i][col], i = kg + 4 r  ->  Ys[(r,dd)][(l',u',p)]
+      // D[i][col], i = kg + 4 r  ->  Ys[(l',u',p)][(r,dd)]
 #pragma unroll
       for (int nt = 0; nt < NT1; ++nt) {
         const int col = nt * 16 + r16;
@@ -118,7 +123,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_absorb_fused(AbsorbArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int i = mt * 16 + kg + 4 * r;
-              if (i < P) Ys[rd * K2 + i * d + p] = acc[mt][nt][r];
+              if (i < P) Ys[(i * d + p) * ldy + rd] = acc[mt][nt][r];
             }
         }
       }
@@ -140,12 +145,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_absorb_fused(AbsorbArgs a) {
 #pragma unroll
         for (int mt = 0; mt < MT2; ++mt) {
           const int row = mt * 16 + r16;                // (r, dd)
-          av[mt] = (kok && row < Q) ? Ys[row * K2 + k] : 0.0;
+          av[mt] = (kok && row < Q) ? Ys[k * ldy + row] : 0.0;
         }
 #pragma unroll
         for (int nt = 0; nt < NT2; ++nt) {
           const int col = nt * 16 + r16;                // (r', d')
-          bv[nt] = (kok && col < P) ? sAb[k * P + col] : 0.0;
+          bv[nt] = (kok && col < P) ? sAb[k * ldb + col] : 0.0;
         }
 #pragma unroll
         for (int mt = 0; mt < MT2; ++mt)
@@ -179,9 +184,10 @@ __global__ __launch_bounds__(64 * kWaves) void k_absorb_fused(AbsorbArgs a) {
 }  // namespace
 
 bool absorb_fused_fits(int DK, int DB, int d) {
-  const long P = (long)DB * DB, Q = (long)DK * DK;
-  return DB > 1 && Q * Q * d <= kMaxBlock && P * P * d <= kMaxBlock && Q * P * d <= kMaxBlock &&
-         P <= 16 * MT1 && Q * d <= 16 * NT1 && Q <= 4 * KS1 && Q <= 16 * MT2 && P <= 16 * NT2 && P * d <= 4 * KS2;
+  const int P = DB * DB, Q = DK * DK;
+  return DB > 1 && (long)Q * padld(Q * d) <= kAkElems && (long)P * d * padld(P) <= kAbElems &&
+         (long)P * d * padld(Q) <= kYElems && P <= 16 * MT1 && Q * d <= 16 * NT1 && Q <= 4 * KS1 &&
+         Q <= 16 * MT2 && P <= 16 * NT2 && P * d <= 4 * KS2;
 }
 
 void absorb_fused(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G, int chi,

@@ -139,22 +139,20 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
     if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
-    double af[TM][4], bf[TN][4];
+    // fragments loaded per k-slot, next to their MFMAs (fewer live registers)
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int s = 0; s < 4; ++s) {
+      double af[TM], bf[TN];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) af[i][s] = As[cur][(wm0 + i * 16 + r16) * LDK + 4 * kg + s];
+      for (int i = 0; i < TM; ++i) af[i] = As[cur][(wm0 + i * 16 + r16) * LDK + 4 * kg + s];
 #pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) bf[j][s] = Bs[cur][(wn0 + j * 16 + r16) * LDK + 4 * kg + s];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
+      for (int j = 0; j < TN; ++j) bf[j] = Bs[cur][(wn0 + j * 16 + r16) * LDK + 4 * kg + s];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
     if (it + 1 < nk) store_tile(cur ^ 1);
     __syncthreads();
   }

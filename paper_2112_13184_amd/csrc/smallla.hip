@@ -151,8 +151,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
 }
 
-// Rinv = R^-1 for R = L^T upper triangular; one wave per column c.
+// Rinv = R^-1 for R = L^T upper triangular; one wave per column c.  Column
+// c of R^-1 is found by back substitution from row c up; row i needs column
+// i of L below the diagonal, which does not depend on the solution, so the
+// columns for the next 8 rows are kept in flight in a register ring.
 __global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* Rinv) {
+  constexpr int RING = 8;
   const int b = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -160,19 +164,34 @@ __global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* R
   const long kk2 = (long)k * k;
   const double* Lb = L + b * kk2;
   double x[3] = {0.0, 0.0, 0.0};     // x[q] = column entry lane + 64 q
-  for (int i = c; i >= 0; --i) {
-    double part = 0.0;
+  double ring[RING][3];
+  auto fetch = [&](int i, double* dst) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int kx = lane + 64 * q;
-      if (kx > i && kx <= c) part += Lb[kx + (long)i * k] * x[q];   // R[i][kx] = L[kx][i]
+      dst[q] = (i >= 0 && kx > i && kx <= c) ? Lb[kx + (long)i * k] : 0.0;   // R[i][kx] = L[kx][i]
     }
-    const double sum = wave_sum(part);
-    if ((i & 63) == lane) {
-      const double v = (((i == c) ? 1.0 : 0.0) - sum) / Lb[i + (long)i * k];
+  };
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        if ((i >> 6) == q) x[q] = v;
+  for (int s = 0; s < RING; ++s) fetch(c - s, ring[s]);
+  for (int base = c; base >= 0; base -= RING) {
+#pragma unroll
+    for (int s = 0; s < RING; ++s) {
+      const int i = base - s;
+      if (i < 0) break;
+      double lc[3] = {ring[s][0], ring[s][1], ring[s][2]};
+      fetch(i - RING, ring[s]);
+      const double dii = Lb[i + (long)i * k];
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) part += lc[q] * x[q];
+      const double sum = wave_sum(part);
+      if ((i & 63) == lane) {
+        const double v = (((i == c) ? 1.0 : 0.0) - sum) / dii;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if ((i >> 6) == q) x[q] = v;
+      }
     }
   }
   double* out = Rinv + b * kk2 + (long)c * k;
