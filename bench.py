@@ -14,8 +14,10 @@ workload (one left move on a random full-dimension environment) and scales
 it to sweeps per second.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,6 +29,21 @@ import numpy as np  # noqa: E402
 import workloads as wl  # noqa: E402
 
 PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "f16split": 2.5e15}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sketch_gemm_d6_chi144_traffic.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2112_13184_amd", "csrc", "gemm.hip")
+
+
+def counted_traffic():
+    """HBM bytes per sketch-GEMM launch (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy of known size) from the committed counter summary, or None when
+    the summary is missing or was taken on another version of the GEMM source."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        src = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    except (OSError, AttributeError, ValueError):
+        return None
+    return rec["hbm_bytes_per_launch"] if rec.get("gemm_source_sha256") == src else None
 METRIC = "CTMRG sweeps/s + MFMA util at D=6 chi=144; solves/s and p99 latency"
 
 
@@ -180,7 +197,7 @@ def main():
                     help="skip the comparison runs in the other precisions")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies (counter calibration)")
-    ap.add_argument("--serving", type=int, default=0, metavar="N",
+    ap.add_argument("--serving", type=int, default=32, metavar="N",
                     help="also run the first N requests of the mixed TFIM serving stream (512 = all)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
     ap.add_argument("--max-active", type=int, default=8)
@@ -206,6 +223,7 @@ def main():
     D, chi, d, p, q = args.D, args.chi, 2, args.p, args.q
     A = wl.random_itps(2, 2, D, d, seed=2)
     dt, phases, energy, cuts = run_sweeps(lib, A, D, chi, d, p, q, args.prec, args.warmup, args.steps)
+    n, k = chi * D * D, min(chi + p, chi * D * D)   # one launch: 2 cuts, corner n x n, panel n x k
     sweeps_per_s = args.steps / dt
     sk = phases["sketch_gemm"]
     achieved = sketch_rate(phases)
@@ -226,8 +244,10 @@ def main():
         "config": {"workload": f"itps_2x2_d2_D{D}_chi{chi}", "Lx": 2, "Ly": 2, "d": d, "D": D,
                    "chi": chi, "rsvd_p": p, "rsvd_q": q, "precision": args.prec, "tensor_seed": 2},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK[args.prec] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK[args.prec],
+                     "traffic": counted_traffic() if args.prec == "f64" else None,
                      "kernel": "sketch GEMMs (n x k panel times n x n corner)",
+                     "alg_bytes_per_launch": 8.0 * 2 * (n * n + 2 * n * k),
                      "launches": sk["launches"], "avg_launch_ms": sk["ms"] / max(sk["launches"], 1),
                      "flops_per_launch": sk["flops"] / max(sk["launches"], 1)},
         "whole_sweep": {"alg_tflop": alg / 1e12, "achieved_tflops": alg * sweeps_per_s / 1e12,

@@ -169,14 +169,16 @@ ctm_status ctm_cut_stats(const ctm_ctx* ctx, int64_t counts[3]);
 
 /* Per-phase GPU timing with HIP events recorded on the context's stream
  * around every launch of a phase, while enabled.  Phases:
- *   0 edge GEMMs      (n x n x chi: enlarged-corner step 2, edge renormalisation)
- *   1 sketch GEMMs    (products with an n x n enlarged corner or absorbed edge)
+ *   0 other contraction GEMMs (edge-corner products, projector formation
+ *                     P~ = G G V', the edge renormalisation, dense-mode M)
+ *   1 sketch GEMMs    (the randomized SVD's products of an n x n enlarged
+ *                     corner with an n x k panel: (10 + 8q) per cut)
  *   2 absorption      (single-layer ket and bra contractions of the site)
  *   3 factorisations  (QR, SVD and projector scaling, FP64)
  *   4 other           (small GEMMs, normalisation, permutations, spectra)
  * flops counts the algorithmic floating-point operations of the launches
- * (2 M N K per GEMM; 0 for phases 3 and 4).  ctm_timing_read() synchronises
- * the stream. */
+ * (2 M N K per GEMM, 4 chi^2 D^6 d per absorption; 0 for phases 3 and 4).
+ * ctm_timing_read() synchronises the stream. */
 #define CTM_NPHASE 5
 typedef struct {
   int64_t launches[CTM_NPHASE];

@@ -53,7 +53,7 @@ class ctm_request(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int), ("tag", ctypes.c_uint64)]
 
 
-PHASES = ("edge_gemm", "sketch_gemm", "absorb", "factorise", "other")
+PHASES = ("contract_gemm", "sketch_gemm", "absorb", "factorise", "other")
 
 
 class ctm_timing(ctypes.Structure):

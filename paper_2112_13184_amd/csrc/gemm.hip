@@ -64,10 +64,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
   __shared__ double Bs[2][BN * LDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tiles_n = (g.N + BN - 1) / BN;
+  const int tiles_n = (g.N + BN - 1) / BN, tiles_m = (g.M + BM - 1) / BM;
   int tile, split, b;
   xcd_remap(tile, split, b);
-  const int tm_ = tile / tiles_n, tn_ = tile % tiles_n;
+  // consecutive tiles share the larger operand's block (A rows or B columns)
+  const bool mfast = g.N > g.M;
+  const int tm_ = mfast ? tile % tiles_m : tile / tiles_n;
+  const int tn_ = mfast ? tile / tiles_m : tile % tiles_n;
   const int m0 = tm_ * BM, n0 = tn_ * BN;
   const int kb = split * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
@@ -254,10 +257,13 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tiles_n = (g.N + BN - 1) / BN;
+  const int tiles_n = (g.N + BN - 1) / BN, tiles_m = (g.M + BM - 1) / BM;
   int tile, split, b;
   xcd_remap(tile, split, b);
-  const int tm_ = tile / tiles_n, tn_ = tile % tiles_n;
+  // consecutive tiles share the larger operand's block (A rows or B columns)
+  const bool mfast = g.N > g.M;
+  const int tm_ = mfast ? tile % tiles_m : tile / tiles_n;
+  const int tn_ = mfast ? tile / tiles_m : tile % tiles_n;
   const int m0 = tm_ * BM, n0 = tn_ * BN;
   const int kb = split * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
@@ -523,6 +529,18 @@ size_t gemm_workspace_elems(int M, int N, int K, int batch) {
 void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, const Operand& A,
           const Operand& B, double beta, const OutOperand& C, int batch, const GemmWorkspace& ws) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
+  // The kernels write 16 consecutive columns per row fragment; a column-major C
+  // is produced as C^T = B^T A^T so that those writes are contiguous.
+  if (C.t0 == nullptr && C.t1 == nullptr && C.s0 == 1 && C.s1 != 1 && (long)M * N > 16) {
+    Operand At, Bt;
+    At.p = B.p; At.s0 = B.s1; At.s1 = B.s0; At.t0 = B.t1; At.t1 = B.t0; At.bs = B.bs;
+    Bt.p = A.p; Bt.s0 = A.s1; Bt.s1 = A.s0; Bt.t0 = A.t1; Bt.t1 = A.t0; Bt.bs = A.bs;
+    OutOperand Ct = C;
+    Ct.s0 = C.s1;
+    Ct.s1 = C.s0;
+    gemm(st, type, N, M, K, alpha, At, Bt, beta, Ct, batch, ws);
+    return;
+  }
   CTM_CHECK(type != GemmType::F16 || ws.amax != nullptr, -1, "gemm: split FP16 needs a scaling workspace");
   KArgs g{};
   const bool dot = (long)M * N <= 16 && K >= 8192;

@@ -443,9 +443,9 @@ void cut_projectors(Context& c, int rot, int x, int y, int slot) {
     double* Hu = c.X2.as<double>();
     double* HdT = c.Ybuf.as<double>();
     double* M = G[0];   // the corners are not needed once H_u and H_d^T exist
-    mm(c, PhaseTimer::SKETCH, n, n, n, rowmajor(G[1], n), rowmajor(G[0], n), out_rowmajor(Hu, n));
-    mm(c, PhaseTimer::SKETCH, n, n, n, rowmajor(G[3], n), rowmajor(G[2], n), out_rowmajor(HdT, n));
-    mm(c, PhaseTimer::SKETCH, n, n, n, rowmajor(Hu, n), rowmajor(HdT, n), out_colmajor(M, n));
+    mm(c, PhaseTimer::EDGE, n, n, n, rowmajor(G[1], n), rowmajor(G[0], n), out_rowmajor(Hu, n));
+    mm(c, PhaseTimer::EDGE, n, n, n, rowmajor(G[3], n), rowmajor(G[2], n), out_rowmajor(HdT, n));
+    mm(c, PhaseTimer::EDGE, n, n, n, rowmajor(Hu, n), rowmajor(HdT, n), out_colmajor(M, n));
     // M column-major: M = U S V^T directly
     double* U = P[0];
     double* VT = P[1];
@@ -457,8 +457,8 @@ void cut_projectors(Context& c, int rot, int x, int y, int slot) {
     scale_columns(c.st, V, n, chi, w);
     scale_columns(c.st, U, n, chi, w);
     // Pt = H_d^T V' ; PT = H_u^T U'
-    mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(HdT, n), colmajor(V, n), out_rowmajor(Pt, chi));
-    mm(c, PhaseTimer::SKETCH, n, chi, n, colmajor(Hu, n), colmajor(U, n), out_rowmajor(PT, chi));
+    mm(c, PhaseTimer::EDGE, n, chi, n, rowmajor(HdT, n), colmajor(V, n), out_rowmajor(Pt, chi));
+    mm(c, PhaseTimer::EDGE, n, chi, n, colmajor(Hu, n), colmajor(U, n), out_rowmajor(PT, chi));
     return;
   }
 
@@ -487,8 +487,8 @@ void cut_projectors(Context& c, int rot, int x, int y, int slot) {
   timed(c, PhaseTimer::LINALG, 0.0, [&] { projector_weights(c.st, S, U, n, kk, chi, kcap, c.cutoff, w, c.keff.as<int>(), c.badflag.as<int>()); });
   scale_columns(c.st, V, n, chi, w);
   // Pt = G_ll (G_lr V')
-  mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(G[2], n), colmajor(V, n), out_colmajor(t1, n));
-  mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(G[3], n), colmajor(t1, n), out_rowmajor(Pt, chi));
+  mm(c, PhaseTimer::EDGE, n, chi, n, rowmajor(G[2], n), colmajor(V, n), out_colmajor(t1, n));
+  mm(c, PhaseTimer::EDGE, n, chi, n, rowmajor(G[3], n), colmajor(t1, n), out_rowmajor(Pt, chi));
   // PT = W Ub' with Ub'(:, i) = Ub(:, i) w_i: scale the rows of VTs first
   // (row i of VTs is column i of Ub)
   transpose_square(c.st, VTs, Us, kk);             // Us <- Ub (col-major)
@@ -579,8 +579,8 @@ static void rsvd_batched(Context& c, int rot, int x, int y0, int s0, int nb, std
   // Pt = G_ll (G_lr V'), PT = W Ub'
   double* Pt = c.Pt.as<double>() + s0 * nc;
   double* PT = c.PT.as<double>() + s0 * nc;
-  mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(Gp(2, s0), n, nn), colmajor(V, n, pk), out_colmajor(t1, n, pk), nb);
-  mm(c, PhaseTimer::SKETCH, n, chi, n, rowmajor(Gp(3, s0), n, nn), colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nb);
+  mm(c, PhaseTimer::EDGE, n, chi, n, rowmajor(Gp(2, s0), n, nn), colmajor(V, n, pk), out_colmajor(t1, n, pk), nb);
+  mm(c, PhaseTimer::EDGE, n, chi, n, rowmajor(Gp(3, s0), n, nn), colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nb);
   mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n, pk), colmajor(Ysv, kk, k2), out_rowmajor(PT, chi, nc), nb);
   // cuts whose Cholesky QR broke down
   int flags[192] = {0};
@@ -692,7 +692,7 @@ void do_move(Context& c, int rot) {
       // T4' = Pt_dn^T absorb(T4 P3_up)
       mm(c, PhaseTimer::EDGE, n, n, chi, rowmajor(c.Tb(s, kt4), chi), rowmajor(P3_up, n), out_rowmajor(c.X2.p, n));
       absorb(c, c.X2.as<double>(), c.Ak(rot, s), c.Ab(rot, s), c.G[0].as<double>(), true);
-      mm(c, PhaseTimer::SKETCH, chi, n, n, colmajor(Pt_dn, chi), rowmajor(c.G[0].p, n), out_rowmajor(T4n, n));
+      mm(c, PhaseTimer::EDGE, chi, n, n, colmajor(Pt_dn, chi), rowmajor(c.G[0].p, n), out_rowmajor(T4n, n));
       normalize_maxabs(c.st, C1n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
       normalize_maxabs(c.st, C4n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
       normalize_maxabs(c.st, T4n, tt, c.redscratch.as<double>(), c.badflag.as<int>());
