@@ -120,6 +120,7 @@ struct Context {
   DevBuf gws;                // GEMM split-K workspace
   size_t gws_elems = 0;
   DevBuf amax;               // split-FP16 operand scaling (2 words)
+  DevBuf camax;              // split FP16: largest |entry| of each corner role over a column's cuts
   GemmType ctype = GemmType::F64;   // arithmetic of the contraction GEMMs
   Arena arena;
   std::vector<int> nact_cut; // per cut of the current column: bond dim after the move

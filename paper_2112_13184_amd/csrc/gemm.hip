@@ -32,7 +32,8 @@ struct KArgs {
   int splits, kchunk;   // split-K: each split covers kchunk of K (multiple of BK)
   double* ws;           // partials [split][batch][M][N] when splits > 1
   int batch;
-  const unsigned* amax; // F16 split: largest |A|, |B| as FP32 bits
+  const unsigned* amaxA;   // F16 split: largest |A| and |B| as FP32 bits
+  const unsigned* amaxB;
 };
 
 __device__ __forceinline__ long off0(const int* t, long s, int i) { return t ? (long)t[i] : (long)i * s; }
@@ -271,8 +272,8 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   const double* B = g.B + (long)b * g.bsb;
   double sa = 1.0, sb = 1.0;
   if (KIND == LP_F16) {
-    sa = f16_scale(g.amax[0]);
-    sb = f16_scale(g.amax[1]);
+    sa = f16_scale(*g.amaxA);
+    sb = f16_scale(*g.amaxB);
   }
 
   int a_r[EA], a_k[EA];
@@ -437,8 +438,8 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
       }
 }
 
-__global__ void k_amax_clear(unsigned* out) {
-  if (threadIdx.x < 2) out[threadIdx.x] = 0u;
+__global__ void k_amax_clear(unsigned* out, int n) {
+  if ((int)threadIdx.x < n) out[threadIdx.x] = 0u;
 }
 
 // out[which] = max(out[which], largest |x| over an R x Cn operand (FP32 bits;
@@ -447,10 +448,13 @@ __global__ void k_operand_amax(const double* P, long s0, long s1, const int* t0,
                                int Cn, int batch, unsigned* out, int which) {
   __shared__ float red[4];
   const long per = (long)R * Cn, total = per * batch;
+  // walk the unit-stride index fastest so that the scan is coalesced
+  const bool rows_fast = (t0 == nullptr && s0 == 1);
   float m = 0.0f;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const long bb = e / per, rem = e % per;
-    const int i = (int)(rem / Cn), j = (int)(rem % Cn);
+    const int i = rows_fast ? (int)(rem % R) : (int)(rem / Cn);
+    const int j = rows_fast ? (int)(rem / R) : (int)(rem % Cn);
     m = fmaxf(m, fabsf((float)P[bb * bs + off0(t0, s0, i) + off0(t1, s1, j)]));
   }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
@@ -520,6 +524,13 @@ int choose_splits(long tiles, int K) {
 
 }  // namespace
 
+void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, unsigned* out) {
+  hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, out, 1);
+  hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, static_cast<const double*>(P.p), P.s0, P.s1, P.t0,
+                     P.t1, P.bs, R, C, batch, out, 0);
+  CTM_HIP(hipGetLastError());
+}
+
 size_t gemm_workspace_elems(int M, int N, int K, int batch) {
   long tiles = (long)ceil_div(M, 64) * ceil_div(N, 64) * batch;
   int s = choose_splits(tiles, K);
@@ -533,8 +544,8 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   // is produced as C^T = B^T A^T so that those writes are contiguous.
   if (C.t0 == nullptr && C.t1 == nullptr && C.s0 == 1 && C.s1 != 1 && (long)M * N > 16) {
     Operand At, Bt;
-    At.p = B.p; At.s0 = B.s1; At.s1 = B.s0; At.t0 = B.t1; At.t1 = B.t0; At.bs = B.bs;
-    Bt.p = A.p; Bt.s0 = A.s1; Bt.s1 = A.s0; Bt.t0 = A.t1; Bt.t1 = A.t0; Bt.bs = A.bs;
+    At.p = B.p; At.s0 = B.s1; At.s1 = B.s0; At.t0 = B.t1; At.t1 = B.t0; At.bs = B.bs; At.amax = B.amax;
+    Bt.p = A.p; Bt.s0 = A.s1; Bt.s1 = A.s0; Bt.t0 = A.t1; Bt.t1 = A.t0; Bt.bs = A.bs; Bt.amax = A.amax;
     OutOperand Ct = C;
     Ct.s0 = C.s1;
     Ct.s1 = C.s0;
@@ -579,14 +590,19 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   }
   if (type != GemmType::F64) kchunk = ((kchunk + 31) / 32) * 32;   // whole 32-wide K steps
   splits = (K > 0) ? ceil_div(K, kchunk) : 1;
-  g.splits = splits; g.kchunk = kchunk; g.ws = ws.p; g.amax = ws.amax;
+  g.splits = splits; g.kchunk = kchunk; g.ws = ws.p;
   if (type == GemmType::F16 && K > 0) {
-    hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, ws.amax);
-    hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.A, g.sa0, g.sa1, g.ta0, g.ta1, g.bsa, M, K,
-                       batch, ws.amax, 0);
-    hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.B, g.sb0, g.sb1, g.tb0, g.tb1, g.bsb, K, N,
-                       batch, ws.amax, 1);
+    // operands without a known maximum are scanned into the workspace words
+    if (!A.amax || !B.amax) hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, ws.amax, 2);
+    if (!A.amax)
+      hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.A, g.sa0, g.sa1, g.ta0, g.ta1, g.bsa, M, K,
+                         batch, ws.amax, 0);
+    if (!B.amax)
+      hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.B, g.sb0, g.sb1, g.tb0, g.tb1, g.bsb, K, N,
+                         batch, ws.amax, 1);
     CTM_HIP(hipGetLastError());
+    g.amaxA = A.amax ? A.amax : ws.amax;
+    g.amaxB = B.amax ? B.amax : ws.amax + 1;
   }
   dim3 grid((unsigned)(ceil_div(M, BM) * ceil_div(N, BN)), (unsigned)splits, (unsigned)batch);
   if (BN == 32) launch_typed<128, 32, 4>(st, type, g, a_kc, b_kc, grid);

@@ -19,6 +19,8 @@ struct Operand {
   const int* t0 = nullptr;   // row offset table (overrides s0)
   const int* t1 = nullptr;   // column offset table (overrides s1)
   long bs = 0;               // batch stride
+  const unsigned* amax = nullptr;   // split FP16: largest |entry| over the batch
+                                    // (FP32 bits, device), else scanned per call
 };
 
 struct OutOperand {
@@ -56,6 +58,9 @@ struct GemmWorkspace {
 // in the arithmetic `type` selects (F16 needs ws.amax).
 void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, const Operand& A,
           const Operand& B, double beta, const OutOperand& C, int batch, const GemmWorkspace& ws);
+
+// *out = largest |entry| (FP32 bits) of an R x C operand over `batch` problems.
+void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, unsigned* out);
 
 // Workspace elements gemm() may need for this shape (0 if no split-K).
 size_t gemm_workspace_elems(int M, int N, int K, int batch);

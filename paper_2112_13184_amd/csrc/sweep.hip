@@ -312,6 +312,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.gws_elems = (size_t)8 * c.n * std::max(c.kk, c.chi);
   c.gws.alloc(sizeof(double) * c.gws_elems);
   c.amax.alloc(sizeof(unsigned) * 2);
+  c.camax.alloc(sizeof(unsigned) * 4);
   switch (cfg.prec) {
     case CTM_F32: c.ctype = GemmType::F32; break;
     case CTM_BF16: c.ctype = GemmType::BF16; break;
@@ -343,7 +344,9 @@ static void mm(Context& c, int phase, int M, int N, int K, const Operand& A, con
 static void absorb(Context& c, const double* X, const double* Ak, const double* Ab, double* out,
                    bool transposed) {
   const int chi = c.chi, DK = c.DK, DB = c.DB, d = c.d;
-  if (c.ctype == GemmType::F64 && absorb_fused_fits(DK, DB, d)) {
+  // the fused kernel (FP64 MFMA, intermediate in LDS) serves every precision:
+  // after fusion the absorption is a small share of the sweep
+  if (absorb_fused_fits(DK, DB, d)) {
     const double flops = 2.0 * chi * chi * (double)DB * DB * DK * DK * d * (DK * DK + DB * DB);
     timed(c, PhaseTimer::ABSORB, flops, [&] { absorb_fused(c.st, X, Ak, Ab, out, chi, DK, DB, d, transposed); });
     return;
@@ -522,9 +525,17 @@ static void rsvd_batched(Context& c, int rot, int x, int y0, int s0, int nb, std
     const uint64_t sid = stream_id(c.moves, x, y);
     timed(c, PhaseTimer::OTHER, 0.0, [&] { omega_fill(c.st, pan(1, slot), n, c.Db, kk, c.cfg.seed, sid); });
   }
+  // split FP16: each corner role's largest entry, scanned once for the column
+  const unsigned* cam = nullptr;
+  if (c.ctype == GemmType::F16) {
+    for (int role = 0; role < 4; ++role)
+      operand_amax(c.st, rowmajor(Gp(role, s0), n, nn), n, n, nb, c.camax.as<unsigned>() + role);
+    cam = c.camax.as<unsigned>();
+  }
   // batched products with the four corners of every cut
   auto prod = [&](int role, bool trans, const double* X, double* Yo, int m) {
     Operand A = trans ? colmajor(Gp(role, s0), n, nn) : rowmajor(Gp(role, s0), n, nn);
+    if (cam) A.amax = cam + role;
     mm(c, PhaseTimer::SKETCH, n, m, n, A, colmajor(X, n, pk), out_colmajor(Yo, n, pk), nb);
   };
   double *Y = pan(0, s0), *Z = pan(1, s0), *W = pan(2, s0), *t1 = pan(3, s0), *t2 = pan(4, s0);
@@ -579,8 +590,13 @@ static void rsvd_batched(Context& c, int rot, int x, int y0, int s0, int nb, std
   // Pt = G_ll (G_lr V'), PT = W Ub'
   double* Pt = c.Pt.as<double>() + s0 * nc;
   double* PT = c.PT.as<double>() + s0 * nc;
-  mm(c, PhaseTimer::EDGE, n, chi, n, rowmajor(Gp(2, s0), n, nn), colmajor(V, n, pk), out_colmajor(t1, n, pk), nb);
-  mm(c, PhaseTimer::EDGE, n, chi, n, rowmajor(Gp(3, s0), n, nn), colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nb);
+  Operand G2 = rowmajor(Gp(2, s0), n, nn), G3 = rowmajor(Gp(3, s0), n, nn);
+  if (cam) {
+    G2.amax = cam + 2;
+    G3.amax = cam + 3;
+  }
+  mm(c, PhaseTimer::EDGE, n, chi, n, G2, colmajor(V, n, pk), out_colmajor(t1, n, pk), nb);
+  mm(c, PhaseTimer::EDGE, n, chi, n, G3, colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nb);
   mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n, pk), colmajor(Ysv, kk, k2), out_rowmajor(PT, chi, nc), nb);
   // cuts whose Cholesky QR broke down
   int flags[192] = {0};
