@@ -61,6 +61,29 @@ bool valid_config(const ctm_config* cfg, std::string& why) {
 
 ctm::Context& ctm::context_of(ctm_ctx* ctx) { return ctx->c; }
 
+ctm_ctx* ctm::create_group(const ctm_config& cfg, const double* tensors, int replicas, const uint64_t* seeds,
+                           ctm_status* st) {
+  std::string why;
+  if (!valid_config(&cfg, why) || !tensors) {
+    *st = CTM_EINVAL;
+    return nullptr;
+  }
+  ctm_ctx* ctx = new (std::nothrow) ctm_ctx();
+  if (!ctx) {
+    *st = CTM_ENOMEM;
+    return nullptr;
+  }
+  *st = guarded(ctx, [&] {
+    ctm::context_init(ctx->c, cfg, tensors, 0, nullptr, replicas, seeds);
+    ctx->rho.alloc(sizeof(double) * 4096);
+  });
+  if (*st != CTM_OK) {
+    ctm_free(ctx);
+    return nullptr;
+  }
+  return ctx;
+}
+
 extern "C" {
 
 ctm_status ctm_init(const ctm_config* cfg, const double* tensors, int tensors_on_device,

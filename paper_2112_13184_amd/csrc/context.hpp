@@ -87,7 +87,14 @@ struct PhaseTimer {
 struct Context {
   ctm_config cfg{};
   PhaseTimer timer;
-  int Lx = 0, Ly = 0, N = 0;
+  int Lx = 0, Ly = 0, N = 0;  // unit cell and its number of sites
+  // Replicas: R independent solves of the same shape in one context.  Replica
+  // r owns the sites r*N .. r*N+N-1 of every per-site buffer; the cuts of a
+  // column of all replicas are batched into the same launches.
+  int R = 1;
+  int NS() const { return R * N; }
+  std::vector<uint64_t> seeds;   // sketch seed per replica
+  std::vector<char> frozen;      // replica no longer updated (converged, capped, cancelled)
   int D = 0, d = 0, DK = 0, DB = 0, Db = 0, chi = 0, n = 0, layers = 2;
   int kk = 0;               // sketch width
   double cutoff = 1e-12;
@@ -123,7 +130,8 @@ struct Context {
   DevBuf camax;              // split FP16: largest |entry| of each corner role over a column's cuts
   GemmType ctype = GemmType::F64;   // arithmetic of the contraction GEMMs
   Arena arena;
-  std::vector<int> nact_cut; // per cut of the current column: bond dim after the move
+  std::vector<int> nact_cut; // per slot of the current column: bond dim after the move
+  std::vector<int> cut_slot; // (r * Lyv + y) -> slot of that cut in this column (-1: frozen)
   int64_t cuts[3] = {0, 0, 0}; // cuts by path: identity, batched randomized SVD, fallback
   bool last_cut_svd = false; // the last cut_projectors() call went through the SVD
 
@@ -131,8 +139,8 @@ struct Context {
   double* C(int s, int k) const { return envC.as<double>() + ((long)s * 4 + k) * chi * chi; }
   double* Ta(int s, int k) const { return envTa.as<double>() + ((long)s * 4 + k) * chi * chi * Db; }
   double* Tb(int s, int k) const { return envTb.as<double>() + ((long)s * 4 + k) * chi * chi * Db; }
-  const double* Ak(int rot, int s) const { return Aket.as<double>() + ((long)rot * N + s) * szk; }
-  const double* Ab(int rot, int s) const { return Abra.as<double>() + ((long)rot * N + s) * szb; }
+  const double* Ak(int rot, int s) const { return Aket.as<double>() + ((long)rot * NS() + s) * szk; }
+  const double* Ab(int rot, int s) const { return Abra.as<double>() + ((long)rot * NS() + s) * szb; }
   GemmWorkspace ws() const { return GemmWorkspace{gws.as<double>(), gws_elems, amax.as<unsigned>()}; }
 };
 
@@ -150,9 +158,13 @@ inline void timed(Context& c, int phase, double flops, F&& f) {
   c.timer.recs.push_back({phase, a, b, flops});
 }
 
+// tensors: `replicas` sets of Lx*Ly site tensors, one after the other;
+// seeds: one sketch seed per replica (nullptr: cfg.seed for all).
 void context_init(Context& c, const ctm_config& cfg, const double* tensors, int on_device,
-                  const double* boundary);
+                  const double* boundary, int replicas = 1, const uint64_t* seeds = nullptr);
 size_t context_footprint(const ctm_config& cfg);
+// Footprint of a context holding `replicas` solves of this configuration.
+size_t context_footprint_group(const ctm_config& cfg, int replicas);
 void do_move(Context& c, int rot);
 // Up to max_sweeps sweeps, stopping when delta < tol or when *cancel (checked
 // before every sweep) becomes true.
@@ -160,8 +172,18 @@ void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta,
                const std::atomic<bool>* cancel = nullptr);
 // The context inside a handle of the C ABI.
 Context& context_of(ctm_ctx* ctx);
-void cut_projectors(Context& c, int rot, int x, int y, int slot);
+// A handle holding `replicas` solves of one configuration (tensors: replicas
+// sets of Lx*Ly host site tensors; seeds: one per replica).  nullptr with
+// *st set on failure; released with ctm_free.
+ctm_ctx* create_group(const ctm_config& cfg, const double* tensors, int replicas, const uint64_t* seeds,
+                      ctm_status* st);
+void cut_projectors(Context& c, int rot, int r, int x, int y, int slot);
 void cut_projectors_fast(Context& c, int rot, int x, int y);
+// Sweeps of every replica until each converges (delta < tol[r]), reaches
+// max_sweeps[r] or is cancelled (cancel[r], checked before every sweep); a
+// finished replica is frozen.  done / delta / converged: one entry per replica.
+void do_sweeps_group(Context& c, const int* max_sweeps, const double* tol, int* done, double* delta,
+                     int* converged, const std::atomic<bool>* const* cancel);
 void enlarged_corner(Context& c, int s, int j, double* out);
 // Reduced density matrices, normalised to trace 1, in the device buffer
 // rho_dev (d*d or d^4 doubles); copied to rho_host when it is not null.
@@ -172,8 +194,8 @@ double expect_op(Context& c, const double* rho_dev, const double* op_host, int d
 // <O> on one site and <h> on the bond (site, site + x) (dir 0) or (site, site + y)
 // (dir 1), contracting the operator into closed networks instead of forming
 // the reduced density matrix (op layout [out][in], as for rho).
-double expect_1site(Context& c, int site, const double* op_host);
-double expect_2site(Context& c, int site, int dir, const double* op_host);
+double expect_1site(Context& c, int site, const double* op_host, int replica = 0);
+double expect_2site(Context& c, int site, int dir, const double* op_host, int replica = 0);
 // Elements of the largest transient the expectation values above (and the
 // classical impurity / ln kappa) allocate.
 size_t observe_arena_elems(long chi, long DK, long DB, long d);

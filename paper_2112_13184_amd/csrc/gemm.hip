@@ -515,8 +515,10 @@ __global__ __launch_bounds__(256) void k_gemm_dot(KArgs g) {
 }
 
 // Choose the split of K so that a small output grid still fills the GPU.
+// `tiles` counts the tiles of one problem of a batch: the split (and so the
+// summation order) of a problem does not depend on how many are batched.
 int choose_splits(long tiles, int K) {
-  const long target = 1024;   // ~4 workgroups per CU on 256 CUs
+  const long target = 512;    // ~2 workgroups per CU on 256 CUs, per problem
   if (tiles >= target / 2) return 1;
   int s = (int)std::min<long>((target + tiles - 1) / tiles, (long)K / 256);
   return std::max(1, std::min(s, 16));
@@ -532,7 +534,7 @@ void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, uns
 }
 
 size_t gemm_workspace_elems(int M, int N, int K, int batch) {
-  long tiles = (long)ceil_div(M, 64) * ceil_div(N, 64) * batch;
+  long tiles = (long)ceil_div(M, 64) * ceil_div(N, 64);
   int s = choose_splits(tiles, K);
   return s > 1 ? (size_t)s * batch * M * N : 0;
 }
@@ -571,7 +573,7 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   // tile shape: narrow N (sketch panels, bond-sized outputs) -> tall tiles
   int BM = 64, BN = 64;
   if (N <= 48) { BM = 128; BN = 32; }
-  long tiles = (long)ceil_div(M, BM) * ceil_div(N, BN) * batch;
+  long tiles = (long)ceil_div(M, BM) * ceil_div(N, BN);
   int splits = (K > 0) ? choose_splits(tiles, K) : 1;
   if (splits > 1 && (ws.p == nullptr || ws.elems < (size_t)splits * batch * M * N)) splits = 1;
   int kchunk = (K > 0) ? ((ceil_div(K, splits) + 15) / 16) * 16 : 16;

@@ -228,9 +228,9 @@ std::vector<double> fetch(Context& c, const double* dev, size_t n) {
 
 }  // namespace
 
-double expect_1site(Context& c, int site, const double* op_host) {
+double expect_1site(Context& c, int site, const double* op_host, int replica) {
   c.arena.reset();
-  View v = view_of(c, site, 0);
+  View v = view_of(c, replica * c.N + site, 0);
   double* res = c.arena.alloc(2);   // value with the operator, norm
   DT LB = left_boundary(c, v), RB = right_boundary(c, v);
   const auto m = c.arena.mark();
@@ -243,14 +243,14 @@ double expect_1site(Context& c, int site, const double* op_host) {
   return h[0] / h[1];
 }
 
-double expect_2site(Context& c, int site, int dir, const double* op_host) {
+double expect_2site(Context& c, int site, int dir, const double* op_host, int replica) {
   c.arena.reset();
   const int rot = (dir == 0) ? 0 : 3;
   int x = site % c.Lx, y = site / c.Lx;
   for (int i = 0; i < rot; ++i) { int t = x; x = -y; y = t; }
   const int s = view_site(c, rot, x, y), t = view_site(c, rot, x + 1, y);
   CTM_CHECK(s == site, -3, "expect_2site: view bookkeeping");
-  View vs = view_of(c, s, rot), vt = view_of(c, t, rot);
+  View vs = view_of(c, replica * c.N + s, rot), vt = view_of(c, replica * c.N + t, rot);
   // h[(ps' pt'), (ps pt)] = sum over (ps', ps) of E_{ps' ps} (x) h_{ps' ps}, one
   // closed two-column network per non-zero block, plus the norm
   const int d = c.d, dd = d * d;

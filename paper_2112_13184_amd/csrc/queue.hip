@@ -5,13 +5,17 @@
 // summed footprints of the running solves plus its own stay within the budget
 // (first fit in arrival order, so a large request does not hold back small
 // ones; a request skipped by 8 later admissions blocks further skipping, so
-// it cannot starve).  Every running solve owns a context with its own HIP
-// stream (default priority), so the kernels of different solves overlap on the
-// device while each worker thread waits for its own stream.  A solve runs
-// sweeps until the corner-spectrum change drops below its tolerance, its sweep
-// cap, or a cancellation (checked between sweeps), then evaluates the energy
-// per site and one-site magnetisations, frees its context and publishes the
-// result.
+// it cannot starve).  Pending requests of the same shape (unit cell, D, d,
+// chi, precision, sketch sizes) are admitted together as one group, up to 8,
+// while the group's footprint fits: the group shares one context, and the
+// cuts of all its solves are batched into the same launches (enlarged-corner
+// products, sketch GEMMs, Cholesky QR, Jacobi SVD).  Every group owns its HIP
+// stream (default priority), so different groups overlap on the device while
+// each worker thread waits for its own stream.  A solve runs sweeps until the
+// corner-spectrum change drops below its tolerance, its sweep cap, or a
+// cancellation (checked between sweeps); a finished solve of a group is
+// frozen while the others go on.  Then the energy per site and one-site
+// magnetisations are evaluated and the results published.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -48,6 +52,14 @@ size_t site_elems(const ctm_config& c) {
   return (size_t)c.Lx * c.Ly * D * D * D * D * d;
 }
 
+constexpr int kMaxGroup = 8;
+
+bool same_shape(const ctm_config& a, const ctm_config& b) {
+  return a.Lx == b.Lx && a.Ly == b.Ly && a.d == b.d && a.D == b.D && a.chi == b.chi && a.layers == b.layers &&
+         a.prec == b.prec && a.svd_rel_cutoff == b.svd_rel_cutoff && a.rsvd_oversample == b.rsvd_oversample &&
+         a.rsvd_power_iters == b.rsvd_power_iters;
+}
+
 }  // namespace
 
 struct ctm_queue {
@@ -64,66 +76,93 @@ struct ctm_queue {
 
 namespace {
 
-// Index in q->pending of the next request to admit, or -1.
-long pick(ctm_queue* q) {
-  if (q->active >= q->max_active) return -1;
+// The next group to admit: indices into q->pending (ascending), and its
+// footprint; empty if nothing fits now.
+std::vector<size_t> pick(ctm_queue* q, size_t* footprint) {
+  std::vector<size_t> g;
+  if (q->active >= q->max_active) return g;
   for (size_t i = 0; i < q->pending.size(); ++i) {
     const auto& j = q->pending[i];
     if (q->used + j->footprint <= q->budget) {
       for (size_t s = 0; s < i; ++s) q->pending[s]->skipped += 1;
-      return (long)i;
+      g.push_back(i);
+      *footprint = j->footprint;
+      // later requests of the same shape join while the group fits
+      const int cap = std::min(kMaxGroup, 64 / std::max(j->req.cfg.Lx, j->req.cfg.Ly));
+      for (size_t k = i + 1; k < q->pending.size() && (int)g.size() < cap; ++k) {
+        if (!same_shape(q->pending[k]->req.cfg, j->req.cfg)) continue;
+        const size_t fp = ctm::context_footprint_group(j->req.cfg, (int)g.size() + 1);
+        if (q->used + fp > q->budget) break;
+        g.push_back(k);
+        *footprint = fp;
+      }
+      return g;
     }
-    if (j->skipped >= 8) return -1;   // oldest request has waited long enough
+    if (j->skipped >= 8) return g;   // oldest request has waited long enough
   }
-  return -1;
+  return g;
 }
 
-void run_job(ctm_queue* q, Job& j) {
-  ctm_result& r = j.res;
-  ctm_config cfg = j.req.cfg;
+void run_group(ctm_queue* q, std::vector<std::shared_ptr<Job>>& jobs) {
+  (void)q;
+  const int R = (int)jobs.size();
+  ctm_config cfg = jobs[0]->req.cfg;
   cfg.stream = nullptr;   // the context creates its own stream
-  ctm_ctx* ctx = nullptr;
-  ctm_status st = ctm_init(&cfg, j.tensors.data(), 0, nullptr, &ctx);
-  if (st != CTM_OK) {
-    r.status = st;
+  std::vector<double> tensors;
+  std::vector<uint64_t> seeds(R);
+  for (int r = 0; r < R; ++r) {
+    tensors.insert(tensors.end(), jobs[r]->tensors.begin(), jobs[r]->tensors.end());
+    seeds[r] = jobs[r]->req.cfg.seed;
+  }
+  ctm_status st = CTM_OK;
+  ctm_ctx* ctx = ctm::create_group(cfg, tensors.data(), R, seeds.data(), &st);
+  if (!ctx) {
+    for (auto& j : jobs) j->res.status = st;
     return;
   }
   const int N = cfg.Lx * cfg.Ly;
   const int d = (cfg.layers == 2) ? cfg.d : 1;
-  int sweeps = 0, conv = 0;
-  double delta = INFINITY;
+  std::vector<int> maxs(R), done(R, 0), conv(R, 0);
+  std::vector<double> tol(R), delta(R, INFINITY);
+  std::vector<const std::atomic<bool>*> cancel(R);
+  for (int r = 0; r < R; ++r) {
+    maxs[r] = jobs[r]->req.max_sweeps;
+    tol[r] = jobs[r]->req.tol;
+    cancel[r] = &jobs[r]->cancel;
+  }
   ctm::Context& c = ctm::context_of(ctx);
+  std::vector<ctm_status> sts(R, CTM_OK);
   try {
-    ctm::do_sweeps(c, j.req.max_sweeps, j.req.tol, &sweeps, &delta, &conv, &j.cancel);
-    if (j.cancel.load()) {
-      st = CTM_ECANCELED;
-    } else {
-      double e = 0.0, v = 0.0;
-      for (int s = 0; s < N && st == CTM_OK; ++s) {
-        for (int dir = 0; dir < 2 && st == CTM_OK; ++dir) {
-          st = ctm_expect_2site(ctx, s, dir, j.bond.data(), &v);
-          e += v;
-        }
-        if (st == CTM_OK && !j.onsite.empty()) {
-          st = ctm_expect_1site(ctx, s, j.onsite.data(), &v);
-          e += v;
-        }
+    ctm::do_sweeps_group(c, maxs.data(), tol.data(), done.data(), delta.data(), conv.data(), cancel.data());
+    for (int r = 0; r < R; ++r) {
+      ctm_result& res = jobs[r]->res;
+      if (jobs[r]->cancel.load()) {
+        sts[r] = CTM_ECANCELED;
+        continue;
       }
-      r.energy_per_site = e / N;
-      if (st == CTM_OK && d == 2 && cfg.layers == 2) {
+      double e = 0.0;
+      for (int s = 0; s < N; ++s) {
+        for (int dir = 0; dir < 2; ++dir) e += ctm::expect_2site(c, s, dir, jobs[r]->bond.data(), r);
+        if (!jobs[r]->onsite.empty()) e += ctm::expect_1site(c, s, jobs[r]->onsite.data(), r);
+      }
+      res.energy_per_site = e / N;
+      if (d == 2 && cfg.layers == 2) {
         const double sz[4] = {1.0, 0.0, 0.0, -1.0};
-        for (int s = 0; s < std::min(N, 4) && st == CTM_OK; ++s) st = ctm_expect_1site(ctx, s, sz, &r.mz[s]);
+        for (int s = 0; s < std::min(N, 4); ++s) res.mz[s] = ctm::expect_1site(c, s, sz, r);
       }
     }
   } catch (const ctm::Error& e) {
-    st = (ctm_status)e.status;
+    for (auto& x : sts) x = (ctm_status)e.status;
   } catch (const std::exception&) {
-    st = CTM_EDEVICE;
+    for (auto& x : sts) x = CTM_EDEVICE;
   }
-  r.status = st;
-  r.sweeps = sweeps;
-  r.converged = conv;
-  r.delta = delta;
+  for (int r = 0; r < R; ++r) {
+    ctm_result& res = jobs[r]->res;
+    res.status = sts[r];
+    res.sweeps = done[r];
+    res.converged = conv[r];
+    res.delta = delta[r];
+  }
   ctm_free(ctx);
 }
 
@@ -131,22 +170,30 @@ void worker(ctm_queue* q) {
   (void)hipSetDevice(q->device);
   std::unique_lock<std::mutex> lk(q->mu);
   for (;;) {
-    long i = -1;
-    q->cv_work.wait(lk, [&] { return q->stop || (i = pick(q)) >= 0; });
-    if (i < 0) return;   // stopping and nothing admissible
-    std::shared_ptr<Job> j = q->pending[i];
-    q->pending.erase(q->pending.begin() + i);
-    q->used += j->footprint;
+    std::vector<size_t> idx;
+    size_t fp = 0;
+    q->cv_work.wait(lk, [&] { return q->stop || !(idx = pick(q, &fp)).empty(); });
+    if (idx.empty()) return;   // stopping and nothing admissible
+    std::vector<std::shared_ptr<Job>> jobs;
+    for (size_t i : idx) jobs.push_back(q->pending[i]);
+    for (size_t k = idx.size(); k-- > 0;) q->pending.erase(q->pending.begin() + idx[k]);
+    q->used += fp;
     q->active += 1;
-    j->state = Job::ACTIVE;
-    j->res.t_admit_ns = now_ns();
+    const int64_t t = now_ns();
+    for (auto& j : jobs) {
+      j->state = Job::ACTIVE;
+      j->res.t_admit_ns = t;
+    }
     lk.unlock();
-    run_job(q, *j);
+    run_group(q, jobs);
     lk.lock();
-    q->used -= j->footprint;
+    q->used -= fp;
     q->active -= 1;
-    j->res.t_done_ns = now_ns();
-    j->state = Job::DONE;
+    const int64_t td = now_ns();
+    for (auto& j : jobs) {
+      j->res.t_done_ns = td;
+      j->state = Job::DONE;
+    }
     q->cv_done.notify_all();
     q->cv_work.notify_all();
   }

@@ -132,7 +132,7 @@ struct Sizes {
   size_t total_bytes;
 };
 
-Sizes sizes_of(const ctm_config& cfg) {
+Sizes sizes_of(const ctm_config& cfg, int R = 1) {
   Sizes s{};
   const long DK = cfg.D, DB = (cfg.layers == 2) ? cfg.D : 1;
   const long d = (cfg.layers == 2) ? cfg.d : 1;
@@ -143,7 +143,7 @@ Sizes sizes_of(const ctm_config& cfg) {
   const int p = cfg.rsvd_oversample;
   s.kk = (p < 0) ? s.n : std::min<long>(s.chi + p, s.n);
   s.y = s.nn * d;
-  const long N = (long)cfg.Lx * cfg.Ly, Lmax = std::max(cfg.Lx, cfg.Ly);
+  const long N = (long)cfg.Lx * cfg.Ly * R, Lmax = (long)std::max(cfg.Lx, cfg.Ly) * R;   // sites, slots
   const long chi = s.chi, n = s.n, kk = s.kk, cc = chi * chi;
   // doubles, in the order context_init allocates them
   size_t e = 0;
@@ -156,7 +156,7 @@ Sizes sizes_of(const ctm_config& cfg) {
     e += 7 * kk * kk * Lmax + kk * Lmax + n * kk * Lmax + 64 + 128;
   e += 3 * Lmax * n * chi + 2 * Lmax * cc + Lmax * cc * s.Db;       // projectors, new C / T
   e += 2 * 4 * N * chi + 4 * N * cc;                                // spectra, corner scratch
-  e += 8 * n * std::max(kk, chi);                                   // split-K partials
+  e += 8 * n * std::max(kk, chi) * R;                               // split-K partials
   e += 4096 + 2048 + 64;                                            // rho, reductions, flags
   e += observe_arena_elems(chi, DK, DB, d);                         // expectation values
   size_t b = 8 * e;
@@ -194,6 +194,7 @@ double* Arena::alloc(size_t elems) {
 }
 
 size_t context_footprint(const ctm_config& cfg) { return sizes_of(cfg).total_bytes; }
+size_t context_footprint_group(const ctm_config& cfg, int replicas) { return sizes_of(cfg, replicas).total_bytes; }
 
 void check_bad(Context& c, const char* where) {
   int bad = 0;
@@ -206,9 +207,14 @@ void check_bad(Context& c, const char* where) {
 }
 
 void context_init(Context& c, const ctm_config& cfg, const double* tensors, int on_device,
-                  const double* boundary) {
+                  const double* boundary, int replicas, const uint64_t* seeds) {
   c.cfg = cfg;
   c.Lx = cfg.Lx; c.Ly = cfg.Ly; c.N = cfg.Lx * cfg.Ly;
+  CTM_CHECK(replicas >= 1 && replicas * std::max(cfg.Lx, cfg.Ly) <= 64, -1, "context: 1..64/max(Lx, Ly) replicas");
+  c.R = replicas;
+  c.seeds.assign(replicas, cfg.seed);
+  if (seeds) c.seeds.assign(seeds, seeds + replicas);
+  c.frozen.assign(replicas, 0);
   c.layers = cfg.layers;
   c.D = cfg.D;
   c.d = (cfg.layers == 2) ? cfg.d : 1;
@@ -219,6 +225,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.n = c.chi * c.Db;
   c.cutoff = (cfg.svd_rel_cutoff > 0) ? cfg.svd_rel_cutoff : 1e-12;
   const Sizes sz = sizes_of(cfg);
+  const int NS = c.NS();
   c.kk = (int)sz.kk;
 
   if (cfg.stream) {
@@ -232,22 +239,22 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   // ---- site tensors and their rotations (host side, tiny) ---------------
   c.szk = (long)c.DK * c.DK * c.DK * c.DK * c.d;
   c.szb = (long)c.DB * c.DB * c.DB * c.DB * c.d;
-  std::vector<double> host((size_t)c.N * c.szk);
+  std::vector<double> host((size_t)NS * c.szk);
   if (on_device) {
     CTM_HIP(hipMemcpy(host.data(), tensors, host.size() * sizeof(double), hipMemcpyDeviceToHost));
   } else {
     std::memcpy(host.data(), tensors, host.size() * sizeof(double));
   }
   for (double v : host) CTM_CHECK(std::isfinite(v), -4, "site tensor has NaN/Inf entries");
-  std::vector<double> ket((size_t)4 * c.N * c.szk), bra((size_t)4 * c.N * c.szb);
-  for (int s = 0; s < c.N; ++s) {
+  std::vector<double> ket((size_t)4 * NS * c.szk), bra((size_t)4 * NS * c.szb);
+  for (int s = 0; s < NS; ++s) {
     std::vector<double> t(host.begin() + (long)s * c.szk, host.begin() + (long)(s + 1) * c.szk), r;
     for (int rot = 0; rot < 4; ++rot) {
-      std::copy(t.begin(), t.end(), ket.begin() + ((long)rot * c.N + s) * c.szk);
+      std::copy(t.begin(), t.end(), ket.begin() + ((long)rot * NS + s) * c.szk);
       if (c.layers == 2)
-        std::copy(t.begin(), t.end(), bra.begin() + ((long)rot * c.N + s) * c.szb);
+        std::copy(t.begin(), t.end(), bra.begin() + ((long)rot * NS + s) * c.szb);
       else
-        bra[(long)rot * c.N + s] = 1.0;
+        bra[(long)rot * NS + s] = 1.0;
       rotate_host(t, r, c.DK, c.d);
       t.swap(r);
     }
@@ -259,9 +266,9 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
 
   // ---- environment ------------------------------------------------------
   const long cc = (long)c.chi * c.chi, tt = cc * c.Db;
-  c.envC.alloc(sizeof(double) * 4 * c.N * cc);
-  c.envTa.alloc(sizeof(double) * 4 * c.N * tt);
-  c.envTb.alloc(sizeof(double) * 4 * c.N * tt);
+  c.envC.alloc(sizeof(double) * 4 * NS * cc);
+  c.envTa.alloc(sizeof(double) * 4 * NS * tt);
+  c.envTb.alloc(sizeof(double) * 4 * NS * tt);
   std::vector<double> hb(c.Db);
   if (boundary) {
     std::memcpy(hb.data(), boundary, sizeof(double) * c.Db);
@@ -270,21 +277,21 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   } else {
     std::fill(hb.begin(), hb.end(), 1.0);
   }
-  std::vector<double> hc(4 * c.N * cc, 0.0), ht(4 * c.N * tt, 0.0);
-  for (int s = 0; s < 4 * c.N; ++s) {
+  std::vector<double> hc(4 * NS * cc, 0.0), ht(4 * NS * tt, 0.0);
+  for (int s = 0; s < 4 * NS; ++s) {
     hc[s * cc] = 1.0;
     for (int b = 0; b < c.Db; ++b) ht[s * tt + b] = hb[b];   // T[0][0][b] in the [prev][next][pair] layout
   }
   CTM_HIP(hipMemcpy(c.envC.p, hc.data(), hc.size() * sizeof(double), hipMemcpyHostToDevice));
   CTM_HIP(hipMemcpy(c.envTa.p, ht.data(), ht.size() * sizeof(double), hipMemcpyHostToDevice));
-  for (int s = 0; s < c.N; ++s)
+  for (int s = 0; s < NS; ++s)
     for (int k = 0; k < 4; ++k) swap_last2(c.st, c.Ta(s, k), c.Tb(s, k), c.chi, c.chi, c.Db);
-  c.cdim.assign(c.N, {{{1, 1}, {1, 1}, {1, 1}, {1, 1}}});
-  c.tdim.assign(c.N, {{{1, 1}, {1, 1}, {1, 1}, {1, 1}}});
+  c.cdim.assign(NS, {{{1, 1}, {1, 1}, {1, 1}, {1, 1}}});
+  c.tdim.assign(NS, {{{1, 1}, {1, 1}, {1, 1}, {1, 1}}});
 
   // ---- workspaces --------------------------------------------------------
   build_tables(c);
-  const int Lmax0 = std::max(c.Lx, c.Ly);
+  const int Lmax0 = std::max(c.Lx, c.Ly) * c.R;   // cut slots of one column, all replicas
   for (auto& g : c.G) g.alloc(sizeof(double) * sz.nn * Lmax0);      // one slot per cut of a column
   c.X1.alloc(sizeof(double) * c.chi * c.n);
   c.X2.alloc(sizeof(double) * sz.nn);
@@ -298,18 +305,18 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.badflag.alloc(sizeof(int));
   CTM_HIP(hipMemset(c.badflag.p, 0, sizeof(int)));
   c.redscratch.alloc(sizeof(double) * 2048);
-  c.delta.alloc(sizeof(double));
-  int Lmax = std::max(c.Lx, c.Ly);
+  c.delta.alloc(sizeof(double) * c.R);
+  int Lmax = Lmax0;
   c.Pt.alloc(sizeof(double) * Lmax * c.n * c.chi);
   c.PT.alloc(sizeof(double) * Lmax * c.n * c.chi);
   c.P3.alloc(sizeof(double) * Lmax * c.n * c.chi);
   c.newC1.alloc(sizeof(double) * Lmax * cc);
   c.newC4.alloc(sizeof(double) * Lmax * cc);
   c.newT4.alloc(sizeof(double) * Lmax * tt);
-  c.spec.alloc(sizeof(double) * 4 * c.N * c.chi);
-  c.specprev.alloc(sizeof(double) * 4 * c.N * c.chi);
-  c.cornerscratch.alloc(sizeof(double) * 4 * c.N * cc);
-  c.gws_elems = (size_t)8 * c.n * std::max(c.kk, c.chi);
+  c.spec.alloc(sizeof(double) * 4 * NS * c.chi);
+  c.specprev.alloc(sizeof(double) * 4 * NS * c.chi);
+  c.cornerscratch.alloc(sizeof(double) * 4 * NS * cc);
+  c.gws_elems = (size_t)8 * c.n * std::max(c.kk, c.chi) * c.R;
   c.gws.alloc(sizeof(double) * c.gws_elems);
   c.amax.alloc(sizeof(unsigned) * 2);
   c.camax.alloc(sizeof(unsigned) * 4);
@@ -320,6 +327,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
     default: c.ctype = GemmType::F64; break;
   }
   c.nact_cut.assign(Lmax, c.chi);
+  c.cut_slot.assign(Lmax, -1);
   c.arena.first_elems = observe_arena_elems(c.chi, c.DK, c.DB, c.d);
   CTM_HIP(hipStreamSynchronize(c.st));
 }
@@ -405,12 +413,13 @@ void apply_Mt(Context& c, double* const G[4], const double* X, double* Z, int m,
 
 // Projectors of the cut (x, y) of a move in frame rot, into slot `slot` of
 // Pt / PT (n x chi, row-major each).  Records the new bond dimension.
-void cut_projectors(Context& c, int rot, int x, int y, int slot) {
+void cut_projectors(Context& c, int rot, int r, int x, int y, int slot) {
   const int chi = c.chi, n = c.n;
   double* Pt = c.Pt.as<double>() + (long)slot * n * chi;
   double* PT = c.PT.as<double>() + (long)slot * n * chi;
-  const int sUL = view_site(c, rot, x, y), sUR = view_site(c, rot, x + 1, y);
-  const int sLR = view_site(c, rot, x + 1, y - 1), sLL = view_site(c, rot, x, y - 1);
+  const int o = r * c.N;
+  const int sUL = o + view_site(c, rot, x, y), sUR = o + view_site(c, rot, x + 1, y);
+  const int sLR = o + view_site(c, rot, x + 1, y - 1), sLL = o + view_site(c, rot, x, y - 1);
   const int nact = c.tdim[sUL][(3 + rot) % 4][0] * c.Db;
   if (nact <= chi) {   // nothing to discard: identity projectors
     identity_panel(c.st, Pt, n, chi, nact);
@@ -468,7 +477,7 @@ void cut_projectors(Context& c, int rot, int x, int y, int slot) {
   const int kk = c.kk;
   double *Y = P[0], *Z = P[1], *W = P[2], *t1 = P[3], *t2 = P[4], *V = P[5], *U = P[6];
   const uint64_t sid = stream_id(c.moves, x, mod(y, (rot % 2 == 0) ? c.Ly : c.Lx));
-  omega_fill(c.st, Z, n, c.Db, kk, c.cfg.seed, sid);
+  omega_fill(c.st, Z, n, c.Db, kk, c.seeds[r], sid);
   apply_M(c, G, Z, Y, kk, t1, t2);
   timed(c, PhaseTimer::LINALG, 0.0, [&] { la_orth(c.la, Y, n, kk); });
   for (int q = 0; q < c.cfg.rsvd_power_iters; ++q) {
@@ -505,16 +514,18 @@ void cut_projectors(Context& c, int rot, int x, int y, int slot) {
 // block one-sided Jacobi.  Returns false (outputs undefined) for the cuts
 // whose Cholesky factorisation was not numerically positive definite; those
 // are recomputed with Householder QR by the caller.
-static void rsvd_batched(Context& c, int rot, int x, int y0, int s0, int nb, std::vector<int>& failed) {
+static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::array<int, 2>>& cuts, int s0,
+                         std::vector<int>& failed) {
+  const int nb = (int)cuts.size();
   const int chi = c.chi, n = c.n, kk = c.kk;
   const long nn = (long)n * n, pk = (long)n * kk, k2 = (long)kk * kk, nc = (long)n * chi;
   auto Gp = [&](int role, int slot) { return c.G[role].as<double>() + slot * nn; };
   auto pan = [&](int i, int slot) { return c.pan[i].as<double>() + slot * pk; };
   std::vector<int> kcap(nb);
   for (int b = 0; b < nb; ++b) {
-    const int y = y0 + b, slot = s0 + b;
-    const int sites[4] = {view_site(c, rot, x, y), view_site(c, rot, x + 1, y), view_site(c, rot, x + 1, y - 1),
-                          view_site(c, rot, x, y - 1)};
+    const int r = cuts[b][0], y = cuts[b][1], slot = s0 + b, o = r * c.N;
+    const int sites[4] = {o + view_site(c, rot, x, y), o + view_site(c, rot, x + 1, y),
+                          o + view_site(c, rot, x + 1, y - 1), o + view_site(c, rot, x, y - 1)};
     kcap[b] = chi;
     for (int q = 0; q < 4; ++q) {
       const int j = (q + rot) % 4, s = sites[q];
@@ -523,7 +534,7 @@ static void rsvd_batched(Context& c, int rot, int x, int y0, int s0, int nb, std
       enlarged_corner(c, s, j, Gp(q, slot));   // roles: 0 UL, 1 UR, 2 LR, 3 LL
     }
     const uint64_t sid = stream_id(c.moves, x, y);
-    timed(c, PhaseTimer::OTHER, 0.0, [&] { omega_fill(c.st, pan(1, slot), n, c.Db, kk, c.cfg.seed, sid); });
+    timed(c, PhaseTimer::OTHER, 0.0, [&] { omega_fill(c.st, pan(1, slot), n, c.Db, kk, c.seeds[r], sid); });
   }
   // split FP16: each corner role's largest entry, scanned once for the column
   const unsigned* cam = nullptr;
@@ -616,46 +627,57 @@ static void rsvd_batched(Context& c, int rot, int x, int y0, int s0, int nb, std
     CTM_HIP(hipStreamSynchronize(c.st));
   }
   if (g_debug) {
-    fprintf(stderr, "[ctm] move %lld rot %d col %d cuts %d..%d: cholqr failed %zu, no-sigma %d, codes", c.moves, rot,
-            x, y0, y0 + nb - 1, failed.size(), (int)numeric);
+    fprintf(stderr, "[ctm] move %lld rot %d col %d slots %d..%d: cholqr failed %zu, no-sigma %d, codes", c.moves,
+            rot, x, s0, s0 + nb - 1, failed.size(), (int)numeric);
     for (int b = 0; b < nb; ++b) fprintf(stderr, " %d", flags[b]);
     fprintf(stderr, "\n");
   }
   if (numeric) throw Error(-4, "projectors: a cut has no singular value above zero");
 }
 
-// Projectors of every cut of column x (identity, batched randomized SVD, or
-// the Householder / exact-SVD path).
+// Projectors of every cut of column x of every live replica (identity,
+// batched randomized SVD, or the Householder / exact-SVD path).  Cut (r, y)
+// gets slot cut_slot[r * Lyv + y]: the live cuts numbered in order.
 static void column_projectors(Context& c, int rot, int x, int Lyv) {
-  std::vector<int> svd;
-  for (int y = 0; y < Lyv; ++y) {
-    const int nact = c.tdim[view_site(c, rot, x, y)][(3 + rot) % 4][0] * c.Db;
-    if (nact <= c.chi) {
-      cut_projectors(c, rot, x, y, y);   // identity
-      ++c.cuts[0];
-    } else {
-      svd.push_back(y);
+  std::vector<std::array<int, 2>> svd;
+  std::vector<int> svd_slot;
+  int slot = 0;
+  for (int r = 0; r < c.R; ++r)
+    for (int y = 0; y < Lyv; ++y) {
+      if (c.frozen[r]) {
+        c.cut_slot[r * Lyv + y] = -1;
+        continue;
+      }
+      c.cut_slot[r * Lyv + y] = slot;
+      const int nact = c.tdim[r * c.N + view_site(c, rot, x, y)][(3 + rot) % 4][0] * c.Db;
+      if (nact <= c.chi) {
+        cut_projectors(c, rot, r, x, y, slot);   // identity
+        ++c.cuts[0];
+      } else {
+        svd.push_back({r, y});
+        svd_slot.push_back(slot);
+      }
+      ++slot;
     }
-  }
   if (svd.empty()) return;
   const bool fast = c.cfg.rsvd_oversample >= 0 && c.sla.kmax > 0 && smallla_fits(c.sla, c.kk);
   if (!fast) {
-    for (int y : svd) cut_projectors(c, rot, x, y, y);
+    for (size_t i = 0; i < svd.size(); ++i) cut_projectors(c, rot, svd[i][0], x, svd[i][1], svd_slot[i]);
     c.cuts[2] += (int64_t)svd.size();
     return;
   }
   std::vector<int> failed;
-  auto run = [&](int y0, int nb) {
-    rsvd_batched(c, rot, x, y0, y0, nb, failed);
-    for (int b : failed) cut_projectors(c, rot, x, y0 + b, y0 + b);   // Householder fallback
-    for (int b = 0; b < nb; ++b) c.nact_cut[y0 + b] = c.chi;
-    c.cuts[1] += nb - (int64_t)failed.size();
+  auto run = [&](const std::vector<std::array<int, 2>>& cuts, int s0) {
+    rsvd_batched(c, rot, x, cuts, s0, failed);
+    for (int b : failed) cut_projectors(c, rot, cuts[b][0], x, cuts[b][1], s0 + b);   // Householder fallback
+    for (int b = 0; b < (int)cuts.size(); ++b) c.nact_cut[s0 + b] = c.chi;
+    c.cuts[1] += (int64_t)cuts.size() - (int64_t)failed.size();
     c.cuts[2] += (int64_t)failed.size();
   };
-  if ((int)svd.size() == Lyv) {
-    run(0, Lyv);
+  if ((int)svd.size() == slot) {
+    run(svd, 0);   // every live cut: one batch over contiguous slots
   } else {
-    for (int y : svd) run(y, 1);
+    for (size_t i = 0; i < svd.size(); ++i) run({svd[i]}, svd_slot[i]);
   }
   c.last_cut_svd = true;
 }
@@ -664,19 +686,20 @@ static void column_projectors(Context& c, int rot, int x, int Lyv) {
 void cut_projectors_fast(Context& c, int rot, int x, int y) {
   const int nact = c.tdim[view_site(c, rot, x, y)][(3 + rot) % 4][0] * c.Db;
   if (nact <= c.chi || c.cfg.rsvd_oversample < 0 || c.sla.kmax == 0 || !smallla_fits(c.sla, c.kk)) {
-    cut_projectors(c, rot, x, y, 0);
+    cut_projectors(c, rot, 0, x, y, 0);
     ++c.cuts[nact <= c.chi ? 0 : 2];
     return;
   }
   std::vector<int> failed;
-  rsvd_batched(c, rot, x, y, 0, 1, failed);
-  if (!failed.empty()) cut_projectors(c, rot, x, y, 0);
+  rsvd_batched(c, rot, x, {{0, y}}, 0, failed);
+  if (!failed.empty()) cut_projectors(c, rot, 0, x, y, 0);
   ++c.cuts[failed.empty() ? 1 : 2];
   c.nact_cut[0] = c.chi;
   c.last_cut_svd = true;
 }
 
-// One directional move (Sec. 2.2) in the frame rotated rot quarter turns.
+// One directional move (Sec. 2.2) in the frame rotated rot quarter turns, for
+// every live replica.
 void do_move(Context& c, int rot) {
   int Lxv, Lyv;
   view_dims(c, rot, Lxv, Lyv);
@@ -685,46 +708,55 @@ void do_move(Context& c, int rot) {
   const int kc1 = (0 + rot) % 4, kt1 = (0 + rot) % 4, kt3 = (2 + rot) % 4, kt4 = (3 + rot) % 4, kc4 = (3 + rot) % 4;
   for (int x = 0; x < Lxv; ++x) {
     column_projectors(c, rot, x, Lyv);
-    std::vector<std::array<int, 2>> newdC1(Lyv), newdT4(Lyv), newdC4(Lyv);
-    for (int y = 0; y < Lyv; ++y) {
-      const int s = view_site(c, rot, x, y);
-      const int up = (y + 1) % Lyv;
-      double* Pt_up = c.Pt.as<double>() + (long)up * n * chi;
-      double* Pt_dn = c.Pt.as<double>() + (long)y * n * chi;
-      double* PT_dn = c.PT.as<double>() + (long)y * n * chi;
-      double* P3_up = c.P3.as<double>() + (long)up * n * chi;
-      swap_last2(c.st, c.PT.as<double>() + (long)up * n * chi, P3_up, chi, Db, chi);
-      double* C1n = c.newC1.as<double>() + y * cc;
-      double* C4n = c.newC4.as<double>() + y * cc;
-      double* T4n = c.newT4.as<double>() + y * tt;
-      // C1' = (C1 T1) Pt_up: X1p[c2][(t4, u)] then times Pt
-      mm(c, PhaseTimer::OTHER, chi, Db, chi, colmajor(c.C(s, kc1), chi), rowmajor(c.Ta(s, kt1), n, Db),
-         out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
-      mm(c, PhaseTimer::OTHER, chi, chi, n, rowmajor(c.X1.p, n), rowmajor(Pt_up, chi), out_rowmajor(C1n, chi));
-      // C4'^T[c3][k] = sum_{(t4,d)} Yc[c3][(t4, d)] PT_dn[(t4, d)][k], Yc[c3] = C4 T3[c3]
-      mm(c, PhaseTimer::OTHER, chi, Db, chi, rowmajor(c.C(s, kc4), chi), rowmajor(c.Ta(s, kt3), Db, (long)chi * Db),
-         out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
-      mm(c, PhaseTimer::OTHER, chi, chi, n, rowmajor(c.X1.p, n), rowmajor(PT_dn, chi), out_colmajor(C4n, chi));
-      // T4' = Pt_dn^T absorb(T4 P3_up)
-      mm(c, PhaseTimer::EDGE, n, n, chi, rowmajor(c.Tb(s, kt4), chi), rowmajor(P3_up, n), out_rowmajor(c.X2.p, n));
-      absorb(c, c.X2.as<double>(), c.Ak(rot, s), c.Ab(rot, s), c.G[0].as<double>(), true);
-      mm(c, PhaseTimer::EDGE, chi, n, n, colmajor(Pt_dn, chi), rowmajor(c.G[0].p, n), out_rowmajor(T4n, n));
-      normalize_maxabs(c.st, C1n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
-      normalize_maxabs(c.st, C4n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
-      normalize_maxabs(c.st, T4n, tt, c.redscratch.as<double>(), c.badflag.as<int>());
-      newdC1[y] = {c.tdim[s][kt1][1], c.nact_cut[up]};
-      newdT4[y] = {c.nact_cut[y], c.nact_cut[up]};
-      newdC4[y] = {c.nact_cut[y], c.tdim[s][kt3][0]};
+    std::vector<std::array<int, 2>> newdC1(c.R * Lyv), newdT4(c.R * Lyv), newdC4(c.R * Lyv);
+    for (int r = 0; r < c.R; ++r) {
+      if (c.frozen[r]) continue;
+      for (int y = 0; y < Lyv; ++y) {
+        const int s = r * c.N + view_site(c, rot, x, y);
+        const int sl = c.cut_slot[r * Lyv + y], up = c.cut_slot[r * Lyv + (y + 1) % Lyv];
+        double* Pt_up = c.Pt.as<double>() + (long)up * n * chi;
+        double* Pt_dn = c.Pt.as<double>() + (long)sl * n * chi;
+        double* PT_dn = c.PT.as<double>() + (long)sl * n * chi;
+        double* P3_up = c.P3.as<double>() + (long)up * n * chi;
+        swap_last2(c.st, c.PT.as<double>() + (long)up * n * chi, P3_up, chi, Db, chi);
+        double* C1n = c.newC1.as<double>() + sl * cc;
+        double* C4n = c.newC4.as<double>() + sl * cc;
+        double* T4n = c.newT4.as<double>() + sl * tt;
+        // C1' = (C1 T1) Pt_up: X1p[c2][(t4, u)] then times Pt
+        mm(c, PhaseTimer::OTHER, chi, Db, chi, colmajor(c.C(s, kc1), chi), rowmajor(c.Ta(s, kt1), n, Db),
+           out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
+        mm(c, PhaseTimer::OTHER, chi, chi, n, rowmajor(c.X1.p, n), rowmajor(Pt_up, chi), out_rowmajor(C1n, chi));
+        // C4'^T[c3][k] = sum_{(t4,d)} Yc[c3][(t4, d)] PT_dn[(t4, d)][k], Yc[c3] = C4 T3[c3]
+        mm(c, PhaseTimer::OTHER, chi, Db, chi, rowmajor(c.C(s, kc4), chi),
+           rowmajor(c.Ta(s, kt3), Db, (long)chi * Db), out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
+        mm(c, PhaseTimer::OTHER, chi, chi, n, rowmajor(c.X1.p, n), rowmajor(PT_dn, chi), out_colmajor(C4n, chi));
+        // T4' = Pt_dn^T absorb(T4 P3_up)
+        mm(c, PhaseTimer::EDGE, n, n, chi, rowmajor(c.Tb(s, kt4), chi), rowmajor(P3_up, n), out_rowmajor(c.X2.p, n));
+        absorb(c, c.X2.as<double>(), c.Ak(rot, s), c.Ab(rot, s), c.G[0].as<double>(), true);
+        mm(c, PhaseTimer::EDGE, chi, n, n, colmajor(Pt_dn, chi), rowmajor(c.G[0].p, n), out_rowmajor(T4n, n));
+        normalize_maxabs(c.st, C1n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
+        normalize_maxabs(c.st, C4n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
+        normalize_maxabs(c.st, T4n, tt, c.redscratch.as<double>(), c.badflag.as<int>());
+        newdC1[r * Lyv + y] = {c.tdim[s][kt1][1], c.nact_cut[up]};
+        newdT4[r * Lyv + y] = {c.nact_cut[sl], c.nact_cut[up]};
+        newdC4[r * Lyv + y] = {c.nact_cut[sl], c.tdim[s][kt3][0]};
+      }
     }
-    for (int y = 0; y < Lyv; ++y) {
-      const int t = view_site(c, rot, x + 1, y);
-      CTM_HIP(hipMemcpyAsync(c.C(t, kc1), c.newC1.as<double>() + y * cc, cc * sizeof(double), hipMemcpyDeviceToDevice, c.st));
-      CTM_HIP(hipMemcpyAsync(c.C(t, kc4), c.newC4.as<double>() + y * cc, cc * sizeof(double), hipMemcpyDeviceToDevice, c.st));
-      CTM_HIP(hipMemcpyAsync(c.Ta(t, kt4), c.newT4.as<double>() + y * tt, tt * sizeof(double), hipMemcpyDeviceToDevice, c.st));
-      swap_last2(c.st, c.Ta(t, kt4), c.Tb(t, kt4), chi, chi, Db);
-      c.cdim[t][kc1] = newdC1[y];
-      c.tdim[t][kt4] = newdT4[y];
-      c.cdim[t][kc4] = newdC4[y];
+    for (int r = 0; r < c.R; ++r) {
+      if (c.frozen[r]) continue;
+      for (int y = 0; y < Lyv; ++y) {
+        const int t = r * c.N + view_site(c, rot, x + 1, y), sl = c.cut_slot[r * Lyv + y];
+        CTM_HIP(hipMemcpyAsync(c.C(t, kc1), c.newC1.as<double>() + sl * cc, cc * sizeof(double),
+                               hipMemcpyDeviceToDevice, c.st));
+        CTM_HIP(hipMemcpyAsync(c.C(t, kc4), c.newC4.as<double>() + sl * cc, cc * sizeof(double),
+                               hipMemcpyDeviceToDevice, c.st));
+        CTM_HIP(hipMemcpyAsync(c.Ta(t, kt4), c.newT4.as<double>() + sl * tt, tt * sizeof(double),
+                               hipMemcpyDeviceToDevice, c.st));
+        swap_last2(c.st, c.Ta(t, kt4), c.Tb(t, kt4), chi, chi, Db);
+        c.cdim[t][kc1] = newdC1[r * Lyv + y];
+        c.tdim[t][kt4] = newdT4[r * Lyv + y];
+        c.cdim[t][kc4] = newdC4[r * Lyv + y];
+      }
     }
   }
   c.moves += 1;
@@ -736,33 +768,71 @@ static const int kSweepRot[4] = {0, 2, 1, 3};   // left, right, up, down
 static void corner_spectra(Context& c, double* out) {
   const long cc = (long)c.chi * c.chi;
   timed(c, PhaseTimer::OTHER, 0.0, [&] {
-    CTM_HIP(hipMemcpyAsync(c.cornerscratch.p, c.envC.p, sizeof(double) * 4 * c.N * cc, hipMemcpyDeviceToDevice, c.st));
-    la_singular_values_batched(c.la, c.cornerscratch.as<double>(), c.chi, 4 * c.N, out);
+    CTM_HIP(hipMemcpyAsync(c.cornerscratch.p, c.envC.p, sizeof(double) * 4 * c.NS() * cc, hipMemcpyDeviceToDevice,
+                           c.st));
+    for (int i = 0; i < 4 * c.NS(); i += 64)
+      la_singular_values_batched(c.la, c.cornerscratch.as<double>() + i * cc, c.chi, std::min(64, 4 * c.NS() - i),
+                                 out + (long)i * c.chi);
   });
+}
+
+// delta of every replica (device, c.delta[r]): spectra of the 4 N corners of
+// replica r against their previous values; prev <- spectra.
+static void replica_deltas(Context& c, double* spec, double* prev) {
+  const long per = 4L * c.N * c.chi;
+  for (int r = 0; r < c.R; ++r)
+    spectra_delta(c.st, spec + r * per, prev + r * per, 4 * c.N, c.chi, c.delta.as<double>() + r);
+}
+
+void do_sweeps_group(Context& c, const int* max_sweeps, const double* tol, int* done, double* delta,
+                     int* converged, const std::atomic<bool>* const* cancel) {
+  const int R = c.R;
+  corner_spectra(c, c.specprev.as<double>());
+  // normalise the reference spectra (deltas of this step are discarded)
+  replica_deltas(c, c.specprev.as<double>(), c.spec.as<double>());
+  CTM_HIP(hipMemcpyAsync(c.specprev.p, c.spec.p, sizeof(double) * 4 * c.NS() * c.chi, hipMemcpyDeviceToDevice,
+                         c.st));
+  std::vector<double> dl(R, INFINITY);
+  for (int r = 0; r < R; ++r) {
+    done[r] = 0;
+    converged[r] = 0;
+    c.frozen[r] = (max_sweeps[r] <= 0) ? 1 : 0;
+  }
+  for (;;) {
+    bool live = false;
+    for (int r = 0; r < R; ++r) {
+      if (!c.frozen[r] && cancel && cancel[r] && cancel[r]->load()) c.frozen[r] = 1;
+      live |= !c.frozen[r];
+    }
+    if (!live) break;
+    for (int m = 0; m < 4; ++m) do_move(c, kSweepRot[m]);
+    corner_spectra(c, c.spec.as<double>());
+    replica_deltas(c, c.spec.as<double>(), c.specprev.as<double>());
+    std::vector<double> h(R);
+    CTM_HIP(hipMemcpyAsync(h.data(), c.delta.p, sizeof(double) * R, hipMemcpyDeviceToHost, c.st));
+    CTM_HIP(hipStreamSynchronize(c.st));
+    for (int r = 0; r < R; ++r) {
+      if (c.frozen[r]) continue;
+      done[r] += 1;
+      dl[r] = h[r];
+      if (dl[r] < tol[r]) converged[r] = 1;
+      if (converged[r] || done[r] >= max_sweeps[r]) c.frozen[r] = 1;
+    }
+  }
+  for (int r = 0; r < R; ++r) {
+    delta[r] = dl[r];
+    c.frozen[r] = 0;
+  }
 }
 
 void do_sweeps(Context& c, int max_sweeps, double tol, int* done, double* delta, int* converged,
                const std::atomic<bool>* cancel) {
-  corner_spectra(c, c.specprev.as<double>());
-  // normalise the reference spectra (delta of this call is discarded)
-  spectra_delta(c.st, c.specprev.as<double>(), c.spec.as<double>(), 4 * c.N, c.chi, c.delta.as<double>());
-  CTM_HIP(hipMemcpyAsync(c.specprev.p, c.spec.p, sizeof(double) * 4 * c.N * c.chi, hipMemcpyDeviceToDevice, c.st));
+  CTM_CHECK(c.R == 1, -1, "do_sweeps: one replica");
+  int d = 0, conv = 0;
   double dl = INFINITY;
-  int it = 0, conv = 0;
-  for (it = 1; it <= max_sweeps; ++it) {
-    if (cancel && cancel->load()) {
-      --it;
-      break;
-    }
-    for (int m = 0; m < 4; ++m) do_move(c, kSweepRot[m]);
-    corner_spectra(c, c.spec.as<double>());
-    spectra_delta(c.st, c.spec.as<double>(), c.specprev.as<double>(), 4 * c.N, c.chi, c.delta.as<double>());
-    CTM_HIP(hipMemcpyAsync(&dl, c.delta.p, sizeof(double), hipMemcpyDeviceToHost, c.st));
-    CTM_HIP(hipStreamSynchronize(c.st));
-    if (dl < tol) { conv = 1; break; }
-  }
-  if (it > max_sweeps) it = max_sweeps;
-  if (done) *done = it;
+  const std::atomic<bool>* cancels[1] = {cancel};
+  do_sweeps_group(c, &max_sweeps, &tol, &d, &dl, &conv, cancel ? cancels : nullptr);
+  if (done) *done = d;
   if (delta) *delta = dl;
   if (converged) *converged = conv;
 }

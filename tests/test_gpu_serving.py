@@ -190,3 +190,42 @@ def test_footprint_bounds_device_memory(lib, D, chi, L):
     print(f"D={D} chi={chi} {L}x{L}: used {used / 2**20:.1f} MiB, footprint {fp / 2**20:.1f} MiB")
     assert used <= fp
     del ctx
+
+
+def test_same_shape_requests_run_as_one_group(lib):
+    """A transverse-field scan at one shape (2x2, D=3, chi=24) plus two other
+    shapes: submitted together, the same-shape requests are admitted as one
+    group (one context, their cuts batched into the same launches) and give
+    the same results as when each runs alone."""
+    hs = [2.6, 2.8, 3.0, 3.2, 3.4]
+    reqs = [dict(A=wl.tfim_request_tensors(h, 3, 2, 2, 0.1, seed=40 + i), h=h, D=3, chi=24, Lx=2, Ly=2)
+            for i, h in enumerate(hs)]
+    reqs += _requests(2, seed=41)
+    alone = []
+    q1 = lib.Queue(64 << 30, 1)
+    for i, r in enumerate(reqs):
+        st, t = _submit(q1, r, i, max_sweeps=8 + i)
+        assert st == B.CTM_OK
+        st, res = q1.wait(t, 120000)
+        assert st == B.CTM_OK, st
+        alone.append((res.energy_per_site, res.sweeps, list(res.mz)))
+    q1.destroy()
+    # one slot: a request of another shape runs first, so that the scan is
+    # pending as a whole when the slot frees up
+    q = lib.Queue(64 << 30, 1)
+    order = [len(hs)] + list(range(len(hs))) + [len(hs) + 1]
+    tickets = {i: _submit(q, reqs[i], i, max_sweeps=8 + i)[1] for i in order}
+    grouped, admits = [], []
+    for i in range(len(reqs)):
+        st, res = q.wait(tickets[i], 120000)
+        assert st == B.CTM_OK, st
+        grouped.append((res.energy_per_site, res.sweeps, list(res.mz)))
+        admits.append(res.t_admit_ns)
+    q.destroy()
+    # the scan shares one admission (one group); different caps per request
+    assert len(set(admits[:len(hs)])) == 1 and admits[len(hs)] < admits[0]
+    for (ea, sa, ma), (eg, sg, mg) in zip(alone, grouped):
+        assert sa == sg
+        assert abs(ea - eg) <= 1e-10
+        assert np.max(np.abs(np.array(ma) - np.array(mg))) <= 1e-10
+    print("bitwise equal:", all(a == g for a, g in zip(alone, grouped)))
