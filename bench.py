@@ -133,6 +133,48 @@ def serving_requests(n, seed=4, rate_hz=None):
     return out
 
 
+def scan_requests(n, D=3, chi=32, L=2, seed=5):
+    """A transverse-field scan at one shape: h evenly over [2.5, 3.5]."""
+    out = []
+    for i in range(n):
+        h = 2.5 + i / max(n - 1, 1)
+        A = wl.tfim_request_tensors(h, D, L, L, 0.1, seed * 1000 + i)
+        out.append(dict(index=i, h=h, D=D, chi=chi, Lx=L, Ly=L, arrival=0.0, A=A, op=wl.tfim_bond(h)))
+    return out
+
+
+def scan_bench(lib, n, max_active, budget_gb, p=16, q=1, tol=1e-10, max_sweeps=40):
+    """Closed-loop throughput of a one-shape scan, grouped (same-shape requests
+    share a context and its launches) and with one request per admission."""
+    out = {"requests": n, "shape": "2x2 D=3 chi=32", "max_active": max_active}
+    for label, mx in (("grouped", max_active), ("one_per_admission", None)):
+        qu = lib.Queue(int(budget_gb * (1 << 30)), max_active)
+        reqs = scan_requests(n)
+        t0 = time.perf_counter()
+        res = []
+        if mx is None:   # submit the next request only when a slot is free: no grouping possible
+            pending = list(reqs)
+            inflight = []
+            while pending or inflight:
+                while pending and len(inflight) < max_active:
+                    r = pending.pop(0)
+                    inflight.append(qu.submit(r["A"], 2, 2, r["D"], r["chi"], r["op"], tol=tol, max_sweeps=max_sweeps,
+                                              rsvd_oversample=p, rsvd_power_iters=q, seed=3)[1])
+                st, rr = qu.wait(inflight.pop(0), -1)
+                res.append(rr)
+        else:
+            tickets = [qu.submit(r["A"], 2, 2, r["D"], r["chi"], r["op"], tol=tol, max_sweeps=max_sweeps,
+                                 rsvd_oversample=p, rsvd_power_iters=q, seed=3)[1] for r in reqs]
+            res = [qu.wait(t, -1)[1] for t in tickets]
+        dt = time.perf_counter() - t0
+        qu.destroy()
+        out[label] = {"solves_per_s": n / dt, "energies": [float(r.energy_per_site) for r in res]}
+        print(f"scan ({label}): {n} done, {dt:.1f} s", file=sys.stderr, flush=True)
+    diff = max(abs(a - b) for a, b in zip(out["grouped"].pop("energies"), out["one_per_admission"].pop("energies")))
+    out["max_energy_diff_grouped_vs_single"] = diff
+    return out
+
+
 def serving_bench(lib, n, max_active, budget_gb, p=16, q=1, tol=1e-10, max_sweeps=40):
     """The mixed TFIM stream through the serving queue: a closed loop (all
     requests at t = 0) gives the capacity; an open loop replays Poisson
@@ -274,6 +316,7 @@ def main():
         out["precisions"] = cmp
     if args.serving:
         out["serving"] = serving_bench(lib, args.serving, args.max_active, args.budget_gb)
+        out["serving_scan"] = scan_bench(lib, 16, args.max_active, args.budget_gb)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, p, q, seed=2)
     print(json.dumps(out), flush=True)
