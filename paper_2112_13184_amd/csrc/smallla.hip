@@ -1,8 +1,9 @@
 // FP64 factorisations of the projector computation, written for one MI355X.
 //
 // * Cholesky QR of a tall n x k panel Y: G = Y^T Y (MFMA GEMM), G (+ shift) =
-//   L L^T in one 1024-thread workgroup with the packed lower triangle in
-//   registers (outer-product form, one barrier per column), R^-1 = L^-T one wave per
+//   L L^T in one 1024-thread workgroup with the matrix in registers, 2-D
+//   cyclic over a 32 x 32 thread grid (outer-product form, one barrier per
+//   column), R^-1 = L^-T one wave per
 //   column, then Y <- Y R^-1 (MFMA GEMM).  The first pass uses the shift of
 //   Fukaya, Kannan, Nakatsukasa, Yamamoto and Yanagisawa (SIAM J. Sci. Comput.
 //   42 (2020) A477), s = 11 (n k + k (k + 1)) u ||Y||_F^2, which keeps the Gram
@@ -24,7 +25,11 @@ namespace ctm {
 namespace {
 
 constexpr int kCholThreads = 1024;
-constexpr int kCholME = (kSmallLAMaxK * (kSmallLAMaxK + 1) / 2 + kCholThreads - 1) / kCholThreads;
+constexpr int kCholT = 32;                                       // threads as a kCholT x kCholT grid
+constexpr int kCholB = (kSmallLAMaxK + kCholT - 1) / kCholT;     // row / column blocks per thread
+static_assert(kCholT * kCholT == kCholThreads, "k_chol: thread grid");
+// Jacobi: columns per block (one wave per pair of a round, 16 blocks at k = 192)
+constexpr int kJacobiMaxBS = 12;
 
 
 __device__ double block_reduce(double v, bool is_max, double* sh) {
@@ -48,18 +53,22 @@ __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 // factors keep the zero).  shifted: add s = shift_scale * trace(G).
 // check_id: flag the problem if the non-zero part of G is not within 0.5 of
 // the identity.  NaN / Inf pivots flag the problem too.
-// The lower triangle lives in registers (entry e of the packed triangle
-// belongs to thread e % 1024); step j broadcasts column j through a
-// double-buffered LDS column, so one barrier per column suffices.
+// The matrix lives in registers, distributed 2-D cyclically: thread
+// (ty, tx) of the 32 x 32 grid holds rows tx + 32 a and columns ty + 32 c.
+// Step j broadcasts column j through a double-buffered LDS column (one
+// barrier per step); each thread then reads its 6 row and 6 column factors
+// and updates at most 36 entries, skipping row and column blocks that lie
+// wholly left of the step.
 __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, int pass, int shifted,
                                                         int check_id, double shift_scale, double drop_rel,
                                                         double* Lout, double* Rout, double* mask, int* flag) {
-  __shared__ double col[2][kSmallLAMaxK];
+  __shared__ double col[2][kCholB * kCholT];
   __shared__ double piv[kSmallLAMaxK];
   __shared__ double red[16];
   __shared__ int bad;
   __shared__ unsigned char dropped[kSmallLAMaxK];
   const int b = blockIdx.x, tid = threadIdx.x;
+  const int tx = tid % kCholT, ty = tid / kCholT;
   const long kk2 = (long)k * k;
   const double* g = G + b * kk2;
   if (tid == 0) bad = 0;
@@ -67,31 +76,26 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   for (int i = tid; i < k; i += blockDim.x) tr += g[i + (long)i * k];
   tr = block_reduce(tr, false, red);
   const double s = shifted ? shift_scale * tr : 0.0;
-  const int T = k * (k + 1) / 2;
-  // entry q of this thread: row i = code >> 8, column l = code & 255; unused
-  // slots carry l = 255, which no step reaches
-  int code[kCholME];
-  double val[kCholME];
+  // val[a][c] = entry (row tx + 32 a, column ty + 32 c); only the lower
+  // triangle is read or written, the rest stays zero
+  double val[kCholB][kCholB];
   double dev = 0.0;
 #pragma unroll
-  for (int q = 0; q < kCholME; ++q) {
-    const int e = tid + q * kCholThreads;
-    code[q] = 255;
-    val[q] = 0.0;
-    if (e < T) {
-      int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-      while (tri(i + 1, 0) <= e) ++i;
-      while (tri(i, 0) > e) --i;
-      const int l = e - tri(i, 0);
-      code[q] = (i << 8) | l;
-      const double v = g[i + (long)l * k];
-      if (check_id) {
-        const double gi = g[i + (long)i * k], gl = g[l + (long)l * k];
-        if (gi > 1e-3 && gl > 1e-3) dev = fmax(dev, fabs(v - (i == l ? 1.0 : 0.0)));
+  for (int a = 0; a < kCholB; ++a)
+#pragma unroll
+    for (int c = 0; c < kCholB; ++c) {
+      const int i = tx + kCholT * a, l = ty + kCholT * c;
+      double v = 0.0;
+      if (i < k && l <= i) {
+        v = g[i + (long)l * k];
+        if (check_id) {
+          const double gi = g[i + (long)i * k], gl = g[l + (long)l * k];
+          if (gi > 1e-3 && gl > 1e-3) dev = fmax(dev, fabs(v - (i == l ? 1.0 : 0.0)));
+        }
+        if (i == l) v += s;
       }
-      val[q] = v + (i == l ? s : 0.0);
+      val[a][c] = v;
     }
-  }
   if (check_id) {
     dev = block_reduce(dev, true, red);
     if (tid == 0 && !(dev <= 0.5)) bad = 2;
@@ -99,9 +103,15 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   double dmax = 0.0;
   for (int j = 0; j < k; ++j) {
     double* cj = col[j & 1];
+    const int jc = j / kCholT;
+    if (ty == j % kCholT) {
 #pragma unroll
-    for (int q = 0; q < kCholME; ++q)
-      if ((code[q] & 255) == j) cj[code[q] >> 8] = val[q];
+      for (int c = 0; c < kCholB; ++c)
+        if (c == jc) {
+#pragma unroll
+          for (int a = 0; a < kCholB; ++a) cj[tx + kCholT * a] = val[a][c];
+        }
+    }
     __syncthreads();
     const double d = cj[j];
     const bool drop = !(d > drop_rel * dmax) || !(d > 0.0) || !isfinite(d);
@@ -113,10 +123,23 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     if (!drop) {
       dmax = fmax(dmax, d);
       const double inv = 1.0 / d;
+      // factors of the entries right of and below the pivot; zero elsewhere
+      double fl[kCholB], fi[kCholB];
 #pragma unroll
-      for (int q = 0; q < kCholME; ++q) {
-        const int l = code[q] & 255;
-        if (l > j && l < 255) val[q] -= cj[code[q] >> 8] * cj[l] * inv;
+      for (int c = 0; c < kCholB; ++c) {
+        const int l = ty + kCholT * c;
+        fl[c] = (l > j && l < k) ? cj[l] * inv : 0.0;
+        const int i = tx + kCholT * c;
+        fi[c] = (i > j && i < k) ? cj[i] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < kCholB; ++c) {
+        if (kCholT * c + kCholT - 1 <= j) continue;      // column block finished
+#pragma unroll
+        for (int a = 0; a < kCholB; ++a) {
+          if (kCholT * a + kCholT - 1 <= j) continue;    // row block finished
+          val[a][c] -= fi[a] * fl[c];
+        }
       }
     }
   }
@@ -131,21 +154,23 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     }
   }
 #pragma unroll
-  for (int q = 0; q < kCholME; ++q) {
-    const int i = code[q] >> 8, l = code[q] & 255;
-    if (l == 255) continue;
-    double v = 0.0, r = 0.0;
-    if (dropped[l]) {
-      v = (i == l) ? 1.0 : 0.0;          // unit column in L, zero row in R
-    } else {
-      // a dependent row i keeps its coefficients on the earlier directions
-      const double sd = sqrt(piv[l]);
-      v = (i == l) ? sd : val[q] / sd;
-      r = v;
+  for (int a = 0; a < kCholB; ++a)
+#pragma unroll
+    for (int c = 0; c < kCholB; ++c) {
+      const int i = tx + kCholT * a, l = ty + kCholT * c;
+      if (i >= k || l > i) continue;
+      double v = 0.0, r = 0.0;
+      if (dropped[l]) {
+        v = (i == l) ? 1.0 : 0.0;          // unit column in L, zero row in R
+      } else {
+        // a dependent row i keeps its coefficients on the earlier directions
+        const double sd = sqrt(piv[l]);
+        v = (i == l) ? sd : val[a][c] / sd;
+        r = v;
+      }
+      Lb[i + (long)l * k] = v;             // L[i][l]
+      Rb[l + (long)i * k] = r;             // R[l][i] = L[i][l]
     }
-    Lb[i + (long)l * k] = v;             // L[i][l]
-    Rb[l + (long)i * k] = r;             // R[l][i] = L[i][l]
-  }
   for (int j = tid; j < k; j += blockDim.x) mask[(long)b * k + j] = dropped[j] ? 0.0 : 1.0;
   // reason code: 10 * pass + 1 (non-finite pivot) or + 2 (not orthonormal)
   if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
@@ -241,11 +266,17 @@ __device__ __forceinline__ int circle(int pos, int round, int m) {
 }
 
 // One tournament round over blocks: workgroup w of problem b orthogonalises
-// the 2*bs columns of its block pair (columns >= k are zero padding), one
-// wave per column pair of each inner round (launched with 64 * bs threads).
-__global__ __launch_bounds__(1024) void k_jacobi_round(double* A, double* J, int k, int nb, int bs, int round,
-                                                       double* off, const int* conv, double tol) {
-  extern __shared__ double sm[];
+// column pairs of its block pair (columns >= k are zero padding), one wave
+// per column pair of each inner step (launched with 64 * bs threads).  In
+// round 0 every block meets another one, so that round runs the full
+// tournament of the 2 bs columns (the pairs inside each block and across);
+// later rounds take only the bs^2 pairs across the two blocks, in bs steps
+// of bs disjoint pairs.  Each column pair is rotated once per sweep.
+__global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, double* J, int k, int nb, int bs,
+                                                                   int round, double* off, const int* conv,
+                                                                   double tol) {
+  __shared__ double sA[2 * kJacobiMaxBS * kSmallLAMaxK];
+  __shared__ double sJ[2 * kJacobiMaxBS * kSmallLAMaxK];
   const int b = blockIdx.y;
   if (conv[b]) return;
   const long kk2 = (long)k * k;
@@ -253,48 +284,52 @@ __global__ __launch_bounds__(1024) void k_jacobi_round(double* A, double* J, int
   double* Jb = J + b * kk2;
   const int pa = circle(blockIdx.x, round, nb), pb = circle(nb - 1 - blockIdx.x, round, nb);
   const int m = 2 * bs;
-  double* As = sm;                 // [m][k]
-  double* Js = sm + (long)m * k;   // [m][k]
   for (long e = threadIdx.x; e < (long)m * k; e += blockDim.x) {
     const int lc = (int)(e / k), r = (int)(e % k);
     const int gc = (lc < bs) ? pa * bs + lc : pb * bs + (lc - bs);
-    As[e] = (gc < k) ? Ab[(long)gc * k + r] : 0.0;
-    Js[e] = (gc < k) ? Jb[(long)gc * k + r] : 0.0;
+    sA[e] = (gc < k) ? Ab[(long)gc * k + r] : 0.0;
+    sJ[e] = (gc < k) ? Jb[(long)gc * k + r] : 0.0;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;   // one wave per pair
+  const int steps = (round == 0) ? m - 1 : bs;
   double offl = 0.0;
-  for (int rr = 0; rr < m - 1; ++rr) {
-    for (int q = wv; q < bs; q += nw) {
-      const int ci = circle(q, rr, m), cj = circle(m - 1 - q, rr, m);
-      double* ai = As + (long)ci * k;
-      double* aj = As + (long)cj * k;
-      double al = 0.0, be = 0.0, ga = 0.0;
+  for (int st = 0; st < steps; ++st) {
+    int ci, cj;
+    if (round == 0) {
+      ci = circle(q, st, m);
+      cj = circle(m - 1 - q, st, m);
+    } else {
+      ci = q;
+      cj = bs + (q + st) % bs;
+    }
+    double* ai = sA + (long)ci * k;
+    double* aj = sA + (long)cj * k;
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int r = lane; r < k; r += 64) {
+      const double x = ai[r], y = aj[r];
+      al += x * x;
+      be += y * y;
+      ga += x * y;
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    const double nrm = sqrt(al * be);
+    if (nrm > 0.0 && fabs(ga) > tol * nrm) {
+      offl = fmax(offl, fabs(ga) / nrm);
+      const double zeta = (be - al) / (2.0 * ga);
+      const double t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+      double* ji = sJ + (long)ci * k;
+      double* jj = sJ + (long)cj * k;
       for (int r = lane; r < k; r += 64) {
         const double x = ai[r], y = aj[r];
-        al += x * x;
-        be += y * y;
-        ga += x * y;
-      }
-      al = wave_sum(al);
-      be = wave_sum(be);
-      ga = wave_sum(ga);
-      const double nrm = sqrt(al * be);
-      if (nrm > 0.0 && fabs(ga) > tol * nrm) {
-        offl = fmax(offl, fabs(ga) / nrm);
-        const double zeta = (be - al) / (2.0 * ga);
-        const double t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        double* ji = Js + (long)ci * k;
-        double* jj = Js + (long)cj * k;
-        for (int r = lane; r < k; r += 64) {
-          const double x = ai[r], y = aj[r];
-          ai[r] = cs * x - sn * y;
-          aj[r] = sn * x + cs * y;
-          const double u = ji[r], v = jj[r];
-          ji[r] = cs * u - sn * v;
-          jj[r] = sn * u + cs * v;
-        }
+        ai[r] = cs * x - sn * y;
+        aj[r] = sn * x + cs * y;
+        const double u = ji[r], v = jj[r];
+        ji[r] = cs * u - sn * v;
+        jj[r] = sn * u + cs * v;
       }
     }
     __syncthreads();
@@ -303,18 +338,18 @@ __global__ __launch_bounds__(1024) void k_jacobi_round(double* A, double* J, int
     const int lc = (int)(e / k), r = (int)(e % k);
     const int gc = (lc < bs) ? pa * bs + lc : pb * bs + (lc - bs);
     if (gc < k) {
-      Ab[(long)gc * k + r] = As[e];
-      Jb[(long)gc * k + r] = Js[e];
+      Ab[(long)gc * k + r] = sA[e];
+      Jb[(long)gc * k + r] = sJ[e];
     }
   }
   // largest relative rotation of this workgroup -> off[b] (positive doubles order like their bits)
-  __shared__ double red[16];
+  __shared__ double red[kJacobiMaxBS];
   offl = wave_max(offl);
-  if (lane == 0) red[wv] = offl;
+  if (lane == 0) red[q] = offl;
   __syncthreads();
   if (threadIdx.x == 0) {
     double mx = red[0];
-    for (int i = 1; i < nw; ++i) mx = fmax(mx, red[i]);
+    for (int i = 1; i < bs; ++i) mx = fmax(mx, red[i]);
     atomicMax(reinterpret_cast<unsigned long long*>(off + b), (unsigned long long)__double_as_longlong(mx));
   }
 }
@@ -369,13 +404,9 @@ void smallla_alloc(SmallLA& s, int kmax, int batch_max, long nmax) {
   CTM_HIP(hipMemset(s.flag.p, 0, sizeof(int) * 256));
 }
 
-static int jacobi_block(int k) { return std::max(1, (k + 31) / 32); }
+static int jacobi_block(int k) { return std::min(kJacobiMaxBS, std::max(1, (k + 15) / 16)); }
 
-bool smallla_fits(const SmallLA& s, int k) {
-  // the Jacobi round stages two blocks of A and of the rotations in LDS
-  const size_t jac = sizeof(double) * 2 * (size_t)(2 * jacobi_block(k)) * k;
-  return k <= kSmallLAMaxK && k <= s.kmax && jac <= 48 * 1024;
-}
+bool smallla_fits(const SmallLA& s, int k) { return k <= kSmallLAMaxK && k <= s.kmax; }
 
 void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, int batch, int passes,
             double* Racc, const GemmWorkspace& ws) {
@@ -430,12 +461,11 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   int* conv = s.flag.as<int>() + 64;
   double* off = s.off.as<double>();
   hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, off, conv);
-  const size_t lds = sizeof(double) * 2 * (size_t)(2 * bs) * k;
   const double tol = 1e-15;
   const int max_sweeps = 14;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < nb - 1; ++r)
-      hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(64 * bs), lds, st, A, J, k, nb, bs, r, off, conv,
+      hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs, r, off, conv,
                          tol);
     hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, batch, tol);
   }
