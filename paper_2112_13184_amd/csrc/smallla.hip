@@ -123,14 +123,21 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     if (!drop) {
       dmax = fmax(dmax, d);
       const double inv = 1.0 / d;
-      // factors of the entries right of and below the pivot; zero elsewhere
+      // factors of the entries right of and below the pivot, zero elsewhere.
+      // All 192 column entries were written (finite unless the problem is
+      // flagged), so the loads need no guard and issue together; the masks
+      // are multipliers so that no load is moved under a branch.
       double fl[kCholB], fi[kCholB];
 #pragma unroll
       for (int c = 0; c < kCholB; ++c) {
-        const int l = ty + kCholT * c;
-        fl[c] = (l > j && l < k) ? cj[l] * inv : 0.0;
-        const int i = tx + kCholT * c;
-        fi[c] = (i > j && i < k) ? cj[i] : 0.0;
+        fl[c] = cj[ty + kCholT * c];
+        fi[c] = cj[tx + kCholT * c];
+      }
+#pragma unroll
+      for (int c = 0; c < kCholB; ++c) {
+        const int l = ty + kCholT * c, i = tx + kCholT * c;
+        fl[c] *= (l > j && l < k) ? inv : 0.0;
+        fi[c] *= (i > j && i < k) ? 1.0 : 0.0;
       }
 #pragma unroll
       for (int c = 0; c < kCholB; ++c) {
@@ -179,9 +186,12 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
 // Rinv = R^-1 for R = L^T upper triangular; one wave per column c.  Column
 // c of R^-1 is found by back substitution from row c up; row i needs column
 // i of L below the diagonal, which does not depend on the solution, so the
-// columns for the next 8 rows are kept in flight in a register ring.
+// columns for the next 16 rows are kept in flight in a register ring (loads
+// unguarded, masked by multiplication).  The reciprocal of L[i][i] stays in
+// the register of the lane that owns row i, so a step waits only on its
+// wave reduction.
 __global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* Rinv) {
-  constexpr int RING = 8;
+  constexpr int RING = 16;
   const int b = blockIdx.y;
   const int lane = threadIdx.x & 63;
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -189,12 +199,20 @@ __global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* R
   const long kk2 = (long)k * k;
   const double* Lb = L + b * kk2;
   double x[3] = {0.0, 0.0, 0.0};     // x[q] = column entry lane + 64 q
+  double rd[3];                      // 1 / L[i][i] for i = lane + 64 q
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = lane + 64 * q;
+    rd[q] = (i <= c) ? 1.0 / Lb[i + (long)i * k] : 0.0;
+  }
   double ring[RING][3];
   auto fetch = [&](int i, double* dst) {
+    const long col = (long)(i < 0 ? 0 : i) * k;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int kx = lane + 64 * q;
-      dst[q] = (i >= 0 && kx > i && kx <= c) ? Lb[kx + (long)i * k] : 0.0;   // R[i][kx] = L[kx][i]
+      const double v = Lb[(kx < k ? kx : k - 1) + col];            // R[i][kx] = L[kx][i]
+      dst[q] = v * ((i >= 0 && kx > i && kx <= c) ? 1.0 : 0.0);
     }
   };
 #pragma unroll
@@ -206,16 +224,14 @@ __global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* R
       if (i < 0) break;
       double lc[3] = {ring[s][0], ring[s][1], ring[s][2]};
       fetch(i - RING, ring[s]);
-      const double dii = Lb[i + (long)i * k];
       double part = 0.0;
 #pragma unroll
       for (int q = 0; q < 3; ++q) part += lc[q] * x[q];
       const double sum = wave_sum(part);
       if ((i & 63) == lane) {
-        const double v = (((i == c) ? 1.0 : 0.0) - sum) / dii;
 #pragma unroll
         for (int q = 0; q < 3; ++q)
-          if ((i >> 6) == q) x[q] = v;
+          if ((i >> 6) == q) x[q] = (((i == c) ? 1.0 : 0.0) - sum) * rd[q];
       }
     }
   }
@@ -315,12 +331,17 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     al = wave_sum(al);
     be = wave_sum(be);
     ga = wave_sum(ga);
-    const double nrm = sqrt(al * be);
-    if (nrm > 0.0 && fabs(ga) > tol * nrm) {
-      offl = fmax(offl, fabs(ga) / nrm);
-      const double zeta = (be - al) / (2.0 * ga);
-      const double t = ((zeta >= 0.0) ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+    // rotate when |ga| > tol sqrt(al be); the angle zeroing the inner product
+    // has tan(2 theta) = 2 ga / (be - al), and with d = be - al,
+    // r = sqrt(d^2 + 4 ga^2), w = sqrt(2 r (r + |d|)) its cosine and sine are
+    // (r + |d|) / w and 2 ga sgn(d) / w (two square roots, one division)
+    const double ab = al * be, g2 = ga * ga;
+    if (g2 > tol * tol * ab) {
+      offl = fmax(offl, g2 / ab);
+      const double dd = be - al, ad = fabs(dd);
+      const double r = sqrt(dd * dd + 4.0 * g2);
+      const double inv = 1.0 / sqrt(2.0 * r * (r + ad));
+      const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
       double* ji = sJ + (long)ci * k;
       double* jj = sJ + (long)cj * k;
       for (int r = lane; r < k; r += 64) {
@@ -342,9 +363,10 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       Jb[(long)gc * k + r] = sJ[e];
     }
   }
-  // largest relative rotation of this workgroup -> off[b] (positive doubles order like their bits)
+  // largest relative inner product of this workgroup -> off[b] (positive
+  // doubles order like their bits); offl holds its square
   __shared__ double red[kJacobiMaxBS];
-  offl = wave_max(offl);
+  offl = sqrt(wave_max(offl));
   if (lane == 0) red[q] = offl;
   __syncthreads();
   if (threadIdx.x == 0) {
