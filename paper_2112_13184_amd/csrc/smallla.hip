@@ -46,6 +46,41 @@ __device__ double block_reduce(double v, bool is_max, double* sh) {
 
 __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 
+// Register blocks of one k_chol thread: row block a, column block c, a >= c.
+constexpr int kCholNB = kCholB * (kCholB + 1) / 2;
+__host__ __device__ constexpr int cblk(int a, int c) { return a * (a + 1) / 2 + c; }
+
+// Column j (in column block JB) -> LDS, by the threads that hold it.
+template <int JB>
+__device__ __forceinline__ void chol_publish(const double (&val)[kCholNB], double* cj, int tx) {
+#pragma unroll
+  for (int a = JB; a < kCholB; ++a) cj[tx + kCholT * a] = val[cblk(a, JB)];
+}
+
+// Rank-one update by the pivot column j (in column block JB): entries right
+// of and below the pivot lose fi * fl, all others see zero factors.  Blocks
+// left of JB are finished and not touched.
+template <int JB>
+__device__ __forceinline__ void chol_update(double (&val)[kCholNB], const double* cj, int j, int k, double inv,
+                                            int tx, int ty) {
+  double fl[kCholB], fi[kCholB];
+#pragma unroll
+  for (int c = JB; c < kCholB; ++c) {
+    fl[c] = cj[ty + kCholT * c];
+    fi[c] = cj[tx + kCholT * c];
+  }
+#pragma unroll
+  for (int c = JB; c < kCholB; ++c) {
+    const int l = ty + kCholT * c, i = tx + kCholT * c;
+    fl[c] *= (l > j && l < k) ? inv : 0.0;
+    fi[c] *= (i > j && i < k) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int a = JB; a < kCholB; ++a)
+#pragma unroll
+    for (int c = JB; c <= a; ++c) val[cblk(a, c)] -= fi[a] * fl[c];
+}
+
 // G_b (k x k, col-major) [+ s I] = L L^T, rank revealing: a pivot below
 // drop_rel times the largest one so far marks its column as dependent
 // (mask 0): the column is taken as zero, L gets a unit diagonal there (so
@@ -53,16 +88,18 @@ __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 // factors keep the zero).  shifted: add s = shift_scale * trace(G).
 // check_id: flag the problem if the non-zero part of G is not within 0.5 of
 // the identity.  NaN / Inf pivots flag the problem too.
-// The matrix lives in registers, distributed 2-D cyclically: thread
-// (ty, tx) of the 32 x 32 grid holds rows tx + 32 a and columns ty + 32 c.
-// Step j broadcasts column j through a double-buffered LDS column (one
-// barrier per step); each thread then reads its 6 row and 6 column factors
-// and updates at most 36 entries, skipping row and column blocks that lie
-// wholly left of the step.
+// The lower triangle lives in registers, distributed 2-D cyclically: thread
+// (ty, tx) of the 32 x 32 grid holds rows tx + 32 a and columns ty + 32 c
+// for the 21 block pairs a >= c.  Step j broadcasts column j through a
+// double-buffered LDS column (one barrier per step); the update is
+// specialised on the block of j, so finished blocks cost nothing.  R is
+// written through an LDS tile, 32 rows of L at a time, so that both outputs
+// are stored along contiguous columns.
 __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, int pass, int shifted,
                                                         int check_id, double shift_scale, double drop_rel,
                                                         double* Lout, double* Rout, double* mask, int* flag) {
   __shared__ double col[2][kCholB * kCholT];
+  __shared__ double tile[kCholT][kCholB * kCholT + 1];
   __shared__ double piv[kSmallLAMaxK];
   __shared__ double red[16];
   __shared__ int bad;
@@ -76,14 +113,14 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   for (int i = tid; i < k; i += blockDim.x) tr += g[i + (long)i * k];
   tr = block_reduce(tr, false, red);
   const double s = shifted ? shift_scale * tr : 0.0;
-  // val[a][c] = entry (row tx + 32 a, column ty + 32 c); only the lower
-  // triangle is read or written, the rest stays zero
-  double val[kCholB][kCholB];
+  // val[cblk(a, c)] = entry (row tx + 32 a, column ty + 32 c); entries above
+  // the diagonal or outside k x k start at zero and are never output
+  double val[kCholNB];
   double dev = 0.0;
 #pragma unroll
   for (int a = 0; a < kCholB; ++a)
 #pragma unroll
-    for (int c = 0; c < kCholB; ++c) {
+    for (int c = 0; c <= a; ++c) {
       const int i = tx + kCholT * a, l = ty + kCholT * c;
       double v = 0.0;
       if (i < k && l <= i) {
@@ -94,7 +131,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
         }
         if (i == l) v += s;
       }
-      val[a][c] = v;
+      val[cblk(a, c)] = v;
     }
   if (check_id) {
     dev = block_reduce(dev, true, red);
@@ -103,14 +140,16 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   double dmax = 0.0;
   for (int j = 0; j < k; ++j) {
     double* cj = col[j & 1];
-    const int jc = j / kCholT;
+    const int jb = j / kCholT;
     if (ty == j % kCholT) {
-#pragma unroll
-      for (int c = 0; c < kCholB; ++c)
-        if (c == jc) {
-#pragma unroll
-          for (int a = 0; a < kCholB; ++a) cj[tx + kCholT * a] = val[a][c];
-        }
+      switch (jb) {
+        case 0: chol_publish<0>(val, cj, tx); break;
+        case 1: chol_publish<1>(val, cj, tx); break;
+        case 2: chol_publish<2>(val, cj, tx); break;
+        case 3: chol_publish<3>(val, cj, tx); break;
+        case 4: chol_publish<4>(val, cj, tx); break;
+        default: chol_publish<5>(val, cj, tx); break;
+      }
     }
     __syncthreads();
     const double d = cj[j];
@@ -123,61 +162,66 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     if (!drop) {
       dmax = fmax(dmax, d);
       const double inv = 1.0 / d;
-      // factors of the entries right of and below the pivot, zero elsewhere.
-      // All 192 column entries were written (finite unless the problem is
-      // flagged), so the loads need no guard and issue together; the masks
-      // are multipliers so that no load is moved under a branch.
-      double fl[kCholB], fi[kCholB];
-#pragma unroll
-      for (int c = 0; c < kCholB; ++c) {
-        fl[c] = cj[ty + kCholT * c];
-        fi[c] = cj[tx + kCholT * c];
-      }
-#pragma unroll
-      for (int c = 0; c < kCholB; ++c) {
-        const int l = ty + kCholT * c, i = tx + kCholT * c;
-        fl[c] *= (l > j && l < k) ? inv : 0.0;
-        fi[c] *= (i > j && i < k) ? 1.0 : 0.0;
-      }
-#pragma unroll
-      for (int c = 0; c < kCholB; ++c) {
-        if (kCholT * c + kCholT - 1 <= j) continue;      // column block finished
-#pragma unroll
-        for (int a = 0; a < kCholB; ++a) {
-          if (kCholT * a + kCholT - 1 <= j) continue;    // row block finished
-          val[a][c] -= fi[a] * fl[c];
-        }
+      switch (jb) {
+        case 0: chol_update<0>(val, cj, j, k, inv, tx, ty); break;
+        case 1: chol_update<1>(val, cj, j, k, inv, tx, ty); break;
+        case 2: chol_update<2>(val, cj, j, k, inv, tx, ty); break;
+        case 3: chol_update<3>(val, cj, j, k, inv, tx, ty); break;
+        case 4: chol_update<4>(val, cj, j, k, inv, tx, ty); break;
+        default: chol_update<5>(val, cj, j, k, inv, tx, ty); break;
       }
     }
   }
   __syncthreads();
   double* Lb = Lout + b * kk2;
   double* Rb = Rout + b * kk2;
-  for (long e = tid; e < kk2; e += blockDim.x) {   // strictly upper part of L / lower part of R
-    const int i = (int)(e % k), l = (int)(e / k);
-    if (i < l) {
-      Lb[e] = 0.0;
-      Rb[l + (long)i * k] = 0.0;
-    }
+  // scale factors of this thread's columns
+  double sd[kCholB];
+  bool dr[kCholB];
+#pragma unroll
+  for (int c = 0; c < kCholB; ++c) {
+    const int l = ty + kCholT * c;
+    dr[c] = l < k ? dropped[l] != 0 : true;
+    sd[c] = (l < k && !dr[c]) ? sqrt(piv[l]) : 1.0;
   }
+  // L: strictly upper part zero; lower part scaled, unit column where dropped
 #pragma unroll
   for (int a = 0; a < kCholB; ++a)
 #pragma unroll
     for (int c = 0; c < kCholB; ++c) {
       const int i = tx + kCholT * a, l = ty + kCholT * c;
-      if (i >= k || l > i) continue;
-      double v = 0.0, r = 0.0;
-      if (dropped[l]) {
-        v = (i == l) ? 1.0 : 0.0;          // unit column in L, zero row in R
-      } else {
+      if (i >= k || l >= k) continue;
+      double v = 0.0;
+      if (c <= a && l <= i) {
+        if (dr[c]) v = (i == l) ? 1.0 : 0.0;
         // a dependent row i keeps its coefficients on the earlier directions
-        const double sd = sqrt(piv[l]);
-        v = (i == l) ? sd : val[a][c] / sd;
-        r = v;
+        else v = (i == l) ? sd[c] : val[cblk(a, c)] / sd[c];
       }
       Lb[i + (long)l * k] = v;             // L[i][l]
-      Rb[l + (long)i * k] = r;             // R[l][i] = L[i][l]
     }
+  // R = L^T with zero rows where dropped: rows 32 a .. 32 a + 31 of L go
+  // through the tile and out as columns of R
+#pragma unroll
+  for (int a = 0; a < kCholB; ++a) {
+    const int i = tx + kCholT * a;
+#pragma unroll
+    for (int c = 0; c < kCholB; ++c) {
+      const int l = ty + kCholT * c;
+      double r = 0.0;
+      if (c <= a && i < k && l <= i && !dr[c]) r = (i == l) ? sd[c] : val[cblk(a, c)] / sd[c];
+      tile[tx][l] = r;
+    }
+    __syncthreads();
+    const int ri = kCholT * a + ty;        // column of R = row of L
+    if (ri < k) {
+#pragma unroll
+      for (int m = 0; m < kCholB; ++m) {
+        const int l = tx + kCholT * m;
+        if (l < k) Rb[l + (long)ri * k] = tile[ty][l];   // R[l][ri] = L[ri][l]
+      }
+    }
+    __syncthreads();
+  }
   for (int j = tid; j < k; j += blockDim.x) mask[(long)b * k + j] = dropped[j] ? 0.0 : 1.0;
   // reason code: 10 * pass + 1 (non-finite pivot) or + 2 (not orthonormal)
   if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
