@@ -53,7 +53,7 @@ __device__ __forceinline__ void xcd_remap(int& tile, int& split, int& b) {
 }
 
 template <int BM, int BN, int WAVES_M, bool A_KC, bool B_KC>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(KArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_f64_kernel(KArgs g) {
   constexpr int BK = 16;
   constexpr int LDK = BK + 1;
   constexpr int WAVES_N = 4 / WAVES_M;
@@ -517,11 +517,25 @@ __global__ __launch_bounds__(256) void k_gemm_dot(KArgs g) {
 // Choose the split of K so that a small output grid still fills the GPU.
 // `tiles` counts the tiles of one problem of a batch: the split (and so the
 // summation order) of a problem does not depend on how many are batched.
+// Among the splits giving at least 512 workgroups (K chunks of at least 256),
+// take the one whose grid comes closest to whole rounds of 1024 workgroups
+// (256 CUs x 4 resident), the smaller split on near ties.
 int choose_splits(long tiles, int K) {
-  const long target = 512;    // ~2 workgroups per CU on 256 CUs, per problem
-  if (tiles >= target / 2) return 1;
-  int s = (int)std::min<long>((target + tiles - 1) / tiles, (long)K / 256);
-  return std::max(1, std::min(s, 16));
+  constexpr long kRound = 1024, kMin = 512;
+  if (tiles >= kMin / 2) return 1;
+  const int smax = (int)std::max<long>(1, std::min<long>(16, (long)K / 256));
+  int best = 1;
+  double best_fill = 0.0;
+  for (int s = 1; s <= smax; ++s) {
+    const long wg = tiles * s;
+    if (wg < kMin && s < smax) continue;
+    const double fill = (double)wg / (double)(((wg + kRound - 1) / kRound) * kRound);
+    if (fill > best_fill + 0.03) {
+      best = s;
+      best_fill = fill;
+    }
+  }
+  return best;
 }
 
 }  // namespace

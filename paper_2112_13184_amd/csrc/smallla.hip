@@ -30,6 +30,7 @@ constexpr int kCholB = (kSmallLAMaxK + kCholT - 1) / kCholT;     // row / column
 static_assert(kCholT * kCholT == kCholThreads, "k_chol: thread grid");
 // Jacobi: columns per block (one wave per pair of a round, 16 blocks at k = 192)
 constexpr int kJacobiMaxBS = 12;
+constexpr int kJacobiRows = (kSmallLAMaxK + 63) / 64;   // rows per lane
 
 
 __device__ double block_reduce(double v, bool is_max, double* sh) {
@@ -365,12 +366,25 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     }
     double* ai = sA + (long)ci * k;
     double* aj = sA + (long)cj * k;
+    double* ji = sJ + (long)ci * k;
+    double* jj = sJ + (long)cj * k;
+    // both columns and their rotation accumulators in registers (rows lane + 64 t)
+    double x[kJacobiRows], y[kJacobiRows], u[kJacobiRows], v[kJacobiRows];
+#pragma unroll
+    for (int t = 0; t < kJacobiRows; ++t) {
+      const int r = lane + 64 * t;
+      const bool ok = r < k;
+      x[t] = ok ? ai[r] : 0.0;
+      y[t] = ok ? aj[r] : 0.0;
+      u[t] = ok ? ji[r] : 0.0;
+      v[t] = ok ? jj[r] : 0.0;
+    }
     double al = 0.0, be = 0.0, ga = 0.0;
-    for (int r = lane; r < k; r += 64) {
-      const double x = ai[r], y = aj[r];
-      al += x * x;
-      be += y * y;
-      ga += x * y;
+#pragma unroll
+    for (int t = 0; t < kJacobiRows; ++t) {
+      al += x[t] * x[t];
+      be += y[t] * y[t];
+      ga += x[t] * y[t];
     }
     al = wave_sum(al);
     be = wave_sum(be);
@@ -386,15 +400,15 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       const double r = sqrt(dd * dd + 4.0 * g2);
       const double inv = 1.0 / sqrt(2.0 * r * (r + ad));
       const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
-      double* ji = sJ + (long)ci * k;
-      double* jj = sJ + (long)cj * k;
-      for (int r = lane; r < k; r += 64) {
-        const double x = ai[r], y = aj[r];
-        ai[r] = cs * x - sn * y;
-        aj[r] = sn * x + cs * y;
-        const double u = ji[r], v = jj[r];
-        ji[r] = cs * u - sn * v;
-        jj[r] = sn * u + cs * v;
+#pragma unroll
+      for (int t = 0; t < kJacobiRows; ++t) {
+        const int row = lane + 64 * t;
+        if (row < k) {
+          ai[row] = cs * x[t] - sn * y[t];
+          aj[row] = sn * x[t] + cs * y[t];
+          ji[row] = cs * u[t] - sn * v[t];
+          jj[row] = sn * u[t] + cs * v[t];
+        }
       }
     }
     __syncthreads();
