@@ -52,7 +52,12 @@ __device__ __forceinline__ void xcd_remap(int& tile, int& split, int& b) {
   b = (int)(id / (nx * ny));
 }
 
-template <int BM, int BN, int WAVES_M, bool A_KC, bool B_KC>
+// TBL: some operand index goes through an offset table.  Without tables a
+// k-tile is loaded from one uniform base per operand plus per-thread 32-bit
+// offsets: rows and columns past the edge are clamped to the last valid one
+// (their products land in outputs that are not stored), so only a partial
+// last k-tile needs a guard, on k.
+template <int BM, int BN, int WAVES_M, bool A_KC, bool B_KC, bool TBL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gemm_f64_kernel(KArgs g) {
   constexpr int BK = 16;
   constexpr int LDK = BK + 1;
@@ -104,9 +109,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
     b_cok[j] = n < g.N;
     b_coff[j] = b_cok[j] ? off0(g.tb1, g.sb1, n) : 0;
   }
+  // table-free offsets within a k-tile (edge rows / columns clamped)
+  int a_off[EA], b_off[EB];
+  if (!TBL) {
+#pragma unroll
+    for (int j = 0; j < EA; ++j)
+      a_off[j] = (int)((long)min(m0 + a_r[j], g.M - 1) * g.sa0 + (long)a_k[j] * g.sa1);
+#pragma unroll
+    for (int j = 0; j < EB; ++j)
+      b_off[j] = (int)((long)min(n0 + b_c[j], g.N - 1) * g.sb1 + (long)b_k[j] * g.sb0);
+  }
 
   double ra[EA], rb[EB];
   auto load_tile = [&](int k0) {
+    if (!TBL) {
+      const double* Ak = A + (long)k0 * g.sa1;
+      const double* Bk = B + (long)k0 * g.sb0;
+      if (k0 + BK <= ke) {
+#pragma unroll
+        for (int j = 0; j < EA; ++j) ra[j] = Ak[a_off[j]];
+#pragma unroll
+        for (int j = 0; j < EB; ++j) rb[j] = Bk[b_off[j]];
+      } else {
+#pragma unroll
+        for (int j = 0; j < EA; ++j) ra[j] = (k0 + a_k[j] < ke) ? Ak[a_off[j]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < EB; ++j) rb[j] = (k0 + b_k[j] < ke) ? Bk[b_off[j]] : 0.0;
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < EA; ++j) {
       int k = k0 + a_k[j];
@@ -199,16 +230,30 @@ __global__ void splitk_reduce(KArgs g) {
   }
 }
 
+template <int BM, int BN, int WAVES_M, bool TBL>
+void launch_f64_t(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
+  if (a_kc && b_kc)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, true, true, TBL>), grid, dim3(256), 0, st, g);
+  else if (a_kc && !b_kc)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, true, false, TBL>), grid, dim3(256), 0, st, g);
+  else if (!a_kc && b_kc)
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, false, true, TBL>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, false, false, TBL>), grid, dim3(256), 0, st, g);
+}
+
+// The table-free kernels take 32-bit offsets within a tile (k-tiles of at
+// most 32).
+bool needs_tables(const KArgs& g) {
+  constexpr long kMaxOff = 0x7fffffffL;
+  return g.ta0 || g.ta1 || g.tb0 || g.tb1 || g.sa0 < 0 || g.sa1 < 0 || g.sb0 < 0 || g.sb1 < 0 ||
+         (long)g.M * g.sa0 + 32L * g.sa1 > kMaxOff || (long)g.N * g.sb1 + 32L * g.sb0 > kMaxOff;
+}
+
 template <int BM, int BN, int WAVES_M>
 void launch_f64(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
-  if (a_kc && b_kc)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, true, true>), grid, dim3(256), 0, st, g);
-  else if (a_kc && !b_kc)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, true, false>), grid, dim3(256), 0, st, g);
-  else if (!a_kc && b_kc)
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, false, true>), grid, dim3(256), 0, st, g);
-  else
-    hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, false, false>), grid, dim3(256), 0, st, g);
+  if (needs_tables(g)) launch_f64_t<BM, BN, WAVES_M, true>(st, g, a_kc, b_kc, grid);
+  else                 launch_f64_t<BM, BN, WAVES_M, false>(st, g, a_kc, b_kc, grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -243,7 +288,7 @@ __device__ __forceinline__ double f16_scale(unsigned mbits) {
   return ldexp(1.0, 14 - (ilogbf(m) + 1));
 }
 
-template <int KIND, int BM, int BN, int WAVES_M, bool A_KC, bool B_KC>
+template <int KIND, int BM, int BN, int WAVES_M, bool A_KC, bool B_KC, bool TBL>
 __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   typedef typename LpStore<KIND>::T T;
   constexpr int BK = 32;
@@ -300,9 +345,35 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
     b_cok[j] = n < g.N;
     b_coff[j] = b_cok[j] ? off0(g.tb1, g.sb1, n) : 0;
   }
+  // table-free offsets within a k-tile (edge rows / columns clamped)
+  int a_off[EA], b_off[EB];
+  if (!TBL) {
+#pragma unroll
+    for (int j = 0; j < EA; ++j)
+      a_off[j] = (int)((long)min(m0 + a_r[j], g.M - 1) * g.sa0 + (long)a_k[j] * g.sa1);
+#pragma unroll
+    for (int j = 0; j < EB; ++j)
+      b_off[j] = (int)((long)min(n0 + b_c[j], g.N - 1) * g.sb1 + (long)b_k[j] * g.sb0);
+  }
 
   double ra[EA], rb[EB];
   auto load_tile = [&](int k0) {
+    if (!TBL) {
+      const double* Ak = A + (long)k0 * g.sa1;
+      const double* Bk = B + (long)k0 * g.sb0;
+      if (k0 + BK <= ke) {
+#pragma unroll
+        for (int j = 0; j < EA; ++j) ra[j] = Ak[a_off[j]];
+#pragma unroll
+        for (int j = 0; j < EB; ++j) rb[j] = Bk[b_off[j]];
+      } else {
+#pragma unroll
+        for (int j = 0; j < EA; ++j) ra[j] = (k0 + a_k[j] < ke) ? Ak[a_off[j]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < EB; ++j) rb[j] = (k0 + b_k[j] < ke) ? Bk[b_off[j]] : 0.0;
+      }
+      return;
+    }
 #pragma unroll
     for (int j = 0; j < EA; ++j) {
       int k = k0 + a_k[j];
@@ -467,16 +538,22 @@ __global__ void k_operand_amax(const double* P, long s0, long s1, const int* t0,
   }
 }
 
+template <int KIND, int BM, int BN, int WAVES_M, bool TBL>
+void launch_lp_t(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
+  if (a_kc && b_kc)
+    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, true, true, TBL>), grid, dim3(256), 0, st, g);
+  else if (a_kc && !b_kc)
+    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, true, false, TBL>), grid, dim3(256), 0, st, g);
+  else if (!a_kc && b_kc)
+    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, false, true, TBL>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, false, false, TBL>), grid, dim3(256), 0, st, g);
+}
+
 template <int KIND, int BM, int BN, int WAVES_M>
 void launch_lp(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
-  if (a_kc && b_kc)
-    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, true, true>), grid, dim3(256), 0, st, g);
-  else if (a_kc && !b_kc)
-    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, true, false>), grid, dim3(256), 0, st, g);
-  else if (!a_kc && b_kc)
-    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, false, true>), grid, dim3(256), 0, st, g);
-  else
-    hipLaunchKernelGGL((gemm_lp_kernel<KIND, BM, BN, WAVES_M, false, false>), grid, dim3(256), 0, st, g);
+  if (needs_tables(g)) launch_lp_t<KIND, BM, BN, WAVES_M, true>(st, g, a_kc, b_kc, grid);
+  else                 launch_lp_t<KIND, BM, BN, WAVES_M, false>(st, g, a_kc, b_kc, grid);
 }
 
 template <int BM, int BN, int WAVES_M>
