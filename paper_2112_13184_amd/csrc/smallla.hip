@@ -20,6 +20,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 namespace ctm {
 namespace {
@@ -300,7 +302,7 @@ __global__ void k_copy_panels(const double* src, long sstride, double* dst, long
 // ---------------------------------------------------------------------------
 // block one-sided Jacobi
 // ---------------------------------------------------------------------------
-__global__ void k_jacobi_init(double* J, int k, double* off, int* conv) {
+__global__ void k_jacobi_init(double* J, int k, double* off, int* conv, int* nsweep) {
   const int b = blockIdx.y;
   const long kk2 = (long)k * k;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < kk2; e += (long)gridDim.x * blockDim.x)
@@ -308,13 +310,16 @@ __global__ void k_jacobi_init(double* J, int k, double* off, int* conv) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     off[b] = 0.0;
     conv[b] = 0;
+    nsweep[b] = 0;
   }
 }
 
-// After a sweep: converged if no pair needed a rotation above tol.
-__global__ void k_jacobi_sweep_end(double* off, int* conv, int batch, double tol) {
+// After a sweep: converged if no pair needed a rotation above tol; nsweep
+// counts the sweeps that ran.
+__global__ void k_jacobi_sweep_end(double* off, int* conv, int* nsweep, int batch, double tol) {
   const int b = threadIdx.x;
   if (b < batch) {
+    if (!conv[b]) ++nsweep[b];
     if (off[b] <= tol) conv[b] = 1;
     off[b] = 0.0;
   }
@@ -345,14 +350,33 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
   double* Jb = J + b * kk2;
   const int pa = circle(blockIdx.x, round, nb), pb = circle(nb - 1 - blockIdx.x, round, nb);
   const int m = 2 * bs;
-  for (long e = threadIdx.x; e < (long)m * k; e += blockDim.x) {
-    const int lc = (int)(e / k), r = (int)(e % k);
-    const int gc = (lc < bs) ? pa * bs + lc : pb * bs + (lc - bs);
-    sA[e] = (gc < k) ? Ab[(long)gc * k + r] : 0.0;
-    sJ[e] = (gc < k) ? Jb[(long)gc * k + r] : 0.0;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;   // one wave per pair
+  // wave q stages local columns q (block pa) and bs + q (block pb): all
+  // global loads first, then the LDS stores
+  {
+    const int gcol[2] = {pa * bs + q, pb * bs + q};
+    double va[2][kJacobiRows], vj[2][kJacobiRows];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int t = 0; t < kJacobiRows; ++t) {
+        const int r = lane + 64 * t;
+        const bool ok = gcol[h] < k && r < k;
+        va[h][t] = ok ? Ab[(long)gcol[h] * k + r] : 0.0;
+        vj[h][t] = ok ? Jb[(long)gcol[h] * k + r] : 0.0;
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int t = 0; t < kJacobiRows; ++t) {
+        const int r = lane + 64 * t;
+        if (r < k) {
+          sA[(h * bs + q) * k + r] = va[h][t];
+          sJ[(h * bs + q) * k + r] = vj[h][t];
+        }
+      }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;   // one wave per pair
   const int steps = (round == 0) ? m - 1 : bs;
   double offl = 0.0;
   for (int st = 0; st < steps; ++st) {
@@ -370,14 +394,17 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     double* jj = sJ + (long)cj * k;
     // both columns and their rotation accumulators in registers (rows lane + 64 t)
     double x[kJacobiRows], y[kJacobiRows], u[kJacobiRows], v[kJacobiRows];
+    // reads past row k stay inside the staging arrays (columns are k apart)
+    // and are replaced by zeros after the load, so no load is predicated
 #pragma unroll
     for (int t = 0; t < kJacobiRows; ++t) {
       const int r = lane + 64 * t;
       const bool ok = r < k;
-      x[t] = ok ? ai[r] : 0.0;
-      y[t] = ok ? aj[r] : 0.0;
-      u[t] = ok ? ji[r] : 0.0;
-      v[t] = ok ? jj[r] : 0.0;
+      const double xa = ai[r], ya = aj[r], ua = ji[r], va = jj[r];
+      x[t] = ok ? xa : 0.0;
+      y[t] = ok ? ya : 0.0;
+      u[t] = ok ? ua : 0.0;
+      v[t] = ok ? va : 0.0;
     }
     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -413,12 +440,18 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     }
     __syncthreads();
   }
-  for (long e = threadIdx.x; e < (long)m * k; e += blockDim.x) {
-    const int lc = (int)(e / k), r = (int)(e % k);
-    const int gc = (lc < bs) ? pa * bs + lc : pb * bs + (lc - bs);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int gc = (h == 0 ? pa : pb) * bs + q;
     if (gc < k) {
-      Ab[(long)gc * k + r] = sA[e];
-      Jb[(long)gc * k + r] = sJ[e];
+#pragma unroll
+      for (int t = 0; t < kJacobiRows; ++t) {
+        const int r = lane + 64 * t;
+        if (r < k) {
+          Ab[(long)gc * k + r] = sA[(h * bs + q) * k + r];
+          Jb[(long)gc * k + r] = sJ[(h * bs + q) * k + r];
+        }
+      }
     }
   }
   // largest relative inner product of this workgroup -> off[b] (positive
@@ -539,19 +572,30 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   if (nb < 2) nb = 2;
   double* J = s.J.as<double>();
   int* conv = s.flag.as<int>() + 64;
+  int* nsweep = s.flag.as<int>() + 192;
   double* off = s.off.as<double>();
-  hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, off, conv);
+  hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, off, conv, nsweep);
   const double tol = 1e-15;
   const int max_sweeps = 14;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < nb - 1; ++r)
       hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs, r, off, conv,
                          tol);
-    hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, batch, tol);
+    hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, tol);
   }
   CTM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, sstride, Y);
   CTM_HIP(hipGetLastError());
+  static const bool debug = getenv("CTM_DEBUG") != nullptr;
+  if (debug) {
+    int h[2][64];
+    CTM_HIP(hipMemcpyAsync(h[0], nsweep, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    CTM_HIP(hipMemcpyAsync(h[1], conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    CTM_HIP(hipStreamSynchronize(st));
+    fprintf(stderr, "[ctm] jacobi k=%d:", k);
+    for (int b = 0; b < batch; ++b) fprintf(stderr, " %d%s", h[0][b], h[1][b] ? "" : "(not converged)");
+    fprintf(stderr, "\n");
+  }
 }
 
 }  // namespace ctm
