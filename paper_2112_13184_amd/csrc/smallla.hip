@@ -314,7 +314,7 @@ __global__ void k_jacobi_init(double* J, int k, double* off, int* conv, int* nsw
   }
 }
 
-// After a sweep: converged if no pair needed a rotation above tol; nsweep
+// After a sweep: converged if no pair needed a rotation (off = 0); nsweep
 // counts the sweeps that ran.
 __global__ void k_jacobi_sweep_end(double* off, int* conv, int* nsweep, int batch, double tol) {
   const int b = threadIdx.x;
@@ -326,9 +326,25 @@ __global__ void k_jacobi_sweep_end(double* off, int* conv, int* nsweep, int batc
 }
 
 __device__ __forceinline__ int circle(int pos, int round, int m) {
-  // position pos in round `round` of a round-robin tournament of m (even) players
+  // position pos in round `round` (< m - 1) of a round-robin tournament of m
+  // (even) players, pos < m
   if (pos == 0) return 0;
-  return ((pos - 1 + round) % (m - 1)) + 1;
+  int t = pos - 1 + round;
+  if (t >= m - 1) t -= m - 1;
+  return t + 1;
+}
+
+// 1 / sqrt(x) for normal or subnormal x > 0: the hardware estimate (about 23
+// correct bits) and two Newton steps y += y (1 - x y^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double h = x * y;
+    const double e = fma(-h, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
 }
 
 // One tournament round over blocks: workgroup w of problem b orthogonalises
@@ -419,13 +435,14 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     // rotate when |ga| > tol sqrt(al be); the angle zeroing the inner product
     // has tan(2 theta) = 2 ga / (be - al), and with d = be - al,
     // r = sqrt(d^2 + 4 ga^2), w = sqrt(2 r (r + |d|)) its cosine and sine are
-    // (r + |d|) / w and 2 ga sgn(d) / w (two square roots, one division)
+    // (r + |d|) / w and 2 ga sgn(d) / w: two reciprocal square roots
     const double ab = al * be, g2 = ga * ga;
     if (g2 > tol * tol * ab) {
-      offl = fmax(offl, g2 / ab);
+      offl = 1.0;                                   // some pair was rotated
       const double dd = be - al, ad = fabs(dd);
-      const double r = sqrt(dd * dd + 4.0 * g2);
-      const double inv = 1.0 / sqrt(2.0 * r * (r + ad));
+      const double X = dd * dd + 4.0 * g2;
+      const double r = X * rsqrt_nr(X);
+      const double inv = rsqrt_nr(2.0 * r * (r + ad));
       const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
 #pragma unroll
       for (int t = 0; t < kJacobiRows; ++t) {
@@ -454,10 +471,10 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       }
     }
   }
-  // largest relative inner product of this workgroup -> off[b] (positive
-  // doubles order like their bits); offl holds its square
+  // 1 if this workgroup rotated a pair (some inner product was above the
+  // tolerance), else 0 -> off[b] (positive doubles order like their bits)
   __shared__ double red[kJacobiMaxBS];
-  offl = sqrt(wave_max(offl));
+  offl = wave_max(offl);
   if (lane == 0) red[q] = offl;
   __syncthreads();
   if (threadIdx.x == 0) {
