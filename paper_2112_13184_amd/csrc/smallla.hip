@@ -549,7 +549,13 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
   double* R = s.R.as<double>();
   double* Ri = s.Rinv.as<double>();
   double* tmp = s.tmp.as<double>();
+  double* Rtmp = s.Rtmp.as<double>();
   for (int pass = 0; pass < passes; ++pass) {
+    // the accumulated factor alternates between Racc and Rtmp so that the
+    // last pass leaves it in Racc; the first pass writes its R there directly
+    double* rdst = ((passes - 1 - pass) % 2 == 0) ? Racc : Rtmp;
+    double* rsrc = (rdst == Racc) ? Rtmp : Racc;
+    double* rout = (Racc && pass == 0) ? rdst : R;
     // G = Y^T Y
     gemm(st, GemmType::F64, k, k, n, 1.0, rowmajor(Y, n, ystride), colmajor(Y, n, ystride), 0.0,
          out_colmajor(G, k, kk2), batch, ws);
@@ -559,7 +565,7 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
     // from the third pass on.
     hipLaunchKernelGGL(k_chol, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass, pass == 0 ? 1 : 0,
                        pass >= 2 ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14,
-                       L, R, s.mask.as<double>(), s.flag.as<int>());
+                       L, rout, s.mask.as<double>(), s.flag.as<int>());
     CTM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_trinv, dim3((k + 3) / 4, batch), dim3(256), 0, st, L, k, Ri);
     CTM_HIP(hipGetLastError());
@@ -568,15 +574,9 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
     hipLaunchKernelGGL(k_copy_panels, dim3(256, batch), dim3(256), 0, st, tmp, (long)n * k, Y, ystride, n, k,
                        s.mask.as<double>());
     CTM_HIP(hipGetLastError());
-    if (Racc) {
-      if (pass == 0) {
-        CTM_HIP(hipMemcpyAsync(Racc, R, sizeof(double) * kk2 * batch, hipMemcpyDeviceToDevice, st));
-      } else {
-        gemm(st, GemmType::F64, k, k, k, 1.0, colmajor(R, k, kk2), colmajor(Racc, k, kk2), 0.0,
-             out_colmajor(s.Rtmp.p, k, kk2), batch, ws);
-        CTM_HIP(hipMemcpyAsync(Racc, s.Rtmp.p, sizeof(double) * kk2 * batch, hipMemcpyDeviceToDevice, st));
-      }
-    }
+    if (Racc && pass > 0)
+      gemm(st, GemmType::F64, k, k, k, 1.0, colmajor(R, k, kk2), colmajor(rsrc, k, kk2), 0.0,
+           out_colmajor(rdst, k, kk2), batch, ws);
   }
 }
 
@@ -593,14 +593,29 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   double* off = s.off.as<double>();
   hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, off, conv, nsweep);
   const double tol = 1e-15;
-  const int max_sweeps = 14;
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    for (int r = 0; r < nb - 1; ++r)
-      hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs, r, off, conv,
-                         tol);
-    hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, tol);
+  // at most 14 sweeps; about 9 reach the tolerance, so the convergence flags
+  // are read back after 7 sweeps and then every 2, rather than launching the
+  // rounds of sweeps that would return at once
+  const int max_sweeps = 14, first = 7, more = 2;
+  auto sweeps = [&](int count) {
+    for (int sw = 0; sw < count; ++sw) {
+      for (int r = 0; r < nb - 1; ++r)
+        hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs, r, off,
+                           conv, tol);
+      hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, tol);
+    }
+    CTM_HIP(hipGetLastError());
+  };
+  sweeps(first);
+  for (int done = first; done < max_sweeps; done += more) {
+    int hconv[64];
+    CTM_HIP(hipMemcpyAsync(hconv, conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    CTM_HIP(hipStreamSynchronize(st));
+    bool all = true;
+    for (int b = 0; b < batch; ++b) all = all && hconv[b] != 0;
+    if (all) break;
+    sweeps(std::min(more, max_sweeps - done));
   }
-  CTM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, sstride, Y);
   CTM_HIP(hipGetLastError());
   static const bool debug = getenv("CTM_DEBUG") != nullptr;

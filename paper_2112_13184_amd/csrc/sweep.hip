@@ -706,6 +706,7 @@ void do_move(Context& c, int rot) {
   const int chi = c.chi, n = c.n, Db = c.Db;
   const long cc = (long)chi * chi, tt = cc * Db;
   const int kc1 = (0 + rot) % 4, kt1 = (0 + rot) % 4, kt3 = (2 + rot) % 4, kt4 = (3 + rot) % 4, kc4 = (3 + rot) % 4;
+  const bool direct = Lxv > 1;
   for (int x = 0; x < Lxv; ++x) {
     column_projectors(c, rot, x, Lyv);
     std::vector<std::array<int, 2>> newdC1(c.R * Lyv), newdT4(c.R * Lyv), newdC4(c.R * Lyv);
@@ -719,9 +720,12 @@ void do_move(Context& c, int rot) {
         double* PT_dn = c.PT.as<double>() + (long)sl * n * chi;
         double* P3_up = c.P3.as<double>() + (long)up * n * chi;
         swap_last2(c.st, c.PT.as<double>() + (long)up * n * chi, P3_up, chi, Db, chi);
-        double* C1n = c.newC1.as<double>() + sl * cc;
-        double* C4n = c.newC4.as<double>() + sl * cc;
-        double* T4n = c.newT4.as<double>() + sl * tt;
+        // the new tensors go to column x + 1; with one column they replace
+        // tensors other cuts still read, so they are staged first
+        const int t = r * c.N + view_site(c, rot, x + 1, y);
+        double* C1n = direct ? c.C(t, kc1) : c.newC1.as<double>() + sl * cc;
+        double* C4n = direct ? c.C(t, kc4) : c.newC4.as<double>() + sl * cc;
+        double* T4n = direct ? c.Ta(t, kt4) : c.newT4.as<double>() + sl * tt;
         // C1' = (C1 T1) Pt_up: X1p[c2][(t4, u)] then times Pt
         mm(c, PhaseTimer::OTHER, chi, Db, chi, colmajor(c.C(s, kc1), chi), rowmajor(c.Ta(s, kt1), n, Db),
            out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
@@ -746,12 +750,14 @@ void do_move(Context& c, int rot) {
       if (c.frozen[r]) continue;
       for (int y = 0; y < Lyv; ++y) {
         const int t = r * c.N + view_site(c, rot, x + 1, y), sl = c.cut_slot[r * Lyv + y];
-        CTM_HIP(hipMemcpyAsync(c.C(t, kc1), c.newC1.as<double>() + sl * cc, cc * sizeof(double),
-                               hipMemcpyDeviceToDevice, c.st));
-        CTM_HIP(hipMemcpyAsync(c.C(t, kc4), c.newC4.as<double>() + sl * cc, cc * sizeof(double),
-                               hipMemcpyDeviceToDevice, c.st));
-        CTM_HIP(hipMemcpyAsync(c.Ta(t, kt4), c.newT4.as<double>() + sl * tt, tt * sizeof(double),
-                               hipMemcpyDeviceToDevice, c.st));
+        if (!direct) {
+          CTM_HIP(hipMemcpyAsync(c.C(t, kc1), c.newC1.as<double>() + sl * cc, cc * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c.st));
+          CTM_HIP(hipMemcpyAsync(c.C(t, kc4), c.newC4.as<double>() + sl * cc, cc * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c.st));
+          CTM_HIP(hipMemcpyAsync(c.Ta(t, kt4), c.newT4.as<double>() + sl * tt, tt * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c.st));
+        }
         swap_last2(c.st, c.Ta(t, kt4), c.Tb(t, kt4), chi, chi, Db);
         c.cdim[t][kc1] = newdC1[r * Lyv + y];
         c.tdim[t][kt4] = newdT4[r * Lyv + y];
