@@ -120,21 +120,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
       b_off[j] = (int)((long)min(n0 + b_c[j], g.N - 1) * g.sb1 + (long)b_k[j] * g.sb0);
   }
 
-  double ra[EA], rb[EB];
+  // ra/rb: the next k-tile; without tables ra2/rb2 hold the one after it
+  // (two tiles of loads in flight, the registers the table offsets would take)
+  double ra[EA], rb[EB], ra2[EA], rb2[EB];
   auto load_tile = [&](int k0) {
     if (!TBL) {
       const double* Ak = A + (long)k0 * g.sa1;
       const double* Bk = B + (long)k0 * g.sb0;
       if (k0 + BK <= ke) {
 #pragma unroll
-        for (int j = 0; j < EA; ++j) ra[j] = Ak[a_off[j]];
+        for (int j = 0; j < EA; ++j) ra2[j] = Ak[a_off[j]];
 #pragma unroll
-        for (int j = 0; j < EB; ++j) rb[j] = Bk[b_off[j]];
+        for (int j = 0; j < EB; ++j) rb2[j] = Bk[b_off[j]];
       } else {
 #pragma unroll
-        for (int j = 0; j < EA; ++j) ra[j] = (k0 + a_k[j] < ke) ? Ak[a_off[j]] : 0.0;
+        for (int j = 0; j < EA; ++j) ra2[j] = (k0 + a_k[j] < ke) ? Ak[a_off[j]] : 0.0;
 #pragma unroll
-        for (int j = 0; j < EB; ++j) rb[j] = (k0 + b_k[j] < ke) ? Bk[b_off[j]] : 0.0;
+        for (int j = 0; j < EB; ++j) rb2[j] = (k0 + b_k[j] < ke) ? Bk[b_off[j]] : 0.0;
       }
       return;
     }
@@ -165,15 +167,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
   const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
   const int r16 = lane & 15, kg = lane >> 4;
 
+  auto shift = [&] {
+#pragma unroll
+    for (int j = 0; j < EA; ++j) ra[j] = ra2[j];
+#pragma unroll
+    for (int j = 0; j < EB; ++j) rb[j] = rb2[j];
+  };
   int nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
   if (nk > 0) {
     load_tile(kb);
+    if (!TBL) shift();
     store_tile(0);
+  }
+  if (!TBL && nk > 1) {
+    load_tile(kb + BK);
+    shift();
   }
   __syncthreads();
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
-    if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
+    if (TBL) {
+      if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
+    } else {
+      if (it + 2 < nk) load_tile(kb + (it + 2) * BK);
+    }
     // fragments loaded per k-slot, next to their MFMAs (fewer live registers)
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -189,6 +206,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
     if (it + 1 < nk) store_tile(cur ^ 1);
+    if (!TBL) shift();
     __syncthreads();
   }
 
