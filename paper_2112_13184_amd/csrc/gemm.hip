@@ -612,11 +612,12 @@ __global__ __launch_bounds__(256) void k_gemm_dot(KArgs g) {
 // Choose the split of K so that a small output grid still fills the GPU.
 // `tiles` counts the tiles of one problem of a batch: the split (and so the
 // summation order) of a problem does not depend on how many are batched.
-// Among the splits giving at least 512 workgroups (K chunks of at least 256),
-// take the one whose grid comes closest to whole rounds of 1024 workgroups
-// (256 CUs x 4 resident), the smaller split on near ties.
-int choose_splits(long tiles, int K) {
-  constexpr long kRound = 1024, kMin = 512;
+// Among the splits giving at least half a round of workgroups (K chunks of at
+// least 256), take the one whose grid comes closest to whole rounds (256 CUs x
+// the workgroups one CU holds: 1024 for the 64 x 64 kernels), the smaller
+// split on near ties.
+int choose_splits(long tiles, int K, long kRound = 1024) {
+  const long kMin = kRound / 2;
   if (tiles >= kMin / 2) return 1;
   const int smax = (int)std::max<long>(1, std::min<long>(16, (long)K / 256));
   int best = 1;
@@ -640,12 +641,6 @@ void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, uns
   hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, static_cast<const double*>(P.p), P.s0, P.s1, P.t0,
                      P.t1, P.bs, R, C, batch, out, 0);
   CTM_HIP(hipGetLastError());
-}
-
-size_t gemm_workspace_elems(int M, int N, int K, int batch) {
-  long tiles = (long)ceil_div(M, 64) * ceil_div(N, 64);
-  int s = choose_splits(tiles, K);
-  return s > 1 ? (size_t)s * batch * M * N : 0;
 }
 
 void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, const Operand& A,
@@ -680,10 +675,21 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   const bool a_kc = (A.t1 == nullptr && A.s1 == 1);
   const bool b_kc = (B.t0 == nullptr && B.s0 == 1);
   // tile shape: narrow N (sketch panels, bond-sized outputs) -> tall tiles
+  // tiles: 64 x 64; 128 x 32 for narrow outputs; in FP64, 48-wide tiles when
+  // 48 pads a dimension less than 64 does (chi = 144 is 3 x 48) and the other
+  // one is long (these kernels hold two workgroups per CU)
+  auto pad = [](int x, int t) { return ceil_div(x, t) * t - x; };
   int BM = 64, BN = 64;
-  if (N <= 48) { BM = 128; BN = 32; }
+  long round = 1024;
+  if (N <= 48) {
+    BM = 128; BN = 32;
+  } else if (type == GemmType::F64 && pad(M, 48) < pad(M, 64) && N >= 512) {
+    BM = 48; BN = 128; round = 512;
+  } else if (type == GemmType::F64 && pad(N, 48) < pad(N, 64) && M >= 512) {
+    BM = 128; BN = 48; round = 512;
+  }
   long tiles = (long)ceil_div(M, BM) * ceil_div(N, BN);
-  int splits = (K > 0) ? choose_splits(tiles, K) : 1;
+  int splits = (K > 0) ? choose_splits(tiles, K, round) : 1;
   if (splits > 1 && (ws.p == nullptr || ws.elems < (size_t)splits * batch * M * N)) splits = 1;
   int kchunk = (K > 0) ? ((ceil_div(K, splits) + 15) / 16) * 16 : 16;
   if (dot) {   // FP64 dot products regardless of type: negligible work, K-chunks of 4096
@@ -716,8 +722,10 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
     g.amaxB = B.amax ? B.amax : ws.amax + 1;
   }
   dim3 grid((unsigned)(ceil_div(M, BM) * ceil_div(N, BN)), (unsigned)splits, (unsigned)batch);
-  if (BN == 32) launch_typed<128, 32, 4>(st, type, g, a_kc, b_kc, grid);
-  else          launch_typed<64, 64, 2>(st, type, g, a_kc, b_kc, grid);
+  if (BN == 32)      launch_typed<128, 32, 4>(st, type, g, a_kc, b_kc, grid);
+  else if (BM == 48) launch_f64<48, 128, 1>(st, g, a_kc, b_kc, grid);
+  else if (BN == 48) launch_f64<128, 48, 4>(st, g, a_kc, b_kc, grid);
+  else               launch_typed<64, 64, 2>(st, type, g, a_kc, b_kc, grid);
   CTM_HIP(hipGetLastError());
   if (splits > 1) {
     long total = (long)batch * M * N;

@@ -62,7 +62,5 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
 // *out = largest |entry| (FP32 bits) of an R x C operand over `batch` problems.
 void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, unsigned* out);
 
-// Workspace elements gemm() may need for this shape (0 if no split-K).
-size_t gemm_workspace_elems(int M, int N, int K, int batch);
 
 }  // namespace ctm
