@@ -374,21 +374,26 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
       b_off[j] = (int)((long)min(n0 + b_c[j], g.N - 1) * g.sb1 + (long)b_k[j] * g.sb0);
   }
 
-  double ra[EA], rb[EB];
+  // ra/rb: the next k-tile; without tables (and except for split FP16, whose
+  // two operand parts leave no registers) ra2/rb2 hold the one after it
+  constexpr bool PF2 = !TBL && KIND != LP_F16;
+  double ra[EA], rb[EB], ra2[EA], rb2[EB];
+  double* const xa = PF2 ? ra2 : ra;
+  double* const xb = PF2 ? rb2 : rb;
   auto load_tile = [&](int k0) {
     if (!TBL) {
       const double* Ak = A + (long)k0 * g.sa1;
       const double* Bk = B + (long)k0 * g.sb0;
       if (k0 + BK <= ke) {
 #pragma unroll
-        for (int j = 0; j < EA; ++j) ra[j] = Ak[a_off[j]];
+        for (int j = 0; j < EA; ++j) xa[j] = Ak[a_off[j]];
 #pragma unroll
-        for (int j = 0; j < EB; ++j) rb[j] = Bk[b_off[j]];
+        for (int j = 0; j < EB; ++j) xb[j] = Bk[b_off[j]];
       } else {
 #pragma unroll
-        for (int j = 0; j < EA; ++j) ra[j] = (k0 + a_k[j] < ke) ? Ak[a_off[j]] : 0.0;
+        for (int j = 0; j < EA; ++j) xa[j] = (k0 + a_k[j] < ke) ? Ak[a_off[j]] : 0.0;
 #pragma unroll
-        for (int j = 0; j < EB; ++j) rb[j] = (k0 + b_k[j] < ke) ? Bk[b_off[j]] : 0.0;
+        for (int j = 0; j < EB; ++j) xb[j] = (k0 + b_k[j] < ke) ? Bk[b_off[j]] : 0.0;
       }
       return;
     }
@@ -432,15 +437,30 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
   const int r16 = lane & 15, kg = lane >> 4;
 
+  auto shift = [&] {
+#pragma unroll
+    for (int j = 0; j < EA; ++j) ra[j] = ra2[j];
+#pragma unroll
+    for (int j = 0; j < EB; ++j) rb[j] = rb2[j];
+  };
   int nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
   if (nk > 0) {
     load_tile(kb);
+    if (PF2) shift();
     store_tile(0);
+  }
+  if (PF2 && nk > 1) {
+    load_tile(kb + BK);
+    shift();
   }
   __syncthreads();
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
-    if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
+    if (!PF2) {
+      if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
+    } else {
+      if (it + 2 < nk) load_tile(kb + (it + 2) * BK);
+    }
     if constexpr (KIND == LP_F32) {
       f4 af[TM][2], bfr[TN][2];
 #pragma unroll
@@ -500,6 +520,7 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
         }
     }
     if (it + 1 < nk) store_tile(cur ^ 1);
+    if (PF2) shift();
     __syncthreads();
   }
 
