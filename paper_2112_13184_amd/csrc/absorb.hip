@@ -124,6 +124,9 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
       for (int mt = 0; mt < MT1; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
+          // k slots past (l', u') = P hold zero rows of Y_p: skip them (the
+          // sums are unchanged; at D = 6 this drops a quarter of stage two)
+          if (mt * 16 + 4 * r >= P) continue;
           const int lu = mt * 16 + 4 * r + kg;          // (l', u') of this lane's k slot
           double bv[NT2];
 #pragma unroll
