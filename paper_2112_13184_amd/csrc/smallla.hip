@@ -53,30 +53,37 @@ __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 constexpr int kCholNB = kCholB * (kCholB + 1) / 2;
 __host__ __device__ constexpr int cblk(int a, int c) { return a * (a + 1) / 2 + c; }
 
-// Column j (in column block JB) -> LDS, by the threads that hold it.
+// Column j (in column block JB) -> LDS, by the threads that hold it, with
+// the rows at and above the pivot taken as zero so that the update needs no
+// masks of its own; the thread holding the pivot also stores it and its
+// reciprocal (computed once per step instead of once per thread).
 template <int JB>
-__device__ __forceinline__ void chol_publish(const double (&val)[kCholNB], double* cj, int tx) {
+__device__ __forceinline__ void chol_publish(const double (&val)[kCholNB], double* cj, int tx, int j,
+                                             double* pv, double* iv) {
 #pragma unroll
-  for (int a = JB; a < kCholB; ++a) cj[tx + kCholT * a] = val[cblk(a, JB)];
+  for (int a = JB; a < kCholB; ++a) {
+    const int i = tx + kCholT * a;
+    cj[i] = (i > j) ? val[cblk(a, JB)] : 0.0;
+  }
+  if (tx == j % kCholT) {
+    const double d = val[cblk(JB, JB)];
+    *pv = d;
+    *iv = 1.0 / d;
+  }
 }
 
-// Rank-one update by the pivot column j (in column block JB): entries right
-// of and below the pivot lose fi * fl, all others see zero factors.  Blocks
-// left of JB are finished and not touched.
+// Rank-one update by the pivot column j (in column block JB): the published
+// column is zero at and above the pivot and outside k x k, so entries right
+// of and below the pivot lose fi * fl and all others lose exactly zero.
+// Blocks left of JB are finished and not touched.
 template <int JB>
-__device__ __forceinline__ void chol_update(double (&val)[kCholNB], const double* cj, int j, int k, double inv,
-                                            int tx, int ty) {
+__device__ __forceinline__ void chol_update(double (&val)[kCholNB], const double* cj, double inv, int tx,
+                                            int ty) {
   double fl[kCholB], fi[kCholB];
 #pragma unroll
   for (int c = JB; c < kCholB; ++c) {
-    fl[c] = cj[ty + kCholT * c];
+    fl[c] = cj[ty + kCholT * c] * inv;
     fi[c] = cj[tx + kCholT * c];
-  }
-#pragma unroll
-  for (int c = JB; c < kCholB; ++c) {
-    const int l = ty + kCholT * c, i = tx + kCholT * c;
-    fl[c] *= (l > j && l < k) ? inv : 0.0;
-    fi[c] *= (i > j && i < k) ? 1.0 : 0.0;
   }
 #pragma unroll
   for (int a = JB; a < kCholB; ++a)
@@ -102,6 +109,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
                                                         int check_id, double shift_scale, double drop_rel,
                                                         double* Lout, double* Rout, double* mask, int* flag) {
   __shared__ double col[2][kCholB * kCholT];
+  __shared__ double pv[2], iv[2];
   __shared__ double tile[kCholT][kCholB * kCholT + 1];
   __shared__ double piv[kSmallLAMaxK];
   __shared__ double red[16];
@@ -146,16 +154,16 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     const int jb = j / kCholT;
     if (ty == j % kCholT) {
       switch (jb) {
-        case 0: chol_publish<0>(val, cj, tx); break;
-        case 1: chol_publish<1>(val, cj, tx); break;
-        case 2: chol_publish<2>(val, cj, tx); break;
-        case 3: chol_publish<3>(val, cj, tx); break;
-        case 4: chol_publish<4>(val, cj, tx); break;
-        default: chol_publish<5>(val, cj, tx); break;
+        case 0: chol_publish<0>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
+        case 1: chol_publish<1>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
+        case 2: chol_publish<2>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
+        case 3: chol_publish<3>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
+        case 4: chol_publish<4>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
+        default: chol_publish<5>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
       }
     }
     __syncthreads();
-    const double d = cj[j];
+    const double d = pv[j & 1];
     const bool drop = !(d > drop_rel * dmax) || !(d > 0.0) || !isfinite(d);
     if (tid == 0) {
       dropped[j] = drop ? 1 : 0;
@@ -164,14 +172,14 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     }
     if (!drop) {
       dmax = fmax(dmax, d);
-      const double inv = 1.0 / d;
+      const double inv = iv[j & 1];
       switch (jb) {
-        case 0: chol_update<0>(val, cj, j, k, inv, tx, ty); break;
-        case 1: chol_update<1>(val, cj, j, k, inv, tx, ty); break;
-        case 2: chol_update<2>(val, cj, j, k, inv, tx, ty); break;
-        case 3: chol_update<3>(val, cj, j, k, inv, tx, ty); break;
-        case 4: chol_update<4>(val, cj, j, k, inv, tx, ty); break;
-        default: chol_update<5>(val, cj, j, k, inv, tx, ty); break;
+        case 0: chol_update<0>(val, cj, inv, tx, ty); break;
+        case 1: chol_update<1>(val, cj, inv, tx, ty); break;
+        case 2: chol_update<2>(val, cj, inv, tx, ty); break;
+        case 3: chol_update<3>(val, cj, inv, tx, ty); break;
+        case 4: chol_update<4>(val, cj, inv, tx, ty); break;
+        default: chol_update<5>(val, cj, inv, tx, ty); break;
       }
     }
   }
