@@ -365,8 +365,11 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, double* J, int k, int nb, int bs,
                                                                    int round, double* off, const int* conv,
                                                                    double tol) {
-  __shared__ double sA[2 * kJacobiMaxBS * kSmallLAMaxK];
-  __shared__ double sJ[2 * kJacobiMaxBS * kSmallLAMaxK];
+  // staged columns are kJacobiLd apart and zero past row k, so that the
+  // steps read and write whole columns without row checks
+  constexpr int kJacobiLd = 64 * kJacobiRows;
+  __shared__ double sA[2 * kJacobiMaxBS * kJacobiLd];
+  __shared__ double sJ[2 * kJacobiMaxBS * kJacobiLd];
   const int b = blockIdx.y;
   if (conv[b]) return;
   const long kk2 = (long)k * k;
@@ -374,7 +377,8 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
   double* Jb = J + b * kk2;
   const int pa = circle(blockIdx.x, round, nb), pb = circle(nb - 1 - blockIdx.x, round, nb);
   const int m = 2 * bs;
-  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;   // one wave per pair
+  // the wave index is uniform: keep it (and the column arithmetic) scalar
+  const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // wave q stages local columns q (block pa) and bs + q (block pb): all
   // global loads first, then the LDS stores
   {
@@ -394,15 +398,14 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
 #pragma unroll
       for (int t = 0; t < kJacobiRows; ++t) {
         const int r = lane + 64 * t;
-        if (r < k) {
-          sA[(h * bs + q) * k + r] = va[h][t];
-          sJ[(h * bs + q) * k + r] = vj[h][t];
-        }
+        sA[(h * bs + q) * kJacobiLd + r] = va[h][t];
+        sJ[(h * bs + q) * kJacobiLd + r] = vj[h][t];
       }
   }
   __syncthreads();
   const int steps = (round == 0) ? m - 1 : bs;
   double offl = 0.0;
+  int cl = q;                                       // (q + st) mod bs
   for (int st = 0; st < steps; ++st) {
     int ci, cj;
     if (round == 0) {
@@ -410,25 +413,21 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       cj = circle(m - 1 - q, st, m);
     } else {
       ci = q;
-      cj = bs + (q + st) % bs;
+      cj = bs + cl;
+      cl = (cl + 1 == bs) ? 0 : cl + 1;
     }
-    double* ai = sA + (long)ci * k;
-    double* aj = sA + (long)cj * k;
-    double* ji = sJ + (long)ci * k;
-    double* jj = sJ + (long)cj * k;
+    double* ai = sA + ci * kJacobiLd + lane;
+    double* aj = sA + cj * kJacobiLd + lane;
+    double* ji = sJ + ci * kJacobiLd + lane;
+    double* jj = sJ + cj * kJacobiLd + lane;
     // both columns and their rotation accumulators in registers (rows lane + 64 t)
     double x[kJacobiRows], y[kJacobiRows], u[kJacobiRows], v[kJacobiRows];
-    // reads past row k stay inside the staging arrays (columns are k apart)
-    // and are replaced by zeros after the load, so no load is predicated
 #pragma unroll
     for (int t = 0; t < kJacobiRows; ++t) {
-      const int r = lane + 64 * t;
-      const bool ok = r < k;
-      const double xa = ai[r], ya = aj[r], ua = ji[r], va = jj[r];
-      x[t] = ok ? xa : 0.0;
-      y[t] = ok ? ya : 0.0;
-      u[t] = ok ? ua : 0.0;
-      v[t] = ok ? va : 0.0;
+      x[t] = ai[64 * t];
+      y[t] = aj[64 * t];
+      u[t] = ji[64 * t];
+      v[t] = jj[64 * t];
     }
     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -454,13 +453,10 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
 #pragma unroll
       for (int t = 0; t < kJacobiRows; ++t) {
-        const int row = lane + 64 * t;
-        if (row < k) {
-          ai[row] = cs * x[t] - sn * y[t];
-          aj[row] = sn * x[t] + cs * y[t];
-          ji[row] = cs * u[t] - sn * v[t];
-          jj[row] = sn * u[t] + cs * v[t];
-        }
+        ai[64 * t] = cs * x[t] - sn * y[t];
+        aj[64 * t] = sn * x[t] + cs * y[t];
+        ji[64 * t] = cs * u[t] - sn * v[t];
+        jj[64 * t] = sn * u[t] + cs * v[t];
       }
     }
     __syncthreads();
@@ -473,8 +469,8 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       for (int t = 0; t < kJacobiRows; ++t) {
         const int r = lane + 64 * t;
         if (r < k) {
-          Ab[(long)gc * k + r] = sA[(h * bs + q) * k + r];
-          Jb[(long)gc * k + r] = sJ[(h * bs + q) * k + r];
+          Ab[(long)gc * k + r] = sA[(h * bs + q) * kJacobiLd + r];
+          Jb[(long)gc * k + r] = sJ[(h * bs + q) * kJacobiLd + r];
         }
       }
     }
