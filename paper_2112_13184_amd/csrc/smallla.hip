@@ -93,9 +93,10 @@ __device__ __forceinline__ void chol_update(double (&val)[kCholNB], const double
 
 // G_b (k x k, col-major) [+ s I] = L L^T, rank revealing: a pivot below
 // drop_rel times the largest one so far marks its column as dependent
-// (mask 0): the column is taken as zero, L gets a unit diagonal there (so
-// that L stays invertible) and R = L^T gets a zero row (so that accumulated
-// factors keep the zero).  shifted: add s = shift_scale * trace(G).
+// (mask 0): the column is taken as zero and R = L^T, the output, gets a zero
+// row there (so that accumulated factors keep the zero); the triangular
+// inverse takes a unit diagonal in its place.  shifted: add s = shift_scale
+// * trace(G).
 // check_id: flag the problem if the non-zero part of G is not within 0.5 of
 // the identity.  NaN / Inf pivots flag the problem too.
 // The lower triangle lives in registers, distributed 2-D cyclically: thread
@@ -103,11 +104,11 @@ __device__ __forceinline__ void chol_update(double (&val)[kCholNB], const double
 // for the 21 block pairs a >= c.  Step j broadcasts column j through a
 // double-buffered LDS column (one barrier per step); the update is
 // specialised on the block of j, so finished blocks cost nothing.  R is
-// written through an LDS tile, 32 rows of L at a time, so that both outputs
-// are stored along contiguous columns.
+// written through an LDS tile, 32 rows of L at a time, so that it is stored
+// along contiguous columns.
 __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, int pass, int shifted,
                                                         int check_id, double shift_scale, double drop_rel,
-                                                        double* Lout, double* Rout, double* mask, int* flag) {
+                                                        double* Rout, double* mask, int* flag) {
   __shared__ double col[2][kCholB * kCholT];
   __shared__ double pv[2], iv[2];
   __shared__ double tile[kCholT][kCholB * kCholT + 1];
@@ -184,7 +185,6 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     }
   }
   __syncthreads();
-  double* Lb = Lout + b * kk2;
   double* Rb = Rout + b * kk2;
   // scale factors of this thread's columns
   double sd[kCholB];
@@ -195,21 +195,6 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     dr[c] = l < k ? dropped[l] != 0 : true;
     sd[c] = (l < k && !dr[c]) ? sqrt(piv[l]) : 1.0;
   }
-  // L: strictly upper part zero; lower part scaled, unit column where dropped
-#pragma unroll
-  for (int a = 0; a < kCholB; ++a)
-#pragma unroll
-    for (int c = 0; c < kCholB; ++c) {
-      const int i = tx + kCholT * a, l = ty + kCholT * c;
-      if (i >= k || l >= k) continue;
-      double v = 0.0;
-      if (c <= a && l <= i) {
-        if (dr[c]) v = (i == l) ? 1.0 : 0.0;
-        // a dependent row i keeps its coefficients on the earlier directions
-        else v = (i == l) ? sd[c] : val[cblk(a, c)] / sd[c];
-      }
-      Lb[i + (long)l * k] = v;             // L[i][l]
-    }
   // R = L^T with zero rows where dropped: rows 32 a .. 32 a + 31 of L go
   // through the tile and out as columns of R
 #pragma unroll
@@ -238,27 +223,31 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
 }
 
-// Rinv = R^-1 for R = L^T upper triangular; one wave per column c.  Column
-// c of R^-1 is found by back substitution from row c up; row i needs column
-// i of L below the diagonal, which does not depend on the solution, so the
-// columns for the next 16 rows are kept in flight in a register ring (loads
-// unguarded, masked by multiplication).  The reciprocal of L[i][i] stays in
-// the register of the lane that owns row i, so a step waits only on its
-// wave reduction.
-__global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* Rinv) {
+// Rinv = U^-1 for the upper triangular U = L^T, one wave per column c.  U
+// equals the stored R except on the diagonal of dropped directions, where
+// R has zero rows and U a unit diagonal (mask 0).  Column c of U^-1 solves
+// U x = e_c by back substitution in column form: from row c up, x_i = b_i /
+// U[i][i], then b loses x_i times column i of U.  A step thus waits on one
+// lane broadcast, not on a wave reduction.  Column i of R does not depend on
+// the solution, so the columns of the next 16 steps are kept in flight in a
+// register ring.  The update also touches row i (and rows below it, where R
+// is zero); x_i is kept apart, so that does not matter.
+__global__ __launch_bounds__(256) void k_trinv(const double* R, const double* mask, int k, double* Rinv) {
   constexpr int RING = 16;
   const int b = blockIdx.y;
   const int lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (c >= k) return;
   const long kk2 = (long)k * k;
-  const double* Lb = L + b * kk2;
-  double x[3] = {0.0, 0.0, 0.0};     // x[q] = column entry lane + 64 q
-  double rd[3];                      // 1 / L[i][i] for i = lane + 64 q
+  const double* Rb = R + b * kk2;
+  const double* mb = mask + (long)b * k;
+  double bv[3], rd[3], xo[3];        // rows lane + 64 q: right-hand side, 1 / U[i][i], solution
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int i = lane + 64 * q;
-    rd[q] = (i <= c) ? 1.0 / Lb[i + (long)i * k] : 0.0;
+    bv[q] = (i == c) ? 1.0 : 0.0;
+    xo[q] = 0.0;
+    rd[q] = (i <= c) ? (mb[i] != 0.0 ? 1.0 / Rb[i + (long)i * k] : 1.0) : 0.0;
   }
   double ring[RING][3];
   auto fetch = [&](int i, double* dst) {
@@ -266,8 +255,7 @@ __global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* R
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int kx = lane + 64 * q;
-      const double v = Lb[(kx < k ? kx : k - 1) + col];            // R[i][kx] = L[kx][i]
-      dst[q] = v * ((i >= 0 && kx > i && kx <= c) ? 1.0 : 0.0);
+      dst[q] = Rb[(kx < k ? kx : k - 1) + col];                  // R[kx][i]
     }
   };
 #pragma unroll
@@ -277,16 +265,16 @@ __global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* R
     for (int s = 0; s < RING; ++s) {
       const int i = base - s;
       if (i < 0) break;
-      double lc[3] = {ring[s][0], ring[s][1], ring[s][2]};
+      double col[3] = {ring[s][0], ring[s][1], ring[s][2]};
       fetch(i - RING, ring[s]);
-      double part = 0.0;
+      const int qi = i >> 6, li = i & 63;
+      const double bq = qi == 0 ? bv[0] : (qi == 1 ? bv[1] : bv[2]);
+      const double rq = qi == 0 ? rd[0] : (qi == 1 ? rd[1] : rd[2]);
+      const double xi = readlane_f64(bq * rq, li);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) part += lc[q] * x[q];
-      const double sum = wave_sum(part);
-      if ((i & 63) == lane) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          if ((i >> 6) == q) x[q] = (((i == c) ? 1.0 : 0.0) - sum) * rd[q];
+      for (int q = 0; q < 3; ++q) {
+        xo[q] = (q == qi && lane == li) ? xi : xo[q];
+        bv[q] = fma(-xi, col[q], bv[q]);
       }
     }
   }
@@ -294,7 +282,7 @@ __global__ __launch_bounds__(256) void k_trinv(const double* L, int k, double* R
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int i = lane + 64 * q;
-    if (i < k) out[i] = (i <= c) ? x[q] : 0.0;
+    if (i < k) out[i] = (i <= c) ? xo[q] : 0.0;
   }
 }
 
@@ -527,7 +515,7 @@ void smallla_alloc(SmallLA& s, int kmax, int batch_max, long nmax) {
   s.kmax = kmax;
   s.batch_max = batch_max;
   const size_t m = (size_t)kmax * kmax * batch_max;
-  s.G.alloc(m * 8); s.L.alloc(m * 8); s.R.alloc(m * 8); s.Rinv.alloc(m * 8);
+  s.G.alloc(m * 8); s.R.alloc(m * 8); s.Rinv.alloc(m * 8);
   s.Racc.alloc(m * 8); s.Rtmp.alloc(m * 8); s.J.alloc(m * 8);
   CTM_CHECK(batch_max <= 64, -1, "smallla: at most 64 problems per batch");
   s.flag.alloc(sizeof(int) * 256);
@@ -549,7 +537,6 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
   const long kk2 = (long)k * k;
   const double shift_scale = 11.0 * ((double)n * k + (double)k * (k + 1)) * 0x1p-53;
   double* G = s.G.as<double>();
-  double* L = s.L.as<double>();
   double* R = s.R.as<double>();
   double* Ri = s.Rinv.as<double>();
   double* tmp = s.tmp.as<double>();
@@ -569,9 +556,9 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
     // from the third pass on.
     hipLaunchKernelGGL(k_chol, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass, pass == 0 ? 1 : 0,
                        pass >= 2 ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14,
-                       L, rout, s.mask.as<double>(), s.flag.as<int>());
+                       rout, s.mask.as<double>(), s.flag.as<int>());
     CTM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_trinv, dim3((k + 3) / 4, batch), dim3(256), 0, st, L, k, Ri);
+    hipLaunchKernelGGL(k_trinv, dim3((k + 3) / 4, batch), dim3(256), 0, st, rout, s.mask.as<double>(), k, Ri);
     CTM_HIP(hipGetLastError());
     gemm(st, GemmType::F64, n, k, k, 1.0, colmajor(Y, n, ystride), colmajor(Ri, k, kk2), 0.0,
          out_colmajor(tmp, n, (long)n * k), batch, ws);

@@ -12,7 +12,7 @@ struct SmallLA {
   // flag: 256 ints; [0, 64) Cholesky failure per problem, [64, 128) Jacobi
   // convergence per problem, [128, 192) projector-weight failure per problem,
   // [192, 256) Jacobi sweeps run per problem
-  DevBuf G, L, R, Rinv, Racc, Rtmp, J, flag, off, tmp, mask;
+  DevBuf G, R, Rinv, Racc, Rtmp, J, flag, off, tmp, mask;
   size_t tmp_elems = 0;
 };
 

@@ -153,7 +153,7 @@ Sizes sizes_of(const ctm_config& cfg, int R = 1) {
   e += 8 * n * kk * Lmax + 6 * kk * kk * Lmax;                      // panels, small matrices
   e += std::max(kk, n) * Lmax + chi * Lmax;                         // singular values, weights
   if (kk <= kSmallLAMaxK && p >= 0)                                 // Cholesky QR / Jacobi
-    e += 7 * kk * kk * Lmax + kk * Lmax + n * kk * Lmax + 64 + 128;
+    e += 6 * kk * kk * Lmax + kk * Lmax + n * kk * Lmax + 64 + 128;
   e += 3 * Lmax * n * chi + 2 * Lmax * cc + Lmax * cc * s.Db;       // projectors, new C / T
   e += 2 * 4 * N * chi + 4 * N * cc;                                // spectra, corner scratch
   e += 8 * n * std::max(kk, chi) * R;                               // split-K partials
