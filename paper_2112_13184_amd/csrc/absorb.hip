@@ -46,6 +46,12 @@ struct AbsorbArgs {
   const double* Ak;
   const double* Ab;
   double* G;
+  // one problem per blockIdx.y: per-problem pointers (device arrays), else
+  // the single problem above
+  const double* const* Xp;
+  const double* const* Akp;
+  const double* const* Abp;
+  double* const* Gp;
   long n;
   int chi, DK, DB, d;
   int transposed;
@@ -55,6 +61,11 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
     AbsorbArgs a) {
   __shared__ double sAk[kAkElems];
   __shared__ double sAb[kAbElems];
+  const int bz = blockIdx.y;
+  const double* Xg = a.Xp ? a.Xp[bz] : a.X;
+  const double* Akg = a.Akp ? a.Akp[bz] : a.Ak;
+  const double* Abg = a.Abp ? a.Abp[bz] : a.Ab;
+  double* Gg = a.Gp ? a.Gp[bz] : a.G;
   const int DK = a.DK, DB = a.DB, d = a.d;
   const int Db = DK * DB;
   const int P = DB * DB;          // (l', u') and (r', d')
@@ -64,12 +75,12 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
   for (int e = tid; e < kAkElems; e += blockDim.x) {
     const int k = e / kAkLd, c = e % kAkLd;          // c = p * 48 + (r, dd)
     const int p = c / kRD, rd = c % kRD;
-    sAk[e] = (k < Q && p < d && rd < Q && c < 2 * kRD) ? a.Ak[((long)k * Q + rd) * d + p] : 0.0;
+    sAk[e] = (k < Q && p < d && rd < Q && c < 2 * kRD) ? Akg[((long)k * Q + rd) * d + p] : 0.0;
   }
   for (int e = tid; e < kAbElems; e += blockDim.x) {
     const int row = e / kAbLd, c = e % kAbLd;        // row = (l', u') * 2 + p, c = (r', d')
     const int lu = row >> 1, p = row & 1;
-    sAb[e] = (lu < P && p < d && c < P) ? a.Ab[((long)lu * P + c) * d + p] : 0.0;
+    sAb[e] = (lu < P && p < d && c < P) ? Abg[((long)lu * P + c) * d + p] : 0.0;
   }
   __syncthreads();
   const int r16 = lane & 15, kg = lane >> 4;
@@ -86,7 +97,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
   const long nwaves = (long)gridDim.x * kWaves;
   for (long pr = (long)blockIdx.x * kWaves + w; pr < npairs; pr += nwaves) {
     const int cp = (int)(pr / a.chi), cn = (int)(pr % a.chi);
-    const double* Xb = a.X + (long)cp * Db * a.n + (long)cn * Db;
+    const double* Xb = Xg + (long)cp * Db * a.n + (long)cn * Db;
     d4 acc2[3][NT2];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -150,8 +161,8 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
             const int i = m2 * 16 + kg + 4 * r;         // (r, dd)
             if (i < Q) {
               const long nxt = (long)cn * Db + (i / DK) * DB + rb, prv = (long)cp * Db + (i % DK) * DB + db;
-              if (a.transposed) a.G[prv * a.n + nxt] = acc2[m2][nt][r];
-              else a.G[nxt * a.n + prv] = acc2[m2][nt][r];
+              if (a.transposed) Gg[prv * a.n + nxt] = acc2[m2][nt][r];
+              else Gg[nxt * a.n + prv] = acc2[m2][nt][r];
             }
           }
       }
@@ -168,17 +179,27 @@ bool absorb_fused_fits(int DK, int DB, int d) {
 
 void absorb_fused(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G, int chi,
                   int DK, int DB, int d, bool transposed) {
+  absorb_fused_batched(st, X, Ak, Ab, G, nullptr, nullptr, nullptr, nullptr, 1, chi, DK, DB, d, transposed);
+}
+
+void absorb_fused_batched(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G,
+                          const double* const* Xp, const double* const* Akp, const double* const* Abp,
+                          double* const* Gp, int batch, int chi, int DK, int DB, int d, bool transposed) {
   CTM_CHECK(absorb_fused_fits(DK, DB, d), -1, "absorb_fused: block too large");
+  CTM_CHECK(batch >= 1 && batch <= 65535, -1, "absorb_fused: batch out of range");
+  CTM_CHECK(batch == 1 || (Xp && Akp && Abp && Gp), -1, "absorb_fused: a batch needs per-problem pointers");
   AbsorbArgs a{};
   a.X = X; a.Ak = Ak; a.Ab = Ab; a.G = G;
+  a.Xp = Xp; a.Akp = Akp; a.Abp = Abp; a.Gp = Gp;
   a.n = (long)chi * DK * DB;
   a.chi = chi; a.DK = DK; a.DB = DB; a.d = d;
   a.transposed = transposed ? 1 : 0;
   const long npairs = (long)chi * chi;
   // two resident workgroups per CU on 256 CUs; each wave strides over pairs
   const long per_block = kWaves;
-  const unsigned blocks = (unsigned)std::min<long>(512, (npairs + per_block - 1) / per_block);
-  hipLaunchKernelGGL(k_absorb_fused, dim3(blocks), dim3(64 * kWaves), 0, st, a);
+  const unsigned blocks = (unsigned)std::min<long>(std::max<long>(1, 512 / batch),
+                                                   (npairs + per_block - 1) / per_block);
+  hipLaunchKernelGGL(k_absorb_fused, dim3(blocks, batch), dim3(64 * kWaves), 0, st, a);
   CTM_HIP(hipGetLastError());
 }
 

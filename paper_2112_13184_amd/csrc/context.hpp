@@ -125,6 +125,14 @@ struct Context {
   DevBuf newC1, newT4, newC4;
   DevBuf spec, specprev, cornerscratch;
   DevBuf gws;                // GEMM split-K workspace
+  // Per-problem pointer tables of batched launches (corners and column
+  // updates of several cuts, whose tensors are not evenly spaced): a ring of
+  // 8-byte words on the device, filled by stream-ordered copies from a pinned
+  // host ring.  The host ring is reused only after the stream has drained.
+  DevBuf ptab;
+  PinnedBuf ptab_host;
+  size_t ptab_words = 0, ptab_used = 0;
+  int bchunk = 1;            // problems per batched corner / update launch (n x n scratch each)
   size_t gws_elems = 0;
   DevBuf amax;               // split-FP16 operand scaling (2 words)
   DevBuf camax;              // split FP16: largest |entry| of each corner role over a column's cuts

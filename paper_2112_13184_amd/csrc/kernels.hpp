@@ -48,4 +48,28 @@ void spectra_delta(hipStream_t st, double* S, double* prev, int ncorner, int chi
 // y[i] = a * x[i]
 void scale(hipStream_t st, double* x, long n, double a);
 
+
+// Batched forms for problems of one shape in one launch (problem b on
+// blockIdx.y).  Pointer arguments of type `T* const*` are device arrays of one
+// device pointer per problem; strides are in elements.  Each problem gets
+// exactly the arithmetic of the single form.
+void swap_last2_batched(hipStream_t st, const double* const* in, double* const* out, int batch, long na, long nb,
+                        long nc);
+// scratch: 1025 doubles per problem.
+void normalize_maxabs_batched(hipStream_t st, double* const* x, int batch, long n, double* scratch, int* bad_flag);
+// Problem b: Om + b * ostride, key seed[b], stream id sid[b] (host arrays,
+// batch <= 64).
+void omega_fill_batched(hipStream_t st, double* Om, long ostride, int batch, int n, int Db, int k, const uint64_t* seed,
+                        const uint64_t* sid);
+void scale_columns_batched(hipStream_t st, double* X, long xstride, int batch, int n, int m, const double* w,
+                           long wstride);
+// Problem b: in / out + b * kk * kk.
+void transpose_square_batched(hipStream_t st, const double* in, double* out, int kk, int batch);
+
+// Problem b: S + b * sstride, U + b * ustride, cap kcap[b] (host array,
+// batch <= 64), weights w + b * chi, keff[b], bad_flag[b].
+void projector_weights_batched(hipStream_t st, const double* S, long sstride, const double* U, long ustride, int n,
+                               int kk, int chi, const int* kcap, double cutoff, double* w, int* keff, int* bad_flag,
+                               int batch);
+
 }  // namespace ctm

@@ -49,6 +49,18 @@ uint64_t stream_id(long long move, int x, int y) {
 
 // Rotate a site tensor t[l][u][r][d][p] (dims Dd) one quarter turn
 // counter-clockwise: out[a][b][c][e][p] = in[e][a][b][c][p].
+// Batched corner and column-update launches give every problem its own n x n
+// and chi x n scratch; at most this much n x n scratch in all (one problem
+// per launch once n x n alone exceeds half of it: large n gains nothing from
+// batching, its launches are long).
+constexpr size_t kBatchScratchBytes = (size_t)256 << 20;
+constexpr size_t kTableWords = (size_t)1 << 18;   // pointer-table ring: 2 MiB
+
+long batch_chunk(long nn, long slots) {
+  const long by_mem = (long)(kBatchScratchBytes / ((size_t)nn * sizeof(double)));
+  return std::max<long>(1, std::min<long>(by_mem < 2 ? 1 : by_mem, 4 * slots));
+}
+
 void rotate_host(const std::vector<double>& in, std::vector<double>& out, int Dd, int d) {
   out.resize(in.size());
   for (int a = 0; a < Dd; ++a)
@@ -149,7 +161,8 @@ Sizes sizes_of(const ctm_config& cfg, int R = 1) {
   size_t e = 0;
   e += 4 * N * (DK * DK * DK * DK * d + DB * DB * DB * DB * d);   // site tensors, 4 rotations
   e += 4 * N * (cc + 2 * cc * s.Db);                               // C, T, transposed T
-  e += 4 * s.nn * Lmax + chi * n + s.nn + s.y;                      // corners, X1, X2, Y
+  const long bch = batch_chunk(s.nn, Lmax);                         // problems per batched launch
+  e += 4 * s.nn * Lmax + bch * (chi * n + s.nn) + s.y;              // corners, X1, X2, Y
   e += 8 * n * kk * Lmax + 6 * kk * kk * Lmax;                      // panels, small matrices
   e += std::max(kk, n) * Lmax + chi * Lmax;                         // singular values, weights
   if (kk <= kSmallLAMaxK && p >= 0)                                 // Cholesky QR / Jacobi
@@ -157,7 +170,8 @@ Sizes sizes_of(const ctm_config& cfg, int R = 1) {
   e += 3 * Lmax * n * chi + 2 * Lmax * cc + Lmax * cc * s.Db;       // projectors, new C / T
   e += 2 * 4 * N * chi + 4 * N * cc;                                // spectra, corner scratch
   e += 8 * n * std::max(kk, chi) * R;                               // split-K partials
-  e += 4096 + 2048 + 64;                                            // rho, reductions, flags
+  e += 4096 + std::max<long>(2048, 1025 * Lmax) + 64;              // rho, reductions, flags
+  e += kTableWords;                                                 // pointer tables
   e += observe_arena_elems(chi, DK, DB, d);                         // expectation values
   size_t b = 8 * e;
   b += 4 * (size_t)(2 * cc * DB * DB + 2 * cc * DK * DK + 4 * DK * DK * d + 4 * DB * DB * d);  // tables
@@ -293,8 +307,13 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   build_tables(c);
   const int Lmax0 = std::max(c.Lx, c.Ly) * c.R;   // cut slots of one column, all replicas
   for (auto& g : c.G) g.alloc(sizeof(double) * sz.nn * Lmax0);      // one slot per cut of a column
-  c.X1.alloc(sizeof(double) * c.chi * c.n);
-  c.X2.alloc(sizeof(double) * sz.nn);
+  c.bchunk = (int)batch_chunk(sz.nn, Lmax0);
+  c.X1.alloc(sizeof(double) * c.chi * c.n * c.bchunk);
+  c.X2.alloc(sizeof(double) * sz.nn * c.bchunk);
+  c.ptab_words = kTableWords;
+  c.ptab.alloc(sizeof(uint64_t) * c.ptab_words);
+  c.ptab_host.alloc(sizeof(uint64_t) * c.ptab_words);
+  c.ptab_used = 0;
   c.Ybuf.alloc(sizeof(double) * sz.y);
   for (auto& p : c.pan) p.alloc(sizeof(double) * c.n * c.kk * Lmax0);
   for (auto& p : c.small) p.alloc(sizeof(double) * (size_t)c.kk * c.kk * Lmax0);
@@ -304,7 +323,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.keff.alloc(sizeof(int) * 64);
   c.badflag.alloc(sizeof(int));
   CTM_HIP(hipMemset(c.badflag.p, 0, sizeof(int)));
-  c.redscratch.alloc(sizeof(double) * 2048);
+  c.redscratch.alloc(sizeof(double) * std::max(2048, 1025 * Lmax0));
   c.delta.alloc(sizeof(double) * c.R);
   int Lmax = Lmax0;
   c.Pt.alloc(sizeof(double) * Lmax * c.n * c.chi);
@@ -375,6 +394,56 @@ static void absorb(Context& c, const double* X, const double* Ak, const double* 
   mm(c, PhaseTimer::ABSORB, chi * chi * DK * DK, DB * DB, DB * DB * d, A2, B2, Co);
 }
 
+// ---- per-problem pointer tables ---------------------------------------------
+// Words are appended host-side into a blob; upload() copies the blob to the
+// device ring in one stream-ordered copy and returns its device address.  The
+// pinned host ring is rewritten only after the stream has drained (when the
+// ring wraps), so no copy out of it can still be pending.
+struct TableBlob {
+  std::vector<uint64_t> w;
+  size_t add(const void* p) { w.push_back((uint64_t)(uintptr_t)p); return w.size() - 1; }
+  size_t add_int(long v) { w.push_back((uint64_t)v); return w.size() - 1; }
+};
+
+static const uint64_t* upload(Context& c, const TableBlob& t) {
+  const size_t words = t.w.size();
+  CTM_CHECK(words <= c.ptab_words, -1, "pointer tables: too many problems in one launch");
+  if (c.ptab_used + words > c.ptab_words) {
+    CTM_HIP(hipStreamSynchronize(c.st));
+    c.ptab_used = 0;
+  }
+  uint64_t* h = c.ptab_host.as<uint64_t>() + c.ptab_used;
+  uint64_t* d = c.ptab.as<uint64_t>() + c.ptab_used;
+  std::memcpy(h, t.w.data(), words * sizeof(uint64_t));
+  CTM_HIP(hipMemcpyAsync(d, h, words * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
+  c.ptab_used += (words + 7) & ~(size_t)7;
+  return d;
+}
+
+template <typename T>
+static T* const* tab_at(const uint64_t* base, size_t i) { return reinterpret_cast<T* const*>(base + i); }
+
+static Operand tab_rowmajor(const uint64_t* base, size_t i, long ld) {
+  Operand o = rowmajor(nullptr, ld);
+  o.bp = tab_at<const void>(base, i);
+  return o;
+}
+static Operand tab_colmajor(const uint64_t* base, size_t i, long ld) {
+  Operand o = colmajor(nullptr, ld);
+  o.bp = tab_at<const void>(base, i);
+  return o;
+}
+static OutOperand tab_out_rowmajor(const uint64_t* base, size_t i, long ld) {
+  OutOperand o = out_rowmajor(nullptr, ld);
+  o.bp = tab_at<void>(base, i);
+  return o;
+}
+static OutOperand tab_out_colmajor(const uint64_t* base, size_t i, long ld) {
+  OutOperand o = out_colmajor(nullptr, ld);
+  o.bp = tab_at<void>(base, i);
+  return o;
+}
+
 // Enlarged corner j of site s: G[(cn, o_n)][(cp, o_p)] (n x n, row-major).
 void enlarged_corner(Context& c, int s, int j, double* out) {
   const int chi = c.chi;
@@ -386,6 +455,53 @@ void enlarged_corner(Context& c, int s, int j, double* out) {
   mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, rowmajor(c.Tb(s, (j + 3) % 4), chi), rowmajor(c.X1.p, n),
      out_rowmajor(c.X2.p, n));
   absorb(c, c.X2.as<double>(), c.Ak(j, s), c.Ab(j, s), out, false);
+}
+
+// Enlarged corners of several (site, corner, output) jobs: the same products
+// as enlarged_corner, c.bchunk corners per launch (each with its own X1 / X2
+// scratch), so that small corners of many cuts share their launches.
+struct CornerJob {
+  int s, j;
+  double* out;
+};
+
+void enlarged_corners(Context& c, const std::vector<CornerJob>& jobs) {
+  const int chi = c.chi;
+  const long n = c.n, nn = n * n, xn = (long)chi * n;
+  if (c.bchunk <= 1 || jobs.size() <= 1 || !absorb_fused_fits(c.DK, c.DB, c.d)) {
+    for (const auto& jb : jobs) enlarged_corner(c, jb.s, jb.j, jb.out);
+    return;
+  }
+  for (size_t i0 = 0; i0 < jobs.size(); i0 += c.bchunk) {
+    const int m = (int)std::min<size_t>(c.bchunk, jobs.size() - i0);
+    TableBlob t;
+    const size_t tC = t.w.size();
+    for (int i = 0; i < m; ++i) t.add(c.C(jobs[i0 + i].s, jobs[i0 + i].j));
+    const size_t tTa = t.w.size();
+    for (int i = 0; i < m; ++i) t.add(c.Ta(jobs[i0 + i].s, jobs[i0 + i].j));
+    const size_t tTb = t.w.size();
+    for (int i = 0; i < m; ++i) t.add(c.Tb(jobs[i0 + i].s, (jobs[i0 + i].j + 3) % 4));
+    const size_t tX = t.w.size();
+    for (int i = 0; i < m; ++i) t.add(c.X2.as<double>() + i * nn);
+    const size_t tAk = t.w.size();
+    for (int i = 0; i < m; ++i) t.add(c.Ak(jobs[i0 + i].j, jobs[i0 + i].s));
+    const size_t tAb = t.w.size();
+    for (int i = 0; i < m; ++i) t.add(c.Ab(jobs[i0 + i].j, jobs[i0 + i].s));
+    const size_t tG = t.w.size();
+    for (int i = 0; i < m; ++i) t.add(jobs[i0 + i].out);
+    const uint64_t* d = upload(c, t);
+    mm(c, PhaseTimer::OTHER, chi, (int)n, chi, tab_colmajor(d, tC, chi), tab_rowmajor(d, tTa, n),
+       out_rowmajor(c.X1.p, n, xn), m);
+    mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, tab_rowmajor(d, tTb, chi), rowmajor(c.X1.p, n, xn),
+       out_rowmajor(c.X2.p, n, nn), m);
+    const int DK = c.DK, DB = c.DB, dd = c.d;
+    const double flops = 2.0 * chi * chi * (double)DB * DB * DK * DK * dd * (DK * DK + DB * DB) * m;
+    timed(c, PhaseTimer::ABSORB, flops, [&] {
+      absorb_fused_batched(c.st, nullptr, nullptr, nullptr, nullptr, tab_at<const double>(d, tX),
+                           tab_at<const double>(d, tAk), tab_at<const double>(d, tAb), tab_at<double>(d, tG), m, chi,
+                           DK, DB, dd, false);
+    });
+  }
 }
 
 namespace {
@@ -522,6 +638,8 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
   auto Gp = [&](int role, int slot) { return c.G[role].as<double>() + slot * nn; };
   auto pan = [&](int i, int slot) { return c.pan[i].as<double>() + slot * pk; };
   std::vector<int> kcap(nb);
+  std::vector<CornerJob> jobs;
+  std::vector<uint64_t> seeds(nb), sids(nb);
   for (int b = 0; b < nb; ++b) {
     const int r = cuts[b][0], y = cuts[b][1], slot = s0 + b, o = r * c.N;
     const int sites[4] = {o + view_site(c, rot, x, y), o + view_site(c, rot, x + 1, y),
@@ -531,11 +649,15 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
       const int j = (q + rot) % 4, s = sites[q];
       kcap[b] = std::min(kcap[b], c.tdim[s][j][1] * c.Db);
       kcap[b] = std::min(kcap[b], c.tdim[s][(j + 3) % 4][0] * c.Db);
-      enlarged_corner(c, s, j, Gp(q, slot));   // roles: 0 UL, 1 UR, 2 LR, 3 LL
+      jobs.push_back({s, j, Gp(q, slot)});   // roles: 0 UL, 1 UR, 2 LR, 3 LL
     }
-    const uint64_t sid = stream_id(c.moves, x, y);
-    timed(c, PhaseTimer::OTHER, 0.0, [&] { omega_fill(c.st, pan(1, slot), n, c.Db, kk, c.seeds[r], sid); });
+    seeds[b] = c.seeds[r];
+    sids[b] = stream_id(c.moves, x, y);
   }
+  enlarged_corners(c, jobs);
+  timed(c, PhaseTimer::OTHER, 0.0, [&] {
+    omega_fill_batched(c.st, pan(1, s0), pk, nb, n, c.Db, kk, seeds.data(), sids.data());
+  });
   // split FP16: each corner role's largest entry, scanned once for the column
   const unsigned* cam = nullptr;
   if (c.ctype == GemmType::F16) {
@@ -584,18 +706,18 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
   // the sketch directions, and converges in fewer sweeps than on R.
   double* Rt = c.small[3].as<double>() + s0 * k2;
   timed(c, PhaseTimer::LINALG, 0.0, [&] {
-    for (int b = 0; b < nb; ++b) transpose_square(c.st, R + b * k2, Rt + b * k2, kk);
+    transpose_square_batched(c.st, R, Rt, kk, nb);
     jacobi_svd(c.st, c.sla, Rt, kk, nb, Ysv, S, std::max(kk, n), X);
   });
   mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Z, n, pk), colmajor(X, kk, k2), out_colmajor(V, n, pk), nb);
   mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Y, n, pk), colmajor(Ysv, kk, k2), out_colmajor(U, n, pk), nb);
-  for (int b = 0; b < nb; ++b) {
-    double* w = c.wvec.as<double>() + (long)(s0 + b) * chi;
+  {
+    double* w = c.wvec.as<double>() + (long)s0 * chi;
     timed(c, PhaseTimer::LINALG, 0.0, [&] {
-      projector_weights(c.st, S + (long)b * std::max(kk, n), U + b * pk, n, kk, chi, kcap[b], c.cutoff, w,
-                        c.keff.as<int>() + s0 + b, c.sla.flag.as<int>() + 128 + b);
-      scale_columns(c.st, V + b * pk, n, chi, w);
-      scale_columns(c.st, Ysv + b * k2, kk, chi, w);
+      projector_weights_batched(c.st, S, std::max(kk, n), U, pk, n, kk, chi, kcap.data(), c.cutoff, w,
+                                c.keff.as<int>() + s0, c.sla.flag.as<int>() + 128, nb);
+      scale_columns_batched(c.st, V, pk, nb, n, chi, w, chi);
+      scale_columns_batched(c.st, Ysv, k2, nb, kk, chi, w, chi);
     });
   }
   // Pt = G_ll (G_lr V'), PT = W Ub'
@@ -698,6 +820,89 @@ void cut_projectors_fast(Context& c, int rot, int x, int y) {
   c.last_cut_svd = true;
 }
 
+// Pointers of one cut's column update (see do_move).
+struct UpdPtrs {
+  int s = 0;
+  double *Pt_up = nullptr, *Pt_dn = nullptr, *PT_dn = nullptr, *PT_up = nullptr, *P3_up = nullptr;
+  double *C1n = nullptr, *C4n = nullptr, *T4n = nullptr;
+};
+
+// The column update of do_move for `count` cuts, c.bchunk cuts per launch:
+// every launch runs one step of the per-cut sequence for all cuts of the
+// chunk, each with its own X1, X2 and G[0] scratch, so each cut gets exactly
+// the arithmetic of the per-cut sequence.  fill(i, ptrs) describes cut i.
+template <typename F>
+static void update_column_batched(Context& c, int rot, size_t count, F&& fill) {
+  const int chi = c.chi, Db = c.Db;
+  const long n = c.n, nn = n * n, cc = (long)chi * chi, tt = cc * Db, xn = (long)chi * n;
+  const int kc1 = rot % 4, kt1 = rot % 4, kt3 = (2 + rot) % 4, kt4 = (3 + rot) % 4, kc4 = (3 + rot) % 4;
+  double* X1 = c.X1.as<double>();
+  double* X2 = c.X2.as<double>();
+  double* G0 = c.G[0].as<double>();
+  for (size_t i0 = 0; i0 < count; i0 += c.bchunk) {
+    const int m = (int)std::min<size_t>(c.bchunk, count - i0);
+    std::vector<UpdPtrs> q(m);
+    for (int i = 0; i < m; ++i) fill(i0 + i, q[i]);
+    TableBlob t;
+    auto each = [&](auto get) {
+      const size_t at = t.w.size();
+      for (int i = 0; i < m; ++i) t.add(get(i));
+      return at;
+    };
+    auto each_inner = [&](auto get) {   // m * chi entries, problem i * chi + k
+      const size_t at = t.w.size();
+      for (int i = 0; i < m; ++i)
+        for (int k = 0; k < chi; ++k) t.add(get(i, k));
+      return at;
+    };
+    const size_t tPTup = each([&](int i) { return q[i].PT_up; });
+    const size_t tP3up = each([&](int i) { return q[i].P3_up; });
+    const size_t tA1 = each_inner([&](int i, int) { return c.C(q[i].s, kc1); });
+    const size_t tB1 = each_inner([&](int i, int k) { return c.Ta(q[i].s, kt1) + (long)k * Db; });
+    const size_t tX1 = each_inner([&](int i, int k) { return X1 + i * xn + (long)k * chi * Db; });
+    const size_t tPtup = each([&](int i) { return q[i].Pt_up; });
+    const size_t tC1n = each([&](int i) { return q[i].C1n; });
+    const size_t tA4 = each_inner([&](int i, int) { return c.C(q[i].s, kc4); });
+    const size_t tB4 = each_inner([&](int i, int k) { return c.Ta(q[i].s, kt3) + (long)k * chi * Db; });
+    const size_t tPTdn = each([&](int i) { return q[i].PT_dn; });
+    const size_t tC4n = each([&](int i) { return q[i].C4n; });
+    const size_t tTb = each([&](int i) { return c.Tb(q[i].s, kt4); });
+    const size_t tX2 = each([&](int i) { return X2 + i * nn; });
+    const size_t tAk = each([&](int i) { return c.Ak(rot, q[i].s); });
+    const size_t tAb = each([&](int i) { return c.Ab(rot, q[i].s); });
+    const size_t tG0 = each([&](int i) { return G0 + i * nn; });
+    const size_t tPtdn = each([&](int i) { return q[i].Pt_dn; });
+    const size_t tT4n = each([&](int i) { return q[i].T4n; });
+    const uint64_t* d = upload(c, t);
+    swap_last2_batched(c.st, tab_at<const double>(d, tPTup), tab_at<double>(d, tP3up), m, chi, Db, chi);
+    // C1' = (C1 T1) Pt_up
+    mm(c, PhaseTimer::OTHER, chi, Db, chi, tab_colmajor(d, tA1, chi), tab_rowmajor(d, tB1, n),
+       tab_out_rowmajor(d, tX1, Db), m * chi);
+    mm(c, PhaseTimer::OTHER, chi, chi, (int)n, rowmajor(X1, n, xn), tab_rowmajor(d, tPtup, chi),
+       tab_out_rowmajor(d, tC1n, chi), m);
+    // C4'^T = (C4 T3) PT_dn
+    mm(c, PhaseTimer::OTHER, chi, Db, chi, tab_rowmajor(d, tA4, chi), tab_rowmajor(d, tB4, Db),
+       tab_out_rowmajor(d, tX1, Db), m * chi);
+    mm(c, PhaseTimer::OTHER, chi, chi, (int)n, rowmajor(X1, n, xn), tab_rowmajor(d, tPTdn, chi),
+       tab_out_colmajor(d, tC4n, chi), m);
+    // T4' = Pt_dn^T absorb(T4 P3_up)
+    mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, tab_rowmajor(d, tTb, chi), tab_rowmajor(d, tP3up, n),
+       out_rowmajor(X2, n, nn), m);
+    const int DK = c.DK, DB = c.DB, dd = c.d;
+    const double flops = 2.0 * chi * chi * (double)DB * DB * DK * DK * dd * (DK * DK + DB * DB) * m;
+    timed(c, PhaseTimer::ABSORB, flops, [&] {
+      absorb_fused_batched(c.st, nullptr, nullptr, nullptr, nullptr, tab_at<const double>(d, tX2),
+                           tab_at<const double>(d, tAk), tab_at<const double>(d, tAb), tab_at<double>(d, tG0), m, chi,
+                           DK, DB, dd, true);
+    });
+    mm(c, PhaseTimer::EDGE, chi, (int)n, (int)n, tab_colmajor(d, tPtdn, chi), rowmajor(G0, n, nn),
+       tab_out_rowmajor(d, tT4n, n), m);
+    normalize_maxabs_batched(c.st, tab_at<double>(d, tC1n), m, cc, c.redscratch.as<double>(), c.badflag.as<int>());
+    normalize_maxabs_batched(c.st, tab_at<double>(d, tC4n), m, cc, c.redscratch.as<double>(), c.badflag.as<int>());
+    normalize_maxabs_batched(c.st, tab_at<double>(d, tT4n), m, tt, c.redscratch.as<double>(), c.badflag.as<int>());
+  }
+}
+
 // One directional move (Sec. 2.2) in the frame rotated rot quarter turns, for
 // every live replica.
 void do_move(Context& c, int rot) {
@@ -710,22 +915,46 @@ void do_move(Context& c, int rot) {
   for (int x = 0; x < Lxv; ++x) {
     column_projectors(c, rot, x, Lyv);
     std::vector<std::array<int, 2>> newdC1(c.R * Lyv), newdT4(c.R * Lyv), newdC4(c.R * Lyv);
+    // the live cuts of the column: old site s, new site t, own slot, slot above
+    struct Upd { int ry, s, t, sl, up; };
+    std::vector<Upd> ups;
     for (int r = 0; r < c.R; ++r) {
       if (c.frozen[r]) continue;
-      for (int y = 0; y < Lyv; ++y) {
-        const int s = r * c.N + view_site(c, rot, x, y);
-        const int sl = c.cut_slot[r * Lyv + y], up = c.cut_slot[r * Lyv + (y + 1) % Lyv];
+      for (int y = 0; y < Lyv; ++y)
+        ups.push_back({r * Lyv + y, r * c.N + view_site(c, rot, x, y), r * c.N + view_site(c, rot, x + 1, y),
+                       c.cut_slot[r * Lyv + y], c.cut_slot[r * Lyv + (y + 1) % Lyv]});
+    }
+    // the new tensors go to column x + 1; with one column they replace
+    // tensors other cuts still read, so they are staged first
+    auto C1n_of = [&](const Upd& u) { return direct ? c.C(u.t, kc1) : c.newC1.as<double>() + u.sl * cc; };
+    auto C4n_of = [&](const Upd& u) { return direct ? c.C(u.t, kc4) : c.newC4.as<double>() + u.sl * cc; };
+    auto T4n_of = [&](const Upd& u) { return direct ? c.Ta(u.t, kt4) : c.newT4.as<double>() + u.sl * tt; };
+    const bool batched = c.bchunk > 1 && ups.size() > 1 && absorb_fused_fits(c.DK, c.DB, c.d);
+    if (batched) {
+      update_column_batched(c, rot, ups.size(), [&](size_t i, UpdPtrs& q) {
+        const Upd& u = ups[i];
+        q.s = u.s;
+        q.Pt_up = c.Pt.as<double>() + (long)u.up * n * chi;
+        q.Pt_dn = c.Pt.as<double>() + (long)u.sl * n * chi;
+        q.PT_dn = c.PT.as<double>() + (long)u.sl * n * chi;
+        q.PT_up = c.PT.as<double>() + (long)u.up * n * chi;
+        q.P3_up = c.P3.as<double>() + (long)u.up * n * chi;
+        q.C1n = C1n_of(u);
+        q.C4n = C4n_of(u);
+        q.T4n = T4n_of(u);
+      });
+    }
+    for (const Upd& u : ups) {
+      const int s = u.s, sl = u.sl, up = u.up;
+      if (!batched) {
         double* Pt_up = c.Pt.as<double>() + (long)up * n * chi;
         double* Pt_dn = c.Pt.as<double>() + (long)sl * n * chi;
         double* PT_dn = c.PT.as<double>() + (long)sl * n * chi;
         double* P3_up = c.P3.as<double>() + (long)up * n * chi;
         swap_last2(c.st, c.PT.as<double>() + (long)up * n * chi, P3_up, chi, Db, chi);
-        // the new tensors go to column x + 1; with one column they replace
-        // tensors other cuts still read, so they are staged first
-        const int t = r * c.N + view_site(c, rot, x + 1, y);
-        double* C1n = direct ? c.C(t, kc1) : c.newC1.as<double>() + sl * cc;
-        double* C4n = direct ? c.C(t, kc4) : c.newC4.as<double>() + sl * cc;
-        double* T4n = direct ? c.Ta(t, kt4) : c.newT4.as<double>() + sl * tt;
+        double* C1n = C1n_of(u);
+        double* C4n = C4n_of(u);
+        double* T4n = T4n_of(u);
         // C1' = (C1 T1) Pt_up: X1p[c2][(t4, u)] then times Pt
         mm(c, PhaseTimer::OTHER, chi, Db, chi, colmajor(c.C(s, kc1), chi), rowmajor(c.Ta(s, kt1), n, Db),
            out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
@@ -741,11 +970,12 @@ void do_move(Context& c, int rot) {
         normalize_maxabs(c.st, C1n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
         normalize_maxabs(c.st, C4n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
         normalize_maxabs(c.st, T4n, tt, c.redscratch.as<double>(), c.badflag.as<int>());
-        newdC1[r * Lyv + y] = {c.tdim[s][kt1][1], c.nact_cut[up]};
-        newdT4[r * Lyv + y] = {c.nact_cut[sl], c.nact_cut[up]};
-        newdC4[r * Lyv + y] = {c.nact_cut[sl], c.tdim[s][kt3][0]};
       }
+      newdC1[u.ry] = {c.tdim[s][kt1][1], c.nact_cut[up]};
+      newdT4[u.ry] = {c.nact_cut[sl], c.nact_cut[up]};
+      newdC4[u.ry] = {c.nact_cut[sl], c.tdim[s][kt3][0]};
     }
+    std::vector<double*> swaps_in, swaps_out;   // batched: Ta -> Tb of the new edges
     for (int r = 0; r < c.R; ++r) {
       if (c.frozen[r]) continue;
       for (int y = 0; y < Lyv; ++y) {
@@ -758,11 +988,24 @@ void do_move(Context& c, int rot) {
           CTM_HIP(hipMemcpyAsync(c.Ta(t, kt4), c.newT4.as<double>() + sl * tt, tt * sizeof(double),
                                  hipMemcpyDeviceToDevice, c.st));
         }
-        swap_last2(c.st, c.Ta(t, kt4), c.Tb(t, kt4), chi, chi, Db);
+        if (batched) {
+          swaps_in.push_back(c.Ta(t, kt4));
+          swaps_out.push_back(c.Tb(t, kt4));
+        } else {
+          swap_last2(c.st, c.Ta(t, kt4), c.Tb(t, kt4), chi, chi, Db);
+        }
         c.cdim[t][kc1] = newdC1[r * Lyv + y];
         c.tdim[t][kt4] = newdT4[r * Lyv + y];
         c.cdim[t][kc4] = newdC4[r * Lyv + y];
       }
+    }
+    if (!swaps_in.empty()) {
+      TableBlob sw;
+      for (double* p : swaps_in) sw.add(p);
+      for (double* p : swaps_out) sw.add(p);
+      const uint64_t* d = upload(c, sw);
+      swap_last2_batched(c.st, tab_at<const double>(d, 0), tab_at<double>(d, swaps_in.size()), (int)swaps_in.size(),
+                         chi, chi, Db);
     }
   }
   c.moves += 1;
