@@ -46,12 +46,12 @@ struct AbsorbArgs {
   const double* Ak;
   const double* Ab;
   double* G;
-  // one problem per blockIdx.y: per-problem pointers (device arrays), else
-  // the single problem above
-  const double* const* Xp;
-  const double* const* Akp;
-  const double* const* Abp;
-  double* const* Gp;
+  // one problem per blockIdx.y: per-problem element offsets from the bases
+  // above (device arrays; null for a single problem)
+  const long* xo;
+  const long* ako;
+  const long* abo;
+  const long* go;
   long n;
   int chi, DK, DB, d;
   int transposed;
@@ -62,10 +62,10 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
   __shared__ double sAk[kAkElems];
   __shared__ double sAb[kAbElems];
   const int bz = blockIdx.y;
-  const double* Xg = a.Xp ? a.Xp[bz] : a.X;
-  const double* Akg = a.Akp ? a.Akp[bz] : a.Ak;
-  const double* Abg = a.Abp ? a.Abp[bz] : a.Ab;
-  double* Gg = a.Gp ? a.Gp[bz] : a.G;
+  const double* Xg = a.X + (a.xo ? a.xo[bz] : 0);
+  const double* Akg = a.Ak + (a.ako ? a.ako[bz] : 0);
+  const double* Abg = a.Ab + (a.abo ? a.abo[bz] : 0);
+  double* Gg = a.G + (a.go ? a.go[bz] : 0);
   const int DK = a.DK, DB = a.DB, d = a.d;
   const int Db = DK * DB;
   const int P = DB * DB;          // (l', u') and (r', d')
@@ -183,14 +183,14 @@ void absorb_fused(hipStream_t st, const double* X, const double* Ak, const doubl
 }
 
 void absorb_fused_batched(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G,
-                          const double* const* Xp, const double* const* Akp, const double* const* Abp,
-                          double* const* Gp, int batch, int chi, int DK, int DB, int d, bool transposed) {
+                          const long* xo, const long* ako, const long* abo, const long* go, int batch, int chi,
+                          int DK, int DB, int d, bool transposed) {
   CTM_CHECK(absorb_fused_fits(DK, DB, d), -1, "absorb_fused: block too large");
   CTM_CHECK(batch >= 1 && batch <= 65535, -1, "absorb_fused: batch out of range");
-  CTM_CHECK(batch == 1 || (Xp && Akp && Abp && Gp), -1, "absorb_fused: a batch needs per-problem pointers");
+  CTM_CHECK(batch == 1 || (xo && ako && abo && go), -1, "absorb_fused: a batch needs per-problem offsets");
   AbsorbArgs a{};
   a.X = X; a.Ak = Ak; a.Ab = Ab; a.G = G;
-  a.Xp = Xp; a.Akp = Akp; a.Abp = Abp; a.Gp = Gp;
+  a.xo = xo; a.ako = ako; a.abo = abo; a.go = go;
   a.n = (long)chi * DK * DB;
   a.chi = chi; a.DK = DK; a.DB = DB; a.d = d;
   a.transposed = transposed ? 1 : 0;

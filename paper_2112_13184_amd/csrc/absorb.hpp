@@ -16,10 +16,10 @@ void absorb_fused(hipStream_t st, const double* X, const double* Ak, const doubl
                   int DK, int DB, int d, bool transposed);
 
 // The same for `batch` problems of one shape in one launch, problem b taking
-// Xp[b], Akp[b], Abp[b] and Gp[b] (device arrays of device pointers; with
-// batch = 1 they may be null and X, Ak, Ab, G are used).
+// X + xo[b], Ak + ako[b], Ab + abo[b] and G + go[b] (device arrays of element
+// offsets; with batch = 1 they may be null).
 void absorb_fused_batched(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G,
-                          const double* const* Xp, const double* const* Akp, const double* const* Abp,
-                          double* const* Gp, int batch, int chi, int DK, int DB, int d, bool transposed);
+                          const long* xo, const long* ako, const long* abo, const long* go, int batch, int chi,
+                          int DK, int DB, int d, bool transposed);
 
 }  // namespace ctm

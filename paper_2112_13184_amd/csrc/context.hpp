@@ -117,7 +117,14 @@ struct Context {
   DevBuf ketA_r, ketA_c, ketC_r, ketC_c, braB_r, braB_c, braCn_r, braCn_c, braCt_r, braCt_c;
 
   // workspaces
-  DevBuf G[4], X1, X2, Ybuf;
+  // the four corner roles [role][slot][n][n], one allocation (so that batched
+  // launches address any corner by an offset from one base)
+  DevBuf Gall;
+  struct View {
+    void* p = nullptr;
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+  } G[4];
+  DevBuf X1, X2, Ybuf;
   DevBuf pan[8];             // n x kk panels
   DevBuf small[6];           // kk x kk
   DevBuf Svals, wvec, keff, badflag, redscratch, delta;

@@ -27,9 +27,9 @@ struct KArgs {
   long sa0, sa1, sb0, sb1, sc0, sc1;
   const int *ta0, *ta1, *tb0, *tb1, *tc0, *tc1;
   long bsa, bsb, bsc;
-  const double* const* pa;   // per-problem base pointers, else base + b * bs
-  const double* const* pb;
-  double* const* pc;
+  const long* oa;   // per-problem element offsets, else b * bs (the base stays a
+  const long* ob;   // kernel argument, so that its loads stay global ones)
+  const long* oc;
   int M, N, K;
   double alpha, beta;
   int splits, kchunk;   // split-K: each split covers kchunk of K (multiple of BK)
@@ -41,7 +41,7 @@ struct KArgs {
 
 __device__ __forceinline__ long off0(const int* t, long s, int i) { return t ? (long)t[i] : (long)i * s; }
 template <typename T>
-__device__ __forceinline__ T* batch_base(T* p, T* const* tab, long bs, int b) { return tab ? tab[b] : p + (long)b * bs; }
+__device__ __forceinline__ T* batch_base(T* p, const long* off, long bs, int b) { return p + (off ? off[b] : (long)b * bs); }
 
 // Workgroups are dispatched to the 8 XCDs round-robin by linear id; remap so
 // that each XCD runs one contiguous range of (tile, split, batch) indices.
@@ -85,8 +85,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
   const int m0 = tm_ * BM, n0 = tn_ * BN;
   const int kb = split * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
-  const double* A = batch_base(g.A, g.pa, g.bsa, b);
-  const double* B = batch_base(g.B, g.pb, g.bsb, b);
+  const double* A = batch_base(g.A, g.oa, g.bsa, b);
+  const double* B = batch_base(g.B, g.ob, g.bsb, b);
 
   // ---- per-thread load coordinates ------------------------------------
   // A tile element (r, kk): A_KC -> threads walk k fastest, else m fastest.
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
   }
 
   // ---- epilogue ----------------------------------------------------------
-  double* C = batch_base(g.C, g.pc, g.bsc, b);
+  double* C = batch_base(g.C, g.oc, g.bsc, b);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -247,7 +247,7 @@ __global__ void splitk_reduce(KArgs g) {
     int b = (int)(t / g.M);
     double s = 0.0;
     for (int k = 0; k < g.splits; ++k) s += g.ws[(((long)k * g.batch + b) * g.M + m) * g.N + n];
-    double* C = batch_base(g.C, g.pc, g.bsc, b);
+    double* C = batch_base(g.C, g.oc, g.bsc, b);
     long o = off0(g.tc0, g.sc0, m) + off0(g.tc1, g.sc1, n);
     C[o] = (g.beta == 0.0) ? s : s + g.beta * C[o];
   }
@@ -336,8 +336,8 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   const int m0 = tm_ * BM, n0 = tn_ * BN;
   const int kb = split * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
-  const double* A = batch_base(g.A, g.pa, g.bsa, b);
-  const double* B = batch_base(g.B, g.pb, g.bsb, b);
+  const double* A = batch_base(g.A, g.oa, g.bsa, b);
+  const double* B = batch_base(g.B, g.ob, g.bsb, b);
   double sa = 1.0, sb = 1.0;
   if (KIND == LP_F16) {
     sa = f16_scale(*g.amaxA);
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
     __syncthreads();
   }
 
-  double* C = batch_base(g.C, g.pc, g.bsc, b);
+  double* C = batch_base(g.C, g.oc, g.bsc, b);
   const double unscale = g.alpha / (sa * sb);
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -560,7 +560,7 @@ __global__ void k_amax_clear(unsigned* out, int n) {
 // out[which] = max(out[which], largest |x| over an R x Cn operand (FP32 bits;
 // non-negative floats order like their bit patterns).
 __global__ void k_operand_amax(const double* P, long s0, long s1, const int* t0, const int* t1, long bs,
-                               const double* const* tab, int R, int Cn, int batch, unsigned* out, int which) {
+                               const long* off, int R, int Cn, int batch, unsigned* out, int which) {
   __shared__ float red[4];
   const long per = (long)R * Cn, total = per * batch;
   // walk the unit-stride index fastest so that the scan is coalesced
@@ -570,7 +570,7 @@ __global__ void k_operand_amax(const double* P, long s0, long s1, const int* t0,
     const long bb = e / per, rem = e % per;
     const int i = rows_fast ? (int)(rem % R) : (int)(rem / Cn);
     const int j = rows_fast ? (int)(rem / R) : (int)(rem % Cn);
-    m = fmaxf(m, fabsf((float)batch_base(P, tab, bs, (int)bb)[off0(t0, s0, i) + off0(t1, s1, j)]));
+    m = fmaxf(m, fabsf((float)batch_base(P, off, bs, (int)bb)[off0(t0, s0, i) + off0(t1, s1, j)]));
   }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -616,8 +616,8 @@ void launch_typed(hipStream_t st, GemmType type, const KArgs& g, bool a_kc, bool
 __global__ __launch_bounds__(256) void k_gemm_dot(KArgs g) {
   __shared__ double red[4][16];
   const int chunk = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const double* A = batch_base(g.A, g.pa, g.bsa, b);
-  const double* B = batch_base(g.B, g.pb, g.bsb, b);
+  const double* A = batch_base(g.A, g.oa, g.bsa, b);
+  const double* B = batch_base(g.B, g.ob, g.bsb, b);
   const int k0 = chunk * g.kchunk, k1 = min(g.K, k0 + g.kchunk);
   const int mn = g.M * g.N;
   for (int o = 0; o < mn; ++o) {
@@ -665,7 +665,7 @@ int choose_splits(long tiles, int K, long kRound = 1024) {
 void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, unsigned* out) {
   hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, out, 1);
   hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, static_cast<const double*>(P.p), P.s0, P.s1, P.t0,
-                     P.t1, P.bs, reinterpret_cast<const double* const*>(P.bp), R, C, batch, out, 0);
+                     P.t1, P.bs, P.bo, R, C, batch, out, 0);
   CTM_HIP(hipGetLastError());
 }
 
@@ -676,9 +676,9 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   // is produced as C^T = B^T A^T so that those writes are contiguous.
   if (C.t0 == nullptr && C.t1 == nullptr && C.s0 == 1 && C.s1 != 1 && (long)M * N > 16) {
     Operand At, Bt;
-    At.p = B.p; At.s0 = B.s1; At.s1 = B.s0; At.t0 = B.t1; At.t1 = B.t0; At.bs = B.bs; At.bp = B.bp;
+    At.p = B.p; At.s0 = B.s1; At.s1 = B.s0; At.t0 = B.t1; At.t1 = B.t0; At.bs = B.bs; At.bo = B.bo;
     At.amax = B.amax;
-    Bt.p = A.p; Bt.s0 = A.s1; Bt.s1 = A.s0; Bt.t0 = A.t1; Bt.t1 = A.t0; Bt.bs = A.bs; Bt.bp = A.bp;
+    Bt.p = A.p; Bt.s0 = A.s1; Bt.s1 = A.s0; Bt.t0 = A.t1; Bt.t1 = A.t0; Bt.bs = A.bs; Bt.bo = A.bo;
     Bt.amax = A.amax;
     OutOperand Ct = C;
     Ct.s0 = C.s1;
@@ -695,9 +695,9 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
   g.sa0 = A.s0; g.sa1 = A.s1; g.ta0 = A.t0; g.ta1 = A.t1; g.bsa = A.bs;
   g.sb0 = B.s0; g.sb1 = B.s1; g.tb0 = B.t0; g.tb1 = B.t1; g.bsb = B.bs;
   g.sc0 = C.s0; g.sc1 = C.s1; g.tc0 = C.t0; g.tc1 = C.t1; g.bsc = C.bs;
-  g.pa = reinterpret_cast<const double* const*>(A.bp);
-  g.pb = reinterpret_cast<const double* const*>(B.bp);
-  g.pc = reinterpret_cast<double* const*>(C.bp);
+  g.oa = A.bo;
+  g.ob = B.bo;
+  g.oc = C.bo;
   g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.beta = beta; g.batch = batch;
   if (K <= 0) {   // C = beta * C
     g.splits = 1; g.kchunk = 1;
@@ -743,10 +743,10 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
     // operands without a known maximum are scanned into the workspace words
     if (!A.amax || !B.amax) hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, ws.amax, 2);
     if (!A.amax)
-      hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.A, g.sa0, g.sa1, g.ta0, g.ta1, g.bsa, g.pa,
+      hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.A, g.sa0, g.sa1, g.ta0, g.ta1, g.bsa, g.oa,
                          M, K, batch, ws.amax, 0);
     if (!B.amax)
-      hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.B, g.sb0, g.sb1, g.tb0, g.tb1, g.bsb, g.pb,
+      hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.B, g.sb0, g.sb1, g.tb0, g.tb1, g.bsb, g.ob,
                          K, N, batch, ws.amax, 1);
     CTM_HIP(hipGetLastError());
     g.amaxA = A.amax ? A.amax : ws.amax;

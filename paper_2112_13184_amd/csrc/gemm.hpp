@@ -3,9 +3,9 @@
 // Every contraction of the CTMRG sweep is written as C = alpha * A * B + beta * C
 // where each operand element (i, j) lives at
 //     base + batch * bs + (t0 ? t0[i] : i * s0) + (t1 ? t1[j] : j * s1),
-// or, for batches whose operands are not evenly spaced (the corners and
-// tensors of different sites), bp[batch] + (row and column offsets) with bp
-// a device array of one base pointer per problem.
+// or, for batches whose problems are not evenly spaced (the corners and
+// tensors of different sites), base + bo[batch] + (row and column offsets)
+// with bo a device array of one element offset per problem.
 // Plain, transposed and batched GEMMs use strides; the single-layer ket / bra
 // absorption, whose row and column indices are products of a chi index and
 // bond indices, uses separable offset tables so that the index permutation
@@ -22,7 +22,7 @@ struct Operand {
   const int* t0 = nullptr;   // row offset table (overrides s0)
   const int* t1 = nullptr;   // column offset table (overrides s1)
   long bs = 0;               // batch stride
-  const void* const* bp = nullptr;   // per-problem base pointers (device; override p and bs)
+  const long* bo = nullptr;  // per-problem element offsets from p (device; override bs)
   const unsigned* amax = nullptr;   // split FP16: largest |entry| over the batch
                                     // (FP32 bits, device), else scanned per call
 };
@@ -33,7 +33,7 @@ struct OutOperand {
   const int* t0 = nullptr;
   const int* t1 = nullptr;
   long bs = 0;
-  void* const* bp = nullptr;         // per-problem base pointers (device; override p and bs)
+  const long* bo = nullptr;  // per-problem element offsets from p (device; override bs)
 };
 
 inline Operand rowmajor(const void* p, long ld, long bs = 0) { Operand o; o.p = p; o.s0 = ld; o.s1 = 1; o.bs = bs; return o; }

@@ -476,6 +476,86 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
   }
 }
 
+// Singular values only, one small m x m matrix (m <= kSvSmallMax) per
+// workgroup: one-sided Jacobi with the whole matrix in LDS and every sweep in
+// the one launch (cyclic tournament over the columns, padded to an even count
+// with a zero column; one wave per column pair of a round; the same rotation
+// and threshold as the blocked Jacobi).  Stops after a sweep without
+// rotations or after max_sweeps; S_b (m values, descending) = column norms.
+constexpr int kSvSmallLd = kSvSmallMax;        // LDS column stride, rows past m zero
+
+__global__ __launch_bounds__(1024) void k_sv_small(const double* A, int m, double* S, double tol, int max_sweeps) {
+  __shared__ double sA[kSvSmallMax * kSvSmallLd];
+  __shared__ double sig[kSvSmallMax];
+  __shared__ int rotated;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), nw = blockDim.x >> 6;
+  const int m2 = m + (m & 1);
+  const double* Ab = A + (long)b * m * m;
+  for (int e = tid; e < m2 * kSvSmallLd; e += blockDim.x) {
+    const int col = e / kSvSmallLd, r = e % kSvSmallLd;
+    sA[e] = (col < m && r < m) ? Ab[(long)col * m + r] : 0.0;
+  }
+  constexpr int RW = kSvSmallLd / 64;           // rows per lane
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < m2 - 1; ++round) {
+      for (int q = w; q < m2 / 2; q += nw) {
+        double* ai = sA + circle(q, round, m2) * kSvSmallLd + lane;
+        double* aj = sA + circle(m2 - 1 - q, round, m2) * kSvSmallLd + lane;
+        double x[RW], y[RW];
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int t = 0; t < RW; ++t) {
+          x[t] = ai[64 * t];
+          y[t] = aj[64 * t];
+          al += x[t] * x[t];
+          be += y[t] * y[t];
+          ga += x[t] * y[t];
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        const double ab = al * be, g2 = ga * ga;
+        if (g2 > tol * tol * ab) {
+          const double dd = be - al, ad = fabs(dd);
+          const double X = dd * dd + 4.0 * g2;
+          const double r = X * rsqrt_nr(X);
+          const double inv = rsqrt_nr(2.0 * r * (r + ad));
+          const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
+#pragma unroll
+          for (int t = 0; t < RW; ++t) {
+            ai[64 * t] = cs * x[t] - sn * y[t];
+            aj[64 * t] = sn * x[t] + cs * y[t];
+          }
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int col = w; col < m; col += nw) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < RW; ++t) {
+      const double v = sA[col * kSvSmallLd + lane + 64 * t];
+      s2 += v * v;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) sig[col] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int col = tid; col < m; col += blockDim.x) {
+    int rnk = 0;
+    for (int o = 0; o < m; ++o) rnk += (sig[o] > sig[col]) || (sig[o] == sig[col] && o < col);
+    S[(long)b * m + rnk] = sig[col];
+  }
+}
+
 // Column norms -> singular values, sorted descending; X = A S^-1, Y = J.
 __global__ __launch_bounds__(256) void k_svd_finalize(const double* A, const double* J, int k, double* X,
                                                        double* S, long sstride, double* Y) {
@@ -620,6 +700,13 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
     for (int b = 0; b < batch; ++b) fprintf(stderr, " %d%s", h[0][b], h[1][b] ? "" : "(not converged)");
     fprintf(stderr, "\n");
   }
+}
+
+
+void singular_values_small(hipStream_t st, const double* A, int m, int batch, double* S) {
+  CTM_CHECK(m >= 1 && m <= kSvSmallMax && batch >= 1, -1, "singular_values_small: size");
+  hipLaunchKernelGGL(k_sv_small, dim3(batch), dim3(1024), 0, st, A, m, S, 1e-15, 30);
+  CTM_HIP(hipGetLastError());
 }
 
 }  // namespace ctm

@@ -21,6 +21,7 @@ bool smallla_fits(const SmallLA& s, int k);
 
 // Largest k (panel width / matrix order) the kernels below handle.
 constexpr int kSmallLAMaxK = 192;
+constexpr int kSvSmallMax = 128;   // largest matrix of singular_values_small
 
 void smallla_alloc(SmallLA& s, int kmax, int batch_max, long nmax);
 
@@ -40,5 +41,10 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
 // col-major, batch strides k*k; S_b = S + b * sstride (sstride >= k).
 void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, long sstride,
                 double* Y);
+
+// Singular values (descending, m per problem at S + b * m) of `batch`
+// column-major m x m matrices at A + b * m * m, m <= kSvSmallMax, by one-sided
+// Jacobi in one workgroup per matrix (A is read, not changed).
+void singular_values_small(hipStream_t st, const double* A, int m, int batch, double* S);
 
 }  // namespace ctm

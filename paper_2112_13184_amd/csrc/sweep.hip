@@ -306,7 +306,8 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   // ---- workspaces --------------------------------------------------------
   build_tables(c);
   const int Lmax0 = std::max(c.Lx, c.Ly) * c.R;   // cut slots of one column, all replicas
-  for (auto& g : c.G) g.alloc(sizeof(double) * sz.nn * Lmax0);      // one slot per cut of a column
+  c.Gall.alloc(sizeof(double) * 4 * sz.nn * Lmax0);                 // one slot per cut of a column
+  for (int q = 0; q < 4; ++q) c.G[q].p = c.Gall.as<double>() + (size_t)q * sz.nn * Lmax0;
   c.bchunk = (int)batch_chunk(sz.nn, Lmax0);
   c.X1.alloc(sizeof(double) * c.chi * c.n * c.bchunk);
   c.X2.alloc(sizeof(double) * sz.nn * c.bchunk);
@@ -401,8 +402,8 @@ static void absorb(Context& c, const double* X, const double* Ak, const double* 
 // ring wraps), so no copy out of it can still be pending.
 struct TableBlob {
   std::vector<uint64_t> w;
-  size_t add(const void* p) { w.push_back((uint64_t)(uintptr_t)p); return w.size() - 1; }
-  size_t add_int(long v) { w.push_back((uint64_t)v); return w.size() - 1; }
+  void add(const void* p) { w.push_back((uint64_t)(uintptr_t)p); }
+  void add_off(const double* p, const double* base) { w.push_back((uint64_t)(int64_t)(p - base)); }
 };
 
 static const uint64_t* upload(Context& c, const TableBlob& t) {
@@ -420,27 +421,30 @@ static const uint64_t* upload(Context& c, const TableBlob& t) {
   return d;
 }
 
+// device views of the uploaded words
 template <typename T>
-static T* const* tab_at(const uint64_t* base, size_t i) { return reinterpret_cast<T* const*>(base + i); }
+static T* const* ptrs_at(const uint64_t* d, size_t i) { return reinterpret_cast<T* const*>(d + i); }
+static const long* offs_at(const uint64_t* d, size_t i) { return reinterpret_cast<const long*>(d + i); }
 
-static Operand tab_rowmajor(const uint64_t* base, size_t i, long ld) {
-  Operand o = rowmajor(nullptr, ld);
-  o.bp = tab_at<const void>(base, i);
+// operands whose problem b starts at base + offs[b]
+static Operand off_rowmajor(const double* base, const uint64_t* d, size_t i, long ld) {
+  Operand o = rowmajor(base, ld);
+  o.bo = offs_at(d, i);
   return o;
 }
-static Operand tab_colmajor(const uint64_t* base, size_t i, long ld) {
-  Operand o = colmajor(nullptr, ld);
-  o.bp = tab_at<const void>(base, i);
+static Operand off_colmajor(const double* base, const uint64_t* d, size_t i, long ld) {
+  Operand o = colmajor(base, ld);
+  o.bo = offs_at(d, i);
   return o;
 }
-static OutOperand tab_out_rowmajor(const uint64_t* base, size_t i, long ld) {
-  OutOperand o = out_rowmajor(nullptr, ld);
-  o.bp = tab_at<void>(base, i);
+static OutOperand off_out_rowmajor(double* base, const uint64_t* d, size_t i, long ld) {
+  OutOperand o = out_rowmajor(base, ld);
+  o.bo = offs_at(d, i);
   return o;
 }
-static OutOperand tab_out_colmajor(const uint64_t* base, size_t i, long ld) {
-  OutOperand o = out_colmajor(nullptr, ld);
-  o.bp = tab_at<void>(base, i);
+static OutOperand off_out_colmajor(double* base, const uint64_t* d, size_t i, long ld) {
+  OutOperand o = out_colmajor(base, ld);
+  o.bo = offs_at(d, i);
   return o;
 }
 
@@ -472,34 +476,41 @@ void enlarged_corners(Context& c, const std::vector<CornerJob>& jobs) {
     for (const auto& jb : jobs) enlarged_corner(c, jb.s, jb.j, jb.out);
     return;
   }
+  const double* envC = c.envC.as<double>();
+  const double* envTa = c.envTa.as<double>();
+  const double* envTb = c.envTb.as<double>();
+  const double* Aket = c.Aket.as<double>();
+  const double* Abra = c.Abra.as<double>();
+  double* X2 = c.X2.as<double>();
+  double* Gall = c.Gall.as<double>();
   for (size_t i0 = 0; i0 < jobs.size(); i0 += c.bchunk) {
     const int m = (int)std::min<size_t>(c.bchunk, jobs.size() - i0);
+    const CornerJob* jb = jobs.data() + i0;
     TableBlob t;
     const size_t tC = t.w.size();
-    for (int i = 0; i < m; ++i) t.add(c.C(jobs[i0 + i].s, jobs[i0 + i].j));
+    for (int i = 0; i < m; ++i) t.add_off(c.C(jb[i].s, jb[i].j), envC);
     const size_t tTa = t.w.size();
-    for (int i = 0; i < m; ++i) t.add(c.Ta(jobs[i0 + i].s, jobs[i0 + i].j));
+    for (int i = 0; i < m; ++i) t.add_off(c.Ta(jb[i].s, jb[i].j), envTa);
     const size_t tTb = t.w.size();
-    for (int i = 0; i < m; ++i) t.add(c.Tb(jobs[i0 + i].s, (jobs[i0 + i].j + 3) % 4));
+    for (int i = 0; i < m; ++i) t.add_off(c.Tb(jb[i].s, (jb[i].j + 3) % 4), envTb);
     const size_t tX = t.w.size();
-    for (int i = 0; i < m; ++i) t.add(c.X2.as<double>() + i * nn);
+    for (int i = 0; i < m; ++i) t.add_off(X2 + i * nn, X2);
     const size_t tAk = t.w.size();
-    for (int i = 0; i < m; ++i) t.add(c.Ak(jobs[i0 + i].j, jobs[i0 + i].s));
+    for (int i = 0; i < m; ++i) t.add_off(c.Ak(jb[i].j, jb[i].s), Aket);
     const size_t tAb = t.w.size();
-    for (int i = 0; i < m; ++i) t.add(c.Ab(jobs[i0 + i].j, jobs[i0 + i].s));
+    for (int i = 0; i < m; ++i) t.add_off(c.Ab(jb[i].j, jb[i].s), Abra);
     const size_t tG = t.w.size();
-    for (int i = 0; i < m; ++i) t.add(jobs[i0 + i].out);
+    for (int i = 0; i < m; ++i) t.add_off(jb[i].out, Gall);
     const uint64_t* d = upload(c, t);
-    mm(c, PhaseTimer::OTHER, chi, (int)n, chi, tab_colmajor(d, tC, chi), tab_rowmajor(d, tTa, n),
+    mm(c, PhaseTimer::OTHER, chi, (int)n, chi, off_colmajor(envC, d, tC, chi), off_rowmajor(envTa, d, tTa, n),
        out_rowmajor(c.X1.p, n, xn), m);
-    mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, tab_rowmajor(d, tTb, chi), rowmajor(c.X1.p, n, xn),
-       out_rowmajor(c.X2.p, n, nn), m);
+    mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, off_rowmajor(envTb, d, tTb, chi), rowmajor(c.X1.p, n, xn),
+       out_rowmajor(X2, n, nn), m);
     const int DK = c.DK, DB = c.DB, dd = c.d;
     const double flops = 2.0 * chi * chi * (double)DB * DB * DK * DK * dd * (DK * DK + DB * DB) * m;
     timed(c, PhaseTimer::ABSORB, flops, [&] {
-      absorb_fused_batched(c.st, nullptr, nullptr, nullptr, nullptr, tab_at<const double>(d, tX),
-                           tab_at<const double>(d, tAk), tab_at<const double>(d, tAb), tab_at<double>(d, tG), m, chi,
-                           DK, DB, dd, false);
+      absorb_fused_batched(c.st, X2, Aket, Abra, Gall, offs_at(d, tX), offs_at(d, tAk), offs_at(d, tAb),
+                           offs_at(d, tG), m, chi, DK, DB, dd, false);
     });
   }
 }
@@ -832,74 +843,91 @@ struct UpdPtrs {
 // chunk, each with its own X1, X2 and G[0] scratch, so each cut gets exactly
 // the arithmetic of the per-cut sequence.  fill(i, ptrs) describes cut i.
 template <typename F>
-static void update_column_batched(Context& c, int rot, size_t count, F&& fill) {
+static void update_column_batched(Context& c, int rot, bool direct, size_t count, F&& fill) {
   const int chi = c.chi, Db = c.Db;
   const long n = c.n, nn = n * n, cc = (long)chi * chi, tt = cc * Db, xn = (long)chi * n;
   const int kc1 = rot % 4, kt1 = rot % 4, kt3 = (2 + rot) % 4, kt4 = (3 + rot) % 4, kc4 = (3 + rot) % 4;
   double* X1 = c.X1.as<double>();
   double* X2 = c.X2.as<double>();
   double* G0 = c.G[0].as<double>();
+  double* envC = c.envC.as<double>();
+  double* envTa = c.envTa.as<double>();
+  const double* envTb = c.envTb.as<double>();
+  const double* Pt = c.Pt.as<double>();
+  const double* PT = c.PT.as<double>();
+  const double* P3 = c.P3.as<double>();
+  const double* Aket = c.Aket.as<double>();
+  const double* Abra = c.Abra.as<double>();
+  // where the new tensors go (see do_move)
+  double* C1base = direct ? envC : c.newC1.as<double>();
+  double* C4base = direct ? envC : c.newC4.as<double>();
+  double* T4base = direct ? envTa : c.newT4.as<double>();
   for (size_t i0 = 0; i0 < count; i0 += c.bchunk) {
     const int m = (int)std::min<size_t>(c.bchunk, count - i0);
     std::vector<UpdPtrs> q(m);
     for (int i = 0; i < m; ++i) fill(i0 + i, q[i]);
     TableBlob t;
-    auto each = [&](auto get) {
+    auto each = [&](auto get) {   // m entries
       const size_t at = t.w.size();
-      for (int i = 0; i < m; ++i) t.add(get(i));
+      for (int i = 0; i < m; ++i) get(i);
       return at;
     };
     auto each_inner = [&](auto get) {   // m * chi entries, problem i * chi + k
       const size_t at = t.w.size();
       for (int i = 0; i < m; ++i)
-        for (int k = 0; k < chi; ++k) t.add(get(i, k));
+        for (int k = 0; k < chi; ++k) get(i, k);
       return at;
     };
-    const size_t tPTup = each([&](int i) { return q[i].PT_up; });
-    const size_t tP3up = each([&](int i) { return q[i].P3_up; });
-    const size_t tA1 = each_inner([&](int i, int) { return c.C(q[i].s, kc1); });
-    const size_t tB1 = each_inner([&](int i, int k) { return c.Ta(q[i].s, kt1) + (long)k * Db; });
-    const size_t tX1 = each_inner([&](int i, int k) { return X1 + i * xn + (long)k * chi * Db; });
-    const size_t tPtup = each([&](int i) { return q[i].Pt_up; });
-    const size_t tC1n = each([&](int i) { return q[i].C1n; });
-    const size_t tA4 = each_inner([&](int i, int) { return c.C(q[i].s, kc4); });
-    const size_t tB4 = each_inner([&](int i, int k) { return c.Ta(q[i].s, kt3) + (long)k * chi * Db; });
-    const size_t tPTdn = each([&](int i) { return q[i].PT_dn; });
-    const size_t tC4n = each([&](int i) { return q[i].C4n; });
-    const size_t tTb = each([&](int i) { return c.Tb(q[i].s, kt4); });
-    const size_t tX2 = each([&](int i) { return X2 + i * nn; });
-    const size_t tAk = each([&](int i) { return c.Ak(rot, q[i].s); });
-    const size_t tAb = each([&](int i) { return c.Ab(rot, q[i].s); });
-    const size_t tG0 = each([&](int i) { return G0 + i * nn; });
-    const size_t tPtdn = each([&](int i) { return q[i].Pt_dn; });
-    const size_t tT4n = each([&](int i) { return q[i].T4n; });
+    // pointer tables (edge transposes, normalisation)
+    const size_t pPTup = each([&](int i) { t.add(q[i].PT_up); });
+    const size_t pP3up = each([&](int i) { t.add(q[i].P3_up); });
+    const size_t pC1n = each([&](int i) { t.add(q[i].C1n); });
+    const size_t pC4n = each([&](int i) { t.add(q[i].C4n); });
+    const size_t pT4n = each([&](int i) { t.add(q[i].T4n); });
+    // offset tables (GEMM, absorption)
+    const size_t oA1 = each_inner([&](int i, int) { t.add_off(c.C(q[i].s, kc1), envC); });
+    const size_t oB1 = each_inner([&](int i, int k) { t.add_off(c.Ta(q[i].s, kt1) + (long)k * Db, envTa); });
+    const size_t oX1 = each_inner([&](int i, int k) { t.add_off(X1 + i * xn + (long)k * chi * Db, X1); });
+    const size_t oPtup = each([&](int i) { t.add_off(q[i].Pt_up, Pt); });
+    const size_t oC1n = each([&](int i) { t.add_off(q[i].C1n, C1base); });
+    const size_t oA4 = each_inner([&](int i, int) { t.add_off(c.C(q[i].s, kc4), envC); });
+    const size_t oB4 = each_inner([&](int i, int k) { t.add_off(c.Ta(q[i].s, kt3) + (long)k * chi * Db, envTa); });
+    const size_t oPTdn = each([&](int i) { t.add_off(q[i].PT_dn, PT); });
+    const size_t oC4n = each([&](int i) { t.add_off(q[i].C4n, C4base); });
+    const size_t oTb = each([&](int i) { t.add_off(c.Tb(q[i].s, kt4), envTb); });
+    const size_t oP3up = each([&](int i) { t.add_off(q[i].P3_up, P3); });
+    const size_t oX2 = each([&](int i) { t.add_off(X2 + i * nn, X2); });
+    const size_t oAk = each([&](int i) { t.add_off(c.Ak(rot, q[i].s), Aket); });
+    const size_t oAb = each([&](int i) { t.add_off(c.Ab(rot, q[i].s), Abra); });
+    const size_t oG0 = each([&](int i) { t.add_off(G0 + i * nn, G0); });
+    const size_t oPtdn = each([&](int i) { t.add_off(q[i].Pt_dn, Pt); });
+    const size_t oT4n = each([&](int i) { t.add_off(q[i].T4n, T4base); });
     const uint64_t* d = upload(c, t);
-    swap_last2_batched(c.st, tab_at<const double>(d, tPTup), tab_at<double>(d, tP3up), m, chi, Db, chi);
+    swap_last2_batched(c.st, ptrs_at<const double>(d, pPTup), ptrs_at<double>(d, pP3up), m, chi, Db, chi);
     // C1' = (C1 T1) Pt_up
-    mm(c, PhaseTimer::OTHER, chi, Db, chi, tab_colmajor(d, tA1, chi), tab_rowmajor(d, tB1, n),
-       tab_out_rowmajor(d, tX1, Db), m * chi);
-    mm(c, PhaseTimer::OTHER, chi, chi, (int)n, rowmajor(X1, n, xn), tab_rowmajor(d, tPtup, chi),
-       tab_out_rowmajor(d, tC1n, chi), m);
+    mm(c, PhaseTimer::OTHER, chi, Db, chi, off_colmajor(envC, d, oA1, chi), off_rowmajor(envTa, d, oB1, n),
+       off_out_rowmajor(X1, d, oX1, Db), m * chi);
+    mm(c, PhaseTimer::OTHER, chi, chi, (int)n, rowmajor(X1, n, xn), off_rowmajor(Pt, d, oPtup, chi),
+       off_out_rowmajor(C1base, d, oC1n, chi), m);
     // C4'^T = (C4 T3) PT_dn
-    mm(c, PhaseTimer::OTHER, chi, Db, chi, tab_rowmajor(d, tA4, chi), tab_rowmajor(d, tB4, Db),
-       tab_out_rowmajor(d, tX1, Db), m * chi);
-    mm(c, PhaseTimer::OTHER, chi, chi, (int)n, rowmajor(X1, n, xn), tab_rowmajor(d, tPTdn, chi),
-       tab_out_colmajor(d, tC4n, chi), m);
+    mm(c, PhaseTimer::OTHER, chi, Db, chi, off_rowmajor(envC, d, oA4, chi), off_rowmajor(envTa, d, oB4, Db),
+       off_out_rowmajor(X1, d, oX1, Db), m * chi);
+    mm(c, PhaseTimer::OTHER, chi, chi, (int)n, rowmajor(X1, n, xn), off_rowmajor(PT, d, oPTdn, chi),
+       off_out_colmajor(C4base, d, oC4n, chi), m);
     // T4' = Pt_dn^T absorb(T4 P3_up)
-    mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, tab_rowmajor(d, tTb, chi), tab_rowmajor(d, tP3up, n),
+    mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, off_rowmajor(envTb, d, oTb, chi), off_rowmajor(P3, d, oP3up, n),
        out_rowmajor(X2, n, nn), m);
     const int DK = c.DK, DB = c.DB, dd = c.d;
     const double flops = 2.0 * chi * chi * (double)DB * DB * DK * DK * dd * (DK * DK + DB * DB) * m;
     timed(c, PhaseTimer::ABSORB, flops, [&] {
-      absorb_fused_batched(c.st, nullptr, nullptr, nullptr, nullptr, tab_at<const double>(d, tX2),
-                           tab_at<const double>(d, tAk), tab_at<const double>(d, tAb), tab_at<double>(d, tG0), m, chi,
-                           DK, DB, dd, true);
+      absorb_fused_batched(c.st, X2, Aket, Abra, G0, offs_at(d, oX2), offs_at(d, oAk), offs_at(d, oAb),
+                           offs_at(d, oG0), m, chi, DK, DB, dd, true);
     });
-    mm(c, PhaseTimer::EDGE, chi, (int)n, (int)n, tab_colmajor(d, tPtdn, chi), rowmajor(G0, n, nn),
-       tab_out_rowmajor(d, tT4n, n), m);
-    normalize_maxabs_batched(c.st, tab_at<double>(d, tC1n), m, cc, c.redscratch.as<double>(), c.badflag.as<int>());
-    normalize_maxabs_batched(c.st, tab_at<double>(d, tC4n), m, cc, c.redscratch.as<double>(), c.badflag.as<int>());
-    normalize_maxabs_batched(c.st, tab_at<double>(d, tT4n), m, tt, c.redscratch.as<double>(), c.badflag.as<int>());
+    mm(c, PhaseTimer::EDGE, chi, (int)n, (int)n, off_colmajor(Pt, d, oPtdn, chi), rowmajor(G0, n, nn),
+       off_out_rowmajor(T4base, d, oT4n, n), m);
+    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pC1n), m, cc, c.redscratch.as<double>(), c.badflag.as<int>());
+    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pC4n), m, cc, c.redscratch.as<double>(), c.badflag.as<int>());
+    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pT4n), m, tt, c.redscratch.as<double>(), c.badflag.as<int>());
   }
 }
 
@@ -931,7 +959,7 @@ void do_move(Context& c, int rot) {
     auto T4n_of = [&](const Upd& u) { return direct ? c.Ta(u.t, kt4) : c.newT4.as<double>() + u.sl * tt; };
     const bool batched = c.bchunk > 1 && ups.size() > 1 && absorb_fused_fits(c.DK, c.DB, c.d);
     if (batched) {
-      update_column_batched(c, rot, ups.size(), [&](size_t i, UpdPtrs& q) {
+      update_column_batched(c, rot, direct, ups.size(), [&](size_t i, UpdPtrs& q) {
         const Upd& u = ups[i];
         q.s = u.s;
         q.Pt_up = c.Pt.as<double>() + (long)u.up * n * chi;
@@ -1004,7 +1032,7 @@ void do_move(Context& c, int rot) {
       for (double* p : swaps_in) sw.add(p);
       for (double* p : swaps_out) sw.add(p);
       const uint64_t* d = upload(c, sw);
-      swap_last2_batched(c.st, tab_at<const double>(d, 0), tab_at<double>(d, swaps_in.size()), (int)swaps_in.size(),
+      swap_last2_batched(c.st, ptrs_at<const double>(d, 0), ptrs_at<double>(d, swaps_in.size()), (int)swaps_in.size(),
                          chi, chi, Db);
     }
   }
@@ -1017,6 +1045,10 @@ static const int kSweepRot[4] = {0, 2, 1, 3};   // left, right, up, down
 static void corner_spectra(Context& c, double* out) {
   const long cc = (long)c.chi * c.chi;
   timed(c, PhaseTimer::OTHER, 0.0, [&] {
+    if (c.chi <= kSvSmallMax) {   // one workgroup per corner, the corners read in place
+      singular_values_small(c.st, c.envC.as<double>(), c.chi, 4 * c.NS(), out);
+      return;
+    }
     CTM_HIP(hipMemcpyAsync(c.cornerscratch.p, c.envC.p, sizeof(double) * 4 * c.NS() * cc, hipMemcpyDeviceToDevice,
                            c.st));
     for (int i = 0; i < 4 * c.NS(); i += 64)

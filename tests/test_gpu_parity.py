@@ -204,6 +204,30 @@ def test_sweeps_energy_and_spectra(lib, Lx, Ly, D, chi, seed):
         assert np.max(np.abs(rho - ref)) < max(1e-10, 20 * sens_r)
 
 
+@pytest.mark.parametrize("chi", [24, 130])
+def test_sweep_delta_is_the_corner_spectra_change(lib, chi):
+    """The stop rule's measure (Sec. 2.2 convergence of the corner spectra):
+    a sweep reports the largest, over corners, of sum |s_new - s_old| of the
+    normalised singular values of each corner.  Checked against NumPy's SVD of
+    the corners read back before and after the sweep; chi = 24 takes the
+    one-workgroup Jacobi, chi = 130 the library SVD."""
+    A = wl.random_itps(2, 2, 3, 2, seed=11)
+    ctx = lib.Ctm(A, 2, 2, 3, chi, rsvd_oversample=16, rsvd_power_iters=1, seed=3)
+    for _ in range(2):
+        ctx.ctm_sweep(1, 0.0)
+
+    def spectra_all():
+        return np.concatenate([_spectra(ctx.ctm_get_env(i)[0], chi) for i in range(4)])
+
+    before = spectra_all()
+    n, delta, _ = ctx.ctm_sweep(1, 0.0)
+    after = spectra_all()
+    ref = np.max(np.sum(np.abs(after - before), axis=1))
+    assert n == 1
+    assert ref > 1e-8
+    assert abs(delta - ref) <= 1e-12 + 1e-9 * ref, (delta, ref)
+
+
 def test_classical_ising_closed_forms(lib):
     beta = 0.5
     a, b, w = wl.ising_classical(beta)
