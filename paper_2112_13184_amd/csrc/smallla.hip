@@ -476,34 +476,41 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
   }
 }
 
-// Singular values only, one small m x m matrix (m <= kSvSmallMax) per
-// workgroup: one-sided Jacobi with the whole matrix in LDS and every sweep in
-// the one launch (cyclic tournament over the columns, padded to an even count
-// with a zero column; one wave per column pair of a round; the same rotation
-// and threshold as the blocked Jacobi).  Stops after a sweep without
-// rotations or after max_sweeps; S_b (m values, descending) = column norms.
-constexpr int kSvSmallLd = kSvSmallMax;        // LDS column stride, rows past m zero
-
-__global__ __launch_bounds__(1024) void k_sv_small(const double* A, int m, double* S, double tol, int max_sweeps) {
-  __shared__ double sA[kSvSmallMax * kSvSmallLd];
-  __shared__ double sig[kSvSmallMax];
+// One-sided Jacobi of one small m x m matrix per workgroup, the whole matrix
+// in LDS (column stride LD, rows past m zero) and every sweep in the one
+// launch: cyclic tournament over the columns (padded to an even count with a
+// zero column), one wave per column pair of a round, the same rotation and
+// threshold as the blocked Jacobi.  Stops after a sweep without rotations or
+// after max_sweeps.  VEC = false (m <= 128): S_b (m values, descending) = the
+// column norms.  VEC = true (m <= 64): the rotations are also accumulated in
+// J (from the identity); A_b and J_b are written back (column-major, ld m)
+// for the finishing kernel, as after the blocked Jacobi.
+template <int LD, bool VEC>
+__global__ __launch_bounds__(1024) void k_jacobi_onewg(double* A, int m, double* S, double* J, double tol,
+                                                       int max_sweeps) {
+  constexpr int NCOL = LD;                       // columns held (m rounded up to even <= LD)
+  __shared__ double sA[NCOL * LD];
+  __shared__ double sJ[VEC ? NCOL * LD : 1];
+  __shared__ double sig[NCOL];
   __shared__ int rotated;
   const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), nw = blockDim.x >> 6;
   const int m2 = m + (m & 1);
-  const double* Ab = A + (long)b * m * m;
-  for (int e = tid; e < m2 * kSvSmallLd; e += blockDim.x) {
-    const int col = e / kSvSmallLd, r = e % kSvSmallLd;
+  double* Ab = A + (long)b * m * m;
+  for (int e = tid; e < m2 * LD; e += blockDim.x) {
+    const int col = e / LD, r = e % LD;
     sA[e] = (col < m && r < m) ? Ab[(long)col * m + r] : 0.0;
+    if (VEC) sJ[e] = (col == r && col < m) ? 1.0 : 0.0;
   }
-  constexpr int RW = kSvSmallLd / 64;           // rows per lane
+  constexpr int RW = LD / 64;                    // rows per lane
   for (int sw = 0; sw < max_sweeps; ++sw) {
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int round = 0; round < m2 - 1; ++round) {
       for (int q = w; q < m2 / 2; q += nw) {
-        double* ai = sA + circle(q, round, m2) * kSvSmallLd + lane;
-        double* aj = sA + circle(m2 - 1 - q, round, m2) * kSvSmallLd + lane;
+        const int ci = circle(q, round, m2), cj = circle(m2 - 1 - q, round, m2);
+        double* ai = sA + ci * LD + lane;
+        double* aj = sA + cj * LD + lane;
         double x[RW], y[RW];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -529,6 +536,16 @@ __global__ __launch_bounds__(1024) void k_sv_small(const double* A, int m, doubl
             ai[64 * t] = cs * x[t] - sn * y[t];
             aj[64 * t] = sn * x[t] + cs * y[t];
           }
+          if (VEC) {
+            double* ji = sJ + ci * LD + lane;
+            double* jj = sJ + cj * LD + lane;
+#pragma unroll
+            for (int t = 0; t < RW; ++t) {
+              const double u = ji[64 * t], v = jj[64 * t];
+              ji[64 * t] = cs * u - sn * v;
+              jj[64 * t] = sn * u + cs * v;
+            }
+          }
           if (lane == 0) rotated = 1;
         }
       }
@@ -538,11 +555,20 @@ __global__ __launch_bounds__(1024) void k_sv_small(const double* A, int m, doubl
     __syncthreads();
     if (!any) break;
   }
+  if (VEC) {
+    double* Jb = J + (long)b * m * m;
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int col = e / m, r = e % m;
+      Ab[e] = sA[col * LD + r];
+      Jb[e] = sJ[col * LD + r];
+    }
+    return;
+  }
   for (int col = w; col < m; col += nw) {
     double s2 = 0.0;
 #pragma unroll
     for (int t = 0; t < RW; ++t) {
-      const double v = sA[col * kSvSmallLd + lane + 64 * t];
+      const double v = sA[col * LD + lane + 64 * t];
       s2 += v * v;
     }
     s2 = wave_sum(s2);
@@ -555,6 +581,8 @@ __global__ __launch_bounds__(1024) void k_sv_small(const double* A, int m, doubl
     S[(long)b * m + rnk] = sig[col];
   }
 }
+
+constexpr int kJacobiOneWgMaxK = 64;   // SVD with vectors in one workgroup up to this k
 
 // Column norms -> singular values, sorted descending; X = A S^-1, Y = J.
 __global__ __launch_bounds__(256) void k_svd_finalize(const double* A, const double* J, int k, double* X,
@@ -659,11 +687,19 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   if (nb & 1) ++nb;
   if (nb < 2) nb = 2;
   double* J = s.J.as<double>();
+  const double tol = 1e-15;
+  if (k <= kJacobiOneWgMaxK) {
+    // every sweep of a problem in one workgroup: one launch, no host reads
+    hipLaunchKernelGGL((k_jacobi_onewg<64, true>), dim3(batch), dim3(1024), 0, st, A, k, nullptr, J, tol, 14);
+    CTM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, sstride, Y);
+    CTM_HIP(hipGetLastError());
+    return;
+  }
   int* conv = s.flag.as<int>() + 64;
   int* nsweep = s.flag.as<int>() + 192;
   double* off = s.off.as<double>();
   hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, off, conv, nsweep);
-  const double tol = 1e-15;
   // at most 14 sweeps; most problems reach the tolerance in 9 (the last one
   // without rotations), a few in 10, so the convergence flags are read back
   // after 9 sweeps and then after each further one (rounds of a converged
@@ -705,7 +741,9 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
 
 void singular_values_small(hipStream_t st, const double* A, int m, int batch, double* S) {
   CTM_CHECK(m >= 1 && m <= kSvSmallMax && batch >= 1, -1, "singular_values_small: size");
-  hipLaunchKernelGGL(k_sv_small, dim3(batch), dim3(1024), 0, st, A, m, S, 1e-15, 30);
+  // the kernel reads A and writes only S
+  hipLaunchKernelGGL((k_jacobi_onewg<kSvSmallMax, false>), dim3(batch), dim3(1024), 0, st, const_cast<double*>(A), m, S,
+                     nullptr, 1e-15, 30);
   CTM_HIP(hipGetLastError());
 }
 
