@@ -278,21 +278,25 @@ __global__ __launch_bounds__(256) void k_trinv(const double* R, const double* ma
       }
     }
   }
+  // a dropped direction c gets a zero column, so that Y U^-1 has a zero
+  // column there (the product applies the mask)
+  const bool keep = mb[c] != 0.0;
   double* out = Rinv + b * kk2 + (long)c * k;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int i = lane + 64 * q;
-    if (i < k) out[i] = (i <= c) ? xo[q] : 0.0;
+    if (i < k) out[i] = (keep && i <= c) ? xo[q] : 0.0;
   }
 }
 
-// dst_b = src_b with column j scaled by mask_b[j] (column-major n x k panels).
+// dst_b = src_b with column j scaled by mask_b[j] (column-major n x k panels;
+// mask null: a plain copy).
 __global__ void k_copy_panels(const double* src, long sstride, double* dst, long dstride, int n, int k,
                               const double* mask) {
   const int b = blockIdx.y;
   const long elems = (long)n * k;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < elems; e += (long)gridDim.x * blockDim.x)
-    dst[b * dstride + e] = src[b * sstride + e] * mask[(long)b * k + e / n];
+    dst[b * dstride + e] = mask ? src[b * sstride + e] * mask[(long)b * k + e / n] : src[b * sstride + e];
 }
 
 // ---------------------------------------------------------------------------
@@ -649,14 +653,19 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
   double* Ri = s.Rinv.as<double>();
   double* tmp = s.tmp.as<double>();
   double* Rtmp = s.Rtmp.as<double>();
+  // the passes alternate between Y and the scratch panels (P holds the
+  // current basis); an odd pass count ends with one copy back into Y
+  double* P = Y;
+  double* Q = tmp;
+  long pstride = ystride, qstride = (long)n * k;
   for (int pass = 0; pass < passes; ++pass) {
     // the accumulated factor alternates between Racc and Rtmp so that the
     // last pass leaves it in Racc; the first pass writes its R there directly
     double* rdst = ((passes - 1 - pass) % 2 == 0) ? Racc : Rtmp;
     double* rsrc = (rdst == Racc) ? Rtmp : Racc;
     double* rout = (Racc && pass == 0) ? rdst : R;
-    // G = Y^T Y
-    gemm(st, GemmType::F64, k, k, n, 1.0, rowmajor(Y, n, ystride), colmajor(Y, n, ystride), 0.0,
+    // G = P^T P
+    gemm(st, GemmType::F64, k, k, n, 1.0, rowmajor(P, n, pstride), colmajor(P, n, pstride), 0.0,
          out_colmajor(G, k, kk2), batch, ws);
     // the shifted pass never drops; later passes drop directions whose pivot is
     // below 1e-14 of the largest (they lie below any projector cutoff).  Only
@@ -668,14 +677,18 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
     CTM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_trinv, dim3((k + 3) / 4, batch), dim3(256), 0, st, rout, s.mask.as<double>(), k, Ri);
     CTM_HIP(hipGetLastError());
-    gemm(st, GemmType::F64, n, k, k, 1.0, colmajor(Y, n, ystride), colmajor(Ri, k, kk2), 0.0,
-         out_colmajor(tmp, n, (long)n * k), batch, ws);
-    hipLaunchKernelGGL(k_copy_panels, dim3(256, batch), dim3(256), 0, st, tmp, (long)n * k, Y, ystride, n, k,
-                       s.mask.as<double>());
-    CTM_HIP(hipGetLastError());
+    // Q = P U^-1 into the other buffer (dropped directions come out zero)
+    gemm(st, GemmType::F64, n, k, k, 1.0, colmajor(P, n, pstride), colmajor(Ri, k, kk2), 0.0,
+         out_colmajor(Q, n, qstride), batch, ws);
+    std::swap(P, Q);
+    std::swap(pstride, qstride);
     if (Racc && pass > 0)
       gemm(st, GemmType::F64, k, k, k, 1.0, colmajor(R, k, kk2), colmajor(rsrc, k, kk2), 0.0,
            out_colmajor(rdst, k, kk2), batch, ws);
+  }
+  if (P != Y) {
+    hipLaunchKernelGGL(k_copy_panels, dim3(256, batch), dim3(256), 0, st, P, pstride, Y, ystride, n, k, nullptr);
+    CTM_HIP(hipGetLastError());
   }
 }
 
