@@ -57,6 +57,32 @@ def test_enlarged_corner_parity(lib, layers, D, chi):
             assert rel_err(G, ref) < 1e-12, (site, j)
 
 
+def test_d8_chi256_enlarged_corner_blocks(lib):
+    """The D=8, chi=256 configuration (double-layer bond 64, n = 16384), whose
+    enlarged corners take the table-addressed absorption GEMMs instead of the
+    fused kernel: sampled blocks of two corners (3 next-leg indices by 3
+    prev-leg indices, all ket/bra pairs of each) against the oracle's
+    definition (Sec. 2.2) evaluated on the same slices, 1e-12 relative."""
+    D, chi = 8, 256
+    Db = D * D
+    A = wl.random_itps(2, 2, D, 2, seed=3)
+    ctx = lib.Ctm(A, 2, 2, D, chi, rsvd_oversample=64, rsvd_power_iters=1, seed=12)
+    ora = Environment(A, 2, 2, chi=chi, layers=2)
+    inject(ora, ctx, random_env(2, 2, chi, Db, seed=9))
+    rng = np.random.default_rng(0)
+    for site, j in ((0, 0), (3, 2)):
+        G = ctx.ctm_enlarged_corner(j, site)
+        assert G.shape == (chi * Db, chi * Db)
+        cn = np.sort(rng.choice(chi, 3, replace=False))
+        cp = np.sort(rng.choice(chi, 3, replace=False))
+        C, Tn, Tp = ora.C[site][j], ora.T[site][j], ora.T[site][(j - 1) % 4]
+        ref = enlarged_corner(C, Tn[:, cn, :], Tp[cp, :, :], ora.site(site, j), 2)
+        rows = (cn[:, None] * Db + np.arange(Db)).reshape(-1)
+        cols = (cp[:, None] * Db + np.arange(Db)).reshape(-1)
+        assert rel_err(G[np.ix_(rows, cols)], ref) < 1e-12, (site, j)
+        del G
+
+
 @pytest.mark.parametrize("mode", ["rsvd", "dense"])
 def test_projectors_parity(lib, mode):
     D, chi, p, q, seed = 2, 10, 6, 2, 21
