@@ -28,11 +28,17 @@ namespace {
 
 constexpr int kCholThreads = 1024;
 constexpr int kCholT = 32;                                       // threads as a kCholT x kCholT grid
-constexpr int kCholB = (kSmallLAMaxK + kCholT - 1) / kCholT;     // row / column blocks per thread
+// row / column blocks per thread: 6 up to k = 192, 10 up to k = 320 (the
+// larger form keeps 55 blocks per thread and spills part of them)
+constexpr int kCholBSmall = 6;
+constexpr int kCholBLarge = (kSmallLAMaxK + kCholT - 1) / kCholT;
 static_assert(kCholT * kCholT == kCholThreads, "k_chol: thread grid");
 // Jacobi: columns per block (one wave per pair of a round, 16 blocks at k = 192)
 constexpr int kJacobiMaxBS = 12;
-constexpr int kJacobiRows = (kSmallLAMaxK + 63) / 64;   // rows per lane
+// rows per lane of the triangular inverse and the Jacobi rounds: 3 up to
+// k = 192, 5 up to k = 320
+constexpr int kRowsSmall = 3;
+constexpr int kRowsLarge = (kSmallLAMaxK + 63) / 64;
 
 
 __device__ double block_reduce(double v, bool is_max, double* sh) {
@@ -50,18 +56,18 @@ __device__ double block_reduce(double v, bool is_max, double* sh) {
 __device__ __forceinline__ int tri(int i, int l) { return i * (i + 1) / 2 + l; }
 
 // Register blocks of one k_chol thread: row block a, column block c, a >= c.
-constexpr int kCholNB = kCholB * (kCholB + 1) / 2;
+template <int KB> struct CholBlocks { static constexpr int NB = KB * (KB + 1) / 2; };
 __host__ __device__ constexpr int cblk(int a, int c) { return a * (a + 1) / 2 + c; }
 
 // Column j (in column block JB) -> LDS, by the threads that hold it, with
 // the rows at and above the pivot taken as zero so that the update needs no
 // masks of its own; the thread holding the pivot also stores it and its
 // reciprocal (computed once per step instead of once per thread).
-template <int JB>
-__device__ __forceinline__ void chol_publish(const double (&val)[kCholNB], double* cj, int tx, int j,
+template <int KB, int JB>
+__device__ __forceinline__ void chol_publish(const double (&val)[CholBlocks<KB>::NB], double* cj, int tx, int j,
                                              double* pv, double* iv) {
 #pragma unroll
-  for (int a = JB; a < kCholB; ++a) {
+  for (int a = JB; a < KB; ++a) {
     const int i = tx + kCholT * a;
     cj[i] = (i > j) ? val[cblk(a, JB)] : 0.0;
   }
@@ -76,17 +82,17 @@ __device__ __forceinline__ void chol_publish(const double (&val)[kCholNB], doubl
 // column is zero at and above the pivot and outside k x k, so entries right
 // of and below the pivot lose fi * fl and all others lose exactly zero.
 // Blocks left of JB are finished and not touched.
-template <int JB>
-__device__ __forceinline__ void chol_update(double (&val)[kCholNB], const double* cj, double inv, int tx,
+template <int KB, int JB>
+__device__ __forceinline__ void chol_update(double (&val)[CholBlocks<KB>::NB], const double* cj, double inv, int tx,
                                             int ty) {
-  double fl[kCholB], fi[kCholB];
+  double fl[KB], fi[KB];
 #pragma unroll
-  for (int c = JB; c < kCholB; ++c) {
+  for (int c = JB; c < KB; ++c) {
     fl[c] = cj[ty + kCholT * c] * inv;
     fi[c] = cj[tx + kCholT * c];
   }
 #pragma unroll
-  for (int a = JB; a < kCholB; ++a)
+  for (int a = JB; a < KB; ++a)
 #pragma unroll
     for (int c = JB; c <= a; ++c) val[cblk(a, c)] -= fi[a] * fl[c];
 }
@@ -106,16 +112,18 @@ __device__ __forceinline__ void chol_update(double (&val)[kCholNB], const double
 // specialised on the block of j, so finished blocks cost nothing.  R is
 // written through an LDS tile, 32 rows of L at a time, so that it is stored
 // along contiguous columns.
+template <int KB>
 __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, int pass, int shifted,
                                                         int check_id, double shift_scale, double drop_rel,
                                                         double* Rout, double* mask, int* flag) {
-  __shared__ double col[2][kCholB * kCholT];
+  constexpr int NB = CholBlocks<KB>::NB;
+  __shared__ double col[2][KB * kCholT];
   __shared__ double pv[2], iv[2];
-  __shared__ double tile[kCholT][kCholB * kCholT + 1];
-  __shared__ double piv[kSmallLAMaxK];
+  __shared__ double tile[kCholT][KB * kCholT + 1];
+  __shared__ double piv[KB * kCholT];
   __shared__ double red[16];
   __shared__ int bad;
-  __shared__ unsigned char dropped[kSmallLAMaxK];
+  __shared__ unsigned char dropped[KB * kCholT];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int tx = tid % kCholT, ty = tid / kCholT;
   const long kk2 = (long)k * k;
@@ -127,10 +135,10 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   const double s = shifted ? shift_scale * tr : 0.0;
   // val[cblk(a, c)] = entry (row tx + 32 a, column ty + 32 c); entries above
   // the diagonal or outside k x k start at zero and are never output
-  double val[kCholNB];
+  double val[NB];
   double dev = 0.0;
 #pragma unroll
-  for (int a = 0; a < kCholB; ++a)
+  for (int a = 0; a < KB; ++a)
 #pragma unroll
     for (int c = 0; c <= a; ++c) {
       const int i = tx + kCholT * a, l = ty + kCholT * c;
@@ -155,12 +163,13 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     const int jb = j / kCholT;
     if (ty == j % kCholT) {
       switch (jb) {
-        case 0: chol_publish<0>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
-        case 1: chol_publish<1>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
-        case 2: chol_publish<2>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
-        case 3: chol_publish<3>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
-        case 4: chol_publish<4>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
-        default: chol_publish<5>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); break;
+#define CHOL_PUBLISH(J) \
+  case J:                \
+    if constexpr (J < KB) chol_publish<KB, J>(val, cj, tx, j, &pv[j & 1], &iv[j & 1]); \
+    break;
+        CHOL_PUBLISH(0) CHOL_PUBLISH(1) CHOL_PUBLISH(2) CHOL_PUBLISH(3) CHOL_PUBLISH(4)
+        CHOL_PUBLISH(5) CHOL_PUBLISH(6) CHOL_PUBLISH(7) CHOL_PUBLISH(8) CHOL_PUBLISH(9)
+#undef CHOL_PUBLISH
       }
     }
     __syncthreads();
@@ -175,22 +184,23 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
       dmax = fmax(dmax, d);
       const double inv = iv[j & 1];
       switch (jb) {
-        case 0: chol_update<0>(val, cj, inv, tx, ty); break;
-        case 1: chol_update<1>(val, cj, inv, tx, ty); break;
-        case 2: chol_update<2>(val, cj, inv, tx, ty); break;
-        case 3: chol_update<3>(val, cj, inv, tx, ty); break;
-        case 4: chol_update<4>(val, cj, inv, tx, ty); break;
-        default: chol_update<5>(val, cj, inv, tx, ty); break;
+#define CHOL_UPDATE(J) \
+  case J:               \
+    if constexpr (J < KB) chol_update<KB, J>(val, cj, inv, tx, ty); \
+    break;
+        CHOL_UPDATE(0) CHOL_UPDATE(1) CHOL_UPDATE(2) CHOL_UPDATE(3) CHOL_UPDATE(4)
+        CHOL_UPDATE(5) CHOL_UPDATE(6) CHOL_UPDATE(7) CHOL_UPDATE(8) CHOL_UPDATE(9)
+#undef CHOL_UPDATE
       }
     }
   }
   __syncthreads();
   double* Rb = Rout + b * kk2;
   // scale factors of this thread's columns
-  double sd[kCholB];
-  bool dr[kCholB];
+  double sd[KB];
+  bool dr[KB];
 #pragma unroll
-  for (int c = 0; c < kCholB; ++c) {
+  for (int c = 0; c < KB; ++c) {
     const int l = ty + kCholT * c;
     dr[c] = l < k ? dropped[l] != 0 : true;
     sd[c] = (l < k && !dr[c]) ? sqrt(piv[l]) : 1.0;
@@ -198,10 +208,10 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   // R = L^T with zero rows where dropped: rows 32 a .. 32 a + 31 of L go
   // through the tile and out as columns of R
 #pragma unroll
-  for (int a = 0; a < kCholB; ++a) {
+  for (int a = 0; a < KB; ++a) {
     const int i = tx + kCholT * a;
 #pragma unroll
-    for (int c = 0; c < kCholB; ++c) {
+    for (int c = 0; c < KB; ++c) {
       const int l = ty + kCholT * c;
       double r = 0.0;
       if (c <= a && i < k && l <= i && !dr[c]) r = (i == l) ? sd[c] : val[cblk(a, c)] / sd[c];
@@ -211,7 +221,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
     const int ri = kCholT * a + ty;        // column of R = row of L
     if (ri < k) {
 #pragma unroll
-      for (int m = 0; m < kCholB; ++m) {
+      for (int m = 0; m < KB; ++m) {
         const int l = tx + kCholT * m;
         if (l < k) Rb[l + (long)ri * k] = tile[ty][l];   // R[l][ri] = L[ri][l]
       }
@@ -232,6 +242,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
 // the solution, so the columns of the next 16 steps are kept in flight in a
 // register ring.  The update also touches row i (and rows below it, where R
 // is zero); x_i is kept apart, so that does not matter.
+template <int ROWS>
 __global__ __launch_bounds__(256) void k_trinv(const double* R, const double* mask, int k, double* Rinv) {
   constexpr int RING = 16;
   const int b = blockIdx.y;
@@ -241,19 +252,19 @@ __global__ __launch_bounds__(256) void k_trinv(const double* R, const double* ma
   const long kk2 = (long)k * k;
   const double* Rb = R + b * kk2;
   const double* mb = mask + (long)b * k;
-  double bv[3], rd[3], xo[3];        // rows lane + 64 q: right-hand side, 1 / U[i][i], solution
+  double bv[ROWS], rd[ROWS], xo[ROWS];        // rows lane + 64 q: right-hand side, 1 / U[i][i], solution
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < ROWS; ++q) {
     const int i = lane + 64 * q;
     bv[q] = (i == c) ? 1.0 : 0.0;
     xo[q] = 0.0;
     rd[q] = (i <= c) ? (mb[i] != 0.0 ? 1.0 / Rb[i + (long)i * k] : 1.0) : 0.0;
   }
-  double ring[RING][3];
+  double ring[RING][ROWS];
   auto fetch = [&](int i, double* dst) {
     const long col = (long)(i < 0 ? 0 : i) * k;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < ROWS; ++q) {
       const int kx = lane + 64 * q;
       dst[q] = Rb[(kx < k ? kx : k - 1) + col];                  // R[kx][i]
     }
@@ -265,14 +276,20 @@ __global__ __launch_bounds__(256) void k_trinv(const double* R, const double* ma
     for (int s = 0; s < RING; ++s) {
       const int i = base - s;
       if (i < 0) break;
-      double col[3] = {ring[s][0], ring[s][1], ring[s][2]};
+      double col[ROWS];
+#pragma unroll
+      for (int q = 0; q < ROWS; ++q) col[q] = ring[s][q];
       fetch(i - RING, ring[s]);
       const int qi = i >> 6, li = i & 63;
-      const double bq = qi == 0 ? bv[0] : (qi == 1 ? bv[1] : bv[2]);
-      const double rq = qi == 0 ? rd[0] : (qi == 1 ? rd[1] : rd[2]);
+      double bq = bv[0], rq = rd[0];
+#pragma unroll
+      for (int q = 1; q < ROWS; ++q) {
+        bq = (qi == q) ? bv[q] : bq;
+        rq = (qi == q) ? rd[q] : rq;
+      }
       const double xi = readlane_f64(bq * rq, li);
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
+      for (int q = 0; q < ROWS; ++q) {
         xo[q] = (q == qi && lane == li) ? xi : xo[q];
         bv[q] = fma(-xi, col[q], bv[q]);
       }
@@ -283,7 +300,7 @@ __global__ __launch_bounds__(256) void k_trinv(const double* R, const double* ma
   const bool keep = mb[c] != 0.0;
   double* out = Rinv + b * kk2 + (long)c * k;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < ROWS; ++q) {
     const int i = lane + 64 * q;
     if (i < k) out[i] = (keep && i <= c) ? xo[q] : 0.0;
   }
@@ -354,12 +371,13 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // tournament of the 2 bs columns (the pairs inside each block and across);
 // later rounds take only the bs^2 pairs across the two blocks, in bs steps
 // of bs disjoint pairs.  Each column pair is rotated once per sweep.
+template <int ROWS>
 __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, double* J, int k, int nb, int bs,
                                                                    int round, double* off, const int* conv,
                                                                    double tol) {
   // staged columns are kJacobiLd apart and zero past row k, so that the
   // steps read and write whole columns without row checks
-  constexpr int kJacobiLd = 64 * kJacobiRows;
+  constexpr int kJacobiLd = 64 * ROWS;
   __shared__ double sA[2 * kJacobiMaxBS * kJacobiLd];
   __shared__ double sJ[2 * kJacobiMaxBS * kJacobiLd];
   const int b = blockIdx.y;
@@ -375,11 +393,11 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
   // global loads first, then the LDS stores
   {
     const int gcol[2] = {pa * bs + q, pb * bs + q};
-    double va[2][kJacobiRows], vj[2][kJacobiRows];
+    double va[2][ROWS], vj[2][ROWS];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int t = 0; t < kJacobiRows; ++t) {
+      for (int t = 0; t < ROWS; ++t) {
         const int r = lane + 64 * t;
         const bool ok = gcol[h] < k && r < k;
         va[h][t] = ok ? Ab[(long)gcol[h] * k + r] : 0.0;
@@ -388,7 +406,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int t = 0; t < kJacobiRows; ++t) {
+      for (int t = 0; t < ROWS; ++t) {
         const int r = lane + 64 * t;
         sA[(h * bs + q) * kJacobiLd + r] = va[h][t];
         sJ[(h * bs + q) * kJacobiLd + r] = vj[h][t];
@@ -413,9 +431,9 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     double* ji = sJ + ci * kJacobiLd + lane;
     double* jj = sJ + cj * kJacobiLd + lane;
     // both columns and their rotation accumulators in registers (rows lane + 64 t)
-    double x[kJacobiRows], y[kJacobiRows], u[kJacobiRows], v[kJacobiRows];
+    double x[ROWS], y[ROWS], u[ROWS], v[ROWS];
 #pragma unroll
-    for (int t = 0; t < kJacobiRows; ++t) {
+    for (int t = 0; t < ROWS; ++t) {
       x[t] = ai[64 * t];
       y[t] = aj[64 * t];
       u[t] = ji[64 * t];
@@ -423,7 +441,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     }
     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-    for (int t = 0; t < kJacobiRows; ++t) {
+    for (int t = 0; t < ROWS; ++t) {
       al += x[t] * x[t];
       be += y[t] * y[t];
       ga += x[t] * y[t];
@@ -444,7 +462,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       const double inv = rsqrt_nr(2.0 * r * (r + ad));
       const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
 #pragma unroll
-      for (int t = 0; t < kJacobiRows; ++t) {
+      for (int t = 0; t < ROWS; ++t) {
         ai[64 * t] = cs * x[t] - sn * y[t];
         aj[64 * t] = sn * x[t] + cs * y[t];
         ji[64 * t] = cs * u[t] - sn * v[t];
@@ -458,7 +476,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     const int gc = (h == 0 ? pa : pb) * bs + q;
     if (gc < k) {
 #pragma unroll
-      for (int t = 0; t < kJacobiRows; ++t) {
+      for (int t = 0; t < ROWS; ++t) {
         const int r = lane + 64 * t;
         if (r < k) {
           Ab[(long)gc * k + r] = sA[(h * bs + q) * kJacobiLd + r];
@@ -655,6 +673,7 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
   double* Rtmp = s.Rtmp.as<double>();
   // the passes alternate between Y and the scratch panels (P holds the
   // current basis); an odd pass count ends with one copy back into Y
+  const bool small = k <= kCholBSmall * kCholT;   // k <= 192: the register-resident forms
   double* P = Y;
   double* Q = tmp;
   long pstride = ystride, qstride = (long)n * k;
@@ -671,11 +690,21 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
     // below 1e-14 of the largest (they lie below any projector cutoff).  Only
     // the output of two passes is near orthonormal, so the identity check runs
     // from the third pass on.
-    hipLaunchKernelGGL(k_chol, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass, pass == 0 ? 1 : 0,
-                       pass >= 2 ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14,
-                       rout, s.mask.as<double>(), s.flag.as<int>());
+    if (small)
+      hipLaunchKernelGGL(k_chol<kCholBSmall>, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass, pass == 0 ? 1 : 0,
+                         pass >= 2 ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14, rout, s.mask.as<double>(),
+                         s.flag.as<int>());
+    else
+      hipLaunchKernelGGL(k_chol<kCholBLarge>, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass, pass == 0 ? 1 : 0,
+                         pass >= 2 ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14, rout, s.mask.as<double>(),
+                         s.flag.as<int>());
     CTM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_trinv, dim3((k + 3) / 4, batch), dim3(256), 0, st, rout, s.mask.as<double>(), k, Ri);
+    if (small)
+      hipLaunchKernelGGL(k_trinv<kRowsSmall>, dim3((k + 3) / 4, batch), dim3(256), 0, st, rout, s.mask.as<double>(),
+                         k, Ri);
+    else
+      hipLaunchKernelGGL(k_trinv<kRowsLarge>, dim3((k + 3) / 4, batch), dim3(256), 0, st, rout, s.mask.as<double>(),
+                         k, Ri);
     CTM_HIP(hipGetLastError());
     // Q = P U^-1 into the other buffer (dropped directions come out zero)
     gemm(st, GemmType::F64, n, k, k, 1.0, colmajor(P, n, pstride), colmajor(Ri, k, kk2), 0.0,
@@ -720,9 +749,14 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   const int max_sweeps = 14, first = 9, more = 1;
   auto sweeps = [&](int count) {
     for (int sw = 0; sw < count; ++sw) {
-      for (int r = 0; r < nb - 1; ++r)
-        hipLaunchKernelGGL(k_jacobi_round, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs, r, off,
-                           conv, tol);
+      for (int r = 0; r < nb - 1; ++r) {
+        if (k <= 64 * kRowsSmall)
+          hipLaunchKernelGGL(k_jacobi_round<kRowsSmall>, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs,
+                             r, off, conv, tol);
+        else
+          hipLaunchKernelGGL(k_jacobi_round<kRowsLarge>, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs,
+                             r, off, conv, tol);
+      }
       hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, tol);
     }
     CTM_HIP(hipGetLastError());

@@ -20,7 +20,7 @@ struct SmallLA {
 bool smallla_fits(const SmallLA& s, int k);
 
 // Largest k (panel width / matrix order) the kernels below handle.
-constexpr int kSmallLAMaxK = 192;
+constexpr int kSmallLAMaxK = 320;
 constexpr int kSvSmallMax = 128;   // largest matrix of singular_values_small
 
 void smallla_alloc(SmallLA& s, int kmax, int batch_max, long nmax);
