@@ -30,16 +30,29 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;
-constexpr int kRD = 48;           // (r, dd) padded: 3 tiles of 16
-constexpr int MT1 = 3;            // stage one row tiles: (l', u') < 48
-constexpr int KS1 = 9;            // stage one k steps: (l, u) < 36
-constexpr int NT2 = 3;            // stage two column tiles: (r', d') < 48
+// Tile counts: NR tiles of 16 over (r, dd), (l', u') and (r', d'), KS1 k steps
+// of 4 over (l, u).  D <= 6: D^2 <= 36 padded to 48 (3 tiles), two waves per
+// SIMD.  D <= 8: 4 tiles, no padding at D = 8; the two accumulator sets take
+// 256 registers, so one wave per SIMD, and Ak, Ab take 152 KB of LDS.
 // LDS leading dimensions are = 16 (mod 32) doubles, so that the two halves of
 // a wave (k-slots 0,1 and 2,3 of a fragment read) fall on disjoint banks.
-constexpr int kAkLd = 2 * kRD + 16;        // [(l,u)][(p, r, dd)]
-constexpr int kAbLd = 48;                  // [((l',u'), p)][(r',d')]
-constexpr int kAkElems = 4 * KS1 * kAkLd;
-constexpr int kAbElems = 16 * MT1 * 2 * kAbLd;
+template <int NR_, int KS1_, int ABLD_, int WPE_>
+struct AbsorbShape {
+  static constexpr int NR = NR_;
+  static constexpr int RD = 16 * NR;            // (r, dd) padded
+  static constexpr int MT1 = NR;                // stage one row tiles: (l', u') < 16 NR
+  static constexpr int KS1 = KS1_;              // stage one k steps: (l, u) < 4 KS1
+  static constexpr int NT2 = NR;                // stage two column tiles: (r', d') < 16 NR
+  static constexpr int AKLD = 2 * RD + 16;      // [(l,u)][(p, r, dd)]
+  static constexpr int ABLD = ABLD_;            // [((l',u'), p)][(r',d')]
+  static constexpr int AKE = 4 * KS1 * AKLD;
+  static constexpr int ABE = 16 * MT1 * 2 * ABLD;
+  static constexpr int WPE = WPE_;
+  static constexpr int MAXQ = 4 * KS1 < RD ? 4 * KS1 : RD;   // largest (l, u) count
+  static constexpr int MAXP = 16 * NR;                       // largest (l', u') count
+};
+using ShapeD6 = AbsorbShape<3, 9, 48, 2>;
+using ShapeD8 = AbsorbShape<4, 16, 80, 1>;
 
 struct AbsorbArgs {
   const double* X;
@@ -57,8 +70,11 @@ struct AbsorbArgs {
   int transposed;
 };
 
-__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))) void k_absorb_fused(
+template <class S>
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(S::WPE))) void k_absorb_fused(
     AbsorbArgs a) {
+  constexpr int NR = S::NR, kRD = S::RD, MT1 = S::MT1, KS1 = S::KS1, NT2 = S::NT2;
+  constexpr int kAkLd = S::AKLD, kAbLd = S::ABLD, kAkElems = S::AKE, kAbElems = S::ABE;
   __shared__ double sAk[kAkElems];
   __shared__ double sAb[kAbElems];
   const int bz = blockIdx.y;
@@ -98,20 +114,20 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
   for (long pr = (long)blockIdx.x * kWaves + w; pr < npairs; pr += nwaves) {
     const int cp = (int)(pr / a.chi), cn = (int)(pr % a.chi);
     const double* Xb = Xg + (long)cp * Db * a.n + (long)cn * Db;
-    d4 acc2[3][NT2];
+    d4 acc2[NR][NT2];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < NR; ++i)
 #pragma unroll
       for (int j = 0; j < NT2; ++j) acc2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     // one physical index p at a time: stage one gives Y[(l',u'), (p, r, dd)]
     // (X is read again for the second p, from L2), stage two consumes it
     for (int p = 0; p < d; ++p) {
       // ---- stage one: Y_p = A1 Ak_p with A1[(l',u')][(l,u)] = X[(l,l'),(u,u')] ----
-      d4 acc1[MT1][3];
+      d4 acc1[MT1][NR];
 #pragma unroll
       for (int i = 0; i < MT1; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) acc1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < NR; ++j) acc1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       // three k steps unrolled: loads in flight for a third of the block,
       // so that the accumulators and fragments fit 256 registers
 #pragma unroll 3
@@ -119,15 +135,15 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
         const int k = ks * 4 + kg;                      // (l, u)
         const bool kok = k < Q;
         const long kx = kok ? (long)(k / DK) * DB * a.n + (k % DK) * DB : 0;
-        double av[MT1], bv[3];
+        double av[MT1], bv[NR];
 #pragma unroll
         for (int mt = 0; mt < MT1; ++mt) av[mt] = (rok[mt] && kok) ? Xb[kx + xoff[mt]] : 0.0;
 #pragma unroll
-        for (int nt = 0; nt < 3; ++nt) bv[nt] = sAk[k * kAkLd + p * kRD + nt * 16 + r16];
+        for (int nt = 0; nt < NR; ++nt) bv[nt] = sAk[k * kAkLd + p * kRD + nt * 16 + r16];
 #pragma unroll
         for (int mt = 0; mt < MT1; ++mt)
 #pragma unroll
-          for (int nt = 0; nt < 3; ++nt)
+          for (int nt = 0; nt < NR; ++nt)
             acc1[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc1[mt][nt], 0, 0, 0);
       }
       // ---- stage two: G[(r,dd)][(r',d')] += sum over (l',u') of Y_p Ab_p ----
@@ -143,7 +159,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
 #pragma unroll
           for (int nt = 0; nt < NT2; ++nt) bv[nt] = sAb[(lu * 2 + p) * kAbLd + nt * 16 + r16];
 #pragma unroll
-          for (int m2 = 0; m2 < 3; ++m2)
+          for (int m2 = 0; m2 < NR; ++m2)
 #pragma unroll
             for (int nt = 0; nt < NT2; ++nt)
               acc2[m2][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc1[mt][m2][r], bv[nt], acc2[m2][nt], 0, 0, 0);
@@ -155,7 +171,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
       if (col < P) {
         const int rb = col / DB, db = col % DB;
 #pragma unroll
-        for (int m2 = 0; m2 < 3; ++m2)
+        for (int m2 = 0; m2 < NR; ++m2)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i = m2 * 16 + kg + 4 * r;         // (r, dd)
@@ -172,9 +188,14 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(2))
 
 }  // namespace
 
-bool absorb_fused_fits(int DK, int DB, int d) {
+template <class S>
+static bool shape_fits(int DK, int DB, int d) {
   const int P = DB * DB, Q = DK * DK;
-  return DB > 1 && d >= 1 && d <= 2 && Q <= 4 * KS1 && Q <= kRD && P <= 16 * MT1 && P <= 16 * NT2;
+  return DB > 1 && d >= 1 && d <= 2 && Q <= S::MAXQ && P <= S::MAXP;
+}
+
+bool absorb_fused_fits(int DK, int DB, int d) {
+  return shape_fits<ShapeD6>(DK, DB, d) || shape_fits<ShapeD8>(DK, DB, d);
 }
 
 void absorb_fused(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G, int chi,
@@ -195,11 +216,17 @@ void absorb_fused_batched(hipStream_t st, const double* X, const double* Ak, con
   a.chi = chi; a.DK = DK; a.DB = DB; a.d = d;
   a.transposed = transposed ? 1 : 0;
   const long npairs = (long)chi * chi;
-  // two resident workgroups per CU on 256 CUs; each wave strides over pairs
+  // resident workgroups per CU on 256 CUs: two (D <= 6) or one (D <= 8, its
+  // LDS); each wave strides over pairs
+  const bool d6 = shape_fits<ShapeD6>(DK, DB, d);
+  const long resident = d6 ? 512 : 256;
   const long per_block = kWaves;
-  const unsigned blocks = (unsigned)std::min<long>(std::max<long>(1, 512 / batch),
+  const unsigned blocks = (unsigned)std::min<long>(std::max<long>(1, resident / batch),
                                                    (npairs + per_block - 1) / per_block);
-  hipLaunchKernelGGL(k_absorb_fused, dim3(blocks, batch), dim3(64 * kWaves), 0, st, a);
+  if (d6)
+    hipLaunchKernelGGL(k_absorb_fused<ShapeD6>, dim3(blocks, batch), dim3(64 * kWaves), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_absorb_fused<ShapeD8>, dim3(blocks, batch), dim3(64 * kWaves), 0, st, a);
   CTM_HIP(hipGetLastError());
 }
 
