@@ -6,7 +6,7 @@
 namespace ctm {
 
 // True if the fused kernel handles these dimensions (D^4 d blocks up to
-// D = 6, d = 2, and a double-layer network).
+// D = 8, d = 2, and a double-layer network).
 bool absorb_fused_fits(int DK, int DB, int d);
 
 // G[(cn, r, r'), (cp, dd, d')] (transposed: G[(cp, dd, d'), (cn, r, r')]) =
