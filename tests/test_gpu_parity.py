@@ -167,6 +167,28 @@ def test_one_move_parity(lib, direction, r):
             assert rel_err(T[k], ora.T[i][k]) < 1e-8, (i, k)
 
 
+def test_one_move_batched_corner_chunks(lib):
+    """One left move at D = 4, chi = 144 (n = 2304) from a random
+    full-dimension environment: n^2 is large enough that a batched corner
+    launch takes 6 of the 8 corners of a column (two launches per column,
+    each corner with its own scratch), the column update runs as one batched
+    launch over both cuts.  Every renormalised tensor against the oracle's
+    move, 1e-8 as for the small one-move test."""
+    D, chi, p, q = 4, 144, 32, 1
+    A = wl.random_itps(2, 2, D, 2, seed=9)
+    ctx = lib.Ctm(A, 2, 2, D, chi, rsvd_oversample=p, rsvd_power_iters=q, seed=3)
+    ora = Environment(A, 2, 2, chi=chi, layers=2, mode="rsvd", oversample=p, power_iters=q, seed=3)
+    inject(ora, ctx, random_env(2, 2, chi, D * D, seed=10))
+    ctx.ctm_move("left")
+    ora.left_move(0)
+    assert ctx.ctm_cut_stats() == (0, 4, 0)
+    for i in range(4):
+        C, T, _ = ctx.ctm_get_env(i)
+        for k in range(4):
+            assert rel_err(C[k], ora.C[i][k]) < 1e-8, (i, k)
+            assert rel_err(T[k], ora.T[i][k]) < 1e-8, (i, k)
+
+
 # --------------------------------------------------------------------------
 # whole runs from the trivial environment
 # --------------------------------------------------------------------------
