@@ -660,6 +660,49 @@ static int jacobi_block(int k) { return std::min(kJacobiMaxBS, std::max(1, (k + 
 
 bool smallla_fits(const SmallLA& s, int k) { return k <= kSmallLAMaxK && k <= s.kmax; }
 
+namespace {
+
+// 32-row register blocks of the Cholesky and 64-row groups per lane of the
+// triangular inverse and Jacobi rounds that k needs (instantiated sizes)
+int chol_blocks_for(int k) {
+  const int b = (k + kCholT - 1) / kCholT;
+  return b <= kCholBSmall ? b : kCholBLarge;
+}
+int rows_for(int k) {
+  const int r = (k + 63) / 64;
+  return r <= kRowsSmall ? r : kRowsLarge;
+}
+
+void launch_chol(hipStream_t st, int kb, int batch, const double* G, int k, int pass, int shifted, int check_id,
+                 double shift_scale, double drop_rel, double* R, double* mask, int* flag) {
+  const dim3 grid(batch), block(kCholThreads);
+  switch (kb) {
+#define CHOL_LAUNCH(KB) \
+  case KB:              \
+    hipLaunchKernelGGL(k_chol<KB>, grid, block, 0, st, G, k, pass, shifted, check_id, shift_scale, drop_rel, R, mask, flag); \
+    break;
+    CHOL_LAUNCH(1) CHOL_LAUNCH(2) CHOL_LAUNCH(3) CHOL_LAUNCH(4) CHOL_LAUNCH(5) CHOL_LAUNCH(6)
+#undef CHOL_LAUNCH
+    default:
+      hipLaunchKernelGGL(k_chol<kCholBLarge>, grid, block, 0, st, G, k, pass, shifted, check_id, shift_scale,
+                         drop_rel, R, mask, flag);
+  }
+  CTM_HIP(hipGetLastError());
+}
+
+void launch_trinv(hipStream_t st, int rows, int batch, const double* R, const double* mask, int k, double* Ri) {
+  const dim3 grid((k + 3) / 4, batch), block(256);
+  switch (rows) {
+    case 1: hipLaunchKernelGGL(k_trinv<1>, grid, block, 0, st, R, mask, k, Ri); break;
+    case 2: hipLaunchKernelGGL(k_trinv<2>, grid, block, 0, st, R, mask, k, Ri); break;
+    case 3: hipLaunchKernelGGL(k_trinv<3>, grid, block, 0, st, R, mask, k, Ri); break;
+    default: hipLaunchKernelGGL(k_trinv<kRowsLarge>, grid, block, 0, st, R, mask, k, Ri);
+  }
+  CTM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
 void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, int batch, int passes,
             double* Racc, const GemmWorkspace& ws) {
   CTM_CHECK(k <= kSmallLAMaxK && k <= s.kmax && batch <= s.batch_max && n >= k, -1, "cholqr: size");
@@ -673,7 +716,9 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
   double* Rtmp = s.Rtmp.as<double>();
   // the passes alternate between Y and the scratch panels (P holds the
   // current basis); an odd pass count ends with one copy back into Y
-  const bool small = k <= kCholBSmall * kCholT;   // k <= 192: the register-resident forms
+  // register blocks and rows per lane sized to k (entries past k are zero
+  // and add nothing, so every size gives the same arithmetic)
+  const int kb = chol_blocks_for(k), rows = rows_for(k);
   double* P = Y;
   double* Q = tmp;
   long pstride = ystride, qstride = (long)n * k;
@@ -690,21 +735,9 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
     // below 1e-14 of the largest (they lie below any projector cutoff).  Only
     // the output of two passes is near orthonormal, so the identity check runs
     // from the third pass on.
-    if (small)
-      hipLaunchKernelGGL(k_chol<kCholBSmall>, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass, pass == 0 ? 1 : 0,
-                         pass >= 2 ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14, rout, s.mask.as<double>(),
-                         s.flag.as<int>());
-    else
-      hipLaunchKernelGGL(k_chol<kCholBLarge>, dim3(batch), dim3(kCholThreads), 0, st, G, k, pass, pass == 0 ? 1 : 0,
-                         pass >= 2 ? 1 : 0, shift_scale, pass == 0 ? 0.0 : 1e-14, rout, s.mask.as<double>(),
-                         s.flag.as<int>());
-    CTM_HIP(hipGetLastError());
-    if (small)
-      hipLaunchKernelGGL(k_trinv<kRowsSmall>, dim3((k + 3) / 4, batch), dim3(256), 0, st, rout, s.mask.as<double>(),
-                         k, Ri);
-    else
-      hipLaunchKernelGGL(k_trinv<kRowsLarge>, dim3((k + 3) / 4, batch), dim3(256), 0, st, rout, s.mask.as<double>(),
-                         k, Ri);
+    launch_chol(st, kb, batch, G, k, pass, pass == 0 ? 1 : 0, pass >= 2 ? 1 : 0, shift_scale,
+                pass == 0 ? 0.0 : 1e-14, rout, s.mask.as<double>(), s.flag.as<int>());
+    launch_trinv(st, rows, batch, rout, s.mask.as<double>(), k, Ri);
     CTM_HIP(hipGetLastError());
     // Q = P U^-1 into the other buffer (dropped directions come out zero)
     gemm(st, GemmType::F64, n, k, k, 1.0, colmajor(P, n, pstride), colmajor(Ri, k, kk2), 0.0,
@@ -750,12 +783,14 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   auto sweeps = [&](int count) {
     for (int sw = 0; sw < count; ++sw) {
       for (int r = 0; r < nb - 1; ++r) {
-        if (k <= 64 * kRowsSmall)
-          hipLaunchKernelGGL(k_jacobi_round<kRowsSmall>, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs,
-                             r, off, conv, tol);
-        else
-          hipLaunchKernelGGL(k_jacobi_round<kRowsLarge>, dim3(nb / 2, batch), dim3(64 * bs), 0, st, A, J, k, nb, bs,
-                             r, off, conv, tol);
+        const dim3 grid(nb / 2, batch), block(64 * bs);
+        switch (rows_for(k)) {
+          case 1:
+          case 2: hipLaunchKernelGGL(k_jacobi_round<2>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, tol); break;
+          case 3: hipLaunchKernelGGL(k_jacobi_round<3>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, tol); break;
+          default:
+            hipLaunchKernelGGL(k_jacobi_round<kRowsLarge>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, tol);
+        }
       }
       hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, tol);
     }
