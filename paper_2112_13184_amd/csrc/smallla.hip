@@ -823,9 +823,13 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
 
 void singular_values_small(hipStream_t st, const double* A, int m, int batch, double* S) {
   CTM_CHECK(m >= 1 && m <= kSvSmallMax && batch >= 1, -1, "singular_values_small: size");
-  // the kernel reads A and writes only S
-  hipLaunchKernelGGL((k_jacobi_onewg<kSvSmallMax, false>), dim3(batch), dim3(1024), 0, st, const_cast<double*>(A), m, S,
-                     nullptr, 1e-15, 30);
+  // the kernel reads A and writes only S; rows per lane sized to m
+  if (m <= 64)
+    hipLaunchKernelGGL((k_jacobi_onewg<64, false>), dim3(batch), dim3(1024), 0, st, const_cast<double*>(A), m, S,
+                       nullptr, 1e-15, 30);
+  else
+    hipLaunchKernelGGL((k_jacobi_onewg<kSvSmallMax, false>), dim3(batch), dim3(1024), 0, st, const_cast<double*>(A), m,
+                       S, nullptr, 1e-15, 30);
   CTM_HIP(hipGetLastError());
 }
 
