@@ -43,6 +43,23 @@ __device__ __forceinline__ long off0(const int* t, long s, int i) { return t ? (
 template <typename T>
 __device__ __forceinline__ T* batch_base(T* p, const long* off, long bs, int b) { return p + (off ? off[b] : (long)b * bs); }
 
+// Raw buffer access to the whole 4 GiB range above `p` (stride 0, no range
+// check in effect): the per-lane offset is one 32-bit byte offset, the base a
+// scalar descriptor.  Callers keep every offset below 2^32 bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const double* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, -1, 0x00020000);
+}
+// ... and to the `elems` doubles above `p` only: loads past them return zero
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const double* p, long elems) {
+  const long bytes = elems > 0 ? 8 * elems : 0;
+  const int n = bytes >= 0xffffffffL ? -1 : (int)(unsigned)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, n, 0x00020000);
+}
+__device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+
 // Workgroups are dispatched to the 8 XCDs round-robin by linear id; remap so
 // that each XCD runs one contiguous range of (tile, split, batch) indices.
 // Neighbouring output tiles share rows of A, which then stay in that XCD's L2.
@@ -115,52 +132,79 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
     b_coff[j] = b_cok[j] ? off0(g.tb1, g.sb1, n) : 0;
   }
   // table-free offsets within a k-tile (edge rows / columns clamped)
-  int a_off[EA], b_off[EB];
+  // (byte offsets for buffer loads: one 32-bit register per load, no 64-bit
+  // address arithmetic)
+  unsigned a_off[EA], b_off[EB];
   if (!TBL) {
 #pragma unroll
     for (int j = 0; j < EA; ++j)
-      a_off[j] = (int)((long)min(m0 + a_r[j], g.M - 1) * g.sa0 + (long)a_k[j] * g.sa1);
+      a_off[j] = 8u * (unsigned)((long)min(m0 + a_r[j], g.M - 1) * g.sa0 + (long)a_k[j] * g.sa1);
 #pragma unroll
     for (int j = 0; j < EB; ++j)
-      b_off[j] = (int)((long)min(n0 + b_c[j], g.N - 1) * g.sb1 + (long)b_k[j] * g.sb0);
+      b_off[j] = 8u * (unsigned)((long)min(n0 + b_c[j], g.N - 1) * g.sb1 + (long)b_k[j] * g.sb0);
   }
+  // one past the last element of each operand, in elements from its base
+  const long a_end = (long)(g.M - 1) * g.sa0 + (long)(g.K - 1) * g.sa1 + 1;
+  const long b_end = (long)(g.N - 1) * g.sb1 + (long)(g.K - 1) * g.sb0 + 1;
 
-  // ra/rb: the next k-tile; without tables ra2/rb2 hold the one after it
-  // (two tiles of loads in flight, the registers the table offsets would take)
+  // Two register sets for k-tiles in flight: while the MFMAs run on one LDS
+  // buffer, one set is stored to the other buffer and the other set receives
+  // the loads of the tile after it.  The sets alternate from one k-tile to
+  // the next (the loop is unrolled by two), so a tile's loads have a whole
+  // k-step before their registers are stored, and no register copies.
+  // Without tables every k-step issues the same eight loads (the last steps
+  // reload the last tile; loads past an operand's end return zero), so the
+  // waits before the stores count exactly the older set; the slots of a
+  // partial last tile at k >= ke are zeroed when it is stored.
+  // With tables (their offsets take the registers) only the first set is used.
   double ra[EA], rb[EB], ra2[EA], rb2[EB];
-  auto load_tile = [&](int k0) {
+  auto load_tile = [&](int k0, double (&xa)[EA], double (&xb)[EB]) {
     if (!TBL) {
-      const double* Ak = A + (long)k0 * g.sa1;
-      const double* Bk = B + (long)k0 * g.sb0;
-      if (k0 + BK <= ke) {
+      const __amdgpu_buffer_rsrc_t Ak = buffer_rsrc(A + (long)k0 * g.sa1, a_end - (long)k0 * g.sa1);
+      const __amdgpu_buffer_rsrc_t Bk = buffer_rsrc(B + (long)k0 * g.sb0, b_end - (long)k0 * g.sb0);
 #pragma unroll
-        for (int j = 0; j < EA; ++j) ra2[j] = Ak[a_off[j]];
+      for (int j = 0; j < EA; ++j) xa[j] = buffer_load_f64(Ak, a_off[j]);
 #pragma unroll
-        for (int j = 0; j < EB; ++j) rb2[j] = Bk[b_off[j]];
-      } else {
-#pragma unroll
-        for (int j = 0; j < EA; ++j) ra2[j] = (k0 + a_k[j] < ke) ? Ak[a_off[j]] : 0.0;
-#pragma unroll
-        for (int j = 0; j < EB; ++j) rb2[j] = (k0 + b_k[j] < ke) ? Bk[b_off[j]] : 0.0;
-      }
+      for (int j = 0; j < EB; ++j) xb[j] = buffer_load_f64(Bk, b_off[j]);
       return;
     }
 #pragma unroll
     for (int j = 0; j < EA; ++j) {
       int k = k0 + a_k[j];
-      ra[j] = (a_rok[j] && k < ke) ? A[a_roff[j] + off0(g.ta1, g.sa1, k)] : 0.0;
+      xa[j] = (a_rok[j] && k < ke) ? A[a_roff[j] + off0(g.ta1, g.sa1, k)] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < EB; ++j) {
       int k = k0 + b_k[j];
-      rb[j] = (b_cok[j] && k < ke) ? B[b_coff[j] + off0(g.tb0, g.sb0, k)] : 0.0;
+      xb[j] = (b_cok[j] && k < ke) ? B[b_coff[j] + off0(g.tb0, g.sb0, k)] : 0.0;
     }
   };
-  auto store_tile = [&](int buf) {
+  // LDS slot of each staged element: where the 256-thread step of the load
+  // pattern is a whole number of rows (k walked fastest) or of k columns, the
+  // slots of one lane are one base plus constant steps (immediate offsets).
+  constexpr bool A_LIN = A_KC ? (256 % BK == 0) : (256 % BM == 0);
+  constexpr bool B_LIN = B_KC ? (256 % BK == 0) : (256 % BN == 0);
+  constexpr int A_JS = A_KC ? (256 / BK) * LDK : 256 / BM;
+  constexpr int B_JS = B_KC ? (256 / BK) * LDK : 256 / BN;
+  const int a_st = a_r[0] * LDK + a_k[0], b_st = b_c[0] * LDK + b_k[0];
+  auto a_slot = [&](int j) { return A_LIN ? a_st + j * A_JS : a_r[j] * LDK + a_k[j]; };
+  auto b_slot = [&](int j) { return B_LIN ? b_st + j * B_JS : b_c[j] * LDK + b_k[j]; };
+  auto store_tile = [&](int buf, const double (&xa)[EA], const double (&xb)[EB]) {
 #pragma unroll
-    for (int j = 0; j < EA; ++j) As[buf][a_r[j] * LDK + a_k[j]] = ra[j];
+    for (int j = 0; j < EA; ++j) As[buf][a_slot(j)] = xa[j];
 #pragma unroll
-    for (int j = 0; j < EB; ++j) Bs[buf][b_c[j] * LDK + b_k[j]] = rb[j];
+    for (int j = 0; j < EB; ++j) Bs[buf][b_slot(j)] = xb[j];
+  };
+  // table-free tiles: the tile starting at k0 may be partial
+  auto store_tile_k = [&](int buf, int k0, const double (&xa)[EA], const double (&xb)[EB]) {
+    if (k0 + BK <= ke) {
+      store_tile(buf, xa, xb);
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < EA; ++j) As[buf][a_slot(j)] = (k0 + a_k[j] < ke) ? xa[j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < EB; ++j) Bs[buf][b_slot(j)] = (k0 + b_k[j] < ke) ? xb[j] : 0.0;
   };
 
   d4 acc[TM][TN];
@@ -172,31 +216,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
   const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
   const int r16 = lane & 15, kg = lane >> 4;
 
-  auto shift = [&] {
-#pragma unroll
-    for (int j = 0; j < EA; ++j) ra[j] = ra2[j];
-#pragma unroll
-    for (int j = 0; j < EB; ++j) rb[j] = rb2[j];
-  };
-  int nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
-  if (nk > 0) {
-    load_tile(kb);
-    if (!TBL) shift();
-    store_tile(0);
-  }
-  if (!TBL && nk > 1) {
-    load_tile(kb + BK);
-    shift();
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int cur = it & 1;
-    if (TBL) {
-      if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
-    } else {
-      if (it + 2 < nk) load_tile(kb + (it + 2) * BK);
-    }
-    // fragments loaded per k-slot, next to their MFMAs (fewer live registers)
+  // one k-tile of MFMAs from LDS buffer `cur`; fragments loaded per k-slot,
+  // next to their MFMAs (fewer live registers)
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       double af[TM], bf[TN];
@@ -210,9 +232,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
-    if (it + 1 < nk) store_tile(cur ^ 1);
-    if (!TBL) shift();
+  };
+
+  const int nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
+  if (TBL) {
+    if (nk > 0) {
+      load_tile(kb, ra, rb);
+      store_tile(0, ra, rb);
+    }
     __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+      const int cur = it & 1;
+      if (it + 1 < nk) load_tile(kb + (it + 1) * BK, ra, rb);
+      compute(cur);
+      if (it + 1 < nk) store_tile(cur ^ 1, ra, rb);
+      __syncthreads();
+    }
+  } else if (nk > 0) {
+    // even k-tiles: loads into set 2 while set 1 (the next tile) is stored;
+    // odd k-tiles: the other way round
+    const int last = kb + (nk - 1) * BK;
+    auto kt = [&](int t) { return min(kb + t * BK, last); };
+    load_tile(kb, ra2, rb2);
+    store_tile_k(0, kb, ra2, rb2);
+    load_tile(kt(1), ra, rb);
+    __syncthreads();
+    for (int it = 0; it < nk; it += 2) {
+      load_tile(kt(it + 2), ra2, rb2);
+      compute(0);
+      if (it + 1 < nk) store_tile_k(1, kt(it + 1), ra, rb);
+      __syncthreads();
+      if (it + 1 >= nk) break;
+      load_tile(kt(it + 3), ra, rb);
+      compute(1);
+      if (it + 2 < nk) store_tile_k(0, kt(it + 2), ra2, rb2);
+      __syncthreads();
+    }
   }
 
   // ---- epilogue ----------------------------------------------------------
@@ -266,16 +321,16 @@ void launch_f64_t(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 gri
 }
 
 // The table-free kernels take 32-bit offsets within a tile (k-tiles of at
-// most 32).
-bool needs_tables(const KArgs& g) {
-  constexpr long kMaxOff = 0x7fffffffL;
+// most 32): element offsets below 2^31 in the reduced-precision kernels, byte
+// offsets below 2^32 (elements below 2^29) in the FP64 one.
+bool needs_tables(const KArgs& g, long kMaxOff = 0x7fffffffL) {
   return g.ta0 || g.ta1 || g.tb0 || g.tb1 || g.sa0 < 0 || g.sa1 < 0 || g.sb0 < 0 || g.sb1 < 0 ||
          (long)g.M * g.sa0 + 32L * g.sa1 > kMaxOff || (long)g.N * g.sb1 + 32L * g.sb0 > kMaxOff;
 }
 
 template <int BM, int BN, int WAVES_M>
 void launch_f64(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
-  if (needs_tables(g)) launch_f64_t<BM, BN, WAVES_M, true>(st, g, a_kc, b_kc, grid);
+  if (needs_tables(g, 0x1fffffffL)) launch_f64_t<BM, BN, WAVES_M, true>(st, g, a_kc, b_kc, grid);
   else                 launch_f64_t<BM, BN, WAVES_M, false>(st, g, a_kc, b_kc, grid);
 }
 
