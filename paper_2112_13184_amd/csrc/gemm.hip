@@ -320,10 +320,9 @@ void launch_f64_t(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 gri
     hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WAVES_M, false, false, TBL>), grid, dim3(256), 0, st, g);
 }
 
-// The table-free kernels take 32-bit offsets within a tile (k-tiles of at
-// most 32): element offsets below 2^31 in the reduced-precision kernels, byte
-// offsets below 2^32 (elements below 2^29) in the FP64 one.
-bool needs_tables(const KArgs& g, long kMaxOff = 0x7fffffffL) {
+// The table-free kernels take 32-bit byte offsets within a tile (k-tiles of
+// at most 32): elements below 2^29.
+bool needs_tables(const KArgs& g, long kMaxOff) {
   return g.ta0 || g.ta1 || g.tb0 || g.tb1 || g.sa0 < 0 || g.sa1 < 0 || g.sb0 < 0 || g.sb1 < 0 ||
          (long)g.M * g.sa0 + 32L * g.sa1 > kMaxOff || (long)g.N * g.sb1 + 32L * g.sb0 > kMaxOff;
 }
@@ -423,49 +422,45 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
     b_cok[j] = n < g.N;
     b_coff[j] = b_cok[j] ? off0(g.tb1, g.sb1, n) : 0;
   }
-  // table-free offsets within a k-tile (edge rows / columns clamped)
-  int a_off[EA], b_off[EB];
+  // table-free byte offsets within a k-tile (edge rows / columns clamped) for
+  // buffer loads, as in the FP64 kernel
+  unsigned a_off[EA], b_off[EB];
   if (!TBL) {
 #pragma unroll
     for (int j = 0; j < EA; ++j)
-      a_off[j] = (int)((long)min(m0 + a_r[j], g.M - 1) * g.sa0 + (long)a_k[j] * g.sa1);
+      a_off[j] = 8u * (unsigned)((long)min(m0 + a_r[j], g.M - 1) * g.sa0 + (long)a_k[j] * g.sa1);
 #pragma unroll
     for (int j = 0; j < EB; ++j)
-      b_off[j] = (int)((long)min(n0 + b_c[j], g.N - 1) * g.sb1 + (long)b_k[j] * g.sb0);
+      b_off[j] = 8u * (unsigned)((long)min(n0 + b_c[j], g.N - 1) * g.sb1 + (long)b_k[j] * g.sb0);
   }
+  const long a_end = (long)(g.M - 1) * g.sa0 + (long)(g.K - 1) * g.sa1 + 1;
+  const long b_end = (long)(g.N - 1) * g.sb1 + (long)(g.K - 1) * g.sb0 + 1;
 
-  // ra/rb: the next k-tile; without tables (and except for split FP16, whose
-  // two operand parts leave no registers) ra2/rb2 hold the one after it
-  constexpr bool PF2 = !TBL && KIND != LP_F16;
+  // Without tables FP32 keeps two register sets of loads that alternate from
+  // one k-tile to the next, as the FP64 kernel does; BF16 (the second set
+  // costs it a wave per SIMD), split FP16 (two operand parts in LDS) and the
+  // table-addressed loads use one set, loaded one k-tile ahead.
+  constexpr bool PF2 = !TBL && KIND == LP_F32;
   double ra[EA], rb[EB], ra2[EA], rb2[EB];
-  double* const xa = PF2 ? ra2 : ra;
-  double* const xb = PF2 ? rb2 : rb;
-  auto load_tile = [&](int k0) {
+  auto load_tile = [&](int k0, double (&xa)[EA], double (&xb)[EB]) {
     if (!TBL) {
-      const double* Ak = A + (long)k0 * g.sa1;
-      const double* Bk = B + (long)k0 * g.sb0;
-      if (k0 + BK <= ke) {
+      const __amdgpu_buffer_rsrc_t Ak = buffer_rsrc(A + (long)k0 * g.sa1, a_end - (long)k0 * g.sa1);
+      const __amdgpu_buffer_rsrc_t Bk = buffer_rsrc(B + (long)k0 * g.sb0, b_end - (long)k0 * g.sb0);
 #pragma unroll
-        for (int j = 0; j < EA; ++j) xa[j] = Ak[a_off[j]];
+      for (int j = 0; j < EA; ++j) xa[j] = buffer_load_f64(Ak, a_off[j]);
 #pragma unroll
-        for (int j = 0; j < EB; ++j) xb[j] = Bk[b_off[j]];
-      } else {
-#pragma unroll
-        for (int j = 0; j < EA; ++j) xa[j] = (k0 + a_k[j] < ke) ? Ak[a_off[j]] : 0.0;
-#pragma unroll
-        for (int j = 0; j < EB; ++j) xb[j] = (k0 + b_k[j] < ke) ? Bk[b_off[j]] : 0.0;
-      }
+      for (int j = 0; j < EB; ++j) xb[j] = buffer_load_f64(Bk, b_off[j]);
       return;
     }
 #pragma unroll
     for (int j = 0; j < EA; ++j) {
       int k = k0 + a_k[j];
-      ra[j] = (a_rok[j] && k < ke) ? A[a_roff[j] + off0(g.ta1, g.sa1, k)] : 0.0;
+      xa[j] = (a_rok[j] && k < ke) ? A[a_roff[j] + off0(g.ta1, g.sa1, k)] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < EB; ++j) {
       int k = k0 + b_k[j];
-      rb[j] = (b_cok[j] && k < ke) ? B[b_coff[j] + off0(g.tb0, g.sb0, k)] : 0.0;
+      xb[j] = (b_cok[j] && k < ke) ? B[b_coff[j] + off0(g.tb0, g.sb0, k)] : 0.0;
     }
   };
   auto put = [&](T* hi, T* lo, int idx, double x, double sc) {
@@ -478,11 +473,22 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
       hi[idx] = (T)(float)x;
     }
   };
-  auto store_tile = [&](int buf) {
+  // store the tile starting at k0; the slots of a partial tile at k >= ke
+  // are zeroed
+  auto store_tile = [&](int buf, int k0, const double (&xa)[EA], const double (&xb)[EB]) {
+    if (k0 + BK <= ke) {
 #pragma unroll
-    for (int j = 0; j < EA; ++j) put(As[buf][0], As[buf][NP - 1], a_r[j] * LDK + a_k[j], ra[j], sa);
+      for (int j = 0; j < EA; ++j) put(As[buf][0], As[buf][NP - 1], a_r[j] * LDK + a_k[j], xa[j], sa);
 #pragma unroll
-    for (int j = 0; j < EB; ++j) put(Bs[buf][0], Bs[buf][NP - 1], b_c[j] * LDK + b_k[j], rb[j], sb);
+      for (int j = 0; j < EB; ++j) put(Bs[buf][0], Bs[buf][NP - 1], b_c[j] * LDK + b_k[j], xb[j], sb);
+      return;
+    }
+#pragma unroll
+    for (int j = 0; j < EA; ++j)
+      put(As[buf][0], As[buf][NP - 1], a_r[j] * LDK + a_k[j], (k0 + a_k[j] < ke) ? xa[j] : 0.0, sa);
+#pragma unroll
+    for (int j = 0; j < EB; ++j)
+      put(Bs[buf][0], Bs[buf][NP - 1], b_c[j] * LDK + b_k[j], (k0 + b_k[j] < ke) ? xb[j] : 0.0, sb);
   };
 
   f4 acc[TM][TN], acc2[TM][TN];
@@ -497,30 +503,8 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
   const int r16 = lane & 15, kg = lane >> 4;
 
-  auto shift = [&] {
-#pragma unroll
-    for (int j = 0; j < EA; ++j) ra[j] = ra2[j];
-#pragma unroll
-    for (int j = 0; j < EB; ++j) rb[j] = rb2[j];
-  };
-  int nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
-  if (nk > 0) {
-    load_tile(kb);
-    if (PF2) shift();
-    store_tile(0);
-  }
-  if (PF2 && nk > 1) {
-    load_tile(kb + BK);
-    shift();
-  }
-  __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int cur = it & 1;
-    if (!PF2) {
-      if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
-    } else {
-      if (it + 2 < nk) load_tile(kb + (it + 2) * BK);
-    }
+  // one k-tile of MFMAs from LDS buffer `cur`
+  auto compute = [&](int cur) {
     if constexpr (KIND == LP_F32) {
       f4 af[TM][2], bfr[TN][2];
 #pragma unroll
@@ -579,9 +563,45 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
           acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc2[i][j], 0, 0, 0);
         }
     }
-    if (it + 1 < nk) store_tile(cur ^ 1);
-    if (PF2) shift();
+  };
+
+  const int nk = (ke > kb) ? (ke - kb + BK - 1) / BK : 0;
+  if (PF2) {
+    if (nk > 0) {
+      // even k-tiles: loads into set 2 while set 1 (the next tile) is
+      // stored; odd k-tiles the other way round; the last steps reload the
+      // last tile so that every step issues the same loads
+      const int last = kb + (nk - 1) * BK;
+      auto kt = [&](int t) { return min(kb + t * BK, last); };
+      load_tile(kb, ra2, rb2);
+      store_tile(0, kb, ra2, rb2);
+      load_tile(kt(1), ra, rb);
+      __syncthreads();
+      for (int it = 0; it < nk; it += 2) {
+        load_tile(kt(it + 2), ra2, rb2);
+        compute(0);
+        if (it + 1 < nk) store_tile(1, kt(it + 1), ra, rb);
+        __syncthreads();
+        if (it + 1 >= nk) break;
+        load_tile(kt(it + 3), ra, rb);
+        compute(1);
+        if (it + 2 < nk) store_tile(0, kt(it + 2), ra2, rb2);
+        __syncthreads();
+      }
+    }
+  } else {
+    if (nk > 0) {
+      load_tile(kb, ra, rb);
+      store_tile(0, kb, ra, rb);
+    }
     __syncthreads();
+    for (int it = 0; it < nk; ++it) {
+      const int cur = it & 1;
+      if (it + 1 < nk) load_tile(kb + (it + 1) * BK, ra, rb);
+      compute(cur);
+      if (it + 1 < nk) store_tile(cur ^ 1, kb + (it + 1) * BK, ra, rb);
+      __syncthreads();
+    }
   }
 
   double* C = batch_base(g.C, g.oc, g.bsc, b);
@@ -651,7 +671,7 @@ void launch_lp_t(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid
 
 template <int KIND, int BM, int BN, int WAVES_M>
 void launch_lp(hipStream_t st, const KArgs& g, bool a_kc, bool b_kc, dim3 grid) {
-  if (needs_tables(g)) launch_lp_t<KIND, BM, BN, WAVES_M, true>(st, g, a_kc, b_kc, grid);
+  if (needs_tables(g, 0x1fffffffL)) launch_lp_t<KIND, BM, BN, WAVES_M, true>(st, g, a_kc, b_kc, grid);
   else                 launch_lp_t<KIND, BM, BN, WAVES_M, false>(st, g, a_kc, b_kc, grid);
 }
 
