@@ -14,6 +14,7 @@
 #include "gemm.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace ctm {
 namespace {
@@ -375,7 +376,8 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;
-  static_assert(TM >= 1 && TN >= 1 && EA >= 1 && EB >= 1, "tile");
+  constexpr bool PAIRS = KIND == LP_BF16;
+  static_assert(TM >= 1 && TN >= 1 && EA >= 2 && EB >= 2 && EA % 2 == 0 && EB % 2 == 0, "tile (pairs of k)");
   __shared__ __attribute__((aligned(16))) T As[2][NP][BM * LDK];
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
 
@@ -403,9 +405,17 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   bool a_rok[EA];
 #pragma unroll
   for (int j = 0; j < EA; ++j) {
-    int e = tid + 256 * j;
-    if (A_KC) { a_k[j] = e % BK; a_r[j] = e / BK; }
-    else      { a_r[j] = e % BM; a_k[j] = e / BM; }
+    // BF16 with k contiguous: each thread takes pairs of consecutive k of one
+    // row (one packed LDS store per pair); else k (A_KC) or m walked fastest
+    if (A_KC && PAIRS) {
+      const int e = tid + 256 * (j / 2);
+      a_k[j] = (e % (BK / 2)) * 2 + (j & 1);
+      a_r[j] = e / (BK / 2);
+    } else {
+      const int e = tid + 256 * j;
+      if (A_KC) { a_k[j] = e % BK; a_r[j] = e / BK; }
+      else      { a_r[j] = e % BM; a_k[j] = e / BM; }
+    }
     int m = m0 + a_r[j];
     a_rok[j] = m < g.M;
     a_roff[j] = a_rok[j] ? off0(g.ta0, g.sa0, m) : 0;
@@ -415,9 +425,15 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
   bool b_cok[EB];
 #pragma unroll
   for (int j = 0; j < EB; ++j) {
-    int e = tid + 256 * j;
-    if (B_KC) { b_k[j] = e % BK; b_c[j] = e / BK; }
-    else      { b_c[j] = e % BN; b_k[j] = e / BN; }
+    if (B_KC && PAIRS) {
+      const int e = tid + 256 * (j / 2);
+      b_k[j] = (e % (BK / 2)) * 2 + (j & 1);
+      b_c[j] = e / (BK / 2);
+    } else {
+      const int e = tid + 256 * j;
+      if (B_KC) { b_k[j] = e % BK; b_c[j] = e / BK; }
+      else      { b_c[j] = e % BN; b_k[j] = e / BN; }
+    }
     int n = n0 + b_c[j];
     b_cok[j] = n < g.N;
     b_coff[j] = b_cok[j] ? off0(g.tb1, g.sb1, n) : 0;
@@ -473,22 +489,55 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
       hi[idx] = (T)(float)x;
     }
   };
-  // store the tile starting at k0; the slots of a partial tile at k >= ke
-  // are zeroed
-  auto store_tile = [&](int buf, int k0, const double (&xa)[EA], const double (&xb)[EB]) {
-    if (k0 + BK <= ke) {
-#pragma unroll
-      for (int j = 0; j < EA; ++j) put(As[buf][0], As[buf][NP - 1], a_r[j] * LDK + a_k[j], xa[j], sa);
-#pragma unroll
-      for (int j = 0; j < EB; ++j) put(Bs[buf][0], Bs[buf][NP - 1], b_c[j] * LDK + b_k[j], xb[j], sb);
-      return;
+  // two consecutive-k values of one row -> LDS as one packed store
+  auto put2 = [&](T* hi, T* lo, int idx, double x0, double x1, double sc) {
+    typedef T t2 __attribute__((ext_vector_type(2)));
+    if constexpr (KIND == LP_F16) {
+      const double y0 = x0 * sc, y1 = x1 * sc;           // exact (power of two)
+      const _Float16 h0 = (_Float16)(float)y0, h1 = (_Float16)(float)y1;
+      *reinterpret_cast<t2*>(hi + idx) = t2{h0, h1};
+      *reinterpret_cast<t2*>(lo + idx) =
+          t2{(_Float16)(float)((y0 - (double)h0) * 2048.0), (_Float16)(float)((y1 - (double)h1) * 2048.0)};
+    } else {
+      *reinterpret_cast<t2*>(hi + idx) = t2{(T)(float)x0, (T)(float)x1};
     }
+  };
+  // store the tile starting at k0; the slots of a partial tile at k >= ke
+  // are zeroed (a separate path, so that whole tiles take no selects)
+  auto store_body = [&](int buf, int k0, const double (&xa)[EA], const double (&xb)[EB], auto part_tag) {
+    constexpr bool part = decltype(part_tag)::value;
+    if constexpr (A_KC && PAIRS) {
 #pragma unroll
-    for (int j = 0; j < EA; ++j)
-      put(As[buf][0], As[buf][NP - 1], a_r[j] * LDK + a_k[j], (k0 + a_k[j] < ke) ? xa[j] : 0.0, sa);
+      for (int j = 0; j < EA; j += 2) {
+        const double x0 = (!part || k0 + a_k[j] < ke) ? xa[j] : 0.0;
+        const double x1 = (!part || k0 + a_k[j + 1] < ke) ? xa[j + 1] : 0.0;
+        put2(As[buf][0], As[buf][NP - 1], a_r[j] * LDK + a_k[j], x0, x1, sa);
+      }
+    } else {
 #pragma unroll
-    for (int j = 0; j < EB; ++j)
-      put(Bs[buf][0], Bs[buf][NP - 1], b_c[j] * LDK + b_k[j], (k0 + b_k[j] < ke) ? xb[j] : 0.0, sb);
+      for (int j = 0; j < EA; ++j)
+        put(As[buf][0], As[buf][NP - 1], a_r[j] * LDK + a_k[j], (!part || k0 + a_k[j] < ke) ? xa[j] : 0.0, sa);
+    }
+    if constexpr (B_KC && PAIRS) {
+#pragma unroll
+      for (int j = 0; j < EB; j += 2) {
+        const double x0 = (!part || k0 + b_k[j] < ke) ? xb[j] : 0.0;
+        const double x1 = (!part || k0 + b_k[j + 1] < ke) ? xb[j + 1] : 0.0;
+        put2(Bs[buf][0], Bs[buf][NP - 1], b_c[j] * LDK + b_k[j], x0, x1, sb);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < EB; ++j)
+        put(Bs[buf][0], Bs[buf][NP - 1], b_c[j] * LDK + b_k[j], (!part || k0 + b_k[j] < ke) ? xb[j] : 0.0, sb);
+    }
+  };
+  // (BF16 measured 2.5% faster over the sweep with the masked path for every
+  // tile, FP32 and split FP16 2% slower)
+  auto store_tile = [&](int buf, int k0, const double (&xa)[EA], const double (&xb)[EB]) {
+    if (KIND != LP_BF16 && k0 + BK <= ke)
+      store_body(buf, k0, xa, xb, std::false_type{});
+    else
+      store_body(buf, k0, xa, xb, std::true_type{});
   };
 
   f4 acc[TM][TN], acc2[TM][TN];
