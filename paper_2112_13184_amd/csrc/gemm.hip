@@ -92,7 +92,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
   __shared__ double As[2][BM * LDK];
   __shared__ double Bs[2][BN * LDK];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform: kept scalar, so the per-wave tile offsets take no vector registers
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int tiles_n = (g.N + BN - 1) / BN, tiles_m = (g.M + BM - 1) / BM;
   int tile, split, b;
   xcd_remap(tile, split, b);
