@@ -4,8 +4,11 @@
 // BK = 16 (FP64).  A and B tiles are staged through LDS as As[m][k] and
 // Bs[n][k] (k contiguous, one padding element per row so that both the
 // transposing stores and the MFMA fragment reads are free of bank conflicts),
-// double buffered with the next tile's global loads in flight during the
-// MFMAs.  Each wave owns a WM x WN sub-tile of 16x16 MFMA blocks.
+// double buffered: while the MFMAs of k-tile t run on one buffer, tile t + 1
+// is stored from registers into the other and, in the FP64 and FP32 kernels,
+// the loads of tile t + 2 are in flight into a second register set (the two
+// sets alternate; the main loop is unrolled by two).  Each wave owns a
+// WM x WN sub-tile of 16x16 MFMA blocks.
 //
 // FP64 uses v_mfma_f64_16x16x4f64: lane l supplies A[l%16][k] and B[k][l%16]
 // for k-slot l/16, and holds D[(l/16) + 4r][l%16] in register r.  Within a K
