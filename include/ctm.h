@@ -85,7 +85,13 @@ typedef struct {
   int rsvd_power_iters;    /* q, number of power iterations                        */
   uint64_t seed;           /* key of the counter-based sketch generator            */
   void* stream;            /* hipStream_t to run on, or NULL for a private stream  */
+  int projector_path;      /* CTM_PATH_AUTO, or CTM_PATH_HOUSEHOLDER to run every
+                              truncating cut through Householder QR and the
+                              library SVD (the path a cut takes when k > 320 or
+                              its Cholesky QR breaks down)                          */
 } ctm_config;
+
+enum { CTM_PATH_AUTO = 0, CTM_PATH_HOUSEHOLDER = 1 };
 
 typedef struct ctm_ctx ctm_ctx;
 
@@ -163,8 +169,9 @@ ctm_status ctm_move_count(const ctm_ctx* ctx, int64_t* moves);
  * counts[0] identity (the cut bond is no larger than chi), counts[1] the
  * batched randomized SVD (Cholesky QR + Jacobi), counts[2] the fallback
  * (Householder QR and LAPACK-style SVD, or the dense SVD when
- * rsvd_oversample < 0) taken when the Cholesky QR of a panel breaks down.
- * All paths compute the same projectors (Sec. 2.2). */
+ * rsvd_oversample < 0) taken when the Cholesky QR of a panel breaks down,
+ * the Jacobi SVD of a cut does not converge, k > 320, or projector_path is
+ * CTM_PATH_HOUSEHOLDER.  All paths compute the same projectors (Sec. 2.2). */
 ctm_status ctm_cut_stats(const ctm_ctx* ctx, int64_t counts[3]);
 
 /* Per-phase GPU timing with HIP events recorded on the context's stream

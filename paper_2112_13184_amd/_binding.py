@@ -43,7 +43,11 @@ class ctm_config(ctypes.Structure):
                 ("chi", ctypes.c_int), ("layers", ctypes.c_int), ("prec", ctypes.c_int),
                 ("svd_rel_cutoff", ctypes.c_double), ("rsvd_oversample", ctypes.c_int),
                 ("rsvd_power_iters", ctypes.c_int), ("seed", ctypes.c_uint64),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("projector_path", ctypes.c_int)]
+
+
+CTM_PATH_AUTO, CTM_PATH_HOUSEHOLDER = 0, 1
+PATHS = {"auto": CTM_PATH_AUTO, "householder": CTM_PATH_HOUSEHOLDER}
 
 
 class ctm_request(ctypes.Structure):
@@ -128,7 +132,7 @@ def _f64(a):
 
 
 def make_config(Lx, Ly, D, chi, d=2, layers=2, prec="f64", svd_rel_cutoff=0.0, rsvd_oversample=32,
-                rsvd_power_iters=1, seed=0, stream=None):
+                rsvd_power_iters=1, seed=0, stream=None, projector_path="auto"):
     cfg = ctm_config()
     cfg.Lx, cfg.Ly, cfg.d, cfg.D, cfg.chi, cfg.layers = Lx, Ly, d, D, chi, layers
     cfg.prec = PRECISIONS[prec] if isinstance(prec, str) else int(prec)
@@ -136,6 +140,7 @@ def make_config(Lx, Ly, D, chi, d=2, layers=2, prec="f64", svd_rel_cutoff=0.0, r
     cfg.rsvd_oversample, cfg.rsvd_power_iters = rsvd_oversample, rsvd_power_iters
     cfg.seed = seed
     cfg.stream = stream
+    cfg.projector_path = PATHS[projector_path] if isinstance(projector_path, str) else int(projector_path)
     return cfg
 
 

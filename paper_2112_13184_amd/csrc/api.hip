@@ -53,6 +53,10 @@ bool valid_config(const ctm_config* cfg, std::string& why) {
   long Db = (long)cfg->D * (cfg->layers == 2 ? cfg->D : 1);
   long n = cfg->chi * Db;
   if (n * n * (cfg->layers == 2 ? cfg->d : 1) > 2000000000L) { why = "chi * Db too large for 32-bit offsets"; return false; }
+  if (cfg->projector_path != CTM_PATH_AUTO && cfg->projector_path != CTM_PATH_HOUSEHOLDER) {
+    why = "projector_path must be CTM_PATH_AUTO or CTM_PATH_HOUSEHOLDER";
+    return false;
+  }
   if (cfg->rsvd_oversample < 0 && n > 8192) { why = "exact SVD mode (rsvd_oversample < 0) needs chi*Db <= 8192"; return false; }
   return true;
 }

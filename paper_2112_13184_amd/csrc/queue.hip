@@ -57,7 +57,7 @@ constexpr int kMaxGroup = 8;
 bool same_shape(const ctm_config& a, const ctm_config& b) {
   return a.Lx == b.Lx && a.Ly == b.Ly && a.d == b.d && a.D == b.D && a.chi == b.chi && a.layers == b.layers &&
          a.prec == b.prec && a.svd_rel_cutoff == b.svd_rel_cutoff && a.rsvd_oversample == b.rsvd_oversample &&
-         a.rsvd_power_iters == b.rsvd_power_iters;
+         a.rsvd_power_iters == b.rsvd_power_iters && a.projector_path == b.projector_path;
 }
 
 }  // namespace

@@ -39,6 +39,9 @@ constexpr int kJacobiMaxBS = 12;
 // k = 192, 5 up to k = 320
 constexpr int kRowsSmall = 3;
 constexpr int kRowsLarge = (kSmallLAMaxK + 63) / 64;
+// failure code of a problem whose Jacobi SVD did not converge (Cholesky
+// failures use 10 * pass + 1 or 2)
+constexpr int kJacobiUnconverged = 100;
 
 
 __device__ double block_reduce(double v, bool is_max, double* sh) {
@@ -333,6 +336,13 @@ __global__ void k_jacobi_init(double* J, int k, double* off, int* conv, int* nsw
 
 // After a sweep: converged if no pair needed a rotation (off = 0); nsweep
 // counts the sweeps that ran.
+// Problems whose Jacobi SVD has not converged get a failure code in the
+// Cholesky-failure slots, so that their cuts take the Householder path.
+__global__ void k_jacobi_mark_unconverged(const int* conv, int* fail, int batch) {
+  const int b = threadIdx.x;
+  if (b < batch && !conv[b]) fail[b] = max(fail[b], kJacobiUnconverged);
+}
+
 __global__ void k_jacobi_sweep_end(double* off, int* conv, int* nsweep, int batch, double tol) {
   const int b = threadIdx.x;
   if (b < batch) {
@@ -509,7 +519,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
 // for the finishing kernel, as after the blocked Jacobi.
 template <int LD, bool VEC>
 __global__ __launch_bounds__(1024) void k_jacobi_onewg(double* A, int m, double* S, double* J, double tol,
-                                                       int max_sweeps) {
+                                                       int max_sweeps, int* fail) {
   constexpr int NCOL = LD;                       // columns held (m rounded up to even <= LD)
   __shared__ double sA[NCOL * LD];
   __shared__ double sJ[VEC ? NCOL * LD : 1];
@@ -576,6 +586,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_onewg(double* A, int m, double*
     const int any = rotated;
     __syncthreads();
     if (!any) break;
+    // still rotating after the last allowed sweep: not converged
+    if (sw == max_sweeps - 1 && fail && tid == 0) fail[b] = max(fail[b], kJacobiUnconverged);
   }
   if (VEC) {
     double* Jb = J + (long)b * m * m;
@@ -731,12 +743,17 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
     // G = P^T P
     gemm(st, GemmType::F64, k, k, n, 1.0, rowmajor(P, n, pstride), colmajor(P, n, pstride), 0.0,
          out_colmajor(G, k, kk2), batch, ws);
-    // the shifted pass never drops; later passes drop directions whose pivot is
-    // below 1e-14 of the largest (they lie below any projector cutoff).  Only
-    // the output of two passes is near orthonormal, so the identity check runs
-    // from the third pass on.
+    // the shifted pass never drops; later passes drop a direction only when its
+    // pivot (squared residual norm) is below 1e-28 of the largest, i.e. its
+    // residual is at the rounding level of the basis (1e-14 relative): such a
+    // column is numerically dependent.  Directions damped by the shifted pass
+    // are far above that and are kept, as Householder QR keeps them; dropping
+    // them at a larger threshold (1e-14 in pivot, 1e-7 in norm) made the kept
+    // subspace change from move to move and stalled the corner-spectrum
+    // convergence of the iteration.  Only the output of two passes is near
+    // orthonormal, so the identity check runs from the third pass on.
     launch_chol(st, kb, batch, G, k, pass, pass == 0 ? 1 : 0, pass >= 2 ? 1 : 0, shift_scale,
-                pass == 0 ? 0.0 : 1e-14, rout, s.mask.as<double>(), s.flag.as<int>());
+                pass == 0 ? 0.0 : 1e-28, rout, s.mask.as<double>(), s.flag.as<int>());
     launch_trinv(st, rows, batch, rout, s.mask.as<double>(), k, Ri);
     CTM_HIP(hipGetLastError());
     // Q = P U^-1 into the other buffer (dropped directions come out zero)
@@ -765,7 +782,8 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   const double tol = 1e-15;
   if (k <= kJacobiOneWgMaxK) {
     // every sweep of a problem in one workgroup: one launch, no host reads
-    hipLaunchKernelGGL((k_jacobi_onewg<64, true>), dim3(batch), dim3(1024), 0, st, A, k, nullptr, J, tol, 14);
+    hipLaunchKernelGGL((k_jacobi_onewg<64, true>), dim3(batch), dim3(1024), 0, st, A, k, nullptr, J, tol, 14,
+                       s.flag.as<int>());
     CTM_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, sstride, Y);
     CTM_HIP(hipGetLastError());
@@ -806,6 +824,7 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
     if (all) break;
     sweeps(std::min(more, max_sweeps - done));
   }
+  hipLaunchKernelGGL(k_jacobi_mark_unconverged, dim3(1), dim3(64), 0, st, conv, s.flag.as<int>(), batch);
   hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, sstride, Y);
   CTM_HIP(hipGetLastError());
   static const bool debug = getenv("CTM_DEBUG") != nullptr;
@@ -826,10 +845,10 @@ void singular_values_small(hipStream_t st, const double* A, int m, int batch, do
   // the kernel reads A and writes only S; rows per lane sized to m
   if (m <= 64)
     hipLaunchKernelGGL((k_jacobi_onewg<64, false>), dim3(batch), dim3(1024), 0, st, const_cast<double*>(A), m, S,
-                       nullptr, 1e-15, 30);
+                       nullptr, 1e-15, 30, nullptr);
   else
     hipLaunchKernelGGL((k_jacobi_onewg<kSvSmallMax, false>), dim3(batch), dim3(1024), 0, st, const_cast<double*>(A), m,
-                       S, nullptr, 1e-15, 30);
+                       S, nullptr, 1e-15, 30, nullptr);
   CTM_HIP(hipGetLastError());
 }
 

@@ -9,7 +9,8 @@ namespace ctm {
 
 struct SmallLA {
   int kmax = 0, batch_max = 0;
-  // flag: 256 ints; [0, 64) Cholesky failure per problem, [64, 128) Jacobi
+  // flag: 256 ints; [0, 64) failure per problem (Cholesky breakdown, or a
+  // Jacobi SVD that did not converge), [64, 128) Jacobi
   // convergence per problem, [128, 192) projector-weight failure per problem,
   // [192, 256) Jacobi sweeps run per problem
   DevBuf G, R, Rinv, Racc, Rtmp, J, flag, off, tmp, mask;

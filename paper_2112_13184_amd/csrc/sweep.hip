@@ -793,7 +793,8 @@ static void column_projectors(Context& c, int rot, int x, int Lyv) {
       ++slot;
     }
   if (svd.empty()) return;
-  const bool fast = c.cfg.rsvd_oversample >= 0 && c.sla.kmax > 0 && smallla_fits(c.sla, c.kk);
+  const bool fast = c.cfg.rsvd_oversample >= 0 && c.cfg.projector_path == CTM_PATH_AUTO && c.sla.kmax > 0 &&
+                    smallla_fits(c.sla, c.kk);
   if (!fast) {
     for (size_t i = 0; i < svd.size(); ++i) cut_projectors(c, rot, svd[i][0], x, svd[i][1], svd_slot[i]);
     c.cuts[2] += (int64_t)svd.size();
@@ -818,7 +819,8 @@ static void column_projectors(Context& c, int rot, int x, int Lyv) {
 // Single cut through the same path as a move (used by ctm_projectors); slot 0.
 void cut_projectors_fast(Context& c, int rot, int x, int y) {
   const int nact = c.tdim[view_site(c, rot, x, y)][(3 + rot) % 4][0] * c.Db;
-  if (nact <= c.chi || c.cfg.rsvd_oversample < 0 || c.sla.kmax == 0 || !smallla_fits(c.sla, c.kk)) {
+  if (nact <= c.chi || c.cfg.rsvd_oversample < 0 || c.cfg.projector_path != CTM_PATH_AUTO || c.sla.kmax == 0 ||
+      !smallla_fits(c.sla, c.kk)) {
     cut_projectors(c, rot, 0, x, y, 0);
     ++c.cuts[nact <= c.chi ? 0 : 2];
     return;

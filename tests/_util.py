@@ -17,6 +17,19 @@ def inject(oracle_env, gpu_ctx, env):
             gpu_ctx.ctm_set_env(i, C, T)
 
 
+def ulp_perturbed(tensors, seed):
+    """Every entry moved one unit in the last place, up or down at random: a
+    change of the inputs at the level of unit roundoff, whose effect on a run
+    is the run's own sensitivity to rounding."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for a in tensors:
+        a = np.asarray(a, dtype=np.float64)
+        up = rng.random(a.shape) < 0.5
+        out.append(np.where(up, np.nextafter(a, np.inf), np.nextafter(a, -np.inf)))
+    return out
+
+
 def rel_err(a, b):
     a, b = np.asarray(a), np.asarray(b)
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

@@ -2,6 +2,8 @@
 the C ABI: results alone and in a mix, closed forms through the queue, HBM
 budget admission, cancellation, and the footprint bound."""
 import ctypes
+import json
+import os
 
 import numpy as np
 import pytest
@@ -99,22 +101,29 @@ def test_mean_field_states_through_queue(lib):
 
 
 def test_queue_matches_oracle(lib):
-    """One request through the queue against the oracle run with the same
-    sweeps (energy per site, 1e-10 or the run's sensitivity)."""
-    r = _requests(1, seed=9, chi_max=20, D_max=2)[0]
-    q = lib.Queue(16 << 30, 2)
-    st, t = q.submit(r["A"], r["Lx"], r["Ly"], r["D"], r["chi"], wl.tfim_bond(r["h"]), tol=0.0, max_sweeps=8,
-                     rsvd_oversample=16, rsvd_power_iters=1, seed=3)
-    assert st == B.CTM_OK
-    st, res = q.wait(t, 60000)
+    """The converged transverse-field Ising requests of the stored oracle runs
+    (D = 2 and 3, 1x1 and 2x2 cells, 40 sweeps), submitted together: energy
+    per site and <sigma_z> against the oracle, 1e-10 (tests/golden/
+    tfim_converged.json, written by make_golden.py from the oracle alone)."""
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tfim_converged.json")))
+    w = g["params"]
+    q = lib.Queue(16 << 30, 4)
+    tickets = []
+    for i, c in enumerate(g["cases"]):
+        A = wl.tfim_request_tensors(c["h"], c["D"], c["L"], c["L"], w["eps"], seed=c["tensor_seed"])
+        st, t = q.submit(A, c["L"], c["L"], c["D"], c["chi"], wl.tfim_bond(c["h"]), tol=0.0,
+                         max_sweeps=w["sweeps"], tag=i, rsvd_oversample=w["p"], rsvd_power_iters=w["q"],
+                         seed=w["sketch_seed"], svd_rel_cutoff=g["cutoff"])
+        assert st == B.CTM_OK
+        tickets.append(t)
+    for c, t in zip(g["cases"], tickets):
+        st, res = q.wait(t, 120000)
+        assert st == B.CTM_OK and res.sweeps == w["sweeps"]
+        de = abs(res.energy_per_site - c["energies"][str(w["sweeps"])])
+        dmz = max(abs(res.mz[i] - c["mz"][i]) for i in range(min(4, c["L"] ** 2)))
+        print(f"queue, tfim L={c['L']} D={c['D']} chi={c['chi']}: |dE| = {de:.2e}, max |d mz| = {dmz:.2e}")
+        assert de < 1e-10 and dmz < 1e-10
     q.destroy()
-    assert st == B.CTM_OK and res.sweeps == 8
-    env = Environment(r["A"], r["Lx"], r["Ly"], chi=r["chi"], layers=2, mode="rsvd", oversample=16,
-                      power_iters=1, seed=3)
-    for _ in range(8):
-        env.sweep()
-    e = ob.energy_per_site(env, wl.tfim_bond(r["h"]))
-    assert abs(res.energy_per_site - e) < 1e-10
 
 
 def test_budget_admission_and_cancel(lib):

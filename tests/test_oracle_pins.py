@@ -264,26 +264,6 @@ def test_classical_ising_error_shrinks_with_chi():
 # --------------------------------------------------------------------------
 # Double layer with exact answers: the Ising PEPS, also gauge transformed
 # --------------------------------------------------------------------------
-def _gauge_2x2(A, D, seed):
-    """Insert G G^-1 on every bond of a 2x2 cell of copies of A."""
-    Gh = [wl.random_gauges(D, seed + k) for k in range(4)]     # horizontal bonds
-    Gv = [wl.random_gauges(D, seed + 10 + k) for k in range(4)]
-    out = []
-    for y in range(2):
-        for x in range(2):
-            i = x + 2 * y
-            h_right = Gh[x + 2 * y]
-            h_left = Gh[((x - 1) % 2) + 2 * y]
-            v_up = Gv[x + 2 * y]
-            v_down = Gv[x + 2 * ((y - 1) % 2)]
-            B = np.einsum("lurdp,Rr->luRdp", A, h_right)
-            B = np.einsum("lurdp,lL->Lurdp", B, np.linalg.inv(h_left))
-            B = np.einsum("lurdp,Uu->lUrdp", B, v_up)
-            B = np.einsum("lurdp,dD->lurDp", B, np.linalg.inv(v_down))
-            out.append(B)
-    return out
-
-
 @pytest.mark.parametrize("cell", ["1x1", "2x2gauged"])
 def test_ising_peps_closed_forms(cell):
     beta = 0.5
@@ -291,7 +271,7 @@ def test_ising_peps_closed_forms(cell):
     if cell == "1x1":
         tensors, Lx, Ly = [A], 1, 1
     else:
-        tensors, Lx, Ly = _gauge_2x2(A, 2, seed=7), 2, 2
+        tensors, Lx, Ly = wl.gauged_2x2(A, 2, seed=7), 2, 2
         wp = None   # gauges on the boundary break the polarised product; use delta
     env = Environment(tensors, Lx, Ly, chi=16, layers=2, boundary=wp, mode="rsvd",
                       oversample=16, power_iters=2, seed=2)

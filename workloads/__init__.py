@@ -64,6 +64,27 @@ def random_gauges(D, seed):
             return G
 
 
+def gauged_2x2(A, D, seed):
+    """A 2x2 cell of copies of A with a random invertible G G^-1 inserted on
+    every bond (the state, and every expectation value, is unchanged; the four
+    site tensors differ)."""
+    Gh = [random_gauges(D, seed + k) for k in range(4)]       # horizontal bonds
+    Gv = [random_gauges(D, seed + 10 + k) for k in range(4)]  # vertical bonds
+    out = []
+    for y in range(2):
+        for x in range(2):
+            h_right = Gh[x + 2 * y]
+            h_left = Gh[((x - 1) % 2) + 2 * y]
+            v_up = Gv[x + 2 * y]
+            v_down = Gv[x + 2 * ((y - 1) % 2)]
+            B = np.einsum("lurdp,Rr->luRdp", A, h_right)
+            B = np.einsum("lurdp,lL->Lurdp", B, np.linalg.inv(h_left))
+            B = np.einsum("lurdp,Uu->lUrdp", B, v_up)
+            B = np.einsum("lurdp,dD->lurDp", B, np.linalg.inv(v_down))
+            out.append(B)
+    return out
+
+
 def random_itps(Lx, Ly, D, d, seed):
     rng = np.random.default_rng(seed)
     out = []
