@@ -10,13 +10,13 @@
  * T (chi x chi x D^2), fixed by directional moves (absorb a column, build the
  * enlarged corners, compute QR-free projectors from a partial / randomized SVD
  * of the 2x2 cluster, renormalise).  The converged environment gives one-site
- * and nearest-neighbour expectation values (Sec. 4.5).
+ * and nearest-neighbour expectation values (Sec. 5.3).
  *
  * Conventions (all arrays row-major, C order, FP64 unless stated):
  *   site tensor     A[l][u][r][d][p] (D^4 d values); classical network
  *                   (layers = 1): a[l][u][r][d] (D^4 values, d must be 1)
  *   site index      i = x + Lx * y, +y points up (r = (0,1) is the upper
- *                   neighbour, Sec. 4.5)
+ *                   neighbour, Sec. 5.3)
  *   pair index      ket * D + bra for a double-layer bond (Db = D^2);
  *                   Db = D for a classical network
  *   environment     per site, clockwise C1 T1 C2 T2 C3 T3 C4 T4 (C1 upper
@@ -27,7 +27,7 @@
  *                   into C3 T2 C2, CTM_UP into C2 T1 C1, CTM_DOWN into C4 T3 C3.
  *   operators       one-site op[out][in] (d x d); two-site
  *                   op[(out_i, out_j)][(in_i, in_j)] (d^2 x d^2), the element
- *                   order of the paper's operator input (Sec. 3.2).
+ *                   order of the paper's operator input (Sec. 5.2).
  *
  * Errors: every call returns a ctm_status.  Invalid arguments give
  * CTM_EINVAL and leave the state unchanged; device failures CTM_EDEVICE;
@@ -95,9 +95,11 @@ enum { CTM_PATH_AUTO = 0, CTM_PATH_HOUSEHOLDER = 1 };
 
 typedef struct ctm_ctx ctm_ctx;
 
-/* Sec. 2.2: set up a context for the given site tensors.  tensors holds
- * Lx*Ly site tensors back to back (site order i = x + Lx*y), in host memory
- * (tensors_on_device = 0) or device memory (1).  boundary (Db values, host)
+/* Sec. 2.2 (the iTPS of Sec. 2.1 and its double layer, Fig. 2): set up a
+ * context for the given site tensors.  tensors holds Lx*Ly site tensors back
+ * to back (site order i = x + Lx*y), in host memory (tensors_on_device = 0)
+ * or device memory (1, read on cfg->stream, after the work enqueued on that
+ * stream before the call, and not referenced afterwards).  boundary (Db values, host)
  * is the vector on every outer leg of the initial environment, or NULL for
  * the ket/bra identity (layers = 2) / all ones (layers = 1).  The initial
  * environment has C = [[1]] and T[0][0][:] = boundary (all chi legs of
@@ -108,7 +110,9 @@ ctm_status ctm_init(const ctm_config* cfg, const double* tensors, int tensors_on
 /* Sec. 2.2: one directional move over every column (row) of the unit cell. */
 ctm_status ctm_move(ctm_ctx* ctx, ctm_dir dir);
 
-/* Up to max_sweeps sweeps (left, right, up, down).  After every sweep the
+/* Sec. 2.2 (iterative determination of C and T) with the convergence
+ * criterion of the ctm parameters (Sec. 5.2), read as follows.
+ * Up to max_sweeps sweeps (left, right, up, down).  After every sweep the
  * singular values of every corner, normalised to sum 1, are compared with
  * those of the previous sweep; the run stops when the largest L1 change
  * (delta) is below tol.  Any out pointer may be NULL.  Not converging is not
@@ -116,7 +120,10 @@ ctm_status ctm_move(ctm_ctx* ctx, ctm_dir dir);
 ctm_status ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done,
                      double* delta, int* converged);
 
-/* Projectors of one cut of a move, computed from the current environment and
+/* Sec. 2.2: the QR-free projectors of one cut, from the partial
+ * (randomized) SVD of the cluster matrix, which is applied only through
+ * products with the four enlarged corners.
+ * Projectors of one cut of a move, computed from the current environment and
  * not applied.  (x, y) are the column and cut row in the frame of the move
  * (the frame in which the move is a left move: the lattice rotated by 0, 2, 1,
  * 3 quarter turns counter-clockwise for left, right, up, down).  With
@@ -126,16 +133,18 @@ ctm_status ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done,
 ctm_status ctm_projectors(ctm_ctx* ctx, ctm_dir dir, int x, int y, double* P, double* Pt,
                           int* k_eff);
 
-/* Enlarged corner of role `corner` (0..3 = C1..C4) around `site`, as the
+/* Sec. 2.2, Fig. 2(c): a corner matrix with its two edge tensors and the
+ * site absorbed.
+ * Enlarged corner of role `corner` (0..3 = C1..C4) around `site`, as the
  * n x n matrix E[(c_next, o_next)][(c_prev, o_prev)] (host buffer): the
  * corner, its two edge tensors and the site seen from that corner, with ket
  * and bra contracted one after the other.  For testing. */
 ctm_status ctm_enlarged_corner(ctm_ctx* ctx, int corner, int site, double* E);
 
-/* Sec. 4.5: <op> at `site` from the 3x3 patch of the environment. */
+/* Sec. 5.3: <op> at `site` from the 3x3 patch of the environment. */
 ctm_status ctm_expect_1site(ctm_ctx* ctx, int site, const double* op, double* val);
 
-/* Sec. 4.5: <op> on the bond from `site` to its neighbour at +x (dir = 0) or
+/* Sec. 5.3: <op> on the bond from `site` to its neighbour at +x (dir = 0) or
  * +y (dir = 1), from the 3x4 / 4x3 patch.  op is d^2 x d^2 (see above). */
 ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, double* val);
 
@@ -144,15 +153,21 @@ ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, d
 ctm_status ctm_rho_1site(ctm_ctx* ctx, int site, double* rho);
 ctm_status ctm_rho_2site(ctm_ctx* ctx, int site, int dir, double* rho);
 
-/* Classical network (layers = 1): Z(b) / Z(a) on the 3x3 patch of `site`,
+/* The single-layer network of Fig. 2(b) contracted with the environment of
+ * Fig. 2(c), for a classical network (layers = 1): Z(b) / Z(a) on the 3x3 patch of `site`,
  * with b (D^4, host) in place of the site tensor (e.g. a magnetisation). */
 ctm_status ctm_impurity(ctm_ctx* ctx, int site, const double* b, double* val);
 
-/* 1x1 cell: ln kappa, the log of the partition function (norm) per site, as
+/* The contraction of the whole network of Fig. 2 (the norm of the iTPS, or
+ * the partition function of a classical network) per site, 1x1 cell:
+ * ln kappa, the log of the partition function (norm) per site, as
  * ln Z(3x3) + ln Z(corners) - ln Z(2x3) - ln Z(3x2). */
 ctm_status ctm_log_kappa(ctm_ctx* ctx, double* ln_kappa);
 
-/* Environment of one site as host FP64: C1..C4 (chi*chi each) then T1..T4
+/* The environment of Fig. 2(c) (corner matrices and edge tensors of one
+ * site), read or replaced, so that a converged environment can be kept and
+ * reused, as the paper's saved tensors are (Sec. 5.3).
+ * Environment of one site as host FP64: C1..C4 (chi*chi each) then T1..T4
  * (chi*chi*Db each), zero padded; bytes must be >= ctm_env_bytes().  dims
  * (16 ints, may be NULL) gets the actual leg dimensions: C_k (next, prev) for
  * k = 1..4, then T_k (prev, next). */
@@ -206,46 +221,85 @@ const char* ctm_last_error(const ctm_ctx* ctx);
 void ctm_free(ctm_ctx* ctx);
 
 /* ------------------------------------------------------------------------ */
-/* Serving: continuous batching of independent CTMRG solves on one GPU.      */
+/* Serving: continuous batching of independent CTMRG solves on one GPU       */
+/* (a Hamiltonian parameter scan, say).  Each request is a CTMRG run of the  */
+/* given site tensors to convergence (Sec. 2.2) followed by the expectation  */
+/* values of Sec. 5.3: energy per site and the requested observables.        */
 /* ------------------------------------------------------------------------ */
 typedef struct ctm_queue ctm_queue;
 
+#define CTM_MAX_OBS 8       /* observables of each kind per request            */
+#define CTM_MAX_SITES 16    /* largest unit cell                               */
+
 typedef struct {
-  ctm_config cfg;            /* stream is ignored: the queue owns its streams      */
-  const double* tensors;     /* host, Lx*Ly site tensors (copied at submit)        */
-  const double* bond_op;     /* d^2 x d^2 bond operator on every +x and +y bond     */
-  const double* onsite_op;   /* d x d, or NULL                                      */
-  double tol;                /* stop when delta < tol                               */
+  ctm_config cfg;            /* stream is ignored: each group runs on its own stream */
+  const double* tensors;     /* Lx*Ly site tensors (layout as for ctm_init); host
+                                memory, or device memory if tensors_on_device     */
+  int tensors_on_device;     /* device tensors are copied at submit, on the queue's
+                                stream (after the work enqueued on it before)      */
+  const double* bond_op;     /* d^2 x d^2 operator on every +x and +y bond (the
+                                Hamiltonian term, Sec. 5.2 element order)          */
+  const double* onsite_op;   /* d x d Hamiltonian term on every site, or NULL     */
+  int n_obs;                 /* one-site observables to measure, 0..CTM_MAX_OBS   */
+  const double* obs_ops;     /* n_obs operators of d x d, back to back ([out][in]) */
+  int n_obs2;                /* two-site observables, 0..CTM_MAX_OBS              */
+  const double* obs2_ops;    /* n_obs2 operators of d^2 x d^2, back to back       */
+  double tol;                /* stop when delta < tol (see ctm_sweep)             */
   int max_sweeps;
-  uint64_t tag;              /* returned unchanged                                  */
+  uint64_t tag;              /* returned unchanged                                */
 } ctm_request;
 
 typedef struct {
-  ctm_status status;
+  ctm_status status;         /* CTM_OK, CTM_ENUMERIC (this solve only), CTM_ECANCELED,
+                                CTM_EDEVICE / CTM_ENOMEM                           */
   int converged, sweeps;
   double delta;
-  double energy_per_site;    /* (1/N) sum_s <h_{s,s+x}> + <h_{s,s+y}> + <h_s>       */
-  double mz[4];              /* <sigma_z> style one-site values of op diag(1,-1)
-                                on the first min(4, N) sites (d = 2 only)          */
+  double energy_per_site;    /* (1/N) sum_s <h_{s,s+x}> + <h_{s,s+y}> + <h_s>     */
+  double obs[CTM_MAX_OBS][CTM_MAX_SITES];      /* <O_k> at site i (i < Lx*Ly)     */
+  double obs2[CTM_MAX_OBS][CTM_MAX_SITES][2];  /* <O2_k> on the bond from site i to
+                                                  i + x [0] and to i + y [1]      */
   uint64_t tag;
-  int64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady clock                   */
+  int64_t t_submit_ns, t_admit_ns, t_done_ns;   /* steady clock; t_done is the time
+                                                   this solve's result was published */
 } ctm_result;
 
-/* A queue admits requests while the summed footprints of the active ones stay
- * within hbm_budget_bytes and at most max_active run at once.  Active solves
- * advance one directional move per scheduling round; moves of solves with the
- * same (D, chi, d, layers) run their enlarged-corner and sketch GEMMs as one
- * grouped launch. */
-ctm_status ctm_queue_create(size_t hbm_budget_bytes, int max_active, ctm_queue** out);
-/* Copies the request and returns at once; *ticket identifies it.  A request
- * whose footprint exceeds the budget is rejected with CTM_ETOOBIG. */
+/* A queue of CTMRG solves run concurrently on the current device.
+ *
+ * Admission: up to max_active groups run at once, each on a worker thread
+ * with its own context and HIP stream; a pending request is admitted (first
+ * fit in arrival order; a request passed over by 8 later admissions stops
+ * further skipping) when the summed footprints (ctm_footprint_bytes) of the
+ * running groups plus its own stay within hbm_budget_bytes.  Later pending
+ * requests of the same shape (every ctm_config field but seed and stream)
+ * join it, up to 8, while the group's footprint fits: the group's solves are
+ * replicas of one context, whose launches cover the cuts of all its live
+ * replicas.
+ * Per solve: sweeps until delta < tol, max_sweeps, cancellation (checked
+ * between sweeps) or a numerical failure of that solve alone (NaN / Inf, or
+ * a cut without singular values: CTM_ENUMERIC); then its observables are
+ * evaluated and its result published at once.  Its slot in the group is then
+ * free: at the next sweep boundary the oldest pending request of the same
+ * shape takes it (no further memory), so a group keeps running while such
+ * requests arrive.  The group's memory returns to the budget when its last
+ * solve is published.  A request's result does not depend on the other
+ * requests it ran with (same seed, same result, bitwise).
+ * stream: hipStream_t (e.g. the caller's torch stream) on which device-side
+ * request tensors are read at submit, or NULL for the null stream. */
+ctm_status ctm_queue_create(size_t hbm_budget_bytes, int max_active, void* stream, ctm_queue** out);
+/* Copies the request (inputs and operators) and returns at once; *ticket
+ * identifies it.  CTM_ETOOBIG if its footprint exceeds the budget, CTM_EINVAL
+ * for a bad shape, NULL pointers or too many observables, CTM_ENUMERIC for
+ * NaN / Inf in the site tensors. */
 ctm_status ctm_queue_submit(ctm_queue* q, const ctm_request* req, uint64_t* ticket);
-/* CTM_EAGAIN while pending; otherwise the final status, result filled in. */
+/* CTM_EAGAIN while pending or running; otherwise the final status, with the
+ * result filled in. */
 ctm_status ctm_queue_poll(ctm_queue* q, uint64_t ticket, ctm_result* res);
 /* Waits up to timeout_ms (< 0: forever); CTM_EAGAIN on timeout. */
 ctm_status ctm_queue_wait(ctm_queue* q, uint64_t ticket, int timeout_ms, ctm_result* res);
+/* A pending request ends at once (CTM_ECANCELED); a running one at its next
+ * sweep boundary. */
 ctm_status ctm_queue_cancel(ctm_queue* q, uint64_t ticket);
-/* Cancels pending requests, waits for active ones, frees everything. */
+/* Cancels pending requests, waits for running ones, frees everything. */
 void ctm_queue_destroy(ctm_queue* q);
 
 #ifdef __cplusplus

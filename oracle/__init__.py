@@ -12,7 +12,7 @@ philox        Philox4x64-10 counter-based generator and the sketch matrix
 ctmrg         environment, enlarged corners, projectors, directional moves
               and sweeps (Sec. 2.2, Fig. 2).
 observables   reduced density matrices, expectation values, ln(kappa),
-              impurity ratios, correlation functions (Sec. 4.5, Eq. (8)).
+              impurity ratios, correlation functions (Sec. 5.3, Eq. (8)).
 closed_forms  Onsager / Yang closed forms of the 2D Ising model.
 bruteforce    exact contraction of small finite networks.
 

@@ -72,3 +72,23 @@ def patch_value(tensors, Lx, Ly, layers, boundary, x0, x1, y0, y1, open_sites=()
                 row.append(A)
         grid.append(row)
     return contract_grid(grid, boundary)
+
+
+def strip_transfer(A, layers, boundary, H):
+    """Column transfer matrix of a strip H sites high, closed at the top and
+    the bottom by ``boundary``: M[(l_1..l_H), (r_1..r_H)] with site 1 at the
+    top, each leg of the double-layer (or classical) tensor.  Used to check
+    the transfer-matrix spectrum of an untruncated environment."""
+    t = double_layer(A) if layers == 2 else np.asarray(A, dtype=np.float64)
+    w = np.asarray(boundary, dtype=np.float64)
+    # top site: close its up leg -> S[l1, r1, d1]
+    S = np.tensordot(t, w, axes=([1], [0]))            # [l, r, d]
+    for _ in range(H - 1):
+        # next site below: contract the open down leg with its up leg
+        S = np.tensordot(S, t, axes=([-1], [1]))       # [..., l_k, r_k, d_k]
+    S = np.tensordot(S, w, axes=([-1], [0]))           # close the bottom
+    # axes now (l_1, r_1, l_2, r_2, ..., l_H, r_H)
+    b = t.shape[0]
+    S = S.reshape((b, b) * H)
+    S = S.transpose(list(range(0, 2 * H, 2)) + list(range(1, 2 * H, 2)))
+    return S.reshape(b ** H, b ** H)

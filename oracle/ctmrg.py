@@ -10,7 +10,7 @@ What this follows
   al. (PRL 113, 046402), modified so that no QR of the half systems is done,
   and with the SVD taken as a partial (randomized, Halko et al. 2011) SVD that
   only applies the matrix to vectors.
-* Sec. 3.2 / 4.5: bra = complex conjugate of ket; +y points up.
+* Sec. 5.2 / 5.3: bra = complex conjugate of ket; +y points up.
 
 Conventions (the paper leaves these open; each one is a reading)
 -----------------------------------------------------------------

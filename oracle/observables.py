@@ -1,6 +1,6 @@
 """Expectation values from a converged environment.  TEST INFRASTRUCTURE ONLY.
 
-Sec. 4.5 of the paper lists what is measured after the CTMRG: one-site
+Sec. 5.3 of the paper lists what is measured after the CTMRG: one-site
 observables, nearest-neighbour two-site observables (with r = (1, 0) the right
 neighbour and r = (0, 1) the upper one), correlation functions
 C(r, r0) = <A(r0) B(r0 + r)> (Eq. (8)) and the correlation length.  Two-site
@@ -175,29 +175,116 @@ def log_kappa(env):
     return float(np.log(z33) + np.log(zc) - np.log(z23) - np.log(z32))
 
 
-def correlation_x(env, i, opA, opB, rmax):
-    """C(r) = <A(s) B(s + r x)> for r = 1..rmax along +x (Eq. (8))."""
-    Lx = env.Lx
-    y = i // Lx
-    out = []
-    C0, T0, A0 = _env_view(env, i, 0)
+def _line(env, i, direction):
+    """Frame and view coordinates for a walk from site i along +x (direction
+    0) or +y (1): the +y walk is a +x walk in the frame rotated three quarter
+    turns counter-clockwise.  Returns (r, xv, yv)."""
+    r = 0 if direction == 0 else 3
+    x, y = i % env.Lx, i // env.Lx
+    for _ in range(r):
+        x, y = -y, x                                   # physical -> view coordinates
+    return r, x, y
+
+
+def correlation(env, i, opA, opB, rmax, direction=0):
+    """C(r) = <A(r0) B(r0 + r e)> for r = 0..rmax (Sec. 5.3, Eq. (8)).
+
+    r0 is site i, e = (1, 0) (direction 0) or (0, 1) (direction 1); A and B
+    are one-site operators op[out, in].  r = 0 is the one-site expectation
+    of the product A B.  For r >= 1 the patch is the left boundary of r0, the
+    column of r0 with A inserted, r - 1 plain columns, the column of r0 + r e
+    with B inserted and its right boundary, over the same patch without
+    operators.  Both boundaries are rescaled by the same factor after every
+    column (the ratio is unchanged).
+    """
+    Lx, Ly = env.Lx, env.Ly
+    r_frame, xv, yv = _line(env, i, direction)
+    vs = lambda a: view_site(Lx, Ly, r_frame, a, yv)
+    assert vs(xv) == i
+    out = [expect(rho_one_site(env, i), np.asarray(opA) @ np.asarray(opB))]
+    C0, T0, A0 = _env_view(env, i, r_frame)
     LB = left_boundary(C0[0], T0[3], C0[3])
     Xop = column(LB, T0[0], T0[2], A0, env.layers, open_phys=True)
-    Xop = np.tensordot(Xop, opA, axes=([3, 4], [1, 0]))       # apply A: sum_{p,p'} X[p,p'] A[p',p]
+    Xop = np.tensordot(Xop, opA, axes=([3, 4], [1, 0]))       # sum_{p,p'} X[p,p'] A[p',p]
     Xid = column(LB, T0[0], T0[2], A0, env.layers)
-    x = i % Lx
-    for r in range(1, rmax + 1):
-        j = ((x + r) % Lx) + Lx * y
-        Cj, Tj, Aj = _env_view(env, j, 0)
+    for dist in range(1, rmax + 1):
+        j = vs(xv + dist)
+        Cj, Tj, Aj = _env_view(env, j, r_frame)
         RB = right_boundary(Cj[1], Tj[1], Cj[2])
         num_col = column(Xop, Tj[0], Tj[2], Aj, env.layers, open_phys=True)
         den_col = column(Xid, Tj[0], Tj[2], Aj, env.layers)
         num = np.tensordot(_close(num_col, RB), opB, axes=([0, 1], [1, 0]))
         den = _close(den_col, RB)
-        out.append(float(num / den))
+        out.append(float(np.real(num / den)))
         Xop = column(Xop, Tj[0], Tj[2], Aj, env.layers)
         Xid = den_col
-        # keep the scale of both boundaries comparable
         sc = np.max(np.abs(Xid))
         Xop, Xid = Xop / sc, Xid / sc
     return np.array(out)
+
+
+def transfer_apply(env, line, direction):
+    """The transfer matrix of one period of the unit cell along +x (direction
+    0, in row `line`) or +y (direction 1, in column `line`), as a function on
+    flattened left boundaries LB[t1, l, t3]: the columns (T1 above, the
+    double-layer site, T3 below) of the period's sites, in order.  Returns
+    (apply, dim, period)."""
+    Lx, Ly = env.Lx, env.Ly
+    i = (0 + Lx * line) if direction == 0 else (line + 0)
+    r_frame, xv, yv = _line(env, i, direction)
+    period = Lx if direction == 0 else Ly
+    cols = []
+    for k in range(period):
+        C, T, A = _env_view(env, view_site(Lx, Ly, r_frame, xv + k, yv), r_frame)
+        cols.append((T[0], T[2], A))
+    shape = (cols[0][0].shape[0], env.Db, cols[0][1].shape[1])
+
+    def apply(v):
+        X = np.asarray(v).reshape(shape)
+        for T1, T3, A in cols:
+            X = column(X, T1, T3, A, env.layers)
+        return X.reshape(-1)
+
+    return apply, int(np.prod(shape)), period
+
+
+def transfer_spectrum(env, line, direction, nev=4):
+    """The nev eigenvalues of largest modulus of the transfer matrix of one
+    period (sorted by modulus, descending, complex).  Dense eigenvalues of
+    the formed matrix up to dimension 3000, else ARPACK (implicitly
+    restarted Arnoldi) through scipy."""
+    apply, dim, _ = transfer_apply(env, line, direction)
+    if dim <= 3000:
+        M = np.empty((dim, dim))
+        e = np.zeros(dim)
+        for c in range(dim):
+            e[c] = 1.0
+            M[:, c] = apply(e)
+            e[c] = 0.0
+        lam = np.linalg.eigvals(M)
+    else:
+        from scipy.sparse.linalg import LinearOperator, eigs
+        op = LinearOperator((dim, dim), matvec=apply, dtype=np.float64)
+        lam = eigs(op, k=min(nev, dim - 2), which="LM", return_eigenvectors=False, tol=1e-13, ncv=40)
+    lam = lam[np.argsort(-np.abs(lam), kind="stable")]
+    return lam[:nev]
+
+
+def correlation_length(lam, period):
+    """(xi, e) from transfer-matrix eigenvalues (Sec. 5.3): e_k =
+    -log|lam_k / lam_0| per lattice spacing (the matrix spans `period`
+    sites), xi = 1 / e_1."""
+    lam = np.asarray(lam)
+    with np.errstate(divide="ignore"):
+        e = -np.log(np.abs(lam[1:]) / np.abs(lam[0])) / period
+    return (1.0 / e[0] if e[0] > 0 else np.inf), e
+
+
+def xi_extrapolate(e1, e2):
+    """Finite-chi extrapolation of Eq. (9) over runs at several chi: the
+    least-squares line e1 = 1/xi(inf) - k (e2 - e1).  Returns (1/xi(inf), k)."""
+    e1, e2 = np.asarray(e1, dtype=np.float64), np.asarray(e2, dtype=np.float64)
+    delta = e2 - e1
+    Amat = np.stack([np.ones_like(delta), -delta], axis=1)
+    (inv_xi, k), *_ = np.linalg.lstsq(Amat, e1, rcond=None)
+    return float(inv_xi), float(k)

@@ -50,10 +50,16 @@ CTM_PATH_AUTO, CTM_PATH_HOUSEHOLDER = 0, 1
 PATHS = {"auto": CTM_PATH_AUTO, "householder": CTM_PATH_HOUSEHOLDER}
 
 
+CTM_MAX_OBS, CTM_MAX_SITES = 8, 16
+
+
 class ctm_request(ctypes.Structure):
     _fields_ = [("cfg", ctm_config), ("tensors", ctypes.POINTER(ctypes.c_double)),
+                ("tensors_on_device", ctypes.c_int),
                 ("bond_op", ctypes.POINTER(ctypes.c_double)),
                 ("onsite_op", ctypes.POINTER(ctypes.c_double)),
+                ("n_obs", ctypes.c_int), ("obs_ops", ctypes.POINTER(ctypes.c_double)),
+                ("n_obs2", ctypes.c_int), ("obs2_ops", ctypes.POINTER(ctypes.c_double)),
                 ("tol", ctypes.c_double), ("max_sweeps", ctypes.c_int), ("tag", ctypes.c_uint64)]
 
 
@@ -67,9 +73,19 @@ class ctm_timing(ctypes.Structure):
 class ctm_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("converged", ctypes.c_int), ("sweeps", ctypes.c_int),
                 ("delta", ctypes.c_double), ("energy_per_site", ctypes.c_double),
-                ("mz", ctypes.c_double * 4), ("tag", ctypes.c_uint64),
+                ("obs", (ctypes.c_double * CTM_MAX_SITES) * CTM_MAX_OBS),
+                ("obs2", ((ctypes.c_double * 2) * CTM_MAX_SITES) * CTM_MAX_OBS),
+                ("tag", ctypes.c_uint64),
                 ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
                 ("t_done_ns", ctypes.c_int64)]
+
+    def observable(self, k, nsites):
+        """<O_k> per site (one-site observable k of the request)."""
+        return np.array([self.obs[k][i] for i in range(nsites)])
+
+    def observable2(self, k, nsites):
+        """<O2_k> per site and bond direction (+x, +y), shape (nsites, 2)."""
+        return np.array([[self.obs2[k][i][dr] for dr in range(2)] for i in range(nsites)])
 
 
 _lib = None
@@ -108,7 +124,7 @@ def load(path=LIB_PATH):
         "ctm_free": (None, [V]),
         "ctm_timing_enable": (I, [V, I]),
         "ctm_timing_read": (I, [V, ctypes.POINTER(ctm_timing)]),
-        "ctm_queue_create": (I, [S, I, ctypes.POINTER(V)]),
+        "ctm_queue_create": (I, [S, I, V, ctypes.POINTER(V)]),
         "ctm_queue_submit": (I, [V, ctypes.POINTER(ctm_request), ctypes.POINTER(ctypes.c_uint64)]),
         "ctm_queue_poll": (I, [V, ctypes.c_uint64, ctypes.POINTER(ctm_result)]),
         "ctm_queue_wait": (I, [V, ctypes.c_uint64, I, ctypes.POINTER(ctm_result)]),
@@ -291,24 +307,45 @@ class Ctm:
 class Queue:
     """A ctm_queue: CTMRG solves admitted by HBM footprint and run concurrently."""
 
-    def __init__(self, hbm_budget_bytes, max_active):
+    def __init__(self, hbm_budget_bytes, max_active, stream=None):
         lib = load()
         q = ctypes.c_void_p()
-        st = lib.ctm_queue_create(int(hbm_budget_bytes), int(max_active), ctypes.byref(q))
+        st = lib.ctm_queue_create(int(hbm_budget_bytes), int(max_active), stream, ctypes.byref(q))
         if st != CTM_OK:
             raise CtmError(st, "ctm_queue_create failed")
-        self._lib, self._q, self._keep = lib, q, {}
+        self._lib, self._q = lib, q
 
     def submit(self, tensors, Lx, Ly, D, chi, bond_op, onsite_op=None, tol=1e-10, max_sweeps=40, tag=0,
-               d=2, **kw):
-        """Returns (status, ticket); inputs are copied by the library."""
+               d=2, obs=(), obs2=(), device_ptr=None, **kw):
+        """Returns (status, ticket); inputs are copied by the library.  obs /
+        obs2: one-site (d x d) and two-site (d^2 x d^2) observables to measure;
+        device_ptr: address of the site tensors in device memory (then
+        ``tensors`` is ignored)."""
         req = ctm_request()
         req.cfg = make_config(Lx, Ly, D, chi, d=d, **kw)
-        t = _f64(np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for a in tensors]))
+        keep = []
+        if device_ptr is not None:
+            req.tensors = ctypes.cast(ctypes.c_void_p(int(device_ptr)), _DP)
+            req.tensors_on_device = 1
+        else:
+            t = _f64(np.concatenate([np.asarray(a, dtype=np.float64).reshape(-1) for a in tensors]))
+            keep.append(t)
+            req.tensors = _dp(t)
         b = _f64(bond_op)
-        o = _f64(onsite_op) if onsite_op is not None else None
-        req.tensors, req.bond_op = _dp(t), _dp(b)
-        req.onsite_op = _dp(o) if o is not None else None
+        keep.append(b)
+        req.bond_op = _dp(b)
+        if onsite_op is not None:
+            o = _f64(onsite_op)
+            keep.append(o)
+            req.onsite_op = _dp(o)
+        if len(obs):
+            a = _f64(np.stack([np.asarray(x, dtype=np.float64) for x in obs]))
+            keep.append(a)
+            req.n_obs, req.obs_ops = len(obs), _dp(a)
+        if len(obs2):
+            a = _f64(np.stack([np.asarray(x, dtype=np.float64) for x in obs2]))
+            keep.append(a)
+            req.n_obs2, req.obs2_ops = len(obs2), _dp(a)
         req.tol, req.max_sweeps, req.tag = float(tol), int(max_sweeps), int(tag)
         ticket = ctypes.c_uint64()
         st = self._lib.ctm_queue_submit(self._q, ctypes.byref(req), ctypes.byref(ticket))

@@ -94,7 +94,13 @@ struct Context {
   int R = 1;
   int NS() const { return R * N; }
   std::vector<uint64_t> seeds;   // sketch seed per replica
-  std::vector<char> frozen;      // replica no longer updated (converged, capped, cancelled)
+  std::vector<long long> rmoves; // moves done by each replica (keys its sketch streams)
+  std::vector<char> frozen;      // replica no longer updated (converged, capped, cancelled, failed)
+  // NaN / Inf or a cut without singular values in a replica's last move.  A
+  // context with isolate set records it here (and the caller freezes the
+  // replica); otherwise the move throws CTM_ENUMERIC.
+  std::vector<char> failed;
+  bool isolate = false;
   int D = 0, d = 0, DK = 0, DB = 0, Db = 0, chi = 0, n = 0, layers = 2;
   int kk = 0;               // sketch width
   double cutoff = 1e-12;
@@ -199,6 +205,15 @@ void cut_projectors_fast(Context& c, int rot, int x, int y);
 // finished replica is frozen.  done / delta / converged: one entry per replica.
 void do_sweeps_group(Context& c, const int* max_sweeps, const double* tol, int* done, double* delta,
                      int* converged, const std::atomic<bool>* const* cancel);
+// The steps of do_sweeps_group, for a caller that drives the replicas itself
+// (the serving queue): group_start takes the reference corner spectra of
+// every replica; group_sweep runs one sweep of the live replicas and returns
+// each replica's delta in host_delta (R values; entries of frozen replicas
+// are not meaningful).  replica_reset starts a new solve in slot r (site
+// tensors, trivial environment, reference spectra, move count, seed).
+void group_start(Context& c);
+void group_sweep(Context& c, double* host_delta);
+void replica_reset(Context& c, int r, const double* tensors_host, uint64_t seed);
 void enlarged_corner(Context& c, int s, int j, double* out);
 // Reduced density matrices, normalised to trace 1, in the device buffer
 // rho_dev (d*d or d^4 doubles); copied to rho_host when it is not null.

@@ -272,7 +272,7 @@ __global__ void k_maxabs_partial_b(double* const* x, long n, double* part) {
   if (threadIdx.x == 0) part[(long)blockIdx.y * kNormSlots + blockIdx.x] = m;
 }
 
-__global__ void k_maxabs_final_b(double* part, int nparts, int* bad) {
+__global__ void k_maxabs_final_b(double* part, int nparts, int* bad, const long* flag_index) {
   __shared__ double sh[16];
   double* pb = part + (long)blockIdx.x * kNormSlots;
   double m = 0.0;
@@ -280,7 +280,7 @@ __global__ void k_maxabs_final_b(double* part, int nparts, int* bad) {
   m = block_max(m, sh);
   if (threadIdx.x == 0) {
     pb[1024] = m;
-    if (!(m > 0.0) || !isfinite(m)) *bad = 1;
+    if (!(m > 0.0) || !isfinite(m)) bad[flag_index ? flag_index[blockIdx.x] : 0] = 1;
   }
 }
 
@@ -469,11 +469,12 @@ void swap_last2_batched(hipStream_t st, const double* const* in, double* const* 
   CTM_HIP(hipGetLastError());
 }
 
-void normalize_maxabs_batched(hipStream_t st, double* const* x, int batch, long n, double* scratch, int* bad_flag) {
+void normalize_maxabs_batched(hipStream_t st, double* const* x, int batch, long n, double* scratch, int* bad_flag,
+                              const long* flag_index) {
   if (batch <= 0) return;
   int nb = std::min(1024, grid_for(n));
   hipLaunchKernelGGL(k_maxabs_partial_b, dim3(nb, batch), dim3(TPB), 0, st, x, n, scratch);
-  hipLaunchKernelGGL(k_maxabs_final_b, dim3(batch), dim3(TPB), 0, st, scratch, nb, bad_flag);
+  hipLaunchKernelGGL(k_maxabs_final_b, dim3(batch), dim3(TPB), 0, st, scratch, nb, bad_flag, flag_index);
   hipLaunchKernelGGL(k_scale_by_inv_b, dim3(grid_for(n), batch), dim3(TPB), 0, st, x, n, scratch);
   CTM_HIP(hipGetLastError());
 }

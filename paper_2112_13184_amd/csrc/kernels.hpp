@@ -55,8 +55,11 @@ void scale(hipStream_t st, double* x, long n, double a);
 // exactly the arithmetic of the single form.
 void swap_last2_batched(hipStream_t st, const double* const* in, double* const* out, int batch, long na, long nb,
                         long nc);
-// scratch: 1025 doubles per problem.
-void normalize_maxabs_batched(hipStream_t st, double* const* x, int batch, long n, double* scratch, int* bad_flag);
+// scratch: 1025 doubles per problem.  A problem whose maximum is 0, NaN or
+// Inf sets bad_flag[flag_index[b]] (device array; bad_flag[0] when
+// flag_index is null).
+void normalize_maxabs_batched(hipStream_t st, double* const* x, int batch, long n, double* scratch, int* bad_flag,
+                              const long* flag_index = nullptr);
 // Problem b: Om + b * ostride, key seed[b], stream id sid[b] (host arrays,
 // batch <= 64).
 void omega_fill_batched(hipStream_t st, double* Om, long ostride, int batch, int n, int Db, int k, const uint64_t* seed,

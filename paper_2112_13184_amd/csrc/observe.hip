@@ -1,4 +1,4 @@
-// Expectation values from the converged environment (Sec. 4.5 of arXiv:2112.13184).
+// Expectation values from the converged environment (Sec. 5.3 of arXiv:2112.13184).
 //
 // Each quantity is a ratio of contractions of one finite patch (3x3 for one
 // site, 3x4 / 4x3 for a bond), so the normalisation of C and T drops out.  The

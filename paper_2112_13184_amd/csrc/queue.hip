@@ -2,22 +2,29 @@
 // admitted by HBM footprint and run concurrently on one GPU.
 //
 // Admission: a pending request starts as soon as a worker slot is free and the
-// summed footprints of the running solves plus its own stay within the budget
+// summed footprints of the running groups plus its own stay within the budget
 // (first fit in arrival order, so a large request does not hold back small
 // ones; a request skipped by 8 later admissions blocks further skipping, so
 // it cannot starve).  Pending requests of the same shape (unit cell, D, d,
-// chi, precision, sketch sizes) are admitted together as one group, up to 8,
-// while the group's footprint fits: the group shares one context, and the
-// cuts of all its solves are batched into the same launches (enlarged-corner
-// products, sketch GEMMs, Cholesky QR, Jacobi SVD).  Every group owns its HIP
-// stream (default priority), so different groups overlap on the device while
-// each worker thread waits for its own stream.  A solve runs sweeps until the
-// corner-spectrum change drops below its tolerance, its sweep cap, or a
-// cancellation (checked between sweeps); a finished solve of a group is
-// frozen while the others go on.  Then the energy per site and one-site
-// magnetisations are evaluated and the results published.
+// chi, precision, sketch sizes, projector path) are admitted together as one
+// group, up to 8, while the group's footprint fits: the group shares one
+// context, and the cuts of all its live solves are batched into the same
+// launches (enlarged-corner products, sketch GEMMs, Cholesky QR, Jacobi SVD).
+// Every group owns its HIP stream (default priority), so different groups
+// overlap on the device while each worker thread waits for its own stream.
+//
+// A group is driven sweep by sweep.  A solve stops when the corner-spectrum
+// change drops below its tolerance, at its sweep cap, when cancelled (checked
+// between sweeps) or when its own numbers fail (NaN / Inf or a cut without
+// singular values; the context isolates replicas, so the others go on).  Its
+// observables are evaluated and its result published at once, and its slot
+// is free: at the next sweep boundary the oldest pending request of the same
+// shape is started in that slot (fresh site tensors and environment, its own
+// move count and seed), without new memory.  The group's footprint returns to
+// the budget when its last solve is published.
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -39,7 +46,7 @@ int64_t now_ns() {
 struct Job {
   uint64_t ticket = 0;
   ctm_request req{};
-  std::vector<double> tensors, bond, onsite;
+  std::vector<double> tensors, bond, onsite, obs, obs2;
   size_t footprint = 0;
   int skipped = 0;
   std::atomic<bool> cancel{false};
@@ -71,6 +78,7 @@ struct ctm_queue {
   int max_active = 1, active = 0, device = 0;
   bool stop = false;
   uint64_t next_ticket = 1;
+  hipStream_t stream = nullptr;   // caller's stream for device-side request tensors
   std::vector<std::thread> workers;
 };
 
@@ -103,8 +111,33 @@ std::vector<size_t> pick(ctm_queue* q, size_t* footprint) {
   return g;
 }
 
-void run_group(ctm_queue* q, std::vector<std::shared_ptr<Job>>& jobs) {
-  (void)q;
+// Energy and observables of replica r (one finished solve).
+void measure(ctm::Context& c, int r, const Job& j, ctm_result& res) {
+  const int N = c.N, d = c.d;
+  double e = 0.0;
+  for (int s = 0; s < N; ++s) {
+    for (int dir = 0; dir < 2; ++dir) e += ctm::expect_2site(c, s, dir, j.bond.data(), r);
+    if (!j.onsite.empty()) e += ctm::expect_1site(c, s, j.onsite.data(), r);
+  }
+  res.energy_per_site = e / N;
+  for (int k = 0; k < j.req.n_obs; ++k)
+    for (int s = 0; s < N; ++s) res.obs[k][s] = ctm::expect_1site(c, s, j.obs.data() + (size_t)k * d * d, r);
+  for (int k = 0; k < j.req.n_obs2; ++k)
+    for (int s = 0; s < N; ++s)
+      for (int dir = 0; dir < 2; ++dir)
+        res.obs2[k][s][dir] = ctm::expect_2site(c, s, dir, j.obs2.data() + (size_t)k * d * d * d * d, r);
+}
+
+void publish(ctm_queue* q, const std::shared_ptr<Job>& j) {
+  std::lock_guard<std::mutex> lk(q->mu);
+  j->res.t_done_ns = now_ns();
+  j->state = Job::DONE;
+  q->cv_done.notify_all();
+}
+
+// Runs a group to its end: the admitted jobs in slots 0..R-1, later
+// same-shape requests in the slots that free up.
+void run_group(ctm_queue* q, std::vector<std::shared_ptr<Job>> jobs) {
   const int R = (int)jobs.size();
   ctm_config cfg = jobs[0]->req.cfg;
   cfg.stream = nullptr;   // the context creates its own stream
@@ -117,51 +150,107 @@ void run_group(ctm_queue* q, std::vector<std::shared_ptr<Job>>& jobs) {
   ctm_status st = CTM_OK;
   ctm_ctx* ctx = ctm::create_group(cfg, tensors.data(), R, seeds.data(), &st);
   if (!ctx) {
-    for (auto& j : jobs) j->res.status = st;
+    for (auto& j : jobs) {
+      j->res.status = st;
+      publish(q, j);
+    }
     return;
   }
-  const int N = cfg.Lx * cfg.Ly;
-  const int d = (cfg.layers == 2) ? cfg.d : 1;
-  std::vector<int> maxs(R), done(R, 0), conv(R, 0);
-  std::vector<double> tol(R), delta(R, INFINITY);
-  std::vector<const std::atomic<bool>*> cancel(R);
-  for (int r = 0; r < R; ++r) {
-    maxs[r] = jobs[r]->req.max_sweeps;
-    tol[r] = jobs[r]->req.tol;
-    cancel[r] = &jobs[r]->cancel;
-  }
   ctm::Context& c = ctm::context_of(ctx);
-  std::vector<ctm_status> sts(R, CTM_OK);
-  try {
-    ctm::do_sweeps_group(c, maxs.data(), tol.data(), done.data(), delta.data(), conv.data(), cancel.data());
+  c.isolate = true;
+  std::vector<std::shared_ptr<Job>> slot = jobs;   // null: free slot
+  std::vector<int> done(R, 0);
+  std::vector<double> delta(R, INFINITY);
+  auto finish = [&](int r, ctm_status status, bool converged) {
+    Job& j = *slot[r];
+    j.res.status = status;
+    j.res.sweeps = done[r];
+    j.res.delta = delta[r];
+    j.res.converged = converged ? 1 : 0;
+    c.frozen[r] = 1;
+    if (status == CTM_OK) {
+      try {
+        measure(c, r, j, j.res);
+      } catch (const ctm::Error& e) {
+        j.res.status = (ctm_status)e.status;
+      } catch (...) {
+        j.res.status = CTM_EDEVICE;
+      }
+    }
+    std::shared_ptr<Job> held = slot[r];
+    publish(q, held);
+    slot[r] = nullptr;
+    // a solve that failed on its own leaves NaN / Inf or zeros in its slot:
+    // restart the slot from its (finite) tensors so that the launches over
+    // every corner of the context (the stop rule's spectra) only see finite
+    // data.  (After a device error the whole group ends instead.)
+    if (c.failed[r]) {
+      try {
+        ctm::replica_reset(c, r, held->tensors.data(), held->req.cfg.seed);
+        c.frozen[r] = 1;
+      } catch (...) {
+      }
+    }
+  };
+  // a free slot takes the oldest pending request of this shape
+  auto refill = [&]() {
     for (int r = 0; r < R; ++r) {
-      ctm_result& res = jobs[r]->res;
-      if (jobs[r]->cancel.load()) {
-        sts[r] = CTM_ECANCELED;
-        continue;
+      if (slot[r]) continue;
+      std::shared_ptr<Job> j;
+      {
+        std::lock_guard<std::mutex> lk(q->mu);
+        for (auto it = q->pending.begin(); it != q->pending.end(); ++it)
+          if (same_shape((*it)->req.cfg, cfg)) {
+            j = *it;
+            q->pending.erase(it);
+            j->state = Job::ACTIVE;
+            j->res.t_admit_ns = now_ns();
+            break;
+          }
       }
-      double e = 0.0;
-      for (int s = 0; s < N; ++s) {
-        for (int dir = 0; dir < 2; ++dir) e += ctm::expect_2site(c, s, dir, jobs[r]->bond.data(), r);
-        if (!jobs[r]->onsite.empty()) e += ctm::expect_1site(c, s, jobs[r]->onsite.data(), r);
+      if (!j) return;
+      slot[r] = j;
+      done[r] = 0;
+      delta[r] = INFINITY;
+      ctm::replica_reset(c, r, j->tensors.data(), j->req.cfg.seed);
+    }
+  };
+  try {
+    ctm::group_start(c);
+    std::vector<double> h(R);
+    for (;;) {
+      for (int r = 0; r < R; ++r) {
+        if (!slot[r]) continue;
+        if (slot[r]->cancel.load()) finish(r, CTM_ECANCELED, false);
+        else if (done[r] >= slot[r]->req.max_sweeps) finish(r, CTM_OK, false);
       }
-      res.energy_per_site = e / N;
-      if (d == 2 && cfg.layers == 2) {
-        const double sz[4] = {1.0, 0.0, 0.0, -1.0};
-        for (int s = 0; s < std::min(N, 4); ++s) res.mz[s] = ctm::expect_1site(c, s, sz, r);
+      refill();
+      for (int r = 0; r < R; ++r)   // a new solve with max_sweeps = 0 ends at once
+        if (slot[r] && done[r] >= slot[r]->req.max_sweeps) finish(r, CTM_OK, false);
+      bool live = false;
+      for (int r = 0; r < R; ++r) {
+        c.frozen[r] = slot[r] ? 0 : 1;
+        live |= slot[r] != nullptr;
+      }
+      if (!live) break;
+      ctm::group_sweep(c, h.data());
+      for (int r = 0; r < R; ++r) {
+        if (!slot[r]) continue;
+        if (c.failed[r]) {
+          finish(r, CTM_ENUMERIC, false);
+          continue;
+        }
+        done[r] += 1;
+        delta[r] = h[r];
+        if (delta[r] < slot[r]->req.tol) finish(r, CTM_OK, true);
       }
     }
   } catch (const ctm::Error& e) {
-    for (auto& x : sts) x = (ctm_status)e.status;
+    for (int r = 0; r < R; ++r)
+      if (slot[r]) finish(r, (ctm_status)e.status, false);
   } catch (const std::exception&) {
-    for (auto& x : sts) x = CTM_EDEVICE;
-  }
-  for (int r = 0; r < R; ++r) {
-    ctm_result& res = jobs[r]->res;
-    res.status = sts[r];
-    res.sweeps = done[r];
-    res.converged = conv[r];
-    res.delta = delta[r];
+    for (int r = 0; r < R; ++r)
+      if (slot[r]) finish(r, CTM_EDEVICE, false);
   }
   ctm_free(ctx);
 }
@@ -185,16 +274,10 @@ void worker(ctm_queue* q) {
       j->res.t_admit_ns = t;
     }
     lk.unlock();
-    run_group(q, jobs);
+    run_group(q, std::move(jobs));
     lk.lock();
     q->used -= fp;
     q->active -= 1;
-    const int64_t td = now_ns();
-    for (auto& j : jobs) {
-      j->res.t_done_ns = td;
-      j->state = Job::DONE;
-    }
-    q->cv_done.notify_all();
     q->cv_work.notify_all();
   }
 }
@@ -215,13 +298,14 @@ bool fill(ctm_queue* q, uint64_t ticket, ctm_result* res, ctm_status* st) {
 
 extern "C" {
 
-ctm_status ctm_queue_create(size_t hbm_budget_bytes, int max_active, ctm_queue** out) {
+ctm_status ctm_queue_create(size_t hbm_budget_bytes, int max_active, void* stream, ctm_queue** out) {
   if (!out || hbm_budget_bytes == 0 || max_active < 1 || max_active > 64) return CTM_EINVAL;
   *out = nullptr;
   ctm_queue* q = new (std::nothrow) ctm_queue();
   if (!q) return CTM_ENOMEM;
   q->budget = hbm_budget_bytes;
   q->max_active = max_active;
+  q->stream = (hipStream_t)stream;
   if (hipGetDevice(&q->device) != hipSuccess) {
     delete q;
     return CTM_EDEVICE;
@@ -244,6 +328,9 @@ ctm_status ctm_queue_create(size_t hbm_budget_bytes, int max_active, ctm_queue**
 
 ctm_status ctm_queue_submit(ctm_queue* q, const ctm_request* req, uint64_t* ticket) {
   if (!q || !req || !ticket || !req->tensors || !req->bond_op || req->max_sweeps < 0) return CTM_EINVAL;
+  if (req->n_obs < 0 || req->n_obs > CTM_MAX_OBS || req->n_obs2 < 0 || req->n_obs2 > CTM_MAX_OBS ||
+      (req->n_obs > 0 && !req->obs_ops) || (req->n_obs2 > 0 && !req->obs2_ops))
+    return CTM_EINVAL;
   const size_t fp = ctm_footprint_bytes(&req->cfg);
   if (fp == 0) return CTM_EINVAL;
   if (fp > q->budget) return CTM_ETOOBIG;
@@ -251,9 +338,24 @@ ctm_status ctm_queue_submit(ctm_queue* q, const ctm_request* req, uint64_t* tick
   const ctm_config& c = req->cfg;
   const int d = (c.layers == 2) ? c.d : 1;
   j->req = *req;
-  j->tensors.assign(req->tensors, req->tensors + site_elems(c));
+  j->tensors.resize(site_elems(c));
+  if (req->tensors_on_device) {
+    if (hipMemcpyAsync(j->tensors.data(), req->tensors, sizeof(double) * j->tensors.size(), hipMemcpyDeviceToHost,
+                       q->stream) != hipSuccess ||
+        hipStreamSynchronize(q->stream) != hipSuccess)
+      return CTM_EDEVICE;
+  } else {
+    std::memcpy(j->tensors.data(), req->tensors, sizeof(double) * j->tensors.size());
+  }
+  for (double v : j->tensors)
+    if (!std::isfinite(v)) return CTM_ENUMERIC;
   j->bond.assign(req->bond_op, req->bond_op + (size_t)d * d * d * d);
   if (req->onsite_op) j->onsite.assign(req->onsite_op, req->onsite_op + (size_t)d * d);
+  if (req->n_obs > 0) j->obs.assign(req->obs_ops, req->obs_ops + (size_t)req->n_obs * d * d);
+  if (req->n_obs2 > 0) j->obs2.assign(req->obs2_ops, req->obs2_ops + (size_t)req->n_obs2 * d * d * d * d);
+  // the request no longer refers to caller memory
+  j->req.tensors = nullptr;
+  j->req.bond_op = j->req.onsite_op = j->req.obs_ops = j->req.obs2_ops = nullptr;
   j->footprint = fp;
   j->res.tag = req->tag;
   j->res.t_submit_ns = now_ns();

@@ -210,14 +210,28 @@ double* Arena::alloc(size_t elems) {
 size_t context_footprint(const ctm_config& cfg) { return sizes_of(cfg).total_bytes; }
 size_t context_footprint_group(const ctm_config& cfg, int replicas) { return sizes_of(cfg, replicas).total_bytes; }
 
+// Reads the per-replica NaN / Inf / zero flags of the kernels since the last
+// check.  A flagged replica is recorded in c.failed; without isolation the
+// call throws CTM_ENUMERIC instead.
 void check_bad(Context& c, const char* where) {
-  int bad = 0;
-  CTM_HIP(hipMemcpyAsync(&bad, c.badflag.p, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  std::vector<int> bad(c.R, 0);
+  CTM_HIP(hipMemcpyAsync(bad.data(), c.badflag.p, sizeof(int) * c.R, hipMemcpyDeviceToHost, c.st));
   CTM_HIP(hipStreamSynchronize(c.st));
-  if (bad) {
-    CTM_HIP(hipMemsetAsync(c.badflag.p, 0, sizeof(int), c.st));
-    throw Error(-4, std::string(where) + ": NaN/Inf or zero environment / cut");
+  bool any = false;
+  for (int r = 0; r < c.R; ++r) {
+    if (bad[r]) c.failed[r] = 1;
+    any |= bad[r] != 0;
   }
+  if (any) {
+    CTM_HIP(hipMemsetAsync(c.badflag.p, 0, sizeof(int) * c.R, c.st));
+    CTM_HIP(hipStreamSynchronize(c.st));
+  }
+  if (!c.isolate)
+    for (int r = 0; r < c.R; ++r)
+      if (c.failed[r]) {
+        c.failed[r] = 0;
+        throw Error(-4, std::string(where) + ": NaN/Inf or zero environment / cut");
+      }
 }
 
 void context_init(Context& c, const ctm_config& cfg, const double* tensors, int on_device,
@@ -229,6 +243,8 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.seeds.assign(replicas, cfg.seed);
   if (seeds) c.seeds.assign(seeds, seeds + replicas);
   c.frozen.assign(replicas, 0);
+  c.failed.assign(replicas, 0);
+  c.rmoves.assign(replicas, 0);
   c.layers = cfg.layers;
   c.D = cfg.D;
   c.d = (cfg.layers == 2) ? cfg.d : 1;
@@ -254,8 +270,9 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.szk = (long)c.DK * c.DK * c.DK * c.DK * c.d;
   c.szb = (long)c.DB * c.DB * c.DB * c.DB * c.d;
   std::vector<double> host((size_t)NS * c.szk);
-  if (on_device) {
-    CTM_HIP(hipMemcpy(host.data(), tensors, host.size() * sizeof(double), hipMemcpyDeviceToHost));
+  if (on_device) {   // read on the context's stream: after the caller's prior work on it
+    CTM_HIP(hipMemcpyAsync(host.data(), tensors, host.size() * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    CTM_HIP(hipStreamSynchronize(c.st));
   } else {
     std::memcpy(host.data(), tensors, host.size() * sizeof(double));
   }
@@ -322,8 +339,8 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.wvec.alloc(sizeof(double) * c.chi * Lmax0);
   if (c.kk <= kSmallLAMaxK && c.cfg.rsvd_oversample >= 0) smallla_alloc(c.sla, c.kk, Lmax0, c.n);
   c.keff.alloc(sizeof(int) * 64);
-  c.badflag.alloc(sizeof(int));
-  CTM_HIP(hipMemset(c.badflag.p, 0, sizeof(int)));
+  c.badflag.alloc(sizeof(int) * c.R);   // one NaN / Inf flag per replica
+  CTM_HIP(hipMemset(c.badflag.p, 0, sizeof(int) * c.R));
   c.redscratch.alloc(sizeof(double) * std::max(2048, 1025 * Lmax0));
   c.delta.alloc(sizeof(double) * c.R);
   int Lmax = Lmax0;
@@ -592,7 +609,7 @@ void cut_projectors(Context& c, int rot, int r, int x, int y, int slot) {
     // V (col-major) = VT^T
     transpose_square(c.st, VT, P[2], n);
     double* V = P[2];
-    projector_weights(c.st, S, U, n, n, chi, kcap, c.cutoff, w, c.keff.as<int>(), c.badflag.as<int>());
+    projector_weights(c.st, S, U, n, n, chi, kcap, c.cutoff, w, c.keff.as<int>(), c.badflag.as<int>() + r);
     scale_columns(c.st, V, n, chi, w);
     scale_columns(c.st, U, n, chi, w);
     // Pt = H_d^T V' ; PT = H_u^T U'
@@ -603,7 +620,7 @@ void cut_projectors(Context& c, int rot, int r, int x, int y, int slot) {
 
   const int kk = c.kk;
   double *Y = P[0], *Z = P[1], *W = P[2], *t1 = P[3], *t2 = P[4], *V = P[5], *U = P[6];
-  const uint64_t sid = stream_id(c.moves, x, mod(y, (rot % 2 == 0) ? c.Ly : c.Lx));
+  const uint64_t sid = stream_id(c.rmoves[r], x, mod(y, (rot % 2 == 0) ? c.Ly : c.Lx));
   omega_fill(c.st, Z, n, c.Db, kk, c.seeds[r], sid);
   apply_M(c, G, Z, Y, kk, t1, t2);
   timed(c, PhaseTimer::LINALG, 0.0, [&] { la_orth(c.la, Y, n, kk); });
@@ -623,7 +640,9 @@ void cut_projectors(Context& c, int rot, int r, int x, int y, int slot) {
   mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Z, n), colmajor(Us, kk), out_colmajor(V, n));
   // U = Q Ub, Ub(i, j) = VTs(j, i)
   mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Y, n), rowmajor(VTs, kk), out_colmajor(U, n));
-  timed(c, PhaseTimer::LINALG, 0.0, [&] { projector_weights(c.st, S, U, n, kk, chi, kcap, c.cutoff, w, c.keff.as<int>(), c.badflag.as<int>()); });
+  timed(c, PhaseTimer::LINALG, 0.0, [&] {
+    projector_weights(c.st, S, U, n, kk, chi, kcap, c.cutoff, w, c.keff.as<int>(), c.badflag.as<int>() + r);
+  });
   scale_columns(c.st, V, n, chi, w);
   // Pt = G_ll (G_lr V')
   mm(c, PhaseTimer::EDGE, n, chi, n, rowmajor(G[2], n), colmajor(V, n), out_colmajor(t1, n));
@@ -663,7 +682,7 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
       jobs.push_back({s, j, Gp(q, slot)});   // roles: 0 UL, 1 UR, 2 LR, 3 LL
     }
     seeds[b] = c.seeds[r];
-    sids[b] = stream_id(c.moves, x, y);
+    sids[b] = stream_id(c.rmoves[r], x, y);
   }
   enlarged_corners(c, jobs);
   timed(c, PhaseTimer::OTHER, 0.0, [&] {
@@ -749,8 +768,12 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
   failed.clear();
   bool any = false, numeric = false;
   for (int b = 0; b < nb; ++b) {
-    if (flags[b]) failed.push_back(b);
-    else if (flags[128 + b]) numeric = true;   // no singular value above zero
+    if (flags[b]) {
+      failed.push_back(b);
+    } else if (flags[128 + b]) {   // no singular value above zero
+      numeric = true;
+      c.failed[cuts[b][0]] = 1;
+    }
     any |= flags[b] || flags[128 + b];
   }
   if (any) {
@@ -765,7 +788,10 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
     for (int b = 0; b < nb; ++b) fprintf(stderr, " %d", flags[b]);
     fprintf(stderr, "\n");
   }
-  if (numeric) throw Error(-4, "projectors: a cut has no singular value above zero");
+  if (numeric && !c.isolate) {
+    for (int b = 0; b < nb; ++b) c.failed[cuts[b][0]] = 0;
+    throw Error(-4, "projectors: a cut has no singular value above zero");
+  }
 }
 
 // Projectors of every cut of column x of every live replica (identity,
@@ -835,7 +861,7 @@ void cut_projectors_fast(Context& c, int rot, int x, int y) {
 
 // Pointers of one cut's column update (see do_move).
 struct UpdPtrs {
-  int s = 0;
+  int s = 0, r = 0;   // old site, replica
   double *Pt_up = nullptr, *Pt_dn = nullptr, *PT_dn = nullptr, *PT_up = nullptr, *P3_up = nullptr;
   double *C1n = nullptr, *C4n = nullptr, *T4n = nullptr;
 };
@@ -904,6 +930,7 @@ static void update_column_batched(Context& c, int rot, bool direct, size_t count
     const size_t oG0 = each([&](int i) { t.add_off(G0 + i * nn, G0); });
     const size_t oPtdn = each([&](int i) { t.add_off(q[i].Pt_dn, Pt); });
     const size_t oT4n = each([&](int i) { t.add_off(q[i].T4n, T4base); });
+    const size_t oRep = each([&](int i) { t.w.push_back((uint64_t)q[i].r); });   // failure flag of each cut
     const uint64_t* d = upload(c, t);
     swap_last2_batched(c.st, ptrs_at<const double>(d, pPTup), ptrs_at<double>(d, pP3up), m, chi, Db, chi);
     // C1' = (C1 T1) Pt_up
@@ -927,9 +954,10 @@ static void update_column_batched(Context& c, int rot, bool direct, size_t count
     });
     mm(c, PhaseTimer::EDGE, chi, (int)n, (int)n, off_colmajor(Pt, d, oPtdn, chi), rowmajor(G0, n, nn),
        off_out_rowmajor(T4base, d, oT4n, n), m);
-    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pC1n), m, cc, c.redscratch.as<double>(), c.badflag.as<int>());
-    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pC4n), m, cc, c.redscratch.as<double>(), c.badflag.as<int>());
-    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pT4n), m, tt, c.redscratch.as<double>(), c.badflag.as<int>());
+    int* bad = c.badflag.as<int>();
+    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pC1n), m, cc, c.redscratch.as<double>(), bad, offs_at(d, oRep));
+    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pC4n), m, cc, c.redscratch.as<double>(), bad, offs_at(d, oRep));
+    normalize_maxabs_batched(c.st, ptrs_at<double>(d, pT4n), m, tt, c.redscratch.as<double>(), bad, offs_at(d, oRep));
   }
 }
 
@@ -964,6 +992,7 @@ void do_move(Context& c, int rot) {
       update_column_batched(c, rot, direct, ups.size(), [&](size_t i, UpdPtrs& q) {
         const Upd& u = ups[i];
         q.s = u.s;
+        q.r = u.ry / Lyv;
         q.Pt_up = c.Pt.as<double>() + (long)u.up * n * chi;
         q.Pt_dn = c.Pt.as<double>() + (long)u.sl * n * chi;
         q.PT_dn = c.PT.as<double>() + (long)u.sl * n * chi;
@@ -997,9 +1026,10 @@ void do_move(Context& c, int rot) {
         mm(c, PhaseTimer::EDGE, n, n, chi, rowmajor(c.Tb(s, kt4), chi), rowmajor(P3_up, n), out_rowmajor(c.X2.p, n));
         absorb(c, c.X2.as<double>(), c.Ak(rot, s), c.Ab(rot, s), c.G[0].as<double>(), true);
         mm(c, PhaseTimer::EDGE, chi, n, n, colmajor(Pt_dn, chi), rowmajor(c.G[0].p, n), out_rowmajor(T4n, n));
-        normalize_maxabs(c.st, C1n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
-        normalize_maxabs(c.st, C4n, cc, c.redscratch.as<double>(), c.badflag.as<int>());
-        normalize_maxabs(c.st, T4n, tt, c.redscratch.as<double>(), c.badflag.as<int>());
+        int* bad = c.badflag.as<int>() + u.ry / Lyv;
+        normalize_maxabs(c.st, C1n, cc, c.redscratch.as<double>(), bad);
+        normalize_maxabs(c.st, C4n, cc, c.redscratch.as<double>(), bad);
+        normalize_maxabs(c.st, T4n, tt, c.redscratch.as<double>(), bad);
       }
       newdC1[u.ry] = {c.tdim[s][kt1][1], c.nact_cut[up]};
       newdT4[u.ry] = {c.nact_cut[sl], c.nact_cut[up]};
@@ -1038,6 +1068,8 @@ void do_move(Context& c, int rot) {
                          chi, chi, Db);
     }
   }
+  for (int r = 0; r < c.R; ++r)
+    if (!c.frozen[r]) c.rmoves[r] += 1;
   c.moves += 1;
   check_bad(c, "ctm_move");
 }
@@ -1067,14 +1099,83 @@ static void replica_deltas(Context& c, double* spec, double* prev) {
     spectra_delta(c.st, spec + r * per, prev + r * per, 4 * c.N, c.chi, c.delta.as<double>() + r);
 }
 
-void do_sweeps_group(Context& c, const int* max_sweeps, const double* tol, int* done, double* delta,
-                     int* converged, const std::atomic<bool>* const* cancel) {
-  const int R = c.R;
+void group_start(Context& c) {
   corner_spectra(c, c.specprev.as<double>());
   // normalise the reference spectra (deltas of this step are discarded)
   replica_deltas(c, c.specprev.as<double>(), c.spec.as<double>());
   CTM_HIP(hipMemcpyAsync(c.specprev.p, c.spec.p, sizeof(double) * 4 * c.NS() * c.chi, hipMemcpyDeviceToDevice,
                          c.st));
+}
+
+void group_sweep(Context& c, double* host_delta) {
+  for (int m = 0; m < 4; ++m) {
+    do_move(c, kSweepRot[m]);
+    // a replica that failed in this move takes no further moves
+    for (int r = 0; r < c.R; ++r)
+      if (c.failed[r]) c.frozen[r] = 1;
+  }
+  corner_spectra(c, c.spec.as<double>());
+  replica_deltas(c, c.spec.as<double>(), c.specprev.as<double>());
+  CTM_HIP(hipMemcpyAsync(host_delta, c.delta.p, sizeof(double) * c.R, hipMemcpyDeviceToHost, c.st));
+  CTM_HIP(hipStreamSynchronize(c.st));
+}
+
+void replica_reset(Context& c, int r, const double* tensors, uint64_t seed) {
+  CTM_CHECK(r >= 0 && r < c.R, -1, "replica_reset: no such slot");
+  const int N = c.N, NS = c.NS(), s0 = r * N;
+  const long cc = (long)c.chi * c.chi, tt = cc * c.Db;
+  for (long i = 0; i < (long)N * c.szk; ++i) CTM_CHECK(std::isfinite(tensors[i]), -4, "site tensor has NaN/Inf entries");
+  // site tensors, four rotations each (host staging lives until the sync below)
+  std::vector<double> ket((size_t)4 * N * c.szk), bra((size_t)4 * N * c.szb, 0.0);
+  for (int i = 0; i < N; ++i) {
+    std::vector<double> t(tensors + (long)i * c.szk, tensors + (long)(i + 1) * c.szk), rt;
+    for (int rot = 0; rot < 4; ++rot) {
+      std::copy(t.begin(), t.end(), ket.begin() + ((long)rot * N + i) * c.szk);
+      if (c.layers == 2)
+        std::copy(t.begin(), t.end(), bra.begin() + ((long)rot * N + i) * c.szb);
+      else
+        bra[(long)rot * N + i] = 1.0;
+      rotate_host(t, rt, c.DK, c.d);
+      t.swap(rt);
+    }
+  }
+  for (int rot = 0; rot < 4; ++rot) {
+    CTM_HIP(hipMemcpyAsync(c.Aket.as<double>() + ((long)rot * NS + s0) * c.szk, ket.data() + (long)rot * N * c.szk,
+                           sizeof(double) * N * c.szk, hipMemcpyHostToDevice, c.st));
+    CTM_HIP(hipMemcpyAsync(c.Abra.as<double>() + ((long)rot * NS + s0) * c.szb, bra.data() + (long)rot * N * c.szb,
+                           sizeof(double) * N * c.szb, hipMemcpyHostToDevice, c.st));
+  }
+  // trivial environment: C = [[1]], T[0][0][:] = the ket/bra identity (or ones)
+  std::vector<double> hc((size_t)4 * N * cc, 0.0), ht((size_t)4 * N * tt, 0.0);
+  for (int k = 0; k < 4 * N; ++k) {
+    hc[k * cc] = 1.0;
+    for (int b = 0; b < c.Db; ++b)
+      ht[k * tt + b] = (c.layers == 2) ? ((b / c.D == b % c.D) ? 1.0 : 0.0) : 1.0;
+  }
+  CTM_HIP(hipMemcpyAsync(c.C(s0, 0), hc.data(), sizeof(double) * hc.size(), hipMemcpyHostToDevice, c.st));
+  CTM_HIP(hipMemcpyAsync(c.Ta(s0, 0), ht.data(), sizeof(double) * ht.size(), hipMemcpyHostToDevice, c.st));
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < 4; ++k) swap_last2(c.st, c.Ta(s0 + i, k), c.Tb(s0 + i, k), c.chi, c.chi, c.Db);
+  for (int i = 0; i < N; ++i) {
+    c.cdim[s0 + i] = {{{1, 1}, {1, 1}, {1, 1}, {1, 1}}};
+    c.tdim[s0 + i] = {{{1, 1}, {1, 1}, {1, 1}, {1, 1}}};
+  }
+  // reference spectra: every corner [[1]] has the normalised spectrum (1, 0, ..)
+  std::vector<double> sp((size_t)4 * N * c.chi, 0.0);
+  for (int k = 0; k < 4 * N; ++k) sp[(long)k * c.chi] = 1.0;
+  CTM_HIP(hipMemcpyAsync(c.specprev.as<double>() + (long)s0 * 4 * c.chi, sp.data(), sizeof(double) * sp.size(),
+                         hipMemcpyHostToDevice, c.st));
+  CTM_HIP(hipStreamSynchronize(c.st));
+  c.rmoves[r] = 0;
+  c.seeds[r] = seed;
+  c.frozen[r] = 0;
+  c.failed[r] = 0;
+}
+
+void do_sweeps_group(Context& c, const int* max_sweeps, const double* tol, int* done, double* delta,
+                     int* converged, const std::atomic<bool>* const* cancel) {
+  const int R = c.R;
+  group_start(c);
   std::vector<double> dl(R, INFINITY);
   for (int r = 0; r < R; ++r) {
     done[r] = 0;
@@ -1088,18 +1189,16 @@ void do_sweeps_group(Context& c, const int* max_sweeps, const double* tol, int* 
       live |= !c.frozen[r];
     }
     if (!live) break;
-    for (int m = 0; m < 4; ++m) do_move(c, kSweepRot[m]);
-    corner_spectra(c, c.spec.as<double>());
-    replica_deltas(c, c.spec.as<double>(), c.specprev.as<double>());
+    std::vector<char> was_live(R);
+    for (int r = 0; r < R; ++r) was_live[r] = !c.frozen[r];
     std::vector<double> h(R);
-    CTM_HIP(hipMemcpyAsync(h.data(), c.delta.p, sizeof(double) * R, hipMemcpyDeviceToHost, c.st));
-    CTM_HIP(hipStreamSynchronize(c.st));
+    group_sweep(c, h.data());
     for (int r = 0; r < R; ++r) {
-      if (c.frozen[r]) continue;
+      if (!was_live[r]) continue;
       done[r] += 1;
       dl[r] = h[r];
       if (dl[r] < tol[r]) converged[r] = 1;
-      if (converged[r] || done[r] >= max_sweeps[r]) c.frozen[r] = 1;
+      if (converged[r] || done[r] >= max_sweeps[r] || c.failed[r]) c.frozen[r] = 1;
     }
   }
   for (int r = 0; r < R; ++r) {

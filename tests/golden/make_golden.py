@@ -52,7 +52,7 @@ WORKLOADS = {
     "itps_d4_chi64": dict(D=4, chi=64, seed=1, p=32, q=2, sketch_seed=11, record=(1, 2, 5, 10, 20, 30),
                           perturb=(0, 1, 2, 3)),
     "itps_d6_chi144": dict(D=6, chi=144, seed=2, p=48, q=1, sketch_seed=12, record=(1, 2, 5, 10, 20, 30),
-                           perturb=(0, 1)),
+                           perturb=(0,)),
     "restart_d4_chi64": dict(D=4, chi=64, seed=1, p=32, q=2, sketch_seed=11, record=(1, 2, 3), env_seed=21,
                              perturb=(0, 1, 2)),
     "restart_d6_chi144": dict(D=6, chi=144, seed=2, p=48, q=1, sketch_seed=12, record=(1, 2), env_seed=21,

@@ -73,7 +73,7 @@ def test_yang_limits():
 
 
 # --------------------------------------------------------------------------
-# Values printed in the paper (worked example of Sec. 3.2)
+# Values printed in the paper (worked example of Sec. 5.2)
 # --------------------------------------------------------------------------
 def _read_golden(name):
     sections, cur = {}, None
@@ -367,3 +367,120 @@ def test_rho_hermitian_positive():
             rho = rho / np.trace(rho)
             assert np.allclose(rho, rho.T, atol=1e-8)
             assert np.linalg.eigvalsh(0.5 * (rho + rho.T)).min() > -1e-6
+
+
+# --------------------------------------------------------------------------
+# Correlation functions and the transfer-matrix spectrum (Sec. 5.3, Eq. (8),
+# Eq. (9))
+# --------------------------------------------------------------------------
+def _op_layer(A, op):
+    """Double-layer tensor with a one-site operator between ket and bra:
+    sum_{p,p'} A[.., p] conj(A[.., p']) op[p', p]."""
+    a = bf.double_layer(A, open_phys=True)
+    return np.tensordot(a, op, axes=([4, 5], [1, 0]))
+
+
+@pytest.mark.parametrize("Lx,Ly,direction", [(1, 1, 0), (1, 1, 1), (2, 1, 0), (1, 2, 1)])
+def test_transfer_spectrum_untruncated_matches_strip(Lx, Ly, direction):
+    """An untruncated environment is an exact finite network, so its transfer
+    matrix over one period is the column transfer matrix of a strip of
+    U + 1 + Dn sites closed by the boundary vectors: the leading eigenvalues
+    (ratios to the largest) agree to rounding."""
+    A = wl.random_itps(Lx, Ly, 2, 2, seed=3)
+    env = Environment(A, Lx, Ly, chi=256, layers=2, mode="dense", seed=1)
+    env.sweep()
+    ext = _extents_after(Lx, Ly, "LRUD")
+    bdy = np.eye(2).reshape(-1)
+    lam = ob.transfer_spectrum(env, 0, direction, 6)
+    if direction == 0:
+        L, R, U, Dn = ext[(0, 0)]
+        M = np.eye(4 ** (U + 1 + Dn))
+        for x in range(Lx):
+            M = M @ bf.strip_transfer(A[x], 2, bdy, U + 1 + Dn)
+    else:
+        # the +y transfer is the +x transfer of the lattice rotated three
+        # quarter turns: sites rotated, the column runs over x
+        L, R, U, Dn = ext[(0, 0)]
+        M = np.eye(4 ** (L + 1 + R))
+        for y in range(Ly):
+            M = M @ bf.strip_transfer(rotate_site(A[Lx * y], 3), 2, bdy, L + 1 + R)
+    ref = np.linalg.eigvals(M)
+    ref = ref[np.argsort(-np.abs(ref), kind="stable")][:6]
+    assert np.allclose(np.sort_complex(lam / lam[0]), np.sort_complex(ref / ref[0]), atol=1e-10)
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_correlation_untruncated_matches_bruteforce(direction):
+    """C(r) = <A(0) B(r e)> of an untruncated 1x1 environment against the
+    brute-force contraction of the finite network with the operators
+    inserted, r = 0..2 (r = 0: the one-site value of the product A B)."""
+    A = wl.random_itps(1, 1, 2, 2, seed=4)[0]
+    env = Environment([A], 1, 1, chi=256, layers=2, mode="dense", seed=1)
+    env.sweep()
+    L, R, U, Dn = _extents_after(1, 1, "LRUD")[(0, 0)]
+    opA = np.array([[0.3, -1.2], [0.7, 2.0]])
+    opB = np.array([[1.1, 0.4], [-0.6, -0.5]])
+    bdy = np.eye(2).reshape(-1)
+    C = ob.correlation(env, 0, opA, opB, 2, direction)
+    for r in range(3):
+        if r == 0:
+            rep = {(0, 0): _op_layer(A, opA @ opB)}
+        else:
+            rep = {(0, 0): _op_layer(A, opA), ((r, 0) if direction == 0 else (0, r)): _op_layer(A, opB)}
+        x1 = R + (r if direction == 0 else 0)
+        y1 = U + (r if direction == 1 else 0)
+        num = bf.patch_value([A], 1, 1, 2, bdy, -L, x1, -Dn, y1, replace=rep)
+        den = bf.patch_value([A], 1, 1, 2, bdy, -L, x1, -Dn, y1)
+        assert abs(C[r] - num / den) < 1e-12 * max(1.0, abs(num / den)), r
+
+
+def test_correlation_product_state():
+    """Product states: C(r) = <A><B> for r >= 1, <A B> at r = 0, and the
+    transfer matrix has one non-zero eigenvalue (infinite e_1)."""
+    rng = np.random.default_rng(2)
+    phis = [rng.standard_normal(2) for _ in range(4)]
+    env = Environment(wl.product_itps(phis, D=2), 2, 2, chi=8, layers=2, mode="rsvd", oversample=8, seed=1)
+    env.run(3, 1e-14)
+    opA, opB = wl.SX, np.array([[0.3, -1.2], [0.7, 2.0]])
+    ev = lambda phi, op: phi @ op @ phi / (phi @ phi)
+    for i in range(4):
+        for direction in (0, 1):
+            C = ob.correlation(env, i, opA, opB, 5, direction)
+            x, y = i % 2, i // 2
+            assert abs(C[0] - ev(phis[i], opA @ opB)) < 1e-13
+            for r in range(1, 6):
+                j = ((x + r) % 2 + 2 * y) if direction == 0 else (x + 2 * ((y + r) % 2))
+                assert abs(C[r] - ev(phis[i], opA) * ev(phis[j], opB)) < 1e-13
+    lam = ob.transfer_spectrum(env, 0, 0, 3)
+    xi, e = ob.correlation_length(lam, 2)
+    assert abs(lam[1]) < 1e-12 * abs(lam[0]) and xi < 0.1
+
+
+def test_ising_peps_correlation_closed_forms():
+    """The Ising PEPS (beta = 0.5): <sz(0) sz(r)> at r = 1 is Onsager's
+    nearest-neighbour correlator, and at large r the square of Yang's
+    magnetisation (the connected part decays with the transfer-matrix gap,
+    xi ~ 2); both directions."""
+    beta = 0.5
+    A, wp = wl.ising_peps(beta)
+    env = Environment([A], 1, 1, chi=16, layers=2, boundary=wp, mode="rsvd", oversample=16, power_iters=2, seed=2)
+    env.run(400, 1e-11)
+    lam = ob.transfer_spectrum(env, 0, 0, 3)
+    xi, e = ob.correlation_length(lam, 1)
+    assert 1.5 < xi < 2.5
+    for direction in (0, 1):
+        C = ob.correlation(env, 0, wl.SZ, wl.SZ, 60, direction)
+        assert abs(C[0] - 1.0) < 1e-12                       # sz^2 = 1
+        assert abs(C[1] - cf.nn_correlator(beta)) < 1e-9
+        assert abs(C[60] - cf.yang_magnetization(beta) ** 2) < 1e-8
+
+
+def test_xi_extrapolation_recovers_line():
+    """Eq. (9): 1/xi(inf) = e1(chi) + k (e2(chi) - e1(chi)); data placed
+    exactly on such a line give back its intercept and k."""
+    inv_xi, k = 0.37, 0.8
+    delta = np.array([0.5, 0.3, 0.2, 0.12])
+    e1 = inv_xi - k * delta
+    e2 = e1 + delta
+    got_inv, got_k = ob.xi_extrapolate(e1, e2)
+    assert abs(got_inv - inv_xi) < 1e-14 and abs(got_k - k) < 1e-13

@@ -17,7 +17,7 @@ Workloads (sizes as in the benchmark configurations):
 * ``random_environment(Lx, Ly, chi, Db, seed)``: N(0, 1) corners and edges
   with every leg of full size (generic spectra at every cut).
 * ``heisenberg_bond()``: S=1/2 Heisenberg bond operator of the paper's worked
-  example (Sec. 3.2), op[(out_i, out_j), (in_i, in_j)].
+  example (Sec. 5.2), op[(out_i, out_j), (in_i, in_j)].
 * ``tfim_bond(h)`` / ``tfim_product_state(h)``: transverse-field Ising in
   Pauli units, H = -sum sz sz - h sum sx, with the field split over the four
   bonds of each site.
@@ -118,7 +118,7 @@ def random_classical(Lx, Ly, D, seed, positive=True):
 
 
 def heisenberg_bond():
-    """S_i.S_j for S = 1/2 from the element list of the paper's example (Sec. 3.2).
+    """S_i.S_j for S = 1/2 from the element list of the paper's example (Sec. 5.2).
 
     Each line there is (in_i, in_j, out_i, out_j, Re, Im); states up = 0, down = 1.
     """
