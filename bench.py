@@ -59,12 +59,20 @@ def flops_per_sweep(D, chi, d, p, q, Lx=2, Ly=2):
     return 2.0 * (4 * ncut * corner + ncut * sketch + ncut * renorm)
 
 
+def oracle_threads():
+    """Threads for the oracle: the job's CPU share (OMP_NUM_THREADS where the
+    host sets it), else every core."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    return max(1, int(env)) if env and env.isdigit() else (os.cpu_count() or 1)
+
+
 def cpu_baseline(D, chi, p, q, seed):
-    """Oracle time for one left move on a random full-dimension environment."""
+    """Oracle time for one left move (a quarter sweep) of the headline
+    workload on a random full-dimension environment."""
     from threadpoolctl import threadpool_limits
 
     from oracle.ctmrg import Environment
-    cores = min(os.cpu_count() or 1, 16)
+    cores = oracle_threads()
     A = wl.random_itps(2, 2, D, 2, seed=seed)
     env = Environment(A, 2, 2, chi=chi, layers=2, mode="rsvd", oversample=p, power_iters=q, seed=7)
     rng = np.random.default_rng(3)
@@ -75,29 +83,82 @@ def cpu_baseline(D, chi, p, q, seed):
         t0 = time.perf_counter()
         env.left_move(0)
         dt = time.perf_counter() - t0
-    return dict(value=1.0 / (4.0 * dt), unit="sweeps/s", cores=cores, kind="oracle",
+    return dict(value=1.0 / (4.0 * dt), unit="sweeps/s", cores=cores, host_cpu_count=os.cpu_count(),
+                kind="oracle",
                 sample=f"one left move (1/4 sweep) of the 2x2 D={D} chi={chi} workload on a random "
-                       f"full-dimension environment, NumPy/OpenBLAS FP64, {dt:.1f} s; scaled x4")
+                       f"full-dimension environment, NumPy/OpenBLAS FP64 on {cores} threads, {dt:.1f} s; scaled x4")
+
+
+def cpu_baseline_extra(serving_res, serving_reqs, rate_hz, n_sample=6):
+    """The rest of the CPU baseline on the same host threads: oracle sweeps/s
+    of the D=4, chi=64 workload (randomized SVD p=32, q=2, and the exact SVD),
+    one sweep each from the trivial boundary; and the serving stream processed
+    FIFO one solve at a time, estimated from a sample of requests (one oracle
+    sweep each, times the sweeps that request takes to converge), replayed on
+    the same arrival trace for p50 / p99."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.ctmrg import Environment
+    cores = oracle_threads()
+    out = {"cores": cores, "host_cpu_count": os.cpu_count(), "kind": "oracle"}
+    A = wl.random_itps(2, 2, 4, 2, seed=1)
+    with threadpool_limits(limits=cores):
+        for mode in ("rsvd", "dense"):
+            env = Environment(A, 2, 2, chi=64, layers=2, mode=mode, oversample=32, power_iters=2, seed=11)
+            env.sweep()   # the first sweep grows the environment; time the second
+            t0 = time.perf_counter()
+            env.sweep()
+            out[f"d4_chi64_{mode}_sweeps_per_s"] = 1.0 / (time.perf_counter() - t0)
+        if serving_res is not None:
+            rng = np.random.default_rng(0)
+            idx = sorted(rng.choice(len(serving_reqs), size=min(n_sample, len(serving_reqs)), replace=False))
+            per_sweep = []
+            for i in idx:
+                r = serving_reqs[i]
+                env = Environment(r["A"], r["Lx"], r["Ly"], chi=r["chi"], layers=2, mode="rsvd", oversample=16,
+                                  power_iters=1, seed=3)
+                env.sweep()
+                t0 = time.perf_counter()
+                env.sweep()
+                per_sweep.append(time.perf_counter() - t0)
+            # service time of every request: a sweep costs about c L^2 n^2 k
+            # (4 L^2 cuts, sketch products of n x n corners with n x k
+            # panels, n = chi D^2, k = chi + 16), c the median over the sample,
+            # times the sweeps the request takes
+            work = lambda r: r["Lx"] ** 2 * float(r["chi"] * r["D"] ** 2) ** 2 * (r["chi"] + 16)
+            c_med = float(np.median([t / work(serving_reqs[i]) for t, i in zip(per_sweep, idx)]))
+            svc = [c_med * work(r) * max(res["sweeps"], 1) for r, res in zip(serving_reqs, serving_res)]
+            t, lat = 0.0, []
+            for r, s in zip(serving_reqs, svc):
+                t = max(t, r["arrival"]) + s
+                lat.append(t - r["arrival"])
+            out["serving_fifo_estimate"] = {
+                "requests": len(serving_reqs), "sampled": [int(i) for i in idx],
+                "sampled_sweep_s": per_sweep, "solves_per_s": len(svc) / sum(svc),
+                "arrival_rate_hz": rate_hz, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "model": "service time = c L^2 (chi D^2)^2 (chi + 16) x the request's sweep count on the GPU "
+                         "run, c the median over the sampled oracle sweeps; FIFO on the open-loop arrival trace"}
+    return out
 
 
 def run_sweeps(lib, A, D, chi, d, p, q, prec, warmup, steps):
-    """warmup untimed sweeps, then `steps` timed sweeps; returns (seconds, phase
-    timings, energy per site after warmup + steps sweeps, cut counts)."""
+    """warmup untimed sweeps, then `steps` timed sweeps through ctm_sweep
+    (the four moves and the stop rule's corner spectra of every sweep);
+    returns (seconds, phase timings, energy per site after warmup + steps
+    sweeps, cut counts)."""
     import torch
     ctx = lib.Ctm(A, 2, 2, D, chi, d=d, prec=prec, rsvd_oversample=p, rsvd_power_iters=q, seed=12)
-    moves = ("left", "right", "up", "down")
-    for _ in range(warmup):
-        for m in moves:
-            ctx.ctm_move(m)
+    if warmup:
+        ctx.ctm_sweep(warmup, 0.0)
     torch.cuda.synchronize()
     ctx.ctm_timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        for m in moves:
-            ctx.ctm_move(m)
+    n, _, _ = ctx.ctm_sweep(steps, 0.0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    assert n == steps
     phases = ctx.ctm_timing_read()
     ctx.ctm_timing_enable(False)
     H = wl.heisenberg_bond()
@@ -175,24 +236,26 @@ def scan_bench(lib, n, max_active, budget_gb, p=16, q=1, tol=1e-10, max_sweeps=4
     return out
 
 
-def serving_bench(lib, n, max_active, budget_gb, p=16, q=1, tol=1e-10, max_sweeps=40):
+def serving_bench(lib, n, max_active, budget_gb, p=16, q=1, tol=1e-10, max_sweeps=40, loads=(0.8,)):
     """The mixed TFIM stream through the serving queue: a closed loop (all
-    requests at t = 0) gives the capacity; an open loop replays Poisson
-    arrivals at 0.8 x that capacity for p50 / p99 latency (arrival to done)."""
+    requests at t = 0) gives the capacity; open loops replay Poisson arrivals
+    at the given fractions of that capacity for p50 / p99 latency (arrival to
+    done).  Every request also measures <sigma_z> on each site."""
     budget = int(budget_gb * (1 << 30))
 
-    def run(reqs, timed_arrivals):
+    def run(reqs, label):
         qu = lib.Queue(budget, max_active)
         tickets = []
         t0 = time.perf_counter()
+        timed = label != "closed"
         for r in reqs:
-            if timed_arrivals:
+            if timed:
                 dt = r["arrival"] - (time.perf_counter() - t0)
                 if dt > 0:
                     time.sleep(dt)
             st, t = qu.submit(r["A"], r["Lx"], r["Ly"], r["D"], r["chi"], r["op"], tol=tol,
                               max_sweeps=max_sweeps, tag=r["index"], rsvd_oversample=p, rsvd_power_iters=q,
-                              seed=3)
+                              seed=3, obs=[wl.SZ])
             if st != 0:
                 raise RuntimeError(f"submit failed with status {st}")
             tickets.append(t)
@@ -202,26 +265,57 @@ def serving_bench(lib, n, max_active, budget_gb, p=16, q=1, tol=1e-10, max_sweep
             if st != 0:
                 raise RuntimeError(f"request failed with status {st}")
             res.append(r)
-            if (i + 1) % 8 == 0 or i + 1 == len(tickets):
-                print(f"serving ({'open' if timed_arrivals else 'closed'} loop): {i + 1}/{len(tickets)} done, "
-                      f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            if (i + 1) % 64 == 0 or i + 1 == len(tickets):
+                print(f"serving ({label}): {i + 1}/{len(tickets)} done, {time.perf_counter() - t0:.1f} s",
+                      file=sys.stderr, flush=True)
         qu.destroy()
         first = min(r.t_submit_ns for r in res)
         last = max(r.t_done_ns for r in res)
         lat = np.array([(r.t_done_ns - r.t_submit_ns) * 1e-6 for r in res])
+        conv = int(sum(r.converged for r in res))
         return dict(solves_per_s=len(res) / ((last - first) * 1e-9), p50_ms=float(np.percentile(lat, 50)),
                     p99_ms=float(np.percentile(lat, 99)), mean_sweeps=float(np.mean([r.sweeps for r in res])),
-                    converged=int(sum(r.converged for r in res)),
-                    energies=[float(r.energy_per_site) for r in res])
+                    converged=conv, converged_fraction=conv / len(res), wall_s=time.perf_counter() - t0,
+                    energies=[float(r.energy_per_site) for r in res], sweeps=[int(r.sweeps) for r in res])
 
-    closed = run(serving_requests(n), False)
-    rate = 0.8 * closed["solves_per_s"]
-    opened = run(serving_requests(n, rate_hz=rate), True)
-    # the same request gives the same energy in both runs (own context each)
-    same = float(np.max(np.abs(np.array(closed.pop("energies")) - np.array(opened.pop("energies")))))
-    return {"requests": n, "max_active": max_active, "budget_gb": budget_gb, "rsvd_p": p, "rsvd_q": q,
-            "tol": tol, "max_sweeps": max_sweeps, "closed_loop": closed,
-            "open_loop": dict(opened, arrival_rate_hz=rate), "max_energy_diff_closed_vs_open": same}
+    reqs = serving_requests(n)
+    closed = run(reqs, "closed")
+    out = {"requests": n, "max_active": max_active, "budget_gb": budget_gb, "rsvd_p": p, "rsvd_q": q,
+           "tol": tol, "max_sweeps": max_sweeps}
+    energies, sweeps = closed.pop("energies"), closed.pop("sweeps")
+    out["closed_loop"] = closed
+    for load in loads:
+        rate = load * closed["solves_per_s"]
+        opened = run(serving_requests(n, rate_hz=rate), f"open {load}x")
+        # the same request gives the same energy in every run
+        same = float(np.max(np.abs(np.array(energies) - np.array(opened.pop("energies")))))
+        opened.pop("sweeps")
+        out[f"open_loop_{load}x"] = dict(opened, arrival_rate_hz=rate, max_energy_diff_vs_closed=same)
+    return out, reqs, sweeps
+
+
+def big_bench(lib, sweeps, D=8, chi=256, p=64, q=1, seed=3, warm=2):
+    """D = 8, chi = 256 (2x2 cell): `sweeps` sweeps from the trivial boundary
+    in FP64 and in split FP16; sweeps/s over the sweeps after the first
+    `warm` (the environment has reached chi by then), the sketch GEMMs'
+    fraction of each precision's peak, and the energy difference after all
+    sweeps."""
+    A = wl.random_itps(2, 2, D, 2, seed=seed)
+    out = {"workload": f"itps_2x2_d2_D{D}_chi{chi}", "D": D, "chi": chi, "rsvd_p": p, "rsvd_q": q,
+           "sweeps": sweeps, "timed_sweeps": sweeps - warm}
+    energies = {}
+    for prec in ("f64", "f16split"):
+        dt, ph, e, cuts = run_sweeps(lib, A, D, chi, 2, p, q, prec, warm, sweeps - warm)
+        r = sketch_rate(ph)
+        energies[prec] = e
+        out[prec] = {"sweeps_per_s": (sweeps - warm) / dt, "sketch_tflops": r / 1e12,
+                     "sketch_frac_of_peak": r / PEAK[prec], "energy_per_site": e,
+                     "cuts": dict(zip(("identity", "rsvd_batched", "fallback"), cuts)),
+                     "phases_ms_per_sweep": {k: v["ms"] / (sweeps - warm) for k, v in ph.items()}}
+        print(f"D={D} chi={chi} {prec}: {(sweeps - warm) / dt:.3f} sweeps/s", file=sys.stderr, flush=True)
+    out["f16split"]["abs_energy_diff_vs_f64"] = abs(energies["f16split"] - energies["f64"])
+    out["f16split"]["sketch_passes"] = "3 MFMA passes per product (hi hi, hi lo, lo hi); the fraction counts the algorithmic flops once"
+    return out
 
 
 def main():
@@ -239,11 +333,15 @@ def main():
                     help="skip the comparison runs in the other precisions")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain device copies (counter calibration)")
-    ap.add_argument("--serving", type=int, default=32, metavar="N",
-                    help="also run the first N requests of the mixed TFIM serving stream (512 = all)")
+    ap.add_argument("--serving", type=int, default=512, metavar="N",
+                    help="also run the first N requests of the mixed TFIM serving stream (512 = all, 0 = none)")
+    ap.add_argument("--loads", default="0.8",
+                    help="open-loop arrival rates as fractions of the closed-loop capacity (comma list)")
     ap.add_argument("--serving-only", action="store_true", help="run only the serving stream")
     ap.add_argument("--max-active", type=int, default=8)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--big-sweeps", type=int, default=20,
+                    help="sweeps of the D=8, chi=256 comparison of split FP16 with FP64 (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
@@ -258,9 +356,10 @@ def main():
         copy_calibration()
         return
     lib.load()
+    loads = tuple(float(x) for x in args.loads.split(",") if x)
     if args.serving_only:
-        print(json.dumps({"serving": serving_bench(lib, args.serving or 512, args.max_active, args.budget_gb)}),
-              flush=True)
+        sv, _, _ = serving_bench(lib, args.serving or 512, args.max_active, args.budget_gb, loads=loads)
+        print(json.dumps({"serving": sv}), flush=True)
         return
     D, chi, d, p, q = args.D, args.chi, 2, args.p, args.q
     A = wl.random_itps(2, 2, D, d, seed=2)
@@ -316,11 +415,19 @@ def main():
                          "energy_per_site": ep, "abs_energy_diff": abs(ep - energy),
                          "phases_ms_per_sweep": {k: v["ms"] / args.steps for k, v in php.items()}}
         out["precisions"] = cmp
+    if args.big_sweeps:
+        out["d8_chi256"] = big_bench(lib, args.big_sweeps)
+    sv_reqs = sv_sweeps = None
     if args.serving:
-        out["serving"] = serving_bench(lib, args.serving, args.max_active, args.budget_gb)
+        out["serving"], sv_reqs, sv_sweeps = serving_bench(lib, args.serving, args.max_active, args.budget_gb,
+                                                           loads=loads)
         out["serving_scan"] = scan_bench(lib, 16, args.max_active, args.budget_gb)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(D, chi, p, q, seed=2)
+        rate = out["serving"][f"open_loop_{loads[0]}x"]["arrival_rate_hz"] if sv_reqs and loads else None
+        arrivals = serving_requests(len(sv_reqs), rate_hz=rate) if sv_reqs and rate else sv_reqs
+        out["cpu_baseline_more"] = cpu_baseline_extra(
+            [{"sweeps": n} for n in sv_sweeps] if sv_sweeps else None, arrivals, rate)
     print(json.dumps(out), flush=True)
 
 

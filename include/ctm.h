@@ -153,6 +153,35 @@ ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, d
 ctm_status ctm_rho_1site(ctm_ctx* ctx, int site, double* rho);
 ctm_status ctm_rho_2site(ctm_ctx* ctx, int site, int dir, double* rho);
 
+/* Sec. 5.3, Eq. (8): the correlation function C(r) = <A(r0) B(r0 + r e)> for
+ * r = 0..rmax, r0 = `site`, e = (1, 0) (dir = 0) or (0, 1) (dir = 1); A and B
+ * are one-site operators (d x d, [out][in], host).  C[0] is the one-site
+ * value of the product A B.  For r >= 1: the left boundary of r0, its column
+ * with A, r - 1 plain columns, the column of r0 + r e with B and its right
+ * boundary, over the same network without operators (the columns' edge
+ * tensors are those of the sites passed).  C: rmax + 1 doubles (host). */
+ctm_status ctm_correlation(ctm_ctx* ctx, int site, int dir, const double* opA, const double* opB, int rmax,
+                           double* C);
+
+/* Sec. 5.3 (correlation length): the nev eigenvalues of largest modulus of
+ * the transfer matrix of one period of the unit cell, along +x (dir = 0) in
+ * row `line` (0 <= line < Ly) or along +y (dir = 1) in column `line`
+ * (0 <= line < Lx): the product of the columns T1 (site) T3 of the period's
+ * sites acting on a left boundary (chi x D^2 x chi).  Computed on the device
+ * by explicitly restarted Arnoldi with full reorthogonalisation (Krylov
+ * dimension min(60, chi^2 D^2), Ritz residuals below 1e-12 |lambda_0|).
+ * re / im (nev doubles each, host): the eigenvalues sorted by modulus,
+ * descending.  e (nev - 1 doubles, may be NULL): e_k = -log|lambda_k /
+ * lambda_0| / period, per lattice spacing.  xi (may be NULL): 1 / e_1, the
+ * correlation length.  1 <= nev <= 16. */
+ctm_status ctm_transfer_spectrum(ctm_ctx* ctx, int dir, int line, int nev, double* re, double* im, double* e,
+                                 double* xi);
+
+/* Sec. 5.3, Eq. (9): finite-chi extrapolation of the correlation length from
+ * runs at n >= 2 values of chi: the least-squares line
+ * e_1(chi) = 1/xi(inf) - k (e_2(chi) - e_1(chi)).  inv_xi: 1/xi(inf); k: its slope. */
+ctm_status ctm_xi_extrapolate(int n, const double* e1, const double* e2, double* inv_xi, double* k);
+
 /* The single-layer network of Fig. 2(b) contracted with the environment of
  * Fig. 2(c), for a classical network (layers = 1): Z(b) / Z(a) on the 3x3 patch of `site`,
  * with b (D^4, host) in place of the site tensor (e.g. a magnetisation). */

@@ -28,7 +28,8 @@ EXPORTS = (
     "ctm_log_kappa", "ctm_env_bytes", "ctm_get_env", "ctm_set_env", "ctm_move_count", "ctm_cut_stats",
     "ctm_footprint_bytes", "ctm_last_error", "ctm_free", "ctm_timing_enable", "ctm_timing_read",
     "ctm_queue_create", "ctm_queue_submit", "ctm_queue_poll", "ctm_queue_wait",
-    "ctm_queue_cancel", "ctm_queue_destroy",
+    "ctm_queue_cancel", "ctm_queue_destroy", "ctm_correlation", "ctm_transfer_spectrum",
+    "ctm_xi_extrapolate",
 )
 
 
@@ -100,6 +101,12 @@ def load(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} not built; run paper_2112_13184_amd.build.build()")
+    # PyTorch wheels bundle their own HIP runtime (same soname as the system
+    # one).  Loading torch first makes the library bind to that runtime, so
+    # that one runtime serves the process: device pointers and streams from
+    # torch are then valid arguments of the library (and torch still finds
+    # the device after the library has used it).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     V, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     sig = {
@@ -130,6 +137,9 @@ def load(path=LIB_PATH):
         "ctm_queue_wait": (I, [V, ctypes.c_uint64, I, ctypes.POINTER(ctm_result)]),
         "ctm_queue_cancel": (I, [V, ctypes.c_uint64]),
         "ctm_queue_destroy": (None, [V]),
+        "ctm_correlation": (I, [V, I, I, _DP, _DP, I, _DP]),
+        "ctm_transfer_spectrum": (I, [V, I, I, I, _DP, _DP, _DP, _DP]),
+        "ctm_xi_extrapolate": (I, [I, _DP, _DP, _DP, _DP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -162,6 +172,16 @@ def make_config(Lx, Ly, D, chi, d=2, layers=2, prec="f64", svd_rel_cutoff=0.0, r
 
 def ctm_footprint_bytes(cfg):
     return int(load().ctm_footprint_bytes(ctypes.byref(cfg)))
+
+
+def ctm_xi_extrapolate(e1, e2):
+    """Eq. (9) over runs at several chi: (1/xi(inf), k)."""
+    a, b = _f64(e1), _f64(e2)
+    inv, k = ctypes.c_double(), ctypes.c_double()
+    st = load().ctm_xi_extrapolate(len(a), _dp(a), _dp(b), ctypes.byref(inv), ctypes.byref(k))
+    if st != CTM_OK:
+        raise CtmError(st, "ctm_xi_extrapolate")
+    return inv.value, k.value
 
 
 class Ctm:
@@ -240,6 +260,21 @@ class Ctm:
         r = np.zeros((self.d * self.d, self.d * self.d))
         self._check(self._lib.ctm_rho_2site(self._h, site, direction, _dp(r)))
         return r
+
+    def ctm_correlation(self, site, direction, opA, opB, rmax):
+        """C(r) = <A(site) B(site + r e)>, r = 0..rmax, e = +x (0) or +y (1)."""
+        out = np.zeros(rmax + 1)
+        a, b = _f64(opA), _f64(opB)
+        self._check(self._lib.ctm_correlation(self._h, site, direction, _dp(a), _dp(b), rmax, _dp(out)))
+        return out
+
+    def ctm_transfer_spectrum(self, direction, line, nev):
+        """(eigenvalues (complex, by modulus), e_k (k = 1..nev-1), xi)."""
+        re, im, e = np.zeros(nev), np.zeros(nev), np.zeros(max(nev - 1, 1))
+        xi = ctypes.c_double()
+        self._check(self._lib.ctm_transfer_spectrum(self._h, direction, line, nev, _dp(re), _dp(im), _dp(e),
+                                                    ctypes.byref(xi)))
+        return re + 1j * im, e[:nev - 1], xi.value
 
     def ctm_impurity(self, site, b):
         v = ctypes.c_double()

@@ -1,4 +1,6 @@
 // C ABI of libctm (declared in include/ctm.h).
+#include <cmath>
+#include <complex>
 #include <cstring>
 #include <new>
 #include <string>
@@ -211,6 +213,61 @@ ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, d
     return CTM_EINVAL;
   }
   return guarded(ctx, [&] { *val = ctm::expect_2site(c, site, dir, op); });
+}
+
+ctm_status ctm_correlation(ctm_ctx* ctx, int site, int dir, const double* opA, const double* opB, int rmax,
+                           double* C) {
+  if (!ctx || !opA || !opB || !C) return CTM_EINVAL;
+  ctm::Context& c = ctx->c;
+  if (site < 0 || site >= c.N || (dir != 0 && dir != 1) || rmax < 0 || rmax > 100000 || c.layers != 2) {
+    c.err = "site / dir / rmax out of range or not an iTPS";
+    return CTM_EINVAL;
+  }
+  return guarded(ctx, [&] { ctm::correlation(c, site, dir, opA, opB, rmax, C); });
+}
+
+ctm_status ctm_transfer_spectrum(ctm_ctx* ctx, int dir, int line, int nev, double* re, double* im, double* e,
+                                 double* xi) {
+  if (!ctx || !re || !im) return CTM_EINVAL;
+  ctm::Context& c = ctx->c;
+  if ((dir != 0 && dir != 1) || line < 0 || line >= (dir == 0 ? c.Ly : c.Lx) || nev < 1 || nev > 16) {
+    c.err = "dir / line / nev out of range";
+    return CTM_EINVAL;
+  }
+  return guarded(ctx, [&] {
+    std::vector<std::complex<double>> lam(nev);
+    ctm::transfer_spectrum(c, dir, line, nev, 60, 1e-12, lam.data());
+    const int period = (dir == 0) ? c.Lx : c.Ly;
+    for (int k = 0; k < nev; ++k) {
+      re[k] = lam[k].real();
+      im[k] = lam[k].imag();
+    }
+    const double l0 = std::abs(lam[0]);
+    auto ek = [&](int k) {
+      const double r = std::abs(lam[k]);
+      return (r > 0.0 && l0 > 0.0) ? -std::log(r / l0) / period : INFINITY;
+    };
+    if (e)
+      for (int k = 1; k < nev; ++k) e[k - 1] = ek(k);
+    if (xi) *xi = (nev > 1) ? 1.0 / ek(1) : 0.0;
+  });
+}
+
+ctm_status ctm_xi_extrapolate(int n, const double* e1, const double* e2, double* inv_xi, double* k) {
+  if (n < 2 || !e1 || !e2 || !inv_xi || !k) return CTM_EINVAL;
+  // least squares for e1 = a + b (e2 - e1): a = 1/xi(inf), b = -k
+  double sx = 0, sy = 0, sxx = 0, sxy = 0;
+  for (int i = 0; i < n; ++i) {
+    const double x = e2[i] - e1[i], y = e1[i];
+    if (!std::isfinite(x) || !std::isfinite(y)) return CTM_ENUMERIC;
+    sx += x; sy += y; sxx += x * x; sxy += x * y;
+  }
+  const double den = n * sxx - sx * sx;
+  if (!(std::fabs(den) > 0.0)) return CTM_ENUMERIC;
+  const double b = (n * sxy - sx * sy) / den;
+  *inv_xi = (sy - b * sx) / n;
+  *k = -b;
+  return CTM_OK;
 }
 
 ctm_status ctm_impurity(ctm_ctx* ctx, int site, const double* b, double* val) {

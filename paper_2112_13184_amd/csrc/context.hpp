@@ -3,6 +3,7 @@
 
 #include <array>
 #include <atomic>
+#include <complex>
 #include <string>
 #include <vector>
 
@@ -230,6 +231,15 @@ double expect_2site(Context& c, int site, int dir, const double* op_host, int re
 // classical impurity / ln kappa) allocate.
 size_t observe_arena_elems(long chi, long DK, long DB, long d);
 double impurity(Context& c, int site, const double* b_host);
+// C(r) = <A(site) B(site + r e)> for r = 0..rmax (out, host), e = +x (dir 0)
+// or +y (dir 1); operators [out][in], host.
+void correlation(Context& c, int site, int dir, const double* opA, const double* opB, int rmax, double* out);
+// The nev eigenvalues of largest modulus of the transfer matrix of one
+// period along +x (dir 0, in row `line`) or +y (dir 1, in column `line`), by
+// explicitly restarted Arnoldi (Krylov dimension `krylov`, Ritz residual
+// tolerance tol relative to |lambda_0|); sorted by modulus, descending.
+// Returns the number of restarts.
+int transfer_spectrum(Context& c, int dir, int line, int nev, int krylov, double tol, std::complex<double>* lam);
 double log_kappa(Context& c);
 void check_bad(Context& c, const char* where);
 

@@ -454,6 +454,11 @@ void spectra_delta(hipStream_t st, double* S, double* prev, int ncorner, int chi
   CTM_HIP(hipGetLastError());
 }
 
+void scale_by_inv(hipStream_t st, double* x, long n, const double* den) {
+  hipLaunchKernelGGL(k_scale_by_inv, dim3(grid_for(n)), dim3(TPB), 0, st, x, n, den);
+  CTM_HIP(hipGetLastError());
+}
+
 void scale(hipStream_t st, double* x, long n, double a) {
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(TPB), 0, st, x, n, a);
   CTM_HIP(hipGetLastError());

@@ -48,6 +48,10 @@ void spectra_delta(hipStream_t st, double* S, double* prev, int ncorner, int chi
 // y[i] = a * x[i]
 void scale(hipStream_t st, double* x, long n, double a);
 
+// x /= *den (a device scalar, e.g. the maximum normalize_maxabs leaves in
+// scratch[1024]); no change if *den is 0 or not finite.
+void scale_by_inv(hipStream_t st, double* x, long n, const double* den);
+
 
 // Batched forms for problems of one shape in one launch (problem b on
 // blockIdx.y).  Pointer arguments of type `T* const*` are device arrays of one

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "context.hpp"
+#include "hessenberg.hpp"
 #include "kernels.hpp"
 
 namespace ctm {
@@ -349,6 +350,171 @@ double log_kappa(Context& c) {
   hipLaunchKernelGGL(k_logkappa, dim3(1), dim3(64), 0, c.st, z33.p, zc.p, z23.p, z32.p, out);
   CTM_HIP(hipGetLastError());
   return fetch_scalar(c, out);
+}
+
+// ---------------------------------------------------------------------------
+// Correlation functions and the transfer-matrix spectrum (Sec. 5.3, Eq. (8)
+// and the correlation length of Eq. (9))
+// ---------------------------------------------------------------------------
+namespace {
+
+// Frame of a walk from `site` along +x (dir 0) or +y (dir 1): the +y walk is
+// a +x walk in the frame rotated three quarter turns; (xv, yv) the site's
+// position in that frame.
+void line_frame(const Context& c, int site, int dir, int& rot, int& xv, int& yv) {
+  rot = (dir == 0) ? 0 : 3;
+  int x = site % c.Lx, y = site / c.Lx;
+  for (int i = 0; i < rot; ++i) { int t = x; x = -y; y = t; }
+  xv = x;
+  yv = y;
+}
+
+// s = x^T y for two device vectors of n elements (one FP64 GEMM), on the device.
+void dot_dev(Context& c, const double* x, const double* y, long n, double* s) {
+  gemm(c.st, GemmType::F64, 1, 1, (int)n, 1.0, rowmajor(x, n), colmajor(y, n), 0.0, out_colmajor(s, 1), 1, c.ws());
+}
+
+}  // namespace
+
+void correlation(Context& c, int site, int dir, const double* opA, const double* opB, int rmax, double* out) {
+  const int d = c.d;
+  // r = 0: the one-site value of the operator product A B
+  std::vector<double> ab((size_t)d * d, 0.0);
+  for (int o = 0; o < d; ++o)
+    for (int i = 0; i < d; ++i)
+      for (int k = 0; k < d; ++k) ab[o * d + i] += opA[o * d + k] * opB[k * d + i];
+  out[0] = expect_1site(c, site, ab.data());
+  if (rmax <= 0) return;
+  c.arena.reset();
+  int rot, xv, yv;
+  line_frame(c, site, dir, rot, xv, yv);
+  CTM_CHECK(view_site(c, rot, xv, yv) == site, -3, "correlation: view bookkeeping");
+  const View vs = view_of(c, site, rot);
+  const long nb = (long)c.chi * c.Db * c.chi;
+  const std::vector<long> bd = {c.chi, c.Db, c.chi};
+  double* res = c.arena.alloc(2 * (size_t)rmax);   // (with B, without) per distance
+  double* xop = c.arena.alloc(nb);                 // left part with A inserted
+  double* xid = c.arena.alloc(nb);                 // left part without operators
+  const DT LB = left_boundary(c, vs);
+  const auto m0 = c.arena.mark();
+  keep(c, column(c, LB, vs.T[0], vs.T[2], vs.Ak, bra_with_op(c, vs.Ab, opA), false), xop);
+  c.arena.release(m0);
+  keep(c, column(c, LB, vs.T[0], vs.T[2], vs.Ak, vs.Ab, false), xid);
+  c.arena.release(m0);
+  for (int r = 1; r <= rmax; ++r) {
+    const View vj = view_of(c, view_site(c, rot, xv + r, yv), rot);
+    const DT Xop = make(xop, bd), Xid = make(xid, bd);
+    const DT RB = right_boundary(c, vj);
+    keep(c, close_lr(c, column(c, Xop, vj.T[0], vj.T[2], vj.Ak, bra_with_op(c, vj.Ab, opB), false), RB),
+         res + 2 * (r - 1));
+    const DT nid = column(c, Xid, vj.T[0], vj.T[2], vj.Ak, vj.Ab, false);
+    keep(c, close_lr(c, nid, RB), res + 2 * (r - 1) + 1);
+    if (r < rmax) {
+      // both boundaries move one column on and are divided by the same
+      // number (the largest entry of the plain one)
+      const DT nop = column(c, Xop, vj.T[0], vj.T[2], vj.Ak, vj.Ab, false);
+      normalize_maxabs(c.st, nid.p, nb, c.redscratch.as<double>(), c.badflag.as<int>());
+      scale_by_inv(c.st, nop.p, nb, c.redscratch.as<double>() + 1024);
+      keep(c, nop, xop);
+      keep(c, nid, xid);
+    }
+    c.arena.release(m0);
+  }
+  const std::vector<double> h = fetch(c, res, 2 * (size_t)rmax);
+  for (int r = 1; r <= rmax; ++r) out[r] = h[2 * (r - 1)] / h[2 * (r - 1) + 1];
+  check_bad(c, "ctm_correlation");
+}
+
+int transfer_spectrum(Context& c, int dir, int line, int nev, int krylov, double tol, std::complex<double>* lam_out) {
+  c.arena.reset();
+  const int site = (dir == 0) ? c.Lx * line : line;
+  int rot, xv, yv;
+  line_frame(c, site, dir, rot, xv, yv);
+  const int period = (dir == 0) ? c.Lx : c.Ly;
+  const long n = (long)c.chi * c.Db * c.chi;
+  const int m = (int)std::min<long>(krylov, n);
+  const std::vector<long> bd = {c.chi, c.Db, c.chi};
+  std::vector<View> cols(period);
+  for (int k = 0; k < period; ++k) cols[k] = view_of(c, view_site(c, rot, xv + k, yv), rot);
+  double* V = c.arena.alloc((size_t)n * (m + 1));   // Krylov basis, one vector per row
+  double* hd = c.arena.alloc((size_t)m + 8);         // projections of one step
+  double* zd = c.arena.alloc((size_t)m + 8);         // restart combination
+  const auto mk = c.arena.mark();
+  // y = E x: the columns of one period, in order (x and y may not overlap)
+  auto matvec = [&](const double* x, double* y) {
+    DT X = make(const_cast<double*>(x), bd);
+    for (int k = 0; k < period; ++k) X = column(c, X, cols[k].T[0], cols[k].T[2], cols[k].Ak, cols[k].Ab, false);
+    keep(c, X, y);
+    c.arena.release(mk);
+  };
+  auto norm_dev = [&](const double* x) {
+    dot_dev(c, x, x, n, hd);
+    return std::sqrt(std::max(0.0, fetch_scalar(c, hd)));
+  };
+  // start vector: Philox uniforms on [-1, 1) (fixed key), unit norm
+  omega_fill(c.st, V, (int)n, 1, 1, 0x7472616e73666572ull, 0);
+  scale(c.st, V, n, 1.0 / norm_dev(V));
+  std::vector<std::complex<double>> lam;
+  int restarts = 0;
+  for (;; ++restarts) {
+    std::vector<double> H((size_t)(m + 1) * m, 0.0);
+    int me = m;
+    double beta = 0.0;
+    for (int j = 0; j < m; ++j) {
+      double* w = V + (size_t)(j + 1) * n;
+      matvec(V + (size_t)j * n, w);
+      // classical Gram-Schmidt, applied twice
+      for (int pass = 0; pass < 2; ++pass) {
+        gemm(c.st, GemmType::F64, j + 1, 1, (int)n, 1.0, rowmajor(V, n), colmajor(w, n), 0.0,
+             out_colmajor(hd, j + 1), 1, c.ws());
+        gemm(c.st, GemmType::F64, (int)n, 1, j + 1, -1.0, colmajor(V, n), colmajor(hd, j + 1), 1.0,
+             out_colmajor(w, n), 1, c.ws());
+        const std::vector<double> h = fetch(c, hd, j + 1);
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += h[i];
+      }
+      beta = norm_dev(w);
+      H[(size_t)(j + 1) * m + j] = beta;
+      double hn = 0.0;
+      for (int i = 0; i <= j; ++i) hn = std::max(hn, std::fabs(H[(size_t)i * m + j]));
+      if (beta <= 1e-14 * std::max(hn, 1e-300)) {   // invariant subspace: the Ritz values are exact
+        me = j + 1;
+        beta = 0.0;
+        break;
+      }
+      scale(c.st, w, n, 1.0 / beta);
+    }
+    std::vector<double> Hm((size_t)me * me);
+    for (int i = 0; i < me; ++i)
+      for (int j = 0; j < me; ++j) Hm[(size_t)i * me + j] = H[(size_t)i * m + j];
+    CTM_CHECK(hessenberg_eigenvalues(Hm, me, lam), -4, "transfer spectrum: Hessenberg QR did not converge");
+    std::stable_sort(lam.begin(), lam.end(),
+                     [](const std::complex<double>& a, const std::complex<double>& b) { return std::abs(a) > std::abs(b); });
+    const int want = std::min(nev, me);
+    // residual of Ritz pair k: beta |e_m^T y_k| (y_k a unit eigenvector of H_m)
+    std::vector<std::vector<std::complex<double>>> Y(want);
+    double worst = 0.0;
+    for (int k = 0; k < want; ++k) {
+      Y[k] = hessenberg_eigenvector(Hm, me, lam[k]);
+      worst = std::max(worst, beta * std::abs(Y[k][me - 1]));
+    }
+    const double scale0 = std::max(std::abs(lam[0]), 1e-300);
+    if (beta == 0.0 || worst <= tol * scale0 || restarts >= 40) break;
+    // restart from the real combination of the wanted Ritz vectors
+    std::vector<double> z(me, 0.0);
+    for (int k = 0; k < want; ++k)
+      for (int i = 0; i < me; ++i) z[i] += Y[k][i].real() + Y[k][i].imag();
+    CTM_HIP(hipMemcpyAsync(zd, z.data(), sizeof(double) * me, hipMemcpyHostToDevice, c.st));
+    double* tmp = V + (size_t)m * n;
+    gemm(c.st, GemmType::F64, (int)n, 1, me, 1.0, colmajor(V, n), colmajor(zd, me), 0.0, out_colmajor(tmp, n), 1,
+         c.ws());
+    CTM_HIP(hipMemcpyAsync(V, tmp, sizeof(double) * n, hipMemcpyDeviceToDevice, c.st));
+    const double nz = norm_dev(V);
+    CTM_CHECK(nz > 0.0, -4, "transfer spectrum: restart vector is zero");
+    scale(c.st, V, n, 1.0 / nz);
+  }
+  for (int k = 0; k < nev; ++k) lam_out[k] = (k < (int)lam.size()) ? lam[k] : 0.0;
+  check_bad(c, "ctm_transfer_spectrum");
+  return restarts;
 }
 
 }  // namespace ctm

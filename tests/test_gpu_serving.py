@@ -1,7 +1,6 @@
 """The serving queue (continuous batching of CTMRG solves on one GPU), through
 the C ABI: results alone and in a mix, closed forms through the queue, HBM
 budget admission, cancellation, and the footprint bound."""
-import ctypes
 import json
 import os
 
@@ -170,12 +169,12 @@ def test_budget_admission_and_cancel(lib):
 
 
 def _device_free_bytes():
-    """hipMemGetInfo from the HIP runtime the library itself uses."""
-    hip = ctypes.CDLL("/opt/rocm/lib/libamdhip64.so")
-    assert hip.hipDeviceSynchronize() == 0
-    free, total = ctypes.c_size_t(), ctypes.c_size_t()
-    assert hip.hipMemGetInfo(ctypes.byref(free), ctypes.byref(total)) == 0
-    return free.value
+    """hipMemGetInfo of the HIP runtime the library itself uses (torch's: the
+    binding loads torch before the library)."""
+    import torch
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    return free
 
 
 @pytest.mark.parametrize("D,chi,L", [(2, 16, 1), (3, 40, 2), (5, 100, 2), (6, 144, 2)])
