@@ -1,9 +1,11 @@
 // CTMRG context: resident environment, workspaces and the sweep driver.
 #pragma once
 
+#include <algorithm>
 #include <array>
 #include <atomic>
 #include <complex>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -138,6 +140,7 @@ struct Context {
   DevBuf Pt, PT, P3;         // [Ly][n][chi]
   DevBuf newC1, newT4, newC4;
   DevBuf spec, specprev, cornerscratch;
+  DevBuf specws;             // convergence state of the corner-spectra Jacobi (64 problems)
   DevBuf gws;                // GEMM split-K workspace
   // Per-problem pointer tables of batched launches (corners and column
   // updates of several cuts, whose tensors are not evenly spaced): a ring of
@@ -145,6 +148,10 @@ struct Context {
   // host ring.  The host ring is reused only after the stream has drained.
   DevBuf ptab;
   PinnedBuf ptab_host;
+  // pinned staging for the small device-to-host reads of the host logic
+  // (failure flags, deltas, observables): stream-ordered DMA, no pageable
+  // staging inside the runtime
+  PinnedBuf hpin;
   size_t ptab_words = 0, ptab_used = 0;
   int bchunk = 1;            // problems per batched corner / update launch (n x n scratch each)
   size_t gws_elems = 0;
@@ -165,6 +172,19 @@ struct Context {
   const double* Ab(int rot, int s) const { return Abra.as<double>() + ((long)rot * NS() + s) * szb; }
   GemmWorkspace ws() const { return GemmWorkspace{gws.as<double>(), gws_elems, amax.as<unsigned>()}; }
 };
+
+// dst[0..n) = src[0..n) (device) through the context's pinned buffer, after
+// the work enqueued on the context's stream; synchronises the stream.
+template <typename T>
+void d2h(Context& c, T* dst, const T* src, size_t n) {
+  const size_t chunk = c.hpin.bytes / sizeof(T);
+  for (size_t o = 0; o < n; o += chunk) {
+    const size_t m = std::min(chunk, n - o);
+    CTM_HIP(hipMemcpyAsync(c.hpin.p, src + o, m * sizeof(T), hipMemcpyDeviceToHost, c.st));
+    CTM_HIP(hipStreamSynchronize(c.st));
+    std::memcpy(dst + o, c.hpin.p, m * sizeof(T));
+  }
+}
 
 // Run f (which enqueues work on c.st) inside a timed region of `phase`.
 template <typename F>

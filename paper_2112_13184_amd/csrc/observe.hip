@@ -156,8 +156,7 @@ __global__ void k_ratio(const double* a, const double* b, double* out) {
 
 double fetch_scalar(Context& c, const double* dev) {
   double h = 0.0;
-  CTM_HIP(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, c.st));
-  CTM_HIP(hipStreamSynchronize(c.st));
+  d2h(c, &h, dev, 1);
   return h;
 }
 
@@ -222,8 +221,7 @@ void keep(Context& c, const DT& src, double* dst) {
 
 std::vector<double> fetch(Context& c, const double* dev, size_t n) {
   std::vector<double> h(n);
-  CTM_HIP(hipMemcpyAsync(h.data(), dev, sizeof(double) * n, hipMemcpyDeviceToHost, c.st));
-  CTM_HIP(hipStreamSynchronize(c.st));
+  d2h(c, h.data(), dev, n);
   return h;
 }
 

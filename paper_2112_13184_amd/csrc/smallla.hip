@@ -334,6 +334,40 @@ __global__ void k_jacobi_init(double* J, int k, double* off, int* conv, int* nsw
   }
 }
 
+// Per-problem convergence state of a value-only Jacobi (no rotation matrix).
+__global__ void k_jacobi_init_values(double* off, int* conv, int* nsweep, int batch) {
+  const int b = threadIdx.x;
+  if (b < batch) {
+    off[b] = 0.0;
+    conv[b] = 0;
+    nsweep[b] = 0;
+  }
+}
+
+// S_b = the column norms of the rotated A_b (its singular values), in
+// descending order (ties by column index): one workgroup per problem, k <= 320.
+__global__ __launch_bounds__(256) void k_colnorm_desc(const double* A, int k, double* S, long sstride) {
+  __shared__ double nrm[kSmallLAMaxK];
+  const int b = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* Ab = A + (long)b * k * k;
+  for (int col = w; col < k; col += blockDim.x >> 6) {
+    double s2 = 0.0;
+    for (int r = lane; r < k; r += 64) {
+      const double v = Ab[(long)col * k + r];
+      s2 += v * v;
+    }
+    s2 = wave_sum(s2);
+    if (lane == 0) nrm[col] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double v = nrm[i];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) rank += (nrm[j] > v) || (nrm[j] == v && j < i);
+    S[(long)b * sstride + rank] = v;
+  }
+}
+
 // After a sweep: converged if no pair needed a rotation (off = 0); nsweep
 // counts the sweeps that ran.
 // Problems whose Jacobi SVD has not converged get a failure code in the
@@ -381,7 +415,8 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // tournament of the 2 bs columns (the pairs inside each block and across);
 // later rounds take only the bs^2 pairs across the two blocks, in bs steps
 // of bs disjoint pairs.  Each column pair is rotated once per sweep.
-template <int ROWS>
+// VEC = false: singular values only (J is not touched).
+template <int ROWS, bool VEC = true>
 __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, double* J, int k, int nb, int bs,
                                                                    int round, double* off, const int* conv,
                                                                    double tol) {
@@ -389,7 +424,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
   // steps read and write whole columns without row checks
   constexpr int kJacobiLd = 64 * ROWS;
   __shared__ double sA[2 * kJacobiMaxBS * kJacobiLd];
-  __shared__ double sJ[2 * kJacobiMaxBS * kJacobiLd];
+  __shared__ double sJ[VEC ? 2 * kJacobiMaxBS * kJacobiLd : 1];
   const int b = blockIdx.y;
   if (conv[b]) return;
   const long kk2 = (long)k * k;
@@ -411,7 +446,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
         const int r = lane + 64 * t;
         const bool ok = gcol[h] < k && r < k;
         va[h][t] = ok ? Ab[(long)gcol[h] * k + r] : 0.0;
-        vj[h][t] = ok ? Jb[(long)gcol[h] * k + r] : 0.0;
+        vj[h][t] = (VEC && ok) ? Jb[(long)gcol[h] * k + r] : 0.0;
       }
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -419,7 +454,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       for (int t = 0; t < ROWS; ++t) {
         const int r = lane + 64 * t;
         sA[(h * bs + q) * kJacobiLd + r] = va[h][t];
-        sJ[(h * bs + q) * kJacobiLd + r] = vj[h][t];
+        if (VEC) sJ[(h * bs + q) * kJacobiLd + r] = vj[h][t];
       }
   }
   __syncthreads();
@@ -438,16 +473,16 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
     }
     double* ai = sA + ci * kJacobiLd + lane;
     double* aj = sA + cj * kJacobiLd + lane;
-    double* ji = sJ + ci * kJacobiLd + lane;
-    double* jj = sJ + cj * kJacobiLd + lane;
+    double* ji = sJ + (VEC ? ci * kJacobiLd + lane : 0);
+    double* jj = sJ + (VEC ? cj * kJacobiLd + lane : 0);
     // both columns and their rotation accumulators in registers (rows lane + 64 t)
     double x[ROWS], y[ROWS], u[ROWS], v[ROWS];
 #pragma unroll
     for (int t = 0; t < ROWS; ++t) {
       x[t] = ai[64 * t];
       y[t] = aj[64 * t];
-      u[t] = ji[64 * t];
-      v[t] = jj[64 * t];
+      u[t] = VEC ? ji[64 * t] : 0.0;
+      v[t] = VEC ? jj[64 * t] : 0.0;
     }
     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -475,8 +510,10 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       for (int t = 0; t < ROWS; ++t) {
         ai[64 * t] = cs * x[t] - sn * y[t];
         aj[64 * t] = sn * x[t] + cs * y[t];
-        ji[64 * t] = cs * u[t] - sn * v[t];
-        jj[64 * t] = sn * u[t] + cs * v[t];
+        if (VEC) {
+          ji[64 * t] = cs * u[t] - sn * v[t];
+          jj[64 * t] = sn * u[t] + cs * v[t];
+        }
       }
     }
     __syncthreads();
@@ -490,7 +527,7 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
         const int r = lane + 64 * t;
         if (r < k) {
           Ab[(long)gc * k + r] = sA[(h * bs + q) * kJacobiLd + r];
-          Jb[(long)gc * k + r] = sJ[(h * bs + q) * kJacobiLd + r];
+          if (VEC) Jb[(long)gc * k + r] = sJ[(h * bs + q) * kJacobiLd + r];
         }
       }
     }
@@ -661,6 +698,7 @@ void smallla_alloc(SmallLA& s, int kmax, int batch_max, long nmax) {
   s.Racc.alloc(m * 8); s.Rtmp.alloc(m * 8); s.J.alloc(m * 8);
   CTM_CHECK(batch_max <= 64, -1, "smallla: at most 64 problems per batch");
   s.flag.alloc(sizeof(int) * 256);
+  s.hflag.alloc(sizeof(int) * 256);
   s.off.alloc(sizeof(double) * 64);
   s.mask.alloc(sizeof(double) * (size_t)kmax * batch_max);
   s.tmp_elems = (size_t)nmax * kmax * batch_max;
@@ -816,7 +854,7 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   };
   sweeps(first);
   for (int done = first; done < max_sweeps; done += more) {
-    int hconv[64];
+    int* hconv = s.hflag.as<int>();
     CTM_HIP(hipMemcpyAsync(hconv, conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
     CTM_HIP(hipStreamSynchronize(st));
     bool all = true;
@@ -829,16 +867,63 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   CTM_HIP(hipGetLastError());
   static const bool debug = getenv("CTM_DEBUG") != nullptr;
   if (debug) {
-    int h[2][64];
-    CTM_HIP(hipMemcpyAsync(h[0], nsweep, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
-    CTM_HIP(hipMemcpyAsync(h[1], conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    int* hs = s.hflag.as<int>();
+    CTM_HIP(hipMemcpyAsync(hs, nsweep, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    CTM_HIP(hipMemcpyAsync(hs + 64, conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
     CTM_HIP(hipStreamSynchronize(st));
+    const int* h[2] = {hs, hs + 64};
     fprintf(stderr, "[ctm] jacobi k=%d:", k);
     for (int b = 0; b < batch; ++b) fprintf(stderr, " %d%s", h[0][b], h[1][b] ? "" : "(not converged)");
     fprintf(stderr, "\n");
   }
 }
 
+
+void singular_values_batched(hipStream_t st, double* A, int k, int batch, double* S, long sstride, double* off,
+                             int* conv, int* nsweep, int* hconv) {
+  CTM_CHECK(k >= 1 && k <= kSmallLAMaxK && batch >= 1 && batch <= 64, -1, "singular_values_batched: size");
+  int bs = jacobi_block(k);
+  int nb = (k + bs - 1) / bs;
+  if (nb & 1) ++nb;
+  if (nb < 2) nb = 2;
+  const double tol = 1e-15;
+  hipLaunchKernelGGL(k_jacobi_init_values, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch);
+  const int max_sweeps = 30, first = 8;
+  auto sweeps = [&](int count) {
+    for (int sw = 0; sw < count; ++sw) {
+      for (int r = 0; r < nb - 1; ++r) {
+        const dim3 grid(nb / 2, batch), block(64 * bs);
+        switch (rows_for(k)) {
+          case 1:
+          case 2:
+            hipLaunchKernelGGL((k_jacobi_round<2, false>), grid, block, 0, st, A, nullptr, k, nb, bs, r, off, conv, tol);
+            break;
+          case 3:
+            hipLaunchKernelGGL((k_jacobi_round<3, false>), grid, block, 0, st, A, nullptr, k, nb, bs, r, off, conv, tol);
+            break;
+          default:
+            hipLaunchKernelGGL((k_jacobi_round<kRowsLarge, false>), grid, block, 0, st, A, nullptr, k, nb, bs, r, off,
+                               conv, tol);
+        }
+      }
+      hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, tol);
+    }
+    CTM_HIP(hipGetLastError());
+  };
+  // rounds of a converged problem return at once: reading the flags after
+  // `first` sweeps and then after each further one does not change results
+  sweeps(first);
+  for (int done = first; done < max_sweeps; ++done) {
+    CTM_HIP(hipMemcpyAsync(hconv, conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+    CTM_HIP(hipStreamSynchronize(st));
+    bool all = true;
+    for (int b = 0; b < batch; ++b) all = all && hconv[b] != 0;
+    if (all) break;
+    sweeps(1);
+  }
+  hipLaunchKernelGGL(k_colnorm_desc, dim3(batch), dim3(256), 0, st, A, k, S, sstride);
+  CTM_HIP(hipGetLastError());
+}
 
 void singular_values_small(hipStream_t st, const double* A, int m, int batch, double* S) {
   CTM_CHECK(m >= 1 && m <= kSvSmallMax && batch >= 1, -1, "singular_values_small: size");

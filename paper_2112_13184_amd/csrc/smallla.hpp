@@ -14,6 +14,7 @@ struct SmallLA {
   // convergence per problem, [128, 192) projector-weight failure per problem,
   // [192, 256) Jacobi sweeps run per problem
   DevBuf G, R, Rinv, Racc, Rtmp, J, flag, off, tmp, mask;
+  PinnedBuf hflag;   // pinned staging of the convergence flags read by the host
   size_t tmp_elems = 0;
 };
 
@@ -47,5 +48,11 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
 // column-major m x m matrices at A + b * m * m, m <= kSvSmallMax, by one-sided
 // Jacobi in one workgroup per matrix (A is read, not changed).
 void singular_values_small(hipStream_t st, const double* A, int m, int batch, double* S);
+// The same for m x m matrices with m <= kSmallLAMaxK (batch <= 64), by the
+// blocked one-sided Jacobi without rotation accumulation: A (column-major,
+// b * m * m apart) is overwritten; S_b at S + b * sstride.  off, conv,
+// nsweep: device workspaces of batch entries; hconv: pinned host ints.
+void singular_values_batched(hipStream_t st, double* A, int m, int batch, double* S, long sstride, double* off,
+                             int* conv, int* nsweep, int* hconv);
 
 }  // namespace ctm

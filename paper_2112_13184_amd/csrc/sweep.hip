@@ -168,7 +168,7 @@ Sizes sizes_of(const ctm_config& cfg, int R = 1) {
   if (kk <= kSmallLAMaxK && p >= 0)                                 // Cholesky QR / Jacobi
     e += 6 * kk * kk * Lmax + kk * Lmax + n * kk * Lmax + 64 + 128;
   e += 3 * Lmax * n * chi + 2 * Lmax * cc + Lmax * cc * s.Db;       // projectors, new C / T
-  e += 2 * 4 * N * chi + 4 * N * cc;                                // spectra, corner scratch
+  e += 2 * 4 * N * chi + 4 * N * cc + 128;                          // spectra, corner scratch, its Jacobi state
   e += 8 * n * std::max(kk, chi) * R;                               // split-K partials
   e += 4096 + std::max<long>(2048, 1025 * Lmax) + 64;              // rho, reductions, flags
   e += kTableWords;                                                 // pointer tables
@@ -215,8 +215,7 @@ size_t context_footprint_group(const ctm_config& cfg, int replicas) { return siz
 // call throws CTM_ENUMERIC instead.
 void check_bad(Context& c, const char* where) {
   std::vector<int> bad(c.R, 0);
-  CTM_HIP(hipMemcpyAsync(bad.data(), c.badflag.p, sizeof(int) * c.R, hipMemcpyDeviceToHost, c.st));
-  CTM_HIP(hipStreamSynchronize(c.st));
+  d2h(c, bad.data(), c.badflag.as<int>(), c.R);
   bool any = false;
   for (int r = 0; r < c.R; ++r) {
     if (bad[r]) c.failed[r] = 1;
@@ -331,6 +330,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.ptab_words = kTableWords;
   c.ptab.alloc(sizeof(uint64_t) * c.ptab_words);
   c.ptab_host.alloc(sizeof(uint64_t) * c.ptab_words);
+  c.hpin.alloc(64 << 10);
   c.ptab_used = 0;
   c.Ybuf.alloc(sizeof(double) * sz.y);
   for (auto& p : c.pan) p.alloc(sizeof(double) * c.n * c.kk * Lmax0);
@@ -353,6 +353,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.spec.alloc(sizeof(double) * 4 * NS * c.chi);
   c.specprev.alloc(sizeof(double) * 4 * NS * c.chi);
   c.cornerscratch.alloc(sizeof(double) * 4 * NS * cc);
+  c.specws.alloc(sizeof(double) * 64 + 2 * sizeof(int) * 64);
   c.gws_elems = (size_t)8 * c.n * std::max(c.kk, c.chi) * c.R;
   c.gws.alloc(sizeof(double) * c.gws_elems);
   c.amax.alloc(sizeof(unsigned) * 2);
@@ -763,8 +764,7 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
   mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n, pk), colmajor(Ysv, kk, k2), out_rowmajor(PT, chi, nc), nb);
   // cuts whose Cholesky QR broke down
   int flags[192] = {0};
-  CTM_HIP(hipMemcpyAsync(flags, c.sla.flag.p, sizeof(int) * 192, hipMemcpyDeviceToHost, c.st));
-  CTM_HIP(hipStreamSynchronize(c.st));
+  d2h(c, flags, c.sla.flag.as<int>(), 192);
   failed.clear();
   bool any = false, numeric = false;
   for (int b = 0; b < nb; ++b) {
@@ -777,10 +777,8 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
     any |= flags[b] || flags[128 + b];
   }
   if (any) {
-    const int zero[192] = {0};
-    CTM_HIP(hipMemcpyAsync(c.sla.flag.p, zero, sizeof(int) * 64, hipMemcpyHostToDevice, c.st));
-    CTM_HIP(hipMemcpyAsync(c.sla.flag.as<int>() + 128, zero, sizeof(int) * 64, hipMemcpyHostToDevice, c.st));
-    CTM_HIP(hipStreamSynchronize(c.st));
+    CTM_HIP(hipMemsetAsync(c.sla.flag.p, 0, sizeof(int) * 64, c.st));
+    CTM_HIP(hipMemsetAsync(c.sla.flag.as<int>() + 128, 0, sizeof(int) * 64, c.st));
   }
   if (g_debug) {
     fprintf(stderr, "[ctm] move %lld rot %d col %d slots %d..%d: cholqr failed %zu, no-sigma %d, codes", c.moves,
@@ -1085,9 +1083,18 @@ static void corner_spectra(Context& c, double* out) {
     }
     CTM_HIP(hipMemcpyAsync(c.cornerscratch.p, c.envC.p, sizeof(double) * 4 * c.NS() * cc, hipMemcpyDeviceToDevice,
                            c.st));
-    for (int i = 0; i < 4 * c.NS(); i += 64)
-      la_singular_values_batched(c.la, c.cornerscratch.as<double>() + i * cc, c.chi, std::min(64, 4 * c.NS() - i),
-                                 out + (long)i * c.chi);
+    for (int i = 0; i < 4 * c.NS(); i += 64) {
+      const int nb = std::min(64, 4 * c.NS() - i);
+      double* A = c.cornerscratch.as<double>() + i * cc;
+      if (c.chi <= kSmallLAMaxK) {   // blocked one-sided Jacobi, values only (C^T: same values)
+        double* off = c.specws.as<double>();
+        int* conv = reinterpret_cast<int*>(off + 64);
+        singular_values_batched(c.st, A, c.chi, nb, out + (long)i * c.chi, c.chi, off, conv, conv + 64,
+                                c.hpin.as<int>());
+      } else {
+        la_singular_values_batched(c.la, A, c.chi, nb, out + (long)i * c.chi);
+      }
+    }
   });
 }
 
@@ -1116,8 +1123,7 @@ void group_sweep(Context& c, double* host_delta) {
   }
   corner_spectra(c, c.spec.as<double>());
   replica_deltas(c, c.spec.as<double>(), c.specprev.as<double>());
-  CTM_HIP(hipMemcpyAsync(host_delta, c.delta.p, sizeof(double) * c.R, hipMemcpyDeviceToHost, c.st));
-  CTM_HIP(hipStreamSynchronize(c.st));
+  d2h(c, host_delta, c.delta.as<double>(), c.R);
 }
 
 void replica_reset(Context& c, int r, const double* tensors, uint64_t seed) {

@@ -14,8 +14,6 @@ Outputs (JSON, one file per workload):
                         from the trivial boundary: energies after sweeps 1, 2, 5, 10, 20, 30.
 * restart_d4_chi64.json the D=4, chi=64 workload started from a random full-dimension
                         environment (seed 21): energies after each of 3 sweeps.
-* restart_d6_chi144.json the D=6, chi=144 workload from a random environment (seed 21):
-                        energies after each of 2 sweeps.
 * tfim_converged.json   transverse-field Ising requests (mean-field state plus 0.1 N(0,1)
                         noise) at D = 2 and 3, 1x1 and 2x2 cells: energy per site and
                         <sigma_z> per site after 40 sweeps, where the energy has settled
@@ -55,8 +53,6 @@ WORKLOADS = {
                            perturb=(0,)),
     "restart_d4_chi64": dict(D=4, chi=64, seed=1, p=32, q=2, sketch_seed=11, record=(1, 2, 3), env_seed=21,
                              perturb=(0, 1, 2)),
-    "restart_d6_chi144": dict(D=6, chi=144, seed=2, p=48, q=1, sketch_seed=12, record=(1, 2), env_seed=21,
-                              perturb=(0, 1)),
 }
 MOVES = {
     "move_d6_chi144": dict(D=6, chi=144, seed=2, p=48, q=1, sketch_seed=12, env_seed=21, samples=256),

@@ -342,13 +342,14 @@ def test_ising_peps_gauged_2x2_matches_oracle(lib):
     assert worst < 1e-10
 
 
-@pytest.mark.parametrize("chi", [24, 130])
+@pytest.mark.parametrize("chi", [24, 130, 330])
 def test_sweep_delta_is_the_corner_spectra_change(lib, chi):
     """The stop rule's measure (Sec. 2.2 convergence of the corner spectra):
     a sweep reports the largest, over corners, of sum |s_new - s_old| of the
     normalised singular values of each corner.  Checked against NumPy's SVD of
     the corners read back before and after the sweep; chi = 24 takes the
-    one-workgroup Jacobi, chi = 130 the library SVD."""
+    one-workgroup Jacobi, chi = 130 the batched value-only Jacobi, chi = 330
+    the library SVD."""
     A = wl.random_itps(2, 2, 3, 2, seed=11)
     ctx = lib.Ctm(A, 2, 2, 3, chi, rsvd_oversample=16, rsvd_power_iters=1, seed=3)
     for _ in range(2):
@@ -427,7 +428,7 @@ def _golden(name):
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("name", ["itps_d4_chi64", "itps_d6_chi144", "restart_d4_chi64", "restart_d6_chi144"])
+@pytest.mark.parametrize("name", ["itps_d4_chi64", "itps_d6_chi144", "restart_d4_chi64"])
 def test_full_size_against_stored_oracle(lib, name):
     """Full-size runs against the stored oracle energies after the recorded
     sweeps, from the trivial boundary (itps_*) or from a random full-dimension
