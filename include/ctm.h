@@ -148,6 +148,23 @@ ctm_status ctm_expect_1site(ctm_ctx* ctx, int site, const double* op, double* va
  * +y (dir = 1), from the 3x4 / 4x3 patch.  op is d^2 x d^2 (see above). */
 ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, double* val);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ctm_expect_2site with every transient of the contraction placed in one
+ * fixed device array of CTM_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each device for the life of the process (set up by ctm_init), instead of
+ * the context's workspace, which ctm_expect_2site grows on first use.  The
+ * call itself allocates nothing (no hipMalloc, no allocating library call);
+ * the context must exist (ctm_init allocates).  CTM_ETOOBIG, state unchanged,
+ * if the contraction needs more than the array (the transients of a bond
+ * grow as chi^2 D^4 (4 + 2 d) doubles: D = 3, chi = 40 fits, D = 4, chi = 64
+ * does not); CTM_EDEVICE if the array's address could not be obtained on the
+ * context's device.  All calls on one GPU share the array and it keeps the
+ * last call's contents (nothing in it needs to start at zero): calls that
+ * overlap on one GPU race, so serialise them. */
+#define CTM_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+ctm_status ctm_expect_2site_noalloc(ctm_ctx* ctx, int site, int dir, const double* op, double* val);
+
 /* Reduced density matrices behind the two calls above (host, ket index first:
  * rho[p][p'] and rho[(p_s, p_t)][(p_s', p_t')]), normalised to trace 1. */
 ctm_status ctm_rho_1site(ctm_ctx* ctx, int site, double* rho);

@@ -29,7 +29,7 @@ EXPORTS = (
     "ctm_footprint_bytes", "ctm_last_error", "ctm_free", "ctm_timing_enable", "ctm_timing_read",
     "ctm_queue_create", "ctm_queue_submit", "ctm_queue_poll", "ctm_queue_wait",
     "ctm_queue_cancel", "ctm_queue_destroy", "ctm_correlation", "ctm_transfer_spectrum",
-    "ctm_xi_extrapolate",
+    "ctm_xi_extrapolate", "ctm_expect_2site_noalloc",
 )
 
 
@@ -140,6 +140,7 @@ def load(path=LIB_PATH):
         "ctm_correlation": (I, [V, I, I, _DP, _DP, I, _DP]),
         "ctm_transfer_spectrum": (I, [V, I, I, I, _DP, _DP, _DP, _DP]),
         "ctm_xi_extrapolate": (I, [I, _DP, _DP, _DP, _DP]),
+        "ctm_expect_2site_noalloc": (I, [V, I, I, _DP, _DP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -249,6 +250,14 @@ class Ctm:
         v = ctypes.c_double()
         o = _f64(op)
         self._check(self._lib.ctm_expect_2site(self._h, site, direction, _dp(o), ctypes.byref(v)))
+        return v.value
+
+    def ctm_expect_2site_noalloc(self, site, direction, op):
+        """ctm_expect_2site with its transients in the library's fixed
+        device array (no device allocation in the call)."""
+        v = ctypes.c_double()
+        o = _f64(op)
+        self._check(self._lib.ctm_expect_2site_noalloc(self._h, site, direction, _dp(o), ctypes.byref(v)))
         return v.value
 
     def ctm_rho_1site(self, site):

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -14,7 +15,29 @@ struct ctm_ctx {
   ctm::DevBuf rho;   // small persistent buffer for reduced density matrices
 };
 
+// Fixed device array for ctm_expect_2site_noalloc: the transients of the
+// bond contraction when the caller cannot allocate.  Each device holds its
+// own copy for the life of the process; its address on a device comes from
+// hipGetSymbolAddress (the name itself is a host-side stand-in).
+constexpr size_t kNoAllocScratchElems = CTM_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kNoAllocScratchElems];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+double* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Once per device, with that device current: the device address of `scratch`.
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::call_once(g_scratch_once[dev], [dev] {
+    void* p = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (g_scratch_err[dev] == hipSuccess) g_scratch_ptr[dev] = static_cast<double*>(p);
+  });
+}
 
 const char* kNullCtx = "null context";
 thread_local std::string g_static_err;
@@ -104,6 +127,7 @@ ctm_status ctm_init(const ctm_config* cfg, const double* tensors, int tensors_on
   ctm_status st = guarded(ctx, [&] {
     ctm::context_init(ctx->c, *cfg, tensors, tensors_on_device, boundary);
     ctx->rho.alloc(sizeof(double) * 4096);
+    scratch_setup(ctx->c.device);
   });
   if (st != CTM_OK) {
     g_static_err = ctx->c.err;
@@ -213,6 +237,36 @@ ctm_status ctm_expect_2site(ctm_ctx* ctx, int site, int dir, const double* op, d
     return CTM_EINVAL;
   }
   return guarded(ctx, [&] { *val = ctm::expect_2site(c, site, dir, op); });
+}
+
+ctm_status ctm_expect_2site_noalloc(ctm_ctx* ctx, int site, int dir, const double* op, double* val) {
+  if (!ctx || !op || !val) return CTM_EINVAL;
+  ctm::Context& c = ctx->c;
+  if (site < 0 || site >= c.N || (dir != 0 && dir != 1) || c.layers != 2) {
+    c.err = "site / dir out of range or not an iTPS";
+    return CTM_EINVAL;
+  }
+  const int dev = c.device;
+  if (dev < 0 || dev >= kMaxDevices || !g_scratch_ptr[dev]) {
+    c.err = std::string("no scratch array on this device: ") +
+            hipGetErrorString(dev >= 0 && dev < kMaxDevices ? g_scratch_err[dev] : hipErrorInvalidDevice);
+    return CTM_EDEVICE;
+  }
+  const size_t need = ctm::observe_arena_elems(c.chi, c.DK, c.DB, c.d);
+  if (need > kNoAllocScratchElems) {
+    c.err = "the bond contraction needs " + std::to_string(need * sizeof(double)) +
+            " bytes of scratch, more than CTM_NOALLOC_SCRATCH_BYTES";
+    return CTM_ETOOBIG;
+  }
+  ctm::Arena& a = c.arena;
+  const auto saved = a.mark();
+  a.ext = g_scratch_ptr[dev];
+  a.ext_elems = kNoAllocScratchElems;
+  const ctm_status st = guarded(ctx, [&] { *val = ctm::expect_2site(c, site, dir, op); });
+  a.ext = nullptr;
+  a.ext_elems = 0;
+  a.release(saved);
+  return st;
 }
 
 ctm_status ctm_correlation(ctm_ctx* ctx, int site, int dir, const double* opA, const double* opB, int rmax,

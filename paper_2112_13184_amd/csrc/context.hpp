@@ -26,6 +26,11 @@ struct Arena {
   std::vector<DevBuf*> chunks;
   size_t cur = 0, used = 0;   // current chunk, elements used in it
   size_t first_elems = 0;
+  // While ext is set, alloc() bumps through this fixed device buffer instead
+  // of the chunks (it never allocates then, and throws CTM_ETOOBIG when the
+  // buffer is full); `used` is the offset into it.
+  double* ext = nullptr;
+  size_t ext_elems = 0;
   double* alloc(size_t elems);
   void reset() { cur = 0; used = 0; }
   std::array<size_t, 2> mark() const { return {cur, used}; }
@@ -104,6 +109,7 @@ struct Context {
   // replica); otherwise the move throws CTM_ENUMERIC.
   std::vector<char> failed;
   bool isolate = false;
+  int device = 0;            // HIP device the context lives on
   int D = 0, d = 0, DK = 0, DB = 0, Db = 0, chi = 0, n = 0, layers = 2;
   int kk = 0;               // sketch width
   double cutoff = 1e-12;

@@ -187,6 +187,12 @@ Sizes sizes_of(const ctm_config& cfg, int R = 1) {
 
 double* Arena::alloc(size_t elems) {
   elems = ((elems + 31) / 32) * 32;
+  if (ext) {
+    CTM_CHECK(used + elems <= ext_elems, -5, "contraction needs more than the fixed scratch array");
+    double* p = ext + used;
+    used += elems;
+    return p;
+  }
   while (cur < chunks.size() && used + elems > chunks[cur]->bytes / sizeof(double)) {
     ++cur;
     used = 0;
@@ -236,6 +242,7 @@ void check_bad(Context& c, const char* where) {
 void context_init(Context& c, const ctm_config& cfg, const double* tensors, int on_device,
                   const double* boundary, int replicas, const uint64_t* seeds) {
   c.cfg = cfg;
+  CTM_HIP(hipGetDevice(&c.device));
   c.Lx = cfg.Lx; c.Ly = cfg.Ly; c.N = cfg.Lx * cfg.Ly;
   CTM_CHECK(replicas >= 1 && replicas * std::max(cfg.Lx, cfg.Ly) <= 64, -1, "context: 1..64/max(Lx, Ly) replicas");
   c.R = replicas;
