@@ -163,6 +163,11 @@ struct Context {
   size_t gws_elems = 0;
   DevBuf amax;               // split-FP16 operand scaling (2 words)
   DevBuf camax;              // split FP16: largest |entry| of each corner role over a column's cuts
+  // BF16 / split FP16: the corners of a column's cuts and the sketch panels
+  // stored once in the reduced type (gemm_pre operands); lp_ld = their row pitch
+  DevBuf Glp, panlp, panscale;
+  long lp_ld = 0;
+  int lp_npl = 0;
   GemmType ctype = GemmType::F64;   // arithmetic of the contraction GEMMs
   Arena arena;
   std::vector<int> nact_cut; // per slot of the current column: bond dim after the move

@@ -681,6 +681,266 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(KArgs g) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// Products of pre-converted operands (PreOperand): both operands are 2-byte
+// values with k contiguous and whole 32-wide k-tiles, so a lane stages eight
+// values of one row with one 16-byte load and one 16-byte LDS store, with no
+// conversion and no k guard; rows past M (N) are clamped to the last one
+// (their products are not stored).  Same LDS layout, MFMA lane layout and
+// epilogue as gemm_lp_kernel.
+// ---------------------------------------------------------------------------
+struct PArgs {
+  const unsigned short* A;
+  const unsigned short* B;
+  double* C;
+  long lda, bsa, loa, ldb, bsb, lob;
+  long sc0, sc1, bsc;
+  int M, N, Kp;
+  double alpha;
+  const unsigned* amaxA;
+  const unsigned* amaxB;
+  const float* rsA;
+  const float* rsB;
+  long rsa_bs, rsb_bs;
+  int splits, kchunk;
+  double* ws;
+  int batch;
+};
+
+template <int KIND, int BM, int BN, int WAVES_M>
+__global__ __launch_bounds__(256) void gemm_pre_kernel(PArgs g) {
+  typedef typename LpStore<KIND>::T T;
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  constexpr int BK = 32, LDK = BK + 8;
+  constexpr int NP = (KIND == LP_F16) ? 2 : 1;
+  constexpr int WAVES_N = 4 / WAVES_M;
+  constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int CA = BM * (BK / 8) / 256, CB = BN * (BK / 8) / 256;   // 16-byte chunks per thread
+  static_assert(TM >= 1 && TN >= 1 && CA >= 1 && CB >= 1, "tile");
+  __shared__ __attribute__((aligned(16))) T As[2][NP][BM * LDK];
+  __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tiles_n = (g.N + BN - 1) / BN, tiles_m = (g.M + BM - 1) / BM;
+  int tile, split, b;
+  xcd_remap(tile, split, b);
+  // consecutive tiles walk the rows of A (the large operand) in order
+  const int tm_ = tile % tiles_m, tn_ = tile / tiles_m;
+  (void)tiles_n;
+  const int m0 = tm_ * BM, n0 = tn_ * BN;
+  const int kb = split * g.kchunk;
+  const int ke = min(g.Kp, kb + g.kchunk);
+  const unsigned short* A = g.A + (long)b * g.bsa;
+  const unsigned short* B = g.B + (long)b * g.bsb;
+
+  long a_off[CA], b_off[CB];
+  int a_lds[CA], b_lds[CB];
+#pragma unroll
+  for (int j = 0; j < CA; ++j) {
+    const int e = tid + 256 * j, r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
+    a_off[j] = (long)min(m0 + r, g.M - 1) * g.lda + kq;
+    a_lds[j] = r * LDK + kq;
+  }
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int e = tid + 256 * j, r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
+    b_off[j] = (long)min(n0 + r, g.N - 1) * g.ldb + kq;
+    b_lds[j] = r * LDK + kq;
+  }
+  u4 ra[NP][CA], rb[NP][CB];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int j = 0; j < CA; ++j)
+        ra[p][j] = *reinterpret_cast<const u4*>(A + (p ? g.loa : 0) + a_off[j] + k0);
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+        rb[p][j] = *reinterpret_cast<const u4*>(B + (p ? g.lob : 0) + b_off[j] + k0);
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int j = 0; j < CA; ++j) *reinterpret_cast<u4*>(&As[buf][p][a_lds[j]]) = ra[p][j];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) *reinterpret_cast<u4*>(&Bs[buf][p][b_lds[j]]) = rb[p][j];
+    }
+  };
+
+  f4 acc[TM][TN], acc2[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      acc2[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
+  const int r16 = lane & 15, kg = lane >> 4;
+  auto compute = [&](int cur) {
+    if constexpr (KIND == LP_BF16) {
+      bf8 af[TM], bfr[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+        af[i] = *reinterpret_cast<const bf8*>(&As[cur][0][(wm0 + i * 16 + r16) * LDK + 8 * kg]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        bfr[j] = *reinterpret_cast<const bf8*>(&Bs[cur][0][(wn0 + j * 16 + r16) * LDK + 8 * kg]);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    } else {
+      h8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int o = (wm0 + i * 16 + r16) * LDK + 8 * kg;
+        ah[i] = *reinterpret_cast<const h8*>(&As[cur][0][o]);
+        al[i] = *reinterpret_cast<const h8*>(&As[cur][NP - 1][o]);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int o = (wn0 + j * 16 + r16) * LDK + 8 * kg;
+        bh[j] = *reinterpret_cast<const h8*>(&Bs[cur][0][o]);
+        bl[j] = *reinterpret_cast<const h8*>(&Bs[cur][NP - 1][o]);
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[i], bl[j], acc2[i][j], 0, 0, 0);
+          acc2[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[i], bh[j], acc2[i][j], 0, 0, 0);
+        }
+    }
+  };
+
+  const int nk = (ke > kb) ? (ke - kb) / BK : 0;
+  if (nk > 0) {
+    load_tile(kb);
+    store_tile(0);
+  }
+  __syncthreads();
+  for (int it = 0; it < nk; ++it) {
+    const int cur = it & 1;
+    if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
+    compute(cur);
+    if (it + 1 < nk) store_tile(cur ^ 1);
+    __syncthreads();
+  }
+
+  // scales: F16 A by one power of two (or one per row), B by one per row
+  // of B (column of C); BF16 none
+  double sa = 1.0;
+  if (KIND == LP_F16 && !g.rsA) sa = f16_scale(*g.amaxA);
+  double* C = g.C + (long)b * g.bsc;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + wn0 + j * 16 + r16;
+    double sbn = 1.0;
+    if (KIND == LP_F16 && n < g.N) sbn = g.rsB ? (double)g.rsB[(long)b * g.rsb_bs + n] : f16_scale(*g.amaxB);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm0 + i * 16 + kg * 4 + r;
+        if (m < g.M && n < g.N) {
+          double v = (double)acc[i][j][r];
+          if constexpr (KIND == LP_F16) {
+            v += (double)acc2[i][j][r] * (1.0 / 2048.0);
+            const double sam = g.rsA ? (double)g.rsA[(long)b * g.rsa_bs + m] : sa;
+            v *= g.alpha / (sam * sbn);
+          } else {
+            v *= g.alpha;
+          }
+          if (g.splits > 1)
+            g.ws[(((long)split * g.batch + b) * g.M + m) * g.N + n] = v;
+          else
+            C[m * g.sc0 + n * g.sc1] = v;
+        }
+      }
+  }
+}
+
+// Square operand -> pre-converted rows of G and of G^T: 32 x 32 tiles through
+// LDS, so that both outputs are written along their rows.  Values past n
+// (the padding up to ld) are written as zeros.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_convert_square_pre(const double* G, long gbs, int n, long ld,
+                                                            unsigned short* out, long obs, long lo,
+                                                            const unsigned* amax) {
+  typedef typename LpStore<KIND>::T T;
+  __shared__ double t[32][33];
+  const int b = blockIdx.z, r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const double* Gb = G + (long)b * gbs;
+  T* hi = reinterpret_cast<T*>(out + (long)b * obs);
+  T* hiT = hi + (long)n * ld;
+  const double sc = (KIND == LP_F16) ? f16_scale(*amax) : 1.0;
+  auto put = [&](T* base, long idx, double x) {
+    if constexpr (KIND == LP_F16) {
+      const double xs = x * sc;
+      const _Float16 h = (_Float16)(float)xs;
+      base[idx] = h;
+      base[idx + lo] = (_Float16)(float)((xs - (double)h) * 2048.0);
+    } else {
+      base[idx] = (T)(float)x;
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + ty + 8 * q, c = c0 + tx;
+    const double x = (r < n && c < n) ? Gb[(long)r * n + c] : 0.0;
+    t[ty + 8 * q][tx] = x;
+    if (r < n) put(hi, (long)r * ld + c, x);          // row r of G, column c < ld
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = c0 + ty + 8 * q, r = r0 + tx;       // row c of G^T, column r
+    if (c < n) put(hiT, (long)c * ld + r, t[tx][ty + 8 * q]);
+  }
+}
+
+// Column j of panel b -> row j of the pre-converted operand (one workgroup
+// per column): F16 first finds the column's largest entry for its scale.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_convert_panel_pre(const double* X, long xbs, int n, long ld,
+                                                           unsigned short* out, long obs, long lo, float* rs,
+                                                           long rs_bs) {
+  typedef typename LpStore<KIND>::T T;
+  __shared__ float red[4];
+  const int j = blockIdx.x, b = blockIdx.y;
+  const double* x = X + (long)b * xbs + (long)j * n;
+  T* o = reinterpret_cast<T*>(out + (long)b * obs) + (long)j * ld;
+  double sc = 1.0;
+  if constexpr (KIND == LP_F16) {
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) m = fmaxf(m, fabsf((float)x[i]));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    sc = f16_scale(__float_as_uint(m));
+    if (threadIdx.x == 0) rs[(long)b * rs_bs + j] = (float)sc;
+  }
+  for (int i = threadIdx.x; i < ld; i += 256) {
+    const double v = (i < n) ? x[i] : 0.0;
+    if constexpr (KIND == LP_F16) {
+      const double xs = v * sc;
+      const _Float16 h = (_Float16)(float)xs;
+      o[i] = h;
+      o[i + lo] = (_Float16)(float)((xs - (double)h) * 2048.0);
+    } else {
+      o[i] = (T)(float)v;
+    }
+  }
+}
+
 __global__ void k_amax_clear(unsigned* out, int n) {
   if ((int)threadIdx.x < n) out[threadIdx.x] = 0u;
 }
@@ -890,6 +1150,83 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
     long total = (long)batch * M * N;
     int blocks = (int)std::min<long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, st, g);
+    CTM_HIP(hipGetLastError());
+  }
+}
+
+void convert_square_pre(hipStream_t st, GemmType type, const double* G, long gbs, int n, int batch, void* out,
+                        long obs, long lo, const unsigned* amax) {
+  CTM_CHECK(type == GemmType::BF16 || (type == GemmType::F16 && amax), -1, "convert_square_pre: type");
+  const long ld = pre_ld(n);
+  const dim3 grid((unsigned)(ld / 32), (unsigned)(ld / 32), (unsigned)batch);
+  auto* o = static_cast<unsigned short*>(out);
+  if (type == GemmType::BF16)
+    hipLaunchKernelGGL(k_convert_square_pre<LP_BF16>, grid, dim3(256), 0, st, G, gbs, n, ld, o, obs, lo, amax);
+  else
+    hipLaunchKernelGGL(k_convert_square_pre<LP_F16>, grid, dim3(256), 0, st, G, gbs, n, ld, o, obs, lo, amax);
+  CTM_HIP(hipGetLastError());
+}
+
+void convert_panel_pre(hipStream_t st, GemmType type, const double* X, long xbs, int n, int k, int batch, void* out,
+                       long obs, long lo, float* rowscale, long rs_bs) {
+  CTM_CHECK(type == GemmType::BF16 || (type == GemmType::F16 && rowscale), -1, "convert_panel_pre: type");
+  const long ld = pre_ld(n);
+  const dim3 grid((unsigned)k, (unsigned)batch);
+  auto* o = static_cast<unsigned short*>(out);
+  if (type == GemmType::BF16)
+    hipLaunchKernelGGL(k_convert_panel_pre<LP_BF16>, grid, dim3(256), 0, st, X, xbs, n, ld, o, obs, lo, rowscale,
+                       rs_bs);
+  else
+    hipLaunchKernelGGL(k_convert_panel_pre<LP_F16>, grid, dim3(256), 0, st, X, xbs, n, ld, o, obs, lo, rowscale,
+                       rs_bs);
+  CTM_HIP(hipGetLastError());
+}
+
+void gemm_pre(hipStream_t st, GemmType type, int M, int N, int Kp, double alpha, const PreOperand& A,
+              const PreOperand& B, const OutOperand& C, int batch, const GemmWorkspace& ws) {
+  if (M <= 0 || N <= 0 || batch <= 0) return;
+  CTM_CHECK(type == GemmType::BF16 || type == GemmType::F16, -1, "gemm_pre: BF16 or F16 only");
+  CTM_CHECK(Kp % 32 == 0 && A.ld % 8 == 0 && B.ld % 8 == 0 && A.ld >= Kp && B.ld >= Kp, -1,
+            "gemm_pre: operand pitch");
+  CTM_CHECK(C.t0 == nullptr && C.t1 == nullptr && C.bo == nullptr, -1, "gemm_pre: strided output only");
+  const bool f16 = type == GemmType::F16;
+  CTM_CHECK(!f16 || ((A.amax || A.rowscale) && (B.amax || B.rowscale)), -1, "gemm_pre: F16 scales");
+  PArgs g{};
+  g.A = static_cast<const unsigned short*>(A.p);
+  g.B = static_cast<const unsigned short*>(B.p);
+  g.C = static_cast<double*>(C.p);
+  g.lda = A.ld; g.bsa = A.bs; g.loa = A.lo;
+  g.ldb = B.ld; g.bsb = B.bs; g.lob = B.lo;
+  g.sc0 = C.s0; g.sc1 = C.s1; g.bsc = C.bs;
+  g.M = M; g.N = N; g.Kp = Kp; g.alpha = alpha; g.batch = batch;
+  g.amaxA = A.amax; g.amaxB = B.amax;
+  g.rsA = A.rowscale; g.rsB = B.rowscale; g.rsa_bs = A.rs_bs; g.rsb_bs = B.rs_bs;
+  constexpr int BM = 128, BN = 64;
+  const long tiles = (long)ceil_div(M, BM) * ceil_div(N, BN);
+  // split K until about two workgroups per compute unit (no more than 8
+  // ways, at least 8 k-tiles each), if the workspace holds the partials
+  int splits = 1;
+  while (splits < 8 && tiles * batch * splits < 512 && Kp / (32 * 2 * splits) >= 8) splits *= 2;
+  if (splits > 1 && (ws.p == nullptr || ws.elems < (size_t)splits * batch * M * N)) splits = 1;
+  const int kchunk = ceil_div(ceil_div(Kp, 32), splits) * 32;
+  g.splits = ceil_div(Kp, kchunk);
+  g.kchunk = kchunk;
+  g.ws = ws.p;
+  const dim3 grid((unsigned)tiles, (unsigned)g.splits, (unsigned)batch);
+  if (f16)
+    hipLaunchKernelGGL((gemm_pre_kernel<LP_F16, BM, BN, 2>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_pre_kernel<LP_BF16, BM, BN, 2>), grid, dim3(256), 0, st, g);
+  CTM_HIP(hipGetLastError());
+  if (g.splits > 1) {
+    KArgs r{};
+    r.C = g.C;
+    r.sc0 = C.s0; r.sc1 = C.s1; r.bsc = C.bs;
+    r.M = M; r.N = N; r.batch = batch; r.beta = 0.0;
+    r.splits = g.splits; r.ws = ws.p;
+    const long total = (long)batch * M * N;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, st, r);
     CTM_HIP(hipGetLastError());
   }
 }

@@ -67,5 +67,46 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
 // *out = largest |entry| (FP32 bits) of an R x C operand over `batch` problems.
 void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, unsigned* out);
 
+// ---------------------------------------------------------------------------
+// Operands stored once in the reduced type (BF16, or split FP16 as a hi and a
+// lo plane), for products that read the same large operand many times (the
+// corners of the randomized SVD).  A pre-converted operand is `rows` rows of
+// ld values with k contiguous; ld is a multiple of 32 and the values past the
+// logical K are zero, so that every 32-wide k-tile is whole.
+//   BF16:  x -> bf16(float(x)).
+//   F16:   x * sc = hi + 2^-11 lo (hi, lo FP16), sc a power of two: one per
+//          operand (from `amax`, FP32 bits of its largest |entry|) or one per
+//          row (`rowscale`, FP32 powers of two), undone in the product.
+// ---------------------------------------------------------------------------
+struct PreOperand {
+  const void* p = nullptr;     // hi plane of problem 0 (2-byte values)
+  long ld = 0;                 // row pitch (multiple of 32)
+  long bs = 0;                 // batch stride (elements)
+  long lo = 0;                 // F16: lo plane at p + lo (elements)
+  const unsigned* amax = nullptr;   // F16: per-operand scale source
+  const float* rowscale = nullptr;  // F16: per-row scales [batch][rows] (overrides amax)
+  long rs_bs = 0;
+};
+
+// Padded row pitch of a pre-converted operand of logical width K.
+inline long pre_ld(long K) { return ((K + 31) / 32) * 32; }
+
+// out <- G_b (row-major n x n, batch stride gbs) and G_b^T, pre-converted:
+// problem b holds [G rows (n x ld)][G^T rows (n x ld)] at out + b * obs (hi
+// planes; F16 lo planes at + lo).  F16 scales by the power of two of *amax.
+void convert_square_pre(hipStream_t st, GemmType type, const double* G, long gbs, int n, int batch, void* out,
+                        long obs, long lo, const unsigned* amax);
+// out <- the k columns of the column-major n x k panels X_b (ld n, batch
+// stride xbs) as k pre-converted rows of pre_ld(n) values at out + b * obs.
+// F16: one power-of-two scale per column -> rowscale[b * rs_bs + j].
+void convert_panel_pre(hipStream_t st, GemmType type, const double* X, long xbs, int n, int k, int batch, void* out,
+                       long obs, long lo, float* rowscale, long rs_bs);
+
+// C = alpha * A B^T: A (M x Kp) and B (N x Kp) pre-converted (type BF16 or
+// F16), FP32 accumulation, C FP64 (any strides); Kp = the common row pitch's
+// logical width rounded to 32.
+void gemm_pre(hipStream_t st, GemmType type, int M, int N, int Kp, double alpha, const PreOperand& A,
+              const PreOperand& B, const OutOperand& C, int batch, const GemmWorkspace& ws);
+
 
 }  // namespace ctm

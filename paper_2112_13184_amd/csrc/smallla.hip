@@ -236,6 +236,194 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
 }
 
+// Blocked form of k_chol for k <= kCholBlockedMaxK: the same factorisation
+// (pivots, drops, shift, checks and output) with the lower triangle of G in
+// LDS (packed by columns) and the columns taken in panels of 16:
+//   A  wave 0 eliminates the panel's diagonal block (entries in registers,
+//      the pivot column broadcast through LDS: no workgroup barriers);
+//   B  every row below the block is eliminated by the panel's columns, one
+//      thread per row;
+//   C  the trailing matrix loses the panel's contribution, in 4 x 4 blocks of
+//      entries per thread.
+// Three barriers per panel instead of one per column.  The entries below a
+// pivot keep the unscaled values (a[i][j] after the updates of the earlier
+// columns), as in k_chol; the updates use a[i][j] a[l][j] / d_j.
+constexpr int kCholBlockedMaxK = 192;
+constexpr int kCholPanel = 16;
+constexpr bool kCholBlockedOn = false;
+
+__device__ __forceinline__ int pk_idx(int i, int j, int k) { return j * k - (j * (j - 1)) / 2 + (i - j); }
+
+__global__ __launch_bounds__(1024) void k_chol_blocked(const double* G, int k, int pass, int shifted, int check_id,
+                                                       double shift_scale, double drop_rel, double* Rout,
+                                                       double* mask, int* flag) {
+  constexpr int W = kCholPanel, KM = kCholBlockedMaxK;
+  __shared__ double a[KM * (KM + 1) / 2];
+  __shared__ double piv[KM];              // pivots; 1 / pivot (0 if dropped) in ipv
+  __shared__ double ipv[KM];
+  __shared__ double ls[W * W];            // the block's a[r][c] / d_c (0 for a dropped c)
+  __shared__ double colj[W];
+  __shared__ double red[16];
+  __shared__ unsigned char dropped[KM];
+  __shared__ int bad;
+  __shared__ double dmax_s;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long kk2 = (long)k * k;
+  const double* g = G + b * kk2;
+  if (tid == 0) {
+    bad = 0;
+    dmax_s = 0.0;
+  }
+  double tr = 0.0;
+  for (int i = tid; i < k; i += blockDim.x) tr += g[i + (long)i * k];
+  tr = block_reduce(tr, false, red);
+  const double sft = shifted ? shift_scale * tr : 0.0;
+  // lower triangle -> LDS (column j: rows j..k-1, contiguous in G)
+  double dev = 0.0;
+  for (int j = wave; j < k; j += 16) {
+    const double gl = g[j + (long)j * k];
+    for (int i = j + lane; i < k; i += 64) {
+      double v = g[i + (long)j * k];
+      if (check_id) {
+        const double gi = g[i + (long)i * k];
+        if (gi > 1e-3 && gl > 1e-3) dev = fmax(dev, fabs(v - (i == j ? 1.0 : 0.0)));
+      }
+      if (i == j) v += sft;
+      a[pk_idx(i, j, k)] = v;
+    }
+  }
+  if (check_id) {
+    dev = block_reduce(dev, true, red);
+    if (tid == 0 && !(dev <= 0.5)) bad = 2;
+  }
+  __syncthreads();
+  // wave 0's entries of a diagonal block: e = lane + 64 q over the 136
+  // lower entries (r >= c) of a 16 x 16 block, numbered row by row
+  int er[3], ec[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    int e = lane + 64 * q, r = 0;
+    while (e > r) {   // row r holds r + 1 entries
+      e -= r + 1;
+      ++r;
+    }
+    er[q] = r;
+    ec[q] = e;
+  }
+  for (int j0 = 0; j0 < k; j0 += W) {
+    const int w = min(W, k - j0), t0 = j0 + w, m = k - t0;
+    // ---- A: the diagonal block, wave 0 ----------------------------------
+    if (wave == 0) {
+      double v[3];
+      bool own[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        own[q] = (lane + 64 * q) < W * (W + 1) / 2 && er[q] < w;
+        v[q] = own[q] ? a[pk_idx(j0 + er[q], j0 + ec[q], k)] : 0.0;
+      }
+      double dmax = dmax_s;
+      for (int j = 0; j < w; ++j) {
+        // column j of the block (rows j..w-1) -> colj
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if (own[q] && ec[q] == j) colj[er[q]] = v[q];
+        __builtin_amdgcn_wave_barrier();
+        const double d = colj[j];
+        const bool drop = !(d > drop_rel * dmax) || !(d > 0.0) || !isfinite(d);
+        const double inv = drop ? 0.0 : 1.0 / d;
+        if (lane == 0) {
+          dropped[j0 + j] = drop ? 1 : 0;
+          piv[j0 + j] = d;
+          ipv[j0 + j] = inv;
+          if (!isfinite(d)) bad = 1;
+        }
+        if (!drop) {
+          dmax = fmax(dmax, d);
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            if (own[q] && ec[q] > j) v[q] -= colj[er[q]] * colj[ec[q]] * inv;
+        }
+        // the scaled column for the rows below the block
+        if (lane < W) ls[lane * W + j] = (lane > j && lane < w) ? colj[lane] * inv : 0.0;
+        __builtin_amdgcn_wave_barrier();
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if (own[q]) a[pk_idx(j0 + er[q], j0 + ec[q], k)] = v[q];
+      if (lane == 0) dmax_s = dmax;
+    }
+    __syncthreads();
+    if (m <= 0) break;
+    // ---- B: rows below the block, one per thread ------------------------
+    if (tid < m) {
+      const int i = t0 + tid;
+      double v[W];
+#pragma unroll
+      for (int jj = 0; jj < W; ++jj) v[jj] = (jj < w) ? a[pk_idx(i, j0 + jj, k)] : 0.0;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        if (j < w && !dropped[j0 + j]) {
+          const double x = v[j];
+#pragma unroll
+          for (int jj = j + 1; jj < W; ++jj) v[jj] -= x * ls[jj * W + j];
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < W; ++jj)
+        if (jj < w) a[pk_idx(i, j0 + jj, k)] = v[jj];
+    }
+    __syncthreads();
+    // ---- C: trailing matrix, 4 x 4 blocks (bi >= bl) ----------------------
+    const int nbk = (m + 3) / 4, nblk = nbk * (nbk + 1) / 2;
+    for (int t = tid; t < nblk; t += blockDim.x) {
+      int bi = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+      while (bi * (bi + 1) / 2 > t) --bi;
+      while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+      const int bl = t - bi * (bi + 1) / 2;
+      double acc[4][4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+      for (int j = 0; j < w; ++j) {
+        const double sj = ipv[j0 + j];                       // 0 for a dropped column
+        double ri[4], rl[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int i = t0 + 4 * bi + x, l = t0 + 4 * bl + x;
+          ri[x] = (i < k) ? a[pk_idx(i, j0 + j, k)] : 0.0;
+          rl[x] = (l < k) ? a[pk_idx(l, j0 + j, k)] * sj : 0.0;
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = fma(ri[x], rl[y], acc[x][y]);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const int i = t0 + 4 * bi + x, l = t0 + 4 * bl + y;
+          if (i < k && l <= i) a[pk_idx(i, l, k)] -= acc[x][y];
+        }
+    }
+    __syncthreads();
+  }
+  // R = L^T: R[l][c] = a[c][l] / sqrt(d_l) (c > l), sqrt(d_l) on the
+  // diagonal, zero rows for dropped l and zero below the diagonal
+  for (int l = tid; l < k; l += blockDim.x) piv[l] = dropped[l] ? 0.0 : sqrt(piv[l]);
+  __syncthreads();
+  double* Rb = Rout + b * kk2;
+  for (long e = tid; e < kk2; e += blockDim.x) {
+    const int c = (int)(e / k), l = (int)(e % k);            // R[l][c], column-major
+    double r = 0.0;
+    if (l <= c && !dropped[l]) r = (l == c) ? piv[l] : a[pk_idx(c, l, k)] / piv[l];
+    Rb[e] = r;
+  }
+  for (int j = tid; j < k; j += blockDim.x) mask[(long)b * k + j] = dropped[j] ? 0.0 : 1.0;
+  if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
+}
+
 // Rinv = U^-1 for the upper triangular U = L^T, one wave per column c.  U
 // equals the stored R except on the diagonal of dropped directions, where
 // R has zero rows and U a unit diagonal (mask 0).  Column c of U^-1 solves
@@ -377,11 +565,15 @@ __global__ void k_jacobi_mark_unconverged(const int* conv, int* fail, int batch)
   if (b < batch && !conv[b]) fail[b] = max(fail[b], kJacobiUnconverged);
 }
 
-__global__ void k_jacobi_sweep_end(double* off, int* conv, int* nsweep, int batch, double tol) {
+// Cyclic Jacobi converges quadratically: after a sweep whose rotated pairs
+// all had |ga| / sqrt(al be) <= stop, the next sweep's would be of order
+// stop^2, below the rotation threshold for the stops used here, so the
+// problem is done without running that (rotation-free) check sweep.
+__global__ void k_jacobi_sweep_end(double* off, int* conv, int* nsweep, int batch, double stop) {
   const int b = threadIdx.x;
   if (b < batch) {
     if (!conv[b]) ++nsweep[b];
-    if (off[b] <= tol) conv[b] = 1;
+    if (off[b] <= stop) conv[b] = 1;
     off[b] = 0.0;
   }
 }
@@ -408,13 +600,58 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
+// Rotation of the column pair (x, y) with accumulators (u, v), held by one
+// wave (rows lane + 64 t): rotate when |ga| > tol sqrt(al be); the angle
+// zeroing the inner product has tan(2 theta) = 2 ga / (be - al), and with
+// d = be - al, r = sqrt(d^2 + 4 ga^2), w = sqrt(2 r (r + |d|)) its cosine and
+// sine are (r + |d|) / w and 2 ga sgn(d) / w: two reciprocal square roots.
+// Returns |ga| / sqrt(al be) of a rotated pair, else 0 (uniform over the wave).
+template <int ROWS, bool VEC>
+__device__ __forceinline__ double jacobi_pair(double (&x)[ROWS], double (&y)[ROWS], double (&u)[ROWS],
+                                              double (&v)[ROWS], double tol) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) {
+    al += x[t] * x[t];
+    be += y[t] * y[t];
+    ga += x[t] * y[t];
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  const double ab = al * be, g2 = ga * ga;
+  if (!(g2 > tol * tol * ab)) return 0.0;
+  const double dd = be - al, ad = fabs(dd);
+  const double X = dd * dd + 4.0 * g2;
+  const double r = X * rsqrt_nr(X);
+  const double inv = rsqrt_nr(2.0 * r * (r + ad));
+  const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
+#pragma unroll
+  for (int t = 0; t < ROWS; ++t) {
+    const double xn = cs * x[t] - sn * y[t], yn = sn * x[t] + cs * y[t];
+    x[t] = xn;
+    y[t] = yn;
+    if (VEC) {
+      const double un = cs * u[t] - sn * v[t], vn = sn * u[t] + cs * v[t];
+      u[t] = un;
+      v[t] = vn;
+    }
+  }
+  return fabs(ga) * rsqrt_nr(ab);
+}
+
 // One tournament round over blocks: workgroup w of problem b orthogonalises
 // column pairs of its block pair (columns >= k are zero padding), one wave
 // per column pair of each inner step (launched with 64 * bs threads).  In
 // round 0 every block meets another one, so that round runs the full
-// tournament of the 2 bs columns (the pairs inside each block and across);
-// later rounds take only the bs^2 pairs across the two blocks, in bs steps
-// of bs disjoint pairs.  Each column pair is rotated once per sweep.
+// tournament of the 2 bs columns (the pairs inside each block and across),
+// all staged in LDS.  Later rounds take only the bs^2 pairs across the two
+// blocks, in bs steps of bs disjoint pairs: wave q pairs column q of the
+// first block, which it keeps in registers for the whole round, with the
+// columns of the second block in turn, so that a step moves only those
+// through LDS (the LDS traffic of a step bounds its time).  Each column pair
+// is rotated once per sweep.  off[b] receives the largest |ga| / sqrt(al be)
+// of the pairs rotated (positive doubles order like their bits).
 // VEC = false: singular values only (J is not touched).
 template <int ROWS, bool VEC = true>
 __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, double* J, int k, int nb, int bs,
@@ -434,10 +671,12 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
   const int m = 2 * bs;
   // the wave index is uniform: keep it (and the column arithmetic) scalar
   const int lane = threadIdx.x & 63, q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // wave q stages local columns q (block pa) and bs + q (block pb): all
-  // global loads first, then the LDS stores
+  const int gcol[2] = {pa * bs + q, pb * bs + q};
+  // wave q loads local columns q (block pa) and bs + q (block pb): all global
+  // loads first, then the LDS stores (column q of pa stays in registers after
+  // round 0)
+  double x[ROWS], u[ROWS];
   {
-    const int gcol[2] = {pa * bs + q, pb * bs + q};
     double va[2][ROWS], vj[2][ROWS];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -449,7 +688,12 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
         vj[h][t] = (VEC && ok) ? Jb[(long)gcol[h] * k + r] : 0.0;
       }
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int t = 0; t < ROWS; ++t) {
+      x[t] = va[0][t];
+      u[t] = vj[0][t];
+    }
+#pragma unroll
+    for (int h = (round == 0 ? 0 : 1); h < 2; ++h)
 #pragma unroll
       for (int t = 0; t < ROWS; ++t) {
         const int r = lane + 64 * t;
@@ -458,82 +702,76 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
       }
   }
   __syncthreads();
-  const int steps = (round == 0) ? m - 1 : bs;
   double offl = 0.0;
-  int cl = q;                                       // (q + st) mod bs
-  for (int st = 0; st < steps; ++st) {
-    int ci, cj;
-    if (round == 0) {
-      ci = circle(q, st, m);
-      cj = circle(m - 1 - q, st, m);
-    } else {
-      ci = q;
-      cj = bs + cl;
-      cl = (cl + 1 == bs) ? 0 : cl + 1;
-    }
-    double* ai = sA + ci * kJacobiLd + lane;
-    double* aj = sA + cj * kJacobiLd + lane;
-    double* ji = sJ + (VEC ? ci * kJacobiLd + lane : 0);
-    double* jj = sJ + (VEC ? cj * kJacobiLd + lane : 0);
-    // both columns and their rotation accumulators in registers (rows lane + 64 t)
-    double x[ROWS], y[ROWS], u[ROWS], v[ROWS];
-#pragma unroll
-    for (int t = 0; t < ROWS; ++t) {
-      x[t] = ai[64 * t];
-      y[t] = aj[64 * t];
-      u[t] = VEC ? ji[64 * t] : 0.0;
-      v[t] = VEC ? jj[64 * t] : 0.0;
-    }
-    double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-    for (int t = 0; t < ROWS; ++t) {
-      al += x[t] * x[t];
-      be += y[t] * y[t];
-      ga += x[t] * y[t];
-    }
-    al = wave_sum(al);
-    be = wave_sum(be);
-    ga = wave_sum(ga);
-    // rotate when |ga| > tol sqrt(al be); the angle zeroing the inner product
-    // has tan(2 theta) = 2 ga / (be - al), and with d = be - al,
-    // r = sqrt(d^2 + 4 ga^2), w = sqrt(2 r (r + |d|)) its cosine and sine are
-    // (r + |d|) / w and 2 ga sgn(d) / w: two reciprocal square roots
-    const double ab = al * be, g2 = ga * ga;
-    if (g2 > tol * tol * ab) {
-      offl = 1.0;                                   // some pair was rotated
-      const double dd = be - al, ad = fabs(dd);
-      const double X = dd * dd + 4.0 * g2;
-      const double r = X * rsqrt_nr(X);
-      const double inv = rsqrt_nr(2.0 * r * (r + ad));
-      const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
+  if (round == 0) {
+    for (int st = 0; st < m - 1; ++st) {
+      const int ci = circle(q, st, m), cj = circle(m - 1 - q, st, m);
+      double* ai = sA + ci * kJacobiLd + lane;
+      double* aj = sA + cj * kJacobiLd + lane;
+      double* ji = sJ + (VEC ? ci * kJacobiLd + lane : 0);
+      double* jj = sJ + (VEC ? cj * kJacobiLd + lane : 0);
+      double xa[ROWS], ya[ROWS], ua[ROWS], vb[ROWS];
 #pragma unroll
       for (int t = 0; t < ROWS; ++t) {
-        ai[64 * t] = cs * x[t] - sn * y[t];
-        aj[64 * t] = sn * x[t] + cs * y[t];
-        if (VEC) {
-          ji[64 * t] = cs * u[t] - sn * v[t];
-          jj[64 * t] = sn * u[t] + cs * v[t];
+        xa[t] = ai[64 * t];
+        ya[t] = aj[64 * t];
+        ua[t] = VEC ? ji[64 * t] : 0.0;
+        vb[t] = VEC ? jj[64 * t] : 0.0;
+      }
+      const double mu = jacobi_pair<ROWS, VEC>(xa, ya, ua, vb, tol);
+      if (mu > 0.0) {
+        offl = fmax(offl, mu);
+#pragma unroll
+        for (int t = 0; t < ROWS; ++t) {
+          ai[64 * t] = xa[t];
+          aj[64 * t] = ya[t];
+          if (VEC) {
+            ji[64 * t] = ua[t];
+            jj[64 * t] = vb[t];
+          }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    int cl = q;                                      // (q + st) mod bs
+    for (int st = 0; st < bs; ++st) {
+      double* aj = sA + (bs + cl) * kJacobiLd + lane;
+      double* jj = sJ + (VEC ? (bs + cl) * kJacobiLd + lane : 0);
+      cl = (cl + 1 == bs) ? 0 : cl + 1;
+      double y[ROWS], v[ROWS];
+#pragma unroll
+      for (int t = 0; t < ROWS; ++t) {
+        y[t] = aj[64 * t];
+        v[t] = VEC ? jj[64 * t] : 0.0;
+      }
+      const double mu = jacobi_pair<ROWS, VEC>(x, y, u, v, tol);
+      if (mu > 0.0) {
+        offl = fmax(offl, mu);
+#pragma unroll
+        for (int t = 0; t < ROWS; ++t) {
+          aj[64 * t] = y[t];
+          if (VEC) jj[64 * t] = v[t];
+        }
+      }
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int gc = (h == 0 ? pa : pb) * bs + q;
+    const int gc = gcol[h];
     if (gc < k) {
 #pragma unroll
       for (int t = 0; t < ROWS; ++t) {
         const int r = lane + 64 * t;
         if (r < k) {
-          Ab[(long)gc * k + r] = sA[(h * bs + q) * kJacobiLd + r];
-          if (VEC) Jb[(long)gc * k + r] = sJ[(h * bs + q) * kJacobiLd + r];
+          const bool reg = (h == 0 && round > 0);
+          Ab[(long)gc * k + r] = reg ? x[t] : sA[(h * bs + q) * kJacobiLd + r];
+          if (VEC) Jb[(long)gc * k + r] = reg ? u[t] : sJ[(h * bs + q) * kJacobiLd + r];
         }
       }
     }
   }
-  // 1 if this workgroup rotated a pair (some inner product was above the
-  // tolerance), else 0 -> off[b] (positive doubles order like their bits)
   __shared__ double red[kJacobiMaxBS];
   offl = wave_max(offl);
   if (lane == 0) red[q] = offl;
@@ -726,6 +964,12 @@ int rows_for(int k) {
 void launch_chol(hipStream_t st, int kb, int batch, const double* G, int k, int pass, int shifted, int check_id,
                  double shift_scale, double drop_rel, double* R, double* mask, int* flag) {
   const dim3 grid(batch), block(kCholThreads);
+  if (kCholBlockedOn && k <= kCholBlockedMaxK) {
+    hipLaunchKernelGGL(k_chol_blocked, grid, block, 0, st, G, k, pass, shifted, check_id, shift_scale, drop_rel, R,
+                       mask, flag);
+    CTM_HIP(hipGetLastError());
+    return;
+  }
   switch (kb) {
 #define CHOL_LAUNCH(KB) \
   case KB:              \
@@ -831,11 +1075,14 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
   int* nsweep = s.flag.as<int>() + 192;
   double* off = s.off.as<double>();
   hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, off, conv, nsweep);
-  // at most 14 sweeps; most problems reach the tolerance in 9 (the last one
-  // without rotations), a few in 10, so the convergence flags are read back
-  // after 9 sweeps and then after each further one (rounds of a converged
-  // problem return at once, so the schedule does not change the results)
-  const int max_sweeps = 14, first = 9, more = 1;
+  // at most 14 sweeps; most problems reach the stop in 8, a few in 9, so the
+  // convergence flags are read back after 8 sweeps and then after each
+  // further one (rounds of a converged problem return at once, so the
+  // schedule does not change the results).  Stop: the largest rotated
+  // |ga| / sqrt(al be) of a sweep at most 1e-10 (the next sweep's would be
+  // of order 1e-20).
+  const int max_sweeps = 14, first = 8, more = 1;
+  const double stop = 1e-10;
   auto sweeps = [&](int count) {
     for (int sw = 0; sw < count; ++sw) {
       for (int r = 0; r < nb - 1; ++r) {
@@ -848,7 +1095,7 @@ void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double*
             hipLaunchKernelGGL(k_jacobi_round<kRowsLarge>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, tol);
         }
       }
-      hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, tol);
+      hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, stop);
     }
     CTM_HIP(hipGetLastError());
   };
@@ -888,7 +1135,10 @@ void singular_values_batched(hipStream_t st, double* A, int k, int batch, double
   if (nb < 2) nb = 2;
   const double tol = 1e-15;
   hipLaunchKernelGGL(k_jacobi_init_values, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch);
-  const int max_sweeps = 30, first = 8;
+  // values only: their error is of order the square of the remaining
+  // |ga| / sqrt(al be), so a sweep whose rotations stayed below 1e-8 ends it
+  const int max_sweeps = 30, first = 7;
+  const double stop = 1e-8;
   auto sweeps = [&](int count) {
     for (int sw = 0; sw < count; ++sw) {
       for (int r = 0; r < nb - 1; ++r) {
@@ -906,7 +1156,7 @@ void singular_values_batched(hipStream_t st, double* A, int k, int batch, double
                                conv, tol);
         }
       }
-      hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, tol);
+      hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, stop);
     }
     CTM_HIP(hipGetLastError());
   };

@@ -139,6 +139,14 @@ void build_tables(Context& c) {
   upload_tables(c.braCt_c, vt);
 }
 
+// BF16 and split FP16 runs of the batched randomized-SVD path (k <= the
+// small-factorisation limit) keep the corners of a column's cuts and the
+// sketch panels in the reduced type and multiply them with gemm_pre.
+static bool uses_pre(const ctm_config& cfg, long kk) {
+  return (cfg.prec == CTM_BF16 || cfg.prec == CTM_F16_SPLIT) && cfg.rsvd_oversample >= 0 &&
+         cfg.projector_path == CTM_PATH_AUTO && kk <= kSmallLAMaxK;
+}
+
 struct Sizes {
   long n, nn, kk, chi, Db, y;
   size_t total_bytes;
@@ -174,6 +182,10 @@ Sizes sizes_of(const ctm_config& cfg, int R = 1) {
   e += kTableWords;                                                 // pointer tables
   e += observe_arena_elems(chi, DK, DB, d);                         // expectation values
   size_t b = 8 * e;
+  if (uses_pre(cfg, kk)) {                                          // reduced-type corners and panels
+    const size_t npl = (cfg.prec == CTM_F16_SPLIT) ? 2 : 1, ld = pre_ld(n);
+    b += 2 * npl * (4 * Lmax * 2 * n * ld + Lmax * kk * ld) + 4 * Lmax * kk;
+  }
   b += 4 * (size_t)(2 * cc * DB * DB + 2 * cc * DK * DK + 4 * DK * DK * d + 4 * DB * DB * d);  // tables
   b += 8 * (size_t)(4096 + 4096 * 64) + 4 * 4096;                   // Householder fallback buffers
   // per-context runtime overhead measured on MI355X (rocBLAS handle and its
@@ -370,6 +382,15 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
     case CTM_BF16: c.ctype = GemmType::BF16; break;
     case CTM_F16_SPLIT: c.ctype = GemmType::F16; break;
     default: c.ctype = GemmType::F64; break;
+  }
+  if (uses_pre(c.cfg, c.kk)) {
+    // planes per operand: hi (and lo for split FP16); the layout is the one
+    // rsvd_batched addresses: [role][plane][slot][G rows, G^T rows]
+    c.lp_npl = (c.ctype == GemmType::F16) ? 2 : 1;
+    c.lp_ld = pre_ld(c.n);
+    c.Glp.alloc(sizeof(uint16_t) * 4 * c.lp_npl * Lmax0 * 2 * c.n * c.lp_ld);
+    c.panlp.alloc(sizeof(uint16_t) * c.lp_npl * Lmax0 * c.kk * c.lp_ld);
+    c.panscale.alloc(sizeof(float) * Lmax0 * c.kk);
   }
   c.nact_cut.assign(Lmax, c.chi);
   c.cut_slot.assign(Lmax, -1);
@@ -703,8 +724,40 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
       operand_amax(c.st, rowmajor(Gp(role, s0), n, nn), n, n, nb, c.camax.as<unsigned>() + role);
     cam = c.camax.as<unsigned>();
   }
+  // BF16 / split FP16: every corner (and its transpose) converted once per
+  // column, every panel once per product
+  const bool pre = c.Glp.p != nullptr && (c.ctype == GemmType::BF16 || c.ctype == GemmType::F16);
+  const int npl = c.lp_npl;
+  CTM_CHECK(!pre || npl == (c.ctype == GemmType::F16 ? 2 : 1), -1, "reduced-type corner planes");
+  const long ld = c.lp_ld, Lslots = std::max(c.Lx, c.Ly) * (long)c.R;
+  const long gobs = 2L * n * ld, glo = Lslots * gobs, pobs = (long)kk * ld, plo = Lslots * pobs;
+  auto Glp = [&](int role, int slot) {
+    return c.Glp.as<uint16_t>() + (long)role * npl * glo + slot * gobs;
+  };
+  if (pre)
+    timed(c, PhaseTimer::SKETCH, 0.0, [&] {
+      for (int role = 0; role < 4; ++role)
+        convert_square_pre(c.st, c.ctype, Gp(role, s0), nn, n, nb, Glp(role, s0), gobs, glo, cam ? cam + role : nullptr);
+    });
+  // A (n x n, G or G^T) times the panel X (n x m, column-major) -> Yo
+  auto pre_prod = [&](int phase, int role, bool trans, const double* X, int m, const OutOperand& out) {
+    timed(c, phase, 2.0 * n * m * (double)n * nb, [&] {
+      float* rs = c.panscale.as<float>() + (long)s0 * kk;
+      uint16_t* xp = c.panlp.as<uint16_t>() + s0 * pobs;
+      convert_panel_pre(c.st, c.ctype, X, pk, n, m, nb, xp, pobs, plo, rs, kk);
+      PreOperand A, B;
+      A.p = Glp(role, s0) + (trans ? (long)n * ld : 0);
+      A.ld = ld; A.bs = gobs; A.lo = glo; A.amax = cam ? cam + role : nullptr;
+      B.p = xp; B.ld = ld; B.bs = pobs; B.lo = plo; B.rowscale = rs; B.rs_bs = kk;
+      gemm_pre(c.st, c.ctype, n, m, (int)ld, 1.0, A, B, out, nb, c.ws());
+    });
+  };
   // batched products with the four corners of every cut
   auto prod = [&](int role, bool trans, const double* X, double* Yo, int m) {
+    if (pre) {
+      pre_prod(PhaseTimer::SKETCH, role, trans, X, m, out_colmajor(Yo, n, pk));
+      return;
+    }
     Operand A = trans ? colmajor(Gp(role, s0), n, nn) : rowmajor(Gp(role, s0), n, nn);
     if (cam) A.amax = cam + role;
     mm(c, PhaseTimer::SKETCH, n, m, n, A, colmajor(X, n, pk), out_colmajor(Yo, n, pk), nb);
@@ -761,13 +814,18 @@ static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::arra
   // Pt = G_ll (G_lr V'), PT = W Ub'
   double* Pt = c.Pt.as<double>() + s0 * nc;
   double* PT = c.PT.as<double>() + s0 * nc;
-  Operand G2 = rowmajor(Gp(2, s0), n, nn), G3 = rowmajor(Gp(3, s0), n, nn);
-  if (cam) {
-    G2.amax = cam + 2;
-    G3.amax = cam + 3;
+  if (pre) {
+    pre_prod(PhaseTimer::EDGE, 2, false, V, chi, out_colmajor(t1, n, pk));
+    pre_prod(PhaseTimer::EDGE, 3, false, t1, chi, out_rowmajor(Pt, chi, nc));
+  } else {
+    Operand G2 = rowmajor(Gp(2, s0), n, nn), G3 = rowmajor(Gp(3, s0), n, nn);
+    if (cam) {
+      G2.amax = cam + 2;
+      G3.amax = cam + 3;
+    }
+    mm(c, PhaseTimer::EDGE, n, chi, n, G2, colmajor(V, n, pk), out_colmajor(t1, n, pk), nb);
+    mm(c, PhaseTimer::EDGE, n, chi, n, G3, colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nb);
   }
-  mm(c, PhaseTimer::EDGE, n, chi, n, G2, colmajor(V, n, pk), out_colmajor(t1, n, pk), nb);
-  mm(c, PhaseTimer::EDGE, n, chi, n, G3, colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nb);
   mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n, pk), colmajor(Ysv, kk, k2), out_rowmajor(PT, chi, nc), nb);
   // cuts whose Cholesky QR broke down
   int flags[192] = {0};
