@@ -65,6 +65,10 @@ struct AbsorbArgs {
   const long* ako;
   const long* abo;
   const long* go;
+  // largest |G| (FP32 bits, atomic max) of each problem: amaxp[b] (device
+  // table) or amax1 for a single problem; null: not computed
+  unsigned* const* amaxp;
+  unsigned* amax1;
   long n;
   int chi, DK, DB, d;
   int transposed;
@@ -111,6 +115,8 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(S::
   }
   const long npairs = (long)a.chi * a.chi;
   const long nwaves = (long)gridDim.x * kWaves;
+  unsigned* amax = a.amaxp ? a.amaxp[bz] : a.amax1;
+  double gmax = 0.0;
   for (long pr = (long)blockIdx.x * kWaves + w; pr < npairs; pr += nwaves) {
     const int cp = (int)(pr / a.chi), cn = (int)(pr % a.chi);
     const double* Xb = Xg + (long)cp * Db * a.n + (long)cn * Db;
@@ -179,9 +185,22 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(S::
               const long nxt = (long)cn * Db + (i / DK) * DB + rb, prv = (long)cp * Db + (i % DK) * DB + db;
               if (a.transposed) Gg[prv * a.n + nxt] = acc2[m2][nt][r];
               else Gg[nxt * a.n + prv] = acc2[m2][nt][r];
+              gmax = fmax(gmax, fabs(acc2[m2][nt][r]));
             }
           }
       }
+    }
+  }
+  if (amax) {
+    __shared__ float red[kWaves];
+    float m = (float)gmax;
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) red[w] = m;
+    __syncthreads();
+    if (tid == 0) {
+      float r = red[0];
+      for (int q = 1; q < kWaves; ++q) r = fmaxf(r, red[q]);
+      atomicMax(amax, __float_as_uint(r));
     }
   }
 }
@@ -199,19 +218,21 @@ bool absorb_fused_fits(int DK, int DB, int d) {
 }
 
 void absorb_fused(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G, int chi,
-                  int DK, int DB, int d, bool transposed) {
-  absorb_fused_batched(st, X, Ak, Ab, G, nullptr, nullptr, nullptr, nullptr, 1, chi, DK, DB, d, transposed);
+                  int DK, int DB, int d, bool transposed, unsigned* amax) {
+  absorb_fused_batched(st, X, Ak, Ab, G, nullptr, nullptr, nullptr, nullptr, 1, chi, DK, DB, d, transposed,
+                       nullptr, amax);
 }
 
 void absorb_fused_batched(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G,
                           const long* xo, const long* ako, const long* abo, const long* go, int batch, int chi,
-                          int DK, int DB, int d, bool transposed) {
+                          int DK, int DB, int d, bool transposed, unsigned* const* amaxp, unsigned* amax1) {
   CTM_CHECK(absorb_fused_fits(DK, DB, d), -1, "absorb_fused: block too large");
   CTM_CHECK(batch >= 1 && batch <= 65535, -1, "absorb_fused: batch out of range");
   CTM_CHECK(batch == 1 || (xo && ako && abo && go), -1, "absorb_fused: a batch needs per-problem offsets");
   AbsorbArgs a{};
   a.X = X; a.Ak = Ak; a.Ab = Ab; a.G = G;
   a.xo = xo; a.ako = ako; a.abo = abo; a.go = go;
+  a.amaxp = amaxp; a.amax1 = amax1;
   a.n = (long)chi * DK * DB;
   a.chi = chi; a.DK = DK; a.DB = DB; a.d = d;
   a.transposed = transposed ? 1 : 0;

@@ -166,6 +166,7 @@ struct Context {
   // BF16 / split FP16: the corners of a column's cuts and the sketch panels
   // stored once in the reduced type (gemm_pre operands); lp_ld = their row pitch
   DevBuf Glp, panlp, panscale;
+  DevBuf x2lp, x2rs;         // BF16 / split FP16 edge-corner product operands and their row scales
   long lp_ld = 0;
   int lp_npl = 0;
   GemmType ctype = GemmType::F64;   // arithmetic of the contraction GEMMs
@@ -246,7 +247,7 @@ void do_sweeps_group(Context& c, const int* max_sweeps, const double* tol, int* 
 void group_start(Context& c);
 void group_sweep(Context& c, double* host_delta);
 void replica_reset(Context& c, int r, const double* tensors_host, uint64_t seed);
-void enlarged_corner(Context& c, int s, int j, double* out);
+void enlarged_corner(Context& c, int s, int j, double* out, unsigned* amax = nullptr);
 // Reduced density matrices, normalised to trace 1, in the device buffer
 // rho_dev (d*d or d^4 doubles); copied to rho_host when it is not null.
 void rho_1site(Context& c, int site, double* rho_dev, double* rho_host);

@@ -707,17 +707,20 @@ struct PArgs {
   int batch;
 };
 
-template <int KIND, int BM, int BN, int WAVES_M>
-__global__ __launch_bounds__(256) void gemm_pre_kernel(PArgs g) {
+template <int KIND, int BM, int BN, int WAVES_M, int WAVES_N, int STAGES>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_pre_kernel(PArgs g) {
   typedef typename LpStore<KIND>::T T;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int BK = 32, LDK = BK + 8;
   constexpr int NP = (KIND == LP_F16) ? 2 : 1;
-  constexpr int WAVES_N = 4 / WAVES_M;
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int CA = BM * (BK / 8) / 256, CB = BN * (BK / 8) / 256;   // 16-byte chunks per thread
-  static_assert(TM >= 1 && TN >= 1 && CA >= 1 && CB >= 1, "tile");
+  // 16-byte chunks (eight k values of a row) per thread and k-tile; the last
+  // round of a count that is not a multiple of the threads is guarded
+  constexpr int NCA = BM * (BK / 8), NCB = BN * (BK / 8);
+  constexpr int CA = (NCA + NT - 1) / NT, CB = (NCB + NT - 1) / NT;
+  static_assert(TM >= 1 && TN >= 1 && WM % 16 == 0 && WN % 16 == 0, "tile");
   __shared__ __attribute__((aligned(16))) T As[2][NP][BM * LDK];
   __shared__ __attribute__((aligned(16))) T Bs[2][NP][BN * LDK];
 
@@ -736,37 +739,45 @@ __global__ __launch_bounds__(256) void gemm_pre_kernel(PArgs g) {
 
   long a_off[CA], b_off[CB];
   int a_lds[CA], b_lds[CB];
+  bool a_in[CA], b_in[CB];
 #pragma unroll
   for (int j = 0; j < CA; ++j) {
-    const int e = tid + 256 * j, r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
-    a_off[j] = (long)min(m0 + r, g.M - 1) * g.lda + kq;
-    a_lds[j] = r * LDK + kq;
+    const int e = tid + NT * j, r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
+    a_in[j] = (NCA % NT == 0) || e < NCA;
+    a_off[j] = (long)min(m0 + (a_in[j] ? r : 0), g.M - 1) * g.lda + kq;
+    a_lds[j] = a_in[j] ? r * LDK + kq : 0;
   }
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
-    const int e = tid + 256 * j, r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
-    b_off[j] = (long)min(n0 + r, g.N - 1) * g.ldb + kq;
-    b_lds[j] = r * LDK + kq;
+    const int e = tid + NT * j, r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
+    b_in[j] = (NCB % NT == 0) || e < NCB;
+    b_off[j] = (long)min(n0 + (b_in[j] ? r : 0), g.N - 1) * g.ldb + kq;
+    b_lds[j] = b_in[j] ? r * LDK + kq : 0;
   }
-  u4 ra[NP][CA], rb[NP][CB];
-  auto load_tile = [&](int k0) {
+  // STAGES k-tiles in flight in registers (the loads of tile t + STAGES are
+  // issued when tile t + 1 moves to LDS), so that a k-tile's global load
+  // latency is spread over several tiles of MFMAs
+  u4 ra[STAGES][NP][CA], rb[STAGES][NP][CB];
+  auto load_tile = [&](int st, int k0) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
       for (int j = 0; j < CA; ++j)
-        ra[p][j] = *reinterpret_cast<const u4*>(A + (p ? g.loa : 0) + a_off[j] + k0);
+        if (a_in[j]) ra[st][p][j] = *reinterpret_cast<const u4*>(A + (p ? g.loa : 0) + a_off[j] + k0);
 #pragma unroll
       for (int j = 0; j < CB; ++j)
-        rb[p][j] = *reinterpret_cast<const u4*>(B + (p ? g.lob : 0) + b_off[j] + k0);
+        if (b_in[j]) rb[st][p][j] = *reinterpret_cast<const u4*>(B + (p ? g.lob : 0) + b_off[j] + k0);
     }
   };
-  auto store_tile = [&](int buf) {
+  auto store_tile = [&](int st, int buf) {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
-      for (int j = 0; j < CA; ++j) *reinterpret_cast<u4*>(&As[buf][p][a_lds[j]]) = ra[p][j];
+      for (int j = 0; j < CA; ++j)
+        if (a_in[j]) *reinterpret_cast<u4*>(&As[buf][p][a_lds[j]]) = ra[st][p][j];
 #pragma unroll
-      for (int j = 0; j < CB; ++j) *reinterpret_cast<u4*>(&Bs[buf][p][b_lds[j]]) = rb[p][j];
+      for (int j = 0; j < CB; ++j)
+        if (b_in[j]) *reinterpret_cast<u4*>(&Bs[buf][p][b_lds[j]]) = rb[st][p][j];
     }
   };
 
@@ -820,17 +831,28 @@ __global__ __launch_bounds__(256) void gemm_pre_kernel(PArgs g) {
   };
 
   const int nk = (ke > kb) ? (ke - kb) / BK : 0;
+  // tile t sits in register stage t % STAGES until it moves to LDS buffer t % 2
   if (nk > 0) {
-    load_tile(kb);
-    store_tile(0);
+    load_tile(0, kb);
+    store_tile(0, 0);
   }
+#pragma unroll
+  for (int t = 1; t <= STAGES; ++t)
+    if (t < nk) load_tile(t % STAGES, kb + t * BK);
   __syncthreads();
-  for (int it = 0; it < nk; ++it) {
-    const int cur = it & 1;
-    if (it + 1 < nk) load_tile(kb + (it + 1) * BK);
-    compute(cur);
-    if (it + 1 < nk) store_tile(cur ^ 1);
-    __syncthreads();
+  for (int it0 = 0; it0 < nk; it0 += STAGES) {
+#pragma unroll
+    for (int u = 0; u < STAGES; ++u) {
+      const int it = it0 + u;
+      if (it < nk) {
+        compute(it & 1);
+        if (it + 1 < nk) {
+          store_tile((u + 1) % STAGES, (it + 1) & 1);
+          if (it + 1 + STAGES < nk) load_tile((u + 1) % STAGES, kb + (it + 1 + STAGES) * BK);
+        }
+        __syncthreads();
+      }
+    }
   }
 
   // scales: F16 A by one power of two (or one per row), B by one per row
@@ -941,33 +963,99 @@ __global__ __launch_bounds__(256) void k_convert_panel_pre(const double* X, long
   }
 }
 
+// Columns of a row-major R x C matrix (leading dimension lds, problem b at
+// src + b * sbs) -> rows of a pre-converted operand: output row c holds
+// column c (R values, zero-padded to pre_ld(R)).  32 columns per workgroup
+// through an LDS tile (R <= kColsPreMaxR); split FP16 scales each output row
+// by the power of two of its largest entry (rowscale[b * rs_bs + c]).
+constexpr int kColsPreMaxR = 320;
+template <int KIND>
+__global__ __launch_bounds__(256) void k_convert_cols_pre(const double* src, long lds, long sbs, int R, int C,
+                                                          long ld, unsigned short* out, long obs, long lo, float* rs,
+                                                          long rs_bs) {
+  typedef typename LpStore<KIND>::T T;
+  __shared__ double t[kColsPreMaxR][33];
+  const int b = blockIdx.y, c0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const double* S = src + (long)b * sbs;
+  for (int r = ty; r < R; r += 8) t[r][tx] = (c0 + tx < C) ? S[(long)r * lds + c0 + tx] : 0.0;
+  __syncthreads();
+  T* O = reinterpret_cast<T*>(out + (long)b * obs);
+  // each wave converts eight output rows (columns of the tile), one at a time
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int q = 0; q < 8; ++q) {
+    const int cc = w * 8 + q, c = c0 + cc;
+    if (c >= C) break;
+    double sc = 1.0;
+    if constexpr (KIND == LP_F16) {
+      float m = 0.0f;
+      for (int r = lane; r < R; r += 64) m = fmaxf(m, fabsf((float)t[r][cc]));
+      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+      sc = f16_scale(__float_as_uint(m));
+      if (lane == 0) rs[(long)b * rs_bs + c] = (float)sc;
+    }
+    T* o = O + (long)c * ld;
+    for (int r = lane; r < ld; r += 64) {
+      const double v = (r < R) ? t[r][cc] : 0.0;
+      if constexpr (KIND == LP_F16) {
+        const double xs = v * sc;
+        const _Float16 h = (_Float16)(float)xs;
+        o[r] = h;
+        o[r + lo] = (_Float16)(float)((xs - (double)h) * 2048.0);
+      } else {
+        o[r] = (T)(float)v;
+      }
+    }
+  }
+}
+
 __global__ void k_amax_clear(unsigned* out, int n) {
   if ((int)threadIdx.x < n) out[threadIdx.x] = 0u;
 }
 
 // out[which] = max(out[which], largest |x| over an R x Cn operand (FP32 bits;
-// non-negative floats order like their bit patterns).
+// non-negative floats order like their bit patterns).  Problem blockIdx.y.
+// Work items are pieces of 256 consecutive elements of a line along the
+// unit-stride index (columns when the rows are unit-stride, else rows), one
+// wave per item with four independent loads per lane; few workgroups, so
+// that the final atomics do not queue up.
 __global__ void k_operand_amax(const double* P, long s0, long s1, const int* t0, const int* t1, long bs,
-                               const long* off, int R, int Cn, int batch, unsigned* out, int which) {
+                               const long* off, int R, int Cn, unsigned* out, int which) {
   __shared__ float red[4];
-  const long per = (long)R * Cn, total = per * batch;
-  // walk the unit-stride index fastest so that the scan is coalesced
+  const double* Pb = batch_base(P, off, bs, (int)blockIdx.y);
   const bool rows_fast = (t0 == nullptr && s0 == 1);
+  const int inner = rows_fast ? R : Cn, outer = rows_fast ? Cn : R;
+  const int pieces = (inner + 255) / 256;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   float m = 0.0f;
-  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const long bb = e / per, rem = e % per;
-    const int i = rows_fast ? (int)(rem % R) : (int)(rem / Cn);
-    const int j = rows_fast ? (int)(rem / R) : (int)(rem % Cn);
-    m = fmaxf(m, fabsf((float)batch_base(P, off, bs, (int)bb)[off0(t0, s0, i) + off0(t1, s1, j)]));
+  const long items = (long)outer * pieces;
+  for (long it = blockIdx.x * 4 + w; it < items; it += gridDim.x * 4) {
+    const int o = (int)(it / pieces), q = (int)(it - (long)o * pieces);
+    const long base = rows_fast ? off0(t1, s1, o) : off0(t0, s0, o);
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = q * 256 + u * 64 + lane;
+      v[u] = (i < inner) ? fabsf((float)Pb[base + (rows_fast ? (long)i : off0(t1, s1, i))]) : 0.0f;
+    }
+    m = fmaxf(m, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
   }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  if (lane == 0) red[w] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
     float r = red[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmaxf(r, red[w]);
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = fmaxf(r, red[q]);
     atomicMax(out + which, __float_as_uint(r));
   }
+}
+
+// grid of k_operand_amax: about 256 workgroups in all (at least one per problem)
+dim3 amax_grid(int R, int Cn, bool rows_fast, int batch) {
+  const int outer = rows_fast ? Cn : R, inner = rows_fast ? R : Cn;
+  const long items = (long)outer * ((inner + 255) / 256);
+  const int per = (int)std::max<long>(1, std::min<long>((items + 3) / 4, 256 / std::max(1, batch)));
+  return dim3((unsigned)per, (unsigned)batch);
 }
 
 template <int KIND, int BM, int BN, int WAVES_M, bool TBL>
@@ -1050,10 +1138,16 @@ int choose_splits(long tiles, int K, long kRound = 1024) {
 
 }  // namespace
 
+void clear_words(hipStream_t st, unsigned* out, int n) {
+  CTM_CHECK(n >= 0 && n <= 64, -1, "clear_words: at most 64 words");
+  hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, out, n);
+  CTM_HIP(hipGetLastError());
+}
+
 void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, unsigned* out) {
   hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, out, 1);
-  hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, static_cast<const double*>(P.p), P.s0, P.s1, P.t0,
-                     P.t1, P.bs, P.bo, R, C, batch, out, 0);
+  hipLaunchKernelGGL(k_operand_amax, amax_grid(R, C, P.t0 == nullptr && P.s0 == 1, batch), dim3(256), 0, st,
+                     static_cast<const double*>(P.p), P.s0, P.s1, P.t0, P.t1, P.bs, P.bo, R, C, out, 0);
   CTM_HIP(hipGetLastError());
 }
 
@@ -1131,11 +1225,11 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
     // operands without a known maximum are scanned into the workspace words
     if (!A.amax || !B.amax) hipLaunchKernelGGL(k_amax_clear, dim3(1), dim3(64), 0, st, ws.amax, 2);
     if (!A.amax)
-      hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.A, g.sa0, g.sa1, g.ta0, g.ta1, g.bsa, g.oa,
-                         M, K, batch, ws.amax, 0);
+      hipLaunchKernelGGL(k_operand_amax, amax_grid(M, K, g.ta0 == nullptr && g.sa0 == 1, batch), dim3(256), 0, st,
+                         g.A, g.sa0, g.sa1, g.ta0, g.ta1, g.bsa, g.oa, M, K, ws.amax, 0);
     if (!B.amax)
-      hipLaunchKernelGGL(k_operand_amax, dim3(512), dim3(256), 0, st, g.B, g.sb0, g.sb1, g.tb0, g.tb1, g.bsb, g.ob,
-                         K, N, batch, ws.amax, 1);
+      hipLaunchKernelGGL(k_operand_amax, amax_grid(K, N, g.tb0 == nullptr && g.sb0 == 1, batch), dim3(256), 0, st,
+                         g.B, g.sb0, g.sb1, g.tb0, g.tb1, g.bsb, g.ob, K, N, ws.amax, 1);
     CTM_HIP(hipGetLastError());
     g.amaxA = A.amax ? A.amax : ws.amax;
     g.amaxB = B.amax ? B.amax : ws.amax + 1;
@@ -1182,6 +1276,22 @@ void convert_panel_pre(hipStream_t st, GemmType type, const double* X, long xbs,
   CTM_HIP(hipGetLastError());
 }
 
+void convert_cols_pre(hipStream_t st, GemmType type, const double* src, long lds, long sbs, int R, int C, int batch,
+                      void* out, long obs, long lo, float* rowscale, long rs_bs) {
+  CTM_CHECK(type == GemmType::BF16 || (type == GemmType::F16 && rowscale), -1, "convert_cols_pre: type");
+  CTM_CHECK(R >= 1 && R <= kColsPreMaxR, -1, "convert_cols_pre: at most 320 rows");
+  const long ld = pre_ld(R);
+  const dim3 grid((unsigned)ceil_div(C, 32), (unsigned)batch);
+  auto* o = static_cast<unsigned short*>(out);
+  if (type == GemmType::BF16)
+    hipLaunchKernelGGL(k_convert_cols_pre<LP_BF16>, grid, dim3(256), 0, st, src, lds, sbs, R, C, ld, o, obs, lo,
+                       rowscale, rs_bs);
+  else
+    hipLaunchKernelGGL(k_convert_cols_pre<LP_F16>, grid, dim3(256), 0, st, src, lds, sbs, R, C, ld, o, obs, lo,
+                       rowscale, rs_bs);
+  CTM_HIP(hipGetLastError());
+}
+
 void gemm_pre(hipStream_t st, GemmType type, int M, int N, int Kp, double alpha, const PreOperand& A,
               const PreOperand& B, const OutOperand& C, int batch, const GemmWorkspace& ws) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
@@ -1201,12 +1311,15 @@ void gemm_pre(hipStream_t st, GemmType type, int M, int N, int Kp, double alpha,
   g.M = M; g.N = N; g.Kp = Kp; g.alpha = alpha; g.batch = batch;
   g.amaxA = A.amax; g.amaxB = B.amax;
   g.rsA = A.rowscale; g.rsB = B.rowscale; g.rsa_bs = A.rs_bs; g.rsb_bs = B.rs_bs;
+  // 128 x 64 tiles, four waves (2 x 2)
   constexpr int BM = 128, BN = 64;
   const long tiles = (long)ceil_div(M, BM) * ceil_div(N, BN);
-  // split K until about two workgroups per compute unit (no more than 8
-  // ways, at least 8 k-tiles each), if the workspace holds the partials
+  // split K until about 256 workgroups per problem (no more than 8 ways, at
+  // least 8 k-tiles each), if the workspace holds the partials; the choice
+  // does not depend on the batch, so a problem gets the same arithmetic in
+  // any batch
   int splits = 1;
-  while (splits < 8 && tiles * batch * splits < 512 && Kp / (32 * 2 * splits) >= 8) splits *= 2;
+  while (splits < 8 && tiles * splits < 256 && Kp / (32 * 2 * splits) >= 8) splits *= 2;
   if (splits > 1 && (ws.p == nullptr || ws.elems < (size_t)splits * batch * M * N)) splits = 1;
   const int kchunk = ceil_div(ceil_div(Kp, 32), splits) * 32;
   g.splits = ceil_div(Kp, kchunk);
@@ -1214,9 +1327,9 @@ void gemm_pre(hipStream_t st, GemmType type, int M, int N, int Kp, double alpha,
   g.ws = ws.p;
   const dim3 grid((unsigned)tiles, (unsigned)g.splits, (unsigned)batch);
   if (f16)
-    hipLaunchKernelGGL((gemm_pre_kernel<LP_F16, BM, BN, 2>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_pre_kernel<LP_F16, BM, BN, 2, 2, 4>), grid, dim3(256), 0, st, g);
   else
-    hipLaunchKernelGGL((gemm_pre_kernel<LP_BF16, BM, BN, 2>), grid, dim3(256), 0, st, g);
+    hipLaunchKernelGGL((gemm_pre_kernel<LP_BF16, BM, BN, 2, 2, 4>), grid, dim3(256), 0, st, g);
   CTM_HIP(hipGetLastError());
   if (g.splits > 1) {
     KArgs r{};

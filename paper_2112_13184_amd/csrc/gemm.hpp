@@ -66,6 +66,8 @@ void gemm(hipStream_t st, GemmType type, int M, int N, int K, double alpha, cons
 
 // *out = largest |entry| (FP32 bits) of an R x C operand over `batch` problems.
 void operand_amax(hipStream_t st, const Operand& P, int R, int C, int batch, unsigned* out);
+// out[0 .. n) = 0 (n <= 64) by a kernel (no memset node in captured graphs).
+void clear_words(hipStream_t st, unsigned* out, int n);
 
 // ---------------------------------------------------------------------------
 // Operands stored once in the reduced type (BF16, or split FP16 as a hi and a
@@ -101,6 +103,13 @@ void convert_square_pre(hipStream_t st, GemmType type, const double* G, long gbs
 // F16: one power-of-two scale per column -> rowscale[b * rs_bs + j].
 void convert_panel_pre(hipStream_t st, GemmType type, const double* X, long xbs, int n, int k, int batch, void* out,
                        long obs, long lo, float* rowscale, long rs_bs);
+
+// out <- the C columns of the row-major R x C matrices src_b (leading
+// dimension lds, batch stride sbs) as C pre-converted rows of pre_ld(R)
+// values at out + b * obs (R <= 320).  F16: one power-of-two scale per
+// output row -> rowscale[b * rs_bs + c].
+void convert_cols_pre(hipStream_t st, GemmType type, const double* src, long lds, long sbs, int R, int C, int batch,
+                      void* out, long obs, long lo, float* rowscale, long rs_bs);
 
 // C = alpha * A B^T: A (M x Kp) and B (N x Kp) pre-converted (type BF16 or
 // F16), FP32 accumulation, C FP64 (any strides); Kp = the common row pitch's

@@ -236,194 +236,6 @@ __global__ __launch_bounds__(kCholThreads) void k_chol(const double* G, int k, i
   if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
 }
 
-// Blocked form of k_chol for k <= kCholBlockedMaxK: the same factorisation
-// (pivots, drops, shift, checks and output) with the lower triangle of G in
-// LDS (packed by columns) and the columns taken in panels of 16:
-//   A  wave 0 eliminates the panel's diagonal block (entries in registers,
-//      the pivot column broadcast through LDS: no workgroup barriers);
-//   B  every row below the block is eliminated by the panel's columns, one
-//      thread per row;
-//   C  the trailing matrix loses the panel's contribution, in 4 x 4 blocks of
-//      entries per thread.
-// Three barriers per panel instead of one per column.  The entries below a
-// pivot keep the unscaled values (a[i][j] after the updates of the earlier
-// columns), as in k_chol; the updates use a[i][j] a[l][j] / d_j.
-constexpr int kCholBlockedMaxK = 192;
-constexpr int kCholPanel = 16;
-constexpr bool kCholBlockedOn = false;
-
-__device__ __forceinline__ int pk_idx(int i, int j, int k) { return j * k - (j * (j - 1)) / 2 + (i - j); }
-
-__global__ __launch_bounds__(1024) void k_chol_blocked(const double* G, int k, int pass, int shifted, int check_id,
-                                                       double shift_scale, double drop_rel, double* Rout,
-                                                       double* mask, int* flag) {
-  constexpr int W = kCholPanel, KM = kCholBlockedMaxK;
-  __shared__ double a[KM * (KM + 1) / 2];
-  __shared__ double piv[KM];              // pivots; 1 / pivot (0 if dropped) in ipv
-  __shared__ double ipv[KM];
-  __shared__ double ls[W * W];            // the block's a[r][c] / d_c (0 for a dropped c)
-  __shared__ double colj[W];
-  __shared__ double red[16];
-  __shared__ unsigned char dropped[KM];
-  __shared__ int bad;
-  __shared__ double dmax_s;
-  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const long kk2 = (long)k * k;
-  const double* g = G + b * kk2;
-  if (tid == 0) {
-    bad = 0;
-    dmax_s = 0.0;
-  }
-  double tr = 0.0;
-  for (int i = tid; i < k; i += blockDim.x) tr += g[i + (long)i * k];
-  tr = block_reduce(tr, false, red);
-  const double sft = shifted ? shift_scale * tr : 0.0;
-  // lower triangle -> LDS (column j: rows j..k-1, contiguous in G)
-  double dev = 0.0;
-  for (int j = wave; j < k; j += 16) {
-    const double gl = g[j + (long)j * k];
-    for (int i = j + lane; i < k; i += 64) {
-      double v = g[i + (long)j * k];
-      if (check_id) {
-        const double gi = g[i + (long)i * k];
-        if (gi > 1e-3 && gl > 1e-3) dev = fmax(dev, fabs(v - (i == j ? 1.0 : 0.0)));
-      }
-      if (i == j) v += sft;
-      a[pk_idx(i, j, k)] = v;
-    }
-  }
-  if (check_id) {
-    dev = block_reduce(dev, true, red);
-    if (tid == 0 && !(dev <= 0.5)) bad = 2;
-  }
-  __syncthreads();
-  // wave 0's entries of a diagonal block: e = lane + 64 q over the 136
-  // lower entries (r >= c) of a 16 x 16 block, numbered row by row
-  int er[3], ec[3];
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    int e = lane + 64 * q, r = 0;
-    while (e > r) {   // row r holds r + 1 entries
-      e -= r + 1;
-      ++r;
-    }
-    er[q] = r;
-    ec[q] = e;
-  }
-  for (int j0 = 0; j0 < k; j0 += W) {
-    const int w = min(W, k - j0), t0 = j0 + w, m = k - t0;
-    // ---- A: the diagonal block, wave 0 ----------------------------------
-    if (wave == 0) {
-      double v[3];
-      bool own[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        own[q] = (lane + 64 * q) < W * (W + 1) / 2 && er[q] < w;
-        v[q] = own[q] ? a[pk_idx(j0 + er[q], j0 + ec[q], k)] : 0.0;
-      }
-      double dmax = dmax_s;
-      for (int j = 0; j < w; ++j) {
-        // column j of the block (rows j..w-1) -> colj
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          if (own[q] && ec[q] == j) colj[er[q]] = v[q];
-        __builtin_amdgcn_wave_barrier();
-        const double d = colj[j];
-        const bool drop = !(d > drop_rel * dmax) || !(d > 0.0) || !isfinite(d);
-        const double inv = drop ? 0.0 : 1.0 / d;
-        if (lane == 0) {
-          dropped[j0 + j] = drop ? 1 : 0;
-          piv[j0 + j] = d;
-          ipv[j0 + j] = inv;
-          if (!isfinite(d)) bad = 1;
-        }
-        if (!drop) {
-          dmax = fmax(dmax, d);
-#pragma unroll
-          for (int q = 0; q < 3; ++q)
-            if (own[q] && ec[q] > j) v[q] -= colj[er[q]] * colj[ec[q]] * inv;
-        }
-        // the scaled column for the rows below the block
-        if (lane < W) ls[lane * W + j] = (lane > j && lane < w) ? colj[lane] * inv : 0.0;
-        __builtin_amdgcn_wave_barrier();
-      }
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-        if (own[q]) a[pk_idx(j0 + er[q], j0 + ec[q], k)] = v[q];
-      if (lane == 0) dmax_s = dmax;
-    }
-    __syncthreads();
-    if (m <= 0) break;
-    // ---- B: rows below the block, one per thread ------------------------
-    if (tid < m) {
-      const int i = t0 + tid;
-      double v[W];
-#pragma unroll
-      for (int jj = 0; jj < W; ++jj) v[jj] = (jj < w) ? a[pk_idx(i, j0 + jj, k)] : 0.0;
-#pragma unroll
-      for (int j = 0; j < W; ++j) {
-        if (j < w && !dropped[j0 + j]) {
-          const double x = v[j];
-#pragma unroll
-          for (int jj = j + 1; jj < W; ++jj) v[jj] -= x * ls[jj * W + j];
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < W; ++jj)
-        if (jj < w) a[pk_idx(i, j0 + jj, k)] = v[jj];
-    }
-    __syncthreads();
-    // ---- C: trailing matrix, 4 x 4 blocks (bi >= bl) ----------------------
-    const int nbk = (m + 3) / 4, nblk = nbk * (nbk + 1) / 2;
-    for (int t = tid; t < nblk; t += blockDim.x) {
-      int bi = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-      while (bi * (bi + 1) / 2 > t) --bi;
-      while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-      const int bl = t - bi * (bi + 1) / 2;
-      double acc[4][4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-      for (int j = 0; j < w; ++j) {
-        const double sj = ipv[j0 + j];                       // 0 for a dropped column
-        double ri[4], rl[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int i = t0 + 4 * bi + x, l = t0 + 4 * bl + x;
-          ri[x] = (i < k) ? a[pk_idx(i, j0 + j, k)] : 0.0;
-          rl[x] = (l < k) ? a[pk_idx(l, j0 + j, k)] * sj : 0.0;
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = fma(ri[x], rl[y], acc[x][y]);
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          const int i = t0 + 4 * bi + x, l = t0 + 4 * bl + y;
-          if (i < k && l <= i) a[pk_idx(i, l, k)] -= acc[x][y];
-        }
-    }
-    __syncthreads();
-  }
-  // R = L^T: R[l][c] = a[c][l] / sqrt(d_l) (c > l), sqrt(d_l) on the
-  // diagonal, zero rows for dropped l and zero below the diagonal
-  for (int l = tid; l < k; l += blockDim.x) piv[l] = dropped[l] ? 0.0 : sqrt(piv[l]);
-  __syncthreads();
-  double* Rb = Rout + b * kk2;
-  for (long e = tid; e < kk2; e += blockDim.x) {
-    const int c = (int)(e / k), l = (int)(e % k);            // R[l][c], column-major
-    double r = 0.0;
-    if (l <= c && !dropped[l]) r = (l == c) ? piv[l] : a[pk_idx(c, l, k)] / piv[l];
-    Rb[e] = r;
-  }
-  for (int j = tid; j < k; j += blockDim.x) mask[(long)b * k + j] = dropped[j] ? 0.0 : 1.0;
-  if (tid == 0 && bad) flag[b] = max(flag[b], 10 * pass + bad);
-}
-
 // Rinv = U^-1 for the upper triangular U = L^T, one wave per column c.  U
 // equals the stored R except on the diagonal of dropped directions, where
 // R has zero rows and U a unit diagonal (mask 0).  Column c of U^-1 solves
@@ -964,12 +776,6 @@ int rows_for(int k) {
 void launch_chol(hipStream_t st, int kb, int batch, const double* G, int k, int pass, int shifted, int check_id,
                  double shift_scale, double drop_rel, double* R, double* mask, int* flag) {
   const dim3 grid(batch), block(kCholThreads);
-  if (kCholBlockedOn && k <= kCholBlockedMaxK) {
-    hipLaunchKernelGGL(k_chol_blocked, grid, block, 0, st, G, k, pass, shifted, check_id, shift_scale, drop_rel, R,
-                       mask, flag);
-    CTM_HIP(hipGetLastError());
-    return;
-  }
   switch (kb) {
 #define CHOL_LAUNCH(KB) \
   case KB:              \
@@ -1053,76 +859,107 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
   }
 }
 
-void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, long sstride,
-                double* Y) {
-  CTM_CHECK(k <= kSmallLAMaxK && batch <= s.batch_max, -1, "jacobi_svd: size");
-  int bs = jacobi_block(k);
-  int nb = (k + bs - 1) / bs;
+namespace {
+
+// Blocking of the Jacobi for order k: bs columns per block, nb blocks (even).
+void jacobi_blocks(int k, int& bs, int& nb) {
+  bs = jacobi_block(k);
+  nb = (k + bs - 1) / bs;
   if (nb & 1) ++nb;
   if (nb < 2) nb = 2;
+}
+
+// At most 14 sweeps; most problems reach the stop in 8, a few in 9, so the
+// convergence flags are read back after 8 sweeps and then after each
+// further one (rounds of a converged problem return at once, so the
+// schedule does not change the results).  Stop: the largest rotated
+// |ga| / sqrt(al be) of a sweep at most 1e-10 (the next sweep's would be of
+// order 1e-20).
+constexpr int kJacobiMaxSweepsVec = 14, kJacobiFirstRead = 8;
+constexpr double kJacobiTol = 1e-15, kJacobiStopVec = 1e-10;
+
+void jacobi_vec_sweeps(hipStream_t st, SmallLA& s, double* A, int k, int batch, int count) {
+  int bs, nb;
+  jacobi_blocks(k, bs, nb);
   double* J = s.J.as<double>();
-  const double tol = 1e-15;
+  int* conv = s.flag.as<int>() + 64;
+  int* nsweep = s.flag.as<int>() + 192;
+  double* off = s.off.as<double>();
+  for (int sw = 0; sw < count; ++sw) {
+    for (int r = 0; r < nb - 1; ++r) {
+      const dim3 grid(nb / 2, batch), block(64 * bs);
+      switch (rows_for(k)) {
+        case 1:
+        case 2:
+          hipLaunchKernelGGL(k_jacobi_round<2>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, kJacobiTol);
+          break;
+        case 3:
+          hipLaunchKernelGGL(k_jacobi_round<3>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, kJacobiTol);
+          break;
+        default:
+          hipLaunchKernelGGL(k_jacobi_round<kRowsLarge>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv,
+                             kJacobiTol);
+      }
+    }
+    hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, kJacobiStopVec);
+  }
+  CTM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void jacobi_svd_start(hipStream_t st, SmallLA& s, double* A, int k, int batch) {
+  CTM_CHECK(k <= kSmallLAMaxK && batch <= s.batch_max, -1, "jacobi_svd: size");
+  double* J = s.J.as<double>();
   if (k <= kJacobiOneWgMaxK) {
     // every sweep of a problem in one workgroup: one launch, no host reads
-    hipLaunchKernelGGL((k_jacobi_onewg<64, true>), dim3(batch), dim3(1024), 0, st, A, k, nullptr, J, tol, 14,
+    hipLaunchKernelGGL((k_jacobi_onewg<64, true>), dim3(batch), dim3(1024), 0, st, A, k, nullptr, J, kJacobiTol, 14,
                        s.flag.as<int>());
-    CTM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, sstride, Y);
     CTM_HIP(hipGetLastError());
     return;
   }
   int* conv = s.flag.as<int>() + 64;
   int* nsweep = s.flag.as<int>() + 192;
-  double* off = s.off.as<double>();
-  hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, off, conv, nsweep);
-  // at most 14 sweeps; most problems reach the stop in 8, a few in 9, so the
-  // convergence flags are read back after 8 sweeps and then after each
-  // further one (rounds of a converged problem return at once, so the
-  // schedule does not change the results).  Stop: the largest rotated
-  // |ga| / sqrt(al be) of a sweep at most 1e-10 (the next sweep's would be
-  // of order 1e-20).
-  const int max_sweeps = 14, first = 8, more = 1;
-  const double stop = 1e-10;
-  auto sweeps = [&](int count) {
-    for (int sw = 0; sw < count; ++sw) {
-      for (int r = 0; r < nb - 1; ++r) {
-        const dim3 grid(nb / 2, batch), block(64 * bs);
-        switch (rows_for(k)) {
-          case 1:
-          case 2: hipLaunchKernelGGL(k_jacobi_round<2>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, tol); break;
-          case 3: hipLaunchKernelGGL(k_jacobi_round<3>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, tol); break;
-          default:
-            hipLaunchKernelGGL(k_jacobi_round<kRowsLarge>, grid, block, 0, st, A, J, k, nb, bs, r, off, conv, tol);
-        }
-      }
-      hipLaunchKernelGGL(k_jacobi_sweep_end, dim3(1), dim3(64), 0, st, off, conv, nsweep, batch, stop);
+  hipLaunchKernelGGL(k_jacobi_init, dim3(64, batch), dim3(256), 0, st, J, k, s.off.as<double>(), conv, nsweep);
+  jacobi_vec_sweeps(st, s, A, k, batch, kJacobiFirstRead);
+}
+
+void jacobi_svd_finish(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, long sstride,
+                       double* Y) {
+  double* J = s.J.as<double>();
+  if (k > kJacobiOneWgMaxK) {
+    int* conv = s.flag.as<int>() + 64;
+    int* nsweep = s.flag.as<int>() + 192;
+    for (int done = kJacobiFirstRead; done < kJacobiMaxSweepsVec; ++done) {
+      int* hconv = s.hflag.as<int>();
+      CTM_HIP(hipMemcpyAsync(hconv, conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+      CTM_HIP(hipStreamSynchronize(st));
+      bool all = true;
+      for (int b = 0; b < batch; ++b) all = all && hconv[b] != 0;
+      if (all) break;
+      jacobi_vec_sweeps(st, s, A, k, batch, 1);
     }
-    CTM_HIP(hipGetLastError());
-  };
-  sweeps(first);
-  for (int done = first; done < max_sweeps; done += more) {
-    int* hconv = s.hflag.as<int>();
-    CTM_HIP(hipMemcpyAsync(hconv, conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
-    CTM_HIP(hipStreamSynchronize(st));
-    bool all = true;
-    for (int b = 0; b < batch; ++b) all = all && hconv[b] != 0;
-    if (all) break;
-    sweeps(std::min(more, max_sweeps - done));
+    hipLaunchKernelGGL(k_jacobi_mark_unconverged, dim3(1), dim3(64), 0, st, conv, s.flag.as<int>(), batch);
+    static const bool debug = getenv("CTM_DEBUG") != nullptr;
+    if (debug) {
+      int* hs = s.hflag.as<int>();
+      CTM_HIP(hipMemcpyAsync(hs, nsweep, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+      CTM_HIP(hipMemcpyAsync(hs + 64, conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
+      CTM_HIP(hipStreamSynchronize(st));
+      const int* h[2] = {hs, hs + 64};
+      fprintf(stderr, "[ctm] jacobi k=%d:", k);
+      for (int b = 0; b < batch; ++b) fprintf(stderr, " %d%s", h[0][b], h[1][b] ? "" : "(not converged)");
+      fprintf(stderr, "\n");
+    }
   }
-  hipLaunchKernelGGL(k_jacobi_mark_unconverged, dim3(1), dim3(64), 0, st, conv, s.flag.as<int>(), batch);
   hipLaunchKernelGGL(k_svd_finalize, dim3(batch), dim3(256), 0, st, A, J, k, X, S, sstride, Y);
   CTM_HIP(hipGetLastError());
-  static const bool debug = getenv("CTM_DEBUG") != nullptr;
-  if (debug) {
-    int* hs = s.hflag.as<int>();
-    CTM_HIP(hipMemcpyAsync(hs, nsweep, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
-    CTM_HIP(hipMemcpyAsync(hs + 64, conv, sizeof(int) * batch, hipMemcpyDeviceToHost, st));
-    CTM_HIP(hipStreamSynchronize(st));
-    const int* h[2] = {hs, hs + 64};
-    fprintf(stderr, "[ctm] jacobi k=%d:", k);
-    for (int b = 0; b < batch; ++b) fprintf(stderr, " %d%s", h[0][b], h[1][b] ? "" : "(not converged)");
-    fprintf(stderr, "\n");
-  }
+}
+
+void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, long sstride,
+                double* Y) {
+  jacobi_svd_start(st, s, A, k, batch);
+  jacobi_svd_finish(st, s, A, k, batch, X, S, sstride, Y);
 }
 
 

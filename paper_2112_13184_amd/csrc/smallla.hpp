@@ -43,6 +43,13 @@ void cholqr(hipStream_t st, SmallLA& s, double* Y, long ystride, int n, int k, i
 // col-major, batch strides k*k; S_b = S + b * sstride (sstride >= k).
 void jacobi_svd(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, long sstride,
                 double* Y);
+// The same in two calls, so that other work can be enqueued between them:
+// _start launches the sweeps that run before the first host read of the
+// convergence flags; _finish reads them (synchronising st), runs the sweeps
+// still needed and writes X, S, Y.
+void jacobi_svd_start(hipStream_t st, SmallLA& s, double* A, int k, int batch);
+void jacobi_svd_finish(hipStream_t st, SmallLA& s, double* A, int k, int batch, double* X, double* S, long sstride,
+                       double* Y);
 
 // Singular values (descending, m per problem at S + b * m) of `batch`
 // column-major m x m matrices at A + b * m * m, m <= kSvSmallMax, by one-sided

@@ -182,6 +182,10 @@ Sizes sizes_of(const ctm_config& cfg, int R = 1) {
   e += kTableWords;                                                 // pointer tables
   e += observe_arena_elems(chi, DK, DB, d);                         // expectation values
   size_t b = 8 * e;
+  if ((cfg.prec == CTM_BF16 || cfg.prec == CTM_F16_SPLIT) && chi <= 320) {   // edge-corner operands
+    const size_t npl = (cfg.prec == CTM_F16_SPLIT) ? 2 : 1;
+    b += 2 * npl * 2 * bch * n * pre_ld(chi) + 4 * 2 * bch * n;
+  }
   if (uses_pre(cfg, kk)) {                                          // reduced-type corners and panels
     const size_t npl = (cfg.prec == CTM_F16_SPLIT) ? 2 : 1, ld = pre_ld(n);
     b += 2 * npl * (4 * Lmax * 2 * n * ld + Lmax * kk * ld) + 4 * Lmax * kk;
@@ -357,6 +361,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.Svals.alloc(sizeof(double) * std::max(c.kk, c.n) * Lmax0);
   c.wvec.alloc(sizeof(double) * c.chi * Lmax0);
   if (c.kk <= kSmallLAMaxK && c.cfg.rsvd_oversample >= 0) smallla_alloc(c.sla, c.kk, Lmax0, c.n);
+
   c.keff.alloc(sizeof(int) * 64);
   c.badflag.alloc(sizeof(int) * c.R);   // one NaN / Inf flag per replica
   CTM_HIP(hipMemset(c.badflag.p, 0, sizeof(int) * c.R));
@@ -376,6 +381,7 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
   c.gws_elems = (size_t)8 * c.n * std::max(c.kk, c.chi) * c.R;
   c.gws.alloc(sizeof(double) * c.gws_elems);
   c.amax.alloc(sizeof(unsigned) * 2);
+
   c.camax.alloc(sizeof(unsigned) * 4);
   switch (cfg.prec) {
     case CTM_F32: c.ctype = GemmType::F32; break;
@@ -391,6 +397,13 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
     c.Glp.alloc(sizeof(uint16_t) * 4 * c.lp_npl * Lmax0 * 2 * c.n * c.lp_ld);
     c.panlp.alloc(sizeof(uint16_t) * c.lp_npl * Lmax0 * c.kk * c.lp_ld);
     c.panscale.alloc(sizeof(float) * Lmax0 * c.kk);
+  }
+  if ((c.ctype == GemmType::BF16 || c.ctype == GemmType::F16) && c.chi <= 320) {
+    // the edge-corner products' operands (rows of Tp, columns of X1), per corner of a chunk
+    const int npl = (c.ctype == GemmType::F16) ? 2 : 1;
+    c.lp_npl = npl;
+    c.x2lp.alloc(sizeof(uint16_t) * 2 * npl * c.bchunk * c.n * pre_ld(c.chi));
+    c.x2rs.alloc(sizeof(float) * 2 * c.bchunk * c.n);
   }
   c.nact_cut.assign(Lmax, c.chi);
   c.cut_slot.assign(Lmax, -1);
@@ -415,14 +428,16 @@ static void mm(Context& c, int phase, int M, int N, int K, const Operand& A, con
   });
 }
 
+// amax (fused kernel only, nullable): receives the largest |out| (FP32 bits).
 static void absorb(Context& c, const double* X, const double* Ak, const double* Ab, double* out,
-                   bool transposed) {
+                   bool transposed, unsigned* amax = nullptr) {
   const int chi = c.chi, DK = c.DK, DB = c.DB, d = c.d;
   // the fused kernel (FP64 MFMA, intermediate in LDS) serves every precision:
   // after fusion the absorption is a small share of the sweep
   if (absorb_fused_fits(DK, DB, d)) {
     const double flops = 2.0 * chi * chi * (double)DB * DB * DK * DK * d * (DK * DK + DB * DB);
-    timed(c, PhaseTimer::ABSORB, flops, [&] { absorb_fused(c.st, X, Ak, Ab, out, chi, DK, DB, d, transposed); });
+    timed(c, PhaseTimer::ABSORB, flops,
+          [&] { absorb_fused(c.st, X, Ak, Ab, out, chi, DK, DB, d, transposed, amax); });
     return;
   }
   Operand A{};
@@ -494,17 +509,43 @@ static OutOperand off_out_colmajor(double* base, const uint64_t* d, size_t i, lo
   return o;
 }
 
-// Enlarged corner j of site s: G[(cn, o_n)][(cp, o_p)] (n x n, row-major).
-void enlarged_corner(Context& c, int s, int j, double* out) {
+// X2_i = Tp_i X1_i (n x chi times chi x n, row-major) for m corners, in BF16
+// or split FP16 from operands converted once per product: the rows of Tp and
+// the columns of X1 become pre-converted rows (gemm_pre), so that the
+// product's short K (chi) costs no conversion work per output tile.
+static void x2_pre(Context& c, const std::vector<const double*>& Tp, const double* X1, long xn, double* X2, long nn) {
+  const int chi = c.chi, n = c.n, m = (int)Tp.size();
+  const long ldc = pre_ld(chi), obs = (long)n * ldc, lo = (long)c.bchunk * obs;
+  uint16_t* Ap = c.x2lp.as<uint16_t>();
+  uint16_t* Bp = Ap + (long)c.lp_npl * lo;
+  float* rsA = c.x2rs.as<float>();
+  float* rsB = rsA + (long)c.bchunk * n;
+  timed(c, PhaseTimer::EDGE, 2.0 * n * (double)n * chi * m, [&] {
+    for (int i = 0; i < m; ++i)   // row r of Tp_i (chi values) -> row r of A_i
+      convert_panel_pre(c.st, c.ctype, Tp[i], 0, chi, n, 1, Ap + i * obs, obs, lo, rsA + (long)i * n, n);
+    convert_cols_pre(c.st, c.ctype, X1, n, xn, chi, n, m, Bp, obs, lo, rsB, n);
+    PreOperand A, B;
+    A.p = Ap; A.ld = ldc; A.bs = obs; A.lo = lo; A.rowscale = rsA; A.rs_bs = n;
+    B.p = Bp; B.ld = ldc; B.bs = obs; B.lo = lo; B.rowscale = rsB; B.rs_bs = n;
+    gemm_pre(c.st, c.ctype, n, n, (int)ldc, 1.0, A, B, out_rowmajor(X2, n, nn), m, c.ws());
+  });
+}
+
+// Enlarged corner j of site s: G[(cn, o_n)][(cp, o_p)] (n x n, row-major);
+// amax (fused absorption only, nullable) receives its largest |entry|.
+void enlarged_corner(Context& c, int s, int j, double* out, unsigned* amax) {
   const int chi = c.chi;
   const long n = c.n;
   // X1[tp][(cn, i_n)] = sum_t C[t][tp] Tn[t][(cn, i_n)]
   mm(c, PhaseTimer::OTHER, chi, (int)n, chi, colmajor(c.C(s, j), chi), rowmajor(c.Ta(s, j), n),
      out_rowmajor(c.X1.p, n));
   // X2[(cp, i_p)][(cn, i_n)] = sum_tp Tp[(cp, i_p)][tp] X1[tp][..]
-  mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, rowmajor(c.Tb(s, (j + 3) % 4), chi), rowmajor(c.X1.p, n),
-     out_rowmajor(c.X2.p, n));
-  absorb(c, c.X2.as<double>(), c.Ak(j, s), c.Ab(j, s), out, false);
+  if (c.x2lp.p)
+    x2_pre(c, {c.Tb(s, (j + 3) % 4)}, c.X1.as<double>(), (long)chi * n, c.X2.as<double>(), n * n);
+  else
+    mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, rowmajor(c.Tb(s, (j + 3) % 4), chi), rowmajor(c.X1.p, n),
+       out_rowmajor(c.X2.p, n));
+  absorb(c, c.X2.as<double>(), c.Ak(j, s), c.Ab(j, s), out, false, amax);
 }
 
 // Enlarged corners of several (site, corner, output) jobs: the same products
@@ -513,13 +554,14 @@ void enlarged_corner(Context& c, int s, int j, double* out) {
 struct CornerJob {
   int s, j;
   double* out;
+  unsigned* amax = nullptr;   // largest |entry| (FP32 bits, atomic max), fused absorption only
 };
 
 void enlarged_corners(Context& c, const std::vector<CornerJob>& jobs) {
   const int chi = c.chi;
   const long n = c.n, nn = n * n, xn = (long)chi * n;
   if (c.bchunk <= 1 || jobs.size() <= 1 || !absorb_fused_fits(c.DK, c.DB, c.d)) {
-    for (const auto& jb : jobs) enlarged_corner(c, jb.s, jb.j, jb.out);
+    for (const auto& jb : jobs) enlarged_corner(c, jb.s, jb.j, jb.out, jb.amax);
     return;
   }
   const double* envC = c.envC.as<double>();
@@ -547,16 +589,28 @@ void enlarged_corners(Context& c, const std::vector<CornerJob>& jobs) {
     for (int i = 0; i < m; ++i) t.add_off(c.Ab(jb[i].j, jb[i].s), Abra);
     const size_t tG = t.w.size();
     for (int i = 0; i < m; ++i) t.add_off(jb[i].out, Gall);
+    const size_t tM = t.w.size();
+    bool with_amax = false;
+    for (int i = 0; i < m; ++i) {
+      t.add(jb[i].amax);
+      with_amax |= jb[i].amax != nullptr;
+    }
     const uint64_t* d = upload(c, t);
     mm(c, PhaseTimer::OTHER, chi, (int)n, chi, off_colmajor(envC, d, tC, chi), off_rowmajor(envTa, d, tTa, n),
        out_rowmajor(c.X1.p, n, xn), m);
-    mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, off_rowmajor(envTb, d, tTb, chi), rowmajor(c.X1.p, n, xn),
-       out_rowmajor(X2, n, nn), m);
+    if (c.x2lp.p) {
+      std::vector<const double*> Tp(m);
+      for (int i = 0; i < m; ++i) Tp[i] = c.Tb(jb[i].s, (jb[i].j + 3) % 4);
+      x2_pre(c, Tp, c.X1.as<double>(), xn, X2, nn);
+    } else {
+      mm(c, PhaseTimer::EDGE, (int)n, (int)n, chi, off_rowmajor(envTb, d, tTb, chi), rowmajor(c.X1.p, n, xn),
+         out_rowmajor(X2, n, nn), m);
+    }
     const int DK = c.DK, DB = c.DB, dd = c.d;
     const double flops = 2.0 * chi * chi * (double)DB * DB * DK * DK * dd * (DK * DK + DB * DB) * m;
     timed(c, PhaseTimer::ABSORB, flops, [&] {
       absorb_fused_batched(c.st, X2, Aket, Abra, Gall, offs_at(d, tX), offs_at(d, tAk), offs_at(d, tAb),
-                           offs_at(d, tG), m, chi, DK, DB, dd, false);
+                           offs_at(d, tG), m, chi, DK, DB, dd, false, with_amax ? ptrs_at<unsigned>(d, tM) : nullptr);
     });
   }
 }
@@ -683,178 +737,239 @@ void cut_projectors(Context& c, int rot, int r, int x, int y, int slot) {
   mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n), colmajor(Us, kk), out_rowmajor(PT, chi));
 }
 
-// Randomized-SVD projectors of cuts y0 .. y0+nb-1 of column x, batched: the
-// cut y0+b works in slot s0+b of every workspace and writes Pt / PT slot
-// s0+b.  Orthonormalisation by shifted Cholesky QR, the final small SVD by
-// block one-sided Jacobi.  Returns false (outputs undefined) for the cuts
-// whose Cholesky factorisation was not numerically positive definite; those
-// are recomputed with Householder QR by the caller.
-static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::array<int, 2>>& cuts, int s0,
-                         std::vector<int>& failed) {
-  const int nb = (int)cuts.size();
-  const int chi = c.chi, n = c.n, kk = c.kk;
-  const long nn = (long)n * n, pk = (long)n * kk, k2 = (long)kk * kk, nc = (long)n * chi;
-  auto Gp = [&](int role, int slot) { return c.G[role].as<double>() + slot * nn; };
-  auto pan = [&](int i, int slot) { return c.pan[i].as<double>() + slot * pk; };
-  std::vector<int> kcap(nb);
-  std::vector<CornerJob> jobs;
-  std::vector<uint64_t> seeds(nb), sids(nb);
-  for (int b = 0; b < nb; ++b) {
-    const int r = cuts[b][0], y = cuts[b][1], slot = s0 + b, o = r * c.N;
-    const int sites[4] = {o + view_site(c, rot, x, y), o + view_site(c, rot, x + 1, y),
-                          o + view_site(c, rot, x + 1, y - 1), o + view_site(c, rot, x, y - 1)};
-    kcap[b] = chi;
-    for (int q = 0; q < 4; ++q) {
-      const int j = (q + rot) % 4, s = sites[q];
-      kcap[b] = std::min(kcap[b], c.tdim[s][j][1] * c.Db);
-      kcap[b] = std::min(kcap[b], c.tdim[s][(j + 3) % 4][0] * c.Db);
-      jobs.push_back({s, j, Gp(q, slot)});   // roles: 0 UL, 1 UR, 2 LR, 3 LL
-    }
-    seeds[b] = c.seeds[r];
-    sids[b] = stream_id(c.rmoves[r], x, y);
+// Randomized-SVD projectors of the cuts of column x, batched: cut b works in
+// slot s0+b of every workspace and writes Pt / PT slot s0+b.  The enlarged
+// corners of all cuts are formed first (prepare); the rest runs on a range of
+// the cuts, in stages that only enqueue work except for the host reads of
+// stage two (the Jacobi convergence flags and the failure flags).
+// Orthonormalisation by shifted Cholesky QR, the final small SVD by block
+// one-sided Jacobi.  Cuts whose Cholesky factorisation was not numerically
+// positive definite come back in `failed` (outputs undefined); the caller
+// recomputes them with Householder QR.
+struct RsvdColumn {
+  Context& c;
+  int rot, x, s0, nb;
+  const std::vector<std::array<int, 2>>& cuts;
+  int chi, n, kk;
+  long nn, pk, k2, nc;
+  std::vector<int> kcap;
+  std::vector<uint64_t> seeds, sids;
+  const unsigned* cam = nullptr;   // split FP16: per-role largest corner entry (whole column)
+  bool pre = false;                // reduced-type corner and panel operands
+  int npl = 1;
+  long ld = 0, gobs = 0, glo = 0, pobs = 0, plo = 0;
+
+  RsvdColumn(Context& cc, int rot_, int x_, const std::vector<std::array<int, 2>>& cuts_, int s0_)
+      : c(cc), rot(rot_), x(x_), s0(s0_), nb((int)cuts_.size()), cuts(cuts_), chi(cc.chi), n(cc.n), kk(cc.kk) {
+    nn = (long)n * n; pk = (long)n * kk; k2 = (long)kk * kk; nc = (long)n * chi;
   }
-  enlarged_corners(c, jobs);
-  timed(c, PhaseTimer::OTHER, 0.0, [&] {
-    omega_fill_batched(c.st, pan(1, s0), pk, nb, n, c.Db, kk, seeds.data(), sids.data());
-  });
-  // split FP16: each corner role's largest entry, scanned once for the column
-  const unsigned* cam = nullptr;
-  if (c.ctype == GemmType::F16) {
-    for (int role = 0; role < 4; ++role)
-      operand_amax(c.st, rowmajor(Gp(role, s0), n, nn), n, n, nb, c.camax.as<unsigned>() + role);
-    cam = c.camax.as<unsigned>();
-  }
-  // BF16 / split FP16: every corner (and its transpose) converted once per
-  // column, every panel once per product
-  const bool pre = c.Glp.p != nullptr && (c.ctype == GemmType::BF16 || c.ctype == GemmType::F16);
-  const int npl = c.lp_npl;
-  CTM_CHECK(!pre || npl == (c.ctype == GemmType::F16 ? 2 : 1), -1, "reduced-type corner planes");
-  const long ld = c.lp_ld, Lslots = std::max(c.Lx, c.Ly) * (long)c.R;
-  const long gobs = 2L * n * ld, glo = Lslots * gobs, pobs = (long)kk * ld, plo = Lslots * pobs;
-  auto Glp = [&](int role, int slot) {
+  double* Gp(int role, int slot) const { return c.G[role].as<double>() + slot * nn; }
+  double* pan(int i, int slot) const { return c.pan[i].as<double>() + slot * pk; }
+  uint16_t* Glp(int role, int slot) const {
     return c.Glp.as<uint16_t>() + (long)role * npl * glo + slot * gobs;
-  };
-  if (pre)
-    timed(c, PhaseTimer::SKETCH, 0.0, [&] {
-      for (int role = 0; role < 4; ++role)
-        convert_square_pre(c.st, c.ctype, Gp(role, s0), nn, n, nb, Glp(role, s0), gobs, glo, cam ? cam + role : nullptr);
-    });
-  // A (n x n, G or G^T) times the panel X (n x m, column-major) -> Yo
-  auto pre_prod = [&](int phase, int role, bool trans, const double* X, int m, const OutOperand& out) {
-    timed(c, phase, 2.0 * n * m * (double)n * nb, [&] {
-      float* rs = c.panscale.as<float>() + (long)s0 * kk;
-      uint16_t* xp = c.panlp.as<uint16_t>() + s0 * pobs;
-      convert_panel_pre(c.st, c.ctype, X, pk, n, m, nb, xp, pobs, plo, rs, kk);
+  }
+
+  // Enlarged corners, sketch seeds and operand scales of every cut (c.st).
+  void prepare() {
+    kcap.assign(nb, chi);
+    seeds.assign(nb, 0);
+    sids.assign(nb, 0);
+    std::vector<CornerJob> jobs;
+    // split FP16: each corner role's largest entry over the column, from the
+    // absorption that forms the corners (or a scan when it is not fused)
+    const bool f16 = c.ctype == GemmType::F16;
+    const bool fused = absorb_fused_fits(c.DK, c.DB, c.d);
+    unsigned* camax = c.camax.as<unsigned>();
+    if (f16 && fused) clear_words(c.st, camax, 4);
+    for (int b = 0; b < nb; ++b) {
+      const int r = cuts[b][0], y = cuts[b][1], slot = s0 + b, o = r * c.N;
+      const int sites[4] = {o + view_site(c, rot, x, y), o + view_site(c, rot, x + 1, y),
+                            o + view_site(c, rot, x + 1, y - 1), o + view_site(c, rot, x, y - 1)};
+      for (int q = 0; q < 4; ++q) {
+        const int j = (q + rot) % 4, s = sites[q];
+        kcap[b] = std::min(kcap[b], c.tdim[s][j][1] * c.Db);
+        kcap[b] = std::min(kcap[b], c.tdim[s][(j + 3) % 4][0] * c.Db);
+        jobs.push_back({s, j, Gp(q, slot), (f16 && fused) ? camax + q : nullptr});   // roles: 0 UL, 1 UR, 2 LR, 3 LL
+      }
+      seeds[b] = c.seeds[r];
+      sids[b] = stream_id(c.rmoves[r], x, y);
+    }
+    enlarged_corners(c, jobs);
+    if (f16) {
+      if (!fused)
+        for (int role = 0; role < 4; ++role)
+          operand_amax(c.st, rowmajor(Gp(role, s0), n, nn), n, n, nb, camax + role);
+      cam = camax;
+    }
+    // BF16 / split FP16: every corner (and its transpose) converted once per
+    // column, every panel once per product
+    pre = c.Glp.p != nullptr && (c.ctype == GemmType::BF16 || c.ctype == GemmType::F16);
+    npl = c.lp_npl;
+    CTM_CHECK(!pre || npl == (c.ctype == GemmType::F16 ? 2 : 1), -1, "reduced-type corner planes");
+    const long Lslots = std::max(c.Lx, c.Ly) * (long)c.R;
+    ld = c.lp_ld;
+    gobs = 2L * n * ld; glo = Lslots * gobs; pobs = (long)kk * ld; plo = Lslots * pobs;
+    if (pre)
+      timed(c, PhaseTimer::SKETCH, 0.0, [&] {
+        for (int role = 0; role < 4; ++role)
+          convert_square_pre(c.st, c.ctype, Gp(role, s0), nn, n, nb, Glp(role, s0), gobs, glo,
+                             cam ? cam + role : nullptr);
+      });
+  }
+
+  // ---- products of cuts [b0, b1) ----------------------------------------
+  // A (n x n, G or G^T) times the panel X (n x m, column-major) -> out
+  void pre_prod(int b0, int b1, int phase, int role, bool trans, const double* X, int m, const OutOperand& out) {
+    const int sb = s0 + b0, nbh = b1 - b0;
+    timed(c, phase, 2.0 * n * m * (double)n * nbh, [&] {
+      float* rs = c.panscale.as<float>() + (long)sb * kk;
+      uint16_t* xp = c.panlp.as<uint16_t>() + sb * pobs;
+      convert_panel_pre(c.st, c.ctype, X, pk, n, m, nbh, xp, pobs, plo, rs, kk);
       PreOperand A, B;
-      A.p = Glp(role, s0) + (trans ? (long)n * ld : 0);
+      A.p = Glp(role, sb) + (trans ? (long)n * ld : 0);
       A.ld = ld; A.bs = gobs; A.lo = glo; A.amax = cam ? cam + role : nullptr;
       B.p = xp; B.ld = ld; B.bs = pobs; B.lo = plo; B.rowscale = rs; B.rs_bs = kk;
-      gemm_pre(c.st, c.ctype, n, m, (int)ld, 1.0, A, B, out, nb, c.ws());
+      gemm_pre(c.st, c.ctype, n, m, (int)ld, 1.0, A, B, out, nbh, c.ws());
     });
-  };
-  // batched products with the four corners of every cut
-  auto prod = [&](int role, bool trans, const double* X, double* Yo, int m) {
+  }
+  void prod(int b0, int b1, int role, bool trans, const double* X, double* Yo, int m) {
     if (pre) {
-      pre_prod(PhaseTimer::SKETCH, role, trans, X, m, out_colmajor(Yo, n, pk));
+      pre_prod(b0, b1, PhaseTimer::SKETCH, role, trans, X, m, out_colmajor(Yo, n, pk));
       return;
     }
-    Operand A = trans ? colmajor(Gp(role, s0), n, nn) : rowmajor(Gp(role, s0), n, nn);
+    const int sb = s0 + b0;
+    Operand A = trans ? colmajor(Gp(role, sb), n, nn) : rowmajor(Gp(role, sb), n, nn);
     if (cam) A.amax = cam + role;
-    mm(c, PhaseTimer::SKETCH, n, m, n, A, colmajor(X, n, pk), out_colmajor(Yo, n, pk), nb);
-  };
-  double *Y = pan(0, s0), *Z = pan(1, s0), *W = pan(2, s0), *t1 = pan(3, s0), *t2 = pan(4, s0);
-  double *V = pan(5, s0), *U = pan(6, s0);
-  auto applyM = [&](const double* X, double* Yo) {   // Yo = G_ur G_ul G_ll G_lr X
-    prod(2, false, X, t1, kk); prod(3, false, t1, t2, kk); prod(0, false, t2, t1, kk); prod(1, false, t1, Yo, kk);
-  };
-  auto applyMt = [&](const double* X, double* Zo) {  // Zo = M^T X, W = G_ul^T G_ur^T X
-    prod(1, true, X, t1, kk); prod(0, true, t1, W, kk); prod(3, true, W, t1, kk); prod(2, true, t1, Zo, kk);
-  };
-  auto orth = [&](double* P, int passes, double* Racc) {
-    timed(c, PhaseTimer::LINALG, 0.0, [&] { cholqr(c.st, c.sla, P, pk, n, kk, nb, passes, Racc, c.ws()); });
-  };
-  // Intermediate bases need unit-norm directions but not full orthogonality:
-  // the shifted pass alone damps every direction below the shift (so power
-  // iterations would lose the small kept singular values), the second pass
-  // restores the norms.  The final basis takes a third pass.
-  applyM(Z, Y);
-  const int q = c.cfg.rsvd_power_iters;
-  orth(Y, q == 0 ? 3 : 2, nullptr);
-  for (int it = 0; it < q; ++it) {
-    applyMt(Y, Z);
-    orth(Z, 2, nullptr);
-    applyM(Z, Y);
-    orth(Y, it == q - 1 ? 3 : 2, nullptr);
+    mm(c, PhaseTimer::SKETCH, n, m, n, A, colmajor(X, n, pk), out_colmajor(Yo, n, pk), b1 - b0);
   }
-  applyMt(Y, Z);                                     // Z = M^T Q = B^T
-  double* R = c.small[0].as<double>() + s0 * k2;
-  double* X = c.small[1].as<double>() + s0 * k2;
-  double* Ysv = c.small[2].as<double>() + s0 * k2;
-  double* S = c.Svals.as<double>() + (long)s0 * std::max(kk, n);
-  orth(Z, 3, R);                                     // Z <- Q2, B^T = Q2 R
-  // R = X diag(S) Ysv^T  ->  B = Ysv S (Q2 X)^T : Ub = Ysv, V = Q2 X.
-  // The one-sided Jacobi runs on R^T = Ysv S X^T, whose rows are graded like
-  // the sketch directions, and converges in fewer sweeps than on R.
-  double* Rt = c.small[3].as<double>() + s0 * k2;
-  timed(c, PhaseTimer::LINALG, 0.0, [&] {
-    transpose_square_batched(c.st, R, Rt, kk, nb);
-    jacobi_svd(c.st, c.sla, Rt, kk, nb, Ysv, S, std::max(kk, n), X);
-  });
-  mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Z, n, pk), colmajor(X, kk, k2), out_colmajor(V, n, pk), nb);
-  mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Y, n, pk), colmajor(Ysv, kk, k2), out_colmajor(U, n, pk), nb);
-  {
-    double* w = c.wvec.as<double>() + (long)s0 * chi;
+  // Yo = G_ur G_ul G_ll G_lr X
+  void applyM(int b0, int b1, const double* X, double* Yo) {
+    double *t1 = pan(3, s0 + b0), *t2 = pan(4, s0 + b0);
+    prod(b0, b1, 2, false, X, t1, kk); prod(b0, b1, 3, false, t1, t2, kk);
+    prod(b0, b1, 0, false, t2, t1, kk); prod(b0, b1, 1, false, t1, Yo, kk);
+  }
+  // Zo = M^T X, W = G_ul^T G_ur^T X
+  void applyMt(int b0, int b1, const double* X, double* Zo) {
+    double *t1 = pan(3, s0 + b0), *W = pan(2, s0 + b0);
+    prod(b0, b1, 1, true, X, t1, kk); prod(b0, b1, 0, true, t1, W, kk);
+    prod(b0, b1, 3, true, W, t1, kk); prod(b0, b1, 2, true, t1, Zo, kk);
+  }
+  void orth(int b0, int b1, double* P, int passes, double* Racc) {
+    timed(c, PhaseTimer::LINALG, 0.0, [&] { cholqr(c.st, c.sla, P, pk, n, kk, b1 - b0, passes, Racc, c.ws()); });
+  }
+
+  // Stage 1a: the sketch matrix and the first range product Y = M Omega.
+  void stage1a(int b0, int b1) {
+    const int sb = s0 + b0, nbh = b1 - b0;
+    timed(c, PhaseTimer::OTHER, 0.0, [&] {
+      omega_fill_batched(c.st, pan(1, sb), pk, nbh, n, c.Db, kk, seeds.data() + b0, sids.data() + b0);
+    });
+    applyM(b0, b1, pan(1, sb), pan(0, sb));
+  }
+  // Stage 1b: power iterations, B^T = M^T Q = Q2 R, and the Jacobi sweeps
+  // that run before the first convergence read.  Intermediate bases need
+  // unit-norm directions but not full orthogonality: the shifted pass alone
+  // damps every direction below the shift (so power iterations would lose
+  // the small kept singular values), the second pass restores the norms.
+  // The final basis takes a third pass.
+  void stage1b(int b0, int b1) {
+    const int sb = s0 + b0, nbh = b1 - b0;
+    double *Y = pan(0, sb), *Z = pan(1, sb);
+    const int q = c.cfg.rsvd_power_iters;
+    orth(b0, b1, Y, q == 0 ? 3 : 2, nullptr);
+    for (int it = 0; it < q; ++it) {
+      applyMt(b0, b1, Y, Z);
+      orth(b0, b1, Z, 2, nullptr);
+      applyM(b0, b1, Z, Y);
+      orth(b0, b1, Y, it == q - 1 ? 3 : 2, nullptr);
+    }
+    applyMt(b0, b1, Y, Z);                           // Z = M^T Q = B^T
+    double* R = c.small[0].as<double>() + sb * k2;
+    orth(b0, b1, Z, 3, R);                           // Z <- Q2, B^T = Q2 R
+    // R = X diag(S) Ysv^T  ->  B = Ysv S (Q2 X)^T : Ub = Ysv, V = Q2 X.
+    // The one-sided Jacobi runs on R^T = Ysv S X^T, whose rows are graded
+    // like the sketch directions, and converges in fewer sweeps than on R.
+    double* Rt = c.small[3].as<double>() + sb * k2;
     timed(c, PhaseTimer::LINALG, 0.0, [&] {
-      projector_weights_batched(c.st, S, std::max(kk, n), U, pk, n, kk, chi, kcap.data(), c.cutoff, w,
-                                c.keff.as<int>() + s0, c.sla.flag.as<int>() + 128, nb);
-      scale_columns_batched(c.st, V, pk, nb, n, chi, w, chi);
-      scale_columns_batched(c.st, Ysv, k2, nb, kk, chi, w, chi);
+      transpose_square_batched(c.st, R, Rt, kk, nbh);
+      jacobi_svd_start(c.st, c.sla, Rt, kk, nbh);
     });
   }
-  // Pt = G_ll (G_lr V'), PT = W Ub'
-  double* Pt = c.Pt.as<double>() + s0 * nc;
-  double* PT = c.PT.as<double>() + s0 * nc;
-  if (pre) {
-    pre_prod(PhaseTimer::EDGE, 2, false, V, chi, out_colmajor(t1, n, pk));
-    pre_prod(PhaseTimer::EDGE, 3, false, t1, chi, out_rowmajor(Pt, chi, nc));
-  } else {
-    Operand G2 = rowmajor(Gp(2, s0), n, nn), G3 = rowmajor(Gp(3, s0), n, nn);
-    if (cam) {
-      G2.amax = cam + 2;
-      G3.amax = cam + 3;
+  // Stage 2: the rest of the Jacobi, the projectors, and the flags (host
+  // reads on c.st).  failed: indices b in [b0, b1).
+  void stage2(int b0, int b1, std::vector<int>& failed) {
+    const int sb = s0 + b0, nbh = b1 - b0;
+    double *Y = pan(0, sb), *Z = pan(1, sb), *W = pan(2, sb), *t1 = pan(3, sb);
+    double *V = pan(5, sb), *U = pan(6, sb);
+    double* X = c.small[1].as<double>() + sb * k2;
+    double* Ysv = c.small[2].as<double>() + sb * k2;
+    double* Rt = c.small[3].as<double>() + sb * k2;
+    double* S = c.Svals.as<double>() + (long)sb * std::max(kk, n);
+    timed(c, PhaseTimer::LINALG, 0.0, [&] { jacobi_svd_finish(c.st, c.sla, Rt, kk, nbh, Ysv, S, std::max(kk, n), X); });
+    mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Z, n, pk), colmajor(X, kk, k2), out_colmajor(V, n, pk), nbh);
+    mm(c, PhaseTimer::LINALG, n, kk, kk, colmajor(Y, n, pk), colmajor(Ysv, kk, k2), out_colmajor(U, n, pk), nbh);
+    {
+      double* w = c.wvec.as<double>() + (long)sb * chi;
+      timed(c, PhaseTimer::LINALG, 0.0, [&] {
+        projector_weights_batched(c.st, S, std::max(kk, n), U, pk, n, kk, chi, kcap.data() + b0, c.cutoff, w,
+                                  c.keff.as<int>() + sb, c.sla.flag.as<int>() + 128, nbh);
+        scale_columns_batched(c.st, V, pk, nbh, n, chi, w, chi);
+        scale_columns_batched(c.st, Ysv, k2, nbh, kk, chi, w, chi);
+      });
     }
-    mm(c, PhaseTimer::EDGE, n, chi, n, G2, colmajor(V, n, pk), out_colmajor(t1, n, pk), nb);
-    mm(c, PhaseTimer::EDGE, n, chi, n, G3, colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nb);
+    // Pt = G_ll (G_lr V'), PT = W Ub'
+    double* Pt = c.Pt.as<double>() + sb * nc;
+    double* PT = c.PT.as<double>() + sb * nc;
+    if (pre) {
+      pre_prod(b0, b1, PhaseTimer::EDGE, 2, false, V, chi, out_colmajor(t1, n, pk));
+      pre_prod(b0, b1, PhaseTimer::EDGE, 3, false, t1, chi, out_rowmajor(Pt, chi, nc));
+    } else {
+      Operand G2 = rowmajor(Gp(2, sb), n, nn), G3 = rowmajor(Gp(3, sb), n, nn);
+      if (cam) {
+        G2.amax = cam + 2;
+        G3.amax = cam + 3;
+      }
+      mm(c, PhaseTimer::EDGE, n, chi, n, G2, colmajor(V, n, pk), out_colmajor(t1, n, pk), nbh);
+      mm(c, PhaseTimer::EDGE, n, chi, n, G3, colmajor(t1, n, pk), out_rowmajor(Pt, chi, nc), nbh);
+    }
+    mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n, pk), colmajor(Ysv, kk, k2), out_rowmajor(PT, chi, nc), nbh);
+    // cuts whose Cholesky QR broke down
+    int flags[192] = {0};
+    d2h(c, flags, c.sla.flag.as<int>(), 192);
+    bool any = false, numeric = false;
+    for (int b = 0; b < nbh; ++b) {
+      if (flags[b]) {
+        failed.push_back(b0 + b);
+      } else if (flags[128 + b]) {   // no singular value above zero
+        numeric = true;
+        c.failed[cuts[b0 + b][0]] = 1;
+      }
+      any |= flags[b] || flags[128 + b];
+    }
+    if (any) {
+      CTM_HIP(hipMemsetAsync(c.sla.flag.p, 0, sizeof(int) * 64, c.st));
+      CTM_HIP(hipMemsetAsync(c.sla.flag.as<int>() + 128, 0, sizeof(int) * 64, c.st));
+    }
+    if (g_debug) {
+      fprintf(stderr, "[ctm] move %lld rot %d col %d slots %d..%d: cholqr codes", c.moves, rot, x, sb, sb + nbh - 1);
+      for (int b = 0; b < nbh; ++b) fprintf(stderr, " %d", flags[b]);
+      fprintf(stderr, "\n");
+    }
+    if (numeric && !c.isolate) {
+      for (int b = b0; b < b1; ++b) c.failed[cuts[b][0]] = 0;
+      throw Error(-4, "projectors: a cut has no singular value above zero");
+    }
   }
-  mm(c, PhaseTimer::LINALG, n, chi, kk, colmajor(W, n, pk), colmajor(Ysv, kk, k2), out_rowmajor(PT, chi, nc), nb);
-  // cuts whose Cholesky QR broke down
-  int flags[192] = {0};
-  d2h(c, flags, c.sla.flag.as<int>(), 192);
+};
+
+static void rsvd_batched(Context& c, int rot, int x, const std::vector<std::array<int, 2>>& cuts, int s0,
+                         std::vector<int>& failed) {
+  RsvdColumn col(c, rot, x, cuts, s0);
   failed.clear();
-  bool any = false, numeric = false;
-  for (int b = 0; b < nb; ++b) {
-    if (flags[b]) {
-      failed.push_back(b);
-    } else if (flags[128 + b]) {   // no singular value above zero
-      numeric = true;
-      c.failed[cuts[b][0]] = 1;
-    }
-    any |= flags[b] || flags[128 + b];
-  }
-  if (any) {
-    CTM_HIP(hipMemsetAsync(c.sla.flag.p, 0, sizeof(int) * 64, c.st));
-    CTM_HIP(hipMemsetAsync(c.sla.flag.as<int>() + 128, 0, sizeof(int) * 64, c.st));
-  }
-  if (g_debug) {
-    fprintf(stderr, "[ctm] move %lld rot %d col %d slots %d..%d: cholqr failed %zu, no-sigma %d, codes", c.moves,
-            rot, x, s0, s0 + nb - 1, failed.size(), (int)numeric);
-    for (int b = 0; b < nb; ++b) fprintf(stderr, " %d", flags[b]);
-    fprintf(stderr, "\n");
-  }
-  if (numeric && !c.isolate) {
-    for (int b = 0; b < nb; ++b) c.failed[cuts[b][0]] = 0;
-    throw Error(-4, "projectors: a cut has no singular value above zero");
-  }
+  col.prepare();
+  col.stage1a(0, col.nb);
+  col.stage1b(0, col.nb);
+  col.stage2(0, col.nb, failed);
 }
 
 // Projectors of every cut of column x of every live replica (identity,
@@ -1086,9 +1201,22 @@ void do_move(Context& c, int rot) {
            rowmajor(c.Ta(s, kt3), Db, (long)chi * Db), out_rowmajor(c.X1.p, Db, (long)chi * Db), chi);
         mm(c, PhaseTimer::OTHER, chi, chi, n, rowmajor(c.X1.p, n), rowmajor(PT_dn, chi), out_colmajor(C4n, chi));
         // T4' = Pt_dn^T absorb(T4 P3_up)
-        mm(c, PhaseTimer::EDGE, n, n, chi, rowmajor(c.Tb(s, kt4), chi), rowmajor(P3_up, n), out_rowmajor(c.X2.p, n));
-        absorb(c, c.X2.as<double>(), c.Ak(rot, s), c.Ab(rot, s), c.G[0].as<double>(), true);
-        mm(c, PhaseTimer::EDGE, chi, n, n, colmajor(Pt_dn, chi), rowmajor(c.G[0].p, n), out_rowmajor(T4n, n));
+        if (c.x2lp.p)
+          x2_pre(c, {c.Tb(s, kt4)}, P3_up, (long)chi * n, c.X2.as<double>(), (long)n * n);
+        else
+          mm(c, PhaseTimer::EDGE, n, n, chi, rowmajor(c.Tb(s, kt4), chi), rowmajor(P3_up, n),
+             out_rowmajor(c.X2.p, n));
+        // split FP16: the absorption also returns the largest |G0|, the scale
+        // source of the product that follows (no scan of G0)
+        unsigned* g0max = nullptr;
+        if (c.ctype == GemmType::F16 && absorb_fused_fits(c.DK, c.DB, c.d)) {
+          g0max = c.camax.as<unsigned>();
+          clear_words(c.st, g0max, 1);
+        }
+        absorb(c, c.X2.as<double>(), c.Ak(rot, s), c.Ab(rot, s), c.G[0].as<double>(), true, g0max);
+        Operand G0op = rowmajor(c.G[0].p, n);
+        G0op.amax = g0max;
+        mm(c, PhaseTimer::EDGE, chi, n, n, colmajor(Pt_dn, chi), G0op, out_rowmajor(T4n, n));
         int* bad = c.badflag.as<int>() + u.ry / Lyv;
         normalize_maxabs(c.st, C1n, cc, c.redscratch.as<double>(), bad);
         normalize_maxabs(c.st, C4n, cc, c.redscratch.as<double>(), bad);
