@@ -74,7 +74,9 @@ struct AbsorbArgs {
   int transposed;
 };
 
-template <class S>
+// MAX: also return the largest |G| (a separate instantiation, so that the
+// plain form keeps its registers for the accumulators)
+template <class S, bool MAX>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(S::WPE))) void k_absorb_fused(
     AbsorbArgs a) {
   constexpr int NR = S::NR, kRD = S::RD, MT1 = S::MT1, KS1 = S::KS1, NT2 = S::NT2;
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(S::
   }
   const long npairs = (long)a.chi * a.chi;
   const long nwaves = (long)gridDim.x * kWaves;
-  unsigned* amax = a.amaxp ? a.amaxp[bz] : a.amax1;
+  unsigned* amax = MAX ? (a.amaxp ? a.amaxp[bz] : a.amax1) : nullptr;
   double gmax = 0.0;
   for (long pr = (long)blockIdx.x * kWaves + w; pr < npairs; pr += nwaves) {
     const int cp = (int)(pr / a.chi), cn = (int)(pr % a.chi);
@@ -185,13 +187,13 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(S::
               const long nxt = (long)cn * Db + (i / DK) * DB + rb, prv = (long)cp * Db + (i % DK) * DB + db;
               if (a.transposed) Gg[prv * a.n + nxt] = acc2[m2][nt][r];
               else Gg[nxt * a.n + prv] = acc2[m2][nt][r];
-              gmax = fmax(gmax, fabs(acc2[m2][nt][r]));
+              if constexpr (MAX) gmax = fmax(gmax, fabs(acc2[m2][nt][r]));
             }
           }
       }
     }
   }
-  if (amax) {
+  if (MAX && amax) {
     __shared__ float red[kWaves];
     float m = (float)gmax;
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
@@ -244,10 +246,12 @@ void absorb_fused_batched(hipStream_t st, const double* X, const double* Ak, con
   const long per_block = kWaves;
   const unsigned blocks = (unsigned)std::min<long>(std::max<long>(1, resident / batch),
                                                    (npairs + per_block - 1) / per_block);
-  if (d6)
-    hipLaunchKernelGGL(k_absorb_fused<ShapeD6>, dim3(blocks, batch), dim3(64 * kWaves), 0, st, a);
-  else
-    hipLaunchKernelGGL(k_absorb_fused<ShapeD8>, dim3(blocks, batch), dim3(64 * kWaves), 0, st, a);
+  const dim3 grid(blocks, batch), block(64 * kWaves);
+  const bool mx = amaxp || amax1;
+  if (d6 && mx)   hipLaunchKernelGGL((k_absorb_fused<ShapeD6, true>), grid, block, 0, st, a);
+  else if (d6)    hipLaunchKernelGGL((k_absorb_fused<ShapeD6, false>), grid, block, 0, st, a);
+  else if (mx)    hipLaunchKernelGGL((k_absorb_fused<ShapeD8, true>), grid, block, 0, st, a);
+  else            hipLaunchKernelGGL((k_absorb_fused<ShapeD8, false>), grid, block, 0, st, a);
   CTM_HIP(hipGetLastError());
 }
 

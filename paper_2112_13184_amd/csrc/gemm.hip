@@ -1311,25 +1311,35 @@ void gemm_pre(hipStream_t st, GemmType type, int M, int N, int Kp, double alpha,
   g.M = M; g.N = N; g.Kp = Kp; g.alpha = alpha; g.batch = batch;
   g.amaxA = A.amax; g.amaxB = B.amax;
   g.rsA = A.rowscale; g.rsB = B.rowscale; g.rsa_bs = A.rs_bs; g.rsb_bs = B.rs_bs;
-  // 128 x 64 tiles, four waves (2 x 2)
-  constexpr int BM = 128, BN = 64;
+  // 128 x 64 tiles with four waves (2 x 2); split FP16 with N > 128 takes
+  // 128 x 192 tiles with eight waves (2 x 4), so that a row block of A (hi
+  // and lo planes) is read once for all of N up to 192 (the sketch products
+  // have N = k <= 192): 32.1 -> 30.5 ms of sketch products per D = 6,
+  // chi = 144 sweep; BF16 measured 17.7 against 18.1 ms with the narrow tiles
+  constexpr int BM = 128;
+  const bool wide = f16 && N > 128;
+  const int BN = wide ? 192 : 64;
   const long tiles = (long)ceil_div(M, BM) * ceil_div(N, BN);
-  // split K until about 256 workgroups per problem (no more than 8 ways, at
-  // least 8 k-tiles each), if the workspace holds the partials; the choice
-  // does not depend on the batch, so a problem gets the same arithmetic in
-  // any batch
+  // split K until about 256 workgroups per problem (128 of the eight-wave
+  // ones; no more than 8 ways, at least 8 k-tiles each), if the workspace
+  // holds the partials; the choice does not depend on the batch, so a
+  // problem gets the same arithmetic in any batch
+  const long target = wide ? 128 : 256;
   int splits = 1;
-  while (splits < 8 && tiles * splits < 256 && Kp / (32 * 2 * splits) >= 8) splits *= 2;
+  while (splits < 8 && tiles * splits < target && Kp / (32 * 2 * splits) >= 8) splits *= 2;
   if (splits > 1 && (ws.p == nullptr || ws.elems < (size_t)splits * batch * M * N)) splits = 1;
   const int kchunk = ceil_div(ceil_div(Kp, 32), splits) * 32;
   g.splits = ceil_div(Kp, kchunk);
   g.kchunk = kchunk;
   g.ws = ws.p;
   const dim3 grid((unsigned)tiles, (unsigned)g.splits, (unsigned)batch);
-  if (f16)
-    hipLaunchKernelGGL((gemm_pre_kernel<LP_F16, BM, BN, 2, 2, 4>), grid, dim3(256), 0, st, g);
-  else
-    hipLaunchKernelGGL((gemm_pre_kernel<LP_BF16, BM, BN, 2, 2, 4>), grid, dim3(256), 0, st, g);
+  if (wide) {
+    if (f16) hipLaunchKernelGGL((gemm_pre_kernel<LP_F16, BM, 192, 2, 4, 2>), grid, dim3(512), 0, st, g);
+    else     hipLaunchKernelGGL((gemm_pre_kernel<LP_BF16, BM, 192, 2, 4, 3>), grid, dim3(512), 0, st, g);
+  } else {
+    if (f16) hipLaunchKernelGGL((gemm_pre_kernel<LP_F16, BM, 64, 2, 2, 4>), grid, dim3(256), 0, st, g);
+    else     hipLaunchKernelGGL((gemm_pre_kernel<LP_BF16, BM, 64, 2, 2, 4>), grid, dim3(256), 0, st, g);
+  }
   CTM_HIP(hipGetLastError());
   if (g.splits > 1) {
     KArgs r{};
