@@ -243,7 +243,8 @@ ctm_status ctm_cut_stats(const ctm_ctx* ctx, int64_t counts[3]);
  *                     corner with an n x k panel: (10 + 8q) per cut)
  *   2 absorption      (single-layer ket and bra contractions of the site)
  *   3 factorisations  (QR, SVD and projector scaling, FP64)
- *   4 other           (small GEMMs, normalisation, permutations, spectra)
+ *   4 other           (small GEMMs, FP64 in every precision; normalisation,
+ *                     permutations, spectra)
  * flops counts the algorithmic floating-point operations of the launches
  * (2 M N K per GEMM, 4 chi^2 D^6 d per absorption; 0 for phases 3 and 4).
  * ctm_timing_read() synchronises the stream. */

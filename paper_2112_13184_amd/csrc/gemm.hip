@@ -41,6 +41,7 @@ struct KArgs {
   int batch;
   const unsigned* amaxA;   // F16 split: largest |A| and |B| as FP32 bits
   const unsigned* amaxB;
+  int ws_cm;            // partials [split][batch][N][M] (column-major outputs)
 };
 
 __device__ __forceinline__ long off0(const int* t, long s, int i) { return t ? (long)t[i] : (long)i * s; }
@@ -298,15 +299,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
 }
 
 // Sum the split-K partials in split order (deterministic) into C.
+// With ws_cm the partials and the walk run m fastest, so that a column-major
+// C is written along its columns.
 __global__ void splitk_reduce(KArgs g) {
   long total = (long)g.batch * g.M * g.N;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    int n = (int)(e % g.N);
-    long t = e / g.N;
-    int m = (int)(t % g.M);
-    int b = (int)(t / g.M);
+    int m, n, b;
+    if (g.ws_cm) {
+      m = (int)(e % g.M);
+      const long t = e / g.M;
+      n = (int)(t % g.N);
+      b = (int)(t / g.N);
+    } else {
+      n = (int)(e % g.N);
+      const long t = e / g.N;
+      m = (int)(t % g.M);
+      b = (int)(t / g.M);
+    }
     double s = 0.0;
-    for (int k = 0; k < g.splits; ++k) s += g.ws[(((long)k * g.batch + b) * g.M + m) * g.N + n];
+    for (int k = 0; k < g.splits; ++k)
+      s += g.ws_cm ? g.ws[(((long)k * g.batch + b) * g.N + n) * g.M + m]
+                   : g.ws[(((long)k * g.batch + b) * g.M + m) * g.N + n];
     double* C = batch_base(g.C, g.oc, g.bsc, b);
     long o = off0(g.tc0, g.sc0, m) + off0(g.tc1, g.sc1, n);
     C[o] = (g.beta == 0.0) ? s : s + g.beta * C[o];
@@ -705,6 +718,7 @@ struct PArgs {
   int splits, kchunk;
   double* ws;
   int batch;
+  int ws_cm;   // partials [split][batch][N][M] (column-major C)
 };
 
 template <int KIND, int BM, int BN, int WAVES_M, int WAVES_N, int STAGES>
@@ -880,7 +894,8 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_pre_kernel(PArgs 
             v *= g.alpha;
           }
           if (g.splits > 1)
-            g.ws[(((long)split * g.batch + b) * g.M + m) * g.N + n] = v;
+            g.ws[g.ws_cm ? (((long)split * g.batch + b) * g.N + n) * g.M + m
+                         : (((long)split * g.batch + b) * g.M + m) * g.N + n] = v;
           else
             C[m * g.sc0 + n * g.sc1] = v;
         }
@@ -1332,6 +1347,7 @@ void gemm_pre(hipStream_t st, GemmType type, int M, int N, int Kp, double alpha,
   g.splits = ceil_div(Kp, kchunk);
   g.kchunk = kchunk;
   g.ws = ws.p;
+  g.ws_cm = (C.s0 == 1 && C.s1 != 1) ? 1 : 0;
   const dim3 grid((unsigned)tiles, (unsigned)g.splits, (unsigned)batch);
   if (wide) {
     if (f16) hipLaunchKernelGGL((gemm_pre_kernel<LP_F16, BM, 192, 2, 4, 2>), grid, dim3(512), 0, st, g);
@@ -1346,7 +1362,7 @@ void gemm_pre(hipStream_t st, GemmType type, int M, int N, int Kp, double alpha,
     r.C = g.C;
     r.sc0 = C.s0; r.sc1 = C.s1; r.bsc = C.bs;
     r.M = M; r.N = N; r.batch = batch; r.beta = 0.0;
-    r.splits = g.splits; r.ws = ws.p;
+    r.splits = g.splits; r.ws = ws.p; r.ws_cm = g.ws_cm;
     const long total = (long)batch * M * N;
     const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(splitk_reduce, dim3(blocks), dim3(256), 0, st, r);

@@ -418,11 +418,15 @@ void context_init(Context& c, const ctm_config& cfg, const double* tensors, int 
 //        (transposed = true: out[(cp,dd,d')][(cn,r,r')])
 // ----------------------------------------------------------------------------
 // GEMM on the context stream, timed under `phase` when timing is on.  The
-// contractions (every phase but LINALG) run in the configured precision; the
-// GEMMs inside the QR / SVD of the projectors stay FP64.
+// large contractions (edge-corner products, sketch products, projector
+// formation, edge renormalisation) run in the configured precision; the GEMMs
+// inside the QR / SVD of the projectors stay FP64, and so do the small
+// products of the OTHER phase (C T and the corner updates: about 1% of a
+// sweep's flops, where split FP16's operand scans and three MFMA passes cost
+// more than FP64: 12.2 against 5.5 ms per D = 6, chi = 144 sweep).
 static void mm(Context& c, int phase, int M, int N, int K, const Operand& A, const Operand& B,
                const OutOperand& C, int batch = 1) {
-  const GemmType t = (phase == PhaseTimer::LINALG) ? GemmType::F64 : c.ctype;
+  const GemmType t = (phase == PhaseTimer::LINALG || phase == PhaseTimer::OTHER) ? GemmType::F64 : c.ctype;
   timed(c, phase, 2.0 * M * N * (double)K * batch, [&] {
     gemm(c.st, t, M, N, K, 1.0, A, B, 0.0, C, batch, c.ws());
   });
