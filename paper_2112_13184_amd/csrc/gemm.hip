@@ -726,7 +726,11 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_pre_kernel(PArgs 
   typedef typename LpStore<KIND>::T T;
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   constexpr int NT = 64 * WAVES_M * WAVES_N;
-  constexpr int BK = 32, LDK = BK + 8;
+  // LDS rows of 32 values (four 16-byte chunks) without padding; chunk q of
+  // row r sits at position q ^ ((r >> 1) & 3), so that the eight lanes of a
+  // 16-byte store phase (two rows, four chunks each) and of a fragment read
+  // phase (eight rows, one chunk) hit eight distinct bank quads
+  constexpr int BK = 32, LDK = BK;
   constexpr int NP = (KIND == LP_F16) ? 2 : 1;
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int TM = WM / 16, TN = WN / 16;
@@ -759,14 +763,14 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_pre_kernel(PArgs 
     const int e = tid + NT * j, r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
     a_in[j] = (NCA % NT == 0) || e < NCA;
     a_off[j] = (long)min(m0 + (a_in[j] ? r : 0), g.M - 1) * g.lda + kq;
-    a_lds[j] = a_in[j] ? r * LDK + kq : 0;
+    a_lds[j] = a_in[j] ? r * LDK + ((kq >> 3) ^ ((r >> 1) & 3)) * 8 : 0;
   }
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
     const int e = tid + NT * j, r = e / (BK / 8), kq = (e % (BK / 8)) * 8;
     b_in[j] = (NCB % NT == 0) || e < NCB;
     b_off[j] = (long)min(n0 + (b_in[j] ? r : 0), g.N - 1) * g.ldb + kq;
-    b_lds[j] = b_in[j] ? r * LDK + kq : 0;
+    b_lds[j] = b_in[j] ? r * LDK + ((kq >> 3) ^ ((r >> 1) & 3)) * 8 : 0;
   }
   // STAGES k-tiles in flight in registers (the loads of tile t + STAGES are
   // issued when tile t + 1 moves to LDS), so that a k-tile's global load
@@ -776,11 +780,11 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_pre_kernel(PArgs 
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
 #pragma unroll
-      for (int j = 0; j < CA; ++j)
-        if (a_in[j]) ra[st][p][j] = *reinterpret_cast<const u4*>(A + (p ? g.loa : 0) + a_off[j] + k0);
+      for (int j = 0; j < CA; ++j)   // unconditional (a_off of an unused chunk is a valid row): uniform counts
+        ra[st][p][j] = *reinterpret_cast<const u4*>(A + (p ? g.loa : 0) + a_off[j] + k0);
 #pragma unroll
       for (int j = 0; j < CB; ++j)
-        if (b_in[j]) rb[st][p][j] = *reinterpret_cast<const u4*>(B + (p ? g.lob : 0) + b_off[j] + k0);
+        rb[st][p][j] = *reinterpret_cast<const u4*>(B + (p ? g.lob : 0) + b_off[j] + k0);
     }
   };
   auto store_tile = [&](int st, int buf) {
@@ -805,15 +809,15 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_pre_kernel(PArgs 
     }
   const int wm0 = (wave / WAVES_N) * WM, wn0 = (wave % WAVES_N) * WN;
   const int r16 = lane & 15, kg = lane >> 4;
+  // position of this lane's fragment (chunk kg) in LDS row `row`
+  auto frag = [&](int row) { return row * LDK + ((kg ^ ((row >> 1) & 3)) * 8); };
   auto compute = [&](int cur) {
     if constexpr (KIND == LP_BF16) {
       bf8 af[TM], bfr[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
-        af[i] = *reinterpret_cast<const bf8*>(&As[cur][0][(wm0 + i * 16 + r16) * LDK + 8 * kg]);
+      for (int i = 0; i < TM; ++i) af[i] = *reinterpret_cast<const bf8*>(&As[cur][0][frag(wm0 + i * 16 + r16)]);
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
-        bfr[j] = *reinterpret_cast<const bf8*>(&Bs[cur][0][(wn0 + j * 16 + r16) * LDK + 8 * kg]);
+      for (int j = 0; j < TN; ++j) bfr[j] = *reinterpret_cast<const bf8*>(&Bs[cur][0][frag(wn0 + j * 16 + r16)]);
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -823,13 +827,13 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_pre_kernel(PArgs 
       h8 ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const int o = (wm0 + i * 16 + r16) * LDK + 8 * kg;
+        const int o = frag(wm0 + i * 16 + r16);
         ah[i] = *reinterpret_cast<const h8*>(&As[cur][0][o]);
         al[i] = *reinterpret_cast<const h8*>(&As[cur][NP - 1][o]);
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const int o = (wn0 + j * 16 + r16) * LDK + 8 * kg;
+        const int o = frag(wn0 + j * 16 + r16);
         bh[j] = *reinterpret_cast<const h8*>(&Bs[cur][0][o]);
         bl[j] = *reinterpret_cast<const h8*>(&Bs[cur][NP - 1][o]);
       }
@@ -845,25 +849,35 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_pre_kernel(PArgs 
   };
 
   const int nk = (ke > kb) ? (ke - kb) / BK : 0;
-  // tile t sits in register stage t % STAGES until it moves to LDS buffer t % 2
+  // Tile t sits in register stage t % STAGES until it moves to LDS buffer
+  // t % 2.  Every step of the main loop issues the same loads (tiles past
+  // the last one reload the last, and are stored into a buffer no step
+  // reads), so that the waits before each store count exactly the younger
+  // stages' loads and STAGES tiles stay in flight.
   if (nk > 0) {
+    const int last = nk - 1;
     load_tile(0, kb);
     store_tile(0, 0);
-  }
 #pragma unroll
-  for (int t = 1; t <= STAGES; ++t)
-    if (t < nk) load_tile(t % STAGES, kb + t * BK);
-  __syncthreads();
-  for (int it0 = 0; it0 < nk; it0 += STAGES) {
+    for (int t = 1; t <= STAGES; ++t) load_tile(t % STAGES, kb + min(t, last) * BK);
+    __syncthreads();
+    int it0 = 0;
+    for (; it0 + STAGES <= nk; it0 += STAGES) {
 #pragma unroll
-    for (int u = 0; u < STAGES; ++u) {
+      for (int u = 0; u < STAGES; ++u) {
+        const int it = it0 + u;
+        compute(it & 1);
+        store_tile((u + 1) % STAGES, (it + 1) & 1);
+        load_tile((u + 1) % STAGES, kb + min(it + 1 + STAGES, last) * BK);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < STAGES; ++u) {   // the last nk mod STAGES tiles
       const int it = it0 + u;
       if (it < nk) {
         compute(it & 1);
-        if (it + 1 < nk) {
-          store_tile((u + 1) % STAGES, (it + 1) & 1);
-          if (it + 1 + STAGES < nk) load_tile((u + 1) % STAGES, kb + (it + 1 + STAGES) * BK);
-        }
+        if (it + 1 < nk) store_tile((u + 1) % STAGES, (it + 1) & 1);
         __syncthreads();
       }
     }
