@@ -349,6 +349,86 @@ ctm_status ctm_queue_cancel(ctm_queue* q, uint64_t ticket);
 /* Cancels pending requests, waits for running ones, frees everything. */
 void ctm_queue_destroy(ctm_queue* q);
 
+/* ------------------------------------------------------------------------
+ * Simple-update imaginary-time evolution and the mean-field environment.
+ *
+ * Sec. 2.3, Eqs. (1)-(3): exp(-T H)|Psi_0> as N_tau first-order
+ * Suzuki-Trotter steps of two-site gates exp(-tau H_ij); after each gate the
+ * bond is truncated back to D (Eq. (4)) with the rest of the network replaced
+ * by the mean-field environment, i.e. the simple update.  Sec. 2.2 (MFE
+ * paragraph): local density matrices contracted with bond weights on the open
+ * bonds, O(D^4) for a site and O(D^5) for a bond.
+ *
+ * State of one problem (Vidal form; all arrays C order, FP64):
+ *   gamma   [N][D][D][D][D][d]  site tensors G_s[l][u][r][d][p], N = Lx*Ly,
+ *                               site s = x + Lx*y, +y up
+ *   lambda  [N][2][D]           bond weights: [s][0] on the bond between s
+ *                               and its right neighbour, [s][1] between s
+ *                               and its upper neighbour.  Leg l of s carries
+ *                               the [.][0] weight of its left neighbour, u
+ *                               its own [s][1], r its own [s][0], d the
+ *                               [.][1] weight of its lower neighbour.
+ *   H       [N][2][d*d][d*d]    bond Hamiltonian of the same bonds,
+ *                               H[(out_i, out_j)][(in_i, in_j)], i = s and j
+ *                               its right (0) or upper (1) neighbour.
+ * A batch holds `batch` independent problems back to back (same shape; each
+ * its own tensors, Hamiltonians and tau), all evolved by one call.
+ * The iTPS a state stands for has A_s = G_s with sqrt(weight) on every leg
+ * (ctm_su_get_itps), which ctm_init / ctm_queue_submit take as site tensors.
+ *
+ * One Trotter step updates the horizontal bonds of sites 0..N-1, then the
+ * vertical bonds of sites 0..N-1.  Bond update (i, j): absorb the weights of
+ * the other legs, contract the shared bond with its weights, apply the gate,
+ * keep the D largest singular triplets of the two-site matrix ((other legs of
+ * i, p_i) x (other legs of j, p_j)); the new weights are those singular
+ * values divided by their 2-norm; the new tensors are the singular vectors
+ * with the absorbed weights divided out again (a weight <= 1e-13 counts as
+ * zero); the sign of each kept pair makes the first entry of its left vector
+ * within 1e-8 of the largest modulus positive.
+ * Limits: Lx, Ly >= 2, Lx*Ly <= 16, 1 <= D <= 8, 1 <= d <= 4,
+ * min(D^3, D d) d <= 64, and the two reduced bond tensors must fit one
+ * workgroup's LDS (D = 8, d = 2 fits); batch <= 65535.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int Lx, Ly;      /* unit cell, both >= 2                                     */
+  int d;           /* physical dimension                                        */
+  int D;           /* bond dimension kept by the truncation                     */
+  int batch;       /* independent problems evolved together                     */
+  void* stream;    /* hipStream_t, or NULL for a private stream                 */
+} ctm_su_config;
+
+typedef struct ctm_su ctm_su;
+
+/* Copies gamma [batch][N][D^4 d] and lambda [batch][N][2][D] (host) to the
+ * device.  CTM_EINVAL for a shape outside the limits. */
+ctm_status ctm_su_create(const ctm_su_config* cfg, const double* gamma, const double* lambda, ctm_su** out);
+/* Eq. (3): H [batch][N][2][d^2][d^2] and tau [batch] (host, finite,
+ * tau >= 0); the gates exp(-tau H) are formed on the device (scaling and
+ * squaring of a Taylor polynomial).  Must precede ctm_su_run. */
+ctm_status ctm_su_set_hamiltonians(ctm_su* su, const double* H, const double* tau);
+/* nsteps Trotter steps of every problem.  CTM_ENUMERIC if a bond of some
+ * problem lost all its singular values (zero or non-finite state). */
+ctm_status ctm_su_run(ctm_su* su, int nsteps);
+/* Device time of the last ctm_su_run (HIP events around its launches), its
+ * launch count and the bond updates it made (any pointer may be NULL). */
+ctm_status ctm_su_stats(const ctm_su* su, double* gpu_ms, long* launches, long* bond_updates);
+/* Copies the state to host arrays of the ctm_su_create layout (either may be NULL). */
+ctm_status ctm_su_get(ctm_su* su, double* gamma, double* lambda);
+/* A_s = G_s times sqrt(weight) on each leg, [batch][N][D^4 d], into host
+ * memory (on_device = 0) or device memory (1). */
+ctm_status ctm_su_get_itps(ctm_su* su, double* tensors, int on_device);
+/* Sec. 2.2, MFE: unit-trace density matrices, rho1 [batch][N][d][d]
+ * (ket index first) of every site (weights squared on its four legs) and rho2
+ * [batch][N][2][d^2][d^2] of every bond, rho2[(p_i, p_j)][(p_i', p_j')] (the
+ * 1 x 2 cluster with weights on its six open legs).  Either may be NULL. */
+ctm_status ctm_su_mfe(ctm_su* su, double* rho1, double* rho2);
+/* MFE energy per site of every problem: energy[b] = (1/N) sum_s
+ * (<H[s][0]> + <H[s][1]> + <onsite_b>), onsite [batch][d][d] or NULL;
+ * bond_energy [batch][N][2] (may be NULL) receives each bond's <H>. */
+ctm_status ctm_su_mfe_energy(ctm_su* su, const double* onsite, double* energy, double* bond_energy);
+const char* ctm_su_last_error(const ctm_su* su);
+void ctm_su_free(ctm_su* su);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,7 +30,14 @@ EXPORTS = (
     "ctm_queue_create", "ctm_queue_submit", "ctm_queue_poll", "ctm_queue_wait",
     "ctm_queue_cancel", "ctm_queue_destroy", "ctm_correlation", "ctm_transfer_spectrum",
     "ctm_xi_extrapolate", "ctm_expect_2site_noalloc",
+    "ctm_su_create", "ctm_su_set_hamiltonians", "ctm_su_run", "ctm_su_stats", "ctm_su_get",
+    "ctm_su_get_itps", "ctm_su_mfe", "ctm_su_mfe_energy", "ctm_su_last_error", "ctm_su_free",
 )
+
+
+class ctm_su_config(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("d", ctypes.c_int), ("D", ctypes.c_int),
+                ("batch", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class CtmError(RuntimeError):
@@ -141,6 +148,16 @@ def load(path=LIB_PATH):
         "ctm_transfer_spectrum": (I, [V, I, I, I, _DP, _DP, _DP, _DP]),
         "ctm_xi_extrapolate": (I, [I, _DP, _DP, _DP, _DP]),
         "ctm_expect_2site_noalloc": (I, [V, I, I, _DP, _DP]),
+        "ctm_su_create": (I, [ctypes.POINTER(ctm_su_config), _DP, _DP, ctypes.POINTER(V)]),
+        "ctm_su_set_hamiltonians": (I, [V, _DP, _DP]),
+        "ctm_su_run": (I, [V, I]),
+        "ctm_su_stats": (I, [V, _DP, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]),
+        "ctm_su_get": (I, [V, _DP, _DP]),
+        "ctm_su_get_itps": (I, [V, _DP, I]),
+        "ctm_su_mfe": (I, [V, _DP, _DP]),
+        "ctm_su_mfe_energy": (I, [V, _DP, _DP, _DP]),
+        "ctm_su_last_error": (ctypes.c_char_p, [V]),
+        "ctm_su_free": (None, [V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -416,5 +433,95 @@ class Queue:
     def __del__(self):
         try:
             self.destroy()
+        except Exception:
+            pass
+
+
+class SimpleUpdate:
+    """A ctm_su handle: simple-update imaginary-time evolution of `batch`
+    independent problems, and their mean-field-environment density matrices.
+
+    gamma: [batch][N][D, D, D, D, d] (or a list of per-problem lists of site
+    tensors), lam: [batch][N][2][D] bond weights (see include/ctm.h)."""
+
+    def __init__(self, gamma, lam, Lx, Ly, D, d=2, batch=None, stream=None):
+        lib = load()
+        g = _f64(np.asarray(gamma, dtype=np.float64)).reshape(-1)
+        lm = _f64(np.asarray(lam, dtype=np.float64)).reshape(-1)
+        N = Lx * Ly
+        if batch is None:
+            batch = g.size // (N * D ** 4 * d)
+        if g.size != batch * N * D ** 4 * d or lm.size != batch * N * 2 * D:
+            raise CtmError(CTM_EINVAL, "gamma / lambda sizes do not match the shape")
+        cfg = ctm_su_config(Lx, Ly, d, D, int(batch), stream)
+        h = ctypes.c_void_p()
+        st = lib.ctm_su_create(ctypes.byref(cfg), _dp(g), _dp(lm), ctypes.byref(h))
+        if st != CTM_OK:
+            raise CtmError(st, (lib.ctm_su_last_error(None) or b"").decode())
+        self._lib, self._h = lib, h
+        self.Lx, self.Ly, self.D, self.d, self.batch, self.N = Lx, Ly, D, d, int(batch), N
+
+    def _check(self, st):
+        if st != CTM_OK:
+            raise CtmError(st, (self._lib.ctm_su_last_error(self._h) or b"").decode())
+
+    def set_hamiltonians(self, H, tau):
+        """H: [batch][N][2][d^2][d^2]; tau: scalar or [batch]."""
+        Hh = _f64(np.asarray(H, dtype=np.float64)).reshape(-1)
+        t = _f64(np.broadcast_to(np.asarray(tau, dtype=np.float64), (self.batch,)))
+        if Hh.size != self.batch * self.N * 2 * self.d ** 4:
+            raise CtmError(CTM_EINVAL, "H size does not match the shape")
+        self._check(self._lib.ctm_su_set_hamiltonians(self._h, _dp(Hh), _dp(t)))
+
+    def run(self, nsteps):
+        self._check(self._lib.ctm_su_run(self._h, int(nsteps)))
+
+    def stats(self):
+        ms, la, bu = ctypes.c_double(), ctypes.c_long(), ctypes.c_long()
+        self._check(self._lib.ctm_su_stats(self._h, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(bu)))
+        return ms.value, la.value, bu.value
+
+    def get(self):
+        """(gamma [batch, N, D, D, D, D, d], lam [batch, N, 2, D])."""
+        g = np.empty((self.batch, self.N) + (self.D,) * 4 + (self.d,))
+        lm = np.empty((self.batch, self.N, 2, self.D))
+        self._check(self._lib.ctm_su_get(self._h, _dp(g), _dp(lm)))
+        return g, lm
+
+    def get_itps(self, device_ptr=None):
+        """A_s = G_s sqrt(weights): a host array [batch, N, D, D, D, D, d], or
+        written to device memory at device_ptr."""
+        if device_ptr is not None:
+            self._check(self._lib.ctm_su_get_itps(self._h, ctypes.cast(ctypes.c_void_p(int(device_ptr)), _DP), 1))
+            return None
+        a = np.empty((self.batch, self.N) + (self.D,) * 4 + (self.d,))
+        self._check(self._lib.ctm_su_get_itps(self._h, _dp(a), 0))
+        return a
+
+    def mfe(self):
+        """(rho1 [batch, N, d, d], rho2 [batch, N, 2, d^2, d^2]), unit trace."""
+        r1 = np.empty((self.batch, self.N, self.d, self.d))
+        r2 = np.empty((self.batch, self.N, 2, self.d ** 2, self.d ** 2))
+        self._check(self._lib.ctm_su_mfe(self._h, _dp(r1), _dp(r2)))
+        return r1, r2
+
+    def mfe_energy(self, onsite=None):
+        """(energy per site [batch], bond energies [batch, N, 2])."""
+        e = np.empty(self.batch)
+        be = np.empty((self.batch, self.N, 2))
+        o = None
+        if onsite is not None:
+            o = _f64(np.broadcast_to(np.asarray(onsite, dtype=np.float64), (self.batch, self.d, self.d)))
+        self._check(self._lib.ctm_su_mfe_energy(self._h, _dp(o) if o is not None else None, _dp(e), _dp(be)))
+        return e, be
+
+    def free(self):
+        if getattr(self, "_h", None):
+            self._lib.ctm_su_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
         except Exception:
             pass

@@ -1,0 +1,939 @@
+// Simple-update imaginary-time evolution and the mean-field environment
+// (Sec. 2.3, Eqs. (1)-(4); Sec. 2.2, mean-field environment).
+//
+// A batch of independent problems (for instance one per field value of a
+// phase scan) evolves at once: one workgroup per problem runs every Trotter
+// step and every bond of its unit cell in order, with the reduced tensors of
+// the bond in LDS.  Bond update (i, j, weight lam on the shared bond k):
+//   M_i[a][(k, p)] = G_i with the weights of its three other legs a absorbed
+//                    (rows D^3, columns D d), likewise M_j;
+//   M_i = Q_i R_i, M_j = Q_j R_j          Householder QR in LDS;
+//   Theta[(x, P)][(y, Q)] = sum_{p q} g[(P Q)][(p q)] sum_k R_i[x][(k p)] lam[k] R_j[y][(k q)];
+//   Theta = U S V^T                       one-sided Jacobi in LDS;
+//   keep the D largest, lam' = S / ||S||_2,
+//   G_i' = (Q_i U)[(a, P)][k] / weights(a), G_j' = (Q_j V) likewise.
+// The product Q_i U is the left factor of the SVD of the full two-site
+// matrix (D^3 d rows), so the sign of each kept pair is fixed on it: the first
+// entry in (a, P) order whose modulus is within 1e-8 of the largest is made
+// positive.  A weight <= 1e-13 is divided out as zero.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "ctm.h"
+#include "wave.hpp"
+
+namespace ctm {
+namespace {
+
+constexpr int kSuThreads = 256;
+constexpr int kSuWaves = kSuThreads / 64;
+constexpr double kSuInvCut = 1e-13;
+constexpr double kSuSignTol = 1e-8;
+constexpr double kSuJacobiTol = 1e-15;
+constexpr int kSuJacobiMaxSweeps = 40;
+constexpr int kSuStepsPerLaunch = 64;
+
+struct SuShape {
+  int Lx, Ly, N, D, d, d2, R, C, k, m, np;
+};
+
+__host__ __device__ inline SuShape su_shape(int Lx, int Ly, int D, int d) {
+  SuShape s;
+  s.Lx = Lx; s.Ly = Ly; s.N = Lx * Ly; s.D = D; s.d = d; s.d2 = d * d;
+  s.R = D * D * D;
+  s.C = D * d;
+  s.k = s.R < s.C ? s.R : s.C;
+  s.m = s.k * d;
+  s.np = s.m + (s.m & 1);
+  return s;
+}
+
+// doubles of LDS one bond update needs
+__host__ __device__ inline long su_lds_need(const SuShape& s) {
+  return 2L * s.R * s.C + (long)s.m * s.np + (long)s.np * s.np + 2L * s.N * s.D + 2L * s.C + s.np + 3L * s.C + 4L * s.D + 8;
+}
+
+struct SuArgs {
+  double* gamma;        // [batch][N][D^4 d]
+  double* lam;          // [batch][N][2][D]
+  const double* gates;  // [batch][N][2][d^2][d^2]
+  int* status;          // [batch]: bit 0 = a bond had no singular value above zero or a non-finite one
+  int Lx, Ly, D, d, nsteps;
+};
+
+// legs of a site other than `leg`, in leg order
+__device__ inline int other_leg(int leg, int t) {
+  return t == 0 ? (leg == 0 ? 1 : 0) : t == 1 ? (leg <= 1 ? 2 : 1) : (leg <= 2 ? 3 : 2);
+}
+// element stride of leg l (0..3) in G[l][u][r][d][p]
+__device__ inline long leg_stride(int leg, int D, int d) {
+  return leg == 0 ? (long)D * D * D * d : leg == 1 ? (long)D * D * d : leg == 2 ? (long)D * d : (long)d;
+}
+// weights on leg `lg` of `site` (l: right bond of the left neighbour, u: own
+// upper bond, r: own right bond, d: upper bond of the lower neighbour)
+__device__ inline const double* leg_weight(const double* lamL, int site, int lg, int Lx, int Ly, int D) {
+  const int sx = site % Lx, sy = site / Lx;
+  switch (lg) {
+    case 0: return lamL + (((sx - 1 + Lx) % Lx + Lx * sy) * 2 + 0) * D;
+    case 1: return lamL + (site * 2 + 1) * D;
+    case 2: return lamL + (site * 2 + 0) * D;
+    default: return lamL + ((sx + Lx * ((sy - 1 + Ly) % Ly)) * 2 + 1) * D;
+  }
+}
+
+__device__ inline int imin_wave(int v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+  return v;
+}
+
+// CAP doubles of LDS; each wave keeps CPW columns of RPL rows per lane of the
+// reconstructed tensors in registers (D^3 <= 64 RPL, D d <= 4 CPW).
+template <int CAP, int RPL, int CPW>
+__global__ __launch_bounds__(kSuThreads) void k_su_run(SuArgs a) {
+  constexpr int kSuMaxRowsPerLane = RPL;
+  constexpr int kSuMaxColsPerWave = CPW;
+  __shared__ double lds[CAP];
+  __shared__ int ip[64 + 32 + 2];
+  const SuShape S = su_shape(a.Lx, a.Ly, a.D, a.d);
+  const int D = S.D, d = S.d, R = S.R, C = S.C, k = S.k, m = S.m, np = S.np, N = S.N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int b = blockIdx.x;
+  const long T = (long)R * D * d;
+  double* G = a.gamma + (long)b * N * T;
+  double* lamG = a.lam + (long)b * N * 2 * D;
+  const double* gates = a.gates + (long)b * N * 2 * S.d2 * S.d2;
+
+  double* Mi = lds;
+  double* Mj = Mi + (long)R * C;
+  double* Th = Mj + (long)R * C;       // m x np, column-major
+  double* Vv = Th + (long)m * np;      // np x np, column-major
+  double* lamL = Vv + (long)np * np;   // [N][2][D]
+  double* taui = lamL + 2 * N * D;
+  double* tauj = taui + C;
+  double* sig = tauj + C;              // np
+  double* cmax = sig + np;             // C
+  double* cval = cmax + C;             // C
+  double* lamN = cval + C;             // D
+  double* flip = lamN + D;             // D
+  double* spare = flip + D;
+  (void)spare;
+  int* perm = ip;                      // D (<= 64 entries reserved)
+  int* cand = ip + 64;                 // C (<= 32)
+  int* flags = ip + 96;                // 2
+
+  for (int e = tid; e < 2 * N * D; e += kSuThreads) lamL[e] = lamG[e];
+  int bad = 0;
+  __syncthreads();
+
+  for (int step = 0; step < a.nsteps; ++step) {
+    for (int dir = 0; dir < 2; ++dir) {
+      for (int s = 0; s < N; ++s) {
+        const int x = s % S.Lx, y = s / S.Lx;
+        const int si = s, li = dir == 0 ? 2 : 1;
+        const int sj = dir == 0 ? (x + 1) % S.Lx + S.Lx * y : x + S.Lx * ((y + 1) % S.Ly);
+        const int lj = dir == 0 ? 0 : 3;
+        const double* lamB = lamL + (s * 2 + dir) * D;
+        const double* g = gates + (long)(s * 2 + dir) * S.d2 * S.d2;
+        // weights and strides of the three other legs of i and j, in leg order
+        const double* wi0 = leg_weight(lamL, si, other_leg(li, 0), S.Lx, S.Ly, D);
+        const double* wi1 = leg_weight(lamL, si, other_leg(li, 1), S.Lx, S.Ly, D);
+        const double* wi2 = leg_weight(lamL, si, other_leg(li, 2), S.Lx, S.Ly, D);
+        const double* wj0 = leg_weight(lamL, sj, other_leg(lj, 0), S.Lx, S.Ly, D);
+        const double* wj1 = leg_weight(lamL, sj, other_leg(lj, 1), S.Lx, S.Ly, D);
+        const double* wj2 = leg_weight(lamL, sj, other_leg(lj, 2), S.Lx, S.Ly, D);
+        const long si0 = leg_stride(other_leg(li, 0), D, d), si1 = leg_stride(other_leg(li, 1), D, d);
+        const long si2 = leg_stride(other_leg(li, 2), D, d), sib = leg_stride(li, D, d);
+        const long sj0 = leg_stride(other_leg(lj, 0), D, d), sj1 = leg_stride(other_leg(lj, 1), D, d);
+        const long sj2 = leg_stride(other_leg(lj, 2), D, d), sjb = leg_stride(lj, D, d);
+        double* Gi = G + (long)si * T;
+        double* Gj = G + (long)sj * T;
+
+        // ---- M_i, M_j (column-major, column c = k d + p) ----
+        for (long e = tid; e < (long)R * C; e += kSuThreads) {
+          const int r = (int)(e % R), c = (int)(e / R);
+          const int a1 = r / (D * D), a2 = (r / D) % D, a3 = r % D;
+          const int kk = c / d, p = c % d;
+          Mi[e] = Gi[a1 * si0 + a2 * si1 + a3 * si2 + kk * sib + p] * wi0[a1] * wi1[a2] * wi2[a3];
+          Mj[e] = Gj[a1 * sj0 + a2 * sj1 + a3 * sj2 + kk * sjb + p] * wj0[a1] * wj1[a2] * wj2[a3];
+        }
+        __syncthreads();
+
+        // ---- Householder QR of M_i and M_j (2 C columns over the waves) ----
+        // The wave that owns column c applies reflector j to it in step j and,
+        // if c = j + 1, then forms reflector j + 1 from it: one barrier a step.
+        auto make_reflector = [&](double* M, double* tau, int j) {
+          double* col = M + (long)j * R;
+          double part = 0.0;
+#pragma unroll
+          for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+            const int r = lane + 64 * t;
+            if (r > j && r < R) part += col[r] * col[r];
+          }
+          const double xn2 = wave_sum(part);
+          const double alpha = col[j];
+          if (xn2 == 0.0) {
+            if (lane == 0) tau[j] = 0.0;
+            return;
+          }
+          const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+          const double sc = 1.0 / (alpha - beta);
+#pragma unroll
+          for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+            const int r = lane + 64 * t;
+            if (r > j && r < R) col[r] *= sc;
+          }
+          if (lane == 0) { tau[j] = (beta - alpha) / beta; col[j] = beta; }
+        };
+        auto apply_reflector = [&](double* M, const double* tau, int j, int c) {
+          const double tj = tau[j];
+          if (tj == 0.0) return;
+          const double* v = M + (long)j * R;
+          double* col = M + (long)c * R;
+          double part = 0.0;
+#pragma unroll
+          for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+            const int r = lane + 64 * t;
+            if (r >= j && r < R) part += (r == j ? 1.0 : v[r]) * col[r];
+          }
+          const double w = tj * wave_sum(part);
+#pragma unroll
+          for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+            const int r = lane + 64 * t;
+            if (r >= j && r < R) col[r] -= w * (r == j ? 1.0 : v[r]);
+          }
+        };
+        if (wave == 0) make_reflector(Mi, taui, 0);
+        if (wave == (C % kSuWaves)) make_reflector(Mj, tauj, 0);
+        __syncthreads();
+        for (int j = 0; j < k; ++j) {
+          for (int gcol = wave; gcol < 2 * C; gcol += kSuWaves) {
+            const bool left = gcol < C;
+            const int c = left ? gcol : gcol - C;
+            if (c <= j) continue;
+            double* M = left ? Mi : Mj;
+            double* tau = left ? taui : tauj;
+            apply_reflector(M, tau, j, c);
+            if (c == j + 1 && j + 1 < k) make_reflector(M, tau, j + 1);
+          }
+          __syncthreads();
+        }
+
+        // ---- Theta = gate applied to R_i lam R_j^T; V = identity ----
+        for (int e = tid; e < m * np; e += kSuThreads) {
+          const int r = e % m, cI = e / m;
+          double val = 0.0;
+          if (cI < m) {
+            const int xr = r / d, P = r % d, yc = cI / d, Q = cI % d;
+            for (int p = 0; p < d; ++p) {
+              for (int q = 0; q < d; ++q) {
+                const double gv = g[(P * d + Q) * S.d2 + p * d + q];
+                if (gv == 0.0) continue;
+                double t = 0.0;
+                for (int kk = 0; kk < D; ++kk) {
+                  const int ca = kk * d + p, cb = kk * d + q;
+                  const double ri = xr <= ca ? Mi[(long)ca * R + xr] : 0.0;
+                  const double rj = yc <= cb ? Mj[(long)cb * R + yc] : 0.0;
+                  t += ri * lamB[kk] * rj;
+                }
+                val += gv * t;
+              }
+            }
+          }
+          Th[e] = val;
+        }
+        for (int e = tid; e < np * np; e += kSuThreads) Vv[e] = (e % np) == (e / np) ? 1.0 : 0.0;
+        if (tid < 2) flags[tid] = 0;
+        __syncthreads();
+
+        // ---- one-sided Jacobi on the columns of Theta (round-robin pairs) ----
+        {
+          const int P = np / 2;
+          int TL = 64;
+          while (TL * P > kSuThreads && TL > 1) TL >>= 1;
+          const int grp = tid / TL, gl = tid % TL;
+          for (int sw = 0; sw < kSuJacobiMaxSweeps; ++sw) {
+            for (int rd = 0; rd < np - 1; ++rd) {
+              if (grp < P) {
+                int pa, pb;
+                if (grp == 0) { pa = np - 1; pb = rd; }
+                else { pa = (rd + grp) % (np - 1); pb = (rd - grp + np - 1) % (np - 1); }
+                double* ca = Th + (long)pa * m;
+                double* cb = Th + (long)pb * m;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int r = gl; r < m; r += TL) {
+                  const double u = ca[r], v = cb[r];
+                  al += u * u; be += v * v; ga += u * v;
+                }
+                for (int off = TL / 2; off >= 1; off >>= 1) {
+                  al += __shfl_xor(al, off);
+                  be += __shfl_xor(be, off);
+                  ga += __shfl_xor(ga, off);
+                }
+                if (ga != 0.0 && fabs(ga) > kSuJacobiTol * sqrt(al * be)) {
+                  const double zeta = (be - al) / (2.0 * ga);
+                  const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                  for (int r = gl; r < m; r += TL) {
+                    const double u = ca[r], v = cb[r];
+                    ca[r] = cs * u - sn * v;
+                    cb[r] = sn * u + cs * v;
+                  }
+                  double* va = Vv + (long)pa * np;
+                  double* vb = Vv + (long)pb * np;
+                  for (int r = gl; r < np; r += TL) {
+                    const double u = va[r], v = vb[r];
+                    va[r] = cs * u - sn * v;
+                    vb[r] = sn * u + cs * v;
+                  }
+                  if (gl == 0) flags[sw & 1] = 1;
+                }
+              }
+              __syncthreads();
+              if (rd == 0 && tid == 0) flags[(sw + 1) & 1] = 0;
+            }
+            if (flags[sw & 1] == 0) break;
+            __syncthreads();
+          }
+        }
+
+        // ---- singular values, the D largest, new weights ----
+        for (int c = tid; c < m; c += kSuThreads) {
+          double ss = 0.0;
+          for (int r = 0; r < m; ++r) ss += Th[(long)c * m + r] * Th[(long)c * m + r];
+          sig[c] = sqrt(ss);
+        }
+        __syncthreads();
+        for (int c = tid; c < m; c += kSuThreads) {
+          const double sc = sig[c];
+          int rank = 0;
+          for (int c2 = 0; c2 < m; ++c2) {
+            const double s2 = sig[c2];
+            rank += (s2 > sc) || (s2 == sc && c2 < c);
+          }
+          if (rank < D) perm[rank] = c;
+        }
+        __syncthreads();
+        double nrm = 0.0;
+        for (int kk = 0; kk < D; ++kk) nrm += sig[perm[kk]] * sig[perm[kk]];
+        nrm = sqrt(nrm);
+        if (!(nrm > 0.0) || !isfinite(nrm)) bad = 1;
+        if (tid < D) lamN[tid] = nrm > 0.0 ? sig[perm[tid]] / nrm : 0.0;
+
+        // ---- G_i' = Q_i U (columns (k', P) in registers), sign rule ----
+        double yv[kSuMaxColsPerWave][kSuMaxRowsPerLane];
+        auto apply_q = [&](const double* M, const double* tau, double (&yy)[kSuMaxRowsPerLane]) {
+          for (int j = k - 1; j >= 0; --j) {
+            const double tj = tau[j];
+            if (tj == 0.0) continue;
+            const double* v = M + (long)j * R;
+            double part = 0.0;
+#pragma unroll
+            for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+              const int r = lane + 64 * t;
+              if (r >= j && r < R) part += (r == j ? 1.0 : v[r]) * yy[t];
+            }
+            const double w = tj * wave_sum(part);
+#pragma unroll
+            for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+              const int r = lane + 64 * t;
+              if (r >= j && r < R) yy[t] -= w * (r == j ? 1.0 : v[r]);
+            }
+          }
+        };
+#pragma unroll
+        for (int q = 0; q < kSuMaxColsPerWave; ++q) {
+          const int cc = wave + kSuWaves * q;
+          if (cc < C) {
+            const int kk = cc / d, P = cc % d;
+            const int pc = perm[kk];
+            const double sv = sig[pc];
+            const double inv = sv > 0.0 ? 1.0 / sv : 0.0;
+#pragma unroll
+            for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+              const int r = lane + 64 * t;
+              yv[q][t] = r < k ? Th[(long)pc * m + r * d + P] * inv : 0.0;
+            }
+            apply_q(Mi, taui, yv[q]);
+            double mx = 0.0;
+#pragma unroll
+            for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+              const int r = lane + 64 * t;
+              if (r < R) mx = fmax(mx, fabs(yv[q][t]));
+            }
+            mx = wave_max(mx);
+            if (lane == 0) cmax[cc] = mx;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kSuMaxColsPerWave; ++q) {
+          const int cc = wave + kSuWaves * q;
+          if (cc < C) {
+            const int kk = cc / d, P = cc % d;
+            double gmax = 0.0;
+            for (int p2 = 0; p2 < d; ++p2) gmax = fmax(gmax, cmax[kk * d + p2]);
+            const double thr = (1.0 - kSuSignTol) * gmax;
+            int best = 1 << 30;
+#pragma unroll
+            for (int t = kSuMaxRowsPerLane - 1; t >= 0; --t) {
+              const int r = lane + 64 * t;
+              if (r < R && fabs(yv[q][t]) >= thr) best = r;
+            }
+            best = imin_wave(best);
+#pragma unroll
+            for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+              const int r = lane + 64 * t;
+              if (r == best) cval[cc] = yv[q][t];
+            }
+            if (lane == 0) cand[cc] = best < (1 << 30) ? best * d + P : (1 << 30);
+          }
+        }
+        __syncthreads();
+        if (tid < D) {
+          int bi = 1 << 30;
+          double bv = 0.0;
+          for (int p2 = 0; p2 < d; ++p2) {
+            const int c2 = tid * d + p2;
+            if (cand[c2] < bi) { bi = cand[c2]; bv = cval[c2]; }
+          }
+          flip[tid] = bv < 0.0 ? -1.0 : 1.0;
+        }
+        __syncthreads();
+        // write G_i'
+#pragma unroll
+        for (int q = 0; q < kSuMaxColsPerWave; ++q) {
+          const int cc = wave + kSuWaves * q;
+          if (cc < C) {
+            const int kk = cc / d, P = cc % d;
+            const double f = flip[kk];
+#pragma unroll
+            for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+              const int r = lane + 64 * t;
+              if (r < R) {
+                const int a1 = r / (D * D), a2 = (r / D) % D, a3 = r % D;
+                const double w0 = wi0[a1], w1 = wi1[a2], w2 = wi2[a3];
+                const double iw = (w0 > kSuInvCut && w1 > kSuInvCut && w2 > kSuInvCut) ? 1.0 / (w0 * w1 * w2) : 0.0;
+                Gi[a1 * si0 + a2 * si1 + a3 * si2 + kk * sib + P] = f * yv[q][t] * iw;
+              }
+            }
+          }
+        }
+        // G_j' = Q_j V, same flips
+#pragma unroll
+        for (int q = 0; q < kSuMaxColsPerWave; ++q) {
+          const int cc = wave + kSuWaves * q;
+          if (cc < C) {
+            const int kk = cc / d, Qp = cc % d;
+            const int pc = perm[kk];
+#pragma unroll
+            for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+              const int r = lane + 64 * t;
+              yv[q][t] = r < k ? Vv[(long)pc * np + r * d + Qp] : 0.0;
+            }
+            apply_q(Mj, tauj, yv[q]);
+            const double f = flip[kk];
+#pragma unroll
+            for (int t = 0; t < kSuMaxRowsPerLane; ++t) {
+              const int r = lane + 64 * t;
+              if (r < R) {
+                const int a1 = r / (D * D), a2 = (r / D) % D, a3 = r % D;
+                const double w0 = wj0[a1], w1 = wj1[a2], w2 = wj2[a3];
+                const double iw = (w0 > kSuInvCut && w1 > kSuInvCut && w2 > kSuInvCut) ? 1.0 / (w0 * w1 * w2) : 0.0;
+                Gj[a1 * sj0 + a2 * sj1 + a3 * sj2 + kk * sjb + Qp] = f * yv[q][t] * iw;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (tid < D) lamL[(s * 2 + dir) * D + tid] = lamN[tid];
+        __syncthreads();
+      }
+    }
+  }
+  for (int e = tid; e < 2 * N * D; e += kSuThreads) lamG[e] = lamL[e];
+  if (bad) atomicOr(a.status + b, 1);
+}
+
+// exp(-tau H) of every bond Hamiltonian: one workgroup per gate, scaling and
+// squaring of a degree-18 Taylor polynomial (Horner form) at norm <= 1/4.
+__global__ __launch_bounds__(256) void k_su_gates(const double* H, const double* tau, double* gates, int N, int d2) {
+  __shared__ double X[256], Pm[256], W[256];
+  __shared__ int sq;
+  const int gidx = blockIdx.x;                 // (b * N + s) * 2 + dir
+  const int b = gidx / (2 * N);
+  const int n = d2, nn = d2 * d2, tid = threadIdx.x;
+  const double* h = H + (long)gidx * nn;
+  const double t = tau[b];
+  if (tid < nn) X[tid] = -t * h[tid];
+  __syncthreads();
+  if (tid == 0) {
+    double nrm = 0.0;                          // 1-norm (largest column sum)
+    for (int c = 0; c < n; ++c) {
+      double cs = 0.0;
+      for (int r = 0; r < n; ++r) cs += fabs(X[r * n + c]);
+      nrm = fmax(nrm, cs);
+    }
+    int s = 0;
+    while (nrm > 0.25 && s < 60) { nrm *= 0.5; ++s; }
+    sq = s;
+  }
+  __syncthreads();
+  const double scale = ldexp(1.0, -sq);
+  if (tid < nn) { X[tid] *= scale; Pm[tid] = (tid / n == tid % n) ? 1.0 : 0.0; }
+  __syncthreads();
+  for (int kdeg = 18; kdeg >= 1; --kdeg) {
+    if (tid < nn) {
+      const int r = tid / n, c = tid % n;
+      double acc = 0.0;
+      for (int q = 0; q < n; ++q) acc += X[r * n + q] * Pm[q * n + c];
+      W[tid] = (r == c ? 1.0 : 0.0) + acc / kdeg;
+    }
+    __syncthreads();
+    if (tid < nn) Pm[tid] = W[tid];
+    __syncthreads();
+  }
+  for (int it = 0; it < sq; ++it) {
+    if (tid < nn) {
+      const int r = tid / n, c = tid % n;
+      double acc = 0.0;
+      for (int q = 0; q < n; ++q) acc += Pm[r * n + q] * Pm[q * n + c];
+      W[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < nn) Pm[tid] = W[tid];
+    __syncthreads();
+  }
+  if (tid < nn) gates[(long)gidx * nn + tid] = Pm[tid];
+}
+
+// Mean-field environment (Sec. 2.2): blockIdx.y = 0 gives the one-site
+// density matrix of site blockIdx.x (weights squared on all four legs),
+// 1 / 2 the bond to its right / upper neighbour:
+//   K_s[k][k'][p][p'] = sum_a A_s[a, k, p] A_s[a, k', p'] (A_s = G_s with its
+//   three other legs weighted), rho[(p q)][(p' q')] = sum_{k k'} K_i lam_k lam_k' K_j.
+// Both are normalised to unit trace.
+constexpr int kMfeCap = 8192 + 2 * 1024 + 256 + 64;
+__global__ __launch_bounds__(256) void k_su_mfe(const double* gamma, const double* lam, double* rho1, double* rho2,
+                                                int Lx, int Ly, int D, int d) {
+  __shared__ double sh[kMfeCap];
+  const int N = Lx * Ly, s = blockIdx.x, kind = blockIdx.y, b = blockIdx.z, tid = threadIdx.x;
+  const int R = D * D * D, C = D * d, d2 = d * d;
+  const long T = (long)R * D * d;
+  const double* G = gamma + (long)b * N * T;
+  const double* lamL = lam + (long)b * N * 2 * D;
+  auto wptr = [&](int site, int lg) { return leg_weight(lamL, site, lg, Lx, Ly, D); };
+  double* red = sh + 8192 + 2048;   // 256 + 64
+  if (kind == 0) {
+    const double* Gs = G + (long)s * T;
+    const double* w0 = wptr(s, 0); const double* w1 = wptr(s, 1);
+    const double* w2 = wptr(s, 2); const double* w3 = wptr(s, 3);
+    // each thread accumulates d^2 partial sums over its leg combinations
+    for (int pp = 0; pp < d2; ++pp) {
+      const int p = pp / d, p2 = pp % d;
+      double acc = 0.0;
+      for (long e = tid; e < (long)R * D; e += 256) {
+        const int l = (int)(e / (D * D * D)), u = (int)((e / (D * D)) % D), r = (int)((e / D) % D), dd = (int)(e % D);
+        const double w = w0[l] * w1[u] * w2[r] * w3[dd];
+        const long base = e * d;
+        acc += Gs[base + p] * Gs[base + p2] * w * w;
+      }
+      red[tid] = acc;
+      __syncthreads();
+      for (int h = 128; h >= 1; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+      }
+      if (tid == 0) sh[pp] = red[0];
+      __syncthreads();
+    }
+    if (tid < d2) {
+      double tr = 0.0;
+      for (int p = 0; p < d; ++p) tr += sh[p * d + p];
+      rho1[((long)b * N + s) * d2 + tid] = sh[tid] / tr;
+    }
+    return;
+  }
+  const int dir = kind - 1;
+  const int x = s % Lx, y = s / Lx;
+  const int si = s, li = dir == 0 ? 2 : 1;
+  const int sj = dir == 0 ? (x + 1) % Lx + Lx * y : x + Lx * ((y + 1) % Ly);
+  const int lj = dir == 0 ? 0 : 3;
+  const double* lamB = lamL + (s * 2 + dir) * D;
+  double* A = sh;                       // R x C
+  double* Ki = sh + 8192;               // C x C
+  double* Kj = Ki + 1024;
+  for (int side = 0; side < 2; ++side) {
+    const int site = side == 0 ? si : sj, leg = side == 0 ? li : lj;
+    const double* w0 = wptr(site, other_leg(leg, 0));
+    const double* w1 = wptr(site, other_leg(leg, 1));
+    const double* w2 = wptr(site, other_leg(leg, 2));
+    const long s0 = leg_stride(other_leg(leg, 0), D, d), s1 = leg_stride(other_leg(leg, 1), D, d);
+    const long s2 = leg_stride(other_leg(leg, 2), D, d), sb = leg_stride(leg, D, d);
+    const double* Gs = G + (long)site * T;
+    for (long e = tid; e < (long)R * C; e += 256) {
+      const int r = (int)(e / C), c = (int)(e % C);
+      const int a1 = r / (D * D), a2 = (r / D) % D, a3 = r % D, kk = c / d, p = c % d;
+      A[e] = Gs[a1 * s0 + a2 * s1 + a3 * s2 + kk * sb + p] * w0[a1] * w1[a2] * w2[a3];
+    }
+    __syncthreads();
+    double* K = side == 0 ? Ki : Kj;
+    for (int e = tid; e < C * C; e += 256) {
+      const int c1 = e / C, c2 = e % C;
+      double acc = 0.0;
+      for (int r = 0; r < R; ++r) acc += A[(long)r * C + c1] * A[(long)r * C + c2];
+      K[e] = acc;
+    }
+    __syncthreads();
+  }
+  // rho[(p q)][(p' q')] = sum_{k k'} Ki[(k p)][(k' p')] lam_k lam_k' Kj[(k q)][(k' q')]
+  const int n4 = d2 * d2;
+  for (int e = tid; e < n4; e += 256) {
+    const int row = e / d2, col = e % d2;
+    const int p = row / d, q = row % d, p2 = col / d, q2 = col % d;
+    double acc = 0.0;
+    for (int k1 = 0; k1 < D; ++k1)
+      for (int k2 = 0; k2 < D; ++k2)
+        acc += Ki[(k1 * d + p) * C + k2 * d + p2] * lamB[k1] * lamB[k2] * Kj[(k1 * d + q) * C + k2 * d + q2];
+    red[e] = acc;
+  }
+  __syncthreads();
+  if (tid < n4) {
+    double tr = 0.0;
+    for (int a = 0; a < d2; ++a) tr += red[a * d2 + a];
+    rho2[(((long)b * N + s) * 2 + dir) * n4 + tid] = red[tid] / tr;
+  }
+}
+
+// energy[b] = (1/N) sum_s (sum_dir tr(rho2 H) + tr(rho1 onsite)), each
+// expectation sum rho[in][out] O[out][in] of unit-trace density matrices.
+__global__ __launch_bounds__(256) void k_su_energy(const double* rho1, const double* rho2, const double* H,
+                                                   const double* onsite, double* energy, double* bond_e, int N, int d) {
+  __shared__ double red[256];
+  const int b = blockIdx.x, tid = threadIdx.x, d2 = d * d, n4 = d2 * d2;
+  double acc = 0.0;
+  for (int s = 0; s < N; ++s) {
+    for (int dir = 0; dir < 2; ++dir) {
+      const long base = (((long)b * N + s) * 2 + dir) * n4;
+      double part = 0.0;
+      for (int e = tid; e < n4; e += 256) {
+        const int a = e / d2, c = e % d2;
+        part += rho2[base + e] * H[base + (long)c * d2 + a];
+      }
+      red[tid] = part;
+      __syncthreads();
+      for (int h = 128; h >= 1; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+      }
+      if (tid == 0) {
+        acc += red[0];
+        if (bond_e) bond_e[((long)b * N + s) * 2 + dir] = red[0];
+      }
+      __syncthreads();
+    }
+    if (onsite && tid == 0) {
+      const double* r1 = rho1 + ((long)b * N + s) * d2;
+      const double* o = onsite + (long)b * d2;
+      for (int a = 0; a < d; ++a)
+        for (int c = 0; c < d; ++c) acc += r1[a * d + c] * o[c * d + a];
+    }
+  }
+  if (tid == 0) energy[b] = acc / N;
+}
+
+// A_s = G_s with sqrt(weight) on every leg (the iTPS the state stands for).
+__global__ void k_su_itps(const double* gamma, const double* lam, double* out, int Lx, int Ly, int D, int d,
+                          long total) {
+  const int N = Lx * Ly;
+  const long T = (long)D * D * D * D * d;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const long bs = e / T, r = e % T;
+    const int b = (int)(bs / N), s = (int)(bs % N);
+    const int l = (int)(r / ((long)D * D * D * d)), u = (int)((r / ((long)D * D * d)) % D);
+    const int rr = (int)((r / ((long)D * d)) % D), dd = (int)((r / d) % D);
+    const double* lamL = lam + (long)b * N * 2 * D;
+    const int sx = s % Lx, sy = s / Lx;
+    const double wl = lamL[(((sx - 1 + Lx) % Lx + Lx * sy) * 2 + 0) * D + l];
+    const double wu = lamL[(s * 2 + 1) * D + u];
+    const double wr = lamL[(s * 2 + 0) * D + rr];
+    const double wd = lamL[((sx + Lx * ((sy - 1 + Ly) % Ly)) * 2 + 1) * D + dd];
+    out[e] = gamma[e] * sqrt(wl * wu * wr * wd);
+  }
+}
+
+}  // namespace
+}  // namespace ctm
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+struct ctm_su {
+  ctm_su_config cfg{};
+  ctm::SuShape S{};
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int cap = 0;                // index of the kernel instantiation
+  ctm::DevBuf gamma, lam, H, tau, gates, status, rho1, rho2, energy, bond_e, onsite;
+  bool gates_set = false;
+  double last_ms = 0.0;
+  long last_launches = 0;
+  long bond_updates = 0;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_su_static_err;
+
+template <typename F>
+ctm_status su_guarded(ctm_su* su, F&& f) {
+  try {
+    f();
+    return CTM_OK;
+  } catch (const ctm::Error& e) {
+    if (su) su->err = e.what();
+    else g_su_static_err = e.what();
+    return (ctm_status)e.status;
+  } catch (const std::bad_alloc&) {
+    if (su) su->err = "host allocation failed";
+    return CTM_ENOMEM;
+  } catch (const std::exception& e) {
+    if (su) su->err = e.what();
+    else g_su_static_err = e.what();
+    return CTM_EDEVICE;
+  }
+}
+
+// kernel instantiations: (LDS doubles, rows per lane, columns per wave)
+struct SuKernelClass {
+  int cap, rpl, cpw;
+  void (*fn)(ctm::SuArgs);
+};
+const SuKernelClass kSuClasses[] = {
+    {3072, 1, 2, ctm::k_su_run<3072, 1, 2>},    {3072, 1, 4, ctm::k_su_run<3072, 1, 4>},
+    {8192, 2, 4, ctm::k_su_run<8192, 2, 4>},    {8192, 4, 8, ctm::k_su_run<8192, 4, 8>},
+    {20224, 4, 8, ctm::k_su_run<20224, 4, 8>},  {20224, 8, 8, ctm::k_su_run<20224, 8, 8>},
+};
+
+// the smallest instantiation that holds the shape, or -1
+int su_kernel_class(const ctm::SuShape& S) {
+  const long need = ctm::su_lds_need(S);
+  const int rpl = (S.R + 63) / 64, cpw = (S.C + ctm::kSuWaves - 1) / ctm::kSuWaves;
+  for (int i = 0; i < (int)(sizeof(kSuClasses) / sizeof(kSuClasses[0])); ++i)
+    if (need <= kSuClasses[i].cap && rpl <= kSuClasses[i].rpl && cpw <= kSuClasses[i].cpw) return i;
+  return -1;
+}
+
+void su_launch_run(ctm_su* su, int nsteps) {
+  ctm::SuArgs a;
+  a.gamma = su->gamma.as<double>();
+  a.lam = su->lam.as<double>();
+  a.gates = su->gates.as<double>();
+  a.status = su->status.as<int>();
+  a.Lx = su->cfg.Lx; a.Ly = su->cfg.Ly; a.D = su->cfg.D; a.d = su->cfg.d; a.nsteps = nsteps;
+  hipLaunchKernelGGL(kSuClasses[su->cap].fn, dim3(su->cfg.batch), dim3(ctm::kSuThreads), 0, su->st, a);
+  CTM_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" {
+
+ctm_status ctm_su_create(const ctm_su_config* cfg, const double* gamma, const double* lambda, ctm_su** out) {
+  if (out) *out = nullptr;
+  return su_guarded(nullptr, [&] {
+    CTM_CHECK(cfg && gamma && lambda && out, CTM_EINVAL, "NULL argument");
+    CTM_CHECK(cfg->Lx >= 2 && cfg->Ly >= 2 && cfg->Lx * cfg->Ly <= 16, CTM_EINVAL,
+              "the simple update needs Lx >= 2, Ly >= 2 and at most 16 sites");
+    CTM_CHECK(cfg->D >= 1 && cfg->D <= 8, CTM_EINVAL, "D must be in 1..8");
+    CTM_CHECK(cfg->d >= 1 && cfg->d <= 4, CTM_EINVAL, "d must be in 1..4");
+    CTM_CHECK(cfg->batch >= 1 && cfg->batch <= 65535, CTM_EINVAL, "batch must be in 1..65535");
+    const ctm::SuShape S = ctm::su_shape(cfg->Lx, cfg->Ly, cfg->D, cfg->d);
+    CTM_CHECK(S.m <= 64, CTM_EINVAL, "min(D^3, D d) * d must be <= 64");
+    const int cap = su_kernel_class(S);
+    CTM_CHECK(cap >= 0, CTM_EINVAL, "bond tensors too large for one workgroup's LDS");
+    auto su = new ctm_su();
+    try {
+      su->cfg = *cfg;
+      su->S = S;
+      su->cap = cap;
+      if (cfg->stream) {
+        su->st = (hipStream_t)cfg->stream;
+      } else {
+        CTM_HIP(hipStreamCreateWithFlags(&su->st, hipStreamNonBlocking));
+        su->own_stream = true;
+      }
+      const long B = cfg->batch, N = S.N, T = (long)S.R * S.D * S.d, n4 = (long)S.d2 * S.d2;
+      su->gamma.alloc(B * N * T * sizeof(double));
+      su->lam.alloc(B * N * 2 * S.D * sizeof(double));
+      su->H.alloc(B * N * 2 * n4 * sizeof(double));
+      su->tau.alloc(B * sizeof(double));
+      su->gates.alloc(B * N * 2 * n4 * sizeof(double));
+      su->status.alloc(B * sizeof(int));
+      su->rho1.alloc(B * N * S.d2 * sizeof(double));
+      su->rho2.alloc(B * N * 2 * n4 * sizeof(double));
+      su->energy.alloc(B * sizeof(double));
+      su->bond_e.alloc(B * N * 2 * sizeof(double));
+      su->onsite.alloc(B * S.d2 * sizeof(double));
+      CTM_HIP(hipMemcpyAsync(su->gamma.p, gamma, su->gamma.bytes, hipMemcpyHostToDevice, su->st));
+      CTM_HIP(hipMemcpyAsync(su->lam.p, lambda, su->lam.bytes, hipMemcpyHostToDevice, su->st));
+      CTM_HIP(hipMemsetAsync(su->status.p, 0, su->status.bytes, su->st));
+      CTM_HIP(hipStreamSynchronize(su->st));
+    } catch (...) {
+      if (su->own_stream && su->st) (void)hipStreamDestroy(su->st);
+      delete su;
+      throw;
+    }
+    *out = su;
+  });
+}
+
+ctm_status ctm_su_set_hamiltonians(ctm_su* su, const double* H, const double* tau) {
+  if (!su) return CTM_EINVAL;
+  return su_guarded(su, [&] {
+    CTM_CHECK(H && tau, CTM_EINVAL, "NULL argument");
+    const long B = su->cfg.batch;
+    for (long b = 0; b < B; ++b) CTM_CHECK(std::isfinite(tau[b]) && tau[b] >= 0.0, CTM_EINVAL, "tau must be finite and >= 0");
+    const long n = (long)su->S.N * 2 * su->S.d2 * su->S.d2;
+    for (long e = 0; e < B * n; ++e) CTM_CHECK(std::isfinite(H[e]), CTM_EINVAL, "Hamiltonian entries must be finite");
+    CTM_HIP(hipMemcpyAsync(su->H.p, H, su->H.bytes, hipMemcpyHostToDevice, su->st));
+    CTM_HIP(hipMemcpyAsync(su->tau.p, tau, su->tau.bytes, hipMemcpyHostToDevice, su->st));
+    hipLaunchKernelGGL(ctm::k_su_gates, dim3(B * su->S.N * 2), dim3(256), 0, su->st, su->H.as<double>(),
+                       su->tau.as<double>(), su->gates.as<double>(), su->S.N, su->S.d2);
+    CTM_HIP(hipGetLastError());
+    CTM_HIP(hipStreamSynchronize(su->st));
+    su->gates_set = true;
+  });
+}
+
+ctm_status ctm_su_run(ctm_su* su, int nsteps) {
+  if (!su) return CTM_EINVAL;
+  return su_guarded(su, [&] {
+    CTM_CHECK(nsteps >= 0, CTM_EINVAL, "nsteps must be >= 0");
+    CTM_CHECK(su->gates_set, CTM_EINVAL, "ctm_su_set_hamiltonians has not been called");
+    hipEvent_t e0, e1;
+    CTM_HIP(hipEventCreate(&e0));
+    CTM_HIP(hipEventCreate(&e1));
+    long launches = 0;
+    try {
+      CTM_HIP(hipMemsetAsync(su->status.p, 0, su->status.bytes, su->st));
+      CTM_HIP(hipEventRecord(e0, su->st));
+      for (int done = 0; done < nsteps; done += ctm::kSuStepsPerLaunch) {
+        su_launch_run(su, std::min(ctm::kSuStepsPerLaunch, nsteps - done));
+        ++launches;
+      }
+      CTM_HIP(hipEventRecord(e1, su->st));
+      CTM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CTM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      su->last_ms = ms;
+      su->last_launches = launches;
+      su->bond_updates = (long)nsteps * 2 * su->S.N * su->cfg.batch;
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::vector<int> stv(su->cfg.batch);
+    CTM_HIP(hipMemcpy(stv.data(), su->status.p, su->status.bytes, hipMemcpyDeviceToHost));
+    for (int b = 0; b < su->cfg.batch; ++b)
+      CTM_CHECK(stv[b] == 0, CTM_ENUMERIC, "problem " + std::to_string(b) +
+                                               ": a bond lost every singular value (zero or non-finite state)");
+  });
+}
+
+ctm_status ctm_su_stats(const ctm_su* su, double* gpu_ms, long* launches, long* bond_updates) {
+  if (!su) return CTM_EINVAL;
+  if (gpu_ms) *gpu_ms = su->last_ms;
+  if (launches) *launches = su->last_launches;
+  if (bond_updates) *bond_updates = su->bond_updates;
+  return CTM_OK;
+}
+
+ctm_status ctm_su_get(ctm_su* su, double* gamma, double* lambda) {
+  if (!su) return CTM_EINVAL;
+  return su_guarded(su, [&] {
+    if (gamma) CTM_HIP(hipMemcpyAsync(gamma, su->gamma.p, su->gamma.bytes, hipMemcpyDeviceToHost, su->st));
+    if (lambda) CTM_HIP(hipMemcpyAsync(lambda, su->lam.p, su->lam.bytes, hipMemcpyDeviceToHost, su->st));
+    CTM_HIP(hipStreamSynchronize(su->st));
+  });
+}
+
+ctm_status ctm_su_get_itps(ctm_su* su, double* tensors, int on_device) {
+  if (!su) return CTM_EINVAL;
+  return su_guarded(su, [&] {
+    CTM_CHECK(tensors, CTM_EINVAL, "NULL argument");
+    const long total = (long)su->cfg.batch * su->S.N * su->S.R * su->S.D * su->S.d;
+    ctm::DevBuf tmp;
+    double* dst = tensors;
+    if (!on_device) {
+      tmp.alloc(total * sizeof(double));
+      dst = tmp.as<double>();
+    }
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(ctm::k_su_itps, dim3(blocks), dim3(256), 0, su->st, su->gamma.as<double>(),
+                       su->lam.as<double>(), dst, su->cfg.Lx, su->cfg.Ly, su->cfg.D, su->cfg.d, total);
+    CTM_HIP(hipGetLastError());
+    if (!on_device) CTM_HIP(hipMemcpyAsync(tensors, dst, total * sizeof(double), hipMemcpyDeviceToHost, su->st));
+    CTM_HIP(hipStreamSynchronize(su->st));
+  });
+}
+
+ctm_status ctm_su_mfe(ctm_su* su, double* rho1, double* rho2) {
+  if (!su) return CTM_EINVAL;
+  return su_guarded(su, [&] {
+    hipLaunchKernelGGL(ctm::k_su_mfe, dim3(su->S.N, 3, su->cfg.batch), dim3(256), 0, su->st, su->gamma.as<double>(),
+                       su->lam.as<double>(), su->rho1.as<double>(), su->rho2.as<double>(), su->cfg.Lx, su->cfg.Ly,
+                       su->cfg.D, su->cfg.d);
+    CTM_HIP(hipGetLastError());
+    if (rho1) CTM_HIP(hipMemcpyAsync(rho1, su->rho1.p, su->rho1.bytes, hipMemcpyDeviceToHost, su->st));
+    if (rho2) CTM_HIP(hipMemcpyAsync(rho2, su->rho2.p, su->rho2.bytes, hipMemcpyDeviceToHost, su->st));
+    CTM_HIP(hipStreamSynchronize(su->st));
+  });
+}
+
+ctm_status ctm_su_mfe_energy(ctm_su* su, const double* onsite, double* energy, double* bond_energy) {
+  if (!su) return CTM_EINVAL;
+  return su_guarded(su, [&] {
+    CTM_CHECK(energy, CTM_EINVAL, "NULL argument");
+    CTM_CHECK(su->gates_set, CTM_EINVAL, "ctm_su_set_hamiltonians has not been called");
+    if (onsite) CTM_HIP(hipMemcpyAsync(su->onsite.p, onsite, su->onsite.bytes, hipMemcpyHostToDevice, su->st));
+    hipLaunchKernelGGL(ctm::k_su_mfe, dim3(su->S.N, 3, su->cfg.batch), dim3(256), 0, su->st, su->gamma.as<double>(),
+                       su->lam.as<double>(), su->rho1.as<double>(), su->rho2.as<double>(), su->cfg.Lx, su->cfg.Ly,
+                       su->cfg.D, su->cfg.d);
+    CTM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(ctm::k_su_energy, dim3(su->cfg.batch), dim3(256), 0, su->st, su->rho1.as<double>(),
+                       su->rho2.as<double>(), su->H.as<double>(), onsite ? su->onsite.as<double>() : nullptr,
+                       su->energy.as<double>(), su->bond_e.as<double>(), su->S.N, su->cfg.d);
+    CTM_HIP(hipGetLastError());
+    CTM_HIP(hipMemcpyAsync(energy, su->energy.p, su->energy.bytes, hipMemcpyDeviceToHost, su->st));
+    if (bond_energy)
+      CTM_HIP(hipMemcpyAsync(bond_energy, su->bond_e.p, su->bond_e.bytes, hipMemcpyDeviceToHost, su->st));
+    CTM_HIP(hipStreamSynchronize(su->st));
+  });
+}
+
+const char* ctm_su_last_error(const ctm_su* su) {
+  if (!su) return g_su_static_err.empty() ? "null simple-update handle" : g_su_static_err.c_str();
+  return su->err.c_str();
+}
+
+void ctm_su_free(ctm_su* su) {
+  if (!su) return;
+  if (su->st) (void)hipStreamSynchronize(su->st);
+  const bool own = su->own_stream;
+  hipStream_t st = su->st;
+  delete su;
+  if (own && st) (void)hipStreamDestroy(st);
+}
+
+}  // extern "C"

@@ -1,0 +1,324 @@
+"""Simple update and mean-field environment: HIP library (C ABI) against the FP64 oracle.
+
+Both sides are FP64 and take the same seeded inputs; the GPU reduces each bond
+by QR and takes a Jacobi SVD of the small core, the oracle takes LAPACK's SVD
+of the full two-site matrix, so results agree to rounding amplified by the
+gaps of the kept spectrum.  Bounds:
+* bond weights: 1e-10 absolute (they are singular values of unit-norm
+  spectra);
+* site tensors compared with the full weight on every leg (indices of a zero
+  weight carry nothing and are arbitrary on both sides): 1e-9 relative to the
+  largest entry;
+* mean-field density matrices and energies: 1e-10 absolute; 1e-12 when both
+  sides contract the same stored state.
+Where the spectrum is degenerate by symmetry (product states, the Heisenberg
+model) only the weights and the observables are compared.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import closed_forms as cf
+from oracle import simple_update as su
+
+pytestmark = pytest.mark.gpu
+
+SZ, SX = wl.SZ, wl.SX
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2112_13184_amd as p
+    p.load()
+    return p
+
+
+def ex1_bond(h):
+    """The paper's transverse-field Ising example in spin units, J_z = -1:
+    -Sz Sz - (h/4)(Sx 1 + 1 Sx), the field split over the four bonds of a site."""
+    Sz, Sx = 0.5 * SZ, 0.5 * SX
+    return -np.kron(Sz, Sz) - 0.25 * h * (np.kron(Sx, wl.ID2) + np.kron(wl.ID2, Sx))
+
+
+def uniform_H(op, N):
+    return [[op, op] for _ in range(N)]
+
+
+def run_both(lib, G0, lh0, lv0, H, tau, Lx, Ly, D, d, nsteps):
+    """One problem through the GPU and the oracle; returns both states."""
+    N = Lx * Ly
+    lam = np.stack([np.stack([lh0[s], lv0[s]]) for s in range(N)])
+    s = lib.SimpleUpdate(np.stack(G0)[None], lam[None], Lx, Ly, D, d=d)
+    s.set_hamiltonians(np.asarray(H)[None], tau)
+    s.run(nsteps)
+    g, lm = s.get()
+    e_gpu, be_gpu = s.mfe_energy()
+    r1, r2 = s.mfe()
+    s.free()
+    Go, lho, lvo = su.simple_update(G0, lh0, lv0, H, tau, Lx, Ly, nsteps)
+    gpu = dict(G=list(g[0]), lh=[lm[0, i, 0] for i in range(N)], lv=[lm[0, i, 1] for i in range(N)],
+               e=e_gpu[0], r1=r1[0], r2=r2[0])
+    orc = dict(G=Go, lh=lho, lv=lvo, e=su.mfe_energy(Go, lho, lvo, Lx, Ly, H))
+    return gpu, orc
+
+
+def compare(gpu, orc, Lx, Ly, tensors=True, tag=""):
+    N = Lx * Ly
+    dl = max(float(np.abs(gpu["lh"][i] - orc["lh"][i]).max()) for i in range(N))
+    dl = max(dl, max(float(np.abs(gpu["lv"][i] - orc["lv"][i]).max()) for i in range(N)))
+    de = abs(gpu["e"] - orc["e"])
+    msg = f"{tag}: weights {dl:.2e}, energy {de:.2e}"
+    if tensors:
+        Wg = su.weighted(gpu["G"], gpu["lh"], gpu["lv"], Lx, Ly)
+        Wo = su.weighted(orc["G"], orc["lh"], orc["lv"], Lx, Ly)
+        dg = max(float(np.abs(a - b).max() / np.abs(b).max()) for a, b in zip(Wg, Wo))
+        msg += f", weighted tensors {dg:.2e}"
+    print(msg)
+    assert dl < 1e-10, msg
+    assert de < 1e-10, msg
+    if tensors:
+        assert dg < 1e-9, msg
+
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_random_state_tfim_parity(lib, D):
+    Lx = Ly = 2
+    N = 4
+    G0 = wl.random_itps(Lx, Ly, D, 2, seed=10 + D)
+    ones = [np.ones(D) for _ in range(N)]
+    H = uniform_H(wl.tfim_bond(3.0), N)
+    gpu, orc = run_both(lib, G0, ones, ones, H, 0.01, Lx, Ly, D, 2, 20)
+    compare(gpu, orc, Lx, Ly, tag=f"D={D}")
+
+
+def test_ragged_cell_and_batch(lib):
+    """A 3x2 cell (odd width, six sites) and a batch of three problems with
+    their own tensors, Hamiltonians and tau."""
+    Lx, Ly, D, d = 3, 2, 3, 2
+    N = Lx * Ly
+    hs, taus = [2.0, 3.0, 4.0], [0.02, 0.01, 0.005]
+    G0s = [wl.random_itps(Lx, Ly, D, d, seed=40 + b) for b in range(3)]
+    rng = np.random.default_rng(7)
+    lam0 = rng.uniform(0.2, 1.0, size=(3, N, 2, D))
+    Hs = [uniform_H(wl.tfim_bond(h), N) for h in hs]
+    s = lib.SimpleUpdate(np.stack([np.stack(g) for g in G0s]), lam0, Lx, Ly, D, d=d)
+    s.set_hamiltonians(np.asarray(Hs), np.asarray(taus))
+    s.run(12)
+    g, lm = s.get()
+    e, _ = s.mfe_energy()
+    s.free()
+    for b in range(3):
+        lh0 = [lam0[b, i, 0] for i in range(N)]
+        lv0 = [lam0[b, i, 1] for i in range(N)]
+        Go, lho, lvo = su.simple_update(G0s[b], lh0, lv0, Hs[b], taus[b], Lx, Ly, 12)
+        gpu = dict(G=list(g[b]), lh=[lm[b, i, 0] for i in range(N)], lv=[lm[b, i, 1] for i in range(N)], e=e[b])
+        orc = dict(G=Go, lh=lho, lv=lvo, e=su.mfe_energy(Go, lho, lvo, Lx, Ly, Hs[b]))
+        compare(gpu, orc, Lx, Ly, tag=f"problem {b}")
+
+
+def test_spin_one_general_hamiltonian(lib):
+    """d = 3 with a random symmetric bond Hamiltonian per bond (and per direction)."""
+    Lx = Ly = 2
+    N, D, d = 4, 2, 3
+    rng = np.random.default_rng(21)
+    H = []
+    for _ in range(N):
+        row = []
+        for _ in range(2):
+            X = rng.standard_normal((9, 9))
+            row.append(0.5 * (X + X.T))
+        H.append(row)
+    G0 = wl.random_itps(Lx, Ly, D, d, seed=5)
+    ones = [np.ones(D) for _ in range(N)]
+    gpu, orc = run_both(lib, G0, ones, ones, H, 0.02, Lx, Ly, D, d, 10)
+    compare(gpu, orc, Lx, Ly, tag="d=3")
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_product_state_tfim(lib, D):
+    """From the polarised product state (rank-deficient first updates, exact
+    zero weights for D = 3): weights and energies."""
+    Lx = Ly = 2
+    N = 4
+    G0 = wl.product_itps([np.array([1.0, 0.0])] * N, D)
+    ones = [np.ones(D) for _ in range(N)]
+    H = uniform_H(ex1_bond(1.2), N)
+    gpu, orc = run_both(lib, G0, ones, ones, H, 0.01, Lx, Ly, D, 2, 50)
+    compare(gpu, orc, Lx, Ly, tensors=False, tag=f"product D={D}")
+
+
+def test_heisenberg_from_noisy_neel(lib):
+    Lx = Ly = 2
+    N, D = 4, 3
+    rng = np.random.default_rng(3)
+    up, dn = np.array([1.0, 0.0]), np.array([0.0, 1.0])
+    G0 = wl.product_itps([up, dn, dn, up], D)
+    G0 = [g + 0.05 * rng.standard_normal(g.shape) for g in G0]
+    ones = [np.ones(D) for _ in range(N)]
+    H = uniform_H(wl.heisenberg_bond(), N)
+    gpu, orc = run_both(lib, G0, ones, ones, H, 0.02, Lx, Ly, D, 2, 30)
+    compare(gpu, orc, Lx, Ly, tensors=False, tag="heisenberg")
+    assert gpu["e"] < -0.5          # below the Neel energy: quantum fluctuations
+
+
+def test_d1_reaches_mean_field(lib):
+    """D = 1 (one row per reduced tensor): the oracle's pinned limit."""
+    Lx = Ly = 2
+    N, h = 4, 2.0
+    G0 = wl.product_itps([np.array([1.0, 0.0])] * N, 1)
+    ones = [np.ones(1) for _ in range(N)]
+    H = uniform_H(wl.tfim_bond(h), N)
+    gpu, orc = run_both(lib, G0, ones, ones, H, 0.01, Lx, Ly, 1, 2, 800)
+    compare(gpu, orc, Lx, Ly, tensors=False, tag="D=1")
+    _, emf = wl.tfim_mean_field(h)
+    assert abs(gpu["e"] - emf) < 1e-4
+
+
+def test_largest_shape_d8(lib):
+    """D = 8, d = 2: 512 x 16 reduced tensors, the largest LDS class."""
+    Lx = Ly = 2
+    N, D = 4, 8
+    G0 = wl.random_itps(Lx, Ly, D, 2, seed=8)
+    ones = [np.ones(D) for _ in range(N)]
+    H = uniform_H(wl.tfim_bond(3.0), N)
+    gpu, orc = run_both(lib, G0, ones, ones, H, 0.01, Lx, Ly, D, 2, 1)
+    compare(gpu, orc, Lx, Ly, tag="D=8")
+
+
+def test_zero_steps_and_zero_tau(lib):
+    """nsteps = 0 leaves the state as given; tau = 0 (identity gates) still
+    truncates and re-gauges every bond, as the oracle does."""
+    Lx = Ly = 2
+    N, D = 4, 2
+    G0 = wl.random_itps(Lx, Ly, D, 2, seed=31)
+    rng = np.random.default_rng(31)
+    lam0 = rng.uniform(0.3, 1.0, size=(N, 2, D))
+    s = lib.SimpleUpdate(np.stack(G0)[None], lam0[None], Lx, Ly, D)
+    s.set_hamiltonians(np.asarray(uniform_H(wl.tfim_bond(3.0), N))[None], 0.0)
+    s.run(0)
+    g, lm = s.get()
+    assert np.array_equal(g[0], np.stack(G0)) and np.array_equal(lm[0], lam0)
+    s.free()
+    lh0 = [lam0[i, 0] for i in range(N)]
+    lv0 = [lam0[i, 1] for i in range(N)]
+    gpu, orc = run_both(lib, G0, lh0, lv0, uniform_H(wl.tfim_bond(3.0), N), 0.0, Lx, Ly, D, 2, 3)
+    compare(gpu, orc, Lx, Ly, tag="tau=0")
+
+
+def test_mfe_of_a_given_state(lib):
+    """The mean-field contraction alone: same stored state (random tensors,
+    random weights) on both sides, every density matrix and the energy."""
+    Lx, Ly, D, d = 2, 3, 3, 2
+    N = Lx * Ly
+    G0 = wl.random_itps(Lx, Ly, D, d, seed=77)
+    rng = np.random.default_rng(77)
+    lam0 = rng.uniform(0.1, 1.0, size=(N, 2, D))
+    lh0 = [lam0[i, 0] for i in range(N)]
+    lv0 = [lam0[i, 1] for i in range(N)]
+    H = [[wl.tfim_bond(2.5), wl.heisenberg_bond()] for _ in range(N)]
+    s = lib.SimpleUpdate(np.stack(G0)[None], lam0[None], Lx, Ly, D, d=d)
+    s.set_hamiltonians(np.asarray(H)[None], 0.01)
+    r1, r2 = s.mfe()
+    onsite = 0.3 * SZ
+    e, be = s.mfe_energy(onsite=onsite)
+    s.free()
+    for i in range(N):
+        ro = su.mfe_rho_site(G0, lh0, lv0, Lx, Ly, i)
+        assert np.abs(r1[0, i] - ro / np.trace(ro)).max() < 1e-12
+        for direction in (0, 1):
+            ro = su.mfe_rho_bond(G0, lh0, lv0, Lx, Ly, i, direction)
+            assert np.abs(r2[0, i, direction] - ro / np.trace(ro)).max() < 1e-12
+            assert abs(be[0, i, direction] - su.expect(ro, H[i][direction])) < 1e-12
+    eo = su.mfe_energy(G0, lh0, lv0, Lx, Ly, H, onsite=onsite)
+    assert abs(e[0] - eo) < 1e-12
+
+
+def test_commuting_gates_feed_ctmrg_to_onsager(lib):
+    """End to end on the GPU: commuting Ising gates from |+x> (exact, bond
+    dimension 2), the iTPS handed to the CTMRG library through device memory,
+    <sz sz> against Onsager at beta = 2 N tau."""
+    import torch
+    Lx = Ly = 2
+    N, D, tau, n = 4, 2, 0.05, 3
+    G0 = wl.product_itps([np.array([1.0, 1.0]) / math.sqrt(2)] * N, D)
+    ones = np.ones((1, N, 2, D))
+    s = lib.SimpleUpdate(np.stack(G0)[None], ones, Lx, Ly, D)
+    s.set_hamiltonians(np.asarray(uniform_H(-np.kron(SZ, SZ), N))[None], tau)
+    s.run(n)
+    buf = torch.empty(N * D ** 4 * 2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    s.get_itps(device_ptr=buf.data_ptr())
+    A = s.get_itps()[0]
+    s.free()
+    ctx = lib.Ctm(None, Lx, Ly, D, chi=24, device_ptr=buf.data_ptr())
+    ctx.ctm_sweep(40, 1e-13)
+    ref = cf.nn_correlator(2 * n * tau)
+    for i in range(N):
+        for direction in (0, 1):
+            v = ctx.ctm_expect_2site(i, direction, np.kron(SZ, SZ))
+            assert abs(v - ref) < 1e-10, (i, direction, v, ref)
+    ctx.ctm_free()
+    assert np.array_equal(buf.cpu().numpy().reshape(A.shape), A)
+
+
+def test_full_size_scan_sampled(lib):
+    """The benchmark's launch configuration (256 problems, D = 4, 2x2 cell,
+    the paper's transverse-field Ising example over a field scan, tau = 0.01)
+    for 100 steps; two problems against the oracle, every problem checked for
+    normalised, sorted, non-negative weights and finite energies."""
+    Lx = Ly = 2
+    N, D, B, n = 4, 4, 256, 100
+    hs = np.linspace(0.0, 2.5, B)
+    G0 = wl.product_itps([np.array([1.0, 0.0])] * N, D)
+    rng = np.random.default_rng(2)
+    G0 = [g + 1e-3 * rng.standard_normal(g.shape) for g in G0]
+    gam = np.broadcast_to(np.stack(G0)[None], (B, N) + G0[0].shape).copy()
+    lam = np.ones((B, N, 2, D))
+    H = np.stack([np.asarray(uniform_H(ex1_bond(h), N)) for h in hs])
+    s = lib.SimpleUpdate(gam, lam, Lx, Ly, D)
+    s.set_hamiltonians(H, 0.01)
+    s.run(n)
+    g, lm = s.get()
+    e, _ = s.mfe_energy()
+    s.free()
+    assert np.all(np.isfinite(e))
+    assert np.all(lm >= 0) and np.all(np.diff(lm, axis=-1) <= 0)
+    assert np.abs(np.sum(lm * lm, axis=-1) - 1).max() < 1e-12
+    for b in (37, 201):
+        ones = [np.ones(D) for _ in range(N)]
+        Go, lho, lvo = su.simple_update(G0, ones, ones, list(H[b]), 0.01, Lx, Ly, n)
+        gpu = dict(G=list(g[b]), lh=[lm[b, i, 0] for i in range(N)], lv=[lm[b, i, 1] for i in range(N)], e=e[b])
+        orc = dict(G=Go, lh=lho, lv=lvo, e=su.mfe_energy(Go, lho, lvo, Lx, Ly, list(H[b])))
+        compare(gpu, orc, Lx, Ly, tag=f"scan problem {b} (h = {hs[b]:.3f})")
+
+
+def test_invalid_arguments(lib):
+    from paper_2112_13184_amd._binding import CTM_EINVAL, CTM_ENUMERIC, CtmError
+    G = np.zeros((1, 2, 2, 2, 2, 2, 2))
+    lam = np.ones((1, 2, 2, 2))
+    with pytest.raises(CtmError) as ex:
+        lib.SimpleUpdate(G, lam, 2, 1, 2)               # Ly = 1: a bond would join a tensor to itself
+    assert ex.value.status == CTM_EINVAL
+    G8 = np.zeros((1, 4) + (8,) * 4 + (3,))
+    with pytest.raises(CtmError) as ex:
+        lib.SimpleUpdate(G8, np.ones((1, 4, 2, 8)), 2, 2, 8, d=3)   # core of 72 columns
+    assert ex.value.status == CTM_EINVAL
+    G0 = np.stack(wl.random_itps(2, 2, 2, 2, seed=1))[None]
+    s = lib.SimpleUpdate(G0, np.ones((1, 4, 2, 2)), 2, 2, 2)
+    with pytest.raises(CtmError) as ex:
+        s.run(1)                                        # no Hamiltonians yet
+    assert ex.value.status == CTM_EINVAL
+    Hbad = np.asarray(uniform_H(wl.tfim_bond(3.0), 4))[None].copy()
+    Hbad[0, 1, 0, 2, 2] = np.nan
+    with pytest.raises(CtmError) as ex:
+        s.set_hamiltonians(Hbad, 0.01)
+    assert ex.value.status == CTM_EINVAL
+    s.free()
+    z = lib.SimpleUpdate(np.zeros_like(G0), np.ones((1, 4, 2, 2)), 2, 2, 2)
+    z.set_hamiltonians(np.asarray(uniform_H(wl.tfim_bond(3.0), 4))[None], 0.01)
+    with pytest.raises(CtmError) as ex:
+        z.run(1)                                        # a zero state has no singular values
+    assert ex.value.status == CTM_ENUMERIC
+    z.free()
