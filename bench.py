@@ -318,6 +318,124 @@ def big_bench(lib, sweeps, D=8, chi=256, p=64, q=1, seed=3, warm=2):
     return out
 
 
+def ex1_bond(h):
+    """The paper's transverse-field Ising example (Sec. 6.1) in spin units,
+    J_z = -1: -Sz Sz - (h/4)(Sx 1 + 1 Sx), the field split over the four bonds
+    of a site."""
+    Sz, Sx = 0.5 * wl.SZ, 0.5 * wl.SX
+    return -np.kron(Sz, Sz) - 0.25 * h * (np.kron(Sx, wl.ID2) + np.kron(wl.ID2, Sx))
+
+
+def su_flops_per_update(D, d):
+    """Algorithmic FP64 flops of one bond update of the reduced simple update:
+    Householder QR of the two D^3 x Dd tensors, the gated core, an SVD of the
+    m x m core with both vector sets (LAPACK count 21 m^3) and the two
+    products Q U, Q V."""
+    R, C = D ** 3, D * d
+    k = min(R, C)
+    m = k * d
+    qr = 2 * 2 * C * C * (R - C / 3.0)
+    core = 2 * k * k * d * d * D + 2 * m * m * d * d
+    svd = 21.0 * m ** 3
+    rec = 2 * 4.0 * R * C * k
+    return qr + core + svd + rec
+
+
+def su_problem_inputs(hs, D, noise=1e-3, seed=2):
+    """Polarised product state (+z) plus noise on every entry, unit weights,
+    the spin-unit Ising bond of each field on every bond of the 2x2 cell."""
+    N = 4
+    rng = np.random.default_rng(seed)
+    G0 = [g + noise * rng.standard_normal(g.shape) for g in wl.product_itps([np.array([1.0, 0.0])] * N, D)]
+    B = len(hs)
+    gam = np.broadcast_to(np.stack(G0)[None], (B, N) + G0[0].shape).copy()
+    lam = np.ones((B, N, 2, D))
+    H = np.stack([np.stack([np.stack([ex1_bond(h), ex1_bond(h)]) for _ in range(N)]) for h in hs])
+    return G0, gam, lam, H
+
+
+def su_bench(lib, B=256, D=4, steps=1000, tau=0.01, cpu=True):
+    """Simple-update imaginary-time evolution of a field scan: B fields of the
+    spin-unit transverse-field Ising model in [0, 2.5], 2x2 cell, D, tau, the
+    given Trotter steps, all problems in one batch.  Device time from the
+    library's HIP events around its launches."""
+    hs = np.linspace(0.0, 2.5, B)
+    _, gam, lam, H = su_problem_inputs(hs, D)
+    warm = lib.SimpleUpdate(gam, lam, 2, 2, D)
+    warm.set_hamiltonians(H, tau)
+    warm.run(10)
+    warm.free()
+    s = lib.SimpleUpdate(gam, lam, 2, 2, D)
+    s.set_hamiltonians(H, tau)
+    t0 = time.perf_counter()
+    s.run(steps)
+    wall = time.perf_counter() - t0
+    gpu_ms, launches, updates = s.stats()
+    e, _ = s.mfe_energy()
+    s.free()
+    f = su_flops_per_update(D, 2)
+    rate = updates / (gpu_ms / 1e3)
+    out = {"workload": f"su_tfim_scan_2x2_D{D}_B{B}", "problems": B, "D": D, "d": 2, "tau": tau,
+           "trotter_steps": steps, "bond_updates": updates, "gpu_ms": gpu_ms, "wall_s": wall,
+           "bond_updates_per_s": rate, "launches": launches,
+           "roofline": {"bound": "alu", "achieved": rate * f / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                        "frac": rate * f / 78.6e12, "flops_per_bond_update": f,
+                        "kernel": "k_su_run (one workgroup per problem, every bond in order)"},
+           "mfe_energy_per_site": {"h_min": float(e[0]), "h_max": float(e[-1])}}
+    if cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import simple_update as osu
+        cores = oracle_threads()
+        G0, _, _, _ = su_problem_inputs(hs[:1], D)
+        ones = [np.ones(D) for _ in range(4)]
+        Hp = [[H[B // 2, i, 0], H[B // 2, i, 1]] for i in range(4)]
+        n_cpu = 250
+        with threadpool_limits(limits=cores):
+            t0 = time.perf_counter()
+            osu.simple_update(G0, ones, ones, Hp, tau, 2, 2, n_cpu)
+            dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n_cpu * 8 / dt, "unit": "bond updates/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{n_cpu} Trotter steps (8 bonds each) of one D={D} problem of the scan, "
+                                         f"full SVD of the two-site matrix, NumPy/OpenBLAS FP64, {dt:.1f} s"}
+    print(f"simple update D={D}: {rate:.3g} bond updates/s ({gpu_ms:.1f} ms for {updates} updates)",
+          file=sys.stderr, flush=True)
+    return out
+
+
+def ex1_scan(lib, fields=32, D=2, steps=1000, tau=0.01, chi=10, sweeps=10):
+    """The paper's transverse-field Ising example end to end (Sec. 6.1:
+    simple updates 1000, tau 0.01, D 2, chi 10, 10 CTMRG sweeps): simple
+    update of every field in one batch, the iTPS of each handed to a CTMRG
+    context in device memory, <S^z> and <S^x> averaged over the cell."""
+    import torch
+    hs = np.linspace(0.0, 2.5, fields)
+    _, gam, lam, H = su_problem_inputs(hs, D)
+    t0 = time.perf_counter()
+    s = lib.SimpleUpdate(gam, lam, 2, 2, D)
+    s.set_hamiltonians(H, tau)
+    s.run(steps)
+    buf = torch.empty(fields * 4 * D ** 4 * 2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    s.get_itps(device_ptr=buf.data_ptr())
+    s.free()
+    t_su = time.perf_counter() - t0
+    sz, sx, es = [], [], []
+    per = 4 * D ** 4 * 2
+    for b in range(fields):
+        ctx = lib.Ctm(None, 2, 2, D, chi=chi, device_ptr=buf.data_ptr() + 8 * b * per)
+        ctx.ctm_sweep(sweeps, 1e-10)
+        sz.append(float(np.mean([abs(ctx.ctm_expect_1site(i, 0.5 * wl.SZ)) for i in range(4)])))
+        sx.append(float(np.mean([ctx.ctm_expect_1site(i, 0.5 * wl.SX) for i in range(4)])))
+        es.append(float(np.mean([ctx.ctm_expect_2site(i, dr, ex1_bond(hs[b])) for i in range(4) for dr in (0, 1)]) * 2))
+        ctx.ctm_free()
+    wall = time.perf_counter() - t0
+    print(f"transverse-field Ising scan: {fields} fields in {wall:.1f} s", file=sys.stderr, flush=True)
+    return {"workload": f"ex1_tfim_scan_2x2_D{D}_chi{chi}", "fields": fields, "su_steps": steps, "tau": tau,
+            "ctm_sweeps": sweeps, "h": [float(h) for h in hs], "abs_sz": sz, "sx": sx, "energy_per_site": es,
+            "su_wall_s": t_su, "wall_s": wall}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +460,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--big-sweeps", type=int, default=20,
                     help="sweeps of the D=8, chi=256 comparison of split FP16 with FP64 (0 = skip)")
+    ap.add_argument("--su", type=int, default=1, help="simple-update and field-scan sections (0 = skip)")
+    ap.add_argument("--su-only", action="store_true", help="run only the simple-update sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
@@ -360,6 +480,11 @@ def main():
     if args.serving_only:
         sv, _, _ = serving_bench(lib, args.serving or 512, args.max_active, args.budget_gb, loads=loads)
         print(json.dumps({"serving": sv}), flush=True)
+        return
+    if args.su_only:
+        out = {"simple_update": su_bench(lib, cpu=not args.no_cpu_baseline),
+               "simple_update_d2": su_bench(lib, D=2, cpu=False), "ex1_scan": ex1_scan(lib)}
+        print(json.dumps(out), flush=True)
         return
     D, chi, d, p, q = args.D, args.chi, 2, args.p, args.q
     A = wl.random_itps(2, 2, D, d, seed=2)
@@ -417,6 +542,9 @@ def main():
         out["precisions"] = cmp
     if args.big_sweeps:
         out["d8_chi256"] = big_bench(lib, args.big_sweeps)
+    if args.su:
+        out["simple_update"] = su_bench(lib, cpu=not args.no_cpu_baseline)
+        out["ex1_scan"] = ex1_scan(lib)
     sv_reqs = sv_sweeps = None
     if args.serving:
         out["serving"], sv_reqs, sv_sweeps = serving_bench(lib, args.serving, args.max_active, args.budget_gb,
