@@ -349,6 +349,25 @@ ctm_status ctm_queue_cancel(ctm_queue* q, uint64_t ticket);
 /* Cancels pending requests, waits for running ones, frees everything. */
 void ctm_queue_destroy(ctm_queue* q);
 
+/* Sec. 2.3, Eq. (4) with the CTMRG environment (the full update): one
+ * first-order Trotter step of the site tensors held by the context, in the
+ * simple update's bond order (horizontal bonds of sites 0..N-1, then the
+ * vertical ones), H [N][2][d^2][d^2] (host) as for ctm_su_set_hamiltonians.
+ * Each bond: QR of both tensors into [other legs][(bond, p)] = X a; the bond
+ * environment N[(rho_i, rho_j)][(rho_i', rho_j')] from the context's current
+ * environment with X_i, X_j in place of the sites, made symmetric and
+ * positive semidefinite; the gate applied to a_i a_j; start from its
+ * truncated SVD; als_iters rounds of alternating least squares (each factor
+ * by the pseudo-inverse of its normal matrix, eigenvalues <= 1e-12 of the
+ * largest dropped); the new tensors X a with the sign of each bond index
+ * fixed (first entry of the left tensor within 1e-8 of its largest modulus
+ * positive) and each divided by its largest |entry|; then env_sweeps CTMRG
+ * sweeps from the current environment.  Needs an FP64 iTPS context (layers
+ * = 2) with Lx, Ly >= 2 and d <= D^2; converge the environment first. */
+ctm_status ctm_fu_step(ctm_ctx* ctx, const double* H, double tau, int als_iters, int env_sweeps);
+/* The context's current site tensors, [N][D^4 d] (host). */
+ctm_status ctm_get_tensors(ctm_ctx* ctx, double* tensors);
+
 /* ------------------------------------------------------------------------
  * Simple-update imaginary-time evolution and the mean-field environment.
  *

@@ -32,6 +32,7 @@ EXPORTS = (
     "ctm_xi_extrapolate", "ctm_expect_2site_noalloc",
     "ctm_su_create", "ctm_su_set_hamiltonians", "ctm_su_run", "ctm_su_stats", "ctm_su_get",
     "ctm_su_get_itps", "ctm_su_mfe", "ctm_su_mfe_energy", "ctm_su_last_error", "ctm_su_free",
+    "ctm_fu_step", "ctm_get_tensors",
 )
 
 
@@ -158,6 +159,8 @@ def load(path=LIB_PATH):
         "ctm_su_mfe_energy": (I, [V, _DP, _DP, _DP]),
         "ctm_su_last_error": (ctypes.c_char_p, [V]),
         "ctm_su_free": (None, [V]),
+        "ctm_fu_step": (I, [V, _DP, D, I, I]),
+        "ctm_get_tensors": (I, [V, _DP]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -307,6 +310,16 @@ class Ctm:
         bb = _f64(b)
         self._check(self._lib.ctm_impurity(self._h, site, _dp(bb), ctypes.byref(v)))
         return v.value
+
+    def ctm_fu_step(self, H, tau, als_iters=5, env_sweeps=1):
+        """One full-update Trotter step; H [N][2][d^2][d^2]."""
+        h = _f64(np.asarray(H, dtype=np.float64)).reshape(-1)
+        self._check(self._lib.ctm_fu_step(self._h, _dp(h), float(tau), int(als_iters), int(env_sweeps)))
+
+    def ctm_get_tensors(self):
+        out = np.empty((self.Lx * self.Ly,) + (self.D,) * 4 + (self.d,))
+        self._check(self._lib.ctm_get_tensors(self._h, _dp(out)))
+        return out
 
     def ctm_log_kappa(self):
         v = ctypes.c_double()

@@ -168,6 +168,21 @@ ctm_status ctm_sweep(ctm_ctx* ctx, int max_sweeps, double tol, int* sweeps_done,
   return guarded(ctx, [&] { ctm::do_sweeps(ctx->c, max_sweeps, tol, sweeps_done, delta, converged); });
 }
 
+ctm_status ctm_fu_step(ctm_ctx* ctx, const double* H, double tau, int als_iters, int env_sweeps) {
+  if (!ctx) return CTM_EINVAL;
+  if (!H || als_iters < 0 || env_sweeps < 0) {
+    ctx->c.err = "ctm_fu_step: NULL Hamiltonians or negative counts";
+    return CTM_EINVAL;
+  }
+  return guarded(ctx, [&] { ctm::full_update_step(ctx->c, H, tau, als_iters, env_sweeps); });
+}
+
+ctm_status ctm_get_tensors(ctm_ctx* ctx, double* tensors) {
+  if (!ctx || !tensors) return CTM_EINVAL;
+  if (ctx->c.R != 1) { ctx->c.err = "ctm_get_tensors: one solve per context"; return CTM_EINVAL; }
+  return guarded(ctx, [&] { ctm::get_site_tensors(ctx->c, tensors); });
+}
+
 ctm_status ctm_projectors(ctm_ctx* ctx, ctm_dir dir, int x, int y, double* P, double* Pt, int* k_eff) {
   if (!ctx) return CTM_EINVAL;
   ctm::Context& c = ctx->c;

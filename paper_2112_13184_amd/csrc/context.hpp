@@ -273,6 +273,20 @@ void correlation(Context& c, int site, int dir, const double* opA, const double*
 // Returns the number of restarts.
 int transfer_spectrum(Context& c, int dir, int line, int nev, int krylov, double tol, std::complex<double>* lam);
 double log_kappa(Context& c);
+// numpy.tensordot / transpose of device tensors, results in c.arena (FP64).
+DT tensordot(Context& c, const DT& A, const std::vector<int>& axA, const DT& B, const std::vector<int>& axB);
+DT tensor_transpose(Context& c, const DT& A, const std::vector<int>& perm);
+// Full update: N[(rho_i, rho_j)][(rho_i', rho_j')] of the bond (site, site + x)
+// (dir 0) or (site, site + y) (dir 1), the bond-density-matrix patch of the
+// environment with the tensors Ei, Ej ([l][u][r][d][rho], rho of dimension r,
+// device, physical frame) in place of the two sites; trace 1, in c.arena.
+DT bond_environment(Context& c, int site, int dir, const double* Ei, const double* Ej, int r);
+// exp(-tau_b H) of batch x N x 2 bond Hamiltonians (d2 x d2, device) on st.
+void trotter_gates(hipStream_t st, const double* H, const double* tau, double* gates, int N, int d2, int batch);
+// One full-update Trotter step (bond Hamiltonians H [N][2][d^2][d^2], host).
+void full_update_step(Context& c, const double* H, double tau, int als_iters, int env_sweeps);
+// Site tensors of every site (rotation 0) to host memory.
+void get_site_tensors(Context& c, double* out);
 void check_bad(Context& c, const char* where);
 
 }  // namespace ctm

@@ -1,4 +1,4 @@
-// FP64 factorisations on the GPU through rocSOLVER (Householder QR, SVD).
+// FP64 factorisations on the GPU through rocSOLVER (Householder QR, SVD, symmetric eigenproblem).
 #include "linalg.hpp"
 
 #include <rocblas/rocblas.h>
@@ -66,6 +66,12 @@ void la_svd(Linalg* la, double* A, int k, double* S, double* U, double* VT) {
   CTM_CHECK(k <= kMaxK, -1, "la_svd: k <= 4096");
   CTM_RB(rocsolver_dgesvd(la->h, rocblas_svect_singular, rocblas_svect_singular, k, k, A, k, S, U, k,
                           VT, k, la->E.as<double>(), rocblas_outofplace, la->info.as<rocblas_int>()));
+}
+
+void la_syev(Linalg* la, double* A, int n, double* W) {
+  CTM_CHECK(n <= kMaxK, -1, "la_syev: n <= 4096");
+  CTM_RB(rocsolver_dsyevd(la->h, rocblas_evect_original, rocblas_fill_lower, n, A, n, W, la->E.as<double>(),
+                          la->info.as<rocblas_int>()));
 }
 
 void la_singular_values_batched(Linalg* la, double* A, int m, int batch, double* S) {

@@ -22,6 +22,10 @@ void la_qr(Linalg* la, double* Z, int n, int k, double* R);
 // column-major; VT holds V^T).  A is destroyed.  S descending.
 void la_svd(Linalg* la, double* A, int k, double* S, double* U, double* VT);
 
+// A (n x n symmetric, column-major; the lower triangle is read) <- its
+// eigenvectors (columns), W <- the eigenvalues, ascending.
+void la_syev(Linalg* la, double* A, int n, double* W);
+
 // Singular values (descending) of `batch` m x m column-major matrices stored
 // back to back; A is destroyed.  S: batch x m.
 void la_singular_values_batched(Linalg* la, double* A, int m, int batch, double* S);

@@ -162,6 +162,38 @@ double fetch_scalar(Context& c, const double* dev) {
 
 }  // namespace
 
+DT tensordot(Context& c, const DT& A, const std::vector<int>& axA, const DT& B, const std::vector<int>& axB) {
+  return tdot(c, A, axA, B, axB);
+}
+
+DT tensor_transpose(Context& c, const DT& A, const std::vector<int>& perm) { return transpose(c, A, perm); }
+
+DT bond_environment(Context& c, int site, int dir, const double* Ei, const double* Ej, int r) {
+  const int rot = (dir == 0) ? 0 : 3;   // +y becomes +x three quarter turns on
+  int x = site % c.Lx, y = site / c.Lx;
+  for (int i = 0; i < rot; ++i) { int t = x; x = -y; y = t; }
+  const int s = view_site(c, rot, x, y), t = view_site(c, rot, x + 1, y);
+  CTM_CHECK(s == site, -3, "bond_environment: view bookkeeping");
+  View vs = view_of(c, s, rot), vt = view_of(c, t, rot);
+  const long D = c.D;
+  DT ei = make(const_cast<double*>(Ei), {D, D, D, D, (long)r});
+  DT ej = make(const_cast<double*>(Ej), {D, D, D, D, (long)r});
+  if (rot == 3) {                      // a quarter turn counter-clockwise three times
+    ei = transpose(c, ei, {3, 0, 1, 2, 4});
+    ej = transpose(c, ej, {3, 0, 1, 2, 4});
+  }
+  DT LB = left_boundary(c, vs), RB = right_boundary(c, vt);
+  DT X = column(c, LB, vs.T[0], vs.T[2], ei, ei, true);
+  X = column(c, X, vt.T[0], vt.T[2], ej, ej, true);
+  DT R = close_lr(c, X, RB);                     // [ri, ri', rj, rj']
+  R = transpose(c, R, {0, 2, 1, 3});             // [(ri, rj), (ri', rj')]
+  const int dim = r * r;
+  DT N = make(c.arena.alloc((size_t)dim * dim), {(long)dim, (long)dim});
+  hipLaunchKernelGGL(k_trace_normalize, dim3(1), dim3(64), 0, c.st, R.p, N.p, dim);
+  CTM_HIP(hipGetLastError());
+  return N;
+}
+
 void rho_1site(Context& c, int site, double* rho_dev, double* rho_host) {
   c.arena.reset();
   View v = view_of(c, site, 0);

@@ -669,6 +669,12 @@ __global__ void k_su_itps(const double* gamma, const double* lam, double* out, i
 }
 
 }  // namespace
+
+void trotter_gates(hipStream_t st, const double* H, const double* tau, double* gates, int N, int d2, int batch) {
+  hipLaunchKernelGGL(k_su_gates, dim3(batch * N * 2), dim3(256), 0, st, H, tau, gates, N, d2);
+  CTM_HIP(hipGetLastError());
+}
+
 }  // namespace ctm
 
 // ---------------------------------------------------------------------------
