@@ -436,6 +436,72 @@ def ex1_scan(lib, fields=32, D=2, steps=1000, tau=0.01, chi=10, sweeps=10):
             "su_wall_s": t_su, "wall_s": wall}
 
 
+def fu_bench(lib, D=4, chi=32, p=32, h=1.5, su_steps=500, fu_steps=3, tau=0.01, als_iters=5, env_sweeps=1,
+             cpu=True):
+    """The paper's optimisation pipeline on one problem (Sec. 2.3): simple
+    updates, the iTPS handed to a CTMRG context and converged, then full-update
+    Trotter steps (each bond with its CTMRG environment, env_sweeps sweeps
+    after each bond).  Reports the time per full-update step and the CTMRG
+    energy per site before and after."""
+    import torch
+    hs = np.array([h])
+    _, gam, lam, H = su_problem_inputs(hs, D)
+    s = lib.SimpleUpdate(gam, lam, 2, 2, D)
+    s.set_hamiltonians(H, tau)
+    s.run(su_steps)
+    buf = torch.empty(4 * D ** 4 * 2, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    s.get_itps(device_ptr=buf.data_ptr())
+    A0 = s.get_itps()[0]
+    s.free()
+    Hb = ex1_bond(h)
+    Hfu = np.asarray([[Hb, Hb] for _ in range(4)])
+    ctx = lib.Ctm(None, 2, 2, D, chi=chi, device_ptr=buf.data_ptr(), rsvd_oversample=p)
+    ctx.ctm_sweep(30, 1e-10)
+    e_su = sum(ctx.ctm_expect_2site(i, dr, Hb) for i in range(4) for dr in (0, 1)) / 4
+    t0 = time.perf_counter()
+    ctx.ctm_sweep(1, 0.0)
+    t_sweep = time.perf_counter() - t0
+    ctx.ctm_fu_step(Hfu, tau, als_iters=als_iters, env_sweeps=env_sweeps)      # warm-up step
+    t0 = time.perf_counter()
+    for _ in range(fu_steps):
+        ctx.ctm_fu_step(Hfu, tau, als_iters=als_iters, env_sweeps=env_sweeps)
+    dt = (time.perf_counter() - t0) / fu_steps
+    ctx.ctm_sweep(30, 1e-10)
+    e_fu = sum(ctx.ctm_expect_2site(i, dr, Hb) for i in range(4) for dr in (0, 1)) / 4
+    ctx.ctm_free()
+    out = {"workload": f"fu_tfim_2x2_D{D}_chi{chi}_h{h}", "D": D, "chi": chi, "rsvd_p": p, "h": h, "tau": tau,
+           "su_steps_before": su_steps, "fu_steps_timed": fu_steps, "als_iters": als_iters,
+           "env_sweeps_per_bond": env_sweeps, "ms_per_fu_step": 1e3 * dt,
+           "bond_updates_per_s": 8.0 / dt, "ms_per_env_sweep": 1e3 * t_sweep,
+           "env_share": 8 * env_sweeps * t_sweep / dt,
+           "energy_per_site_su": e_su, "energy_per_site_after_fu": e_fu}
+    if cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import full_update as ofu
+        from oracle.ctmrg import Environment
+        cores = oracle_threads()
+        from oracle.simple_update import gate as ogate
+        with threadpool_limits(limits=cores):
+            env = Environment([np.array(a) for a in A0], 2, 2, chi=chi, oversample=p)
+            for _ in range(3):
+                env.sweep()
+            t0 = time.perf_counter()
+            ofu.bond_update(env, 0, 0, ogate(Hb, tau), als_iters)
+            t_bond = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            env.sweep()
+            t_env = time.perf_counter() - t0
+        step = 8 * (t_bond + env_sweeps * t_env)
+        out["cpu_baseline"] = {"value": 8.0 / step, "unit": "bond updates/s", "cores": cores, "kind": "oracle",
+                               "sample": f"one full-update bond update ({t_bond:.1f} s) and one CTMRG sweep "
+                                         f"({t_env:.1f} s) of the same D={D}, chi={chi} workload, NumPy/OpenBLAS "
+                                         f"FP64; a Trotter step is 8 of each"}
+    print(f"full update D={D} chi={chi}: {1e3 * dt:.0f} ms per Trotter step", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -483,7 +549,8 @@ def main():
         return
     if args.su_only:
         out = {"simple_update": su_bench(lib, cpu=not args.no_cpu_baseline),
-               "simple_update_d2": su_bench(lib, D=2, cpu=False), "ex1_scan": ex1_scan(lib)}
+               "simple_update_d2": su_bench(lib, D=2, cpu=False), "ex1_scan": ex1_scan(lib),
+               "full_update": fu_bench(lib, cpu=not args.no_cpu_baseline)}
         print(json.dumps(out), flush=True)
         return
     D, chi, d, p, q = args.D, args.chi, 2, args.p, args.q
@@ -545,6 +612,9 @@ def main():
     if args.su:
         out["simple_update"] = su_bench(lib, cpu=not args.no_cpu_baseline)
         out["ex1_scan"] = ex1_scan(lib)
+        # the oracle's full-update bond update takes about a minute: its CPU leg
+        # runs with --su-only
+        out["full_update"] = fu_bench(lib, cpu=False)
     sv_reqs = sv_sweeps = None
     if args.serving:
         out["serving"], sv_reqs, sv_sweeps = serving_bench(lib, args.serving, args.max_active, args.budget_gb,
