@@ -36,6 +36,8 @@ constexpr int kSuWaves = kSuThreads / 64;
 constexpr double kSuInvCut = 1e-13;
 constexpr double kSuSignTol = 1e-8;
 constexpr double kSuJacobiTol = 1e-15;
+constexpr double kSuJacobiStop = 1e-10;
+constexpr double kSuJacobiZero = 1e-30;
 constexpr int kSuJacobiMaxSweeps = 40;
 constexpr int kSuStepsPerLaunch = 64;
 
@@ -87,6 +89,17 @@ __device__ inline const double* leg_weight(const double* lamL, int site, int lg,
   }
 }
 
+// Sum over aligned groups of TL lanes (TL = 1, 2, 4, 8 or 16) inside the
+// 16-lane DPP rows; every lane of a group receives its group's sum.  All 64
+// lanes must be active.
+__device__ inline double group_sum(double v, int TL) {
+  if (TL >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  if (TL >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  if (TL >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+  if (TL >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+  return v;
+}
+
 __device__ inline int imin_wave(int v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
@@ -126,7 +139,6 @@ __global__ __launch_bounds__(kSuThreads) void k_su_run(SuArgs a) {
   (void)spare;
   int* perm = ip;                      // D (<= 64 entries reserved)
   int* cand = ip + 64;                 // C (<= 32)
-  int* flags = ip + 96;                // 2
 
   for (int e = tid; e < 2 * N * D; e += kSuThreads) lamL[e] = lamG[e];
   int bad = 0;
@@ -249,59 +261,70 @@ __global__ __launch_bounds__(kSuThreads) void k_su_run(SuArgs a) {
           Th[e] = val;
         }
         for (int e = tid; e < np * np; e += kSuThreads) Vv[e] = (e % np) == (e / np) ? 1.0 : 0.0;
-        if (tid < 2) flags[tid] = 0;
         __syncthreads();
 
         // ---- one-sided Jacobi on the columns of Theta (round-robin pairs) ----
-        {
+        // One wave runs every round: the np / 2 pairs of a round go to groups
+        // of TL lanes (the largest power of two <= 16 with np / 2 groups in 64
+        // lanes) inside the 16-lane DPP rows, whose
+        // sums take log2(TL) DPP steps; the wave's LDS accesses stay in
+        // program order, so the rounds need no barrier.
+        if (wave == 0) {
           const int P = np / 2;
-          int TL = 64;
-          while (TL * P > kSuThreads && TL > 1) TL >>= 1;
-          const int grp = tid / TL, gl = tid % TL;
+          int TL = 16;                        // a power of two: groups stay inside DPP rows
+          while (TL * P > 64) TL >>= 1;
+          const int grp = lane / TL, gl = lane % TL;
+          const bool active = grp < P;
+          // columns with |c|^2 <= 1e-30 ||Theta||_F^2 are rounding noise: no rotation
+          double fro = 0.0;
+          for (int e = lane; e < m * m; e += 64) fro += Th[e] * Th[e];
+          const double tiny = kSuJacobiZero * wave_sum(fro);
           for (int sw = 0; sw < kSuJacobiMaxSweeps; ++sw) {
+            int rotated = 0, large = 0;         // any rotation; any with |gamma| > 1e-10 sqrt(alpha beta)
             for (int rd = 0; rd < np - 1; ++rd) {
-              if (grp < P) {
-                int pa, pb;
-                if (grp == 0) { pa = np - 1; pb = rd; }
-                else { pa = (rd + grp) % (np - 1); pb = (rd - grp + np - 1) % (np - 1); }
-                double* ca = Th + (long)pa * m;
-                double* cb = Th + (long)pb * m;
-                double al = 0.0, be = 0.0, ga = 0.0;
+              int pa = 0, pb = 0;
+              if (grp == 0) { pa = np - 1; pb = rd; }
+              else { pa = (rd + grp) % (np - 1); pb = (rd - grp + np - 1) % (np - 1); }
+              double* ca = Th + (long)pa * m;
+              double* cb = Th + (long)pb * m;
+              double al = 0.0, be = 0.0, ga = 0.0;
+              if (active) {
                 for (int r = gl; r < m; r += TL) {
                   const double u = ca[r], v = cb[r];
                   al += u * u; be += v * v; ga += u * v;
                 }
-                for (int off = TL / 2; off >= 1; off >>= 1) {
-                  al += __shfl_xor(al, off);
-                  be += __shfl_xor(be, off);
-                  ga += __shfl_xor(ga, off);
-                }
-                if (ga != 0.0 && fabs(ga) > kSuJacobiTol * sqrt(al * be)) {
-                  const double zeta = (be - al) / (2.0 * ga);
-                  const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                  const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-                  for (int r = gl; r < m; r += TL) {
-                    const double u = ca[r], v = cb[r];
-                    ca[r] = cs * u - sn * v;
-                    cb[r] = sn * u + cs * v;
-                  }
-                  double* va = Vv + (long)pa * np;
-                  double* vb = Vv + (long)pb * np;
-                  for (int r = gl; r < np; r += TL) {
-                    const double u = va[r], v = vb[r];
-                    va[r] = cs * u - sn * v;
-                    vb[r] = sn * u + cs * v;
-                  }
-                  if (gl == 0) flags[sw & 1] = 1;
-                }
               }
-              __syncthreads();
-              if (rd == 0 && tid == 0) flags[(sw + 1) & 1] = 0;
+              al = group_sum(al, TL);
+              be = group_sum(be, TL);
+              ga = group_sum(ga, TL);
+              const double g2 = ga * ga, ab = al * be;
+              if (active && ga != 0.0 && al > tiny && be > tiny && g2 > kSuJacobiTol * kSuJacobiTol * ab) {
+                large |= g2 > kSuJacobiStop * kSuJacobiStop * ab;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
+                for (int r = gl; r < m; r += TL) {
+                  const double u = ca[r], v = cb[r];
+                  ca[r] = cs * u - sn * v;
+                  cb[r] = sn * u + cs * v;
+                }
+                double* va = Vv + (long)pa * np;
+                double* vb = Vv + (long)pb * np;
+                for (int r = gl; r < np; r += TL) {
+                  const double u = va[r], v = vb[r];
+                  va[r] = cs * u - sn * v;
+                  vb[r] = sn * u + cs * v;
+                }
+                rotated = 1;
+              }
+              __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             }
-            if (flags[sw & 1] == 0) break;
-            __syncthreads();
+            // quadratic convergence: after a sweep whose rotations were all
+            // below 1e-10 the remaining off-diagonal terms are ~1e-20
+            if (!__any(rotated) || !__any(large)) break;
           }
         }
+        __syncthreads();
 
         // ---- singular values, the D largest, new weights ----
         for (int c = tid; c < m; c += kSuThreads) {
