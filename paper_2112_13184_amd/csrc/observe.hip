@@ -168,28 +168,48 @@ DT tensordot(Context& c, const DT& A, const std::vector<int>& axA, const DT& B, 
 
 DT tensor_transpose(Context& c, const DT& A, const std::vector<int>& perm) { return transpose(c, A, perm); }
 
+// B = A / tr(A), A dim x dim: one workgroup
+__global__ __launch_bounds__(256) void k_trace_scale(const double* A, double* B, int dim) {
+  __shared__ double red[256];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < dim; i += 256) t += A[(long)i * dim + i];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int h = 128; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double inv = 1.0 / red[0];
+  for (long e = threadIdx.x; e < (long)dim * dim; e += 256) B[e] = A[e] * inv;
+}
+
 DT bond_environment(Context& c, int site, int dir, const double* Ei, const double* Ej, int r) {
   const int rot = (dir == 0) ? 0 : 3;   // +y becomes +x three quarter turns on
   int x = site % c.Lx, y = site / c.Lx;
   for (int i = 0; i < rot; ++i) { int t = x; x = -y; y = t; }
   const int s = view_site(c, rot, x, y), t = view_site(c, rot, x + 1, y);
   CTM_CHECK(s == site, -3, "bond_environment: view bookkeeping");
-  View vs = view_of(c, s, rot), vt = view_of(c, t, rot);
+  // The left half (C1 T4 C4, T1 / X_i / T3 of site s) in the frame `rot`, the
+  // right half as a left half of site t in the frame turned two more quarter
+  // turns (there C3 T2 C2 form its left boundary and T3 / T1 sit above /
+  // below); the two meet on the cut bond and on the edge legs between the
+  // columns, so neither half carries the other's open legs.
+  const int rot2 = (rot + 2) % 4;
+  View vs = view_of(c, s, rot), vt = view_of(c, t, rot2);
   const long D = c.D;
   DT ei = make(const_cast<double*>(Ei), {D, D, D, D, (long)r});
   DT ej = make(const_cast<double*>(Ej), {D, D, D, D, (long)r});
-  if (rot == 3) {                      // a quarter turn counter-clockwise three times
-    ei = transpose(c, ei, {3, 0, 1, 2, 4});
-    ej = transpose(c, ej, {3, 0, 1, 2, 4});
-  }
-  DT LB = left_boundary(c, vs), RB = right_boundary(c, vt);
-  DT X = column(c, LB, vs.T[0], vs.T[2], ei, ei, true);
-  X = column(c, X, vt.T[0], vt.T[2], ej, ej, true);
-  DT R = close_lr(c, X, RB);                     // [ri, ri', rj, rj']
+  for (int q = 0; q < rot; ++q) ei = transpose(c, ei, {1, 2, 3, 0, 4});    // a quarter turn each
+  for (int q = 0; q < rot2; ++q) ej = transpose(c, ej, {1, 2, 3, 0, 4});
+  DT Xi = column(c, left_boundary(c, vs), vs.T[0], vs.T[2], ei, ei, true);   // [t1', R, t3', ri, ri']
+  DT Xj = column(c, left_boundary(c, vt), vt.T[0], vt.T[2], ej, ej, true);   // [t3-side, R, t1-side, rj, rj']
+  // Xi's t1' (right leg of T1 of s) meets the leg of T1 of t that Xj leaves
+  // as its third index, Xi's t3' its first
+  DT R = tdot(c, Xi, {0, 1, 2}, Xj, {2, 1, 0});   // [ri, ri', rj, rj']
   R = transpose(c, R, {0, 2, 1, 3});             // [(ri, rj), (ri', rj')]
   const int dim = r * r;
   DT N = make(c.arena.alloc((size_t)dim * dim), {(long)dim, (long)dim});
-  hipLaunchKernelGGL(k_trace_normalize, dim3(1), dim3(64), 0, c.st, R.p, N.p, dim);
+  hipLaunchKernelGGL(k_trace_scale, dim3(1), dim3(256), 0, c.st, R.p, N.p, dim);
   CTM_HIP(hipGetLastError());
   return N;
 }
