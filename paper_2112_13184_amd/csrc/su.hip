@@ -89,6 +89,19 @@ __device__ inline const double* leg_weight(const double* lamL, int site, int lg,
   }
 }
 
+// 1 / sqrt(x), x > 0 normal: the hardware estimate and two Newton steps
+// y += y (1 - x y^2) / 2 (each roughly doubles the correct bits).
+__device__ inline double su_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double h = x * y;
+    const double e = fma(-h, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Sum over aligned groups of TL lanes (TL = 1, 2, 4, 8 or 16) inside the
 // 16-lane DPP rows; every lane of a group receives its group's sum.  All 64
 // lanes must be active.
@@ -300,9 +313,15 @@ __global__ __launch_bounds__(kSuThreads) void k_su_run(SuArgs a) {
               const double g2 = ga * ga, ab = al * be;
               if (active && ga != 0.0 && al > tiny && be > tiny && g2 > kSuJacobiTol * kSuJacobiTol * ab) {
                 large |= g2 > kSuJacobiStop * kSuJacobiStop * ab;
-                const double zeta = (be - al) / (2.0 * ga);
-                const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                const double cs = rsqrt(1.0 + tt * tt), sn = cs * tt;
+                // the angle zeroing the inner product: tan(2 theta) = 2 ga / (be - al);
+                // with dd = be - al, q = sqrt(dd^2 + 4 ga^2), w = sqrt(2 q (q + |dd|)):
+                // cos = (q + |dd|) / w, sin = 2 ga sgn(dd) / w, from two reciprocal
+                // square roots and no division
+                const double dd = be - al, ad = fabs(dd);
+                const double X = dd * dd + 4.0 * g2;
+                const double q = X * su_rsqrt(X);
+                const double inv = su_rsqrt(2.0 * q * (q + ad));
+                const double cs = (q + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
                 for (int r = gl; r < m; r += TL) {
                   const double u = ca[r], v = cb[r];
                   ca[r] = cs * u - sn * v;
