@@ -419,7 +419,9 @@ typedef struct {
 typedef struct ctm_su ctm_su;
 
 /* Copies gamma [batch][N][D^4 d] and lambda [batch][N][2][D] (host) to the
- * device.  CTM_EINVAL for a shape outside the limits. */
+ * device.  CTM_EINVAL, before any device call, for a shape outside the
+ * limits, a non-finite tensor entry or a weight that is negative or not
+ * finite. */
 ctm_status ctm_su_create(const ctm_su_config* cfg, const double* gamma, const double* lambda, ctm_su** out);
 /* Eq. (3): H [batch][N][2][d^2][d^2] and tau [batch] (host, finite,
  * tau >= 0); the gates exp(-tau H) are formed on the device (scaling and

@@ -807,6 +807,12 @@ ctm_status ctm_su_create(const ctm_su_config* cfg, const double* gamma, const do
     CTM_CHECK(S.m <= 64, CTM_EINVAL, "min(D^3, D d) * d must be <= 64");
     const int cap = su_kernel_class(S);
     CTM_CHECK(cap >= 0, CTM_EINVAL, "bond tensors too large for one workgroup's LDS");
+    {
+      const long B = cfg->batch, T = (long)S.N * S.R * S.D * S.d, L = (long)S.N * 2 * S.D;
+      for (long e = 0; e < B * T; ++e) CTM_CHECK(std::isfinite(gamma[e]), CTM_EINVAL, "site tensors must be finite");
+      for (long e = 0; e < B * L; ++e)
+        CTM_CHECK(std::isfinite(lambda[e]) && lambda[e] >= 0.0, CTM_EINVAL, "bond weights must be finite and >= 0");
+    }
     auto su = new ctm_su();
     try {
       su->cfg = *cfg;

@@ -71,3 +71,31 @@ def test_footprint_grows_with_chi(lib):
 
 def test_package_reexports_binding():
     assert pkg.Ctm is B.Ctm and callable(pkg.load)
+
+
+def test_simple_update_rejects_bad_arguments_before_any_device_call(lib):
+    def create(Lx, Ly, D, d, batch, gamma, lam):
+        cfg = B.ctm_su_config(Lx, Ly, d, D, batch, None)
+        h = ctypes.c_void_p()
+        g = (ctypes.c_double * max(len(gamma), 1))(*gamma)
+        lm = (ctypes.c_double * max(len(lam), 1))(*lam)
+        st = lib.ctm_su_create(ctypes.byref(cfg), ctypes.cast(g, B._DP), ctypes.cast(lm, B._DP), ctypes.byref(h))
+        return st, h.value
+    N, D, d = 4, 2, 2
+    gam = [0.5] * (N * D ** 4 * d)
+    lam = [1.0] * (N * 2 * D)
+    assert create(2, 1, D, d, 1, gam[:32], lam[:8])[0] == B.CTM_EINVAL      # Ly = 1
+    assert create(2, 2, 9, d, 1, gam, lam)[0] == B.CTM_EINVAL                # D > 8
+    assert create(2, 2, 8, 3, 1, gam, lam)[0] == B.CTM_EINVAL                # core of 72 columns
+    assert create(2, 2, D, d, 0, gam, lam)[0] == B.CTM_EINVAL                # empty batch
+    bad_w = list(lam)
+    bad_w[3] = -0.1
+    assert create(2, 2, D, d, 1, gam, bad_w)[0] == B.CTM_EINVAL              # negative weight
+    bad_g = list(gam)
+    bad_g[7] = float("nan")
+    st, h = create(2, 2, D, d, 1, bad_g, lam)
+    assert st == B.CTM_EINVAL and not h
+    assert lib.ctm_su_last_error(None)
+    assert lib.ctm_su_run(None, 1) == B.CTM_EINVAL
+    assert lib.ctm_fu_step(None, None, 0.01, 1, 1) == B.CTM_EINVAL
+    lib.ctm_su_free(None)
