@@ -48,10 +48,15 @@ Readings (the paper does not fix these)
   lam' = S[:D] / ||S[:D]||_2; G_i' = U[(a, p), k] divided by the weights of
   a, G_j' likewise from V.  A weight w <= 1e-13 is divided out as 0 (its index
   carries no state).
-* Sign of a kept singular pair: the first entry (in (a, p) order) of U[:, k]
-  whose modulus is at least (1 - 1e-8) of the column's largest is made
-  positive, V[:, k] flipped with it.  The tolerance makes the choice
-  insensitive to rounding when symmetric entries tie.
+* Sign (phase) of a kept singular pair: the first entry (in (a, p) order) of
+  U[:, k] whose modulus is at least (1 - 1e-8) of the column's largest is made
+  real and positive, the pair's V column taking the same phase so that
+  U S V^H is unchanged.  The tolerance makes the choice insensitive to
+  rounding when symmetric entries tie.
+* Complex tensors and Hamiltonians (Sec. 5.2 allows complex tensors): the
+  bra is the complex conjugate of the ket; the two-site matrix is
+  Psi = U S V^H, the new right tensor is the transpose of V^H (no conjugate:
+  the ket tensors meet directly on the bond); the weights stay real.
 * The initial weights are supplied by the caller (all ones in the tests).
 
 Parity status
@@ -106,7 +111,8 @@ def bond(Lx, Ly, s, direction):
 
 def gate(H, tau):
     """Trotter gate exp(-tau H) of a two-site Hamiltonian (Eq. (3))."""
-    return expm(-tau * np.asarray(H, dtype=np.float64))
+    H = np.asarray(H)
+    return expm(-tau * (H if np.iscomplexobj(H) else H.astype(np.float64)))
 
 
 def _scale_legs(G, ws, skip, inverse=False):
@@ -138,7 +144,7 @@ def _leg_back(B, leg):
 
 
 def sign_fix(U, Vt):
-    """Sign rule of the kept singular pairs (see the module docstring)."""
+    """Sign (phase) rule of the kept singular pairs (see the module docstring)."""
     U = U.copy()
     Vt = Vt.copy()
     for k in range(U.shape[1]):
@@ -147,7 +153,11 @@ def sign_fix(U, Vt):
         if m == 0.0:
             continue
         first = int(np.argmax(col >= (1.0 - SIGN_TOL) * m))
-        if U[first, k] < 0.0:
+        if np.iscomplexobj(U):
+            ph = U[first, k] / abs(U[first, k])
+            U[:, k] = U[:, k] * np.conj(ph)
+            Vt[k, :] = Vt[k, :] * ph
+        elif U[first, k] < 0.0:
             U[:, k] = -U[:, k]
             Vt[k, :] = -Vt[k, :]
     return U, Vt
@@ -166,7 +176,7 @@ def bond_update(Gi, Gj, wi, wj, lam, g, leg_i, leg_j, D):
     Psi = two_site(Gi, Gj, wi, wj, lam, leg_i, leg_j)
     Da = Psi.shape[:3]
     Db = Psi.shape[4:7]
-    g4 = np.asarray(g, dtype=np.float64).reshape(d, d, d, d)
+    g4 = np.asarray(g).reshape(d, d, d, d)
     Psi = np.einsum("PQpq,abcpefgq->abcPefgQ", g4, Psi)
     M = Psi.reshape(int(np.prod(Da)) * d, int(np.prod(Db)) * d)
     U, S_all, Vt = np.linalg.svd(M, full_matrices=False)
@@ -208,7 +218,8 @@ def simple_update(G, lam_h, lam_v, H, tau, Lx, Ly, nsteps):
 
     Returns new (G, lam_h, lam_v) lists; the inputs are not modified."""
     assert Lx >= 2 and Ly >= 2
-    G = [np.array(g, dtype=np.float64) for g in G]
+    cplx = any(np.iscomplexobj(g) for g in G) or any(np.iscomplexobj(np.asarray(h)) for row in H for h in row)
+    G = [np.array(g, dtype=np.complex128 if cplx else np.float64) for g in G]
     lam_h = [np.array(v, dtype=np.float64) for v in lam_h]
     lam_v = [np.array(v, dtype=np.float64) for v in lam_v]
     D = G[0].shape[0]
@@ -242,7 +253,7 @@ def mfe_rho_site(G, lam_h, lam_v, Lx, Ly, s):
     A = _scale_legs(G[s], leg_weights(lam_h, lam_v, Lx, Ly, s), skip=-1)
     d = A.shape[4]
     A = A.reshape(-1, d)
-    return A.T @ A
+    return A.T @ A.conj()
 
 
 def mfe_rho_bond(G, lam_h, lam_v, Lx, Ly, s, direction):
@@ -257,12 +268,12 @@ def mfe_rho_bond(G, lam_h, lam_v, Lx, Ly, s, direction):
     d = G[i].shape[4]
     Da = int(np.prod(Psi.shape[:3]))
     X = Psi.reshape(Da, d, Da, d).transpose(1, 3, 0, 2).reshape(d * d, Da * Da)
-    return X @ X.T
+    return X @ X.conj().T
 
 
 def expect(rho, op):
-    """<O> = sum rho[in, out] O[out, in] / tr rho."""
-    return float(np.sum(rho.T * op) / np.trace(rho))
+    """<O> = sum rho[in, out] O[out, in] / tr rho (real part: Hermitian O)."""
+    return float(np.real(np.sum(rho.T * op) / np.trace(rho)))
 
 
 def mfe_energy(G, lam_h, lam_v, Lx, Ly, H, onsite=None):

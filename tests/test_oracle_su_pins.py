@@ -161,3 +161,69 @@ def test_weights_are_normalised_sorted_and_gauge_fixed(D):
         m = np.abs(col).max()
         first = int(np.argmax(np.abs(col) >= (1 - su.SIGN_TOL) * m))
         assert col[first] > 0
+
+
+SY = np.array([[0.0, -1.0j], [1.0j, 0.0]])
+
+
+def test_complex_field_along_y_is_a_rotation():
+    """H = -(h/4)(sy 1 + 1 sy) (complex): exp(tau h sy) per step on each site
+    takes |up> to cosh(a)|up> + i sinh(a)|down>, a = N tau h, so
+    <sy> = tanh(2a); the state stays a product."""
+    h, tau, n = 0.9, 0.05, 8
+    Hy = -0.25 * h * (np.kron(SY, wl.ID2) + np.kron(wl.ID2, SY))
+    G, lh, lv = _start([np.array([1.0, 0.0])] * N, 2)
+    G, lh, lv = su.simple_update(G, lh, lv, [[Hy, Hy]] * N, tau, LX, LY, n)
+    assert np.iscomplexobj(G[0])
+    for s in range(N):
+        rho = su.mfe_rho_site(G, lh, lv, LX, LY, s)
+        assert abs(su.expect(rho, SY) - math.tanh(2 * n * tau * h)) < 1e-13
+        assert abs(su.expect(rho, wl.SX)) < 1e-13
+        assert lh[s][1] < 1e-14 and lv[s][1] < 1e-14
+
+
+def test_local_unitary_rotation_of_a_real_problem():
+    """Rotating every site's physical index by U_s = diag(1, exp(i phi_s))
+    (tensors U_s A_s, bond Hamiltonians (U_i x U_j) H (U_i x U_j)^H, complex)
+    gives the same evolution: weights and mean-field energies equal those of
+    the real problem.  A conjugate missing or misplaced anywhere breaks it."""
+    D = 2
+    A = wl.random_itps(LX, LY, D, 2, seed=13)
+    ones = [np.ones(D) for _ in range(N)]
+    Hb = wl.tfim_bond(2.5)
+    H = [[Hb, Hb] for _ in range(N)]
+    Gr, lhr, lvr = su.simple_update(A, ones, ones, H, 0.02, LX, LY, 15)
+    phis = [0.3, 1.1, -0.7, 2.0]
+    Us = [np.diag([1.0, np.exp(1j * p)]) for p in phis]
+    Ac = [np.einsum("PQ,lurdQ->lurdP", Us[s], A[s]) for s in range(N)]
+    Hc = []
+    for s in range(N):
+        row = []
+        for direction in (0, 1):
+            i, _, j, _ = su.bond(LX, LY, s, direction)
+            UU = np.kron(Us[i], Us[j])
+            row.append(UU @ Hb @ UU.conj().T)
+        Hc.append(row)
+    Gc, lhc, lvc = su.simple_update(Ac, ones, ones, Hc, 0.02, LX, LY, 15)
+    for s in range(N):
+        assert np.abs(lhc[s] - lhr[s]).max() < 1e-12 and np.abs(lvc[s] - lvr[s]).max() < 1e-12
+    assert abs(su.mfe_energy(Gc, lhc, lvc, LX, LY, Hc) - su.mfe_energy(Gr, lhr, lvr, LX, LY, H)) < 1e-12
+
+
+def test_complex_dimers_follow_the_exact_two_site_evolution():
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    Hd = X + X.conj().T
+    phis = [rng.standard_normal(2) + 1j * rng.standard_normal(2) for _ in range(N)]
+    tau, n = 0.03, 6
+    H = [[Hd if s in (0, 2) else ZERO4, ZERO4] for s in range(N)]
+    G = [np.zeros((2, 2, 2, 2, 2), dtype=complex) for _ in range(N)]
+    for s in range(N):
+        G[s][0, 0, 0, 0, :] = phis[s]
+    ones = [np.ones(2) for _ in range(N)]
+    G, lh, lv = su.simple_update(G, ones, ones, H, tau, LX, LY, n)
+    for s in (0, 2):
+        psi = expm(-n * tau * Hd) @ np.kron(phis[s], phis[s + 1])
+        psi = psi / np.linalg.norm(psi)
+        rho = su.mfe_rho_bond(G, lh, lv, LX, LY, s, 0)
+        assert np.abs(rho / np.trace(rho) - np.outer(psi, psi.conj())).max() < 1e-13
