@@ -406,7 +406,8 @@ ctm_status ctm_get_tensors(ctm_ctx* ctx, double* tensors);
  * within 1e-8 of the largest modulus positive.
  * Limits: Lx, Ly >= 2, Lx*Ly <= 16, 1 <= D <= 8, 1 <= d <= 4,
  * min(D^3, D d) d <= 64, and the two reduced bond tensors must fit one
- * workgroup's LDS (D = 8, d = 2 fits); batch <= 65535.
+ * workgroup's LDS (D = 8, d = 2 fits in real arithmetic, D = 6, d = 2 in
+ * complex); batch <= 65535.
  * ------------------------------------------------------------------------ */
 typedef struct {
   int Lx, Ly;      /* unit cell, both >= 2                                     */
@@ -414,6 +415,13 @@ typedef struct {
   int D;           /* bond dimension kept by the truncation                     */
   int batch;       /* independent problems evolved together                     */
   void* stream;    /* hipStream_t, or NULL for a private stream                 */
+  int complex_tensors;  /* 1: complex site tensors, Hamiltonians, gates and
+                           density matrices, stored as (re, im) pairs of
+                           doubles (every such array twice as long); the bra
+                           is conj(ket); weights and energies stay real.
+                           The phase of each kept pair makes the first
+                           near-largest entry of its left vector real and
+                           positive.  0: real (FP64).                       */
 } ctm_su_config;
 
 typedef struct ctm_su ctm_su;

@@ -38,7 +38,7 @@ EXPORTS = (
 
 class ctm_su_config(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("d", ctypes.c_int), ("D", ctypes.c_int),
-                ("batch", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("batch", ctypes.c_int), ("stream", ctypes.c_void_p), ("complex_tensors", ctypes.c_int)]
 
 
 class CtmError(RuntimeError):
@@ -455,18 +455,22 @@ class SimpleUpdate:
     independent problems, and their mean-field-environment density matrices.
 
     gamma: [batch][N][D, D, D, D, d] (or a list of per-problem lists of site
-    tensors), lam: [batch][N][2][D] bond weights (see include/ctm.h)."""
+    tensors), lam: [batch][N][2][D] bond weights (see include/ctm.h).  With
+    complex_tensors the tensors, Hamiltonians and density matrices are
+    complex128 arrays (passed to the library as (re, im) pairs)."""
 
-    def __init__(self, gamma, lam, Lx, Ly, D, d=2, batch=None, stream=None):
+    def __init__(self, gamma, lam, Lx, Ly, D, d=2, batch=None, stream=None, complex_tensors=False):
         lib = load()
-        g = _f64(np.asarray(gamma, dtype=np.float64)).reshape(-1)
+        self.cplx = bool(complex_tensors)
+        g = self._scal(gamma)
         lm = _f64(np.asarray(lam, dtype=np.float64)).reshape(-1)
         N = Lx * Ly
+        w = 2 if self.cplx else 1
         if batch is None:
-            batch = g.size // (N * D ** 4 * d)
-        if g.size != batch * N * D ** 4 * d or lm.size != batch * N * 2 * D:
+            batch = g.size // (N * D ** 4 * d * w)
+        if g.size != batch * N * D ** 4 * d * w or lm.size != batch * N * 2 * D:
             raise CtmError(CTM_EINVAL, "gamma / lambda sizes do not match the shape")
-        cfg = ctm_su_config(Lx, Ly, d, D, int(batch), stream)
+        cfg = ctm_su_config(Lx, Ly, d, D, int(batch), stream, 1 if self.cplx else 0)
         h = ctypes.c_void_p()
         st = lib.ctm_su_create(ctypes.byref(cfg), _dp(g), _dp(lm), ctypes.byref(h))
         if st != CTM_OK:
@@ -474,15 +478,27 @@ class SimpleUpdate:
         self._lib, self._h = lib, h
         self.Lx, self.Ly, self.D, self.d, self.batch, self.N = Lx, Ly, D, d, int(batch), N
 
+    def _scal(self, x):
+        """Flat FP64 buffer of a tensor argument ((re, im) pairs when complex)."""
+        if self.cplx:
+            return np.ascontiguousarray(np.asarray(x, dtype=np.complex128)).reshape(-1).view(np.float64)
+        return _f64(np.asarray(x, dtype=np.float64)).reshape(-1)
+
+    def _out(self, shape):
+        return np.empty(shape, dtype=np.complex128 if self.cplx else np.float64)
+
+    def _ptr(self, a):
+        return a.reshape(-1).view(np.float64).ctypes.data_as(_DP) if self.cplx else _dp(a)
+
     def _check(self, st):
         if st != CTM_OK:
             raise CtmError(st, (self._lib.ctm_su_last_error(self._h) or b"").decode())
 
     def set_hamiltonians(self, H, tau):
         """H: [batch][N][2][d^2][d^2]; tau: scalar or [batch]."""
-        Hh = _f64(np.asarray(H, dtype=np.float64)).reshape(-1)
+        Hh = self._scal(H)
         t = _f64(np.broadcast_to(np.asarray(tau, dtype=np.float64), (self.batch,)))
-        if Hh.size != self.batch * self.N * 2 * self.d ** 4:
+        if Hh.size != self.batch * self.N * 2 * self.d ** 4 * (2 if self.cplx else 1):
             raise CtmError(CTM_EINVAL, "H size does not match the shape")
         self._check(self._lib.ctm_su_set_hamiltonians(self._h, _dp(Hh), _dp(t)))
 
@@ -496,9 +512,9 @@ class SimpleUpdate:
 
     def get(self):
         """(gamma [batch, N, D, D, D, D, d], lam [batch, N, 2, D])."""
-        g = np.empty((self.batch, self.N) + (self.D,) * 4 + (self.d,))
+        g = self._out((self.batch, self.N) + (self.D,) * 4 + (self.d,))
         lm = np.empty((self.batch, self.N, 2, self.D))
-        self._check(self._lib.ctm_su_get(self._h, _dp(g), _dp(lm)))
+        self._check(self._lib.ctm_su_get(self._h, self._ptr(g), _dp(lm)))
         return g, lm
 
     def get_itps(self, device_ptr=None):
@@ -507,15 +523,15 @@ class SimpleUpdate:
         if device_ptr is not None:
             self._check(self._lib.ctm_su_get_itps(self._h, ctypes.cast(ctypes.c_void_p(int(device_ptr)), _DP), 1))
             return None
-        a = np.empty((self.batch, self.N) + (self.D,) * 4 + (self.d,))
-        self._check(self._lib.ctm_su_get_itps(self._h, _dp(a), 0))
+        a = self._out((self.batch, self.N) + (self.D,) * 4 + (self.d,))
+        self._check(self._lib.ctm_su_get_itps(self._h, self._ptr(a), 0))
         return a
 
     def mfe(self):
         """(rho1 [batch, N, d, d], rho2 [batch, N, 2, d^2, d^2]), unit trace."""
-        r1 = np.empty((self.batch, self.N, self.d, self.d))
-        r2 = np.empty((self.batch, self.N, 2, self.d ** 2, self.d ** 2))
-        self._check(self._lib.ctm_su_mfe(self._h, _dp(r1), _dp(r2)))
+        r1 = self._out((self.batch, self.N, self.d, self.d))
+        r2 = self._out((self.batch, self.N, 2, self.d ** 2, self.d ** 2))
+        self._check(self._lib.ctm_su_mfe(self._h, self._ptr(r1), self._ptr(r2)))
         return r1, r2
 
     def mfe_energy(self, onsite=None):
@@ -524,7 +540,7 @@ class SimpleUpdate:
         be = np.empty((self.batch, self.N, 2))
         o = None
         if onsite is not None:
-            o = _f64(np.broadcast_to(np.asarray(onsite, dtype=np.float64), (self.batch, self.d, self.d)))
+            o = self._scal(np.broadcast_to(np.asarray(onsite), (self.batch, self.d, self.d)))
         self._check(self._lib.ctm_su_mfe_energy(self._h, _dp(o) if o is not None else None, _dp(e), _dp(be)))
         return e, be
 

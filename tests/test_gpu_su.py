@@ -368,3 +368,119 @@ def test_field_scan_pipeline_trends_and_ctmrg_parity(lib):
     assert all(a > b for a, b in zip(sz, sz[1:]))
     assert all(a < b for a, b in zip(sx, sx[1:]))
     assert sz[-1] < 0.02 and sx[-1] > 0.45
+
+
+SY = np.array([[0.0, -1.0j], [1.0j, 0.0]])
+
+
+def _complex_problem(D, seed, d=2):
+    rng = np.random.default_rng(seed)
+    G0 = [(rng.standard_normal((D,) * 4 + (d,)) + 1j * rng.standard_normal((D,) * 4 + (d,))) for _ in range(4)]
+    G0 = [g / np.abs(g).max() for g in G0]
+    H = []
+    for _ in range(4):
+        row = []
+        for _ in range(2):
+            X = rng.standard_normal((d * d, d * d)) + 1j * rng.standard_normal((d * d, d * d))
+            row.append(0.5 * (X + X.conj().T))
+        H.append(row)
+    return G0, H
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_complex_random_state_parity(lib, D):
+    """Complex tensors and a random complex Hermitian Hamiltonian per bond:
+    weights, tensors (with the full weights) and energies against the
+    oracle."""
+    Lx = Ly = 2
+    N = 4
+    G0, H = _complex_problem(D, 50 + D)
+    ones = [np.ones(D) for _ in range(N)]
+    lam = np.ones((1, N, 2, D))
+    s = lib.SimpleUpdate(np.stack(G0)[None], lam, Lx, Ly, D, complex_tensors=True)
+    s.set_hamiltonians(np.asarray(H)[None], 0.02)
+    s.run(10)
+    g, lm = s.get()
+    e, _ = s.mfe_energy()
+    r1, r2 = s.mfe()
+    s.free()
+    Go, lho, lvo = su.simple_update(G0, ones, ones, H, 0.02, Lx, Ly, 10)
+    gpu = dict(G=list(g[0]), lh=[lm[0, i, 0] for i in range(N)], lv=[lm[0, i, 1] for i in range(N)], e=e[0])
+    orc = dict(G=Go, lh=lho, lv=lvo, e=su.mfe_energy(Go, lho, lvo, Lx, Ly, H))
+    compare(gpu, orc, Lx, Ly, tag=f"complex D={D}")
+    for i in range(N):
+        ro = su.mfe_rho_site(Go, lho, lvo, Lx, Ly, i)
+        assert np.abs(r1[0, i] - ro / np.trace(ro)).max() < 1e-10
+        rb = su.mfe_rho_bond(Go, lho, lvo, Lx, Ly, i, 1)
+        assert np.abs(r2[0, i, 1] - rb / np.trace(rb)).max() < 1e-10
+
+
+def test_complex_field_along_y(lib):
+    h, tau, n = 0.9, 0.05, 8
+    Hy = -0.25 * h * (np.kron(SY, wl.ID2) + np.kron(wl.ID2, SY))
+    G0 = np.stack(wl.product_itps([np.array([1.0, 0.0])] * 4, 2)).astype(complex)
+    s = lib.SimpleUpdate(G0[None], np.ones((1, 4, 2, 2)), 2, 2, 2, complex_tensors=True)
+    s.set_hamiltonians(np.asarray(uniform_H(Hy, 4))[None], tau)
+    s.run(n)
+    r1, _ = s.mfe()
+    s.free()
+    for i in range(4):
+        assert abs(np.real(np.trace(r1[0, i] @ SY)) - math.tanh(2 * n * tau * h)) < 1e-12   # sum rho[in][out] O[out][in]
+
+
+def test_complex_local_unitary_rotation_matches_the_real_problem(lib):
+    """The local-unitary pin of the oracle, on the GPU: a real problem and its
+    rotation by U_s = diag(1, exp(i phi_s)) give the same weights and energies."""
+    Lx = Ly = 2
+    N, D = 4, 2
+    A = wl.random_itps(Lx, Ly, D, 2, seed=13)
+    Hb = wl.tfim_bond(2.5)
+    H = uniform_H(Hb, N)
+    lam = np.ones((1, N, 2, D))
+    sr = lib.SimpleUpdate(np.stack(A)[None], lam, Lx, Ly, D)
+    sr.set_hamiltonians(np.asarray(H)[None], 0.02)
+    sr.run(15)
+    _, lmr = sr.get()
+    er, _ = sr.mfe_energy()
+    sr.free()
+    Us = [np.diag([1.0, np.exp(1j * p)]) for p in (0.3, 1.1, -0.7, 2.0)]
+    Ac = np.stack([np.einsum("PQ,lurdQ->lurdP", Us[s], A[s]) for s in range(N)])
+    Hc = []
+    for s in range(N):
+        row = []
+        for direction in (0, 1):
+            i, _, j, _ = su.bond(Lx, Ly, s, direction)
+            UU = np.kron(Us[i], Us[j])
+            row.append(UU @ Hb @ UU.conj().T)
+        Hc.append(row)
+    sc = lib.SimpleUpdate(Ac[None], lam, Lx, Ly, D, complex_tensors=True)
+    sc.set_hamiltonians(np.asarray(Hc)[None], 0.02)
+    sc.run(15)
+    _, lmc = sc.get()
+    ec, _ = sc.mfe_energy()
+    sc.free()
+    assert np.abs(lmc - lmr).max() < 1e-12
+    assert abs(ec[0] - er[0]) < 1e-12
+
+
+def test_complex_mode_on_real_data_equals_the_real_path(lib):
+    Lx = Ly = 2
+    N, D = 4, 3
+    A = np.stack(wl.random_itps(Lx, Ly, D, 2, seed=23))
+    H = np.asarray(uniform_H(wl.tfim_bond(3.0), N))
+    lam = np.ones((1, N, 2, D))
+    out = []
+    for cplx in (False, True):
+        s = lib.SimpleUpdate(A[None], lam, Lx, Ly, D, complex_tensors=cplx)
+        s.set_hamiltonians(H[None], 0.01)
+        s.run(10)
+        g, lm = s.get()
+        e, _ = s.mfe_energy()
+        s.free()
+        out.append((g, lm, e))
+    assert np.abs(out[1][1] - out[0][1]).max() < 1e-13
+    assert abs(out[1][2][0] - out[0][2][0]) < 1e-13
+    assert np.abs(out[1][0].imag).max() < 1e-13
+    w = [su.weighted(list(o[0][0]), [o[1][0, i, 0] for i in range(N)], [o[1][0, i, 1] for i in range(N)], Lx, Ly)
+         for o in out]
+    assert max(float(np.abs(a - b).max()) for a, b in zip(w[0], w[1])) < 1e-11
