@@ -354,18 +354,18 @@ def su_problem_inputs(hs, D, noise=1e-3, seed=2):
     return G0, gam, lam, H
 
 
-def su_bench(lib, B=256, D=4, steps=1000, tau=0.01, cpu=True):
+def su_bench(lib, B=256, D=4, steps=1000, tau=0.01, cpu=True, cplx=False):
     """Simple-update imaginary-time evolution of a field scan: B fields of the
     spin-unit transverse-field Ising model in [0, 2.5], 2x2 cell, D, tau, the
     given Trotter steps, all problems in one batch.  Device time from the
     library's HIP events around its launches."""
     hs = np.linspace(0.0, 2.5, B)
     _, gam, lam, H = su_problem_inputs(hs, D)
-    warm = lib.SimpleUpdate(gam, lam, 2, 2, D)
+    warm = lib.SimpleUpdate(gam, lam, 2, 2, D, complex_tensors=cplx)
     warm.set_hamiltonians(H, tau)
     warm.run(10)
     warm.free()
-    s = lib.SimpleUpdate(gam, lam, 2, 2, D)
+    s = lib.SimpleUpdate(gam, lam, 2, 2, D, complex_tensors=cplx)
     s.set_hamiltonians(H, tau)
     t0 = time.perf_counter()
     s.run(steps)
@@ -375,12 +375,15 @@ def su_bench(lib, B=256, D=4, steps=1000, tau=0.01, cpu=True):
     s.free()
     f = su_flops_per_update(D, 2)
     rate = updates / (gpu_ms / 1e3)
-    out = {"workload": f"su_tfim_scan_2x2_D{D}_B{B}", "problems": B, "D": D, "d": 2, "tau": tau,
+    out = {"workload": f"su_tfim_scan_2x2_D{D}_B{B}" + ("_complex" if cplx else ""), "problems": B, "D": D,
+           "d": 2, "tau": tau, "arithmetic": "complex FP64" if cplx else "FP64",
            "trotter_steps": steps, "bond_updates": updates, "gpu_ms": gpu_ms, "wall_s": wall,
            "bond_updates_per_s": rate, "launches": launches,
            "roofline": {"bound": "alu", "achieved": rate * f / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                         "frac": rate * f / 78.6e12, "flops_per_bond_update": f,
-                        "kernel": "k_su_run (one workgroup per problem, every bond in order)"},
+                        "kernel": "k_su_run (one workgroup per problem, every bond in order)",
+                        "flops_counted": "real flops of the real algorithm" + ("; complex arithmetic does about "
+                                                                             "four times as many" if cplx else "")},
            "mfe_energy_per_site": {"h_min": float(e[0]), "h_max": float(e[-1])}}
     if cpu:
         from threadpoolctl import threadpool_limits
@@ -398,7 +401,7 @@ def su_bench(lib, B=256, D=4, steps=1000, tau=0.01, cpu=True):
         out["cpu_baseline"] = {"value": n_cpu * 8 / dt, "unit": "bond updates/s", "cores": cores, "kind": "oracle",
                                "sample": f"{n_cpu} Trotter steps (8 bonds each) of one D={D} problem of the scan, "
                                          f"full SVD of the two-site matrix, NumPy/OpenBLAS FP64, {dt:.1f} s"}
-    print(f"simple update D={D}: {rate:.3g} bond updates/s ({gpu_ms:.1f} ms for {updates} updates)",
+    print(f"simple update D={D}{' complex' if cplx else ''}: {rate:.3g} bond updates/s ({gpu_ms:.1f} ms for {updates} updates)",
           file=sys.stderr, flush=True)
     return out
 
@@ -549,7 +552,8 @@ def main():
         return
     if args.su_only:
         out = {"simple_update": su_bench(lib, cpu=not args.no_cpu_baseline),
-               "simple_update_d2": su_bench(lib, D=2, cpu=False), "ex1_scan": ex1_scan(lib),
+               "simple_update_d2": su_bench(lib, D=2, cpu=False),
+               "simple_update_complex": su_bench(lib, cpu=False, cplx=True), "ex1_scan": ex1_scan(lib),
                "full_update": fu_bench(lib, cpu=not args.no_cpu_baseline)}
         print(json.dumps(out), flush=True)
         return
@@ -611,6 +615,7 @@ def main():
         out["d8_chi256"] = big_bench(lib, args.big_sweeps)
     if args.su:
         out["simple_update"] = su_bench(lib, cpu=not args.no_cpu_baseline)
+        out["simple_update_complex"] = su_bench(lib, cpu=False, cplx=True)
         out["ex1_scan"] = ex1_scan(lib)
         # the oracle's full-update bond update takes about a minute: its CPU leg
         # runs with --su-only
