@@ -236,7 +236,11 @@ ctm_status ctm_move_count(const ctm_ctx* ctx, int64_t* moves);
 ctm_status ctm_cut_stats(const ctm_ctx* ctx, int64_t counts[3]);
 
 /* Per-phase GPU timing with HIP events recorded on the context's stream
- * around every launch of a phase, while enabled.  Phases:
+ * around the launches of the timed phases, while enabled: on = 1 times every
+ * phase, on = 2 the sketch GEMMs only, on = 0 stops.  Each pair of events
+ * leaves a short idle gap (about 10 us) on the stream; the four sketch
+ * products of one application of M (or M^T) share one pair, so their ms
+ * include the split-K reductions between them.  Phases:
  *   0 other contraction GEMMs (edge-corner products, projector formation
  *                     P~ = G G V', the edge renormalisation, dense-mode M)
  *   1 sketch GEMMs    (the randomized SVD's products of an n x n enlarged
@@ -254,7 +258,7 @@ typedef struct {
   double ms[CTM_NPHASE];
   double flops[CTM_NPHASE];
 } ctm_timing;
-ctm_status ctm_timing_enable(ctm_ctx* ctx, int on);   /* on != 0 also clears the counters */
+ctm_status ctm_timing_enable(ctm_ctx* ctx, int on);   /* 0, 1 or 2; also clears the counters */
 ctm_status ctm_timing_read(ctm_ctx* ctx, ctm_timing* out);
 
 /* Device memory a context with this configuration allocates (resident state

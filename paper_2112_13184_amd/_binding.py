@@ -358,7 +358,8 @@ class Ctm:
         return tuple(int(v) for v in c)
 
     def ctm_timing_enable(self, on=True):
-        self._check(self._lib.ctm_timing_enable(self._h, 1 if on else 0))
+        """on: False (off), True or 1 (every phase), 2 (the sketch GEMMs only)."""
+        self._check(self._lib.ctm_timing_enable(self._h, int(on)))
 
     def ctm_timing_read(self):
         t = ctm_timing()

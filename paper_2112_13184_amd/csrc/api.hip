@@ -408,11 +408,12 @@ ctm_status ctm_cut_stats(const ctm_ctx* ctx, int64_t counts[3]) {
 }
 
 ctm_status ctm_timing_enable(ctm_ctx* ctx, int on) {
-  if (!ctx) return CTM_EINVAL;
+  if (!ctx || on < 0 || on > 2) return CTM_EINVAL;
   return guarded(ctx, [&] {
     CTM_HIP(hipStreamSynchronize(ctx->c.st));
     ctx->c.timer.clear();
-    ctx->c.timer.on = (on != 0);
+    // 1: every phase; 2: the sketch GEMMs only
+    ctx->c.timer.mask = on == 2 ? (1u << ctm::PhaseTimer::SKETCH) : on ? (1u << ctm::PhaseTimer::N) - 1 : 0u;
   });
 }
 

@@ -57,10 +57,18 @@ struct DT {
 // Per-phase launch timing with HIP events on the context stream.
 struct PhaseTimer {
   enum { EDGE = 0, SKETCH = 1, ABSORB = 2, LINALG = 3, OTHER = 4, N = 5 };
-  bool on = false;
+  // phases timed (bit per phase); each pair of events leaves a dispatch gap
+  // of about 10 us on the stream, so a run can time its dominant phase only
+  unsigned mask = 0;
+  // an open group (one pair of events around several launches of a phase):
+  // the timed() calls inside it add their launches and flops to it
+  bool grouped = false;
+  int group_phase = 0;
+  int64_t group_launches = 0;
+  double group_flops = 0.0;
   std::vector<hipEvent_t> pool;
   size_t next = 0;
-  struct Rec { int phase; hipEvent_t a, b; double flops; };
+  struct Rec { int phase; hipEvent_t a, b; double flops; int64_t launches; };
   std::vector<Rec> recs;
   int64_t launches[N] = {};
   double ms[N] = {}, flops[N] = {};
@@ -82,7 +90,7 @@ struct PhaseTimer {
       float t = 0.f;
       CTM_HIP(hipEventSynchronize(r.b));
       CTM_HIP(hipEventElapsedTime(&t, r.a, r.b));
-      launches[r.phase] += 1;
+      launches[r.phase] += r.launches;
       ms[r.phase] += t;
       flops[r.phase] += r.flops;
     }
@@ -201,15 +209,45 @@ void d2h(Context& c, T* dst, const T* src, size_t n) {
 // Run f (which enqueues work on c.st) inside a timed region of `phase`.
 template <typename F>
 inline void timed(Context& c, int phase, double flops, F&& f) {
-  if (!c.timer.on) {
+  PhaseTimer& t = c.timer;
+  if (!(t.mask >> phase & 1u)) {
     f();
     return;
   }
-  hipEvent_t a = c.timer.get(), b = c.timer.get();
+  if (t.grouped) {
+    f();
+    if (phase == t.group_phase) {
+      t.group_launches += 1;
+      t.group_flops += flops;
+    }
+    return;
+  }
+  hipEvent_t a = t.get(), b = t.get();
   CTM_HIP(hipEventRecord(a, c.st));
   f();
   CTM_HIP(hipEventRecord(b, c.st));
-  c.timer.recs.push_back({phase, a, b, flops});
+  t.recs.push_back({phase, a, b, flops, 1});
+}
+
+// One pair of events around f, whose timed() launches of `phase` are counted
+// in it (launches of other phases inside f are not timed).
+template <typename F>
+inline void timed_group(Context& c, int phase, F&& f) {
+  PhaseTimer& t = c.timer;
+  if (!(t.mask >> phase & 1u) || t.grouped) {
+    f();
+    return;
+  }
+  hipEvent_t a = t.get(), b = t.get();
+  CTM_HIP(hipEventRecord(a, c.st));
+  t.grouped = true;
+  t.group_phase = phase;
+  t.group_launches = 0;
+  t.group_flops = 0.0;
+  f();
+  t.grouped = false;
+  CTM_HIP(hipEventRecord(b, c.st));
+  t.recs.push_back({phase, a, b, t.group_flops, t.group_launches});
 }
 
 // tensors: `replicas` sets of Lx*Ly site tensors, one after the other;

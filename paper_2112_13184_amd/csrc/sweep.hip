@@ -626,19 +626,23 @@ namespace {
 void apply_M(Context& c, double* const G[4], const double* X, double* Y, int m, double* t1, double* t2) {
   const int n = c.n;
   // G order: 0 = UL, 1 = UR, 2 = LR, 3 = LL
-  mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[2], n), colmajor(X, n), out_colmajor(t1, n));
-  mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[3], n), colmajor(t1, n), out_colmajor(t2, n));
-  mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[0], n), colmajor(t2, n), out_colmajor(t1, n));
-  mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[1], n), colmajor(t1, n), out_colmajor(Y, n));
+  timed_group(c, PhaseTimer::SKETCH, [&] {
+    mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[2], n), colmajor(X, n), out_colmajor(t1, n));
+    mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[3], n), colmajor(t1, n), out_colmajor(t2, n));
+    mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[0], n), colmajor(t2, n), out_colmajor(t1, n));
+    mm(c, PhaseTimer::SKETCH, n, m, n, rowmajor(G[1], n), colmajor(t1, n), out_colmajor(Y, n));
+  });
 }
 
 // Z = M^T X; W (if not null) receives G_ul^T G_ur^T X.
 void apply_Mt(Context& c, double* const G[4], const double* X, double* Z, int m, double* t1, double* W) {
   const int n = c.n;
-  mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[1], n), colmajor(X, n), out_colmajor(t1, n));
-  mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[0], n), colmajor(t1, n), out_colmajor(W, n));
-  mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[3], n), colmajor(W, n), out_colmajor(t1, n));
-  mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[2], n), colmajor(t1, n), out_colmajor(Z, n));
+  timed_group(c, PhaseTimer::SKETCH, [&] {
+    mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[1], n), colmajor(X, n), out_colmajor(t1, n));
+    mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[0], n), colmajor(t1, n), out_colmajor(W, n));
+    mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[3], n), colmajor(W, n), out_colmajor(t1, n));
+    mm(c, PhaseTimer::SKETCH, n, m, n, colmajor(G[2], n), colmajor(t1, n), out_colmajor(Z, n));
+  });
 }
 
 }  // namespace
@@ -850,14 +854,18 @@ struct RsvdColumn {
   // Yo = G_ur G_ul G_ll G_lr X
   void applyM(int b0, int b1, const double* X, double* Yo) {
     double *t1 = pan(3, s0 + b0), *t2 = pan(4, s0 + b0);
-    prod(b0, b1, 2, false, X, t1, kk); prod(b0, b1, 3, false, t1, t2, kk);
-    prod(b0, b1, 0, false, t2, t1, kk); prod(b0, b1, 1, false, t1, Yo, kk);
+    timed_group(c, PhaseTimer::SKETCH, [&] {
+      prod(b0, b1, 2, false, X, t1, kk); prod(b0, b1, 3, false, t1, t2, kk);
+      prod(b0, b1, 0, false, t2, t1, kk); prod(b0, b1, 1, false, t1, Yo, kk);
+    });
   }
   // Zo = M^T X, W = G_ul^T G_ur^T X
   void applyMt(int b0, int b1, const double* X, double* Zo) {
     double *t1 = pan(3, s0 + b0), *W = pan(2, s0 + b0);
-    prod(b0, b1, 1, true, X, t1, kk); prod(b0, b1, 0, true, t1, W, kk);
-    prod(b0, b1, 3, true, W, t1, kk); prod(b0, b1, 2, true, t1, Zo, kk);
+    timed_group(c, PhaseTimer::SKETCH, [&] {
+      prod(b0, b1, 1, true, X, t1, kk); prod(b0, b1, 0, true, t1, W, kk);
+      prod(b0, b1, 3, true, W, t1, kk); prod(b0, b1, 2, true, t1, Zo, kk);
+    });
   }
   void orth(int b0, int b1, double* P, int passes, double* Racc) {
     timed(c, PhaseTimer::LINALG, 0.0, [&] { cholqr(c.st, c.sla, P, pk, n, kk, b1 - b0, passes, Racc, c.ws()); });

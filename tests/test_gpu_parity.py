@@ -482,3 +482,33 @@ def test_full_size_one_move(lib, direction):
         got = x.reshape(-1)[np.asarray(rec["pos"])]
         assert np.max(np.abs(got - np.asarray(rec["val"]))) < 1e-8, key
         assert abs(np.linalg.norm(x) - rec["fro"]) < 1e-8 * rec["fro"], key
+
+
+def test_timing_modes(lib):
+    """ctm_timing_enable: 1 times every phase, 2 the sketch products only (four
+    products per pair of events), 0 stops; other values are rejected.  The
+    sweeps give the same energy whichever mode is on."""
+    from paper_2112_13184_amd._binding import CTM_EINVAL, CtmError
+    A = wl.random_itps(2, 2, 3, 2, seed=7)
+    H = wl.heisenberg_bond()
+    energies, counts = [], []
+    for mode in (0, 1, 2):
+        ctx = lib.Ctm(A, 2, 2, 3, 24, rsvd_oversample=16, seed=4)
+        ctx.ctm_sweep(2, 0.0)
+        ctx.ctm_timing_enable(mode)
+        ctx.ctm_sweep(2, 0.0)
+        ph = ctx.ctm_timing_read()
+        energies.append(sum(ctx.ctm_expect_2site(i, dr, H) for i in range(4) for dr in (0, 1)))
+        counts.append({k: v["launches"] for k, v in ph.items()})
+        if mode == 2:
+            sk = ph["sketch_gemm"]
+            assert sk["ms"] > 0 and sk["flops"] > 0
+        with pytest.raises(CtmError) as ex:
+            ctx.ctm_timing_enable(3)
+        assert ex.value.status == CTM_EINVAL
+        ctx.ctm_free()
+    assert energies[0] == energies[1] == energies[2]
+    assert all(v == 0 for v in counts[0].values())
+    assert all(v > 0 for v in counts[1].values()), counts[1]
+    assert counts[2]["sketch_gemm"] == counts[1]["sketch_gemm"] > 0
+    assert all(v == 0 for k, v in counts[2].items() if k != "sketch_gemm"), counts[2]
