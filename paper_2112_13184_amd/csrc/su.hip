@@ -343,9 +343,17 @@ __global__ __launch_bounds__(kSuThreads) void k_su_run(SuArgs a) {
           for (int sw = 0; sw < kSuJacobiMaxSweeps; ++sw) {
             int rotated = 0, large = 0;         // any rotation; any with |gamma| > 1e-10 sqrt(alpha beta)
             for (int rd = 0; rd < np - 1; ++rd) {
+              // round-robin pairs; for the active groups rd + grp and
+              // rd - grp + np - 1 lie in [0, 2 (np - 1)), so one conditional
+              // subtraction reduces them (inactive lanes keep column 0)
               int pa = 0, pb = 0;
               if (grp == 0) { pa = np - 1; pb = rd; }
-              else { pa = (rd + grp) % (np - 1); pb = (rd - grp + np - 1) % (np - 1); }
+              else if (active) {
+                pa = rd + grp;
+                pa = pa >= np - 1 ? pa - (np - 1) : pa;
+                pb = rd - grp + np - 1;
+                pb = pb >= np - 1 ? pb - (np - 1) : pb;
+              }
               T* ca = Th + (long)pa * m;
               T* cb = Th + (long)pb * m;
               double al = 0.0, be = 0.0;
