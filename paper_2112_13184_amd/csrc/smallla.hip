@@ -595,25 +595,46 @@ __global__ __launch_bounds__(64 * kJacobiMaxBS) void k_jacobi_round(double* A, d
   }
 }
 
+// Sum over each half (32 lanes) of the wave; every lane of a half receives
+// its half's sum.  DPP inside the rows of 16, then row 0 into row 1 and row 2
+// into row 3 (row_bcast:15), read from lanes 31 and 63.
+__device__ __forceinline__ double half_sum(double v, bool upper) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  v += dpp_rows_f64<0x142, 0xA>(0.0, v);
+  const double lo = readlane_f64(v, 31), hi = readlane_f64(v, 63);
+  return upper ? hi : lo;
+}
+
 // One-sided Jacobi of one small m x m matrix per workgroup, the whole matrix
 // in LDS (column stride LD, rows past m zero) and every sweep in the one
 // launch: cyclic tournament over the columns (padded to an even count with a
-// zero column), one wave per column pair of a round, the same rotation and
-// threshold as the blocked Jacobi.  Stops after a sweep without rotations or
-// after max_sweeps.  VEC = false (m <= 128): S_b (m values, descending) = the
-// column norms.  VEC = true (m <= 64): the rotations are also accumulated in
-// J (from the identity); A_b and J_b are written back (column-major, ld m)
-// for the finishing kernel, as after the blocked Jacobi.
+// zero column), one half-wave (32 lanes, LD / 32 rows each) per column pair
+// of a round, so that the sixteen waves take 32 pairs at once; the same
+// rotation and threshold as the blocked Jacobi, and no rotation of columns at
+// the rounding level of the matrix.  Stops after a sweep without
+// rotations, after a sweep whose largest rotated |ga| / sqrt(al be) was at
+// most `stop` (the next sweep's would be of order stop^2, below tol for
+// stop = 1e-10; stop = 0: only the first rule), or after max_sweeps.
+// VEC = false (m <= 128): S_b (m values, descending) = the column norms.
+// VEC = true (m <= 64): the rotations are also accumulated in J (from the
+// identity); A_b and J_b are written back (column-major, ld m) for the
+// finishing kernel, as after the blocked Jacobi.
 template <int LD, bool VEC>
 __global__ __launch_bounds__(1024) void k_jacobi_onewg(double* A, int m, double* S, double* J, double tol,
-                                                       int max_sweeps, int* fail) {
+                                                       double stop, int max_sweeps, int* fail) {
   constexpr int NCOL = LD;                       // columns held (m rounded up to even <= LD)
   __shared__ double sA[NCOL * LD];
   __shared__ double sJ[VEC ? NCOL * LD : 1];
   __shared__ double sig[NCOL];
   __shared__ int rotated;
+  __shared__ unsigned long long offmax;          // largest rotated ratio of the sweep (bits)
   const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), nw = blockDim.x >> 6;
+  const bool upper = lane >= 32;
+  const int hl = lane & 31;
   const int m2 = m + (m & 1);
   double* Ab = A + (long)b * m * m;
   for (int e = tid; e < m2 * LD; e += blockDim.x) {
@@ -621,30 +642,49 @@ __global__ __launch_bounds__(1024) void k_jacobi_onewg(double* A, int m, double*
     sA[e] = (col < m && r < m) ? Ab[(long)col * m + r] : 0.0;
     if (VEC) sJ[e] = (col == r && col < m) ? 1.0 : 0.0;
   }
-  constexpr int RW = LD / 64;                    // rows per lane
+  constexpr int RW = LD / 32;                    // rows per lane
+  // columns with |c|^2 <= 1e-30 ||A||_F^2 are at the rounding level of the
+  // matrix: pairs with such a column are not rotated (noise columns would
+  // otherwise keep rotating against each other at O(1) angles)
+  __shared__ double fred[16];
+  double f2 = 0.0;
+  __syncthreads();
+  for (int e = tid; e < m2 * LD; e += blockDim.x) f2 += sA[e] * sA[e];
+  f2 = wave_sum(f2);
+  if (lane == 0) fred[w] = f2;
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int i = 0; i < nw; ++i) fro2 += fred[i];
+  const double tiny = 1e-30 * fro2;
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    if (tid == 0) rotated = 0;
+    if (tid == 0) {
+      rotated = 0;
+      offmax = 0ull;
+    }
     __syncthreads();
     for (int round = 0; round < m2 - 1; ++round) {
-      for (int q = w; q < m2 / 2; q += nw) {
-        const int ci = circle(q, round, m2), cj = circle(m2 - 1 - q, round, m2);
-        double* ai = sA + ci * LD + lane;
-        double* aj = sA + cj * LD + lane;
+      // pair slots: half h of wave w takes pairs 2 w + h, 2 w + h + 2 nw, ...
+      for (int q0 = 2 * w; q0 < m2 / 2; q0 += 2 * nw) {
+        const int q = q0 + (upper ? 1 : 0);
+        const bool act = q < m2 / 2;
+        const int ci = act ? circle(q, round, m2) : 0, cj = act ? circle(m2 - 1 - q, round, m2) : 0;
+        double* ai = sA + ci * LD + hl;
+        double* aj = sA + cj * LD + hl;
         double x[RW], y[RW];
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
         for (int t = 0; t < RW; ++t) {
-          x[t] = ai[64 * t];
-          y[t] = aj[64 * t];
+          x[t] = act ? ai[32 * t] : 0.0;
+          y[t] = act ? aj[32 * t] : 0.0;
           al += x[t] * x[t];
           be += y[t] * y[t];
           ga += x[t] * y[t];
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
+        al = half_sum(al, upper);
+        be = half_sum(be, upper);
+        ga = half_sum(ga, upper);
         const double ab = al * be, g2 = ga * ga;
-        if (g2 > tol * tol * ab) {
+        if (act && al > tiny && be > tiny && g2 > tol * tol * ab) {
           const double dd = be - al, ad = fabs(dd);
           const double X = dd * dd + 4.0 * g2;
           const double r = X * rsqrt_nr(X);
@@ -652,27 +692,32 @@ __global__ __launch_bounds__(1024) void k_jacobi_onewg(double* A, int m, double*
           const double cs = (r + ad) * inv, sn = 2.0 * ga * (dd >= 0.0 ? inv : -inv);
 #pragma unroll
           for (int t = 0; t < RW; ++t) {
-            ai[64 * t] = cs * x[t] - sn * y[t];
-            aj[64 * t] = sn * x[t] + cs * y[t];
+            ai[32 * t] = cs * x[t] - sn * y[t];
+            aj[32 * t] = sn * x[t] + cs * y[t];
           }
           if (VEC) {
-            double* ji = sJ + ci * LD + lane;
-            double* jj = sJ + cj * LD + lane;
+            double* ji = sJ + ci * LD + hl;
+            double* jj = sJ + cj * LD + hl;
 #pragma unroll
             for (int t = 0; t < RW; ++t) {
-              const double u = ji[64 * t], v = jj[64 * t];
-              ji[64 * t] = cs * u - sn * v;
-              jj[64 * t] = sn * u + cs * v;
+              const double u = ji[32 * t], v = jj[32 * t];
+              ji[32 * t] = cs * u - sn * v;
+              jj[32 * t] = sn * u + cs * v;
             }
           }
-          if (lane == 0) rotated = 1;
+          if (hl == 0) {
+            rotated = 1;
+            const double ratio = fabs(ga) * rsqrt_nr(ab);
+            atomicMax(&offmax, (unsigned long long)__double_as_longlong(ratio));
+          }
         }
       }
       __syncthreads();
     }
     const int any = rotated;
+    const double worst = __longlong_as_double((long long)offmax);
     __syncthreads();
-    if (!any) break;
+    if (!any || worst <= stop) break;
     // still rotating after the last allowed sweep: not converged
     if (sw == max_sweeps - 1 && fail && tid == 0) fail[b] = max(fail[b], kJacobiUnconverged);
   }
@@ -688,7 +733,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_onewg(double* A, int m, double*
   for (int col = w; col < m; col += nw) {
     double s2 = 0.0;
 #pragma unroll
-    for (int t = 0; t < RW; ++t) {
+    for (int t = 0; t < LD / 64; ++t) {
       const double v = sA[col * LD + lane + 64 * t];
       s2 += v * v;
     }
@@ -913,7 +958,8 @@ void jacobi_svd_start(hipStream_t st, SmallLA& s, double* A, int k, int batch) {
   double* J = s.J.as<double>();
   if (k <= kJacobiOneWgMaxK) {
     // every sweep of a problem in one workgroup: one launch, no host reads
-    hipLaunchKernelGGL((k_jacobi_onewg<64, true>), dim3(batch), dim3(1024), 0, st, A, k, nullptr, J, kJacobiTol, 14,
+    hipLaunchKernelGGL((k_jacobi_onewg<64, true>), dim3(batch), dim3(1024), 0, st, A, k, nullptr, J, kJacobiTol,
+                       kJacobiStopVec, 14,
                        s.flag.as<int>());
     CTM_HIP(hipGetLastError());
     return;
@@ -1017,10 +1063,10 @@ void singular_values_small(hipStream_t st, const double* A, int m, int batch, do
   // the kernel reads A and writes only S; rows per lane sized to m
   if (m <= 64)
     hipLaunchKernelGGL((k_jacobi_onewg<64, false>), dim3(batch), dim3(1024), 0, st, const_cast<double*>(A), m, S,
-                       nullptr, 1e-15, 30, nullptr);
+                       nullptr, 1e-15, 0.0, 30, nullptr);
   else
     hipLaunchKernelGGL((k_jacobi_onewg<kSvSmallMax, false>), dim3(batch), dim3(1024), 0, st, const_cast<double*>(A), m,
-                       S, nullptr, 1e-15, 30, nullptr);
+                       S, nullptr, 1e-15, 0.0, 30, nullptr);
   CTM_HIP(hipGetLastError());
 }
 
