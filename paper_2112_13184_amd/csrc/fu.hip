@@ -30,6 +30,7 @@
 #include "context.hpp"
 #include "gemm.hpp"
 #include "linalg.hpp"
+#include "wave.hpp"
 
 namespace ctm {
 namespace {
@@ -80,15 +81,122 @@ __global__ void k_fu_pos_cols(const double* V, const double* w, double* Vs, int 
   }
 }
 
-// Y[i][:] *= 1 / w_i where w_i > cut * max(w_max, 0), else 0 (w ascending)
+// Y[i][:] *= 1 / w_i where w_i > cut * max(w_max, 0), else 0 (w in any order)
 __global__ void k_fu_pinv_rows(double* Y, const double* w, int n, int m) {
-  const double wmax = fmax(w[n - 1], 0.0);
+  double wmax = 0.0;                               // the largest eigenvalue (any order)
+  for (int i = 0; i < n; ++i) wmax = fmax(wmax, w[i]);
   const long total = (long)n * m;
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
     const int i = (int)(e / m);
     const double wi = w[i];
     Y[e] = wi > kFuPinvCut * wmax ? Y[e] / wi : 0.0;
   }
+}
+
+// Eigen-decomposition of one symmetric n x n matrix (n <= kFuEigMax) in one
+// workgroup by the cyclic two-sided Jacobi method: each round applies the
+// n / 2 rotations of a round-robin tournament of disjoint index pairs
+// (p, q) together, A <- J^T A J with J the rotation that zeroes a_pq of the
+// pair's 2 x 2 block (t = sgn(z) / (|z| + sqrt(z^2 + 1)), z = (a_qq - a_pp) /
+// (2 a_pq), c = 1 / sqrt(t^2 + 1), s = t c), rows first, then columns and
+// the accumulated V <- V J.  An entry is rotated away while |a_pq| exceeds
+// 1e-16 ||A||_F; the iteration ends after a sweep with no rotation (or
+// after kFuEigMaxSweeps).  A (column-major, symmetric) is read; W receives
+// the eigenvalues (unsorted) and V the eigenvectors (column j for W[j],
+// column-major n x n).  *unconverged is set when the sweep cap is reached.
+constexpr int kFuEigMax = 64;
+constexpr int kFuEigLd = kFuEigMax + 1;
+constexpr int kFuEigMaxSweeps = 30;
+
+__device__ __forceinline__ int eig_circle(int pos, int round, int m) {
+  if (pos == 0) return 0;
+  int t = pos - 1 + round;
+  if (t >= m - 1) t -= m - 1;
+  return t + 1;
+}
+
+__global__ __launch_bounds__(1024) void k_sym_eig(const double* A, int n, double* W, double* V, int* unconverged) {
+  __shared__ double a[kFuEigMax * kFuEigLd];
+  __shared__ double v[kFuEigMax * kFuEigLd];
+  __shared__ double cs[kFuEigMax / 2], sn[kFuEigMax / 2];
+  __shared__ int pp[kFuEigMax / 2], qq[kFuEigMax / 2];
+  __shared__ double red[16];
+  __shared__ int rotated;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  const int m = n + (n & 1), half = m / 2;
+  // a[i + kFuEigLd j] = A(i, j), zero in the padding row and column; v = I
+  double f2 = 0.0;
+  for (int e = tid; e < m * m; e += blockDim.x) {
+    const int i = e % m, j = e / m;
+    const double x = (i < n && j < n) ? A[i + (long)j * n] : 0.0;
+    a[i + kFuEigLd * j] = x;
+    v[i + kFuEigLd * j] = (i == j) ? 1.0 : 0.0;
+    f2 += x * x;
+  }
+  f2 = wave_sum(f2);
+  if (lane == 0) red[w] = f2;
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int i = 0; i < nw; ++i) fro2 += red[i];
+  const double thr = 1e-16 * sqrt(fro2);
+  int sw = 0;
+  for (; sw < kFuEigMaxSweeps; ++sw) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < m - 1; ++round) {
+      if (tid < half) {
+        int p = eig_circle(tid, round, m), q = eig_circle(m - 1 - tid, round, m);
+        if (p > q) { const int t = p; p = q; q = t; }
+        const double apq = a[p + kFuEigLd * q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > thr) {
+          const double z = (a[q + kFuEigLd * q] - a[p + kFuEigLd * p]) / (2.0 * apq);
+          const double t = fabs(z) > 1e150 ? 0.5 / z : (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(z * z + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+          rotated = 1;
+        }
+        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+      }
+      __syncthreads();
+      // rows p, q of A
+      for (int e = tid; e < half * m; e += blockDim.x) {
+        const int k = e / m, j = e % m;
+        const double c = cs[k], s = sn[k];
+        if (s != 0.0) {
+          const int p = pp[k], q = qq[k];
+          const double x = a[p + kFuEigLd * j], y = a[q + kFuEigLd * j];
+          a[p + kFuEigLd * j] = c * x - s * y;
+          a[q + kFuEigLd * j] = s * x + c * y;
+        }
+      }
+      __syncthreads();
+      // columns p, q of A and of V
+      for (int e = tid; e < half * m; e += blockDim.x) {
+        const int k = e / m, i = e % m;
+        const double c = cs[k], s = sn[k];
+        if (s != 0.0) {
+          const int p = pp[k], q = qq[k];
+          const double x = a[i + kFuEigLd * p], y = a[i + kFuEigLd * q];
+          a[i + kFuEigLd * p] = c * x - s * y;
+          a[i + kFuEigLd * q] = s * x + c * y;
+          const double u = v[i + kFuEigLd * p], z = v[i + kFuEigLd * q];
+          v[i + kFuEigLd * p] = c * u - s * z;
+          v[i + kFuEigLd * q] = s * u + c * z;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  for (int e = tid; e < n * n; e += blockDim.x) {
+    const int i = e % n, j = e / n;
+    V[e] = v[i + kFuEigLd * j];
+  }
+  for (int j = tid; j < n; j += blockDim.x) W[j] = a[j + kFuEigLd * j];
+  if (tid == 0 && unconverged) *unconverged = sw == kFuEigMaxSweeps ? 1 : 0;
 }
 
 // Theta'[(x P)][(y Q)], a_i(x, c) = Ri[x + c C] (column-major C x C), likewise a_j
@@ -206,6 +314,17 @@ DT dt(double* p, std::vector<long> dims) {
 int other_leg_h(int leg, int t) { return t == 0 ? (leg == 0 ? 1 : 0) : t == 1 ? (leg <= 1 ? 2 : 1) : (leg <= 2 ? 3 : 2); }
 
 // X = pinv(sym(Rm)) Sm, Rm n x n, Sm n x m (row-major, arena)
+// Eigenvalues W and eigenvectors (columns of V, in place) of the symmetric
+// n x n matrix V: one-workgroup Jacobi up to kFuEigMax, else rocSOLVER.
+void sym_eig(Context& c, double* V, int n, double* W) {
+  if (n <= kFuEigMax) {
+    hipLaunchKernelGGL(k_sym_eig, dim3(1), dim3(1024), 0, c.st, V, n, W, V, nullptr);
+    CTM_HIP(hipGetLastError());
+  } else {
+    la_syev(c.la, V, n, W);
+  }
+}
+
 double* pinv_solve(Context& c, const double* Rm, const double* Sm, int n, int m) {
   double* V = c.arena.alloc((size_t)n * n);
   double* W = c.arena.alloc(n);
@@ -213,7 +332,7 @@ double* pinv_solve(Context& c, const double* Rm, const double* Sm, int n, int m)
   double* X = c.arena.alloc((size_t)n * m);
   hipLaunchKernelGGL(k_fu_sym, dim3(blocks_for((long)n * n)), dim3(256), 0, c.st, Rm, V, n);
   CTM_HIP(hipGetLastError());
-  la_syev(c.la, V, n, W);                                        // V <- eigenvectors (columns)
+  sym_eig(c, V, n, W);                                           // V <- eigenvectors (columns)
   gemm(c.st, GemmType::F64, n, m, n, 1.0, rowmajor(V, n), rowmajor(Sm, m), 0.0, out_rowmajor(Y, m), 1, c.ws());
   hipLaunchKernelGGL(k_fu_pinv_rows, dim3(blocks_for((long)n * m)), dim3(256), 0, c.st, Y, W, n, m);
   CTM_HIP(hipGetLastError());
@@ -268,7 +387,7 @@ void fu_bond(Context& c, int s, int dir, const double* g, int als_iters) {
   double* Np = c.arena.alloc((size_t)n2 * n2);
   hipLaunchKernelGGL(k_fu_sym, dim3(blocks_for((long)n2 * n2)), dim3(256), 0, c.st, Nraw.p, V, n2);
   CTM_HIP(hipGetLastError());
-  la_syev(c.la, V, n2, W);
+  sym_eig(c, V, n2, W);
   hipLaunchKernelGGL(k_fu_pos_cols, dim3(blocks_for((long)n2 * n2)), dim3(256), 0, c.st, V, W, Vs, n2);
   CTM_HIP(hipGetLastError());
   gemm(c.st, GemmType::F64, n2, n2, n2, 1.0, colmajor(Vs, n2), rowmajor(V, n2), 0.0, out_rowmajor(Np, n2), 1,
