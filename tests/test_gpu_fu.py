@@ -90,6 +90,33 @@ def test_two_steps_heisenberg_parity(lib):
     assert abs(e_gpu - e_orc) < 1e-9
 
 
+def test_spin_one_odd_order_parity(lib):
+    """d = 3, D = 3: the ALS normal matrices have odd order r D = 27 (the
+    padded path of the one-workgroup eigensolver), the bond environment order
+    r^2 = 81 (rocSOLVER's).  A random symmetric two-site Hamiltonian, one step
+    against the oracle; the sketch covers every cut (k = chi + p >= chi D^2)."""
+    D, d, chi, p = 3, 3, 12, 96
+    A = wl.random_itps(LX, LY, D, d, seed=21)
+    ctx = lib.Ctm(A, LX, LY, D, chi=chi, d=d, rsvd_oversample=p)
+    ctx.ctm_sweep(4, 0.0)
+    env = Environment([np.array(a) for a in A], LX, LY, chi=chi, oversample=p)
+    for _ in range(4):
+        env.sweep()
+    rng = np.random.default_rng(4)
+    Hd = rng.standard_normal((d * d, d * d))
+    Hd = Hd + Hd.T
+    H = [[Hd, Hd] for _ in range(N)]
+    ctx.ctm_fu_step(np.asarray(H), 0.02, als_iters=2, env_sweeps=1)
+    fu.full_update_step(env, H, 0.02, als_iters=2, env_sweeps=1)
+    G = ctx.ctm_get_tensors()
+    dt = max(float(np.abs(G[i] - env.A[i]).max() / np.abs(env.A[i]).max()) for i in range(N))
+    e_gpu, e_orc = gpu_energy(ctx, Hd), energy(env, Hd)
+    print(f"tensors {dt:.2e}, energy {abs(e_gpu - e_orc):.2e}")
+    ctx.ctm_free()
+    assert dt < 1e-8
+    assert abs(e_gpu - e_orc) < 1e-9
+
+
 def test_commuting_ising_gates_reach_onsager(lib):
     D, chi, p = 2, 16, 48
     tau, n = 0.05, 3
