@@ -199,6 +199,86 @@ __global__ __launch_bounds__(1024) void k_sym_eig(const double* A, int n, double
   if (tid == 0 && unconverged) *unconverged = sw == kFuEigMaxSweeps ? 1 : 0;
 }
 
+// Householder QR of one tall n x k matrix (column-major, n >= k, n k <=
+// kQrMaxElems) in one workgroup, as LAPACK's geqr2 and org2r: reflector j
+// has v = (1, x / (alpha - beta)), beta = -sgn(alpha) sqrt(alpha^2 + |x|^2),
+// tau = (beta - alpha) / beta (tau = 0 when x = 0), applied to the columns
+// right of j (one wave per column); then Q is formed in place from the
+// reflectors in reverse order.  Z receives Q (n x k), R the k x k upper
+// triangle (column-major).
+constexpr int kQrMaxElems = 8192;
+constexpr int kQrMaxK = 64;
+
+__device__ double qr_block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += red[i];
+  return r;
+}
+
+// H = I - tau v v^T (v_j = 1, v_i = a[i + n j] below j) on columns j+1..k-1
+__device__ void qr_apply_right_of(double* a, int n, int k, int j, double tau) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (tau == 0.0) return;
+  for (int c = j + 1 + w; c < k; c += nw) {
+    double dot = 0.0;
+    for (int i = j + 1 + lane; i < n; i += 64) dot += a[i + n * j] * a[i + n * c];
+    dot = wave_sum(dot) + a[j + n * c];
+    const double f = tau * dot;
+    if (lane == 0) a[j + n * c] -= f;
+    for (int i = j + 1 + lane; i < n; i += 64) a[i + n * c] -= f * a[i + n * j];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_small_qr(double* Z, int n, int k, double* R) {
+  __shared__ double a[kQrMaxElems];
+  __shared__ double tau[kQrMaxK];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * k; e += blockDim.x) a[e] = Z[e];
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    double x2 = 0.0;
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) x2 += a[i + n * j] * a[i + n * j];
+    x2 = qr_block_sum(x2, red);
+    const double alpha = a[j + n * j];
+    double t = 0.0;
+    if (x2 > 0.0) {
+      const double beta = -copysign(sqrt(alpha * alpha + x2), alpha);
+      t = (beta - alpha) / beta;
+      const double sc = 1.0 / (alpha - beta);
+      for (int i = j + 1 + tid; i < n; i += blockDim.x) a[i + n * j] *= sc;
+      __syncthreads();
+      if (tid == 0) a[j + n * j] = beta;
+    }
+    if (tid == 0) tau[j] = t;
+    __syncthreads();
+    qr_apply_right_of(a, n, k, j, t);
+    __syncthreads();
+  }
+  for (int e = tid; e < k * k; e += blockDim.x) {
+    const int r = e % k, c = e / k;
+    R[e] = r <= c ? a[r + n * c] : 0.0;
+  }
+  __syncthreads();
+  for (int j = k - 1; j >= 0; --j) {
+    const double t = tau[j];
+    if (j < k - 1) qr_apply_right_of(a, n, k, j, t);
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) {
+      if (i > j) a[i + n * j] *= -t;
+      else if (i == j) a[i + n * j] = 1.0 - t;
+      else a[i + n * j] = 0.0;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * k; e += blockDim.x) Z[e] = a[e];
+}
+
 // Theta'[(x P)][(y Q)], a_i(x, c) = Ri[x + c C] (column-major C x C), likewise a_j
 __global__ void k_fu_core(const double* Ri, const double* Rj, const double* g, double* Th, int D, int d, int C) {
   const int n = C * d;
@@ -325,6 +405,17 @@ void sym_eig(Context& c, double* V, int n, double* W) {
   }
 }
 
+// Z (n x k) <- Q, R <- the k x k factor: one workgroup up to n k = kQrMaxElems,
+// else rocSOLVER.
+void small_qr(Context& c, double* Z, int n, int k, double* R) {
+  if ((long)n * k <= kQrMaxElems && k <= kQrMaxK && n >= k) {
+    hipLaunchKernelGGL(k_small_qr, dim3(1), dim3(256), 0, c.st, Z, n, k, R);
+    CTM_HIP(hipGetLastError());
+  } else {
+    la_qr(c.la, Z, n, k, R);
+  }
+}
+
 double* pinv_solve(Context& c, const double* Rm, const double* Sm, int n, int m) {
   double* V = c.arena.alloc((size_t)n * n);
   double* W = c.arena.alloc(n);
@@ -369,8 +460,8 @@ void fu_bond(Context& c, int s, int dir, const double* g, int als_iters) {
   DT Mj = tensor_transpose(c, Aj, {lj, 4, other_leg_h(lj, 0), other_leg_h(lj, 1), other_leg_h(lj, 2)});
   double* Ri = c.arena.alloc((size_t)C * C);
   double* Rj = c.arena.alloc((size_t)C * C);
-  la_qr(c.la, Mi.p, R3, C, Ri);
-  la_qr(c.la, Mj.p, R3, C, Rj);
+  small_qr(c, Mi.p, R3, C, Ri);
+  small_qr(c, Mj.p, R3, C, Rj);
 
   // 2. bond environment
   double* Ei = c.arena.alloc((size_t)R3 * D * r);
