@@ -32,6 +32,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kWaves = 4;
 // Tile counts: NR tiles of 16 over (r, dd), (l', u') and (r', d'), KS1 k steps
 // of 4 over (l, u).  D <= 4: one tile (D^2 <= 16), four waves per SIMD.
+// D = 5: D^2 = 25 padded to 32 (2 tiles), three waves per SIMD (LDS).
 // D <= 6: D^2 <= 36 padded to 48 (3 tiles), two waves per SIMD.  D <= 8: 4 tiles, no padding at D = 8; the two accumulator sets take
 // 256 registers, so one wave per SIMD, and Ak, Ab take 152 KB of LDS.
 // LDS leading dimensions are = 16 (mod 32) doubles, so that the two halves of
@@ -52,6 +53,7 @@ struct AbsorbShape {
   static constexpr int MAXP = 16 * NR;                       // largest (l', u') count
 };
 using ShapeD4 = AbsorbShape<1, 4, 48, 4>;
+using ShapeD5 = AbsorbShape<2, 7, 48, 3>;
 using ShapeD6 = AbsorbShape<3, 9, 48, 2>;
 using ShapeD8 = AbsorbShape<4, 16, 80, 1>;
 
@@ -217,7 +219,8 @@ static bool shape_fits(int DK, int DB, int d) {
 }
 
 bool absorb_fused_fits(int DK, int DB, int d) {
-  return shape_fits<ShapeD4>(DK, DB, d) || shape_fits<ShapeD6>(DK, DB, d) || shape_fits<ShapeD8>(DK, DB, d);
+  return shape_fits<ShapeD4>(DK, DB, d) || shape_fits<ShapeD5>(DK, DB, d) || shape_fits<ShapeD6>(DK, DB, d) ||
+         shape_fits<ShapeD8>(DK, DB, d);
 }
 
 void absorb_fused(hipStream_t st, const double* X, const double* Ak, const double* Ab, double* G, int chi,
@@ -240,11 +243,12 @@ void absorb_fused_batched(hipStream_t st, const double* X, const double* Ak, con
   a.chi = chi; a.DK = DK; a.DB = DB; a.d = d;
   a.transposed = transposed ? 1 : 0;
   const long npairs = (long)chi * chi;
-  // resident workgroups per CU on 256 CUs: four (D <= 4), two (D <= 6) or
-  // one (D <= 8, its LDS); each wave strides over pairs
+  // resident workgroups per CU on 256 CUs: four (D <= 4), three (D = 5, its
+  // LDS), two (D <= 6) or one (D <= 8, its LDS); each wave strides over pairs
   const bool d4 = shape_fits<ShapeD4>(DK, DB, d);
-  const bool d6 = !d4 && shape_fits<ShapeD6>(DK, DB, d);
-  const long resident = d4 ? 1024 : d6 ? 512 : 256;
+  const bool d5 = !d4 && shape_fits<ShapeD5>(DK, DB, d);
+  const bool d6 = !d4 && !d5 && shape_fits<ShapeD6>(DK, DB, d);
+  const long resident = d4 ? 1024 : d5 ? 768 : d6 ? 512 : 256;
   const long per_block = kWaves;
   const unsigned blocks = (unsigned)std::min<long>(std::max<long>(1, resident / batch),
                                                    (npairs + per_block - 1) / per_block);
@@ -252,6 +256,8 @@ void absorb_fused_batched(hipStream_t st, const double* X, const double* Ak, con
   const bool mx = amaxp || amax1;
   if (d4 && mx)        hipLaunchKernelGGL((k_absorb_fused<ShapeD4, true>), grid, block, 0, st, a);
   else if (d4)         hipLaunchKernelGGL((k_absorb_fused<ShapeD4, false>), grid, block, 0, st, a);
+  else if (d5 && mx)   hipLaunchKernelGGL((k_absorb_fused<ShapeD5, true>), grid, block, 0, st, a);
+  else if (d5)         hipLaunchKernelGGL((k_absorb_fused<ShapeD5, false>), grid, block, 0, st, a);
   else if (d6 && mx)   hipLaunchKernelGGL((k_absorb_fused<ShapeD6, true>), grid, block, 0, st, a);
   else if (d6)    hipLaunchKernelGGL((k_absorb_fused<ShapeD6, false>), grid, block, 0, st, a);
   else if (mx)    hipLaunchKernelGGL((k_absorb_fused<ShapeD8, true>), grid, block, 0, st, a);

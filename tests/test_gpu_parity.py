@@ -43,7 +43,8 @@ def lib():
 # --------------------------------------------------------------------------
 # single building blocks on an injected environment
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("layers,D,chi", [(2, 3, 13), (2, 2, 20), (1, 3, 21)])
+# D = 2, 3, 4: the one-tile absorption; D = 5: two tiles; D = 6: three
+@pytest.mark.parametrize("layers,D,chi", [(2, 3, 13), (2, 2, 20), (2, 4, 9), (2, 5, 7), (2, 6, 5), (1, 3, 21)])
 def test_enlarged_corner_parity(lib, layers, D, chi):
     d = 2 if layers == 2 else 1
     Db = D * D if layers == 2 else D
