@@ -436,9 +436,34 @@ def ex1_scan(lib, fields=32, D=2, steps=1000, tau=0.01, chi=10, sweeps=10):
         ctx.ctm_free()
     wall = time.perf_counter() - t0
     print(f"transverse-field Ising scan: {fields} fields in {wall:.1f} s", file=sys.stderr, flush=True)
+    # the same CTMRG solves through the serving queue, which runs same-shape
+    # requests as replicas of one context (the simple update's device output
+    # copied at submit)
+    t1 = time.perf_counter()
+    q = lib.Queue(16 << 30, 8)
+    tickets = []
+    for b in range(fields):
+        st, tk = q.submit(None, 2, 2, D, chi, ex1_bond(hs[b]), tol=1e-10, max_sweeps=sweeps,
+                          device_ptr=buf.data_ptr() + 8 * b * per, obs=[0.5 * wl.SZ, 0.5 * wl.SX], tag=b)
+        assert st == 0, st
+        tickets.append(tk)
+    qsz, qsx, qes = [], [], []
+    for tk in tickets:
+        st, r = q.wait(tk)
+        assert st == 0 and r.status == 0, (st, r.status)
+        qsz.append(float(np.mean(np.abs(r.observable(0, 4)))))
+        qsx.append(float(np.mean(r.observable(1, 4))))
+        qes.append(float(r.energy_per_site))
+    q.destroy()
+    t_queue = time.perf_counter() - t1
+    diff = max(max(abs(a - b) for a, b in zip(es, qes)), max(abs(a - b) for a, b in zip(sz, qsz)),
+               max(abs(a - b) for a, b in zip(sx, qsx)))
+    print(f"transverse-field Ising scan, CTMRG through the queue: {t_queue:.2f} s "
+          f"(one context per field: {wall - t_su:.2f} s), max difference {diff:.1e}", file=sys.stderr, flush=True)
     return {"workload": f"ex1_tfim_scan_2x2_D{D}_chi{chi}", "fields": fields, "su_steps": steps, "tau": tau,
             "ctm_sweeps": sweeps, "h": [float(h) for h in hs], "abs_sz": sz, "sx": sx, "energy_per_site": es,
-            "su_wall_s": t_su, "wall_s": wall}
+            "su_wall_s": t_su, "wall_s": wall, "ctm_queue_wall_s": t_queue,
+            "ctm_sequential_wall_s": wall - t_su, "queue_max_abs_diff": diff}
 
 
 def fu_bench(lib, D=4, chi=32, p=32, h=1.5, su_steps=500, fu_steps=3, tau=0.01, als_iters=5, env_sweeps=1,
