@@ -142,7 +142,7 @@ def cpu_baseline_extra(serving_res, serving_reqs, rate_hz, n_sample=6):
     return out
 
 
-def run_sweeps(lib, A, D, chi, d, p, q, prec, warmup, steps, timing=2):
+def run_sweeps(lib, A, D, chi, d, p, q, prec, warmup, steps, timing=2, seed=12):
     """warmup untimed sweeps, then `steps` timed sweeps through ctm_sweep
     (the four moves and the stop rule's corner spectra of every sweep);
     returns (seconds, phase timings, energy per site after warmup + steps
@@ -151,7 +151,7 @@ def run_sweeps(lib, A, D, chi, d, p, q, prec, warmup, steps, timing=2):
     events add about 10 us of idle stream per pair, so that pass is for the
     phase breakdown, not for the rate)."""
     import torch
-    ctx = lib.Ctm(A, 2, 2, D, chi, d=d, prec=prec, rsvd_oversample=p, rsvd_power_iters=q, seed=12)
+    ctx = lib.Ctm(A, 2, 2, D, chi, d=d, prec=prec, rsvd_oversample=p, rsvd_power_iters=q, seed=seed)
     if warmup:
         ctx.ctm_sweep(warmup, 0.0)
     torch.cuda.synchronize()
@@ -295,6 +295,24 @@ def serving_bench(lib, n, max_active, budget_gb, p=16, q=1, tol=1e-10, max_sweep
         opened.pop("sweeps")
         out[f"open_loop_{load}x"] = dict(opened, arrival_rate_hz=rate, max_energy_diff_vs_closed=same)
     return out, reqs, sweeps
+
+
+def d4_bench(lib, sweeps=30, warm=2):
+    """D = 4, chi = 64 (2x2 cell, p = 32, q = 2, sketch seed 11, tensors of
+    seed 1): sweeps/s over the sweeps after the first `warm`, the sketch
+    GEMMs' fraction of the FP64 peak, and the energy per site after all
+    sweeps against the oracle's stored run of the same sweeps."""
+    A = wl.random_itps(2, 2, 4, 2, seed=1)
+    dt, ph, e, cuts = run_sweeps(lib, A, 4, 64, 2, 32, 2, "f64", warm, sweeps - warm, seed=11)
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "itps_d4_chi64.json")) as f:
+        ref = json.load(f)["energies"][str(sweeps)]
+    r = sketch_rate(ph)
+    print(f"D=4 chi=64 f64: {(sweeps - warm) / dt:.2f} sweeps/s", file=sys.stderr, flush=True)
+    return {"workload": "itps_2x2_d2_D4_chi64", "rsvd_p": 32, "rsvd_q": 2, "sweeps": sweeps,
+            "timed_sweeps": sweeps - warm, "sweeps_per_s": (sweeps - warm) / dt, "sketch_tflops": r / 1e12,
+            "sketch_frac_of_peak": r / PEAK["f64"], "energy_per_site": e, "oracle_energy_per_site": ref,
+            "abs_energy_diff_vs_oracle": abs(e - ref),
+            "cuts": dict(zip(("identity", "rsvd_batched", "fallback"), cuts))}
 
 
 def big_bench(lib, sweeps, D=8, chi=256, p=64, q=1, seed=3, warm=2):
@@ -642,6 +660,7 @@ def main():
                          "energy_per_site": ep, "abs_energy_diff": abs(ep - energy)}
         out["precisions"] = cmp
     if args.big_sweeps:
+        out["d4_chi64"] = d4_bench(lib)
         out["d8_chi256"] = big_bench(lib, args.big_sweeps)
     if args.su:
         out["simple_update"] = su_bench(lib, cpu=not args.no_cpu_baseline)
