@@ -20,8 +20,10 @@
 //      of its largest modulus positive (A_j' flipped with it); each tensor is
 //      divided by its largest |entry|; all four rotations are rewritten;
 //   8. env_sweeps CTMRG sweeps from the current environment.
-// Every step runs on the context's stream; the small dense factorisations go
-// through rocSOLVER, the contractions through the FP64 MFMA GEMM.
+// Every step runs on the context's stream.  The QRs (up to 8192 entries) and
+// the symmetric eigenproblems (up to order 64) are one-workgroup kernels
+// here, larger ones and the SVD of step 5 go through rocSOLVER; the
+// contractions through the FP64 MFMA GEMM.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
