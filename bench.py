@@ -598,6 +598,7 @@ def main():
     if args.su_only:
         out = {"simple_update": su_bench(lib, cpu=not args.no_cpu_baseline),
                "simple_update_d2": su_bench(lib, D=2, cpu=False),
+               "simple_update_b1024": su_bench(lib, B=1024, steps=400, cpu=False),
                "simple_update_complex": su_bench(lib, cpu=False, cplx=True), "ex1_scan": ex1_scan(lib),
                "full_update": fu_bench(lib, cpu=not args.no_cpu_baseline)}
         print(json.dumps(out), flush=True)
@@ -665,6 +666,8 @@ def main():
     if args.su:
         out["simple_update"] = su_bench(lib, cpu=not args.no_cpu_baseline)
         out["simple_update_complex"] = su_bench(lib, cpu=False, cplx=True)
+        # 1024 fields: four problems per CU, the throughput of a saturated GPU
+        out["simple_update_b1024"] = su_bench(lib, B=1024, steps=400, cpu=False)
         out["ex1_scan"] = ex1_scan(lib)
         # the oracle's full-update bond update takes about a minute: its CPU leg
         # runs with --su-only
